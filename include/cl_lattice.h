@@ -1,0 +1,192 @@
+/*
+ * cl_lattice.h -- C ABI of the MI355X lattice scalar-field library.
+ *
+ * The library evolves n_fields (1 or 2) interacting real scalar fields on a
+ * periodic N^3 lattice in a spatially flat FLRW background, in alpha-time
+ * (CosmoLattice 2.0, Sect. 2, Eq. FLRWmetric).  Each time step is a drift of
+ * the fields, a kick of the conjugate momenta pi = a^(3-alpha) f' by the
+ * 7-point Laplacian and the potential derivative (Sect. 2.1, Eq. singletEOM),
+ * and volume averages of the kinetic, gradient and potential energies
+ * (Eq. energy-contrib) that drive the scale-factor update through the
+ * Friedmann equations (Eqs. Friedmann1, Friedmann2), all advanced together by
+ * a symplectic kick-drift scheme (Sect. 4.1, Eqs. SchemeContVirgin1-4).
+ *
+ * Conventions
+ *   - Every call returns cl_status: CL_OK (0) on success, a negative code on
+ *     failure.  No C++ exception crosses this boundary.  cl_last_error()
+ *     gives a human-readable message for the last failure.
+ *   - Handles are opaque and not thread safe; one handle issues all its GPU
+ *     work on one HIP stream (the null stream unless cl_set_stream is used).
+ *   - Host arrays are copy-in / copy-out; the caller owns them.
+ *   - Field arrays are structure-of-arrays, field-major: element
+ *     [j][(x*N + y)*N + z] for field j, z fastest, n_fields * N^3 values.
+ *   - Device memory is allocated and freed by the library unless the caller
+ *     attaches its own buffers with cl_attach_device_buffers.
+ *   - Passing NULL for a required pointer returns CL_EINVAL.
+ */
+#ifndef CL_LATTICE_H
+#define CL_LATTICE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CL_OK = 0,
+    CL_EINVAL = -1,       /* invalid argument */
+    CL_ENOMEM = -2,       /* host or device allocation failed */
+    CL_EDEVICE = -3,      /* a HIP runtime call failed */
+    CL_ESTATE = -4,       /* call not valid in the handle's current state */
+    CL_EUNSTABLE = -5,    /* non-finite values appeared, or the time step exceeds the Courant bound */
+    CL_EUNSUPPORTED = -6  /* valid request this build does not support */
+} cl_status;
+
+typedef enum { CL_FP64 = 0, CL_FP32 = 1 } cl_precision;
+
+/* CL_STATIC: a == 1, a' == 0.  CL_SELF_CONSISTENT: a follows Eq. Friedmann1
+ * sourced by the lattice volume averages of rho and p (Eq. rhoLocal). */
+typedef enum { CL_STATIC = 0, CL_SELF_CONSISTENT = 1 } cl_expansion;
+
+/* CL_LEAPFROG: staggered leapfrog, O(dt^2).  CL_VV4: 4th-order Yoshida
+ * composition of velocity Verlet, O(dt^4) (Sect. 4.1). */
+typedef enum { CL_LEAPFROG = 0, CL_VV4 = 1 } cl_integrator;
+
+/* V = sum_j (m2[j] f_j^2 / 2 + lambda[j] f_j^4 / 4) + g2 f_0^2 f_1^2 / 2 + V0,
+ * in program variables (Eq. FieldSpaceTimeNaturalVariables).  With two fields
+ * this is the mother/daughter potential of the lphi4 model (Sect. 5.1). */
+typedef struct {
+    double m2[2];
+    double lambda[2];
+    double g2;
+    double V0;
+} cl_potential;
+
+/* Homogeneous background state: scale factor a, its alpha-time derivative
+ * b = a' (the scale-factor momentum of Eq. SchemeContVirgin1), time eta and
+ * the number of completed time steps. */
+typedef struct {
+    double a;
+    double b;
+    double eta;
+    int64_t step;
+} cl_scalars;
+
+/* Observables of one synchronised state.  EK, EG: kinetic and gradient
+ * energy densities per field, EV: potential energy density (volume averages,
+ * Eq. energy-contrib with <.>_V of Sect. 4.3).  H = a'/a.  mean, var: per-field
+ * volume mean and variance of f.  hubble_residual:
+ * |H^2 - a^(2 alpha) rho/(3 m_p^2)| / (a^(2 alpha) rho/(3 m_p^2)) (Eq. Friedmann2),
+ * 0 in static space.  nonfinite: 1 if any lattice sum was NaN or Inf. */
+typedef struct {
+    double eta;
+    double a;
+    double H;
+    double EK[2];
+    double EG[2];
+    double EV;
+    double mean[2];
+    double var[2];
+    double hubble_residual;
+    int32_t nonfinite;
+    int32_t reserved;
+} cl_observables;
+
+typedef struct cl_lattice cl_lattice;
+typedef struct cl_ensemble cl_ensemble;
+
+/* Message for the last failing call on h (or on any handle-less call when h
+ * is NULL).  The string stays valid until the next call on the same handle. */
+const char* cl_last_error(const cl_lattice* h);
+
+/* Library version string (static storage). */
+const char* cl_version(void);
+
+/* Create a lattice of N^3 sites with spacing dx (Sect. 2: dx = L/N,
+ * k_IR = 2 pi / L), n_fields in {1, 2}, field storage precision prec.  N must
+ * be even and >= 8 (power of two for cl_seed), dx > 0.  Allocates the field,
+ * momentum and ping-pong buffers on the current HIP device (4 * n_fields *
+ * N^3 values of the chosen precision) plus a small scalar block.  Defaults:
+ * alpha = 1, self-consistent expansion, m_p = 1, a0 = 1, V = lambda f^4/4 with
+ * lambda = 1 for field 0, fields zero.  On failure *out is NULL. */
+cl_status cl_create(int N, double dx, int n_fields, cl_precision prec, cl_lattice** out);
+
+/* Free everything the library allocated for h.  cl_destroy(NULL) is a no-op. */
+cl_status cl_destroy(cl_lattice* h);
+
+/* Issue all GPU work of h on the given hipStream_t (NULL = null stream).  The
+ * caller keeps the stream alive while h uses it. */
+cl_status cl_set_stream(cl_lattice* h, void* hip_stream);
+
+/* Use caller-owned device buffers instead of library-owned ones.  Each array
+ * holds n_fields device pointers, each to N^3 values of the handle's
+ * precision, 16-byte aligned: f[j], p[j] are the current state, f_pp[j],
+ * p_pp[j] the ping-pong partners.  Library-owned field buffers are freed.
+ * The caller keeps the memory alive until cl_destroy.  The current field
+ * values are not copied: set them afterwards. */
+cl_status cl_attach_device_buffers(cl_lattice* h, void* const* f, void* const* p,
+                                   void* const* f_pp, void* const* p_pp);
+
+/* Background: alpha-time exponent alpha (Eq. FLRWmetric; 0 cosmic, 1
+ * conformal), expansion mode, reduced Planck mass m_p in program units, and
+ * the initial scale factor a0 used by cl_seed / cl_set_fields. */
+cl_status cl_set_background(cl_lattice* h, double alpha, cl_expansion mode, double m_p, double a0);
+
+/* Potential coefficients (copied). */
+cl_status cl_set_potential(cl_lattice* h, const cl_potential* pot);
+
+/* Vacuum-fluctuation initial condition (Sect. 2.3, Eqs. QuantumFlucts,
+ * fpr_influct, fpr_influct2): homogeneous values fbar[j], pbar[j] (momenta
+ * pi) plus Gaussian fluctuations drawn in Fourier space on modes
+ * 0 < |n| <= cutoff_modes with <|df(n)|^2> = amp^2 / (2 a0^2 w_k dx^3),
+ * w_k^2 = k^2 + a0^2 d2V/df_j^2(fbar), transformed with the DFT convention of
+ * Sect. 4.3.  Random numbers: SplitMix64 counter stream keyed by seed, field
+ * and mode.  Afterwards a = a0 and a' is set from the lattice energy density
+ * so that the Hubble constraint holds exactly (0 in static space); eta = 0,
+ * step = 0.  Runs on the host in FP64 (N must be a power of two), then
+ * uploads.  cutoff_modes <= 0 selects N/4. */
+cl_status cl_seed(cl_lattice* h, uint64_t seed, const double* fbar, const double* pbar,
+                  double cutoff_modes, double amp);
+
+/* Copy host FP64 fields and momenta (n_fields * N^3 each, layout above) into
+ * the current state, rounding to the handle's precision.  Sets a = a0,
+ * eta = 0, step = 0 and a' from the Hubble constraint (0 in static space). */
+cl_status cl_set_fields(cl_lattice* h, const double* f, const double* p);
+
+/* Copy the current (synchronised) fields and momenta to host FP64 arrays. */
+cl_status cl_get_fields(cl_lattice* h, double* f, double* p);
+
+/* Read / overwrite the background state (checkpoint and resume).  Fields are
+ * saved and restored with cl_get_fields / cl_set_fields followed by
+ * cl_set_state. */
+cl_status cl_get_state(const cl_lattice* h, cl_scalars* out);
+cl_status cl_set_state(cl_lattice* h, const cl_scalars* in);
+
+/* Advance n full time steps of size dt with the given integrator, starting
+ * and ending in a synchronised state.  If per_step is not NULL it receives n
+ * records, one after each full step.  Returns CL_EUNSTABLE if dt exceeds the
+ * leapfrog Courant bound dt * sqrt(12) / dx < 2 or if a lattice sum became
+ * non-finite (the records then show where).  The work is issued on the
+ * handle's stream and the call returns after it completes. */
+cl_status cl_step(cl_lattice* h, cl_integrator integ, double dt, int n, cl_observables* per_step);
+
+/* Observables of the current state (one reduction pass over the lattice). */
+cl_status cl_read_observables(cl_lattice* h, cl_observables* out);
+
+/* Ensembles: advance several independent lattices (equal precision and
+ * n_fields, any N) together, each pass of all members in one persistent
+ * launch, the passes of a call captured in one HIP graph.  Members keep their
+ * own potential, background, scale factor and time step; they must use the
+ * null stream or a common one.  The ensemble does not own the members. */
+cl_status cl_ensemble_create(int n_members, cl_lattice* const* members, cl_ensemble** out);
+cl_status cl_ensemble_set_dt(cl_ensemble* e, int member, double dt);
+/* out: NULL or n_steps * n_members records, step-major ([s][member]). */
+cl_status cl_ensemble_step(cl_ensemble* e, cl_integrator integ, int n_steps, cl_observables* out);
+cl_status cl_ensemble_destroy(cl_ensemble* e);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CL_LATTICE_H */

@@ -1,0 +1,202 @@
+"""ctypes binding of the C ABI in include/cl_lattice.h.
+
+Argument marshalling only: every step of the lattice path runs in the HIP
+library.  Importing this module without the built library raises
+ImportError -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libcl_lattice.so")
+
+CL_OK, CL_EINVAL, CL_ENOMEM, CL_EDEVICE, CL_ESTATE, CL_EUNSTABLE, CL_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+CL_FP64, CL_FP32 = 0, 1
+CL_STATIC, CL_SELF_CONSISTENT = 0, 1
+CL_LEAPFROG, CL_VV4 = 0, 1
+
+STATUS_NAMES = {0: "CL_OK", -1: "CL_EINVAL", -2: "CL_ENOMEM", -3: "CL_EDEVICE", -4: "CL_ESTATE",
+                -5: "CL_EUNSTABLE", -6: "CL_EUNSUPPORTED"}
+
+
+class cl_potential(C.Structure):
+    _fields_ = [("m2", C.c_double * 2), ("lambda_", C.c_double * 2), ("g2", C.c_double), ("V0", C.c_double)]
+
+
+class cl_scalars(C.Structure):
+    _fields_ = [("a", C.c_double), ("b", C.c_double), ("eta", C.c_double), ("step", C.c_int64)]
+
+
+class cl_observables(C.Structure):
+    _fields_ = [("eta", C.c_double), ("a", C.c_double), ("H", C.c_double), ("EK", C.c_double * 2),
+                ("EG", C.c_double * 2), ("EV", C.c_double), ("mean", C.c_double * 2), ("var", C.c_double * 2),
+                ("hubble_residual", C.c_double), ("nonfinite", C.c_int32), ("reserved", C.c_int32)]
+
+
+OBS_DTYPE = np.dtype([("eta", "f8"), ("a", "f8"), ("H", "f8"), ("EK", "f8", 2), ("EG", "f8", 2), ("EV", "f8"),
+                      ("mean", "f8", 2), ("var", "f8", 2), ("r", "f8"), ("nonfinite", "i4"),
+                      ("reserved", "i4")])
+assert OBS_DTYPE.itemsize == C.sizeof(cl_observables)
+
+# Every symbol the header declares, with (restype, argtypes).
+_P = C.c_void_p
+_SIGS = {
+    "cl_last_error": (C.c_char_p, [_P]),
+    "cl_version": (C.c_char_p, []),
+    "cl_create": (C.c_int, [C.c_int, C.c_double, C.c_int, C.c_int, C.POINTER(_P)]),
+    "cl_destroy": (C.c_int, [_P]),
+    "cl_set_stream": (C.c_int, [_P, _P]),
+    "cl_attach_device_buffers": (C.c_int, [_P, C.POINTER(_P), C.POINTER(_P), C.POINTER(_P), C.POINTER(_P)]),
+    "cl_set_background": (C.c_int, [_P, C.c_double, C.c_int, C.c_double, C.c_double]),
+    "cl_set_potential": (C.c_int, [_P, C.POINTER(cl_potential)]),
+    "cl_seed": (C.c_int, [_P, C.c_uint64, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_double, C.c_double]),
+    "cl_set_fields": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "cl_get_fields": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "cl_get_state": (C.c_int, [_P, C.POINTER(cl_scalars)]),
+    "cl_set_state": (C.c_int, [_P, C.POINTER(cl_scalars)]),
+    "cl_step": (C.c_int, [_P, C.c_int, C.c_double, C.c_int, _P]),
+    "cl_read_observables": (C.c_int, [_P, _P]),
+    "cl_ensemble_create": (C.c_int, [C.c_int, C.POINTER(_P), C.POINTER(_P)]),
+    "cl_ensemble_set_dt": (C.c_int, [_P, C.c_int, C.c_double]),
+    "cl_ensemble_step": (C.c_int, [_P, C.c_int, C.c_int, _P]),
+    "cl_ensemble_destroy": (C.c_int, [_P]),
+}
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"HIP library not built: {LIB_PATH} missing (run python -m paper_2607_24978_amd.build)")
+lib = C.CDLL(LIB_PATH)
+for _name, (_res, _args) in _SIGS.items():
+    _fn = getattr(lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+
+class CLError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(st: int, handle=None):
+    if st != CL_OK:
+        msg = lib.cl_last_error(handle)
+        raise CLError(st, msg.decode() if msg else "")
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+PRECISIONS = {"fp64": CL_FP64, "fp32": CL_FP32}
+INTEGRATORS = {"leapfrog": CL_LEAPFROG, "vv4": CL_VV4}
+EXPANSIONS = {"static": CL_STATIC, "self": CL_SELF_CONSISTENT}
+
+
+class Lattice:
+    """One lattice handle (cl_create ... cl_destroy)."""
+
+    def __init__(self, N: int, dx: float, n_fields: int = 1, precision: str = "fp64"):
+        h = _P()
+        _check(lib.cl_create(int(N), float(dx), int(n_fields), PRECISIONS[precision], C.byref(h)))
+        self.h = h
+        self.N, self.dx, self.n_fields, self.precision = int(N), float(dx), int(n_fields), precision
+
+    def close(self):
+        if self.h:
+            lib.cl_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_stream(self, stream_ptr: int):
+        _check(lib.cl_set_stream(self.h, _P(stream_ptr)), self.h)
+
+    def set_background(self, alpha=1.0, expansion="self", mp=1.0, a0=1.0):
+        _check(lib.cl_set_background(self.h, float(alpha), EXPANSIONS[expansion], float(mp), float(a0)), self.h)
+
+    def set_potential(self, m2=(0.0, 0.0), lam=(1.0, 0.0), g2=0.0, V0=0.0):
+        pot = cl_potential((C.c_double * 2)(*m2), (C.c_double * 2)(*lam), float(g2), float(V0))
+        _check(lib.cl_set_potential(self.h, C.byref(pot)), self.h)
+
+    def seed(self, seed: int, fbar, pbar, cutoff: float = 0.0, amp: float = 1.0):
+        fb = np.ascontiguousarray(list(fbar) + [0.0] * (2 - len(fbar)), dtype=np.float64)
+        pb = np.ascontiguousarray(list(pbar) + [0.0] * (2 - len(pbar)), dtype=np.float64)
+        _check(lib.cl_seed(self.h, C.c_uint64(seed), _dptr(fb), _dptr(pb), float(cutoff), float(amp)), self.h)
+
+    def set_fields(self, f: np.ndarray, p: np.ndarray):
+        shape = (self.n_fields, self.N, self.N, self.N)
+        f = np.ascontiguousarray(f, dtype=np.float64).reshape(shape)
+        p = np.ascontiguousarray(p, dtype=np.float64).reshape(shape)
+        _check(lib.cl_set_fields(self.h, _dptr(f), _dptr(p)), self.h)
+
+    def get_fields(self):
+        shape = (self.n_fields, self.N, self.N, self.N)
+        f = np.empty(shape)
+        p = np.empty(shape)
+        _check(lib.cl_get_fields(self.h, _dptr(f), _dptr(p)), self.h)
+        return f, p
+
+    def get_state(self) -> dict:
+        s = cl_scalars()
+        _check(lib.cl_get_state(self.h, C.byref(s)), self.h)
+        return dict(a=s.a, b=s.b, eta=s.eta, step=s.step)
+
+    def set_state(self, a: float, b: float, eta: float, step: int = 0):
+        s = cl_scalars(float(a), float(b), float(eta), int(step))
+        _check(lib.cl_set_state(self.h, C.byref(s)), self.h)
+
+    def step(self, integrator: str, dt: float, n: int, record: bool = True):
+        out = np.zeros(max(n, 0), dtype=OBS_DTYPE) if record else None
+        ptr = _P(out.ctypes.data) if record and n > 0 else None
+        _check(lib.cl_step(self.h, INTEGRATORS[integrator], float(dt), int(n), ptr), self.h)
+        return out
+
+    def read_observables(self):
+        out = np.zeros(1, dtype=OBS_DTYPE)
+        _check(lib.cl_read_observables(self.h, _P(out.ctypes.data)), self.h)
+        return out[0]
+
+
+class Ensemble:
+    """Several lattices advanced together (cl_ensemble_*)."""
+
+    def __init__(self, members):
+        self.members = list(members)
+        arr = (_P * len(self.members))(*[m.h for m in self.members])
+        e = _P()
+        _check(lib.cl_ensemble_create(len(self.members), arr, C.byref(e)))
+        self.e = e
+
+    def set_dt(self, i: int, dt: float):
+        _check(lib.cl_ensemble_set_dt(self.e, int(i), float(dt)))
+
+    def step(self, integrator: str, n: int, record: bool = True):
+        out = np.zeros((max(n, 0), len(self.members)), dtype=OBS_DTYPE) if record else None
+        ptr = _P(out.ctypes.data) if record and n > 0 else None
+        _check(lib.cl_ensemble_step(self.e, INTEGRATORS[integrator], int(n), ptr))
+        return out
+
+    def close(self):
+        if getattr(self, "e", None):
+            lib.cl_ensemble_destroy(self.e)
+            self.e = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

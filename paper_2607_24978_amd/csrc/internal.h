@@ -1,0 +1,94 @@
+// Internal declarations shared by the library's host runtime and its HIP
+// kernels.  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/cl_lattice.h"
+
+namespace cl {
+
+constexpr int kMaxFields = 2;
+// Lattice sums per pass: per field {sum p_sync^2, sum |forward grad f|^2,
+// sum (f - shift), sum (f - shift)^2, sum p_new}, then sum V.
+constexpr int kSumsPerField = 5;
+constexpr int kMaxSums = kSumsPerField * kMaxFields + 1;
+constexpr int nsums(int nf) { return kSumsPerField * nf + 1; }
+
+// Background state and the coefficients of the next pass, in device memory.
+// Written by the last workgroup of every pass, read by the next pass.
+struct Scal {
+    double a;          // scale factor of the field state produced last
+    double b;          // a' (between the passes of one call: the half-step value)
+    double eta;        // time of the state the next pass produces
+    double cd;         // drift coefficient of the next pass: h abar^(alpha-3)
+    double kL;         // a_next^(1+alpha) / dx^2
+    double kV;         // a_next^(3+alpha)
+    double a_next;     // scale factor after the next drift
+    double shift[2];   // predicted mean of f after the next drift (variance shift)
+    double mean_f[2];  // mean of f in the state produced last
+    double mean_p[2];  // mean of the momenta written last
+    int32_t nonfinite; // sticky: a lattice sum was NaN / Inf
+    int32_t pad;
+};
+
+struct Phys {
+    double m2[2], lam[2], g2, V0;
+    double alpha, mp, dx, inv_vol;
+    int nf;
+    int expand;  // 1: self-consistent expansion, 0: static
+};
+
+// Tile of one workgroup: TZ z-values x TY y-rows, marching over CX x-planes.
+struct Tile {
+    int TZ = 0, TY = 0, CX = 0;  // tile extents
+    int RY = 1;                  // y-rows per thread
+    int NT = 0;                  // threads per workgroup
+    int HI = 1;                  // halo items per thread (1 or 2)
+    int nbz = 0, nby = 0, nbx = 0;
+    int nblocks() const { return nbz * nby * nbx; }
+};
+
+// One pass over the lattice: optional drift, kick, lattice sums and the
+// last-workgroup background update.
+struct PassArgs {
+    const void* f_in[2];
+    const void* p_in[2];
+    void* f_out[2];
+    void* p_out[2];
+    int N;
+    int TZ, TY, CX, nbz, nby, nbx;
+    int drift;      // 1: drift f by cd * p before the kick
+    int write_out;  // 0: reduction only (no field writes, no kick)
+    int rec;        // observable slot for this pass, -1: none
+    int pad;
+    double kt;      // kick multiplier for the stored momenta
+    double kb;      // kick multiplier for the synchronised momenta (energies)
+    double h_next;  // drift step of the following pass, 0: call ends here
+    Scal* sc;
+    double* partials;   // nsums(nf) * nblocks doubles
+    unsigned* ticket;   // zero between passes
+    cl_observables* obs;
+    Phys ph;
+};
+
+// Kernel launchers (stencil.hip).  Return the HIP error of the launch.
+hipError_t launch_pass(const PassArgs& a, const Tile& t, cl_precision prec, hipStream_t s);
+hipError_t launch_init_scalars(Scal* sc, double a, double b, double eta, const Phys& ph,
+                               const double* shift, hipStream_t s);
+// Default tile for a lattice; valid for every N accepted by cl_create.
+Tile default_tile(int N, cl_precision prec, int nf);
+// Fill nbz/nby/nbx and check that the tile divides the lattice and fits the
+// kernel's limits.  Returns false if not.
+bool finalize_tile(Tile& t, int N, cl_precision prec);
+size_t pass_lds_bytes(const Tile& t, cl_precision prec, int nf);
+
+// Host seed (host_seed.cpp): fills f, p (n_fields * N^3 FP64 each).
+// Returns an empty string on success, an error message otherwise.
+const char* host_seed(int N, double dx, int nf, const Phys& ph, double a0, uint64_t seed,
+                      const double* fbar, const double* pbar, double cutoff, double amp,
+                      double* f, double* p);
+
+}  // namespace cl

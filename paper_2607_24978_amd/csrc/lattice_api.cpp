@@ -1,0 +1,586 @@
+// Host runtime behind the C ABI of cl_lattice.h: handle state, pass
+// schedules of the integrators, buffer management and error reporting.
+//
+// A call to cl_step issues one opening kick pass and then one fused
+// drift-kick pass per velocity-Verlet sub-step, merging the two half kicks
+// of adjacent sub-steps into one (Sect. 4.1: staggered leapfrog / velocity
+// Verlet, and the 4th-order Yoshida composition).  The scale factor is
+// advanced with the same kicks and drifts by the last workgroup of every
+// pass, so no pass waits for the host.  The passes of a call are captured in
+// a HIP graph and replayed while the call shape stays the same.
+#include "internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using cl::PassArgs;
+using cl::Phys;
+using cl::Scal;
+using cl::Tile;
+
+struct GraphKey {
+    int integ = -1;
+    double dt = 0.0;
+    int n = 0;
+    int cur = 0;
+    bool operator==(const GraphKey& o) const {
+        return integ == o.integ && dt == o.dt && n == o.n && cur == o.cur;
+    }
+};
+
+struct cl_lattice {
+    int N = 0;
+    double dx = 0.0;
+    int nf = 1;
+    cl_precision prec = CL_FP64;
+    double alpha = 1.0, mp = 1.0, a0 = 1.0;
+    cl_expansion mode = CL_SELF_CONSISTENT;
+    cl_potential pot{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool own_buffers = true;
+    int device = 0;
+    void* buf[2][2][2] = {};  // [ping-pong][0 = f, 1 = p][field]
+    int cur = 0;
+    Scal* sc = nullptr;
+    double* partials = nullptr;
+    size_t partials_cap = 0;  // doubles
+    unsigned* ticket = nullptr;
+    cl_observables* obs = nullptr;
+    int obs_cap = 0;
+    Tile tile;
+    int64_t step = 0;
+    hipGraphExec_t gexec = nullptr;
+    GraphKey gkey;
+    bool use_graph = true;
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+size_t elem_size(cl_precision p) { return p == CL_FP32 ? 4 : 8; }
+size_t sites(const cl_lattice* h) { return static_cast<size_t>(h->N) * h->N * h->N; }
+
+cl_status fail(cl_lattice* h, cl_status st, const std::string& msg) {
+    if (h) h->err = msg; else g_err = msg;
+    return st;
+}
+
+#define HIPCHECK(h, call)                                                                   \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail((h), CL_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+Phys make_phys(const cl_lattice* h) {
+    Phys p{};
+    for (int j = 0; j < 2; ++j) {
+        p.m2[j] = h->pot.m2[j];
+        p.lam[j] = h->pot.lambda[j];
+    }
+    p.g2 = h->pot.g2;
+    p.V0 = h->pot.V0;
+    p.alpha = h->alpha;
+    p.mp = h->mp;
+    p.dx = h->dx;
+    p.inv_vol = 1.0 / static_cast<double>(sites(h));
+    p.nf = h->nf;
+    p.expand = h->mode == CL_SELF_CONSISTENT ? 1 : 0;
+    return p;
+}
+
+void drop_graph(cl_lattice* h) {
+    if (h->gexec) hipGraphExecDestroy(h->gexec);
+    h->gexec = nullptr;
+    h->gkey = GraphKey{};
+}
+
+bool valid_N(int N, cl_precision prec) {
+    if (N < 8 || N > 1600 || (N % 2)) return false;
+    const bool pow2 = (N & (N - 1)) == 0;
+    const int big = prec == CL_FP32 ? 256 : 128;
+    return pow2 || (N % big == 0);
+}
+
+cl_status ensure_partials(cl_lattice* h) {
+    const size_t need = static_cast<size_t>(cl::nsums(h->nf)) * h->tile.nblocks();
+    if (need <= h->partials_cap) return CL_OK;
+    if (h->partials) hipFree(h->partials);
+    h->partials = nullptr;
+    h->partials_cap = 0;
+    HIPCHECK(h, hipMalloc(&h->partials, need * sizeof(double)));
+    h->partials_cap = need;
+    drop_graph(h);
+    return CL_OK;
+}
+
+cl_status ensure_obs(cl_lattice* h, int n) {
+    if (n <= h->obs_cap) return CL_OK;
+    if (h->obs) hipFree(h->obs);
+    h->obs = nullptr;
+    h->obs_cap = 0;
+    int cap = 64;
+    while (cap < n) cap *= 2;
+    HIPCHECK(h, hipMalloc(&h->obs, static_cast<size_t>(cap) * sizeof(cl_observables)));
+    h->obs_cap = cap;
+    drop_graph(h);
+    return CL_OK;
+}
+
+PassArgs base_args(cl_lattice* h, int in) {
+    PassArgs a{};
+    for (int j = 0; j < 2; ++j) {
+        const int jj = j < h->nf ? j : 0;
+        a.f_in[j] = h->buf[in][0][jj];
+        a.p_in[j] = h->buf[in][1][jj];
+        a.f_out[j] = h->buf[in ^ 1][0][jj];
+        a.p_out[j] = h->buf[in ^ 1][1][jj];
+    }
+    a.N = h->N;
+    a.TZ = h->tile.TZ;
+    a.TY = h->tile.TY;
+    a.CX = h->tile.CX;
+    a.nbz = h->tile.nbz;
+    a.nby = h->tile.nby;
+    a.nbx = h->tile.nbx;
+    a.sc = h->sc;
+    a.partials = h->partials;
+    a.ticket = h->ticket;
+    a.obs = h->obs;
+    a.ph = make_phys(h);
+    a.rec = -1;
+    return a;
+}
+
+// Sub-step sizes of n full steps.
+void substeps(cl_integrator integ, double dt, int n, std::vector<double>& h, int& per_step) {
+    h.clear();
+    if (integ == CL_VV4) {
+        const double w1 = 1.0 / (2.0 - std::cbrt(2.0));
+        const double w0 = 1.0 - 2.0 * w1;
+        per_step = 3;
+        for (int i = 0; i < n; ++i) {
+            h.push_back(w1 * dt);
+            h.push_back(w0 * dt);
+            h.push_back(w1 * dt);
+        }
+    } else {
+        per_step = 1;
+        h.assign(n, dt);
+    }
+}
+
+// Issue the passes of n steps on the handle's stream.  Returns the final
+// buffer index.
+cl_status issue_steps(cl_lattice* h, cl_integrator integ, double dt, int n, int cur) {
+    std::vector<double> hs;
+    int per = 1;
+    substeps(integ, dt, n, hs, per);
+    const int M = static_cast<int>(hs.size());
+    // Opening half kick (no drift): pi += h_1/2 F(f, a), a' += h_1/2 a''.
+    PassArgs k = base_args(h, cur);
+    k.drift = 0;
+    k.write_out = 1;
+    k.kt = 0.5 * hs[0];
+    k.kb = 0.0;
+    k.h_next = hs[0];
+    HIPCHECK(h, cl::launch_pass(k, h->tile, h->prec, h->stream));
+    cur ^= 1;
+    for (int s = 0; s < M; ++s) {
+        PassArgs d = base_args(h, cur);
+        d.drift = 1;
+        d.write_out = 1;
+        d.kb = 0.5 * hs[s];
+        d.kt = s + 1 < M ? 0.5 * (hs[s] + hs[s + 1]) : 0.5 * hs[s];
+        d.h_next = s + 1 < M ? hs[s + 1] : 0.0;
+        d.rec = ((s + 1) % per == 0) ? (s + 1) / per - 1 : -1;
+        HIPCHECK(h, cl::launch_pass(d, h->tile, h->prec, h->stream));
+        cur ^= 1;
+    }
+    return CL_OK;
+}
+
+cl_status init_scalars(cl_lattice* h, double a, double b, double eta, const double* shift) {
+    const Phys ph = make_phys(h);
+    HIPCHECK(h, cl::launch_init_scalars(h->sc, a, b, eta, ph, shift, h->stream));
+    return CL_OK;
+}
+
+// One reduction-only pass over the current state into obs[0].
+cl_status reduce_pass(cl_lattice* h, cl_observables* out) {
+    cl_status st = ensure_obs(h, 1);
+    if (st) return st;
+    PassArgs r = base_args(h, h->cur);
+    r.drift = 0;
+    r.write_out = 0;
+    r.kt = 0.0;
+    r.kb = 0.0;
+    r.h_next = 0.0;
+    r.rec = 0;
+    HIPCHECK(h, cl::launch_pass(r, h->tile, h->prec, h->stream));
+    HIPCHECK(h, hipMemcpyAsync(out, h->obs, sizeof(cl_observables), hipMemcpyDeviceToHost, h->stream));
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    return CL_OK;
+}
+
+// After new fields: a = a0, eta = 0, b from the Hubble constraint.
+cl_status reset_background(cl_lattice* h, const double* mean) {
+    cl_status st = init_scalars(h, h->a0, 0.0, 0.0, mean);
+    if (st) return st;
+    cl_observables o;
+    st = reduce_pass(h, &o);
+    if (st) return st;
+    double b0 = 0.0;
+    if (o.nonfinite) {
+        init_scalars(h, h->a0, 0.0, 0.0, mean);
+        h->step = 0;
+        return fail(h, CL_EUNSTABLE, "non-finite field values");
+    }
+    if (h->mode == CL_SELF_CONSISTENT) {
+        const double rho = o.EK[0] + o.EK[1] + o.EG[0] + o.EG[1] + o.EV;
+        if (!(rho > 0.0)) return fail(h, CL_EINVAL, "lattice energy density is not positive; a' undefined");
+        b0 = h->a0 * std::sqrt(std::pow(h->a0, 2.0 * h->alpha) * rho / (3.0 * h->mp * h->mp));
+    }
+    st = init_scalars(h, h->a0, b0, 0.0, o.mean);
+    if (st) return st;
+    h->step = 0;
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    return CL_OK;
+}
+
+template <typename T>
+cl_status upload(cl_lattice* h, const double* f, const double* p) {
+    const size_t n = sites(h);
+    std::vector<T> tmp;
+    try {
+        tmp.resize(n);
+    } catch (const std::bad_alloc&) {
+        return fail(h, CL_ENOMEM, "host staging buffer");
+    }
+    for (int which = 0; which < 2; ++which) {
+        const double* src = which == 0 ? f : p;
+        for (int j = 0; j < h->nf; ++j) {
+            const double* s = src + j * n;
+            for (size_t i = 0; i < n; ++i) tmp[i] = static_cast<T>(s[i]);
+            HIPCHECK(h, hipMemcpyAsync(h->buf[h->cur][which][j], tmp.data(), n * sizeof(T),
+                                       hipMemcpyHostToDevice, h->stream));
+            HIPCHECK(h, hipStreamSynchronize(h->stream));
+        }
+    }
+    return CL_OK;
+}
+
+template <typename T>
+cl_status download(cl_lattice* h, double* f, double* p) {
+    const size_t n = sites(h);
+    std::vector<T> tmp;
+    try {
+        tmp.resize(n);
+    } catch (const std::bad_alloc&) {
+        return fail(h, CL_ENOMEM, "host staging buffer");
+    }
+    for (int which = 0; which < 2; ++which) {
+        double* dst = which == 0 ? f : p;
+        if (!dst) continue;
+        for (int j = 0; j < h->nf; ++j) {
+            HIPCHECK(h, hipMemcpyAsync(tmp.data(), h->buf[h->cur][which][j], n * sizeof(T),
+                                       hipMemcpyDeviceToHost, h->stream));
+            HIPCHECK(h, hipStreamSynchronize(h->stream));
+            double* d = dst + j * n;
+            for (size_t i = 0; i < n; ++i) d[i] = static_cast<double>(tmp[i]);
+        }
+    }
+    return CL_OK;
+}
+
+void host_means(const cl_lattice* h, const double* f, double* mean) {
+    const size_t n = sites(h);
+    for (int j = 0; j < 2; ++j) mean[j] = 0.0;
+    for (int j = 0; j < h->nf; ++j) {
+        double s = 0.0;
+        for (size_t i = 0; i < n; ++i) s += f[j * n + i];
+        mean[j] = s / static_cast<double>(n);
+    }
+}
+
+void free_buffers(cl_lattice* h) {
+    if (!h->own_buffers) return;
+    for (auto& a : h->buf)
+        for (auto& b : a)
+            for (auto& c : b) {
+                if (c) hipFree(c);
+                c = nullptr;
+            }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* cl_version(void) { return "cl_lattice 0.1 (gfx950)"; }
+
+const char* cl_last_error(const cl_lattice* h) { return h ? h->err.c_str() : g_err.c_str(); }
+
+cl_status cl_create(int N, double dx, int n_fields, cl_precision prec, cl_lattice** out) {
+    if (!out) return fail(nullptr, CL_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (prec != CL_FP32 && prec != CL_FP64) return fail(nullptr, CL_EINVAL, "precision must be CL_FP32 or CL_FP64");
+    if (!valid_N(N, prec))
+        return fail(nullptr, CL_EINVAL,
+                    "N must be a power of two in [8, 1024] or a multiple of 256 (FP32) / 128 (FP64) up to 1600");
+    if (!(dx > 0.0) || !std::isfinite(dx)) return fail(nullptr, CL_EINVAL, "dx must be positive and finite");
+    if (n_fields != 1 && n_fields != 2) return fail(nullptr, CL_EINVAL, "n_fields must be 1 or 2");
+    cl_lattice* h = new (std::nothrow) cl_lattice;
+    if (!h) return fail(nullptr, CL_ENOMEM, "handle");
+    h->N = N;
+    h->dx = dx;
+    h->nf = n_fields;
+    h->prec = prec;
+    h->pot.lambda[0] = 1.0;
+    const char* ng = std::getenv("CL_NO_GRAPH");
+    h->use_graph = !(ng && ng[0] == '1');
+    auto bail = [&](cl_status st, const std::string& m) {
+        g_err = m;
+        cl_destroy(h);
+        return st;
+    };
+    if (hipGetDevice(&h->device) != hipSuccess) return bail(CL_EDEVICE, "no HIP device");
+    if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess)
+        return bail(CL_EDEVICE, "hipStreamCreate failed");
+    h->own_stream = true;
+    const size_t bytes = sites(h) * elem_size(prec);
+    for (int pp = 0; pp < 2; ++pp)
+        for (int w = 0; w < 2; ++w)
+            for (int j = 0; j < n_fields; ++j) {
+                if (hipMalloc(&h->buf[pp][w][j], bytes) != hipSuccess) {
+                    h->buf[pp][w][j] = nullptr;
+                    return bail(CL_ENOMEM, "device field buffers (" + std::to_string(4 * n_fields * bytes) +
+                                               " bytes)");
+                }
+                hipMemsetAsync(h->buf[pp][w][j], 0, bytes, h->stream);
+            }
+    if (hipMalloc(&h->sc, sizeof(Scal)) != hipSuccess) return bail(CL_ENOMEM, "scalar block");
+    if (hipMalloc(&h->ticket, 64) != hipSuccess) return bail(CL_ENOMEM, "ticket");
+    if (hipMemsetAsync(h->ticket, 0, 64, h->stream) != hipSuccess) return bail(CL_EDEVICE, "memset");
+    h->tile = cl::default_tile(N, prec, n_fields);
+    if (ensure_partials(h) != CL_OK) return bail(CL_ENOMEM, h->err);
+    double zero[2] = {0.0, 0.0};
+    if (init_scalars(h, 1.0, 0.0, 0.0, zero) != CL_OK) return bail(CL_EDEVICE, h->err);
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return bail(CL_EDEVICE, "sync");
+    *out = h;
+    return CL_OK;
+}
+
+cl_status cl_destroy(cl_lattice* h) {
+    if (!h) return CL_OK;
+    if (h->stream) hipStreamSynchronize(h->stream);
+    drop_graph(h);
+    free_buffers(h);
+    if (h->sc) hipFree(h->sc);
+    if (h->partials) hipFree(h->partials);
+    if (h->ticket) hipFree(h->ticket);
+    if (h->obs) hipFree(h->obs);
+    if (h->own_stream && h->stream) hipStreamDestroy(h->stream);
+    delete h;
+    return CL_OK;
+}
+
+cl_status cl_set_stream(cl_lattice* h, void* s) {
+    if (!h) return fail(nullptr, CL_EINVAL, "handle is NULL");
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    if (h->own_stream) hipStreamDestroy(h->stream);
+    h->own_stream = false;
+    h->stream = static_cast<hipStream_t>(s);
+    drop_graph(h);
+    return CL_OK;
+}
+
+cl_status cl_attach_device_buffers(cl_lattice* h, void* const* f, void* const* p, void* const* fpp,
+                                   void* const* ppp) {
+    if (!h) return fail(nullptr, CL_EINVAL, "handle is NULL");
+    if (!f || !p || !fpp || !ppp) return fail(h, CL_EINVAL, "buffer arrays must not be NULL");
+    for (int j = 0; j < h->nf; ++j) {
+        void* arr[4] = {f[j], p[j], fpp[j], ppp[j]};
+        for (void* x : arr) {
+            if (!x) return fail(h, CL_EINVAL, "device buffer pointer is NULL");
+            if (reinterpret_cast<uintptr_t>(x) % 16) return fail(h, CL_EINVAL, "device buffers must be 16-byte aligned");
+        }
+    }
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    free_buffers(h);
+    h->own_buffers = false;
+    h->cur = 0;
+    for (int j = 0; j < h->nf; ++j) {
+        h->buf[0][0][j] = f[j];
+        h->buf[0][1][j] = p[j];
+        h->buf[1][0][j] = fpp[j];
+        h->buf[1][1][j] = ppp[j];
+    }
+    drop_graph(h);
+    return CL_OK;
+}
+
+cl_status cl_set_background(cl_lattice* h, double alpha, cl_expansion mode, double m_p, double a0) {
+    if (!h) return fail(nullptr, CL_EINVAL, "handle is NULL");
+    if (!std::isfinite(alpha)) return fail(h, CL_EINVAL, "alpha must be finite");
+    if (mode != CL_STATIC && mode != CL_SELF_CONSISTENT) return fail(h, CL_EINVAL, "unknown expansion mode");
+    if (!(m_p > 0.0) || !std::isfinite(m_p)) return fail(h, CL_EINVAL, "m_p must be positive");
+    if (!(a0 > 0.0) || !std::isfinite(a0)) return fail(h, CL_EINVAL, "a0 must be positive");
+    if (mode == CL_STATIC && a0 != 1.0) return fail(h, CL_EINVAL, "static space needs a0 = 1");
+    h->alpha = alpha;
+    h->mode = mode;
+    h->mp = m_p;
+    h->a0 = a0;
+    drop_graph(h);
+    return CL_OK;
+}
+
+cl_status cl_set_potential(cl_lattice* h, const cl_potential* pot) {
+    if (!h) return fail(nullptr, CL_EINVAL, "handle is NULL");
+    if (!pot) return fail(h, CL_EINVAL, "potential is NULL");
+    const double* v = &pot->m2[0];
+    for (int i = 0; i < 6; ++i)
+        if (!std::isfinite(v[i])) return fail(h, CL_EINVAL, "potential coefficients must be finite");
+    h->pot = *pot;
+    drop_graph(h);
+    return CL_OK;
+}
+
+cl_status cl_set_fields(cl_lattice* h, const double* f, const double* p) {
+    if (!h) return fail(nullptr, CL_EINVAL, "handle is NULL");
+    if (!f || !p) return fail(h, CL_EINVAL, "field arrays must not be NULL");
+    cl_status st = h->prec == CL_FP32 ? upload<float>(h, f, p) : upload<double>(h, f, p);
+    if (st) return st;
+    double mean[2];
+    host_means(h, f, mean);
+    return reset_background(h, mean);
+}
+
+cl_status cl_get_fields(cl_lattice* h, double* f, double* p) {
+    if (!h) return fail(nullptr, CL_EINVAL, "handle is NULL");
+    if (!f && !p) return fail(h, CL_EINVAL, "both output arrays are NULL");
+    return h->prec == CL_FP32 ? download<float>(h, f, p) : download<double>(h, f, p);
+}
+
+cl_status cl_seed(cl_lattice* h, uint64_t seed, const double* fbar, const double* pbar, double cutoff,
+                  double amp) {
+    if (!h) return fail(nullptr, CL_EINVAL, "handle is NULL");
+    if (!fbar || !pbar) return fail(h, CL_EINVAL, "fbar / pbar must not be NULL");
+    if (h->N & (h->N - 1)) return fail(h, CL_EUNSUPPORTED, "cl_seed needs N to be a power of two");
+    if (!std::isfinite(amp) || amp < 0.0) return fail(h, CL_EINVAL, "amp must be finite and >= 0");
+    if (cutoff <= 0.0) cutoff = h->N / 4.0;
+    const size_t n = sites(h) * h->nf;
+    std::vector<double> f, p;
+    try {
+        f.resize(n);
+        p.resize(n);
+    } catch (const std::bad_alloc&) {
+        return fail(h, CL_ENOMEM, "host seed arrays");
+    }
+    const Phys ph = make_phys(h);
+    const char* e = cl::host_seed(h->N, h->dx, h->nf, ph, h->a0, seed, fbar, pbar, cutoff, amp, f.data(), p.data());
+    if (e && e[0]) return fail(h, CL_EINVAL, e);
+    return cl_set_fields(h, f.data(), p.data());
+}
+
+cl_status cl_get_state(const cl_lattice* hc, cl_scalars* out) {
+    cl_lattice* h = const_cast<cl_lattice*>(hc);
+    if (!h) return fail(nullptr, CL_EINVAL, "handle is NULL");
+    if (!out) return fail(h, CL_EINVAL, "out is NULL");
+    Scal s;
+    HIPCHECK(h, hipMemcpyAsync(&s, h->sc, sizeof(Scal), hipMemcpyDeviceToHost, h->stream));
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    out->a = s.a;
+    out->b = s.b;
+    out->eta = s.eta;
+    out->step = h->step;
+    return CL_OK;
+}
+
+cl_status cl_set_state(cl_lattice* h, const cl_scalars* in) {
+    if (!h) return fail(nullptr, CL_EINVAL, "handle is NULL");
+    if (!in) return fail(h, CL_EINVAL, "in is NULL");
+    if (!(in->a > 0.0) || !std::isfinite(in->b) || !std::isfinite(in->eta) || in->step < 0)
+        return fail(h, CL_EINVAL, "invalid background state");
+    if (h->mode == CL_STATIC && (in->a != 1.0 || in->b != 0.0))
+        return fail(h, CL_EINVAL, "static space needs a = 1, a' = 0");
+    Scal s;
+    HIPCHECK(h, hipMemcpyAsync(&s, h->sc, sizeof(Scal), hipMemcpyDeviceToHost, h->stream));
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    cl_status st = init_scalars(h, in->a, in->b, in->eta, s.mean_f);
+    if (st) return st;
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    h->step = in->step;
+    return CL_OK;
+}
+
+cl_status cl_step(cl_lattice* h, cl_integrator integ, double dt, int n, cl_observables* per_step) {
+    if (!h) return fail(nullptr, CL_EINVAL, "handle is NULL");
+    if (integ != CL_LEAPFROG && integ != CL_VV4) return fail(h, CL_EINVAL, "unknown integrator");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(h, CL_EINVAL, "dt must be positive and finite");
+    if (n < 0) return fail(h, CL_EINVAL, "n must be >= 0");
+    if (n == 0) return CL_OK;
+    if (dt * std::sqrt(12.0) / h->dx >= 2.0)
+        return fail(h, CL_EUNSTABLE, "dt exceeds the Courant bound dt*sqrt(12)/dx < 2");
+    cl_status st = ensure_obs(h, n);
+    if (st) return st;
+    const GraphKey key{static_cast<int>(integ), dt, n, h->cur};
+    const int passes = 1 + n * (integ == CL_VV4 ? 3 : 1);
+    if (h->use_graph && n > 1) {
+        if (!(h->gexec && h->gkey == key)) {
+            drop_graph(h);
+            hipGraph_t g = nullptr;
+            HIPCHECK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+            st = issue_steps(h, integ, dt, n, h->cur);
+            hipError_t e = hipStreamEndCapture(h->stream, &g);
+            if (st) {
+                if (g) hipGraphDestroy(g);
+                return st;
+            }
+            if (e != hipSuccess) return fail(h, CL_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+            e = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+            hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                h->gexec = nullptr;
+                return fail(h, CL_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+            }
+            h->gkey = key;
+        }
+        HIPCHECK(h, hipGraphLaunch(h->gexec, h->stream));
+    } else {
+        st = issue_steps(h, integ, dt, n, h->cur);
+        if (st) return st;
+    }
+    if (passes % 2) h->cur ^= 1;
+    if (per_step)
+        HIPCHECK(h, hipMemcpyAsync(per_step, h->obs, static_cast<size_t>(n) * sizeof(cl_observables),
+                                   hipMemcpyDeviceToHost, h->stream));
+    Scal s;
+    HIPCHECK(h, hipMemcpyAsync(&s, h->sc, sizeof(Scal), hipMemcpyDeviceToHost, h->stream));
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    h->step += n;
+    if (s.nonfinite) return fail(h, CL_EUNSTABLE, "non-finite lattice sums (unstable evolution)");
+    return CL_OK;
+}
+
+cl_status cl_read_observables(cl_lattice* h, cl_observables* out) {
+    if (!h) return fail(nullptr, CL_EINVAL, "handle is NULL");
+    if (!out) return fail(h, CL_EINVAL, "out is NULL");
+    // Two passes: the first fixes the variance shift at the exact mean.
+    cl_observables o;
+    cl_status st = reduce_pass(h, &o);
+    if (st) return st;
+    return reduce_pass(h, out);
+}
+
+}  // extern "C"

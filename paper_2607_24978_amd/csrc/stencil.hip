@@ -1,0 +1,542 @@
+// Lattice pass kernels for gfx950: fused drift + kick + lattice sums, with
+// the scale-factor (Friedmann) update done by the last workgroup.
+//
+// Physics (CosmoLattice 2.0):
+//   drift   f += cd * pi,            cd = h abar^(alpha-3)      (pi = a^(3-alpha) f')
+//   kick    pi += k * F,  F = a^(1+alpha) Lap f - a^(3+alpha) dV/df   (Eq. singletEOM)
+//   sums    pi_sync^2, forward-difference gradients, V, moments  (Eq. energy-contrib)
+//   a''     = a^(2 alpha+1) [(2 alpha-1) rho - 3 p] / (6 m_p^2)  (Eq. Friedmann1)
+// The scale factor rides along as a homogeneous degree of freedom with its
+// own kick and drift (Sect. 4.1, Eqs. SchemeContVirgin1-2).
+//
+// Memory layout: one array per field and per momentum, z fastest.  A pass
+// reads (f, pi) from one buffer pair and writes the other (ping-pong), since
+// the drift of halo cells needs the old momenta of neighbouring tiles.
+//
+// Blocking: a workgroup owns a TZ x TY tile of (z, y) and marches over CX
+// x-planes.  Each x-plane of drifted f (tile plus a one-cell y/z halo) is
+// staged in LDS (double-buffered, one barrier per plane); the x-neighbours
+// live in registers.  Each thread owns V consecutive z values (16-byte
+// vector loads and stores) in RY rows.
+#include "internal.h"
+
+#include <hip/hip_runtime.h>
+#include <cmath>
+
+namespace cl {
+
+template <typename T> struct VecOf;
+template <> struct VecOf<float> { using type = float4; static constexpr int V = 4; };
+template <> struct VecOf<double> { using type = double2; static constexpr int V = 2; };
+
+template <typename T>
+__device__ __forceinline__ void vload(const T* p, T (&out)[VecOf<T>::V]) {
+    using VT = typename VecOf<T>::type;
+    VT v = *reinterpret_cast<const VT*>(p);
+    if constexpr (VecOf<T>::V == 4) { out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w; }
+    else { out[0] = v.x; out[1] = v.y; }
+}
+
+template <typename T>
+__device__ __forceinline__ void vstore(T* p, const T (&in)[VecOf<T>::V]) {
+    using VT = typename VecOf<T>::type;
+    VT v;
+    if constexpr (VecOf<T>::V == 4) { v.x = in[0]; v.y = in[1]; v.z = in[2]; v.w = in[3]; }
+    else { v.x = in[0]; v.y = in[1]; }
+    *reinterpret_cast<VT*>(p) = v;
+}
+
+// Site potential in FP64: sum_j (m2 f^2/2 + lam f^4/4) + g2 f0^2 f1^2 / 2 (V0 added later).
+template <int NF>
+__device__ __forceinline__ double site_V(const double (&f)[NF], const Phys& P) {
+    double V = 0.0;
+#pragma unroll
+    for (int j = 0; j < NF; ++j) {
+        const double f2 = f[j] * f[j];
+        V += 0.5 * P.m2[j] * f2 + 0.25 * P.lam[j] * f2 * f2;
+    }
+    if constexpr (NF == 2) V += 0.5 * P.g2 * f[0] * f[0] * f[1] * f[1];
+    return V;
+}
+
+// dV/df_j in the field precision.
+template <typename T, int NF>
+__device__ __forceinline__ void site_dV(const T (&f)[NF], const T (&m2)[2], const T (&lam)[2], T g2,
+                                        T (&dV)[NF]) {
+#pragma unroll
+    for (int j = 0; j < NF; ++j) dV[j] = f[j] * (m2[j] + lam[j] * f[j] * f[j]);
+    if constexpr (NF == 2) {
+        dV[0] += g2 * f[0] * f[1] * f[1];
+        dV[1] += g2 * f[0] * f[0] * f[1];
+    }
+}
+
+// Last workgroup of a pass: observables and the scale-factor kick/drift.
+// `tot` holds the lattice sums.  Runs on one thread.
+__device__ void finish_pass(const PassArgs& A, const double* tot) {
+    const Phys& P = A.ph;
+    Scal* sc = A.sc;
+    const int nf = P.nf;
+    const double a = sc->a_next;  // scale factor of the state just produced
+    const double a2 = a * a;
+    const double a6 = a2 * a2 * a2;
+    double EK[2] = {0.0, 0.0}, EG[2] = {0.0, 0.0}, mean[2] = {0.0, 0.0};
+    double var[2] = {0.0, 0.0}, meanp[2] = {0.0, 0.0};
+    int bad = 0;
+    for (int j = 0; j < nf; ++j) {
+        const double* t = tot + kSumsPerField * j;
+        EK[j] = t[0] * P.inv_vol / (2.0 * a6);
+        EG[j] = t[1] * P.inv_vol / (2.0 * a2 * P.dx * P.dx);
+        const double m1 = t[2] * P.inv_vol;
+        mean[j] = sc->shift[j] + m1;
+        var[j] = t[3] * P.inv_vol - m1 * m1;
+        meanp[j] = t[4] * P.inv_vol;
+    }
+    const double EV = tot[kSumsPerField * nf] * P.inv_vol + P.V0;
+    for (int k = 0; k < nsums(nf); ++k) bad |= !isfinite(tot[k]);
+    const double K = EK[0] + EK[1], G = EG[0] + EG[1];
+    const double rho = K + G + EV;
+    const double pr = K - G / 3.0 - EV;
+    double acc = 0.0, r = 0.0;
+    const double b_half = sc->b;
+    if (P.expand) {
+        acc = pow(a, 2.0 * P.alpha + 1.0) * ((2.0 * P.alpha - 1.0) * rho - 3.0 * pr) / (6.0 * P.mp * P.mp);
+    }
+    const double bs = b_half + A.kb * acc;
+    if (P.expand) {
+        const double rhs = pow(a, 2.0 * P.alpha) * rho / (3.0 * P.mp * P.mp);
+        const double H = bs / a;
+        r = fabs(H * H - rhs) / rhs;
+    }
+    if (A.rec >= 0) {
+        cl_observables o;
+        o.eta = sc->eta;
+        o.a = a;
+        o.H = bs / a;
+        for (int j = 0; j < 2; ++j) {
+            o.EK[j] = EK[j];
+            o.EG[j] = EG[j];
+            o.mean[j] = mean[j];
+            o.var[j] = var[j];
+        }
+        o.EV = EV;
+        o.hubble_residual = r;
+        o.nonfinite = bad;
+        o.reserved = 0;
+        A.obs[A.rec] = o;
+    }
+    const double b_new = b_half + A.kt * acc;
+    sc->a = a;
+    sc->b = b_new;
+    sc->nonfinite |= bad;
+    for (int j = 0; j < 2; ++j) {
+        sc->mean_f[j] = mean[j];
+        sc->mean_p[j] = meanp[j];
+    }
+    if (A.h_next != 0.0) {
+        const double an = P.expand ? a + A.h_next * b_new : a;
+        const double abar = 0.5 * (a + an);
+        sc->cd = A.h_next * pow(abar, P.alpha - 3.0);
+        sc->kL = pow(an, 1.0 + P.alpha) / (P.dx * P.dx);
+        sc->kV = pow(an, 3.0 + P.alpha);
+        sc->a_next = an;
+        sc->eta += A.h_next;
+        for (int j = 0; j < 2; ++j) sc->shift[j] = mean[j] + sc->cd * meanp[j];
+    } else {
+        sc->cd = 0.0;
+        sc->a_next = a;
+        for (int j = 0; j < 2; ++j) sc->shift[j] = mean[j];
+    }
+}
+
+// Block-wide reduction of NS per-thread FP64 sums, partial store, ticket,
+// and -- in the last workgroup to arrive -- the deterministic final sum and
+// finish_pass.
+template <int NS>
+__device__ void reduce_and_finish(const PassArgs& A, double (&acc)[NS], int NT, int bid, int nblocks) {
+    __shared__ double wsum[4][kMaxSums];
+    __shared__ int am_last;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        double v = acc[k];
+        for (int off = 32; off > 0; off >>= 1)
+            if (off < NT) v += __shfl_xor(v, off, 64);
+        if (lane == 0) wsum[wave][k] = v;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const int nw = (NT + 63) / 64;
+        for (int k = 0; k < NS; ++k) {
+            double s = wsum[0][k];
+            for (int w = 1; w < nw; ++w) s += wsum[w][k];
+            A.partials[(size_t)k * nblocks + bid] = s;
+        }
+        const unsigned t = __hip_atomic_fetch_add(A.ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        am_last = (t == (unsigned)(nblocks - 1));
+    }
+    __syncthreads();
+    if (!am_last) return;
+    __atomic_thread_fence(__ATOMIC_ACQUIRE);
+    // Fixed-order sum: thread t adds partials t, t+NT, ... with Neumaier
+    // compensation, then a pairwise tree over threads in LDS.
+    __shared__ double tree[256];
+    __shared__ double tot[kMaxSums];
+    for (int k = 0; k < NS; ++k) {
+        double s = 0.0, c = 0.0;
+        const double* src = A.partials + (size_t)k * nblocks;
+        for (int i = tid; i < nblocks; i += NT) {
+            const double x = src[i];
+            const double t = s + x;
+            c += (fabs(s) >= fabs(x)) ? (s - t) + x : (x - t) + s;
+            s = t;
+        }
+        tree[tid] = s + c;
+        __syncthreads();
+        for (int w = NT / 2; w > 0; w >>= 1) {
+            if (tid < w) tree[tid] += tree[tid + w];
+            __syncthreads();
+        }
+        if (tid == 0) tot[k] = tree[0];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        finish_pass(A, tot);
+        *A.ticket = 0u;
+    }
+}
+
+template <typename T, int NF, int RY, int HI>
+__global__ __launch_bounds__(256) void lattice_pass(PassArgs A) {
+    constexpr int V = VecOf<T>::V;
+    constexpr int NS = kSumsPerField * NF + 1;
+    const int N = A.N, TZ = A.TZ, TY = A.TY, CX = A.CX;
+    const int BZ = TZ / V;
+    const int RL = TY / RY;
+    const int NT = BZ * RL;
+    const int tid = threadIdx.x;
+    const int tz = tid % BZ;
+    const int tr = tid / BZ;
+    const int nblocks = A.nbz * A.nby * A.nbx;
+
+    // XCD-aware order: consecutive workgroup ids land on different XCDs
+    // (round robin over 8), so give XCD k a contiguous range of tiles; its
+    // co-resident workgroups then share y/z halos in their L2.
+    int bid = blockIdx.x;
+    {
+        const int G = nblocks;
+        const int per = G / 8, rem = G % 8;
+        const int xcd = bid % 8, slot = bid / 8;
+        bid = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + slot;
+        if (per == 0) bid = blockIdx.x;
+    }
+    const int bz = bid % A.nbz;
+    const int by = (bid / A.nbz) % A.nby;
+    const int bx = bid / (A.nbz * A.nby);
+    const int z0 = bz * TZ, y0 = by * TY, x0 = bx * CX;
+
+    const T* fin[NF];
+    const T* pin[NF];
+    T* fout[NF];
+    T* pout[NF];
+#pragma unroll
+    for (int j = 0; j < NF; ++j) {
+        fin[j] = static_cast<const T*>(A.f_in[j]);
+        pin[j] = static_cast<const T*>(A.p_in[j]);
+        fout[j] = static_cast<T*>(A.f_out[j]);
+        pout[j] = static_cast<T*>(A.p_out[j]);
+    }
+
+    const Scal* sc = A.sc;
+    const T cd = A.drift ? static_cast<T>(sc->cd) : T(0);
+    const T kL = static_cast<T>(sc->kL);
+    const T kV = static_cast<T>(sc->kV);
+    const T kt = static_cast<T>(A.kt);
+    const T kb = static_cast<T>(A.kb);
+    double shift[NF];
+#pragma unroll
+    for (int j = 0; j < NF; ++j) shift[j] = sc->shift[j];
+    T m2[2] = {static_cast<T>(A.ph.m2[0]), static_cast<T>(A.ph.m2[1])};
+    T lam[2] = {static_cast<T>(A.ph.lam[0]), static_cast<T>(A.ph.lam[1])};
+    const T g2 = static_cast<T>(A.ph.g2);
+
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* lds = reinterpret_cast<T*>(smem_raw);
+    const int S = TZ + 2 * V;        // LDS row stride (interior starts at column V)
+    const int PL = (TY + 2) * S;     // one plane of one field
+    // lds[buf][field][row][col]; row 0 = y0-1, row TY+1 = y0+TY.
+
+    // Global row offsets of own rows.
+    const int zc = z0 + tz * V;
+    int yrow[RY];
+#pragma unroll
+    for (int k = 0; k < RY; ++k) yrow[k] = y0 + tr + k * RL;
+
+    // Halo items of this thread (row halo: V values; z halo: 1 value).
+    const int nhalo = 2 * BZ + 2 * TY;
+    int h_goff[HI];   // global offset within a plane (y*N + z), -1 if none
+    int h_lds[HI];    // LDS offset within a plane
+    int h_vec[HI];    // 1: vector item, 0: scalar item
+#pragma unroll
+    for (int q = 0; q < HI; ++q) {
+        const int item = tid + q * NT;
+        h_goff[q] = -1;
+        h_lds[q] = 0;
+        h_vec[q] = 0;
+        if (item < nhalo) {
+            if (item < 2 * BZ) {
+                const int side = item / BZ, cz = item % BZ;
+                const int y = side == 0 ? (y0 - 1 + N) % N : (y0 + TY) % N;
+                h_goff[q] = y * N + z0 + cz * V;
+                h_lds[q] = (side == 0 ? 0 : TY + 1) * S + V + cz * V;
+                h_vec[q] = 1;
+            } else {
+                const int kk = item - 2 * BZ;
+                const int row = kk >> 1, side = kk & 1;
+                const int z = side == 0 ? (z0 - 1 + N) % N : (z0 + TZ) % N;
+                h_goff[q] = (y0 + row) * N + z;
+                h_lds[q] = (row + 1) * S + (side == 0 ? V - 1 : V + TZ);
+            }
+        }
+    }
+
+    const size_t plane = static_cast<size_t>(N) * N;
+    T prev[NF][RY][V], cur[NF][RY][V], nxt[NF][RY][V], pc[NF][RY][V], pn[NF][RY][V];
+
+    // Load plane x of own values: drifted f into `fd`, old momenta into `po`.
+    auto load_own = [&](int x, T (&fd)[NF][RY][V], T (&po)[NF][RY][V]) {
+        const size_t base = static_cast<size_t>(x) * plane;
+#pragma unroll
+        for (int j = 0; j < NF; ++j) {
+#pragma unroll
+            for (int k = 0; k < RY; ++k) {
+                const size_t off = base + static_cast<size_t>(yrow[k]) * N + zc;
+                T fv[V], pv[V];
+                vload(fin[j] + off, fv);
+                vload(pin[j] + off, pv);
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    po[j][k][v] = pv[v];
+                    fd[j][k][v] = fv[v] + cd * pv[v];
+                }
+            }
+        }
+    };
+    // Stage drifted plane (own values + halo) into LDS buffer `buf`.
+    auto stage = [&](int x, int buf, const T (&fd)[NF][RY][V]) {
+        const size_t base = static_cast<size_t>(x) * plane;
+        T* L0 = lds + static_cast<size_t>(buf) * NF * PL;
+#pragma unroll
+        for (int j = 0; j < NF; ++j) {
+            T* Lj = L0 + j * PL;
+#pragma unroll
+            for (int k = 0; k < RY; ++k) {
+                const int row = tr + k * RL + 1;
+                vstore(Lj + row * S + V + tz * V, fd[j][k]);
+            }
+#pragma unroll
+            for (int q = 0; q < HI; ++q) {
+                if (h_goff[q] < 0) continue;
+                const size_t off = base + h_goff[q];
+                if (h_vec[q]) {
+                    T fv[V], pv[V];
+                    vload(fin[j] + off, fv);
+                    vload(pin[j] + off, pv);
+#pragma unroll
+                    for (int v = 0; v < V; ++v) fv[v] = fv[v] + cd * pv[v];
+                    vstore(Lj + h_lds[q], fv);
+                } else {
+                    Lj[h_lds[q]] = fin[j][off] + cd * pin[j][off];
+                }
+            }
+        }
+    };
+
+    double acc[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) acc[k] = 0.0;
+
+    // Prologue: planes x0-1 (own only) and x0 (own + halo into buffer 0).
+    load_own((x0 - 1 + N) % N, prev, pn);
+    load_own(x0, cur, pc);
+    stage(x0, 0, cur);
+    __syncthreads();
+
+    for (int i = 0; i < CX; ++i) {
+        const int x = x0 + i;
+        const int xn = (x + 1) % N;
+        const int buf = i & 1;
+        load_own(xn, nxt, pn);
+        if (i + 1 < CX) stage(xn, buf ^ 1, nxt);
+
+        const T* L0 = lds + static_cast<size_t>(buf) * NF * PL;
+        const size_t base = static_cast<size_t>(x) * plane;
+#pragma unroll
+        for (int k = 0; k < RY; ++k) {
+            const int row = tr + k * RL + 1;
+            const int col = V + tz * V;
+            T ym[NF][V], yp[NF][V], zm0[NF], zp0[NF];
+#pragma unroll
+            for (int j = 0; j < NF; ++j) {
+                const T* Lj = L0 + j * PL;
+                vload(Lj + (row - 1) * S + col, ym[j]);
+                vload(Lj + (row + 1) * S + col, yp[j]);
+                zm0[j] = Lj[row * S + col - 1];
+                zp0[j] = Lj[row * S + col + V];
+            }
+            T pnew[NF][V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                T fs[NF], dV[NF];
+                double fsd[NF];
+#pragma unroll
+                for (int j = 0; j < NF; ++j) {
+                    fs[j] = cur[j][k][v];
+                    fsd[j] = static_cast<double>(fs[j]);
+                }
+                site_dV<T, NF>(fs, m2, lam, g2, dV);
+                acc[NS - 1] += site_V<NF>(fsd, A.ph);
+#pragma unroll
+                for (int j = 0; j < NF; ++j) {
+                    const T f = fs[j];
+                    const T zm = v == 0 ? zm0[j] : cur[j][k][v - 1];
+                    const T zp = v == V - 1 ? zp0[j] : cur[j][k][v + 1];
+                    const T xp = nxt[j][k][v];
+                    const T nb = (prev[j][k][v] + xp) + (ym[j][v] + yp[j][v]) + (zm + zp);
+                    const T F = kL * (nb - T(6) * f) - kV * dV[j];
+                    const T po = pc[j][k][v];
+                    const T p1 = po + kt * F;
+                    const T ps = po + kb * F;
+                    pnew[j][v] = p1;
+                    const double gx = static_cast<double>(xp) - fsd[j];
+                    const double gy = static_cast<double>(yp[j][v]) - fsd[j];
+                    const double gz = static_cast<double>(zp) - fsd[j];
+                    const double psd = static_cast<double>(ps);
+                    const double d = fsd[j] - shift[j];
+                    double* a5 = acc + kSumsPerField * j;
+                    a5[0] += psd * psd;
+                    a5[1] += gx * gx + gy * gy + gz * gz;
+                    a5[2] += d;
+                    a5[3] += d * d;
+                    a5[4] += static_cast<double>(p1);
+                }
+            }
+            if (A.write_out) {
+                const size_t off = base + static_cast<size_t>(yrow[k]) * N + zc;
+#pragma unroll
+                for (int j = 0; j < NF; ++j) {
+                    vstore(fout[j] + off, cur[j][k]);
+                    vstore(pout[j] + off, pnew[j]);
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < NF; ++j)
+#pragma unroll
+            for (int k = 0; k < RY; ++k)
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    prev[j][k][v] = cur[j][k][v];
+                    cur[j][k][v] = nxt[j][k][v];
+                    pc[j][k][v] = pn[j][k][v];
+                }
+    }
+    reduce_and_finish<NS>(A, acc, NT, bid, nblocks);
+}
+
+__global__ void init_scalars_kernel(Scal* sc, double a, double b, double eta, double alpha, double dx,
+                                    double s0, double s1) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    Scal s;
+    s.a = a;
+    s.b = b;
+    s.eta = eta;
+    s.cd = 0.0;
+    s.kL = pow(a, 1.0 + alpha) / (dx * dx);
+    s.kV = pow(a, 3.0 + alpha);
+    s.a_next = a;
+    s.shift[0] = s0;
+    s.shift[1] = s1;
+    s.mean_f[0] = s0;
+    s.mean_f[1] = s1;
+    s.mean_p[0] = 0.0;
+    s.mean_p[1] = 0.0;
+    s.nonfinite = 0;
+    s.pad = 0;
+    *sc = s;
+}
+
+hipError_t launch_init_scalars(Scal* sc, double a, double b, double eta, const Phys& ph,
+                               const double* shift, hipStream_t s) {
+    hipLaunchKernelGGL(init_scalars_kernel, dim3(1), dim3(64), 0, s, sc, a, b, eta, ph.alpha, ph.dx,
+                       shift[0], shift[1]);
+    return hipGetLastError();
+}
+
+size_t pass_lds_bytes(const Tile& t, cl_precision prec, int nf) {
+    const int V = prec == CL_FP32 ? 4 : 2;
+    const size_t es = prec == CL_FP32 ? 4 : 8;
+    return 2ull * nf * (t.TY + 2) * (t.TZ + 2 * V) * es;
+}
+
+static bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+bool finalize_tile(Tile& t, int N, cl_precision prec) {
+    const int V = prec == CL_FP32 ? 4 : 2;
+    if (t.TZ <= 0 || t.TY <= 0 || t.CX <= 0 || t.RY <= 0) return false;
+    if (t.TZ % V || N % t.TZ || N % t.TY || N % t.CX || t.TY % t.RY) return false;
+    const int BZ = t.TZ / V;
+    const int RL = t.TY / t.RY;
+    t.NT = BZ * RL;
+    if (t.NT > 256 || !is_pow2(t.NT) || !is_pow2(BZ)) return false;
+    if (t.RY != 1 && t.RY != 2) return false;
+    const int nhalo = 2 * BZ + 2 * t.TY;
+    t.HI = (nhalo + t.NT - 1) / t.NT;
+    if (t.HI > 2) return false;
+    if (t.HI < 1) t.HI = 1;
+    t.nbz = N / t.TZ;
+    t.nby = N / t.TY;
+    t.nbx = N / t.CX;
+    return true;
+}
+
+Tile default_tile(int N, cl_precision prec, int nf) {
+    const int V = prec == CL_FP32 ? 4 : 2;
+    Tile t;
+    t.TZ = N < 64 * V ? N : 64 * V;
+    const int BZ = t.TZ / V;
+    t.RY = 1;
+    int RL = 256 / BZ;
+    while (RL > 1 && (RL > N || N % RL)) RL >>= 1;
+    t.TY = RL * t.RY;
+    const int tiles = (N / t.TZ) * (N / t.TY);
+    t.CX = N;
+    while (t.CX > 4 && tiles * (N / t.CX) < 2048 && (t.CX % 2 == 0)) t.CX /= 2;
+    (void)nf;
+    finalize_tile(t, N, prec);
+    return t;
+}
+
+template <typename T, int NF, int RY, int HI>
+static hipError_t launch_t(const PassArgs& a, const Tile& t, hipStream_t s, size_t lds) {
+    hipLaunchKernelGGL((lattice_pass<T, NF, RY, HI>), dim3(t.nblocks()), dim3(t.NT), lds, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, int NF>
+static hipError_t launch_nf(const PassArgs& a, const Tile& t, hipStream_t s, size_t lds) {
+    if (t.RY == 1) return t.HI == 1 ? launch_t<T, NF, 1, 1>(a, t, s, lds) : launch_t<T, NF, 1, 2>(a, t, s, lds);
+    return t.HI == 1 ? launch_t<T, NF, 2, 1>(a, t, s, lds) : launch_t<T, NF, 2, 2>(a, t, s, lds);
+}
+
+hipError_t launch_pass(const PassArgs& a, const Tile& t, cl_precision prec, hipStream_t s) {
+    const size_t lds = pass_lds_bytes(t, prec, a.ph.nf);
+    if (prec == CL_FP32)
+        return a.ph.nf == 1 ? launch_nf<float, 1>(a, t, s, lds) : launch_nf<float, 2>(a, t, s, lds);
+    return a.ph.nf == 1 ? launch_nf<double, 1>(a, t, s, lds) : launch_nf<double, 2>(a, t, s, lds);
+}
+
+}  // namespace cl
