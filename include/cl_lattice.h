@@ -174,6 +174,36 @@ cl_status cl_step(cl_lattice* h, cl_integrator integ, double dt, int n, cl_obser
 /* Observables of the current state (one reduction pass over the lattice). */
 cl_status cl_read_observables(cl_lattice* h, cl_observables* out);
 
+/* Work decomposition of the lattice passes: each workgroup owns a tz x ty
+ * tile of (z, y) and marches over cx x-planes; ry is the number of y rows per
+ * thread (1 or 2).  tz, ty, cx must divide N; tz is a multiple of 4 (FP32) or
+ * 2 (FP64) with at most 256 threads per workgroup.  An invalid tile returns
+ * CL_EINVAL and leaves the current one in place. */
+typedef struct {
+    int tz;
+    int ty;
+    int cx;
+    int ry;
+} cl_tile;
+
+cl_status cl_get_tile(const cl_lattice* h, cl_tile* out);
+cl_status cl_set_tile(cl_lattice* h, const cl_tile* t);
+
+/* Autotuner: times `reps` fused drift-kick passes of every candidate tile on
+ * the current state (fields and background are left unchanged), selects the
+ * fastest and writes a JSON report (NUL-terminated, truncated to
+ * report_cap) if report is not NULL.  If the environment variable
+ * CL_TUNE_CACHE names a file, the result is appended there as one JSON line
+ * and later cl_create calls for the same (N, n_fields, precision) start from
+ * it. */
+cl_status cl_autotune(cl_lattice* h, int reps, char* report, size_t report_cap);
+
+/* Streaming-copy probe on the current device: copies `bytes` (rounded down
+ * to 16) between two scratch buffers `reps` times and returns the achieved
+ * read+write bandwidth in GB/s (1e9 bytes/s).  Allocates and frees its own
+ * buffers. */
+cl_status cl_copy_bandwidth(size_t bytes, int reps, double* gbps);
+
 /* Ensembles: advance several independent lattices (equal precision and
  * n_fields, any N) together, each pass of all members in one persistent
  * launch, the passes of a call captured in one HIP graph.  Members keep their

@@ -37,6 +37,10 @@ class cl_observables(C.Structure):
                 ("hubble_residual", C.c_double), ("nonfinite", C.c_int32), ("reserved", C.c_int32)]
 
 
+class cl_tile(C.Structure):
+    _fields_ = [("tz", C.c_int), ("ty", C.c_int), ("cx", C.c_int), ("ry", C.c_int)]
+
+
 OBS_DTYPE = np.dtype([("eta", "f8"), ("a", "f8"), ("H", "f8"), ("EK", "f8", 2), ("EG", "f8", 2), ("EV", "f8"),
                       ("mean", "f8", 2), ("var", "f8", 2), ("r", "f8"), ("nonfinite", "i4"),
                       ("reserved", "i4")])
@@ -60,6 +64,10 @@ _SIGS = {
     "cl_set_state": (C.c_int, [_P, C.POINTER(cl_scalars)]),
     "cl_step": (C.c_int, [_P, C.c_int, C.c_double, C.c_int, _P]),
     "cl_read_observables": (C.c_int, [_P, _P]),
+    "cl_get_tile": (C.c_int, [_P, C.POINTER(cl_tile)]),
+    "cl_set_tile": (C.c_int, [_P, C.POINTER(cl_tile)]),
+    "cl_autotune": (C.c_int, [_P, C.c_int, C.c_char_p, C.c_size_t]),
+    "cl_copy_bandwidth": (C.c_int, [C.c_size_t, C.c_int, C.POINTER(C.c_double)]),
     "cl_ensemble_create": (C.c_int, [C.c_int, C.POINTER(_P), C.POINTER(_P)]),
     "cl_ensemble_set_dt": (C.c_int, [_P, C.c_int, C.c_double]),
     "cl_ensemble_step": (C.c_int, [_P, C.c_int, C.c_int, _P]),
@@ -165,10 +173,32 @@ class Lattice:
         _check(lib.cl_step(self.h, INTEGRATORS[integrator], float(dt), int(n), ptr), self.h)
         return out
 
+    def get_tile(self) -> dict:
+        t = cl_tile()
+        _check(lib.cl_get_tile(self.h, C.byref(t)), self.h)
+        return dict(tz=t.tz, ty=t.ty, cx=t.cx, ry=t.ry)
+
+    def set_tile(self, tz: int, ty: int, cx: int, ry: int = 1):
+        t = cl_tile(int(tz), int(ty), int(cx), int(ry))
+        _check(lib.cl_set_tile(self.h, C.byref(t)), self.h)
+
+    def autotune(self, reps: int = 3) -> dict:
+        import json
+        buf = C.create_string_buffer(1 << 16)
+        _check(lib.cl_autotune(self.h, int(reps), buf, len(buf)), self.h)
+        return json.loads(buf.value.decode())
+
     def read_observables(self):
         out = np.zeros(1, dtype=OBS_DTYPE)
         _check(lib.cl_read_observables(self.h, _P(out.ctypes.data)), self.h)
         return out[0]
+
+
+def copy_bandwidth(nbytes: int, reps: int = 10) -> float:
+    """Streaming-copy bandwidth of the current device in GB/s (cl_copy_bandwidth)."""
+    g = C.c_double()
+    _check(lib.cl_copy_bandwidth(C.c_size_t(nbytes), int(reps), C.byref(g)))
+    return g.value
 
 
 class Ensemble:

@@ -39,6 +39,8 @@ struct Phys {
     double alpha, mp, dx, inv_vol;
     int nf;
     int expand;  // 1: self-consistent expansion, 0: static
+    int fp32;    // 1: fields stored in FP32
+    int pad;
 };
 
 // Tile of one workgroup: TZ z-values x TY y-rows, marching over CX x-planes.
@@ -84,6 +86,9 @@ Tile default_tile(int N, cl_precision prec, int nf);
 // kernel's limits.  Returns false if not.
 bool finalize_tile(Tile& t, int N, cl_precision prec);
 size_t pass_lds_bytes(const Tile& t, cl_precision prec, int nf);
+// All valid tiles the autotuner tries for a lattice.
+void candidate_tiles(int N, cl_precision prec, int nf, Tile* out, int* count, int cap);
+hipError_t launch_copy(const void* in, void* out, size_t bytes, hipStream_t s);
 
 // Host seed (host_seed.cpp): fills f, p (n_fields * N^3 FP64 each).
 // Returns an empty string on success, an error message otherwise.

@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
@@ -57,8 +58,8 @@ struct cl_lattice {
     int obs_cap = 0;
     Tile tile;
     int64_t step = 0;
-    hipGraphExec_t gexec = nullptr;
-    GraphKey gkey;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};  // one per starting buffer
+    GraphKey gkey[2];
     bool use_graph = true;
     std::string err;
 };
@@ -96,13 +97,16 @@ Phys make_phys(const cl_lattice* h) {
     p.inv_vol = 1.0 / static_cast<double>(sites(h));
     p.nf = h->nf;
     p.expand = h->mode == CL_SELF_CONSISTENT ? 1 : 0;
+    p.fp32 = h->prec == CL_FP32 ? 1 : 0;
     return p;
 }
 
 void drop_graph(cl_lattice* h) {
-    if (h->gexec) hipGraphExecDestroy(h->gexec);
-    h->gexec = nullptr;
-    h->gkey = GraphKey{};
+    for (int i = 0; i < 2; ++i) {
+        if (h->gexec[i]) hipGraphExecDestroy(h->gexec[i]);
+        h->gexec[i] = nullptr;
+        h->gkey[i] = GraphKey{};
+    }
 }
 
 bool valid_N(int N, cl_precision prec) {
@@ -112,8 +116,9 @@ bool valid_N(int N, cl_precision prec) {
     return pow2 || (N % big == 0);
 }
 
-cl_status ensure_partials(cl_lattice* h) {
-    const size_t need = static_cast<size_t>(cl::nsums(h->nf)) * h->tile.nblocks();
+cl_status ensure_partials(cl_lattice* h, int nblocks = 0) {
+    if (nblocks <= 0) nblocks = h->tile.nblocks();
+    const size_t need = static_cast<size_t>(cl::nsums(h->nf)) * nblocks;
     if (need <= h->partials_cap) return CL_OK;
     if (h->partials) hipFree(h->partials);
     h->partials = nullptr;
@@ -313,6 +318,37 @@ void host_means(const cl_lattice* h, const double* f, double* mean) {
     }
 }
 
+const char* prec_name(cl_precision p) { return p == CL_FP32 ? "fp32" : "fp64"; }
+
+// Last cached tile for (N, n_fields, precision) in the CL_TUNE_CACHE file.
+bool cached_tile(int N, int nf, cl_precision prec, Tile& t) {
+    const char* path = std::getenv("CL_TUNE_CACHE");
+    if (!path || !path[0]) return false;
+    FILE* fp = std::fopen(path, "r");
+    if (!fp) return false;
+    char line[512];
+    bool found = false;
+    while (std::fgets(line, sizeof line, fp)) {
+        int n = 0, f = 0, tz = 0, ty = 0, cx = 0, ry = 0;
+        char pr[8] = {0};
+        if (std::sscanf(line, "{\"arch\":\"gfx950\",\"N\":%d,\"nf\":%d,\"prec\":\"%4[^\"]\",\"tz\":%d,\"ty\":%d,\"cx\":%d,\"ry\":%d",
+                        &n, &f, pr, &tz, &ty, &cx, &ry) == 7 &&
+            n == N && f == nf && std::strcmp(pr, prec_name(prec)) == 0) {
+            Tile c;
+            c.TZ = tz;
+            c.TY = ty;
+            c.CX = cx;
+            c.RY = ry;
+            if (cl::finalize_tile(c, N, prec)) {
+                t = c;
+                found = true;
+            }
+        }
+    }
+    std::fclose(fp);
+    return found;
+}
+
 void free_buffers(cl_lattice* h) {
     if (!h->own_buffers) return;
     for (auto& a : h->buf)
@@ -373,6 +409,7 @@ cl_status cl_create(int N, double dx, int n_fields, cl_precision prec, cl_lattic
     if (hipMalloc(&h->ticket, 64) != hipSuccess) return bail(CL_ENOMEM, "ticket");
     if (hipMemsetAsync(h->ticket, 0, 64, h->stream) != hipSuccess) return bail(CL_EDEVICE, "memset");
     h->tile = cl::default_tile(N, prec, n_fields);
+    cached_tile(N, n_fields, prec, h->tile);
     if (ensure_partials(h) != CL_OK) return bail(CL_ENOMEM, h->err);
     double zero[2] = {0.0, 0.0};
     if (init_scalars(h, 1.0, 0.0, 0.0, zero) != CL_OK) return bail(CL_EDEVICE, h->err);
@@ -537,8 +574,10 @@ cl_status cl_step(cl_lattice* h, cl_integrator integ, double dt, int n, cl_obser
     const GraphKey key{static_cast<int>(integ), dt, n, h->cur};
     const int passes = 1 + n * (integ == CL_VV4 ? 3 : 1);
     if (h->use_graph && n > 1) {
-        if (!(h->gexec && h->gkey == key)) {
-            drop_graph(h);
+        hipGraphExec_t& gx = h->gexec[h->cur];
+        if (!(gx && h->gkey[h->cur] == key)) {
+            if (gx) hipGraphExecDestroy(gx);
+            gx = nullptr;
             hipGraph_t g = nullptr;
             HIPCHECK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
             st = issue_steps(h, integ, dt, n, h->cur);
@@ -548,15 +587,15 @@ cl_status cl_step(cl_lattice* h, cl_integrator integ, double dt, int n, cl_obser
                 return st;
             }
             if (e != hipSuccess) return fail(h, CL_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
-            e = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+            e = hipGraphInstantiate(&gx, g, nullptr, nullptr, 0);
             hipGraphDestroy(g);
             if (e != hipSuccess) {
-                h->gexec = nullptr;
+                gx = nullptr;
                 return fail(h, CL_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
             }
-            h->gkey = key;
+            h->gkey[h->cur] = key;
         }
-        HIPCHECK(h, hipGraphLaunch(h->gexec, h->stream));
+        HIPCHECK(h, hipGraphLaunch(gx, h->stream));
     } else {
         st = issue_steps(h, integ, dt, n, h->cur);
         if (st) return st;
@@ -581,6 +620,152 @@ cl_status cl_read_observables(cl_lattice* h, cl_observables* out) {
     cl_status st = reduce_pass(h, &o);
     if (st) return st;
     return reduce_pass(h, out);
+}
+
+cl_status cl_get_tile(const cl_lattice* h, cl_tile* out) {
+    if (!h) return fail(nullptr, CL_EINVAL, "handle is NULL");
+    if (!out) return fail(const_cast<cl_lattice*>(h), CL_EINVAL, "out is NULL");
+    out->tz = h->tile.TZ;
+    out->ty = h->tile.TY;
+    out->cx = h->tile.CX;
+    out->ry = h->tile.RY;
+    return CL_OK;
+}
+
+cl_status cl_set_tile(cl_lattice* h, const cl_tile* t) {
+    if (!h) return fail(nullptr, CL_EINVAL, "handle is NULL");
+    if (!t) return fail(h, CL_EINVAL, "tile is NULL");
+    Tile c;
+    c.TZ = t->tz;
+    c.TY = t->ty;
+    c.CX = t->cx;
+    c.RY = t->ry;
+    if (!cl::finalize_tile(c, h->N, h->prec)) return fail(h, CL_EINVAL, "tile does not fit this lattice");
+    if (cl::pass_lds_bytes(c, h->prec, h->nf) > 60 * 1024) return fail(h, CL_EINVAL, "tile needs too much LDS");
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    const Tile old = h->tile;
+    h->tile = c;
+    cl_status st = ensure_partials(h);
+    if (st) {
+        h->tile = old;
+        return st;
+    }
+    drop_graph(h);
+    return CL_OK;
+}
+
+cl_status cl_autotune(cl_lattice* h, int reps, char* report, size_t cap) {
+    if (!h) return fail(nullptr, CL_EINVAL, "handle is NULL");
+    if (reps < 1) reps = 3;
+    std::vector<Tile> cands(1024);
+    int nc = 0;
+    cl::candidate_tiles(h->N, h->prec, h->nf, cands.data(), &nc, static_cast<int>(cands.size()));
+    if (nc == 0) return fail(h, CL_EUNSUPPORTED, "no candidate tile");
+    int maxb = 0;
+    for (int i = 0; i < nc; ++i) maxb = std::max(maxb, cands[i].nblocks());
+    cl_status st = ensure_partials(h, maxb);
+    if (st) return st;
+    Scal saved;
+    HIPCHECK(h, hipMemcpyAsync(&saved, h->sc, sizeof(Scal), hipMemcpyDeviceToHost, h->stream));
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    hipEvent_t e0, e1;
+    HIPCHECK(h, hipEventCreate(&e0));
+    HIPCHECK(h, hipEventCreate(&e1));
+    std::string js = "{\"N\":" + std::to_string(h->N) + ",\"nf\":" + std::to_string(h->nf) + ",\"prec\":\"" +
+                     prec_name(h->prec) + "\",\"reps\":" + std::to_string(reps) + ",\"candidates\":[";
+    int best = -1;
+    float best_ms = 0.0f;
+    for (int i = 0; i < nc; ++i) {
+        const Tile& t = cands[i];
+        PassArgs a = base_args(h, h->cur);
+        a.TZ = t.TZ;
+        a.TY = t.TY;
+        a.CX = t.CX;
+        a.nbz = t.nbz;
+        a.nby = t.nby;
+        a.nbx = t.nbx;
+        a.partials = h->partials;
+        a.drift = 1;
+        a.write_out = 1;
+        a.kt = 0.0;
+        a.kb = 0.0;
+        a.h_next = 0.0;
+        a.rec = -1;
+        hipError_t e = cl::launch_pass(a, t, h->prec, h->stream);  // warm-up
+        if (e != hipSuccess) continue;
+        hipEventRecord(e0, h->stream);
+        for (int r = 0; r < reps; ++r) cl::launch_pass(a, t, h->prec, h->stream);
+        hipEventRecord(e1, h->stream);
+        HIPCHECK(h, hipEventSynchronize(e1));
+        float ms = 0.0f;
+        hipEventElapsedTime(&ms, e0, e1);
+        ms /= reps;
+        char item[160];
+        std::snprintf(item, sizeof item, "%s{\"tz\":%d,\"ty\":%d,\"cx\":%d,\"ry\":%d,\"us\":%.2f}",
+                      i ? "," : "", t.TZ, t.TY, t.CX, t.RY, ms * 1e3);
+        js += item;
+        if (best < 0 || ms < best_ms) {
+            best = i;
+            best_ms = ms;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    HIPCHECK(h, hipMemcpyAsync(h->sc, &saved, sizeof(Scal), hipMemcpyHostToDevice, h->stream));
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    if (best < 0) return fail(h, CL_EDEVICE, "no candidate tile launched");
+    h->tile = cands[best];
+    drop_graph(h);
+    char tail[200];
+    std::snprintf(tail, sizeof tail, "],\"best\":{\"tz\":%d,\"ty\":%d,\"cx\":%d,\"ry\":%d,\"us\":%.2f}}",
+                  h->tile.TZ, h->tile.TY, h->tile.CX, h->tile.RY, best_ms * 1e3);
+    js += tail;
+    if (report && cap) {
+        std::strncpy(report, js.c_str(), cap - 1);
+        report[cap - 1] = '\0';
+    }
+    const char* path = std::getenv("CL_TUNE_CACHE");
+    if (path && path[0]) {
+        FILE* fp = std::fopen(path, "a");
+        if (fp) {
+            std::fprintf(fp, "{\"arch\":\"gfx950\",\"N\":%d,\"nf\":%d,\"prec\":\"%s\",\"tz\":%d,\"ty\":%d,\"cx\":%d,\"ry\":%d,\"us\":%.2f}\n",
+                         h->N, h->nf, prec_name(h->prec), h->tile.TZ, h->tile.TY, h->tile.CX, h->tile.RY,
+                         best_ms * 1e3);
+            std::fclose(fp);
+        }
+    }
+    return CL_OK;
+}
+
+cl_status cl_copy_bandwidth(size_t bytes, int reps, double* gbps) {
+    if (!gbps) return fail(nullptr, CL_EINVAL, "gbps is NULL");
+    bytes &= ~static_cast<size_t>(15);
+    if (bytes == 0 || reps < 1) return fail(nullptr, CL_EINVAL, "bytes and reps must be positive");
+    void* a = nullptr;
+    void* b = nullptr;
+    if (hipMalloc(&a, bytes) != hipSuccess) return fail(nullptr, CL_ENOMEM, "copy probe buffer");
+    if (hipMalloc(&b, bytes) != hipSuccess) {
+        hipFree(a);
+        return fail(nullptr, CL_ENOMEM, "copy probe buffer");
+    }
+    hipMemset(a, 0, bytes);
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    cl::launch_copy(a, b, bytes, nullptr);
+    hipEventRecord(e0, nullptr);
+    for (int r = 0; r < reps; ++r) cl::launch_copy(a, b, bytes, nullptr);
+    hipEventRecord(e1, nullptr);
+    hipEventSynchronize(e1);
+    float ms = 0.0f;
+    hipEventElapsedTime(&ms, e0, e1);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipFree(a);
+    hipFree(b);
+    if (!(ms > 0.0f)) return fail(nullptr, CL_EDEVICE, "copy probe timing failed");
+    *gbps = 2.0 * static_cast<double>(bytes) * reps / (ms * 1e-3) / 1e9;
+    return CL_OK;
 }
 
 }  // extern "C"

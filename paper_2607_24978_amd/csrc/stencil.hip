@@ -46,19 +46,6 @@ __device__ __forceinline__ void vstore(T* p, const T (&in)[VecOf<T>::V]) {
     *reinterpret_cast<VT*>(p) = v;
 }
 
-// Site potential in FP64: sum_j (m2 f^2/2 + lam f^4/4) + g2 f0^2 f1^2 / 2 (V0 added later).
-template <int NF>
-__device__ __forceinline__ double site_V(const double (&f)[NF], const Phys& P) {
-    double V = 0.0;
-#pragma unroll
-    for (int j = 0; j < NF; ++j) {
-        const double f2 = f[j] * f[j];
-        V += 0.5 * P.m2[j] * f2 + 0.25 * P.lam[j] * f2 * f2;
-    }
-    if constexpr (NF == 2) V += 0.5 * P.g2 * f[0] * f[0] * f[1] * f[1];
-    return V;
-}
-
 // dV/df_j in the field precision.
 template <typename T, int NF>
 __device__ __forceinline__ void site_dV(const T (&f)[NF], const T (&m2)[2], const T (&lam)[2], T g2,
@@ -88,7 +75,9 @@ __device__ void finish_pass(const PassArgs& A, const double* tot) {
         EK[j] = t[0] * P.inv_vol / (2.0 * a6);
         EG[j] = t[1] * P.inv_vol / (2.0 * a2 * P.dx * P.dx);
         const double m1 = t[2] * P.inv_vol;
-        mean[j] = sc->shift[j] + m1;
+        // the kernels subtract the shift rounded to the field precision
+        const double c = P.fp32 ? static_cast<double>(static_cast<float>(sc->shift[j])) : sc->shift[j];
+        mean[j] = c + m1;
         var[j] = t[3] * P.inv_vol - m1 * m1;
         meanp[j] = t[4] * P.inv_vol;
     }
@@ -226,11 +215,9 @@ __global__ __launch_bounds__(256) void lattice_pass(PassArgs A) {
     // co-resident workgroups then share y/z halos in their L2.
     int bid = blockIdx.x;
     {
-        const int G = nblocks;
-        const int per = G / 8, rem = G % 8;
+        const int per = nblocks / 8, rem = nblocks % 8;
         const int xcd = bid % 8, slot = bid / 8;
-        bid = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + slot;
-        if (per == 0) bid = blockIdx.x;
+        if (per > 0) bid = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + slot;
     }
     const int bz = bid % A.nbz;
     const int by = (bid / A.nbz) % A.nby;
@@ -255,12 +242,16 @@ __global__ __launch_bounds__(256) void lattice_pass(PassArgs A) {
     const T kV = static_cast<T>(sc->kV);
     const T kt = static_cast<T>(A.kt);
     const T kb = static_cast<T>(A.kb);
-    double shift[NF];
+    // Variance shift in the field precision: f - c is exact for f near c.
+    T shift[NF];
 #pragma unroll
-    for (int j = 0; j < NF; ++j) shift[j] = sc->shift[j];
-    T m2[2] = {static_cast<T>(A.ph.m2[0]), static_cast<T>(A.ph.m2[1])};
-    T lam[2] = {static_cast<T>(A.ph.lam[0]), static_cast<T>(A.ph.lam[1])};
+    for (int j = 0; j < NF; ++j) shift[j] = static_cast<T>(sc->shift[j]);
+    const T m2[2] = {static_cast<T>(A.ph.m2[0]), static_cast<T>(A.ph.m2[1])};
+    const T lam[2] = {static_cast<T>(A.ph.lam[0]), static_cast<T>(A.ph.lam[1])};
     const T g2 = static_cast<T>(A.ph.g2);
+    const T hm2[2] = {T(0.5) * m2[0], T(0.5) * m2[1]};
+    const T qlam[2] = {T(0.25) * lam[0], T(0.25) * lam[1]};
+    const T hg2 = T(0.5) * g2;
 
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* lds = reinterpret_cast<T*>(smem_raw);
@@ -268,30 +259,29 @@ __global__ __launch_bounds__(256) void lattice_pass(PassArgs A) {
     const int PL = (TY + 2) * S;     // one plane of one field
     // lds[buf][field][row][col]; row 0 = y0-1, row TY+1 = y0+TY.
 
-    // Global row offsets of own rows.
     const int zc = z0 + tz * V;
     int yrow[RY];
 #pragma unroll
-    for (int k = 0; k < RY; ++k) yrow[k] = y0 + tr + k * RL;
+    for (int k = 0; k < RY; ++k) yrow[k] = (y0 + tr + k * RL) * N + zc;
 
     // Halo items of this thread (row halo: V values; z halo: 1 value).
     const int nhalo = 2 * BZ + 2 * TY;
-    int h_goff[HI];   // global offset within a plane (y*N + z), -1 if none
+    int h_goff[HI];   // offset within a plane (y*N + z), -1 if none
     int h_lds[HI];    // LDS offset within a plane
-    int h_vec[HI];    // 1: vector item, 0: scalar item
+    bool h_vec[HI];   // vector item (row halo) or scalar item (z halo)
 #pragma unroll
     for (int q = 0; q < HI; ++q) {
         const int item = tid + q * NT;
         h_goff[q] = -1;
         h_lds[q] = 0;
-        h_vec[q] = 0;
+        h_vec[q] = false;
         if (item < nhalo) {
             if (item < 2 * BZ) {
                 const int side = item / BZ, cz = item % BZ;
                 const int y = side == 0 ? (y0 - 1 + N) % N : (y0 + TY) % N;
                 h_goff[q] = y * N + z0 + cz * V;
                 h_lds[q] = (side == 0 ? 0 : TY + 1) * S + V + cz * V;
-                h_vec[q] = 1;
+                h_vec[q] = true;
             } else {
                 const int kk = item - 2 * BZ;
                 const int row = kk >> 1, side = kk & 1;
@@ -303,52 +293,62 @@ __global__ __launch_bounds__(256) void lattice_pass(PassArgs A) {
     }
 
     const size_t plane = static_cast<size_t>(N) * N;
-    T prev[NF][RY][V], cur[NF][RY][V], nxt[NF][RY][V], pc[NF][RY][V], pn[NF][RY][V];
-
-    // Load plane x of own values: drifted f into `fd`, old momenta into `po`.
-    auto load_own = [&](int x, T (&fd)[NF][RY][V], T (&po)[NF][RY][V]) {
+    // Raw (undrifted) loads of one plane: own values and halo items.
+    T rf[NF][RY][V], rp[NF][RY][V], hf[NF][HI][V], hp[NF][HI][V];
+    auto issue = [&](int x, bool halo) {
         const size_t base = static_cast<size_t>(x) * plane;
 #pragma unroll
         for (int j = 0; j < NF; ++j) {
 #pragma unroll
             for (int k = 0; k < RY; ++k) {
-                const size_t off = base + static_cast<size_t>(yrow[k]) * N + zc;
-                T fv[V], pv[V];
-                vload(fin[j] + off, fv);
-                vload(pin[j] + off, pv);
+                vload(fin[j] + base + yrow[k], rf[j][k]);
+                vload(pin[j] + base + yrow[k], rp[j][k]);
+            }
+            if (halo) {
 #pragma unroll
-                for (int v = 0; v < V; ++v) {
-                    po[j][k][v] = pv[v];
-                    fd[j][k][v] = fv[v] + cd * pv[v];
+                for (int q = 0; q < HI; ++q) {
+                    if (h_goff[q] < 0) continue;
+                    if (h_vec[q]) {
+                        vload(fin[j] + base + h_goff[q], hf[j][q]);
+                        vload(pin[j] + base + h_goff[q], hp[j][q]);
+                    } else {
+                        hf[j][q][0] = fin[j][base + h_goff[q]];
+                        hp[j][q][0] = pin[j][base + h_goff[q]];
+                    }
                 }
             }
         }
     };
-    // Stage drifted plane (own values + halo) into LDS buffer `buf`.
-    auto stage = [&](int x, int buf, const T (&fd)[NF][RY][V]) {
-        const size_t base = static_cast<size_t>(x) * plane;
-        T* L0 = lds + static_cast<size_t>(buf) * NF * PL;
+    // Drift the raw plane: own values into fd / po, and (if stage >= 0) the
+    // drifted own values and halo into LDS buffer `stage`.
+    T prev[NF][RY][V], cur[NF][RY][V], nxt[NF][RY][V], pc[NF][RY][V], pn[NF][RY][V];
+    auto consume = [&](T (&fd)[NF][RY][V], T (&po)[NF][RY][V], int stage_buf) {
+#pragma unroll
+        for (int j = 0; j < NF; ++j)
+#pragma unroll
+            for (int k = 0; k < RY; ++k)
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    po[j][k][v] = rp[j][k][v];
+                    fd[j][k][v] = rf[j][k][v] + cd * rp[j][k][v];
+                }
+        if (stage_buf < 0) return;
+        T* L0 = lds + static_cast<size_t>(stage_buf) * NF * PL;
 #pragma unroll
         for (int j = 0; j < NF; ++j) {
             T* Lj = L0 + j * PL;
 #pragma unroll
-            for (int k = 0; k < RY; ++k) {
-                const int row = tr + k * RL + 1;
-                vstore(Lj + row * S + V + tz * V, fd[j][k]);
-            }
+            for (int k = 0; k < RY; ++k) vstore(Lj + (tr + k * RL + 1) * S + V + tz * V, fd[j][k]);
 #pragma unroll
             for (int q = 0; q < HI; ++q) {
                 if (h_goff[q] < 0) continue;
-                const size_t off = base + h_goff[q];
                 if (h_vec[q]) {
-                    T fv[V], pv[V];
-                    vload(fin[j] + off, fv);
-                    vload(pin[j] + off, pv);
+                    T fv[V];
 #pragma unroll
-                    for (int v = 0; v < V; ++v) fv[v] = fv[v] + cd * pv[v];
+                    for (int v = 0; v < V; ++v) fv[v] = hf[j][q][v] + cd * hp[j][q][v];
                     vstore(Lj + h_lds[q], fv);
                 } else {
-                    Lj[h_lds[q]] = fin[j][off] + cd * pin[j][off];
+                    Lj[h_lds[q]] = hf[j][q][0] + cd * hp[j][q][0];
                 }
             }
         }
@@ -358,21 +358,29 @@ __global__ __launch_bounds__(256) void lattice_pass(PassArgs A) {
 #pragma unroll
     for (int k = 0; k < NS; ++k) acc[k] = 0.0;
 
-    // Prologue: planes x0-1 (own only) and x0 (own + halo into buffer 0).
-    load_own((x0 - 1 + N) % N, prev, pn);
-    load_own(x0, cur, pc);
-    stage(x0, 0, cur);
+    // Prologue: plane x0-1 (own only), plane x0 (own + halo into buffer 0),
+    // then the loads of plane x0+1 stay in flight into the first iteration.
+    issue((x0 - 1 + N) % N, false);
+    consume(prev, pn, -1);
+    issue(x0, true);
+    consume(cur, pc, 0);
+    issue((x0 + 1) % N, CX > 1);
     __syncthreads();
 
     for (int i = 0; i < CX; ++i) {
         const int x = x0 + i;
-        const int xn = (x + 1) % N;
         const int buf = i & 1;
-        load_own(xn, nxt, pn);
-        if (i + 1 < CX) stage(xn, buf ^ 1, nxt);
+        // plane x+1 arrives: drift it and stage it for the next iteration
+        consume(nxt, pn, i + 1 < CX ? (buf ^ 1) : -1);
+        // loads of plane x+2 overlap the compute of plane x
+        if (i + 1 < CX) issue((x + 2) % N, i + 2 < CX);
 
         const T* L0 = lds + static_cast<size_t>(buf) * NF * PL;
         const size_t base = static_cast<size_t>(x) * plane;
+        // Per-plane partial sums in the field precision, promoted once.
+        T part[NS];
+#pragma unroll
+        for (int q = 0; q < NS; ++q) part[q] = T(0);
 #pragma unroll
         for (int k = 0; k < RY; ++k) {
             const int row = tr + k * RL + 1;
@@ -390,14 +398,19 @@ __global__ __launch_bounds__(256) void lattice_pass(PassArgs A) {
 #pragma unroll
             for (int v = 0; v < V; ++v) {
                 T fs[NF], dV[NF];
-                double fsd[NF];
 #pragma unroll
-                for (int j = 0; j < NF; ++j) {
-                    fs[j] = cur[j][k][v];
-                    fsd[j] = static_cast<double>(fs[j]);
-                }
+                for (int j = 0; j < NF; ++j) fs[j] = cur[j][k][v];
                 site_dV<T, NF>(fs, m2, lam, g2, dV);
-                acc[NS - 1] += site_V<NF>(fsd, A.ph);
+                {
+                    T Vs = T(0);
+#pragma unroll
+                    for (int j = 0; j < NF; ++j) {
+                        const T f2 = fs[j] * fs[j];
+                        Vs += f2 * (hm2[j] + qlam[j] * f2);
+                    }
+                    if constexpr (NF == 2) Vs += hg2 * (fs[0] * fs[0]) * (fs[1] * fs[1]);
+                    part[NS - 1] += Vs;
+                }
 #pragma unroll
                 for (int j = 0; j < NF; ++j) {
                     const T f = fs[j];
@@ -410,28 +423,26 @@ __global__ __launch_bounds__(256) void lattice_pass(PassArgs A) {
                     const T p1 = po + kt * F;
                     const T ps = po + kb * F;
                     pnew[j][v] = p1;
-                    const double gx = static_cast<double>(xp) - fsd[j];
-                    const double gy = static_cast<double>(yp[j][v]) - fsd[j];
-                    const double gz = static_cast<double>(zp) - fsd[j];
-                    const double psd = static_cast<double>(ps);
-                    const double d = fsd[j] - shift[j];
-                    double* a5 = acc + kSumsPerField * j;
-                    a5[0] += psd * psd;
-                    a5[1] += gx * gx + gy * gy + gz * gz;
-                    a5[2] += d;
-                    a5[3] += d * d;
-                    a5[4] += static_cast<double>(p1);
+                    const T gx = xp - f, gy = yp[j][v] - f, gz = zp - f;
+                    const T d = f - shift[j];
+                    T* q5 = part + kSumsPerField * j;
+                    q5[0] += ps * ps;
+                    q5[1] += gx * gx + gy * gy + gz * gz;
+                    q5[2] += d;
+                    q5[3] += d * d;
+                    q5[4] += p1;
                 }
             }
             if (A.write_out) {
-                const size_t off = base + static_cast<size_t>(yrow[k]) * N + zc;
 #pragma unroll
                 for (int j = 0; j < NF; ++j) {
-                    vstore(fout[j] + off, cur[j][k]);
-                    vstore(pout[j] + off, pnew[j]);
+                    vstore(fout[j] + base + yrow[k], cur[j][k]);
+                    vstore(pout[j] + base + yrow[k], pnew[j]);
                 }
             }
         }
+#pragma unroll
+        for (int q = 0; q < NS; ++q) acc[q] += static_cast<double>(part[q]);
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < NF; ++j)
@@ -467,6 +478,22 @@ __global__ void init_scalars_kernel(Scal* sc, double a, double b, double eta, do
     s.nonfinite = 0;
     s.pad = 0;
     *sc = s;
+}
+
+// Plain streaming copy (16-byte vectors, grid-stride): the achievable
+// read+write bandwidth ceiling for the pass kernels' access pattern.
+__global__ __launch_bounds__(256) void copy_kernel(const float4* __restrict__ in, float4* __restrict__ out,
+                                                   size_t n) {
+    const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
+    for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) out[i] = in[i];
+}
+
+hipError_t launch_copy(const void* in, void* out, size_t bytes, hipStream_t s) {
+    const size_t n = bytes / 16;
+    const int blocks = 256 * 32;
+    hipLaunchKernelGGL(copy_kernel, dim3(blocks), dim3(256), 0, s, static_cast<const float4*>(in),
+                       static_cast<float4*>(out), n);
+    return hipGetLastError();
 }
 
 hipError_t launch_init_scalars(Scal* sc, double a, double b, double eta, const Phys& ph,
@@ -518,6 +545,34 @@ Tile default_tile(int N, cl_precision prec, int nf) {
     (void)nf;
     finalize_tile(t, N, prec);
     return t;
+}
+
+void candidate_tiles(int N, cl_precision prec, int nf, Tile* out, int* count, int cap) {
+    const int V = prec == CL_FP32 ? 4 : 2;
+    int n = 0;
+    for (int tzm : {64, 32, 16}) {
+        const int TZ = N < tzm * V ? N : tzm * V;
+        if (tzm != 64 && TZ == N) continue;  // same as the full-row candidate
+        const int BZ = TZ / V;
+        for (int RY : {1, 2})
+            for (int NT : {64, 128, 256}) {
+                if (NT < BZ) continue;
+                const int TY = (NT / BZ) * RY;
+                if (TY > N) continue;
+                for (int CX = 2; CX <= N; CX *= 2) {
+                    if (CX != N && (CX < 4 || CX > 256)) continue;
+                    Tile t;
+                    t.TZ = TZ;
+                    t.TY = TY;
+                    t.CX = CX;
+                    t.RY = RY;
+                    if (!finalize_tile(t, N, prec)) continue;
+                    if (pass_lds_bytes(t, prec, nf) > 60 * 1024) continue;
+                    if (n < cap) out[n++] = t;
+                }
+            }
+    }
+    *count = n;
 }
 
 template <typename T, int NF, int RY, int HI>

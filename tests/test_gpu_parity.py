@@ -44,12 +44,20 @@ def rel_err(got, want):
     return np.max(np.abs(got - want) / np.maximum(np.abs(want), 1e-300))
 
 
-def compare_records(recs_gpu, recs_orc, nf, tol, expansion="self", skip_var=False):
-    keys = ["a", "H", "EV"] if expansion == "self" else ["EV"]
+def compare_records(recs_gpu, recs_orc, nf, tol, expansion="self", skip_var=False, energy_scale=False):
+    """Per-step relative comparison.  With energy_scale, the kinetic and
+    potential energies -- which pass through zero as the homogeneous field
+    oscillates -- are compared relative to the total energy density rho of
+    the same step instead of to themselves."""
+    keys = ["a", "H"] if expansion == "self" else []
     for k in keys:
         g = recs_gpu[k]
         o = np.array([r[k] for r in recs_orc])
         assert rel_err(g, o) <= tol, (k, rel_err(g, o))
+    rho = np.array([sum(r["EK"]) + sum(r["EG"]) + r["EV"] for r in recs_orc])
+    o = np.array([r["EV"] for r in recs_orc])
+    scale = rho if energy_scale else np.abs(o)
+    assert np.max(np.abs(recs_gpu["EV"] - o) / scale) <= tol, ("EV", np.max(np.abs(recs_gpu["EV"] - o) / scale))
     g = recs_gpu["eta"]
     o = np.array([r["eta"] for r in recs_orc])
     assert np.max(np.abs(g - o)) <= 1e-12 * np.max(np.abs(o))
@@ -57,7 +65,9 @@ def compare_records(recs_gpu, recs_orc, nf, tol, expansion="self", skip_var=Fals
         for k in (["EK", "EG"] + ([] if skip_var else ["var"])):
             g = recs_gpu[k][:, j]
             o = np.array([r[k][j] for r in recs_orc])
-            assert rel_err(g, o) <= tol, (k, j, rel_err(g, o))
+            sc = rho if (energy_scale and k == "EK") else np.abs(o)
+            err = np.max(np.abs(g - o) / np.maximum(sc, 1e-300))
+            assert err <= tol, (k, j, err)
         g = recs_gpu["mean"][:, j]
         o = np.array([r["mean"][j] for r in recs_orc])
         scale = max(np.max(np.abs(o)), 1e-300)
@@ -91,7 +101,8 @@ def run_both(w, n, integrator, expansion="self", precision="fp64", amp=None):
     lat.set_fields(s0.f, s0.p)
     st = lat.get_state()
     if expansion == "self":
-        assert abs(st["b"] - s0.b) <= 1e-12 * s0.b
+        # FP32 storage rounds f, p at ~6e-8 relative, which moves rho and b0
+        assert abs(st["b"] - s0.b) <= (1e-12 if precision == "fp64" else 1e-6) * s0.b
     recs = lat.step(integrator, w.dt, n)
     f, p = lat.get_fields()
     s, orecs = L.run(s0, w.dt, n, P, integrator)
@@ -146,7 +157,7 @@ def test_fp32_parity_config0():
     volume averages within 1e-4 relative over the 200-step run."""
     w = W.C0
     recs, orecs, (f, p), s = run_both(w, w.steps, "leapfrog", precision="fp32")
-    compare_records(recs, orecs, 1, 1e-4)
+    compare_records(recs, orecs, 1, 1e-4, energy_scale=True)
     # fields: FP32 storage rounding bounds the norm-wise error
     assert np.max(np.abs(f - s.f)) <= 1e-5 * np.max(np.abs(s.f))
 
@@ -155,7 +166,7 @@ def test_fp32_parity_config0():
 def test_fp32_parity_two_field(integrator):
     w = W.C1.with_(N=32, k_ir=2.0, precision="fp32")
     recs, orecs, (f, p), s = run_both(w, 30, integrator, amp=1.0)
-    compare_records(recs, orecs, 2, 1e-4)
+    compare_records(recs, orecs, 2, 1e-4, energy_scale=True)
 
 
 # ------------------------------------------------------------------ runtime properties
@@ -209,21 +220,77 @@ def test_deterministic_and_checkpoint_resume():
         assert np.array_equal(r2b[k], outs[0][1][k]), k
 
 
-def test_graph_and_direct_launch_agree():
-    """Repeated calls with the same shape replay a cached HIP graph; the
-    first call and n = 1 calls launch directly.  All give the same numbers."""
+def test_graph_and_direct_launch_agree(monkeypatch):
+    """Repeated calls of one shape replay a cached HIP graph (one per
+    starting buffer); CL_NO_GRAPH=1 launches every pass directly.  Both give
+    bitwise equal results.  Calls of different lengths agree to rounding
+    only (adjacent half kicks are merged inside a call)."""
+    w = W.C0.with_(N=16)
+    s0 = oracle_seed(w, amp=10.0)
+    outs = []
+    for env in ("0", "1"):
+        monkeypatch.setenv("CL_NO_GRAPH", env)
+        lat = make_lattice(w)
+        lat.set_fields(s0.f, s0.p)
+        r = np.concatenate([lat.step("leapfrog", w.dt, 3) for _ in range(3)]
+                           + [lat.step("vv4", w.dt, 2) for _ in range(3)])
+        outs.append((r, lat.get_fields()[0]))
+        lat.close()
+    assert outs[0][0].tobytes() == outs[1][0].tobytes()
+    assert np.array_equal(outs[0][1], outs[1][1])
+    lat = make_lattice(w)
+    lat.set_fields(s0.f, s0.p)
+    r1 = np.concatenate([lat.step("leapfrog", w.dt, 1) for _ in range(9)])
+    lat.close()
+    assert rel_err(r1["EG"][:, 0], outs[0][0]["EG"][:9, 0]) <= 1e-12
+    assert rel_err(r1["a"], outs[0][0]["a"][:9]) <= 1e-14
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_tiles_agree(precision):
+    """Every candidate tile computes the same site updates: fields bitwise
+    equal across tiles, lattice sums equal up to summation order."""
+    w = W.C1.with_(N=32, k_ir=2.0, precision=precision)
+    s0 = oracle_seed(w, amp=5.0)
+    lat = make_lattice(w)
+    lat.set_fields(s0.f, s0.p)
+    rep = lat.autotune(reps=1)
+    lat.close()
+    tiles = rep["candidates"]
+    assert len(tiles) >= 4
+    ref = None
+    for t in tiles[:: max(1, len(tiles) // 12)] + [rep["best"]]:
+        lat = make_lattice(w)
+        lat.set_tile(t["tz"], t["ty"], t["cx"], t["ry"])
+        lat.set_fields(s0.f, s0.p)
+        r = lat.step("vv4", w.dt, 4)
+        f, p = lat.get_fields()
+        lat.close()
+        if ref is None:
+            ref = (r, f, p)
+            continue
+        assert np.array_equal(f, ref[1]) and np.array_equal(p, ref[2]), t
+        tol = 1e-13 if precision == "fp64" else 1e-6
+        for k in ("a", "EV"):
+            assert rel_err(r[k], ref[0][k]) <= tol, (t, k)
+        assert rel_err(r["EG"][:, 1], ref[0]["EG"][:, 1]) <= tol, t
+
+
+def test_autotune_keeps_state():
     w = W.C0.with_(N=16)
     s0 = oracle_seed(w, amp=10.0)
     lat = make_lattice(w)
     lat.set_fields(s0.f, s0.p)
-    ra = np.concatenate([lat.step("leapfrog", w.dt, 1) for _ in range(6)])
-    fa, _ = lat.get_fields()
-    lat.set_fields(s0.f, s0.p)
-    rb = np.concatenate([lat.step("leapfrog", w.dt, 3) for _ in range(2)])
-    fb, _ = lat.get_fields()
+    st0 = lat.get_state()
+    rep = lat.autotune(reps=2)
+    assert lat.get_tile() == {k: rep["best"][k] for k in ("tz", "ty", "cx", "ry")}
+    assert lat.get_state() == st0
+    f, p = lat.get_fields()
+    assert np.array_equal(f, s0.f) and np.array_equal(p, s0.p)
+    lib = _lib()
+    with pytest.raises(lib.CLError):
+        lat.set_tile(12, 4, 4, 1)
     lat.close()
-    assert np.array_equal(fa, fb)
-    assert np.array_equal(ra["a"], rb["a"]) and np.array_equal(ra["EG"], rb["EG"])
 
 
 def test_errors_and_instability():
