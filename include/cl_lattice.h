@@ -119,14 +119,16 @@ cl_status cl_destroy(cl_lattice* h);
  * caller keeps the stream alive while h uses it. */
 cl_status cl_set_stream(cl_lattice* h, void* hip_stream);
 
-/* Use caller-owned device buffers instead of library-owned ones.  Each array
- * holds n_fields device pointers, each to N^3 values of the handle's
- * precision, 16-byte aligned: f[j], p[j] are the current state, f_pp[j],
- * p_pp[j] the ping-pong partners.  Library-owned field buffers are freed.
- * The caller keeps the memory alive until cl_destroy.  The current field
- * values are not copied: set them afterwards. */
-cl_status cl_attach_device_buffers(cl_lattice* h, void* const* f, void* const* p,
-                                   void* const* f_pp, void* const* p_pp);
+/* Use caller-owned device memory instead of library-owned buffers.  Each of
+ * the two buffers (the state and its ping-pong partner) holds
+ * 2 * n_fields * N^3 values of the handle's precision, 16-byte aligned, in the
+ * library's row-interleaved layout: for row (x, y) the arrays f_0 ..
+ * f_{n_fields-1}, pi_0 .. pi_{n_fields-1} follow each other, N values each,
+ * so array a at (x, y, z) is element ((x*N + y)*2*n_fields + a)*N + z.  The
+ * current state is in `state`.  Library-owned buffers are freed.  The caller
+ * keeps the memory alive until cl_destroy.  Field values are not copied: set
+ * them afterwards. */
+cl_status cl_attach_device_buffers(cl_lattice* h, void* state, void* state_pp);
 
 /* Background: alpha-time exponent alpha (Eq. FLRWmetric; 0 cosmic, 1
  * conformal), expansion mode, reduced Planck mass m_p in program units, and

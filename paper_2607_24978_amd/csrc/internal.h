@@ -55,17 +55,20 @@ struct Tile {
 
 // One pass over the lattice: optional drift, kick, lattice sums and the
 // last-workgroup background update.
+//
+// Device layout of a state buffer: for every (x, y) row, the 2*nf arrays
+// f_0 .. f_{nf-1}, pi_0 .. pi_{nf-1} follow each other, each N values along z:
+// element (a, x, y, z) at ((x*N + y)*2*nf + a)*N + z.  A pass then reads one
+// contiguous address stream and writes another.
 struct PassArgs {
-    const void* f_in[2];
-    const void* p_in[2];
-    void* f_out[2];
-    void* p_out[2];
+    const void* in;   // state read by the pass
+    void* out;        // state written by the pass (the ping-pong partner)
     int N;
     int TZ, TY, CX, nbz, nby, nbx;
     int drift;      // 1: drift f by cd * p before the kick
     int write_out;  // 0: reduction only (no field writes, no kick)
     int rec;        // observable slot for this pass, -1: none
-    int pad;
+    int flags;      // bit 0: nontemporal stores, bit 1: nontemporal loads
     double kt;      // kick multiplier for the stored momenta
     double kb;      // kick multiplier for the synchronised momenta (energies)
     double h_next;  // drift step of the following pass, 0: call ends here

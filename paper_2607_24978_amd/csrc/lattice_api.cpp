@@ -48,7 +48,8 @@ struct cl_lattice {
     bool own_stream = false;
     bool own_buffers = true;
     int device = 0;
-    void* buf[2][2][2] = {};  // [ping-pong][0 = f, 1 = p][field]
+    void* buf[2] = {nullptr, nullptr};  // ping-pong state buffers (row-interleaved layout)
+    int pass_flags = 1;                 // nontemporal stores
     int cur = 0;
     Scal* sc = nullptr;
     double* partials = nullptr;
@@ -144,13 +145,9 @@ cl_status ensure_obs(cl_lattice* h, int n) {
 
 PassArgs base_args(cl_lattice* h, int in) {
     PassArgs a{};
-    for (int j = 0; j < 2; ++j) {
-        const int jj = j < h->nf ? j : 0;
-        a.f_in[j] = h->buf[in][0][jj];
-        a.p_in[j] = h->buf[in][1][jj];
-        a.f_out[j] = h->buf[in ^ 1][0][jj];
-        a.p_out[j] = h->buf[in ^ 1][1][jj];
-    }
+    a.in = h->buf[in];
+    a.out = h->buf[in ^ 1];
+    a.flags = h->pass_flags;
     a.N = h->N;
     a.TZ = h->tile.TZ;
     a.TY = h->tile.TY;
@@ -263,9 +260,12 @@ cl_status reset_background(cl_lattice* h, const double* mean) {
     return CL_OK;
 }
 
+// Host SoA arrays (field-major, N^3 each) <-> device row-interleaved state:
+// array a of row r sits at (r * 2nf + a) * N.
 template <typename T>
 cl_status upload(cl_lattice* h, const double* f, const double* p) {
     const size_t n = sites(h);
+    const size_t N = static_cast<size_t>(h->N);
     std::vector<T> tmp;
     try {
         tmp.resize(n);
@@ -277,8 +277,10 @@ cl_status upload(cl_lattice* h, const double* f, const double* p) {
         for (int j = 0; j < h->nf; ++j) {
             const double* s = src + j * n;
             for (size_t i = 0; i < n; ++i) tmp[i] = static_cast<T>(s[i]);
-            HIPCHECK(h, hipMemcpyAsync(h->buf[h->cur][which][j], tmp.data(), n * sizeof(T),
-                                       hipMemcpyHostToDevice, h->stream));
+            const int arr = which * h->nf + j;
+            char* dst = static_cast<char*>(h->buf[h->cur]) + arr * N * sizeof(T);
+            HIPCHECK(h, hipMemcpy2DAsync(dst, 2 * h->nf * N * sizeof(T), tmp.data(), N * sizeof(T), N * sizeof(T),
+                                         N * N, hipMemcpyHostToDevice, h->stream));
             HIPCHECK(h, hipStreamSynchronize(h->stream));
         }
     }
@@ -288,6 +290,7 @@ cl_status upload(cl_lattice* h, const double* f, const double* p) {
 template <typename T>
 cl_status download(cl_lattice* h, double* f, double* p) {
     const size_t n = sites(h);
+    const size_t N = static_cast<size_t>(h->N);
     std::vector<T> tmp;
     try {
         tmp.resize(n);
@@ -298,8 +301,10 @@ cl_status download(cl_lattice* h, double* f, double* p) {
         double* dst = which == 0 ? f : p;
         if (!dst) continue;
         for (int j = 0; j < h->nf; ++j) {
-            HIPCHECK(h, hipMemcpyAsync(tmp.data(), h->buf[h->cur][which][j], n * sizeof(T),
-                                       hipMemcpyDeviceToHost, h->stream));
+            const int arr = which * h->nf + j;
+            const char* src = static_cast<const char*>(h->buf[h->cur]) + arr * N * sizeof(T);
+            HIPCHECK(h, hipMemcpy2DAsync(tmp.data(), N * sizeof(T), src, 2 * h->nf * N * sizeof(T), N * sizeof(T),
+                                         N * N, hipMemcpyDeviceToHost, h->stream));
             HIPCHECK(h, hipStreamSynchronize(h->stream));
             double* d = dst + j * n;
             for (size_t i = 0; i < n; ++i) d[i] = static_cast<double>(tmp[i]);
@@ -351,12 +356,10 @@ bool cached_tile(int N, int nf, cl_precision prec, Tile& t) {
 
 void free_buffers(cl_lattice* h) {
     if (!h->own_buffers) return;
-    for (auto& a : h->buf)
-        for (auto& b : a)
-            for (auto& c : b) {
-                if (c) hipFree(c);
-                c = nullptr;
-            }
+    for (auto& b : h->buf) {
+        if (b) hipFree(b);
+        b = nullptr;
+    }
 }
 
 }  // namespace
@@ -394,17 +397,16 @@ cl_status cl_create(int N, double dx, int n_fields, cl_precision prec, cl_lattic
     if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess)
         return bail(CL_EDEVICE, "hipStreamCreate failed");
     h->own_stream = true;
-    const size_t bytes = sites(h) * elem_size(prec);
-    for (int pp = 0; pp < 2; ++pp)
-        for (int w = 0; w < 2; ++w)
-            for (int j = 0; j < n_fields; ++j) {
-                if (hipMalloc(&h->buf[pp][w][j], bytes) != hipSuccess) {
-                    h->buf[pp][w][j] = nullptr;
-                    return bail(CL_ENOMEM, "device field buffers (" + std::to_string(4 * n_fields * bytes) +
-                                               " bytes)");
-                }
-                hipMemsetAsync(h->buf[pp][w][j], 0, bytes, h->stream);
-            }
+    const size_t bytes = 2 * n_fields * sites(h) * elem_size(prec);
+    for (int pp = 0; pp < 2; ++pp) {
+        if (hipMalloc(&h->buf[pp], bytes) != hipSuccess) {
+            h->buf[pp] = nullptr;
+            return bail(CL_ENOMEM, "device state buffers (2 x " + std::to_string(bytes) + " bytes)");
+        }
+        hipMemsetAsync(h->buf[pp], 0, bytes, h->stream);
+    }
+    const char* nt = std::getenv("CL_PASS_FLAGS");
+    if (nt && nt[0]) h->pass_flags = std::atoi(nt);
     if (hipMalloc(&h->sc, sizeof(Scal)) != hipSuccess) return bail(CL_ENOMEM, "scalar block");
     if (hipMalloc(&h->ticket, 64) != hipSuccess) return bail(CL_ENOMEM, "ticket");
     if (hipMemsetAsync(h->ticket, 0, 64, h->stream) != hipSuccess) return bail(CL_EDEVICE, "memset");
@@ -442,27 +444,18 @@ cl_status cl_set_stream(cl_lattice* h, void* s) {
     return CL_OK;
 }
 
-cl_status cl_attach_device_buffers(cl_lattice* h, void* const* f, void* const* p, void* const* fpp,
-                                   void* const* ppp) {
+cl_status cl_attach_device_buffers(cl_lattice* h, void* state, void* state_pp) {
     if (!h) return fail(nullptr, CL_EINVAL, "handle is NULL");
-    if (!f || !p || !fpp || !ppp) return fail(h, CL_EINVAL, "buffer arrays must not be NULL");
-    for (int j = 0; j < h->nf; ++j) {
-        void* arr[4] = {f[j], p[j], fpp[j], ppp[j]};
-        for (void* x : arr) {
-            if (!x) return fail(h, CL_EINVAL, "device buffer pointer is NULL");
-            if (reinterpret_cast<uintptr_t>(x) % 16) return fail(h, CL_EINVAL, "device buffers must be 16-byte aligned");
-        }
-    }
+    if (!state || !state_pp) return fail(h, CL_EINVAL, "device buffer pointer is NULL");
+    if (state == state_pp) return fail(h, CL_EINVAL, "the two state buffers must differ");
+    for (void* x : {state, state_pp})
+        if (reinterpret_cast<uintptr_t>(x) % 16) return fail(h, CL_EINVAL, "device buffers must be 16-byte aligned");
     HIPCHECK(h, hipStreamSynchronize(h->stream));
     free_buffers(h);
     h->own_buffers = false;
     h->cur = 0;
-    for (int j = 0; j < h->nf; ++j) {
-        h->buf[0][0][j] = f[j];
-        h->buf[0][1][j] = p[j];
-        h->buf[1][0][j] = fpp[j];
-        h->buf[1][1][j] = ppp[j];
-    }
+    h->buf[0] = state;
+    h->buf[1] = state_pp;
     drop_graph(h);
     return CL_OK;
 }

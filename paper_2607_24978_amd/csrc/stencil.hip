@@ -9,9 +9,10 @@
 // The scale factor rides along as a homogeneous degree of freedom with its
 // own kick and drift (Sect. 4.1, Eqs. SchemeContVirgin1-2).
 //
-// Memory layout: one array per field and per momentum, z fastest.  A pass
-// reads (f, pi) from one buffer pair and writes the other (ping-pong), since
-// the drift of halo cells needs the old momenta of neighbouring tiles.
+// Memory layout: per (x, y) row the arrays f_0.., pi_0.. follow each other,
+// z fastest, so a pass reads one contiguous address stream and writes
+// another.  A pass reads one state buffer and writes the other (ping-pong),
+// since the drift of halo cells needs the old momenta of neighbouring tiles.
 //
 // Blocking: a workgroup owns a TZ x TY tile of (z, y) and marches over CX
 // x-planes.  Each x-plane of drifted f (tile plus a one-cell y/z halo) is
@@ -35,6 +36,29 @@ __device__ __forceinline__ void vload(const T* p, T (&out)[VecOf<T>::V]) {
     VT v = *reinterpret_cast<const VT*>(p);
     if constexpr (VecOf<T>::V == 4) { out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w; }
     else { out[0] = v.x; out[1] = v.y; }
+}
+
+template <typename T> struct NatVec;
+template <> struct NatVec<float> { typedef float type __attribute__((ext_vector_type(4))); };
+template <> struct NatVec<double> { typedef double type __attribute__((ext_vector_type(2))); };
+
+// Streaming variants: the nontemporal hint keeps data that is not reused in
+// this pass from displacing the halo lines in the caches.
+template <typename T>
+__device__ __forceinline__ void vload_nt(const T* p, T (&out)[VecOf<T>::V]) {
+    using NV = typename NatVec<T>::type;
+    NV v = __builtin_nontemporal_load(reinterpret_cast<const NV*>(p));
+#pragma unroll
+    for (int i = 0; i < VecOf<T>::V; ++i) out[i] = v[i];
+}
+
+template <typename T>
+__device__ __forceinline__ void vstore_nt(T* p, const T (&in)[VecOf<T>::V]) {
+    using NV = typename NatVec<T>::type;
+    NV v;
+#pragma unroll
+    for (int i = 0; i < VecOf<T>::V; ++i) v[i] = in[i];
+    __builtin_nontemporal_store(v, reinterpret_cast<NV*>(p));
 }
 
 template <typename T>
@@ -224,17 +248,21 @@ __global__ __launch_bounds__(256) void lattice_pass(PassArgs A) {
     const int bx = bid / (A.nbz * A.nby);
     const int z0 = bz * TZ, y0 = by * TY, x0 = bx * CX;
 
+    // Row-interleaved state: array a of row (x, y) starts at ((x*N + y)*2NF + a)*N.
+    const int rs = 2 * NF * N;  // row stride (elements)
     const T* fin[NF];
     const T* pin[NF];
     T* fout[NF];
     T* pout[NF];
 #pragma unroll
     for (int j = 0; j < NF; ++j) {
-        fin[j] = static_cast<const T*>(A.f_in[j]);
-        pin[j] = static_cast<const T*>(A.p_in[j]);
-        fout[j] = static_cast<T*>(A.f_out[j]);
-        pout[j] = static_cast<T*>(A.p_out[j]);
+        fin[j] = static_cast<const T*>(A.in) + j * N;
+        pin[j] = static_cast<const T*>(A.in) + (NF + j) * N;
+        fout[j] = static_cast<T*>(A.out) + j * N;
+        pout[j] = static_cast<T*>(A.out) + (NF + j) * N;
     }
+    const bool nt_store = A.flags & 1;
+    const bool nt_load = A.flags & 2;
 
     const Scal* sc = A.sc;
     const T cd = A.drift ? static_cast<T>(sc->cd) : T(0);
@@ -262,7 +290,7 @@ __global__ __launch_bounds__(256) void lattice_pass(PassArgs A) {
     const int zc = z0 + tz * V;
     int yrow[RY];
 #pragma unroll
-    for (int k = 0; k < RY; ++k) yrow[k] = (y0 + tr + k * RL) * N + zc;
+    for (int k = 0; k < RY; ++k) yrow[k] = (y0 + tr + k * RL) * rs + zc;
 
     // Halo items of this thread (row halo: V values; z halo: 1 value).
     const int nhalo = 2 * BZ + 2 * TY;
@@ -279,20 +307,20 @@ __global__ __launch_bounds__(256) void lattice_pass(PassArgs A) {
             if (item < 2 * BZ) {
                 const int side = item / BZ, cz = item % BZ;
                 const int y = side == 0 ? (y0 - 1 + N) % N : (y0 + TY) % N;
-                h_goff[q] = y * N + z0 + cz * V;
+                h_goff[q] = y * rs + z0 + cz * V;
                 h_lds[q] = (side == 0 ? 0 : TY + 1) * S + V + cz * V;
                 h_vec[q] = true;
             } else {
                 const int kk = item - 2 * BZ;
                 const int row = kk >> 1, side = kk & 1;
                 const int z = side == 0 ? (z0 - 1 + N) % N : (z0 + TZ) % N;
-                h_goff[q] = (y0 + row) * N + z;
+                h_goff[q] = (y0 + row) * rs + z;
                 h_lds[q] = (row + 1) * S + (side == 0 ? V - 1 : V + TZ);
             }
         }
     }
 
-    const size_t plane = static_cast<size_t>(N) * N;
+    const size_t plane = static_cast<size_t>(N) * rs;
     // Raw (undrifted) loads of one plane: own values and halo items.
     T rf[NF][RY][V], rp[NF][RY][V], hf[NF][HI][V], hp[NF][HI][V];
     auto issue = [&](int x, bool halo) {
@@ -301,8 +329,13 @@ __global__ __launch_bounds__(256) void lattice_pass(PassArgs A) {
         for (int j = 0; j < NF; ++j) {
 #pragma unroll
             for (int k = 0; k < RY; ++k) {
-                vload(fin[j] + base + yrow[k], rf[j][k]);
-                vload(pin[j] + base + yrow[k], rp[j][k]);
+                if (nt_load) {
+                    vload_nt(fin[j] + base + yrow[k], rf[j][k]);
+                    vload_nt(pin[j] + base + yrow[k], rp[j][k]);
+                } else {
+                    vload(fin[j] + base + yrow[k], rf[j][k]);
+                    vload(pin[j] + base + yrow[k], rp[j][k]);
+                }
             }
             if (halo) {
 #pragma unroll
@@ -436,8 +469,13 @@ __global__ __launch_bounds__(256) void lattice_pass(PassArgs A) {
             if (A.write_out) {
 #pragma unroll
                 for (int j = 0; j < NF; ++j) {
-                    vstore(fout[j] + base + yrow[k], cur[j][k]);
-                    vstore(pout[j] + base + yrow[k], pnew[j]);
+                    if (nt_store) {
+                        vstore_nt(fout[j] + base + yrow[k], cur[j][k]);
+                        vstore_nt(pout[j] + base + yrow[k], pnew[j]);
+                    } else {
+                        vstore(fout[j] + base + yrow[k], cur[j][k]);
+                        vstore(pout[j] + base + yrow[k], pnew[j]);
+                    }
                 }
             }
         }
