@@ -43,22 +43,47 @@ def kpass_bytes_per_site(precision: str, nf: int) -> int:
     return 3 * nf * (4 if precision == "fp32" else 8)
 
 
-def make(w, precision, stream):
+def measured_traffic(workload: str, tile: dict):
+    """HBM bytes per launch from the committed rocprofv3 counter record, or None
+    when the kernel source changed since the counters were taken or the tile
+    differs."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = open(os.path.join(ROOT, rec["kernel_source"]), "rb").read()
+    if hashlib.sha256(src).hexdigest()[:16] != rec["sha256_prefix"]:
+        return None
+    key = [tile["tz"], tile["ty"], tile["cx"], tile["ry"], tile["pd"]]
+    for e in rec["entries"]:
+        if e["workload"] == workload and e["tile"] == key:
+            return e["traffic_bytes_per_launch"]
+    return None
+
+
+def make(w, precision, stream, tune=True, tile=None):
     from paper_2607_24978_amd import _lib
     lat = _lib.Lattice(w.N, w.dx, w.n_fields, precision)
     lat.set_stream(stream.cuda_stream)
     lat.set_background(w.alpha, w.expansion, w.mp, w.a0)
     lat.set_potential(w.m2, w.lam, w.g2, w.V0)
     lat.seed(w.seed, w.fbar[:w.n_fields], w.pbar[:w.n_fields], w.cutoff_modes, w.amp)
+    if tile is not None:
+        lat.set_tile(*tile)
+    elif tune:
+        lat.autotune(reps=3)  # the library's own tile search (state is left unchanged)
     return lat
 
 
-def timed_run(w, precision, steps, warmup, chunk):
-    """Seed, run `warmup` untimed steps, then `steps` timed steps in calls of
-    `chunk` steps.  Returns (records of all steps, seconds, event ms, passes)."""
+def timed_run(w, precision, steps, warmup, chunk, tune=True, tile=None):
+    """Seed, autotune, run `warmup` untimed steps, then `steps` timed steps in
+    calls of `chunk` steps.  Returns (records of all steps, seconds, event ms,
+    fused passes, calls, tile)."""
     import torch
     stream = torch.cuda.Stream()
-    lat = make(w, precision, stream)
+    lat = make(w, precision, stream, tune, tile)
+    tile = lat.get_tile()
     recs = []
     for _ in range(warmup // chunk):
         recs.append(lat.step(w.integrator, w.dt, chunk))
@@ -78,25 +103,30 @@ def timed_run(w, precision, steps, warmup, chunk):
     lat.close()
     per = 3 if w.integrator == "vv4" else 1
     dk_passes = ncalls * chunk * per
-    return np.concatenate(recs), t1 - t0, e0.elapsed_time(e1), dk_passes, ncalls
+    return np.concatenate(recs), t1 - t0, e0.elapsed_time(e1), dk_passes, ncalls, tile
 
 
 def linear_regime_deviation(r32, r64, nf):
     """Max relative deviation of the FP32 run's volume averages from the FP64
-    run's, over the steps where every field's variance is still within
-    1e4 of its initial value (the linear regime)."""
+    run's, over the steps where every field's variance is still within 1e4 of
+    its initial value (the linear regime).  a, H, EG and var are compared to
+    themselves; EK and EV, which pass through zero as the homogeneous field
+    oscillates, relative to the total energy density of the same step."""
     v0 = r64["var"][0, :nf]
     lin = np.all(r64["var"][:, :nf] <= 1e4 * v0, axis=1)
     end = int(np.argmin(lin)) if not np.all(lin) else len(lin)
     out = {"linear_regime_steps": end}
+    rho = (r64["EK"][:end, :nf].sum(1) + r64["EG"][:end, :nf].sum(1) + r64["EV"][:end])
     worst = 0.0
-    for k in ("a", "EV"):
-        d = np.max(np.abs(r32[k][:end] - r64[k][:end]) / np.abs(r64[k][:end]))
+    for k in ("a", "H", "EV"):
+        scale = rho if k == "EV" else np.abs(r64[k][:end])
+        d = np.max(np.abs(r32[k][:end] - r64[k][:end]) / scale)
         out[k] = float(d)
         worst = max(worst, d)
     for k in ("EK", "EG", "var"):
         for j in range(nf):
-            d = np.max(np.abs(r32[k][:end, j] - r64[k][:end, j]) / np.abs(r64[k][:end, j]))
+            scale = rho if k == "EK" else np.abs(r64[k][:end, j])
+            d = np.max(np.abs(r32[k][:end, j] - r64[k][:end, j]) / scale)
             out[f"{k}{j}"] = float(d)
             worst = max(worst, d)
     out["max"] = float(worst)
@@ -124,11 +154,15 @@ def cpu_baseline(w, steps=1):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5000)
-    ap.add_argument("--warmup", type=int, default=500)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (5000 for c1, 200 for c3)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps (500 for c1, 50 for c3)")
     ap.add_argument("--chunk", type=int, default=500)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--tile", default=None, help="force the FP32 tile tz,ty,cx,ry,pd instead of autotuning")
+    ap.add_argument("--workload", choices=["c1", "c3"], default="c1",
+                    help="c1: 256^3 two-field VV4 (default); c3: 1024^3 two-field leapfrog")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -136,11 +170,21 @@ def main():
     import torch
     torch.cuda.set_device(0)
 
-    w = W.C1
+    from paper_2607_24978_amd import _lib
+    w = W.C1 if args.workload == "c1" else W.C3
+    if args.workload == "c3":
+        args.no_fp64 = True  # the all-FP64 form of the 1024^3 run is not part of this workload
+    if args.steps is None:
+        args.steps = 5000 if args.workload == "c1" else 200
+    if args.warmup is None:
+        args.warmup = 500 if args.workload == "c1" else 50
     chunk = max(1, min(args.chunk, args.steps))
     if args.steps % chunk:
         chunk = math.gcd(args.steps, chunk)
-    r32, sec32, ms32, dk32, calls32 = timed_run(w, "fp32", args.steps, args.warmup, chunk)
+    copy_gbs = _lib.copy_bandwidth(1 << 30, 10)
+    tile = tuple(int(v) for v in args.tile.split(",")) if args.tile else None
+    r32, sec32, ms32, dk32, calls32, tile32 = timed_run(w, "fp32", args.steps, args.warmup, chunk,
+                                                       not args.no_tune, tile)
     value = w.sites * args.steps / sec32
     ms_per_step = 1e3 * sec32 / args.steps
     # dominant kernel: the fused drift-kick-reduce pass (plus one opening kick per call)
@@ -154,15 +198,17 @@ def main():
         "vs_baseline": None, "dtype": "fp32", "data": "synthetic (seeded vacuum fluctuations)",
         "config": {"workload": w.name, "N": w.N, "n_fields": w.n_fields, "k_ir": w.k_ir, "q": w.g2,
                    "integrator": w.integrator, "dt": w.dt, "sums_and_scale_factor": "fp64",
-                   "steps_per_call": chunk, "parallelism": "1 GPU"},
+                   "steps_per_call": chunk, "tile": tile32, "parallelism": "1 GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(w.name, tile32),
                      "kernel": "lattice_pass<float,2>", "avg_launch_us": avg_ms * 1e3,
-                     "alg_bytes_per_launch": alg / launches},
+                     "alg_bytes_per_launch": alg / launches,
+                     "copy_ceiling_GBps": copy_gbs, "frac_of_copy_ceiling": achieved / copy_gbs},
     }
     forms = {"fp32": {"site_updates_per_s": value, "hbm_frac": achieved / HBM_PEAK_GBS}}
     if not args.no_fp64:
-        r64, sec64, ms64, dk64, calls64 = timed_run(w, "fp64", args.steps, args.warmup, chunk)
+        r64, sec64, ms64, dk64, calls64, _ = timed_run(w, "fp64", args.steps, args.warmup, chunk,
+                                                        not args.no_tune)
         alg64 = dk64 * bytes_per_site("fp64", 2) * w.sites + calls64 * kpass_bytes_per_site("fp64", 2) * w.sites
         ach64 = alg64 / (ms64 * 1e-3) / 1e9
         forms["fp64"] = {"site_updates_per_s": w.sites * args.steps / sec64, "hbm_frac": ach64 / HBM_PEAK_GBS}
@@ -170,7 +216,8 @@ def main():
         forms["fp32_speedup_vs_fp64"] = value / forms["fp64"]["site_updates_per_s"]
     line["forms"] = forms
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(w, steps=1)
+        # the oracle on the 256^3 workload (the 1024^3 one does not fit a numpy run of ~30 s)
+        line["cpu_baseline"] = cpu_baseline(W.C1, steps=1)
     print(json.dumps(line), flush=True)
 
 

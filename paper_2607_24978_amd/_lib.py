@@ -11,6 +11,14 @@ import os
 
 import numpy as np
 
+# PyTorch ships its own HIP runtime under the same soname as the system one.
+# Load it first so the library, torch streams and torch device memory share
+# one runtime instance in this process.
+try:
+    import torch  # noqa: F401
+except ImportError:  # the library also works without torch
+    torch = None
+
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libcl_lattice.so")
 
@@ -38,7 +46,7 @@ class cl_observables(C.Structure):
 
 
 class cl_tile(C.Structure):
-    _fields_ = [("tz", C.c_int), ("ty", C.c_int), ("cx", C.c_int), ("ry", C.c_int)]
+    _fields_ = [("tz", C.c_int), ("ty", C.c_int), ("cx", C.c_int), ("ry", C.c_int), ("pd", C.c_int)]
 
 
 OBS_DTYPE = np.dtype([("eta", "f8"), ("a", "f8"), ("H", "f8"), ("EK", "f8", 2), ("EG", "f8", 2), ("EV", "f8"),
@@ -181,10 +189,10 @@ class Lattice:
     def get_tile(self) -> dict:
         t = cl_tile()
         _check(lib.cl_get_tile(self.h, C.byref(t)), self.h)
-        return dict(tz=t.tz, ty=t.ty, cx=t.cx, ry=t.ry)
+        return dict(tz=t.tz, ty=t.ty, cx=t.cx, ry=t.ry, pd=t.pd)
 
-    def set_tile(self, tz: int, ty: int, cx: int, ry: int = 1):
-        t = cl_tile(int(tz), int(ty), int(cx), int(ry))
+    def set_tile(self, tz: int, ty: int, cx: int, ry: int = 1, pd: int = 1):
+        t = cl_tile(int(tz), int(ty), int(cx), int(ry), int(pd))
         _check(lib.cl_set_tile(self.h, C.byref(t)), self.h)
 
     def autotune(self, reps: int = 3) -> dict:

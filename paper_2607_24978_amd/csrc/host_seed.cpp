@@ -105,22 +105,31 @@ struct Radix2 {
     }
 };
 
-// Unscaled inverse 3D transform of a [N][N][N] array (z fastest).
-void inverse_3d(cplx* a, int N) {
+// Unscaled inverse 3D transform of a [N][N][N] array (z fastest) whose
+// nonzero modes all satisfy n_x^2 + n_y^2 + n_z^2 <= c2: lines and planes
+// that hold only zeros are skipped (their transform is zero).
+void inverse_3d(cplx* a, int N, double c2) {
     const Radix2 fft(N);
     const int64_t NN = static_cast<int64_t>(N) * N;
-    // z lines: contiguous.
-    parallel_for(NN, [&](int64_t line) { fft.run(a + line * N); });
+    // z lines: contiguous; only (n_x, n_y) inside the disc carry data.
+    parallel_for(NN, [&](int64_t line) {
+        const int nx = mode_of(static_cast<int>(line / N), N), ny = mode_of(static_cast<int>(line % N), N);
+        if (static_cast<double>(nx * nx + ny * ny) <= c2) fft.run(a + line * N);
+    });
     // y and x lines: gather blocks of B neighbouring z columns to use whole cache lines.
-    constexpr int B = 8;
+    constexpr int B = 16;
     const int nb = (N + B - 1) / B;
     for (int axis = 1; axis >= 0; --axis) {
         const int64_t stride = axis == 1 ? N : NN;
-        // lines indexed by (other coordinate, z block)
         parallel_for(static_cast<int64_t>(N) * nb, [&](int64_t item) {
+            const int other = static_cast<int>(item / nb);
+            // y lines at fixed x: zero unless |n_x| lies inside the cutoff
+            if (axis == 1) {
+                const int nx = mode_of(other, N);
+                if (static_cast<double>(nx) * nx > c2) return;
+            }
             thread_local std::vector<cplx> tmp;
             tmp.resize(static_cast<size_t>(B) * N);
-            const int other = static_cast<int>(item / nb);
             const int zb = static_cast<int>(item % nb) * B;
             const int nz = std::min(B, N - zb);
             const int64_t base = (axis == 1 ? static_cast<int64_t>(other) * NN : static_cast<int64_t>(other) * N) + zb;
@@ -208,7 +217,7 @@ const char* host_seed(int N, double dx, int nf, const Phys& ph, double a0, uint6
                 }
             }
         });
-        inverse_3d(Z.data(), N);
+        inverse_3d(Z.data(), N, c2);
         const double inv = 1.0 / static_cast<double>(N3);
         double* fj = f + static_cast<size_t>(j) * N3;
         double* pj = p + static_cast<size_t>(j) * N3;

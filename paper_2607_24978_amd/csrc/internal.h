@@ -49,6 +49,7 @@ struct Tile {
     int RY = 1;                  // y-rows per thread
     int NT = 0;                  // threads per workgroup
     int HI = 1;                  // halo items per thread (1 or 2)
+    int PD = 1;                  // x-planes of loads kept in flight (1 or 2)
     int nbz = 0, nby = 0, nbx = 0;
     int nblocks() const { return nbz * nby * nbx; }
 };

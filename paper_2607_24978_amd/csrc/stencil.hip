@@ -23,6 +23,7 @@
 
 #include <hip/hip_runtime.h>
 #include <cmath>
+#include <type_traits>
 
 namespace cl {
 
@@ -221,7 +222,7 @@ __device__ void reduce_and_finish(const PassArgs& A, double (&acc)[NS], int NT, 
     }
 }
 
-template <typename T, int NF, int RY, int HI>
+template <typename T, int NF, int RY, int HI, int PD>
 __global__ __launch_bounds__(256) void lattice_pass(PassArgs A) {
     constexpr int V = VecOf<T>::V;
     constexpr int NS = kSumsPerField * NF + 1;
@@ -321,20 +322,26 @@ __global__ __launch_bounds__(256) void lattice_pass(PassArgs A) {
     }
 
     const size_t plane = static_cast<size_t>(N) * rs;
-    // Raw (undrifted) loads of one plane: own values and halo items.
-    T rf[NF][RY][V], rp[NF][RY][V], hf[NF][HI][V], hp[NF][HI][V];
-    auto issue = [&](int x, bool halo) {
+    // Raw (undrifted) loads of up to PD planes in flight: own values and halo
+    // items.  Set S of the ring holds planes x0+1+S, x0+1+S+PD, ...
+    T rf[PD][NF][RY][V], rp[PD][NF][RY][V], hf[PD][NF][HI][V], hp[PD][NF][HI][V];
+    // Issue the loads of plane x0+k (k may be -1) into set S; halo items only
+    // when the plane will be staged in LDS (k < CX).
+    auto issue = [&](auto Sc, int k) {
+        constexpr int S_ = decltype(Sc)::value;
+        const int x = (x0 + k + N) % N;
+        const bool halo = k >= 0 && k < CX;
         const size_t base = static_cast<size_t>(x) * plane;
 #pragma unroll
         for (int j = 0; j < NF; ++j) {
 #pragma unroll
-            for (int k = 0; k < RY; ++k) {
+            for (int r = 0; r < RY; ++r) {
                 if (nt_load) {
-                    vload_nt(fin[j] + base + yrow[k], rf[j][k]);
-                    vload_nt(pin[j] + base + yrow[k], rp[j][k]);
+                    vload_nt(fin[j] + base + yrow[r], rf[S_][j][r]);
+                    vload_nt(pin[j] + base + yrow[r], rp[S_][j][r]);
                 } else {
-                    vload(fin[j] + base + yrow[k], rf[j][k]);
-                    vload(pin[j] + base + yrow[k], rp[j][k]);
+                    vload(fin[j] + base + yrow[r], rf[S_][j][r]);
+                    vload(pin[j] + base + yrow[r], rp[S_][j][r]);
                 }
             }
             if (halo) {
@@ -342,28 +349,29 @@ __global__ __launch_bounds__(256) void lattice_pass(PassArgs A) {
                 for (int q = 0; q < HI; ++q) {
                     if (h_goff[q] < 0) continue;
                     if (h_vec[q]) {
-                        vload(fin[j] + base + h_goff[q], hf[j][q]);
-                        vload(pin[j] + base + h_goff[q], hp[j][q]);
+                        vload(fin[j] + base + h_goff[q], hf[S_][j][q]);
+                        vload(pin[j] + base + h_goff[q], hp[S_][j][q]);
                     } else {
-                        hf[j][q][0] = fin[j][base + h_goff[q]];
-                        hp[j][q][0] = pin[j][base + h_goff[q]];
+                        hf[S_][j][q][0] = fin[j][base + h_goff[q]];
+                        hp[S_][j][q][0] = pin[j][base + h_goff[q]];
                     }
                 }
             }
         }
     };
-    // Drift the raw plane: own values into fd / po, and (if stage >= 0) the
-    // drifted own values and halo into LDS buffer `stage`.
+    // Drift the raw plane of set S: own values into fd / po, and (if
+    // stage_buf >= 0) the drifted own values and halo into LDS buffer stage_buf.
     T prev[NF][RY][V], cur[NF][RY][V], nxt[NF][RY][V], pc[NF][RY][V], pn[NF][RY][V];
-    auto consume = [&](T (&fd)[NF][RY][V], T (&po)[NF][RY][V], int stage_buf) {
+    auto consume = [&](auto Sc, T (&fd)[NF][RY][V], T (&po)[NF][RY][V], int stage_buf) {
+        constexpr int S_ = decltype(Sc)::value;
 #pragma unroll
         for (int j = 0; j < NF; ++j)
 #pragma unroll
-            for (int k = 0; k < RY; ++k)
+            for (int r = 0; r < RY; ++r)
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
-                    po[j][k][v] = rp[j][k][v];
-                    fd[j][k][v] = rf[j][k][v] + cd * rp[j][k][v];
+                    po[j][r][v] = rp[S_][j][r][v];
+                    fd[j][r][v] = rf[S_][j][r][v] + cd * rp[S_][j][r][v];
                 }
         if (stage_buf < 0) return;
         T* L0 = lds + static_cast<size_t>(stage_buf) * NF * PL;
@@ -371,17 +379,17 @@ __global__ __launch_bounds__(256) void lattice_pass(PassArgs A) {
         for (int j = 0; j < NF; ++j) {
             T* Lj = L0 + j * PL;
 #pragma unroll
-            for (int k = 0; k < RY; ++k) vstore(Lj + (tr + k * RL + 1) * S + V + tz * V, fd[j][k]);
+            for (int r = 0; r < RY; ++r) vstore(Lj + (tr + r * RL + 1) * S + V + tz * V, fd[j][r]);
 #pragma unroll
             for (int q = 0; q < HI; ++q) {
                 if (h_goff[q] < 0) continue;
                 if (h_vec[q]) {
                     T fv[V];
 #pragma unroll
-                    for (int v = 0; v < V; ++v) fv[v] = hf[j][q][v] + cd * hp[j][q][v];
+                    for (int v = 0; v < V; ++v) fv[v] = hf[S_][j][q][v] + cd * hp[S_][j][q][v];
                     vstore(Lj + h_lds[q], fv);
                 } else {
-                    Lj[h_lds[q]] = hf[j][q][0] + cd * hp[j][q][0];
+                    Lj[h_lds[q]] = hf[S_][j][q][0] + cd * hp[S_][j][q][0];
                 }
             }
         }
@@ -391,22 +399,27 @@ __global__ __launch_bounds__(256) void lattice_pass(PassArgs A) {
 #pragma unroll
     for (int k = 0; k < NS; ++k) acc[k] = 0.0;
 
+    using S0 = std::integral_constant<int, 0>;
+    using S1 = std::integral_constant<int, PD - 1>;
     // Prologue: plane x0-1 (own only), plane x0 (own + halo into buffer 0),
-    // then the loads of plane x0+1 stay in flight into the first iteration.
-    issue((x0 - 1 + N) % N, false);
-    consume(prev, pn, -1);
-    issue(x0, true);
-    consume(cur, pc, 0);
-    issue((x0 + 1) % N, CX > 1);
+    // then the loads of planes x0+1 .. x0+PD stay in flight into the loop.
+    issue(S0{}, -1);
+    consume(S0{}, prev, pn, -1);
+    issue(S0{}, 0);
+    consume(S0{}, cur, pc, 0);
+    issue(S0{}, 1);
+    if constexpr (PD == 2) {
+        if (2 <= CX) issue(S1{}, 2);
+    }
     __syncthreads();
 
-    for (int i = 0; i < CX; ++i) {
+    // One x-plane: plane x+1 arrives from set S (drift, stage), the loads of
+    // plane x+1+PD go out into the same set, then plane x is computed.
+    auto body = [&](auto Sc, int i) {
         const int x = x0 + i;
         const int buf = i & 1;
-        // plane x+1 arrives: drift it and stage it for the next iteration
-        consume(nxt, pn, i + 1 < CX ? (buf ^ 1) : -1);
-        // loads of plane x+2 overlap the compute of plane x
-        if (i + 1 < CX) issue((x + 2) % N, i + 2 < CX);
+        consume(Sc, nxt, pn, i + 1 < CX ? (buf ^ 1) : -1);
+        if (i + 1 + PD <= CX) issue(Sc, i + 1 + PD);
 
         const T* L0 = lds + static_cast<size_t>(buf) * NF * PL;
         const size_t base = static_cast<size_t>(x) * plane;
@@ -492,6 +505,12 @@ __global__ __launch_bounds__(256) void lattice_pass(PassArgs A) {
                     cur[j][k][v] = nxt[j][k][v];
                     pc[j][k][v] = pn[j][k][v];
                 }
+    };
+    for (int i = 0; i < CX; i += PD) {
+        body(S0{}, i);
+        if constexpr (PD == 2) {
+            if (i + 1 < CX) body(S1{}, i + 1);
+        }
     }
     reduce_and_finish<NS>(A, acc, NT, bid, nblocks);
 }
@@ -518,17 +537,34 @@ __global__ void init_scalars_kernel(Scal* sc, double a, double b, double eta, do
     *sc = s;
 }
 
-// Plain streaming copy (16-byte vectors, grid-stride): the achievable
-// read+write bandwidth ceiling for the pass kernels' access pattern.
+// Streaming copy: four 16-byte vectors per thread per iteration, loads
+// first, nontemporal hints on both sides -- the best one-stream-in,
+// one-stream-out pattern we found, used as the measured bandwidth ceiling.
 __global__ __launch_bounds__(256) void copy_kernel(const float4* __restrict__ in, float4* __restrict__ out,
                                                    size_t n) {
-    const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
-    for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) out[i] = in[i];
+    using NV = NatVec<float>::type;
+    const NV* src = reinterpret_cast<const NV*>(in);
+    NV* dst = reinterpret_cast<NV*>(out);
+    constexpr int U = 4;
+    const size_t chunk = static_cast<size_t>(blockDim.x) * U;
+    for (size_t base = static_cast<size_t>(blockIdx.x) * chunk; base < n; base += static_cast<size_t>(gridDim.x) * chunk) {
+        NV v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const size_t i = base + u * blockDim.x + threadIdx.x;
+            if (i < n) v[u] = __builtin_nontemporal_load(src + i);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const size_t i = base + u * blockDim.x + threadIdx.x;
+            if (i < n) __builtin_nontemporal_store(v[u], dst + i);
+        }
+    }
 }
 
 hipError_t launch_copy(const void* in, void* out, size_t bytes, hipStream_t s) {
     const size_t n = bytes / 16;
-    const int blocks = 256 * 32;
+    const int blocks = 4096;
     hipLaunchKernelGGL(copy_kernel, dim3(blocks), dim3(256), 0, s, static_cast<const float4*>(in),
                        static_cast<float4*>(out), n);
     return hipGetLastError();
@@ -558,6 +594,7 @@ bool finalize_tile(Tile& t, int N, cl_precision prec) {
     t.NT = BZ * RL;
     if (t.NT > 256 || !is_pow2(t.NT) || !is_pow2(BZ)) return false;
     if (t.RY != 1 && t.RY != 2) return false;
+    if (t.PD != 1 && t.PD != 2) return false;
     const int nhalo = 2 * BZ + 2 * t.TY;
     t.HI = (nhalo + t.NT - 1) / t.NT;
     if (t.HI > 2) return false;
@@ -597,32 +634,39 @@ void candidate_tiles(int N, cl_precision prec, int nf, Tile* out, int* count, in
                 if (NT < BZ) continue;
                 const int TY = (NT / BZ) * RY;
                 if (TY > N) continue;
-                for (int CX = 2; CX <= N; CX *= 2) {
-                    if (CX != N && (CX < 4 || CX > 256)) continue;
-                    Tile t;
-                    t.TZ = TZ;
-                    t.TY = TY;
-                    t.CX = CX;
-                    t.RY = RY;
-                    if (!finalize_tile(t, N, prec)) continue;
-                    if (pass_lds_bytes(t, prec, nf) > 60 * 1024) continue;
-                    if (n < cap) out[n++] = t;
-                }
+                for (int CX = 2; CX <= N; CX *= 2)
+                    for (int PD : {1, 2}) {
+                        if (CX != N && (CX < 4 || CX > 256)) continue;
+                        Tile t;
+                        t.TZ = TZ;
+                        t.TY = TY;
+                        t.CX = CX;
+                        t.RY = RY;
+                        t.PD = PD;
+                        if (!finalize_tile(t, N, prec)) continue;
+                        if (pass_lds_bytes(t, prec, nf) > 60 * 1024) continue;
+                        if (n < cap) out[n++] = t;
+                    }
             }
     }
     *count = n;
 }
 
-template <typename T, int NF, int RY, int HI>
+template <typename T, int NF, int RY, int HI, int PD>
 static hipError_t launch_t(const PassArgs& a, const Tile& t, hipStream_t s, size_t lds) {
-    hipLaunchKernelGGL((lattice_pass<T, NF, RY, HI>), dim3(t.nblocks()), dim3(t.NT), lds, s, a);
+    hipLaunchKernelGGL((lattice_pass<T, NF, RY, HI, PD>), dim3(t.nblocks()), dim3(t.NT), lds, s, a);
     return hipGetLastError();
+}
+
+template <typename T, int NF, int RY, int HI>
+static hipError_t launch_pd(const PassArgs& a, const Tile& t, hipStream_t s, size_t lds) {
+    return t.PD == 2 ? launch_t<T, NF, RY, HI, 2>(a, t, s, lds) : launch_t<T, NF, RY, HI, 1>(a, t, s, lds);
 }
 
 template <typename T, int NF>
 static hipError_t launch_nf(const PassArgs& a, const Tile& t, hipStream_t s, size_t lds) {
-    if (t.RY == 1) return t.HI == 1 ? launch_t<T, NF, 1, 1>(a, t, s, lds) : launch_t<T, NF, 1, 2>(a, t, s, lds);
-    return t.HI == 1 ? launch_t<T, NF, 2, 1>(a, t, s, lds) : launch_t<T, NF, 2, 2>(a, t, s, lds);
+    if (t.RY == 1) return t.HI == 1 ? launch_pd<T, NF, 1, 1>(a, t, s, lds) : launch_pd<T, NF, 1, 2>(a, t, s, lds);
+    return t.HI == 1 ? launch_pd<T, NF, 2, 1>(a, t, s, lds) : launch_pd<T, NF, 2, 2>(a, t, s, lds);
 }
 
 hipError_t launch_pass(const PassArgs& a, const Tile& t, cl_precision prec, hipStream_t s) {

@@ -261,7 +261,7 @@ def test_tiles_agree(precision):
     ref = None
     for t in tiles[:: max(1, len(tiles) // 12)] + [rep["best"]]:
         lat = make_lattice(w)
-        lat.set_tile(t["tz"], t["ty"], t["cx"], t["ry"])
+        lat.set_tile(t["tz"], t["ty"], t["cx"], t["ry"], t["pd"])
         lat.set_fields(s0.f, s0.p)
         r = lat.step("vv4", w.dt, 4)
         f, p = lat.get_fields()
@@ -283,7 +283,7 @@ def test_autotune_keeps_state():
     lat.set_fields(s0.f, s0.p)
     st0 = lat.get_state()
     rep = lat.autotune(reps=2)
-    assert lat.get_tile() == {k: rep["best"][k] for k in ("tz", "ty", "cx", "ry")}
+    assert lat.get_tile() == {k: rep["best"][k] for k in ("tz", "ty", "cx", "ry", "pd")}
     assert lat.get_state() == st0
     f, p = lat.get_fields()
     assert np.array_equal(f, s0.f) and np.array_equal(p, s0.p)
