@@ -210,7 +210,7 @@ cl_status cl_autotune(cl_lattice* h, int reps, char* report, size_t report_cap);
 cl_status cl_copy_bandwidth(size_t bytes, int reps, double* gbps);
 
 /* Ensembles: advance several independent lattices (equal precision and
- * n_fields, any N) together, each pass of all members in one persistent
+ * n_fields, any N >= 32 accepted by cl_create) together, each pass of all members in one persistent
  * launch, the passes of a call captured in one HIP graph.  Members keep their
  * own potential, background, scale factor and time step; they must use the
  * null stream or a common one.  The ensemble does not own the members. */
@@ -218,6 +218,10 @@ cl_status cl_ensemble_create(int n_members, cl_lattice* const* members, cl_ensem
 cl_status cl_ensemble_set_dt(cl_ensemble* e, int member, double dt);
 /* out: NULL or n_steps * n_members records, step-major ([s][member]). */
 cl_status cl_ensemble_step(cl_ensemble* e, cl_integrator integ, int n_steps, cl_observables* out);
+/* Tile the ensemble kernel uses for one member (ry = 1, pd = 2).  A member
+ * stepped on its own with this tile (cl_set_tile) gives bitwise the same
+ * result as inside the ensemble. */
+cl_status cl_ensemble_get_tile(const cl_ensemble* e, int member, cl_tile* out);
 cl_status cl_ensemble_destroy(cl_ensemble* e);
 
 #ifdef __cplusplus

@@ -80,6 +80,7 @@ _SIGS = {
     "cl_ensemble_set_dt": (C.c_int, [_P, C.c_int, C.c_double]),
     "cl_ensemble_step": (C.c_int, [_P, C.c_int, C.c_int, _P]),
     "cl_ensemble_destroy": (C.c_int, [_P]),
+    "cl_ensemble_get_tile": (C.c_int, [_P, C.c_int, C.POINTER(cl_tile)]),
 }
 
 if not os.path.exists(LIB_PATH):
@@ -232,6 +233,11 @@ class Ensemble:
         ptr = _P(out.ctypes.data) if record and n > 0 else None
         _check(lib.cl_ensemble_step(self.e, INTEGRATORS[integrator], int(n), ptr))
         return out
+
+    def get_tile(self, i: int) -> dict:
+        t = cl_tile()
+        _check(lib.cl_ensemble_get_tile(self.e, int(i), C.byref(t)))
+        return dict(tz=t.tz, ty=t.ty, cx=t.cx, ry=t.ry, pd=t.pd)
 
     def close(self):
         if getattr(self, "e", None):

@@ -80,7 +80,44 @@ struct PassArgs {
     Phys ph;
 };
 
+// One member of an ensemble, as the persistent ensemble kernel sees it.
+// Refreshed from the member handles before every ensemble call.
+struct EnsMember {
+    void* buf[2];        // state buffers; a pass reads buf[cur0 ^ parity]
+    int N, TZ, TY, CX;   // tile (TZ * TY / vector width == 256 threads)
+    int nbz, nby, nbx, nitems;
+    int cur0;            // buffer holding the state when the call starts
+    int pad;
+    double dt;
+    Phys ph;
+    Scal* sc;
+    double* partials;    // nsums(nf) * nitems, slot = logical tile id
+    unsigned* ticket;
+};
+
+struct EnsItem {
+    int member;
+    int tile;  // logical tile id: bz + nbz * (by + nby * bx)
+};
+
+// One pass over every member, in one persistent launch.  Kick and drift
+// steps are given in units of each member's dt.
+struct EnsArgs {
+    const EnsMember* members;
+    const EnsItem* items;
+    int nitems, nmembers;
+    int parity;  // pass index parity within the call
+    int drift, write_out, flags, rec;
+    int lds_bytes;  // dynamic shared memory: the largest member tile
+    double ckt, ckb, chn;
+    unsigned* counter;    // [0] work items handed out, [1] workgroups finished
+    cl_observables* obs;  // [rec][member]
+};
+
 // Kernel launchers (stencil.hip).  Return the HIP error of the launch.
+hipError_t launch_ensemble_pass(const EnsArgs& a, cl_precision prec, int nf, int grid, hipStream_t s);
+size_t ensemble_lds_bytes(cl_precision prec, int nf, int maxTY, int maxTZ);
+int ensemble_grid(cl_precision prec, int nf, size_t lds);
 hipError_t launch_pass(const PassArgs& a, const Tile& t, cl_precision prec, hipStream_t s);
 hipError_t launch_init_scalars(Scal* sc, double a, double b, double eta, const Phys& ph,
                                const double* shift, hipStream_t s);
@@ -101,3 +138,46 @@ const char* host_seed(int N, double dx, int nf, const Phys& ph, double a0, uint6
                       double* f, double* p);
 
 }  // namespace cl
+
+#include <string>
+
+struct GraphKey {
+    int integ = -1;
+    double dt = 0.0;
+    int n = 0;
+    int cur = 0;
+    bool operator==(const GraphKey& o) const {
+        return integ == o.integ && dt == o.dt && n == o.n && cur == o.cur;
+    }
+};
+
+struct cl_lattice {
+    int N = 0;
+    double dx = 0.0;
+    int nf = 1;
+    cl_precision prec = CL_FP64;
+    double alpha = 1.0, mp = 1.0, a0 = 1.0;
+    cl_expansion mode = CL_SELF_CONSISTENT;
+    cl_potential pot{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool own_buffers = true;
+    int device = 0;
+    void* buf[2] = {nullptr, nullptr};  // ping-pong state buffers (row-interleaved layout)
+    int pass_flags = 1;                 // nontemporal stores
+    int cur = 0;
+    cl::Scal* sc = nullptr;
+    double* partials = nullptr;
+    size_t partials_cap = 0;  // doubles
+    unsigned* ticket = nullptr;
+    cl_observables* obs = nullptr;
+    int obs_cap = 0;
+    cl::Tile tile;
+    int64_t step = 0;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};  // one per starting buffer
+    GraphKey gkey[2];
+    bool use_graph = true;
+    std::string err;
+};
+
+

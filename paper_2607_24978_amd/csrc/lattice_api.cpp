@@ -26,45 +26,6 @@ using cl::Phys;
 using cl::Scal;
 using cl::Tile;
 
-struct GraphKey {
-    int integ = -1;
-    double dt = 0.0;
-    int n = 0;
-    int cur = 0;
-    bool operator==(const GraphKey& o) const {
-        return integ == o.integ && dt == o.dt && n == o.n && cur == o.cur;
-    }
-};
-
-struct cl_lattice {
-    int N = 0;
-    double dx = 0.0;
-    int nf = 1;
-    cl_precision prec = CL_FP64;
-    double alpha = 1.0, mp = 1.0, a0 = 1.0;
-    cl_expansion mode = CL_SELF_CONSISTENT;
-    cl_potential pot{};
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    bool own_buffers = true;
-    int device = 0;
-    void* buf[2] = {nullptr, nullptr};  // ping-pong state buffers (row-interleaved layout)
-    int pass_flags = 1;                 // nontemporal stores
-    int cur = 0;
-    Scal* sc = nullptr;
-    double* partials = nullptr;
-    size_t partials_cap = 0;  // doubles
-    unsigned* ticket = nullptr;
-    cl_observables* obs = nullptr;
-    int obs_cap = 0;
-    Tile tile;
-    int64_t step = 0;
-    hipGraphExec_t gexec[2] = {nullptr, nullptr};  // one per starting buffer
-    GraphKey gkey[2];
-    bool use_graph = true;
-    std::string err;
-};
-
 namespace {
 
 thread_local std::string g_err;
@@ -185,26 +146,28 @@ void substeps(cl_integrator integ, double dt, int n, std::vector<double>& h, int
 // Issue the passes of n steps on the handle's stream.  Returns the final
 // buffer index.
 cl_status issue_steps(cl_lattice* h, cl_integrator integ, double dt, int n, int cur) {
-    std::vector<double> hs;
+    // Sub-step sizes in units of dt; every kick and drift step is formed as
+    // (coefficient) * dt, exactly as the ensemble kernel forms it per member.
+    std::vector<double> c;
     int per = 1;
-    substeps(integ, dt, n, hs, per);
-    const int M = static_cast<int>(hs.size());
+    substeps(integ, 1.0, n, c, per);
+    const int M = static_cast<int>(c.size());
     // Opening half kick (no drift): pi += h_1/2 F(f, a), a' += h_1/2 a''.
     PassArgs k = base_args(h, cur);
     k.drift = 0;
     k.write_out = 1;
-    k.kt = 0.5 * hs[0];
+    k.kt = (0.5 * c[0]) * dt;
     k.kb = 0.0;
-    k.h_next = hs[0];
+    k.h_next = c[0] * dt;
     HIPCHECK(h, cl::launch_pass(k, h->tile, h->prec, h->stream));
     cur ^= 1;
     for (int s = 0; s < M; ++s) {
         PassArgs d = base_args(h, cur);
         d.drift = 1;
         d.write_out = 1;
-        d.kb = 0.5 * hs[s];
-        d.kt = s + 1 < M ? 0.5 * (hs[s] + hs[s + 1]) : 0.5 * hs[s];
-        d.h_next = s + 1 < M ? hs[s + 1] : 0.0;
+        d.kb = (0.5 * c[s]) * dt;
+        d.kt = (s + 1 < M ? 0.5 * (c[s] + c[s + 1]) : 0.5 * c[s]) * dt;
+        d.h_next = s + 1 < M ? c[s + 1] * dt : 0.0;
         d.rec = ((s + 1) % per == 0) ? (s + 1) / per - 1 : -1;
         HIPCHECK(h, cl::launch_pass(d, h->tile, h->prec, h->stream));
         cur ^= 1;
@@ -775,6 +738,281 @@ cl_status cl_copy_bandwidth(size_t bytes, int reps, double* gbps) {
     hipFree(b);
     if (!(ms > 0.0f)) return fail(nullptr, CL_EDEVICE, "copy probe timing failed");
     *gbps = 2.0 * static_cast<double>(bytes) * reps / (ms * 1e-3) / 1e9;
+    return CL_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- ensembles
+//
+// Independent lattices (uneven sizes allowed) advanced together: every pass
+// of every member runs in one persistent launch that hands out tiles of all
+// members from a work counter; the passes of a call are captured in one HIP
+// graph.  Members keep their own potential, background, scale factor, time
+// step and state buffers, so a member's handle stays usable on its own.
+
+struct cl_ensemble {
+    std::vector<cl_lattice*> m;
+    cl_precision prec = CL_FP32;
+    int nf = 1;
+    std::vector<cl::EnsMember> table;
+    cl::EnsMember* staging = nullptr;  // pinned host copy of the member table
+    cl::EnsMember* d_table = nullptr;
+    cl::EnsItem* d_items = nullptr;
+    int nitems = 0;
+    double* d_partials = nullptr;
+    unsigned* d_tickets = nullptr;
+    unsigned* d_counter = nullptr;
+    cl_observables* d_obs = nullptr;
+    size_t obs_cap = 0;
+    std::vector<double> dt;
+    hipStream_t stream = nullptr;
+    int grid = 0;
+    size_t lds = 0;
+    hipGraphExec_t gexec = nullptr;
+    int g_integ = -1, g_n = -1;
+};
+
+namespace {
+
+cl_status efail(cl_status st, const std::string& msg) {
+    g_err = msg;
+    return st;
+}
+
+#define EHIP(call)                                                                              \
+    do {                                                                                        \
+        hipError_t e_ = (call);                                                                 \
+        if (e_ != hipSuccess) return efail(CL_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// Tile of one member: 256 threads, full rows when N <= 64 vectors, about
+// 16k sites per work item.
+bool ensemble_tile(int N, cl_precision prec, cl::EnsMember& t) {
+    const int V = prec == CL_FP32 ? 4 : 2;
+    t.TZ = N < 64 * V ? N : 64 * V;
+    if (t.TZ % V || N % t.TZ) return false;
+    const int BZ = t.TZ / V;
+    if (256 % BZ) return false;
+    t.TY = 256 / BZ;
+    if (t.TY > N || N % t.TY) return false;
+    int cx = 16384 / (t.TZ * t.TY);
+    if (cx < 2) cx = 2;
+    while (cx > N || N % cx) cx /= 2;
+    if (cx < 1) return false;
+    t.CX = cx;
+    t.nbz = N / t.TZ;
+    t.nby = N / t.TY;
+    t.nbx = N / t.CX;
+    t.nitems = t.nbz * t.nby * t.nbx;
+    // halo items must fit one per thread
+    return 2 * BZ + 2 * t.TY <= 256;
+}
+
+void ens_free(cl_ensemble* e) {
+    if (e->stream) hipStreamSynchronize(e->stream);
+    if (e->gexec) hipGraphExecDestroy(e->gexec);
+    if (e->staging) hipHostFree(e->staging);
+    for (void* p : {(void*)e->d_table, (void*)e->d_items, (void*)e->d_partials, (void*)e->d_tickets,
+                    (void*)e->d_counter, (void*)e->d_obs})
+        if (p) hipFree(p);
+    if (e->stream) hipStreamDestroy(e->stream);
+    delete e;
+}
+
+}  // namespace
+
+extern "C" {
+
+cl_status cl_ensemble_create(int n, cl_lattice* const* members, cl_ensemble** out) {
+    if (!out) return efail(CL_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || !members) return efail(CL_EINVAL, "need at least one member");
+    cl_ensemble* e = new (std::nothrow) cl_ensemble;
+    if (!e) return efail(CL_ENOMEM, "ensemble handle");
+    auto bail = [&](cl_status st, const std::string& msg) {
+        ens_free(e);
+        return efail(st, msg);
+    };
+    e->prec = members[0] ? members[0]->prec : CL_FP32;
+    e->nf = members[0] ? members[0]->nf : 1;
+    std::vector<cl::EnsItem> items;
+    size_t poff = 0;
+    int maxTY = 0, maxTZ = 0;
+    for (int i = 0; i < n; ++i) {
+        cl_lattice* h = members[i];
+        if (!h) return bail(CL_EINVAL, "member " + std::to_string(i) + " is NULL");
+        for (int k = 0; k < i; ++k)
+            if (members[k] == h) return bail(CL_EINVAL, "a lattice appears twice in the ensemble");
+        if (h->prec != e->prec || h->nf != e->nf)
+            return bail(CL_EINVAL, "all members need the same precision and number of fields");
+        cl::EnsMember t{};
+        if (!ensemble_tile(h->N, h->prec, t))
+            return bail(CL_EUNSUPPORTED, "member " + std::to_string(i) + ": N = " + std::to_string(h->N) +
+                                             " is too small for an ensemble tile (N >= 32 needed)");
+        for (int k = 0; k < t.nitems; ++k) items.push_back({i, k});
+        t.partials = reinterpret_cast<double*>(poff);  // offset, fixed up below
+        poff += static_cast<size_t>(cl::nsums(e->nf)) * t.nitems;
+        maxTY = std::max(maxTY, t.TY);
+        maxTZ = std::max(maxTZ, t.TZ);
+        e->table.push_back(t);
+        e->m.push_back(h);
+    }
+    e->dt.assign(n, 0.0);
+    e->nitems = static_cast<int>(items.size());
+    if (hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking) != hipSuccess)
+        return bail(CL_EDEVICE, "hipStreamCreate failed");
+    if (hipMalloc(&e->d_partials, poff * sizeof(double)) != hipSuccess ||
+        hipMalloc(&e->d_tickets, n * sizeof(unsigned)) != hipSuccess ||
+        hipMalloc(&e->d_counter, 64) != hipSuccess ||
+        hipMalloc(&e->d_items, items.size() * sizeof(cl::EnsItem)) != hipSuccess ||
+        hipMalloc(&e->d_table, n * sizeof(cl::EnsMember)) != hipSuccess ||
+        hipHostMalloc(&e->staging, n * sizeof(cl::EnsMember)) != hipSuccess)
+        return bail(CL_ENOMEM, "ensemble device tables");
+    for (int i = 0; i < n; ++i) {
+        e->table[i].partials = e->d_partials + reinterpret_cast<size_t>(e->table[i].partials);
+        e->table[i].ticket = e->d_tickets + i;
+    }
+    if (hipMemsetAsync(e->d_tickets, 0, n * sizeof(unsigned), e->stream) != hipSuccess ||
+        hipMemsetAsync(e->d_counter, 0, 64, e->stream) != hipSuccess ||
+        hipMemcpyAsync(e->d_items, items.data(), items.size() * sizeof(cl::EnsItem), hipMemcpyHostToDevice,
+                       e->stream) != hipSuccess ||
+        hipStreamSynchronize(e->stream) != hipSuccess)
+        return bail(CL_EDEVICE, "ensemble table upload");
+    e->lds = cl::ensemble_lds_bytes(e->prec, e->nf, maxTY, maxTZ);
+    e->grid = std::min(cl::ensemble_grid(e->prec, e->nf, e->lds), e->nitems);
+    *out = e;
+    return CL_OK;
+}
+
+cl_status cl_ensemble_set_dt(cl_ensemble* e, int i, double dt) {
+    if (!e) return efail(CL_EINVAL, "ensemble is NULL");
+    if (i < 0 || i >= static_cast<int>(e->m.size())) return efail(CL_EINVAL, "member index out of range");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return efail(CL_EINVAL, "dt must be positive and finite");
+    if (dt * std::sqrt(12.0) / e->m[i]->dx >= 2.0)
+        return efail(CL_EUNSTABLE, "dt exceeds the Courant bound dt*sqrt(12)/dx < 2 of member " + std::to_string(i));
+    e->dt[i] = dt;
+    return CL_OK;
+}
+
+cl_status cl_ensemble_step(cl_ensemble* e, cl_integrator integ, int n, cl_observables* out) {
+    if (!e) return efail(CL_EINVAL, "ensemble is NULL");
+    if (integ != CL_LEAPFROG && integ != CL_VV4) return efail(CL_EINVAL, "unknown integrator");
+    if (n < 0) return efail(CL_EINVAL, "n must be >= 0");
+    if (n == 0) return CL_OK;
+    const int nm = static_cast<int>(e->m.size());
+    for (int i = 0; i < nm; ++i)
+        if (!(e->dt[i] > 0.0)) return efail(CL_ESTATE, "dt of member " + std::to_string(i) + " not set");
+    // members' own queued work finishes first
+    for (cl_lattice* h : e->m) EHIP(hipStreamSynchronize(h->stream));
+    for (int i = 0; i < nm; ++i) {
+        cl::EnsMember& t = e->table[i];
+        cl_lattice* h = e->m[i];
+        t.buf[0] = h->buf[0];
+        t.buf[1] = h->buf[1];
+        t.N = h->N;
+        t.cur0 = h->cur;
+        t.dt = e->dt[i];
+        t.ph = make_phys(h);
+        t.sc = h->sc;
+        e->staging[i] = t;
+    }
+    EHIP(hipMemcpyAsync(e->d_table, e->staging, nm * sizeof(cl::EnsMember), hipMemcpyHostToDevice, e->stream));
+    const size_t need = static_cast<size_t>(n) * nm;
+    if (need > e->obs_cap) {
+        if (e->d_obs) hipFree(e->d_obs);
+        e->d_obs = nullptr;
+        e->obs_cap = 0;
+        EHIP(hipMalloc(&e->d_obs, need * sizeof(cl_observables)));
+        e->obs_cap = need;
+        if (e->gexec) hipGraphExecDestroy(e->gexec);
+        e->gexec = nullptr;
+    }
+    std::vector<double> c;
+    int per = 1;
+    substeps(integ, 1.0, n, c, per);
+    const int M = static_cast<int>(c.size());
+    const int passes = 1 + M;
+    if (!(e->gexec && e->g_integ == static_cast<int>(integ) && e->g_n == n)) {
+        if (e->gexec) hipGraphExecDestroy(e->gexec);
+        e->gexec = nullptr;
+        cl::EnsArgs a{};
+        a.members = e->d_table;
+        a.items = e->d_items;
+        a.nitems = e->nitems;
+        a.nmembers = nm;
+        a.write_out = 1;
+        a.flags = 1;
+        a.counter = e->d_counter;
+        a.obs = e->d_obs;
+        a.lds_bytes = static_cast<int>(e->lds);
+        hipGraph_t g = nullptr;
+        EHIP(hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal));
+        hipError_t err = hipSuccess;
+        // opening half kick
+        a.parity = 0;
+        a.drift = 0;
+        a.rec = -1;
+        a.ckt = 0.5 * c[0];
+        a.ckb = 0.0;
+        a.chn = c[0];
+        if (err == hipSuccess) err = cl::launch_ensemble_pass(a, e->prec, e->nf, e->grid, e->stream);
+        for (int s = 0; s < M && err == hipSuccess; ++s) {
+            a.parity = (s + 1) & 1;
+            a.drift = 1;
+            a.ckb = 0.5 * c[s];
+            a.ckt = s + 1 < M ? 0.5 * (c[s] + c[s + 1]) : 0.5 * c[s];
+            a.chn = s + 1 < M ? c[s + 1] : 0.0;
+            a.rec = ((s + 1) % per == 0) ? (s + 1) / per - 1 : -1;
+            err = cl::launch_ensemble_pass(a, e->prec, e->nf, e->grid, e->stream);
+        }
+        hipError_t e2 = hipStreamEndCapture(e->stream, &g);
+        if (err != hipSuccess || e2 != hipSuccess) {
+            if (g) hipGraphDestroy(g);
+            return efail(CL_EDEVICE, std::string("ensemble graph capture: ") +
+                                         hipGetErrorString(err != hipSuccess ? err : e2));
+        }
+        err = hipGraphInstantiate(&e->gexec, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (err != hipSuccess) {
+            e->gexec = nullptr;
+            return efail(CL_EDEVICE, std::string("ensemble graph instantiate: ") + hipGetErrorString(err));
+        }
+        e->g_integ = static_cast<int>(integ);
+        e->g_n = n;
+    }
+    EHIP(hipGraphLaunch(e->gexec, e->stream));
+    std::vector<cl_observables> tmp;
+    cl_observables* dst = out;
+    if (!dst) {
+        tmp.resize(need);
+        dst = tmp.data();
+    }
+    EHIP(hipMemcpyAsync(dst, e->d_obs, need * sizeof(cl_observables), hipMemcpyDeviceToHost, e->stream));
+    EHIP(hipStreamSynchronize(e->stream));
+    for (cl_lattice* h : e->m) {
+        if (passes % 2) h->cur ^= 1;
+        h->step += n;
+    }
+    for (size_t k = 0; k < need; ++k)
+        if (dst[k].nonfinite) return efail(CL_EUNSTABLE, "non-finite lattice sums in an ensemble member");
+    return CL_OK;
+}
+
+cl_status cl_ensemble_get_tile(const cl_ensemble* e, int i, cl_tile* out) {
+    if (!e || !out) return efail(CL_EINVAL, "ensemble or out is NULL");
+    if (i < 0 || i >= static_cast<int>(e->m.size())) return efail(CL_EINVAL, "member index out of range");
+    const cl::EnsMember& t = e->table[i];
+    out->tz = t.TZ;
+    out->ty = t.TY;
+    out->cx = t.CX;
+    out->ry = 1;
+    out->pd = 2;
+    return CL_OK;
+}
+
+cl_status cl_ensemble_destroy(cl_ensemble* e) {
+    if (e) ens_free(e);
     return CL_OK;
 }
 

@@ -85,9 +85,8 @@ __device__ __forceinline__ void site_dV(const T (&f)[NF], const T (&m2)[2], cons
 
 // Last workgroup of a pass: observables and the scale-factor kick/drift.
 // `tot` holds the lattice sums.  Runs on one thread.
-__device__ void finish_pass(const PassArgs& A, const double* tot) {
-    const Phys& P = A.ph;
-    Scal* sc = A.sc;
+__device__ void finish_pass(const Phys& P, Scal* sc, double kt, double kb, double h_next, cl_observables* rec_out,
+                            const double* tot) {
     const int nf = P.nf;
     const double a = sc->a_next;  // scale factor of the state just produced
     const double a2 = a * a;
@@ -116,13 +115,13 @@ __device__ void finish_pass(const PassArgs& A, const double* tot) {
     if (P.expand) {
         acc = pow(a, 2.0 * P.alpha + 1.0) * ((2.0 * P.alpha - 1.0) * rho - 3.0 * pr) / (6.0 * P.mp * P.mp);
     }
-    const double bs = b_half + A.kb * acc;
+    const double bs = b_half + kb * acc;
     if (P.expand) {
         const double rhs = pow(a, 2.0 * P.alpha) * rho / (3.0 * P.mp * P.mp);
         const double H = bs / a;
         r = fabs(H * H - rhs) / rhs;
     }
-    if (A.rec >= 0) {
+    if (rec_out) {
         cl_observables o;
         o.eta = sc->eta;
         o.a = a;
@@ -137,9 +136,9 @@ __device__ void finish_pass(const PassArgs& A, const double* tot) {
         o.hubble_residual = r;
         o.nonfinite = bad;
         o.reserved = 0;
-        A.obs[A.rec] = o;
+        *rec_out = o;
     }
-    const double b_new = b_half + A.kt * acc;
+    const double b_new = b_half + kt * acc;
     sc->a = a;
     sc->b = b_new;
     sc->nonfinite |= bad;
@@ -147,14 +146,14 @@ __device__ void finish_pass(const PassArgs& A, const double* tot) {
         sc->mean_f[j] = mean[j];
         sc->mean_p[j] = meanp[j];
     }
-    if (A.h_next != 0.0) {
-        const double an = P.expand ? a + A.h_next * b_new : a;
+    if (h_next != 0.0) {
+        const double an = P.expand ? a + h_next * b_new : a;
         const double abar = 0.5 * (a + an);
-        sc->cd = A.h_next * pow(abar, P.alpha - 3.0);
+        sc->cd = h_next * pow(abar, P.alpha - 3.0);
         sc->kL = pow(an, 1.0 + P.alpha) / (P.dx * P.dx);
         sc->kV = pow(an, 3.0 + P.alpha);
         sc->a_next = an;
-        sc->eta += A.h_next;
+        sc->eta += h_next;
         for (int j = 0; j < 2; ++j) sc->shift[j] = mean[j] + sc->cd * meanp[j];
     } else {
         sc->cd = 0.0;
@@ -163,12 +162,17 @@ __device__ void finish_pass(const PassArgs& A, const double* tot) {
     }
 }
 
-// Block-wide reduction of NS per-thread FP64 sums, partial store, ticket,
-// and -- in the last workgroup to arrive -- the deterministic final sum and
-// finish_pass.
+// Block-wide reduction of NS per-thread FP64 sums into partial slot `slot`
+// of `nslots`, then a ticket; the last workgroup to arrive sums all slots in
+// a fixed order (thread t takes slots t, t+NT, ... with Neumaier
+// compensation, then a pairwise tree over threads), leaves the totals in
+// `tot` (shared memory) and returns true.  Deterministic for a fixed
+// nslots and NT.  Resets the ticket for the next pass.
 template <int NS>
-__device__ void reduce_and_finish(const PassArgs& A, double (&acc)[NS], int NT, int bid, int nblocks) {
+__device__ bool reduce_partials(double (&acc)[NS], int NT, double* partials, int slot, int nslots, unsigned* ticket,
+                                double* tot) {
     __shared__ double wsum[4][kMaxSums];
+    __shared__ double tree[256];
     __shared__ int am_last;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -186,22 +190,18 @@ __device__ void reduce_and_finish(const PassArgs& A, double (&acc)[NS], int NT, 
         for (int k = 0; k < NS; ++k) {
             double s = wsum[0][k];
             for (int w = 1; w < nw; ++w) s += wsum[w][k];
-            A.partials[(size_t)k * nblocks + bid] = s;
+            partials[(size_t)k * nslots + slot] = s;
         }
-        const unsigned t = __hip_atomic_fetch_add(A.ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        am_last = (t == (unsigned)(nblocks - 1));
+        const unsigned t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        am_last = (t == (unsigned)(nslots - 1));
     }
     __syncthreads();
-    if (!am_last) return;
+    if (!am_last) return false;
     __atomic_thread_fence(__ATOMIC_ACQUIRE);
-    // Fixed-order sum: thread t adds partials t, t+NT, ... with Neumaier
-    // compensation, then a pairwise tree over threads in LDS.
-    __shared__ double tree[256];
-    __shared__ double tot[kMaxSums];
     for (int k = 0; k < NS; ++k) {
         double s = 0.0, c = 0.0;
-        const double* src = A.partials + (size_t)k * nblocks;
-        for (int i = tid; i < nblocks; i += NT) {
+        const double* src = partials + (size_t)k * nslots;
+        for (int i = tid; i < nslots; i += NT) {
             const double x = src[i];
             const double t = s + x;
             c += (fabs(s) >= fabs(x)) ? (s - t) + x : (x - t) + s;
@@ -216,39 +216,36 @@ __device__ void reduce_and_finish(const PassArgs& A, double (&acc)[NS], int NT, 
         if (tid == 0) tot[k] = tree[0];
         __syncthreads();
     }
-    if (tid == 0) {
-        finish_pass(A, tot);
-        *A.ticket = 0u;
-    }
+    if (tid == 0) *ticket = 0u;
+    return true;
 }
 
+// Everything one workgroup does for one tile: march over CX x-planes of the
+// TZ x TY tile at (z0, y0, x0), drifting, kicking and writing the new state
+// and accumulating the per-thread lattice sums into `acc`.
+struct TileJob {
+    const void* in;
+    void* out;
+    int N, TZ, TY, CX;
+    int z0, y0, x0;
+    int drift, write_out, flags;
+    double kt, kb;
+    const Scal* sc;
+    const Phys* ph;
+};
+
 template <typename T, int NF, int RY, int HI, int PD>
-__global__ __launch_bounds__(256) void lattice_pass(PassArgs A) {
+__device__ void march_tile(const TileJob& J, unsigned char* smem_raw, double (&acc)[kSumsPerField * NF + 1]) {
     constexpr int V = VecOf<T>::V;
     constexpr int NS = kSumsPerField * NF + 1;
-    const int N = A.N, TZ = A.TZ, TY = A.TY, CX = A.CX;
+    const int N = J.N, TZ = J.TZ, TY = J.TY, CX = J.CX;
+    const int z0 = J.z0, y0 = J.y0, x0 = J.x0;
     const int BZ = TZ / V;
     const int RL = TY / RY;
     const int NT = BZ * RL;
     const int tid = threadIdx.x;
     const int tz = tid % BZ;
     const int tr = tid / BZ;
-    const int nblocks = A.nbz * A.nby * A.nbx;
-
-    // XCD-aware order: consecutive workgroup ids land on different XCDs
-    // (round robin over 8), so give XCD k a contiguous range of tiles; its
-    // co-resident workgroups then share y/z halos in their L2.
-    int bid = blockIdx.x;
-    {
-        const int per = nblocks / 8, rem = nblocks % 8;
-        const int xcd = bid % 8, slot = bid / 8;
-        if (per > 0) bid = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + slot;
-    }
-    const int bz = bid % A.nbz;
-    const int by = (bid / A.nbz) % A.nby;
-    const int bx = bid / (A.nbz * A.nby);
-    const int z0 = bz * TZ, y0 = by * TY, x0 = bx * CX;
-
     // Row-interleaved state: array a of row (x, y) starts at ((x*N + y)*2NF + a)*N.
     const int rs = 2 * NF * N;  // row stride (elements)
     const T* fin[NF];
@@ -257,32 +254,31 @@ __global__ __launch_bounds__(256) void lattice_pass(PassArgs A) {
     T* pout[NF];
 #pragma unroll
     for (int j = 0; j < NF; ++j) {
-        fin[j] = static_cast<const T*>(A.in) + j * N;
-        pin[j] = static_cast<const T*>(A.in) + (NF + j) * N;
-        fout[j] = static_cast<T*>(A.out) + j * N;
-        pout[j] = static_cast<T*>(A.out) + (NF + j) * N;
+        fin[j] = static_cast<const T*>(J.in) + j * N;
+        pin[j] = static_cast<const T*>(J.in) + (NF + j) * N;
+        fout[j] = static_cast<T*>(J.out) + j * N;
+        pout[j] = static_cast<T*>(J.out) + (NF + j) * N;
     }
-    const bool nt_store = A.flags & 1;
-    const bool nt_load = A.flags & 2;
+    const bool nt_store = J.flags & 1;
+    const bool nt_load = J.flags & 2;
 
-    const Scal* sc = A.sc;
-    const T cd = A.drift ? static_cast<T>(sc->cd) : T(0);
+    const Scal* sc = J.sc;
+    const T cd = J.drift ? static_cast<T>(sc->cd) : T(0);
     const T kL = static_cast<T>(sc->kL);
     const T kV = static_cast<T>(sc->kV);
-    const T kt = static_cast<T>(A.kt);
-    const T kb = static_cast<T>(A.kb);
+    const T kt = static_cast<T>(J.kt);
+    const T kb = static_cast<T>(J.kb);
     // Variance shift in the field precision: f - c is exact for f near c.
     T shift[NF];
 #pragma unroll
     for (int j = 0; j < NF; ++j) shift[j] = static_cast<T>(sc->shift[j]);
-    const T m2[2] = {static_cast<T>(A.ph.m2[0]), static_cast<T>(A.ph.m2[1])};
-    const T lam[2] = {static_cast<T>(A.ph.lam[0]), static_cast<T>(A.ph.lam[1])};
-    const T g2 = static_cast<T>(A.ph.g2);
+    const T m2[2] = {static_cast<T>(J.ph->m2[0]), static_cast<T>(J.ph->m2[1])};
+    const T lam[2] = {static_cast<T>(J.ph->lam[0]), static_cast<T>(J.ph->lam[1])};
+    const T g2 = static_cast<T>(J.ph->g2);
     const T hm2[2] = {T(0.5) * m2[0], T(0.5) * m2[1]};
     const T qlam[2] = {T(0.25) * lam[0], T(0.25) * lam[1]};
     const T hg2 = T(0.5) * g2;
 
-    extern __shared__ __align__(16) unsigned char smem_raw[];
     T* lds = reinterpret_cast<T*>(smem_raw);
     const int S = TZ + 2 * V;        // LDS row stride (interior starts at column V)
     const int PL = (TY + 2) * S;     // one plane of one field
@@ -395,9 +391,6 @@ __global__ __launch_bounds__(256) void lattice_pass(PassArgs A) {
         }
     };
 
-    double acc[NS];
-#pragma unroll
-    for (int k = 0; k < NS; ++k) acc[k] = 0.0;
 
     using S0 = std::integral_constant<int, 0>;
     using S1 = std::integral_constant<int, PD - 1>;
@@ -479,7 +472,7 @@ __global__ __launch_bounds__(256) void lattice_pass(PassArgs A) {
                     q5[4] += p1;
                 }
             }
-            if (A.write_out) {
+            if (J.write_out) {
 #pragma unroll
                 for (int j = 0; j < NF; ++j) {
                     if (nt_store) {
@@ -512,7 +505,47 @@ __global__ __launch_bounds__(256) void lattice_pass(PassArgs A) {
             if (i + 1 < CX) body(S1{}, i + 1);
         }
     }
-    reduce_and_finish<NS>(A, acc, NT, bid, nblocks);
+}
+
+template <typename T, int NF, int RY, int HI, int PD>
+__global__ __launch_bounds__(256) void lattice_pass(PassArgs A) {
+    constexpr int NS = kSumsPerField * NF + 1;
+    const int nblocks = A.nbz * A.nby * A.nbx;
+    // XCD-aware order: consecutive workgroup ids land on different XCDs
+    // (round robin over 8), so give XCD k a contiguous range of tiles; its
+    // co-resident workgroups then share y/z halos in their L2.
+    int bid = blockIdx.x;
+    {
+        const int per = nblocks / 8, rem = nblocks % 8;
+        const int xcd = bid % 8, slot = bid / 8;
+        if (per > 0) bid = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + slot;
+    }
+    TileJob J;
+    J.in = A.in;
+    J.out = A.out;
+    J.N = A.N;
+    J.TZ = A.TZ;
+    J.TY = A.TY;
+    J.CX = A.CX;
+    J.z0 = (bid % A.nbz) * A.TZ;
+    J.y0 = ((bid / A.nbz) % A.nby) * A.TY;
+    J.x0 = (bid / (A.nbz * A.nby)) * A.CX;
+    J.drift = A.drift;
+    J.write_out = A.write_out;
+    J.flags = A.flags;
+    J.kt = A.kt;
+    J.kb = A.kb;
+    J.sc = A.sc;
+    J.ph = &A.ph;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double acc[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) acc[k] = 0.0;
+    march_tile<T, NF, RY, HI, PD>(J, smem_raw, acc);
+    const int NT = (A.TZ / VecOf<T>::V) * (A.TY / RY);
+    __shared__ double tot[kMaxSums];
+    if (reduce_partials<NS>(acc, NT, A.partials, bid, nblocks, A.ticket, tot) && threadIdx.x == 0)
+        finish_pass(A.ph, A.sc, A.kt, A.kb, A.h_next, A.rec >= 0 ? A.obs + A.rec : nullptr, tot);
 }
 
 __global__ void init_scalars_kernel(Scal* sc, double a, double b, double eta, double alpha, double dx,
@@ -620,6 +653,96 @@ Tile default_tile(int N, cl_precision prec, int nf) {
     (void)nf;
     finalize_tile(t, N, prec);
     return t;
+}
+
+// Persistent ensemble pass: workgroups take tiles of all members from one
+// work counter until none is left.  Each member has its own partial slots
+// and ticket; the workgroup that finishes a member's last tile sums that
+// member's slots in fixed order and advances its scale factor.  The last
+// workgroup to leave resets the counters for the next pass.
+template <typename T, int NF>
+__global__ __launch_bounds__(256) void ensemble_pass(EnsArgs E) {
+    constexpr int NS = kSumsPerField * NF + 1;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double tot[kMaxSums];
+    __shared__ int item_s;
+    for (;;) {
+        __syncthreads();  // the previous tile no longer reads shared memory
+        if (threadIdx.x == 0)
+            item_s = static_cast<int>(__hip_atomic_fetch_add(&E.counter[0], 1u, __ATOMIC_RELAXED,
+                                                              __HIP_MEMORY_SCOPE_AGENT));
+        __syncthreads();
+        const int it = item_s;
+        if (it >= E.nitems) break;
+        const EnsItem I = E.items[it];
+        const EnsMember& M = E.members[I.member];
+        const double kt = E.ckt * M.dt, kb = E.ckb * M.dt, hn = E.chn * M.dt;
+        TileJob J;
+        J.in = M.buf[M.cur0 ^ E.parity];
+        J.out = M.buf[M.cur0 ^ E.parity ^ 1];
+        J.N = M.N;
+        J.TZ = M.TZ;
+        J.TY = M.TY;
+        J.CX = M.CX;
+        J.z0 = (I.tile % M.nbz) * M.TZ;
+        J.y0 = ((I.tile / M.nbz) % M.nby) * M.TY;
+        J.x0 = (I.tile / (M.nbz * M.nby)) * M.CX;
+        J.drift = E.drift;
+        J.write_out = E.write_out;
+        J.flags = E.flags;
+        J.kt = kt;
+        J.kb = kb;
+        J.sc = M.sc;
+        J.ph = &M.ph;
+        double acc[NS];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) acc[k] = 0.0;
+        march_tile<T, NF, 1, 1, 2>(J, smem_raw, acc);
+        if (reduce_partials<NS>(acc, 256, M.partials, I.tile, M.nitems, M.ticket, tot) && threadIdx.x == 0)
+            finish_pass(M.ph, M.sc, kt, kb, hn, E.rec >= 0 ? E.obs + (size_t)E.rec * E.nmembers + I.member : nullptr,
+                        tot);
+    }
+    if (threadIdx.x == 0) {
+        const unsigned done = __hip_atomic_fetch_add(&E.counter[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (done == gridDim.x - 1) {
+            __hip_atomic_store(&E.counter[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&E.counter[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+size_t ensemble_lds_bytes(cl_precision prec, int nf, int maxTY, int maxTZ) {
+    const int V = prec == CL_FP32 ? 4 : 2;
+    const size_t es = prec == CL_FP32 ? 4 : 8;
+    return 2ull * nf * (maxTY + 2) * (maxTZ + 2 * V) * es;
+}
+
+template <typename T, int NF>
+static int grid_for(size_t lds) {
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ensemble_pass<T, NF>, 256, lds) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    return per_cu * cus;
+}
+
+int ensemble_grid(cl_precision prec, int nf, size_t lds) {
+    if (prec == CL_FP32) return nf == 1 ? grid_for<float, 1>(lds) : grid_for<float, 2>(lds);
+    return nf == 1 ? grid_for<double, 1>(lds) : grid_for<double, 2>(lds);
+}
+
+hipError_t launch_ensemble_pass(const EnsArgs& a, cl_precision prec, int nf, int grid, hipStream_t s) {
+    const size_t lds = static_cast<size_t>(a.lds_bytes);
+    if (prec == CL_FP32) {
+        if (nf == 1) hipLaunchKernelGGL((ensemble_pass<float, 1>), dim3(grid), dim3(256), lds, s, a);
+        else hipLaunchKernelGGL((ensemble_pass<float, 2>), dim3(grid), dim3(256), lds, s, a);
+    } else {
+        if (nf == 1) hipLaunchKernelGGL((ensemble_pass<double, 1>), dim3(grid), dim3(256), lds, s, a);
+        else hipLaunchKernelGGL((ensemble_pass<double, 2>), dim3(grid), dim3(256), lds, s, a);
+    }
+    return hipGetLastError();
 }
 
 void candidate_tiles(int N, cl_precision prec, int nf, Tile* out, int* count, int cap) {
