@@ -25,7 +25,15 @@
 #include <cmath>
 #include <type_traits>
 
+// Every fused multiply-add below is written out; no other contraction, so
+// all kernel instantiations (tiles, prefetch depths, the ensemble kernel)
+// round every site update identically.
+#pragma clang fp contract(off)
+
 namespace cl {
+
+__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 template <typename T> struct VecOf;
 template <> struct VecOf<float> { using type = float4; static constexpr int V = 4; };
@@ -76,10 +84,10 @@ template <typename T, int NF>
 __device__ __forceinline__ void site_dV(const T (&f)[NF], const T (&m2)[2], const T (&lam)[2], T g2,
                                         T (&dV)[NF]) {
 #pragma unroll
-    for (int j = 0; j < NF; ++j) dV[j] = f[j] * (m2[j] + lam[j] * f[j] * f[j]);
+    for (int j = 0; j < NF; ++j) dV[j] = f[j] * fmad(lam[j], f[j] * f[j], m2[j]);
     if constexpr (NF == 2) {
-        dV[0] += g2 * f[0] * f[1] * f[1];
-        dV[1] += g2 * f[0] * f[0] * f[1];
+        dV[0] = fmad(g2 * f[0], f[1] * f[1], dV[0]);
+        dV[1] = fmad(g2 * f[1], f[0] * f[0], dV[1]);
     }
 }
 
@@ -367,7 +375,7 @@ __device__ void march_tile(const TileJob& J, unsigned char* smem_raw, double (&a
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
                     po[j][r][v] = rp[S_][j][r][v];
-                    fd[j][r][v] = rf[S_][j][r][v] + cd * rp[S_][j][r][v];
+                    fd[j][r][v] = fmad(cd, rp[S_][j][r][v], rf[S_][j][r][v]);
                 }
         if (stage_buf < 0) return;
         T* L0 = lds + static_cast<size_t>(stage_buf) * NF * PL;
@@ -382,10 +390,10 @@ __device__ void march_tile(const TileJob& J, unsigned char* smem_raw, double (&a
                 if (h_vec[q]) {
                     T fv[V];
 #pragma unroll
-                    for (int v = 0; v < V; ++v) fv[v] = hf[S_][j][q][v] + cd * hp[S_][j][q][v];
+                    for (int v = 0; v < V; ++v) fv[v] = fmad(cd, hp[S_][j][q][v], hf[S_][j][q][v]);
                     vstore(Lj + h_lds[q], fv);
                 } else {
-                    Lj[h_lds[q]] = hf[S_][j][q][0] + cd * hp[S_][j][q][0];
+                    Lj[h_lds[q]] = fmad(cd, hp[S_][j][q][0], hf[S_][j][q][0]);
                 }
             }
         }
@@ -445,9 +453,9 @@ __device__ void march_tile(const TileJob& J, unsigned char* smem_raw, double (&a
 #pragma unroll
                     for (int j = 0; j < NF; ++j) {
                         const T f2 = fs[j] * fs[j];
-                        Vs += f2 * (hm2[j] + qlam[j] * f2);
+                        Vs = fmad(f2, fmad(qlam[j], f2, hm2[j]), Vs);
                     }
-                    if constexpr (NF == 2) Vs += hg2 * (fs[0] * fs[0]) * (fs[1] * fs[1]);
+                    if constexpr (NF == 2) Vs = fmad(hg2 * (fs[0] * fs[0]), fs[1] * fs[1], Vs);
                     part[NS - 1] += Vs;
                 }
 #pragma unroll
@@ -456,19 +464,19 @@ __device__ void march_tile(const TileJob& J, unsigned char* smem_raw, double (&a
                     const T zm = v == 0 ? zm0[j] : cur[j][k][v - 1];
                     const T zp = v == V - 1 ? zp0[j] : cur[j][k][v + 1];
                     const T xp = nxt[j][k][v];
-                    const T nb = (prev[j][k][v] + xp) + (ym[j][v] + yp[j][v]) + (zm + zp);
-                    const T F = kL * (nb - T(6) * f) - kV * dV[j];
+                    const T nb = ((prev[j][k][v] + xp) + (ym[j][v] + yp[j][v])) + (zm + zp);
+                    const T F = fmad(kL, fmad(T(-6), f, nb), -(kV * dV[j]));
                     const T po = pc[j][k][v];
-                    const T p1 = po + kt * F;
-                    const T ps = po + kb * F;
+                    const T p1 = fmad(kt, F, po);
+                    const T ps = fmad(kb, F, po);
                     pnew[j][v] = p1;
                     const T gx = xp - f, gy = yp[j][v] - f, gz = zp - f;
                     const T d = f - shift[j];
                     T* q5 = part + kSumsPerField * j;
-                    q5[0] += ps * ps;
-                    q5[1] += gx * gx + gy * gy + gz * gz;
+                    q5[0] = fmad(ps, ps, q5[0]);
+                    q5[1] = fmad(gz, gz, fmad(gy, gy, fmad(gx, gx, q5[1])));
                     q5[2] += d;
-                    q5[3] += d * d;
+                    q5[3] = fmad(d, d, q5[3]);
                     q5[4] += p1;
                 }
             }
