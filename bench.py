@@ -133,6 +133,55 @@ def linear_regime_deviation(r32, r64, nf):
     return out
 
 
+def batched_run(steps, warmup, solo_steps=100):
+    """The 96-member uneven ensemble (48 x 32^3, 32 x 64^3, 16 x 128^3, FP32,
+    one field, leapfrog): all members advanced together, one persistent
+    launch per pass, passes captured in a HIP graph.  Also times every member
+    run on its own for `solo_steps` steps, for the batching gain."""
+    import torch
+    from paper_2607_24978_amd import _lib
+    ws = W.ensemble_members()
+    lats = []
+    for w in ws:
+        lat = _lib.Lattice(w.N, w.dx, 1, "fp32")
+        lat.set_potential(w.m2, w.lam, w.g2, w.V0)
+        lat.seed(w.seed, w.fbar[:1], w.pbar[:1], w.cutoff_modes, w.amp)
+        lats.append(lat)
+    sites = sum(w.sites for w in ws)
+    # solo: each member on its own stream-less handle, back to back
+    torch.cuda.synchronize()
+    for lat, w in zip(lats, ws):
+        lat.step("leapfrog", w.dt, 2)
+    t0 = time.perf_counter()
+    for lat, w in zip(lats, ws):
+        lat.step("leapfrog", w.dt, solo_steps)
+    solo_s = time.perf_counter() - t0
+    ens = _lib.Ensemble(lats)
+    for i, w in enumerate(ws):
+        ens.set_dt(i, w.dt)
+    chunk = min(steps, 500)
+    ens.step("leapfrog", chunk)  # warm-up call captures the graph
+    for _ in range(max(0, warmup - chunk) // chunk):
+        ens.step("leapfrog", chunk)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps // chunk):
+        r = ens.step("leapfrog", chunk)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    nsteps = (steps // chunk) * chunk
+    ok = not bool(np.any(r["nonfinite"]))
+    ens.close()
+    for lat in lats:
+        lat.close()
+    launches = nsteps + steps // chunk
+    achieved = sites * 16 * launches / sec / 1e9
+    return {"members": len(ws), "sites": sites, "steps": nsteps, "site_updates_per_s": sites * nsteps / sec,
+            "ms_per_step": 1e3 * sec / nsteps, "hbm_frac": achieved / HBM_PEAK_GBS,
+            "solo_site_updates_per_s": sites * solo_steps / solo_s,
+            "batched_speedup_vs_solo": (sites * nsteps / sec) / (sites * solo_steps / solo_s), "finite": ok}
+
+
 def cpu_baseline(w, steps=1):
     """The FP64 oracle as it stands, on the same 256^3 workload, for a bounded
     number of full steps on the host (numpy, single thread)."""
@@ -160,6 +209,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--tile", default=None, help="force the FP32 tile tz,ty,cx,ry,pd instead of autotuning")
     ap.add_argument("--workload", choices=["c1", "c3"], default="c1",
                     help="c1: 256^3 two-field VV4 (default); c3: 1024^3 two-field leapfrog")
@@ -214,6 +264,8 @@ def main():
         forms["fp64"] = {"site_updates_per_s": w.sites * args.steps / sec64, "hbm_frac": ach64 / HBM_PEAK_GBS}
         forms["fp32_vs_fp64_rel_dev"] = linear_regime_deviation(r32, r64, w.n_fields)
         forms["fp32_speedup_vs_fp64"] = value / forms["fp64"]["site_updates_per_s"]
+    if not args.no_batched and args.workload == "c1":
+        forms["batched"] = batched_run(1000, 500)
     line["forms"] = forms
     if not args.no_cpu:
         # the oracle on the 256^3 workload (the 1024^3 one does not fit a numpy run of ~30 s)
