@@ -49,6 +49,25 @@ class cl_tile(C.Structure):
     _fields_ = [("tz", C.c_int), ("ty", C.c_int), ("cx", C.c_int), ("ry", C.c_int), ("pd", C.c_int)]
 
 
+class cl_surrogate_cfg(C.Structure):
+    _fields_ = [("n_fields", C.c_int), ("extra_inputs", C.c_int), ("hidden", C.c_int), ("layers", C.c_int),
+                ("jump_steps", C.c_int), ("init_seed", C.c_uint64)]
+
+
+class cl_train_cfg(C.Structure):
+    _fields_ = [("epochs", C.c_int), ("lr", C.c_double), ("lr_final", C.c_double), ("shuffle_seed", C.c_uint64),
+                ("holdout", C.c_int)]
+
+
+class cl_train_report(C.Structure):
+    _fields_ = [("steps", C.c_int), ("first_loss", C.c_double), ("last_epoch_loss", C.c_double),
+                ("holdout_loss", C.c_double), ("holdout_zero", C.c_double), ("seconds", C.c_double)]
+
+
+class cl_surrogate_report(C.Structure):
+    _fields_ = [("jumps", C.c_int), ("fallbacks", C.c_int), ("max_residual", C.c_double), ("seconds", C.c_double)]
+
+
 OBS_DTYPE = np.dtype([("eta", "f8"), ("a", "f8"), ("H", "f8"), ("EK", "f8", 2), ("EG", "f8", 2), ("EV", "f8"),
                       ("mean", "f8", 2), ("var", "f8", 2), ("r", "f8"), ("nonfinite", "i4"),
                       ("reserved", "i4")])
@@ -81,6 +100,24 @@ _SIGS = {
     "cl_ensemble_step": (C.c_int, [_P, C.c_int, C.c_int, _P]),
     "cl_ensemble_destroy": (C.c_int, [_P]),
     "cl_ensemble_get_tile": (C.c_int, [_P, C.c_int, C.POINTER(cl_tile)]),
+    "cl_surrogate_last_error": (C.c_char_p, []),
+    "cl_surrogate_create": (C.c_int, [C.POINTER(cl_surrogate_cfg), C.POINTER(_P)]),
+    "cl_surrogate_destroy": (C.c_int, [_P]),
+    "cl_surrogate_num_params": (C.c_int, [_P, C.POINTER(C.c_int64)]),
+    "cl_surrogate_get_params": (C.c_int, [_P, C.POINTER(C.c_float)]),
+    "cl_surrogate_set_params": (C.c_int, [_P, C.POINTER(C.c_float)]),
+    "cl_surrogate_forward": (C.c_int, [_P, C.c_int, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
+    "cl_surrogate_loss_grad": (C.c_int, [_P, C.c_int, C.POINTER(C.c_float), C.POINTER(C.c_float),
+                                         C.POINTER(C.c_double), C.POINTER(C.c_float)]),
+    "cl_surrogate_dataset_reserve": (C.c_int, [_P, C.c_int, C.c_int]),
+    "cl_surrogate_record_input": (C.c_int, [_P, _P]),
+    "cl_surrogate_record_target": (C.c_int, [_P, _P]),
+    "cl_surrogate_dataset_size": (C.c_int, [_P, C.POINTER(C.c_int)]),
+    "cl_surrogate_train": (C.c_int, [_P, C.POINTER(cl_train_cfg), C.POINTER(cl_train_report)]),
+    "cl_surrogate_save": (C.c_int, [_P, C.c_char_p]),
+    "cl_surrogate_load": (C.c_int, [_P, C.c_char_p]),
+    "cl_surrogate_advance": (C.c_int, [_P, _P, C.c_int, C.c_double, C.c_int, C.c_double, _P,
+                                       C.POINTER(cl_surrogate_report)]),
 }
 
 if not os.path.exists(LIB_PATH):
@@ -213,6 +250,103 @@ def copy_bandwidth(nbytes: int, reps: int = 10) -> float:
     g = C.c_double()
     _check(lib.cl_copy_bandwidth(C.c_size_t(nbytes), int(reps), C.byref(g)))
     return g.value
+
+
+def _scheck(st: int):
+    if st != CL_OK:
+        msg = lib.cl_surrogate_last_error()
+        raise CLError(st, msg.decode() if msg else "")
+
+
+def _fptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+class Surrogate:
+    """The learned surrogate (cl_surrogate_*)."""
+
+    def __init__(self, n_fields=2, extra_inputs=2, hidden=32, layers=5, jump_steps=16, init_seed=0):
+        cfg = cl_surrogate_cfg(n_fields, extra_inputs, hidden, layers, jump_steps, init_seed)
+        h = _P()
+        _scheck(lib.cl_surrogate_create(C.byref(cfg), C.byref(h)))
+        self.s = h
+        self.n_fields, self.extra_inputs, self.layers, self.jump_steps = n_fields, extra_inputs, layers, jump_steps
+        self.cin = 2 * n_fields + extra_inputs
+        self.cout = 2 * n_fields
+
+    def close(self):
+        if getattr(self, "s", None):
+            lib.cl_surrogate_destroy(self.s)
+            self.s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def num_params(self) -> int:
+        n = C.c_int64()
+        _scheck(lib.cl_surrogate_num_params(self.s, C.byref(n)))
+        return n.value
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(self.num_params(), dtype=np.float32)
+        _scheck(lib.cl_surrogate_get_params(self.s, _fptr(out)))
+        return out
+
+    def set_params(self, theta):
+        theta = np.ascontiguousarray(theta, dtype=np.float32)
+        _scheck(lib.cl_surrogate_set_params(self.s, _fptr(theta)))
+
+    def forward(self, x):
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        N = x.shape[-1]
+        y = np.empty((self.cout, N, N, N), dtype=np.float32)
+        _scheck(lib.cl_surrogate_forward(self.s, N, _fptr(x), _fptr(y)))
+        return y
+
+    def loss_grad(self, x, t):
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        t = np.ascontiguousarray(t, dtype=np.float32)
+        loss = C.c_double()
+        g = np.empty(self.num_params(), dtype=np.float32)
+        _scheck(lib.cl_surrogate_loss_grad(self.s, x.shape[-1], _fptr(x), _fptr(t), C.byref(loss), _fptr(g)))
+        return loss.value, g
+
+    def dataset_reserve(self, N: int, max_pairs: int):
+        _scheck(lib.cl_surrogate_dataset_reserve(self.s, int(N), int(max_pairs)))
+
+    def record_input(self, lat: "Lattice"):
+        _scheck(lib.cl_surrogate_record_input(self.s, lat.h))
+
+    def record_target(self, lat: "Lattice"):
+        _scheck(lib.cl_surrogate_record_target(self.s, lat.h))
+
+    def dataset_size(self) -> int:
+        n = C.c_int()
+        _scheck(lib.cl_surrogate_dataset_size(self.s, C.byref(n)))
+        return n.value
+
+    def train(self, epochs=1, lr=1e-3, lr_final=1e-5, shuffle_seed=0, holdout=0) -> dict:
+        cfg = cl_train_cfg(int(epochs), float(lr), float(lr_final), int(shuffle_seed), int(holdout))
+        rep = cl_train_report()
+        _scheck(lib.cl_surrogate_train(self.s, C.byref(cfg), C.byref(rep)))
+        return {k: getattr(rep, k) for k, _ in cl_train_report._fields_}
+
+    def save(self, path: str):
+        _scheck(lib.cl_surrogate_save(self.s, path.encode()))
+
+    def load(self, path: str):
+        _scheck(lib.cl_surrogate_load(self.s, path.encode()))
+
+    def advance(self, lat: "Lattice", fallback: str, dt: float, n_jumps: int, threshold: float = 1e-3):
+        out = np.zeros(max(n_jumps, 0), dtype=OBS_DTYPE)
+        rep = cl_surrogate_report()
+        ptr = _P(out.ctypes.data) if n_jumps > 0 else None
+        _scheck(lib.cl_surrogate_advance(lat.h, self.s, INTEGRATORS[fallback], float(dt), int(n_jumps),
+                                         float(threshold), ptr, C.byref(rep)))
+        return out, {k: getattr(rep, k) for k, _ in cl_surrogate_report._fields_}
 
 
 class Ensemble:

@@ -1,0 +1,891 @@
+// Host runtime of the learned surrogate (cl_surrogate.h): parameters,
+// device buffers, the training loop (forward, MSE, backward, Adam) and the
+// network jump with its Hubble-constraint fallback.
+#include "../../include/cl_surrogate.h"
+#include "internal.h"
+#include "surrogate.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <random>
+#include <string>
+#include <vector>
+
+using cl::sg::ConvArgs;
+
+namespace {
+
+thread_local std::string s_err;
+
+cl_status sfail(cl_status st, const std::string& m) {
+    s_err = m;
+    return st;
+}
+
+#define SHIP(call)                                                                                   \
+    do {                                                                                             \
+        hipError_t e_ = (call);                                                                      \
+        if (e_ != hipSuccess) return sfail(CL_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+struct Layer {
+    int cin = 0, cout = 0;     // real channels
+    int cinp = 0, coutp = 0;   // padded (8 or 32 in; 16 or 32 out)
+    int nb = 0;                // 16-wide output blocks
+    size_t w_off = 0, b_off = 0;  // offsets in the flat parameter vector
+    uint16_t* wf = nullptr;    // forward weights
+    uint16_t* wd = nullptr;    // input-gradient weights (layers > 0)
+    float* bias = nullptr;
+    int cinp_d = 0, coutp_d = 0;  // input-gradient conv: inputs = cout (padded), outputs = cin
+};
+
+template <typename T>
+T* dalloc(size_t n) {
+    void* p = nullptr;
+    if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) return nullptr;
+    return static_cast<T*>(p);
+}
+
+}  // namespace
+
+struct cl_surrogate {
+    cl_surrogate_cfg cfg{};
+    std::vector<Layer> L;
+    int64_t nparams = 0;
+    float *theta = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;
+    int adam_t = 0;
+    hipStream_t stream = nullptr;
+    // activation buffers for one lattice size
+    int bufN = 0;
+    uint16_t* x0 = nullptr;               // [n3][8]
+    std::vector<uint16_t*> act;           // [layers-1] x [n3][32]
+    std::vector<float*> zpre;             // [layers-1] x [n3][32]
+    float* y = nullptr;                   // [n3][4..8]
+    float* dA = nullptr;                  // [n3][32]
+    uint16_t* dZ = nullptr;               // [n3][32]
+    uint16_t* dy = nullptr;               // [n3][8]
+    float* target = nullptr;              // [c][n3]
+    float* wpart = nullptr;               // wgrad partials
+    int wgrid = 0, wstride = 0;
+    double* lpart = nullptr;              // loss partials
+    int lgrid = 256;
+    // dataset
+    int dsN = 0, ds_cap = 0, ds_n = 0;
+    bool pending = false;
+    float* ds_fluct = nullptr;            // [cap][c][n3]
+    float* ds_incr = nullptr;             // [cap][c][n3]
+    std::vector<std::vector<double>> ds_extra;  // raw broadcast features per pair
+    // normalisation
+    bool scaled = false;
+    double in_scale[4] = {1, 1, 1, 1}, out_scale[4] = {1, 1, 1, 1};
+    double ex_mean[4] = {0, 0, 0, 0}, ex_std[4] = {1, 1, 1, 1};
+    // inference snapshot
+    void* snap = nullptr;
+    size_t snap_bytes = 0;
+};
+
+namespace {
+
+int nfc(const cl_surrogate* s) { return 2 * s->cfg.n_fields; }
+int cin0(const cl_surrogate* s) { return nfc(s) + s->cfg.extra_inputs; }
+
+void free_bufs(cl_surrogate* s) {
+    auto f = [](void* p) {
+        if (p) hipFree(p);
+    };
+    f(s->x0);
+    for (auto p : s->act) f(p);
+    for (auto p : s->zpre) f(p);
+    f(s->y);
+    f(s->dA);
+    f(s->dZ);
+    f(s->dy);
+    f(s->target);
+    f(s->wpart);
+    f(s->lpart);
+    s->x0 = nullptr;
+    s->act.clear();
+    s->zpre.clear();
+    s->y = s->dA = s->target = s->wpart = nullptr;
+    s->dZ = s->dy = nullptr;
+    s->lpart = nullptr;
+    s->bufN = 0;
+}
+
+cl_status ensure_bufs(cl_surrogate* s, int N, bool training) {
+    if (s->bufN == N && (!training || !s->zpre.empty())) return CL_OK;
+    free_bufs(s);
+    const size_t n3 = static_cast<size_t>(N) * N * N;
+    const int nl = static_cast<int>(s->L.size());
+    s->x0 = dalloc<uint16_t>(n3 * 8);
+    s->y = dalloc<float>(n3 * 8);
+    bool ok = s->x0 && s->y;
+    for (int l = 0; l + 1 < nl; ++l) {
+        s->act.push_back(dalloc<uint16_t>(n3 * 32));
+        ok = ok && s->act.back();
+        if (training) {
+            s->zpre.push_back(dalloc<float>(n3 * 32));
+            ok = ok && s->zpre.back();
+        }
+    }
+    if (training) {
+        s->dA = dalloc<float>(n3 * 32);
+        s->dZ = dalloc<uint16_t>(n3 * 32);
+        s->dy = dalloc<uint16_t>(n3 * 8);
+        s->target = dalloc<float>(n3 * 8);
+        s->wgrid = 512;
+        s->wstride = 27 * 32 * 32 + 32;
+        s->wpart = dalloc<float>(static_cast<size_t>(s->wgrid) * s->wstride);
+        s->lpart = dalloc<double>(s->lgrid);
+        ok = ok && s->dA && s->dZ && s->dy && s->target && s->wpart && s->lpart;
+    }
+    if (!ok) {
+        free_bufs(s);
+        return sfail(CL_ENOMEM, "surrogate activation buffers");
+    }
+    s->bufN = N;
+    return CL_OK;
+}
+
+// FP32 master parameters -> BF16 forward / input-gradient weights, FP32 bias.
+cl_status prepare(cl_surrogate* s) {
+    for (size_t l = 0; l < s->L.size(); ++l) {
+        const Layer& ly = s->L[l];
+        cl::sg::PrepArgs a{};
+        a.theta = s->theta + ly.w_off;
+        a.bias_offset = static_cast<int>(ly.b_off - ly.w_off);
+        a.cout = ly.cout;
+        a.cin = ly.cin;
+        a.coutp = ly.coutp;
+        a.cinp = ly.cinp;
+        a.no_f = ly.cinp == 32 ? 27 : 28;
+        a.wf = ly.wf;
+        a.wd = ly.wd;
+        a.coutp_d = ly.coutp_d;
+        a.cinp_d = ly.cinp_d;
+        a.no_d = ly.cinp_d == 32 ? 27 : 28;
+        a.bias = ly.bias;
+        SHIP(cl::sg::launch_prepare_layer(a, s->stream));
+    }
+    return CL_OK;
+}
+
+// Network forward from s->x0; training keeps the pre-activations.
+cl_status forward(cl_surrogate* s, int N, bool training) {
+    const int nl = static_cast<int>(s->L.size());
+    const int n3 = N * N * N;
+    for (int l = 0; l < nl; ++l) {
+        const Layer& ly = s->L[l];
+        ConvArgs a{};
+        a.in = l == 0 ? static_cast<const void*>(s->x0) : static_cast<const void*>(s->act[l - 1]);
+        a.w = ly.wf;
+        a.bias = ly.bias;
+        a.N = N;
+        a.nsites = n3;
+        a.cout = ly.coutp == 16 ? 4 * ((ly.cout + 3) / 4) : 32;
+        if (l + 1 < nl) {
+            a.z_out = training ? s->zpre[l] : nullptr;
+            a.z_stride = 32;
+            a.a_out = s->act[l];
+            a.a_stride = 32;
+            a.gelu = 1;
+        } else {
+            a.z_out = s->y;
+            a.z_stride = a.cout;
+            a.a_out = nullptr;
+            a.gelu = 0;
+        }
+        const int groups = n3 / 16;
+        const int grid = std::max(1, std::min(1024, (groups + 15) / 16));
+        SHIP(cl::sg::launch_conv_fwd(a, ly.cinp, ly.nb, grid, s->stream));
+    }
+    return CL_OK;
+}
+
+int ystride(const cl_surrogate* s) { return 4 * ((s->L.back().cout + 3) / 4); }
+
+// MSE and gradient of every parameter into s->grad; returns the loss.
+cl_status loss_and_backward(cl_surrogate* s, int N, double* loss) {
+    const int nl = static_cast<int>(s->L.size());
+    const size_t n3 = static_cast<size_t>(N) * N * N;
+    const int co = s->L.back().cout;
+    SHIP(cl::sg::launch_mse_grad(s->y, ystride(s), s->target, co, n3, 1.0 / (static_cast<double>(n3) * co), s->dy,
+                                 s->lpart, s->lgrid, s->stream));
+    for (int l = nl - 1; l >= 0; --l) {
+        const Layer& ly = s->L[l];
+        const void* dz = nullptr;
+        int dz_stride = 0;
+        if (l == nl - 1) {
+            dz = s->dy;
+            dz_stride = 8;
+        } else {
+            SHIP(cl::sg::launch_gelu_backward(s->dA, s->zpre[l], s->dZ, n3 * 32, s->stream));
+            dz = s->dZ;
+            dz_stride = 32;
+        }
+        cl::sg::WgradArgs w{};
+        w.dz = dz;
+        w.x = l == 0 ? static_cast<const void*>(s->x0) : static_cast<const void*>(s->act[l - 1]);
+        w.partials = s->wpart;
+        w.N = N;
+        w.nsites = static_cast<int>(n3);
+        w.cout_stride = dz_stride;
+        w.partial_stride = s->wstride;
+        const int grid = std::min(s->wgrid, static_cast<int>(n3 / 32));
+        SHIP(cl::sg::launch_conv_wgrad(w, ly.cinp, ly.nb, grid, s->stream));
+        cl::sg::WgradReduceArgs r{};
+        r.partials = s->wpart;
+        r.nparts = grid;
+        r.partial_stride = s->wstride;
+        r.coutp = ly.coutp;
+        r.cinp = ly.cinp == 32 ? 32 : 16;
+        r.cout = ly.cout;
+        r.cin = ly.cin;
+        r.gW = s->grad + ly.w_off;
+        r.gb = s->grad + ly.b_off;
+        SHIP(cl::sg::launch_wgrad_reduce(r, s->stream));
+        if (l > 0) {
+            // input gradient: a convolution of dz with the flipped, transposed weights
+            ConvArgs a{};
+            a.in = dz;
+            a.w = ly.wd;
+            a.bias = nullptr;
+            a.N = N;
+            a.nsites = static_cast<int>(n3);
+            a.cout = 32;
+            a.z_out = s->dA;
+            a.z_stride = 32;
+            a.a_out = nullptr;
+            a.gelu = 0;
+            const int groups = static_cast<int>(n3 / 16);
+            const int grid2 = std::max(1, std::min(1024, (groups + 15) / 16));
+            SHIP(cl::sg::launch_conv_fwd(a, ly.cinp_d, 2, grid2, s->stream));
+        }
+    }
+    std::vector<double> lp(s->lgrid);
+    SHIP(hipMemcpyAsync(lp.data(), s->lpart, s->lgrid * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    SHIP(hipStreamSynchronize(s->stream));
+    double sum = 0.0;
+    for (double x : lp) sum += x;
+    *loss = sum / (static_cast<double>(n3) * co);
+    return CL_OK;
+}
+
+bool valid_net_N(int N) { return N >= 16 && (N & (N - 1)) == 0; }
+// The weight-gradient kernel takes 32-site segments of one z row.
+bool valid_train_N(int N) { return N >= 32 && (N & (N - 1)) == 0; }
+
+// Host FP32 [c][n3] -> BF16 [site][8] in s->x0 (through a staging upload).
+cl_status upload_input(cl_surrogate* s, int N, const float* x) {
+    const size_t n3 = static_cast<size_t>(N) * N * N;
+    const int c = cin0(s);
+    std::vector<uint16_t> h(n3 * 8, 0);
+    for (int k = 0; k < c; ++k)
+        for (size_t i = 0; i < n3; ++i) {
+            uint32_t u;
+            std::memcpy(&u, &x[k * n3 + i], 4);
+            u += 0x7FFFu + ((u >> 16) & 1u);
+            h[i * 8 + k] = static_cast<uint16_t>(u >> 16);
+        }
+    SHIP(hipMemcpyAsync(s->x0, h.data(), h.size() * 2, hipMemcpyHostToDevice, s->stream));
+    SHIP(hipStreamSynchronize(s->stream));
+    return CL_OK;
+}
+
+// Hartree-corrected lattice-mean force of the homogeneous modes, dV/df_j
+// averaged over Gaussian fluctuations of variance var_k about fbar.
+void mean_force(const cl_lattice* h, const double* f, const double* var, double* dv) {
+    const cl_potential& p = h->pot;
+    const int nf = h->nf;
+    for (int j = 0; j < nf; ++j) dv[j] = p.m2[j] * f[j] + p.lambda[j] * (f[j] * f[j] * f[j] + 3.0 * f[j] * var[j]);
+    if (nf == 2) {
+        dv[0] += p.g2 * f[0] * (f[1] * f[1] + var[1]);
+        dv[1] += p.g2 * f[1] * (f[0] * f[0] + var[0]);
+    }
+}
+
+double hom_V(const cl_lattice* h, const double* f, const double* var) {
+    const cl_potential& p = h->pot;
+    double V = p.V0;
+    for (int j = 0; j < h->nf; ++j) {
+        const double f2 = f[j] * f[j];
+        V += 0.5 * p.m2[j] * (f2 + var[j]) + 0.25 * p.lambda[j] * (f2 * f2 + 6.0 * f2 * var[j] + 3.0 * var[j] * var[j]);
+    }
+    if (h->nf == 2) V += 0.5 * p.g2 * (f[0] * f[0] + var[0]) * (f[1] * f[1] + var[1]);
+    return V;
+}
+
+// Advance (fbar, pbar, a, b) over n steps of dt with the integrator's
+// sub-step pattern; the fluctuations' kinetic + gradient energy rides along
+// as radiation, rho_r ~ a^-4, p_r = rho_r / 3.
+void advance_homogeneous(const cl_lattice* h, cl_integrator integ, double dt, int n, double* f, double* pm, double& a,
+                         double& b, const double* var, double rho_r0, double a_ref) {
+    const double al = h->alpha, mp = h->mp;
+    const bool expand = h->mode == CL_SELF_CONSISTENT;
+    auto accel = [&](double aa) {
+        if (!expand) return 0.0;
+        double K = 0.0;
+        for (int j = 0; j < h->nf; ++j) K += pm[j] * pm[j] / (2.0 * std::pow(aa, 6.0));
+        const double V = hom_V(h, f, var);
+        const double rr = rho_r0 * std::pow(a_ref / aa, 4.0);
+        const double rho = K + V + rr, pr = K - V + rr / 3.0;
+        return std::pow(aa, 2.0 * al + 1.0) * ((2.0 * al - 1.0) * rho - 3.0 * pr) / (6.0 * mp * mp);
+    };
+    auto kick = [&](double hh, double aa) {
+        double dv[2];
+        mean_force(h, f, var, dv);
+        for (int j = 0; j < h->nf; ++j) pm[j] -= hh * std::pow(aa, 3.0 + al) * dv[j];
+    };
+    auto vv2 = [&](double hh) {
+        kick(0.5 * hh, a);
+        b += 0.5 * hh * accel(a);
+        const double an = expand ? a + hh * b : a;
+        const double abar = 0.5 * (a + an);
+        for (int j = 0; j < h->nf; ++j) f[j] += hh * std::pow(abar, al - 3.0) * pm[j];
+        a = an;
+        kick(0.5 * hh, a);
+        b += 0.5 * hh * accel(a);
+    };
+    const double w1 = 1.0 / (2.0 - std::cbrt(2.0)), w0 = 1.0 - 2.0 * w1;
+    for (int i = 0; i < n; ++i) {
+        if (integ == CL_VV4) {
+            vv2(w1 * dt);
+            vv2(w0 * dt);
+            vv2(w1 * dt);
+        } else {
+            vv2(dt);
+        }
+    }
+}
+
+// Raw broadcast features of a lattice state: (a, H, <f_0>, <pi_0>).
+void raw_extra(const cl_observables& o, const cl::Scal& sc, double* e) {
+    e[0] = o.a;
+    e[1] = o.H;
+    e[2] = o.mean[0];
+    e[3] = sc.mean_p[0];
+}
+
+cl_status read_lattice(cl_lattice* h, cl_observables* o, cl::Scal* sc) {
+    cl_status st = cl_read_observables(h, o);
+    if (st) return sfail(st, std::string("reading lattice observables: ") + cl_last_error(h));
+    SHIP(hipMemcpyAsync(sc, h->sc, sizeof(cl::Scal), hipMemcpyDeviceToHost, h->stream));
+    SHIP(hipStreamSynchronize(h->stream));
+    return CL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* cl_surrogate_last_error(void) { return s_err.c_str(); }
+
+cl_status cl_surrogate_create(const cl_surrogate_cfg* cfg, cl_surrogate** out) {
+    if (!out) return sfail(CL_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!cfg) return sfail(CL_EINVAL, "cfg is NULL");
+    if (cfg->n_fields < 1 || cfg->n_fields > 2) return sfail(CL_EINVAL, "n_fields must be 1 or 2");
+    if (cfg->extra_inputs < 0 || 2 * cfg->n_fields + cfg->extra_inputs > 8)
+        return sfail(CL_EINVAL, "at most 8 input channels");
+    if (cfg->hidden != 32) return sfail(CL_EUNSUPPORTED, "hidden width must be 32");
+    if (cfg->layers < 2 || cfg->layers > 16) return sfail(CL_EINVAL, "layers must be in [2, 16]");
+    if (cfg->jump_steps < 1) return sfail(CL_EINVAL, "jump_steps must be >= 1");
+    cl_surrogate* s = new (std::nothrow) cl_surrogate;
+    if (!s) return sfail(CL_ENOMEM, "surrogate handle");
+    s->cfg = *cfg;
+    size_t off = 0;
+    for (int l = 0; l < cfg->layers; ++l) {
+        Layer ly;
+        ly.cin = l == 0 ? cin0(s) : 32;
+        ly.cout = l + 1 == cfg->layers ? nfc(s) : 32;
+        ly.cinp = ly.cin <= 8 ? 8 : 32;
+        ly.coutp = ly.cout <= 16 ? 16 : 32;
+        if (l + 1 < cfg->layers) ly.coutp = 32;
+        ly.nb = ly.coutp / 16;
+        ly.cinp_d = ly.cout <= 8 ? 8 : 32;
+        ly.coutp_d = 32;
+        ly.w_off = off;
+        off += static_cast<size_t>(ly.cout) * ly.cin * 27;
+        ly.b_off = off;
+        off += ly.cout;
+        s->L.push_back(ly);
+    }
+    s->nparams = static_cast<int64_t>(off);
+    auto bail = [&](cl_status st, const std::string& m) {
+        cl_surrogate_destroy(s);
+        return sfail(st, m);
+    };
+    if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) return bail(CL_EDEVICE, "stream");
+    s->theta = dalloc<float>(off);
+    s->grad = dalloc<float>(off);
+    s->m = dalloc<float>(off);
+    s->v = dalloc<float>(off);
+    if (!s->theta || !s->grad || !s->m || !s->v) return bail(CL_ENOMEM, "parameters");
+    for (auto& ly : s->L) {
+        const int nof = ly.cinp == 32 ? 27 : 28;
+        const int nod = ly.cinp_d == 32 ? 27 : 28;
+        ly.wf = dalloc<uint16_t>(static_cast<size_t>(nof) * ly.coutp * ly.cinp);
+        ly.wd = dalloc<uint16_t>(static_cast<size_t>(nod) * ly.coutp_d * ly.cinp_d);
+        ly.bias = dalloc<float>(32);
+        if (!ly.wf || !ly.wd || !ly.bias) return bail(CL_ENOMEM, "layer weights");
+    }
+    // He-style uniform initialisation on the host, biases zero
+    std::vector<float> th(off, 0.0f);
+    std::mt19937_64 rng(cfg->init_seed);
+    for (const auto& ly : s->L) {
+        const double bound = std::sqrt(6.0 / (27.0 * ly.cin));
+        std::uniform_real_distribution<double> U(-bound, bound);
+        for (size_t i = 0; i < static_cast<size_t>(ly.cout) * ly.cin * 27; ++i) th[ly.w_off + i] = static_cast<float>(U(rng));
+    }
+    cl_status st = cl_surrogate_set_params(s, th.data());
+    if (st) return bail(st, s_err);
+    *out = s;
+    return CL_OK;
+}
+
+cl_status cl_surrogate_destroy(cl_surrogate* s) {
+    if (!s) return CL_OK;
+    if (s->stream) hipStreamSynchronize(s->stream);
+    free_bufs(s);
+    for (auto& ly : s->L) {
+        if (ly.wf) hipFree(ly.wf);
+        if (ly.wd) hipFree(ly.wd);
+        if (ly.bias) hipFree(ly.bias);
+    }
+    for (void* p : {(void*)s->theta, (void*)s->grad, (void*)s->m, (void*)s->v, (void*)s->ds_fluct,
+                    (void*)s->ds_incr, s->snap})
+        if (p) hipFree(p);
+    if (s->stream) hipStreamDestroy(s->stream);
+    delete s;
+    return CL_OK;
+}
+
+cl_status cl_surrogate_num_params(const cl_surrogate* s, int64_t* n) {
+    if (!s || !n) return sfail(CL_EINVAL, "NULL argument");
+    *n = s->nparams;
+    return CL_OK;
+}
+
+cl_status cl_surrogate_get_params(cl_surrogate* s, float* theta) {
+    if (!s || !theta) return sfail(CL_EINVAL, "NULL argument");
+    SHIP(hipMemcpyAsync(theta, s->theta, s->nparams * sizeof(float), hipMemcpyDeviceToHost, s->stream));
+    SHIP(hipStreamSynchronize(s->stream));
+    return CL_OK;
+}
+
+cl_status cl_surrogate_set_params(cl_surrogate* s, const float* theta) {
+    if (!s || !theta) return sfail(CL_EINVAL, "NULL argument");
+    for (int64_t i = 0; i < s->nparams; ++i)
+        if (!std::isfinite(theta[i])) return sfail(CL_EINVAL, "non-finite parameter");
+    SHIP(hipMemcpyAsync(s->theta, theta, s->nparams * sizeof(float), hipMemcpyHostToDevice, s->stream));
+    SHIP(hipMemsetAsync(s->m, 0, s->nparams * sizeof(float), s->stream));
+    SHIP(hipMemsetAsync(s->v, 0, s->nparams * sizeof(float), s->stream));
+    s->adam_t = 0;
+    cl_status st = prepare(s);
+    if (st) return st;
+    SHIP(hipStreamSynchronize(s->stream));
+    return CL_OK;
+}
+
+cl_status cl_surrogate_forward(cl_surrogate* s, int N, const float* x, float* y) {
+    if (!s || !x || !y) return sfail(CL_EINVAL, "NULL argument");
+    if (!valid_net_N(N)) return sfail(CL_EINVAL, "N must be a power of two >= 16");
+    cl_status st = ensure_bufs(s, N, false);
+    if (st) return st;
+    st = upload_input(s, N, x);
+    if (st) return st;
+    st = forward(s, N, false);
+    if (st) return st;
+    const size_t n3 = static_cast<size_t>(N) * N * N;
+    const int ys = ystride(s), co = s->L.back().cout;
+    std::vector<float> h(n3 * ys);
+    SHIP(hipMemcpyAsync(h.data(), s->y, h.size() * 4, hipMemcpyDeviceToHost, s->stream));
+    SHIP(hipStreamSynchronize(s->stream));
+    for (int c = 0; c < co; ++c)
+        for (size_t i = 0; i < n3; ++i) y[c * n3 + i] = h[i * ys + c];
+    return CL_OK;
+}
+
+cl_status cl_surrogate_loss_grad(cl_surrogate* s, int N, const float* x, const float* t, double* loss, float* grad) {
+    if (!s || !x || !t || !loss || !grad) return sfail(CL_EINVAL, "NULL argument");
+    if (!valid_train_N(N)) return sfail(CL_EINVAL, "N must be a power of two >= 32");
+    cl_status st = ensure_bufs(s, N, true);
+    if (st) return st;
+    st = upload_input(s, N, x);
+    if (st) return st;
+    const size_t n3 = static_cast<size_t>(N) * N * N;
+    const int co = s->L.back().cout;
+    SHIP(hipMemcpyAsync(s->target, t, n3 * co * sizeof(float), hipMemcpyHostToDevice, s->stream));
+    st = forward(s, N, true);
+    if (st) return st;
+    st = loss_and_backward(s, N, loss);
+    if (st) return st;
+    SHIP(hipMemcpyAsync(grad, s->grad, s->nparams * sizeof(float), hipMemcpyDeviceToHost, s->stream));
+    SHIP(hipStreamSynchronize(s->stream));
+    return CL_OK;
+}
+
+cl_status cl_surrogate_dataset_reserve(cl_surrogate* s, int N, int max_pairs) {
+    if (!s) return sfail(CL_EINVAL, "NULL surrogate");
+    if (!valid_train_N(N) || max_pairs < 1) return sfail(CL_EINVAL, "N must be a power of two >= 32, max_pairs >= 1");
+    if (s->ds_fluct) hipFree(s->ds_fluct);
+    if (s->ds_incr) hipFree(s->ds_incr);
+    s->ds_fluct = s->ds_incr = nullptr;
+    const size_t per = static_cast<size_t>(nfc(s)) * N * N * N;
+    s->ds_fluct = dalloc<float>(per * max_pairs);
+    s->ds_incr = dalloc<float>(per * max_pairs);
+    if (!s->ds_fluct || !s->ds_incr) return sfail(CL_ENOMEM, "dataset (" + std::to_string(2 * per * max_pairs * 4) + " bytes)");
+    s->dsN = N;
+    s->ds_cap = max_pairs;
+    s->ds_n = 0;
+    s->pending = false;
+    s->ds_extra.clear();
+    return CL_OK;
+}
+
+static cl_status record(cl_surrogate* s, cl_lattice* h, bool input) {
+    if (!s || !h) return sfail(CL_EINVAL, "NULL argument");
+    if (!s->ds_fluct) return sfail(CL_ESTATE, "no dataset reserved");
+    if (h->N != s->dsN || h->nf != s->cfg.n_fields) return sfail(CL_EINVAL, "lattice does not match the dataset");
+    if (input == s->pending) return sfail(CL_ESTATE, input ? "input already recorded" : "no input recorded");
+    if (input && s->ds_n >= s->ds_cap) return sfail(CL_ESTATE, "dataset full");
+    cl_observables o;
+    cl::Scal sc;
+    cl_status st = read_lattice(h, &o, &sc);
+    if (st) return st;
+    const size_t n3 = static_cast<size_t>(h->N) * h->N * h->N;
+    const size_t per = static_cast<size_t>(nfc(s)) * n3;
+    cl::sg::PackArgs a{};
+    a.state = h->buf[h->cur];
+    a.N = h->N;
+    a.nf = h->nf;
+    for (int j = 0; j < h->nf; ++j) {
+        a.mean[j] = o.mean[j];
+        a.mean[h->nf + j] = sc.mean_p[j];
+    }
+    for (int c = 0; c < 4; ++c) a.inv_scale[c] = 1.0;
+    a.nextra = 0;
+    if (input) {
+        a.fluct_out = s->ds_fluct + per * s->ds_n;
+        std::vector<double> e(4);
+        raw_extra(o, sc, e.data());
+        s->ds_extra.push_back(e);
+    } else {
+        a.fluct_sub = s->ds_incr + per * s->ds_n;
+        a.fluct_sub_ref = s->ds_fluct + per * s->ds_n;
+    }
+    SHIP(cl::sg::launch_pack_state(a, h->prec == CL_FP32, h->stream));
+    SHIP(hipStreamSynchronize(h->stream));
+    if (input) {
+        s->pending = true;
+    } else {
+        s->pending = false;
+        s->ds_n += 1;
+    }
+    (void)n3;
+    return CL_OK;
+}
+
+cl_status cl_surrogate_record_input(cl_surrogate* s, cl_lattice* h) { return record(s, h, true); }
+cl_status cl_surrogate_record_target(cl_surrogate* s, cl_lattice* h) { return record(s, h, false); }
+
+cl_status cl_surrogate_dataset_size(const cl_surrogate* s, int* pairs) {
+    if (!s || !pairs) return sfail(CL_EINVAL, "NULL argument");
+    *pairs = s->ds_n;
+    return CL_OK;
+}
+
+// Per-channel RMS of the recorded fluctuations and increments, and the
+// mean / spread of the broadcast features, over the first `count` pairs.
+static cl_status fix_scales(cl_surrogate* s, int count) {
+    const size_t n3 = static_cast<size_t>(s->dsN) * s->dsN * s->dsN;
+    const int C = nfc(s);
+    std::vector<float> h(n3);
+    double sf[4] = {0, 0, 0, 0}, si[4] = {0, 0, 0, 0};
+    const int stride = std::max(1, count / 16);  // a sample of the pairs is enough for the scales
+    int used = 0;
+    for (int p = 0; p < count; p += stride, ++used)
+        for (int c = 0; c < C; ++c) {
+            for (int which = 0; which < 2; ++which) {
+                const float* src = (which == 0 ? s->ds_fluct : s->ds_incr) + (static_cast<size_t>(p) * C + c) * n3;
+                SHIP(hipMemcpy(h.data(), src, n3 * 4, hipMemcpyDeviceToHost));
+                double acc = 0.0;
+                for (size_t i = 0; i < n3; ++i) acc += static_cast<double>(h[i]) * h[i];
+                (which == 0 ? sf : si)[c] += acc / n3;
+            }
+        }
+    for (int c = 0; c < C; ++c) {
+        s->in_scale[c] = std::sqrt(sf[c] / used);
+        s->out_scale[c] = std::sqrt(si[c] / used);
+        if (!(s->in_scale[c] > 0)) s->in_scale[c] = 1.0;
+        if (!(s->out_scale[c] > 0)) s->out_scale[c] = 1.0;
+    }
+    for (int k = 0; k < 4; ++k) {
+        double m = 0.0, q = 0.0;
+        for (int p = 0; p < count; ++p) m += s->ds_extra[p][k];
+        m /= count;
+        for (int p = 0; p < count; ++p) q += (s->ds_extra[p][k] - m) * (s->ds_extra[p][k] - m);
+        s->ex_mean[k] = m;
+        s->ex_std[k] = count > 1 && q > 0 ? std::sqrt(q / (count - 1)) : 1.0;
+    }
+    s->scaled = true;
+    return CL_OK;
+}
+
+static cl_status load_sample(cl_surrogate* s, int p) {
+    const size_t n3 = static_cast<size_t>(s->dsN) * s->dsN * s->dsN;
+    const int C = nfc(s);
+    cl::sg::SampleArgs a{};
+    a.fluct = s->ds_fluct + static_cast<size_t>(p) * C * n3;
+    a.incr = s->ds_incr + static_cast<size_t>(p) * C * n3;
+    for (int c = 0; c < C; ++c) {
+        a.inv_in[c] = static_cast<float>(1.0 / s->in_scale[c]);
+        a.inv_out[c] = static_cast<float>(1.0 / s->out_scale[c]);
+    }
+    a.nextra = s->cfg.extra_inputs;
+    for (int k = 0; k < a.nextra; ++k) a.extra[k] = static_cast<float>((s->ds_extra[p][k] - s->ex_mean[k]) / s->ex_std[k]);
+    a.nfc = C;
+    a.x = s->x0;
+    a.target = s->target;
+    a.n3 = n3;
+    SHIP(cl::sg::launch_pack_sample(a, s->stream));
+    return CL_OK;
+}
+
+cl_status cl_surrogate_train(cl_surrogate* s, const cl_train_cfg* cfg, cl_train_report* rep) {
+    if (!s || !cfg) return sfail(CL_EINVAL, "NULL argument");
+    if (s->pending) return sfail(CL_ESTATE, "an input is recorded without its target");
+    const int ntrain = s->ds_n - std::max(0, cfg->holdout);
+    if (ntrain < 1) return sfail(CL_ESTATE, "no training pairs");
+    if (cfg->epochs < 1 || !(cfg->lr > 0.0)) return sfail(CL_EINVAL, "epochs >= 1 and lr > 0 needed");
+    const auto t0 = std::chrono::steady_clock::now();
+    const int N = s->dsN;
+    cl_status st = ensure_bufs(s, N, true);
+    if (st) return st;
+    if (!s->scaled) {
+        st = fix_scales(s, ntrain);
+        if (st) return st;
+    }
+    std::vector<int> order(ntrain);
+    std::iota(order.begin(), order.end(), 0);
+    std::mt19937_64 rng(cfg->shuffle_seed);
+    const int total = cfg->epochs * ntrain;
+    double first = -1.0, epoch_sum = 0.0;
+    int step = 0;
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    for (int ep = 0; ep < cfg->epochs; ++ep) {
+        std::shuffle(order.begin(), order.end(), rng);
+        epoch_sum = 0.0;
+        for (int k = 0; k < ntrain; ++k, ++step) {
+            st = load_sample(s, order[k]);
+            if (st) return st;
+            st = forward(s, N, true);
+            if (st) return st;
+            double loss = 0.0;
+            st = loss_and_backward(s, N, &loss);
+            if (st) return st;
+            if (!std::isfinite(loss)) return sfail(CL_EUNSTABLE, "non-finite training loss");
+            if (first < 0) first = loss;
+            epoch_sum += loss;
+            const double lr = cfg->lr_final + 0.5 * (cfg->lr - cfg->lr_final) * (1.0 + std::cos(M_PI * step / total));
+            s->adam_t += 1;
+            const float c1 = 1.0f - std::pow(b1, static_cast<float>(s->adam_t));
+            const float c2 = 1.0f - std::pow(b2, static_cast<float>(s->adam_t));
+            SHIP(cl::sg::launch_adam(s->theta, s->grad, s->m, s->v, static_cast<int>(s->nparams), static_cast<float>(lr),
+                                     b1, b2, eps, c1, c2, s->stream));
+            st = prepare(s);
+            if (st) return st;
+        }
+    }
+    double hold = 0.0, zero = 0.0;
+    const int nh = s->ds_n - ntrain;
+    for (int p = ntrain; p < s->ds_n; ++p) {
+        st = load_sample(s, p);
+        if (st) return st;
+        st = forward(s, N, true);
+        if (st) return st;
+        double loss = 0.0;
+        st = loss_and_backward(s, N, &loss);
+        if (st) return st;
+        hold += loss;
+        // zero-increment predictor: mean of the squared normalised target
+        std::vector<float> t(static_cast<size_t>(nfc(s)) * N * N * N);
+        SHIP(hipMemcpy(t.data(), s->target, t.size() * 4, hipMemcpyDeviceToHost));
+        double z = 0.0;
+        for (float x : t) z += static_cast<double>(x) * x;
+        zero += z / t.size();
+    }
+    SHIP(hipStreamSynchronize(s->stream));
+    if (rep) {
+        rep->steps = step;
+        rep->first_loss = first;
+        rep->last_epoch_loss = epoch_sum / ntrain;
+        rep->holdout_loss = nh ? hold / nh : 0.0;
+        rep->holdout_zero = nh ? zero / nh : 0.0;
+        rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return CL_OK;
+}
+
+cl_status cl_surrogate_save(const cl_surrogate* cs, const char* path) {
+    cl_surrogate* s = const_cast<cl_surrogate*>(cs);
+    if (!s || !path) return sfail(CL_EINVAL, "NULL argument");
+    std::vector<float> th(s->nparams);
+    cl_status st = cl_surrogate_get_params(s, th.data());
+    if (st) return st;
+    FILE* f = std::fopen(path, "wb");
+    if (!f) return sfail(CL_EINVAL, std::string("cannot open ") + path);
+    const char magic[8] = {'C', 'L', 'S', 'G', '0', '0', '0', '1'};
+    std::fwrite(magic, 1, 8, f);
+    std::fwrite(&s->cfg, sizeof(s->cfg), 1, f);
+    std::fwrite(&s->nparams, sizeof(s->nparams), 1, f);
+    std::fwrite(th.data(), sizeof(float), th.size(), f);
+    const int scaled = s->scaled ? 1 : 0;
+    std::fwrite(&scaled, sizeof(int), 1, f);
+    std::fwrite(s->in_scale, sizeof(double), 4, f);
+    std::fwrite(s->out_scale, sizeof(double), 4, f);
+    std::fwrite(s->ex_mean, sizeof(double), 4, f);
+    std::fwrite(s->ex_std, sizeof(double), 4, f);
+    const bool ok = std::fclose(f) == 0;
+    return ok ? CL_OK : sfail(CL_EINVAL, "write failed");
+}
+
+cl_status cl_surrogate_load(cl_surrogate* s, const char* path) {
+    if (!s || !path) return sfail(CL_EINVAL, "NULL argument");
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return sfail(CL_EINVAL, std::string("cannot open ") + path);
+    char magic[8];
+    cl_surrogate_cfg cfg;
+    int64_t np = 0;
+    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "CLSG0001", 8) == 0 &&
+              std::fread(&cfg, sizeof(cfg), 1, f) == 1 && std::fread(&np, sizeof(np), 1, f) == 1;
+    if (!ok || np != s->nparams || cfg.layers != s->cfg.layers || cfg.n_fields != s->cfg.n_fields ||
+        cfg.extra_inputs != s->cfg.extra_inputs) {
+        std::fclose(f);
+        return sfail(CL_EINVAL, "file does not match this surrogate");
+    }
+    std::vector<float> th(np);
+    int scaled = 0;
+    ok = std::fread(th.data(), sizeof(float), np, f) == static_cast<size_t>(np) &&
+         std::fread(&scaled, sizeof(int), 1, f) == 1 && std::fread(s->in_scale, sizeof(double), 4, f) == 4 &&
+         std::fread(s->out_scale, sizeof(double), 4, f) == 4 && std::fread(s->ex_mean, sizeof(double), 4, f) == 4 &&
+         std::fread(s->ex_std, sizeof(double), 4, f) == 4;
+    std::fclose(f);
+    if (!ok) return sfail(CL_EINVAL, "truncated surrogate file");
+    s->scaled = scaled != 0;
+    s->cfg.jump_steps = cfg.jump_steps;
+    return cl_surrogate_set_params(s, th.data());
+}
+
+cl_status cl_surrogate_advance(cl_lattice* h, cl_surrogate* s, cl_integrator fallback, double dt, int n_jumps,
+                               double threshold, cl_observables* per_jump, cl_surrogate_report* rep) {
+    if (!h || !s) return sfail(CL_EINVAL, "NULL argument");
+    if (h->nf != s->cfg.n_fields) return sfail(CL_EINVAL, "lattice fields do not match the surrogate");
+    if (!valid_net_N(h->N)) return sfail(CL_EINVAL, "lattice N must be a power of two >= 16");
+    if (!s->scaled) return sfail(CL_ESTATE, "surrogate has no normalisation (train or load it first)");
+    if (!(dt > 0.0) || n_jumps < 0) return sfail(CL_EINVAL, "dt > 0 and n_jumps >= 0 needed");
+    const auto t0 = std::chrono::steady_clock::now();
+    const int N = h->N, K = s->cfg.jump_steps;
+    cl_status st = ensure_bufs(s, N, false);
+    if (st) return st;
+    const size_t bytes = static_cast<size_t>(2 * h->nf) * N * N * N * (h->prec == CL_FP32 ? 4 : 8);
+    if (s->snap_bytes < bytes) {
+        if (s->snap) hipFree(s->snap);
+        s->snap = nullptr;
+        s->snap_bytes = 0;
+        SHIP(hipMalloc(&s->snap, bytes));
+        s->snap_bytes = bytes;
+    }
+    int fallbacks = 0;
+    double maxr = 0.0;
+    for (int j = 0; j < n_jumps; ++j) {
+        cl_observables o;
+        cl::Scal sc;
+        st = read_lattice(h, &o, &sc);
+        if (st) return st;
+        cl_scalars bg;
+        cl_get_state(h, &bg);
+        SHIP(hipMemcpyAsync(s->snap, h->buf[h->cur], bytes, hipMemcpyDeviceToDevice, h->stream));
+        // network input from the current state
+        cl::sg::PackArgs pa{};
+        pa.state = h->buf[h->cur];
+        pa.N = N;
+        pa.nf = h->nf;
+        double e[4];
+        raw_extra(o, sc, e);
+        for (int jf = 0; jf < h->nf; ++jf) {
+            pa.mean[jf] = o.mean[jf];
+            pa.mean[h->nf + jf] = sc.mean_p[jf];
+        }
+        for (int c = 0; c < 2 * h->nf; ++c) pa.inv_scale[c] = 1.0 / s->in_scale[c];
+        pa.nextra = s->cfg.extra_inputs;
+        for (int k = 0; k < pa.nextra; ++k) pa.extra[k] = static_cast<float>((e[k] - s->ex_mean[k]) / s->ex_std[k]);
+        pa.x_out = s->x0;
+        SHIP(cl::sg::launch_pack_state(pa, h->prec == CL_FP32, h->stream));
+        SHIP(hipStreamSynchronize(h->stream));
+        st = forward(s, N, false);
+        if (st) return st;
+        SHIP(hipStreamSynchronize(s->stream));
+        // homogeneous modes and background over the jump, in FP64
+        double f[2] = {o.mean[0], o.mean[1]}, pm[2] = {sc.mean_p[0], sc.mean_p[1]}, var[2] = {o.var[0], o.var[1]};
+        double rho_hom_K = 0.0;
+        for (int jf = 0; jf < h->nf; ++jf) rho_hom_K += pm[jf] * pm[jf] / (2.0 * std::pow(o.a, 6.0));
+        const double rho_lat = o.EK[0] + o.EK[1] + o.EG[0] + o.EG[1] + o.EV;
+        const double rho_r0 = std::max(0.0, rho_lat - rho_hom_K - hom_V(h, f, var));
+        double a = bg.a, b = bg.b;
+        const double a_ref = a;
+        advance_homogeneous(h, fallback, dt, K, f, pm, a, b, var, rho_r0, a_ref);
+        cl::sg::UnpackArgs ua{};
+        ua.state = h->buf[h->cur];
+        ua.N = N;
+        ua.nf = h->nf;
+        for (int jf = 0; jf < h->nf; ++jf) {
+            ua.old_mean[jf] = o.mean[jf];
+            ua.old_mean[h->nf + jf] = sc.mean_p[jf];
+            ua.new_mean[jf] = f[jf];
+            ua.new_mean[h->nf + jf] = pm[jf];
+        }
+        for (int c = 0; c < 2 * h->nf; ++c) ua.out_scale[c] = s->out_scale[c];
+        ua.y = s->y;
+        ua.ystride = ystride(s);
+        SHIP(cl::sg::launch_unpack_jump(ua, h->prec == CL_FP32, h->stream));
+        SHIP(hipStreamSynchronize(h->stream));
+        cl_scalars nb{a, b, bg.eta + K * dt, bg.step + K};
+        st = cl_set_state(h, &nb);
+        if (st) return sfail(st, cl_last_error(h));
+        cl_observables after;
+        st = cl_read_observables(h, &after);
+        if (st) return sfail(st, cl_last_error(h));
+        const double r = after.hubble_residual;
+        if (std::isfinite(r)) maxr = std::max(maxr, r);
+        if (!(r <= threshold) || after.nonfinite) {
+            // undo the jump and run the integrator instead
+            SHIP(hipMemcpyAsync(h->buf[h->cur], s->snap, bytes, hipMemcpyDeviceToDevice, h->stream));
+            SHIP(hipStreamSynchronize(h->stream));
+            st = cl_set_state(h, &bg);
+            if (st) return sfail(st, cl_last_error(h));
+            std::vector<cl_observables> recs(K);
+            st = cl_step(h, fallback, dt, K, recs.data());
+            if (st) return sfail(st, cl_last_error(h));
+            after = recs.back();
+            ++fallbacks;
+        }
+        if (per_jump) per_jump[j] = after;
+    }
+    if (rep) {
+        rep->jumps = n_jumps;
+        rep->fallbacks = fallbacks;
+        rep->max_residual = maxr;
+        rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return CL_OK;
+}
+
+}  // extern "C"
