@@ -182,6 +182,145 @@ def batched_run(steps, warmup, solo_steps=100):
             "batched_speedup_vs_solo": (sites * nsteps / sec) / (sites * solo_steps / solo_s), "finite": ok}
 
 
+def _scalar_errors(rec, ref, nf):
+    """Max relative deviation of per-jump volume averages from the reference
+    (a, H, EG, var relative to themselves; EK and EV relative to the total
+    energy density, as they pass through zero)."""
+    rho = ref["EK"][:, :nf].sum(1) + ref["EG"][:, :nf].sum(1) + ref["EV"]
+    out = {}
+    for k in ("a", "H", "EV"):
+        scale = rho if k == "EV" else np.abs(ref[k])
+        out[k] = float(np.max(np.abs(rec[k] - ref[k]) / scale))
+    for k in ("EK", "EG", "var"):
+        for j in range(nf):
+            scale = rho if k == "EK" else np.abs(ref[k][:, j])
+            out[f"{k}{j}"] = float(np.max(np.abs(rec[k][:, j] - ref[k][:, j]) / scale))
+    out["max"] = max(out.values())
+    return out
+
+
+def _field_error(lat, ref_lat):
+    """Norm-wise relative field error max_j ||f_j - f_ref_j||_inf / ||f_ref_j - <f_ref_j>||_inf
+    (fluctuations, since the homogeneous value would hide them)."""
+    f, p = lat.get_fields()
+    fr, pr = ref_lat.get_fields()
+    err = 0.0
+    for x, xr in ((f, fr), (p, pr)):
+        for j in range(x.shape[0]):
+            d = xr[j] - xr[j].mean()
+            err = max(err, float(np.max(np.abs(x[j].astype(np.float64) - xr[j])) / np.max(np.abs(d))))
+    return err
+
+
+def surrogate_run(epochs=4, pairs_per_seed=64, train_seeds=range(2000, 2008), eval_seed=3000, jumps=312,
+                  extra_inputs=4, eval_256=True):
+    """The learned surrogate on the two-field q = 100 workload: training pairs
+    (state, state 16 VV4 steps later) from seeded 128^3 runs (k_IR = 0.5,
+    dt = 0.05 dx), start steps spread over 5000 steps; training with the
+    library's kernels; evaluation on an unseen seed against the FP64 VV4
+    integrator over `jumps` jumps, next to the FP32 integrator forms, with the
+    Hubble-residual fallback at 1e-3."""
+    import torch
+    from paper_2607_24978_amd import _lib
+    K = 16
+    wt = W.C1.with_(N=128, precision="fp64")
+    out = {"train_N": wt.N, "k_ir": wt.k_ir, "dt": wt.dt, "jump_steps": K, "extra_inputs": extra_inputs}
+    s = _lib.Surrogate(n_fields=2, extra_inputs=extra_inputs, layers=5, jump_steps=K, init_seed=0)
+    seeds = list(train_seeds)
+    s.dataset_reserve(wt.N, len(seeds) * pairs_per_seed)
+    t0 = time.perf_counter()
+    gap = (5000 - K) // pairs_per_seed   # start steps 0, gap, 2 gap, ... within the 5000-step run
+    for seed in seeds:
+        w = wt.with_(seed=seed)
+        lat = _lib.Lattice(w.N, w.dx, 2, "fp64")
+        lat.set_background(w.alpha, w.expansion, w.mp, w.a0)
+        lat.set_potential(w.m2, w.lam, w.g2, w.V0)
+        lat.seed(w.seed, w.fbar[:2], w.pbar[:2], w.cutoff_modes, w.amp)
+        for i in range(pairs_per_seed):
+            if i and gap > K:
+                lat.step("vv4", w.dt, gap - K, record=False)
+            s.record_input(lat)
+            lat.step("vv4", w.dt, K, record=False)
+            s.record_target(lat)
+        lat.close()
+    torch.cuda.synchronize()
+    out["pairs"] = s.dataset_size()
+    out["datagen_s"] = time.perf_counter() - t0
+    rep = s.train(epochs=epochs, lr=1e-3, lr_final=1e-5, shuffle_seed=0, holdout=pairs_per_seed // 2)
+    out["train"] = rep
+    out["train_steps_per_s"] = rep["steps"] / rep["seconds"]
+
+    def evaluate(N, k_ir, njumps):
+        w = W.C1.with_(N=N, k_ir=k_ir, seed=eval_seed)
+
+        def lattice(prec):
+            lat = _lib.Lattice(w.N, w.dx, 2, prec)
+            lat.set_background(w.alpha, w.expansion, w.mp, w.a0)
+            lat.set_potential(w.m2, w.lam, w.g2, w.V0)
+            lat.seed(w.seed, w.fbar[:2], w.pbar[:2], w.cutoff_modes, w.amp)
+            return lat
+
+        res = {"N": N, "k_ir": k_ir, "dx": w.dx, "jumps": njumps, "steps": njumps * K}
+        # every form makes one untimed jump first (graph capture, buffers), then njumps timed ones
+        ref = lattice("fp64")
+        rr = np.concatenate([ref.step("vv4", w.dt, K)[-1:] for _ in range(njumps + 1)])[1:]
+        forms = {}
+        for name, prec, integ, mult in (("fp32_vv4", "fp32", "vv4", 1), ("fp64_vv4", "fp64", "vv4", 1),
+                                        ("fp32_leapfrog", "fp32", "leapfrog", 1),
+                                        ("fp32_leapfrog_dt4", "fp32", "leapfrog", 4),
+                                        ("fp32_leapfrog_dt8", "fp32", "leapfrog", 8)):
+            lat = lattice(prec)
+            n = K // mult
+            lat.step(integ, w.dt * mult, n, record=False)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            recs = np.concatenate([lat.step(integ, w.dt * mult, n)[-1:] for _ in range(njumps)])
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t1
+            e = {"effective_site_updates_per_s": w.sites * njumps * K / sec, "seconds": sec}
+            if name != "fp64_vv4":
+                e["error_vs_fp64_vv4"] = _scalar_errors(recs, rr, 2)["max"]
+                e["field_error"] = _field_error(lat, ref)
+            forms[name] = e
+            lat.close()
+        lat = lattice("fp32")
+        s.advance(lat, "vv4", w.dt, 1, threshold=1e-3)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        recs, srep = s.advance(lat, "vv4", w.dt, njumps, threshold=1e-3)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t1
+        errs = _scalar_errors(recs, rr, 2)
+        forms["surrogate"] = {"effective_site_updates_per_s": w.sites * njumps * K / sec, "seconds": sec,
+                              "fallbacks": srep["fallbacks"], "fallback_rate": srep["fallbacks"] / max(1, njumps),
+                              "max_residual": srep["max_residual"], "error_vs_fp64_vv4": errs["max"],
+                              "errors": errs, "field_error": _field_error(lat, ref)}
+        # the network alone: jumps that never fall back (threshold infinite), errors included
+        lat.close()
+        lat = lattice("fp32")
+        s.advance(lat, "vv4", w.dt, 1, threshold=float("inf"))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        recs, srep = s.advance(lat, "vv4", w.dt, njumps, threshold=float("inf"))
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t1
+        errs = _scalar_errors(recs, rr, 2)
+        forms["surrogate_no_gate"] = {"effective_site_updates_per_s": w.sites * njumps * K / sec, "seconds": sec,
+                                      "max_residual": srep["max_residual"], "error_vs_fp64_vv4": errs["max"],
+                                      "errors": errs, "field_error": _field_error(lat, ref)}
+        lat.close()
+        ref.close()
+        res["forms"] = forms
+        return res
+
+    out["eval"] = [evaluate(128, 0.5, jumps)]
+    if eval_256:
+        out["eval"].append(evaluate(256, 0.25, jumps))        # training dx, larger box
+        out["eval"].append(evaluate(256, 0.5, min(jumps, 40)))  # half the training dx: out of distribution
+    s.close()
+    return out
+
+
 def cpu_baseline(w, steps=1):
     """The FP64 oracle as it stands, on the same 256^3 workload, for a bounded
     number of full steps on the host (numpy, single thread)."""
@@ -211,6 +350,11 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--tile", default=None, help="force the FP32 tile tz,ty,cx,ry,pd instead of autotuning")
+    ap.add_argument("--surrogate", action="store_true", help="also train and evaluate the learned surrogate")
+    ap.add_argument("--sg-epochs", type=int, default=4)
+    ap.add_argument("--sg-pairs", type=int, default=64, help="training pairs per seed (8 seeds)")
+    ap.add_argument("--sg-jumps", type=int, default=312)
+    ap.add_argument("--sg-extra", type=int, default=4, help="broadcast inputs: 4 = (a, H, <phi>, <pi_phi>), 2 = (a, H)")
     ap.add_argument("--workload", choices=["c1", "c3"], default="c1",
                     help="c1: 256^3 two-field VV4 (default); c3: 1024^3 two-field leapfrog")
     args = ap.parse_args()
@@ -266,6 +410,9 @@ def main():
         forms["fp32_speedup_vs_fp64"] = value / forms["fp64"]["site_updates_per_s"]
     if not args.no_batched and args.workload == "c1":
         forms["batched"] = batched_run(1000, 500)
+    if args.surrogate and args.workload == "c1":
+        forms["surrogate"] = surrogate_run(epochs=args.sg_epochs, pairs_per_seed=args.sg_pairs,
+                                           jumps=args.sg_jumps, extra_inputs=args.sg_extra)
     line["forms"] = forms
     if not args.no_cpu:
         # the oracle on the 256^3 workload (the 1024^3 one does not fit a numpy run of ~30 s)

@@ -109,10 +109,16 @@ cl_status cl_surrogate_save(const cl_surrogate* s, const char* path);
 cl_status cl_surrogate_load(cl_surrogate* s, const char* path);
 
 /* Advance the lattice by n_jumps applications of the network, each standing
- * for jump_steps steps of size dt.  After a jump, if the Hubble-constraint
- * residual exceeds `threshold` (or any sum is non-finite) the jump is undone
- * and the integrator `fallback` runs jump_steps steps instead.  per_jump
- * (nullable) receives one record per jump. */
+ * for jump_steps steps of size dt.  One jump: snapshot the state; the network
+ * predicts the fluctuation increment; the homogeneous modes and (a, a') are
+ * advanced by the FP64 equations of motion over the jump (predictor, with the
+ * fluctuations' energy redshifting as radiation); then (a, a') are
+ * re-integrated with the volume sums <pi^2>, <(grad f)^2>, <V> interpolated
+ * linearly between the start and the predicted endpoint (corrector; the sums
+ * do not depend on a, so one pass is converged).  If the Hubble-constraint
+ * residual at the endpoint exceeds `threshold` (or any sum is non-finite) the
+ * jump is undone and the integrator `fallback` runs jump_steps steps instead.
+ * per_jump (nullable) receives one record per jump. */
 cl_status cl_surrogate_advance(cl_lattice* h, cl_surrogate* s, cl_integrator fallback, double dt, int n_jumps,
                                double threshold, cl_observables* per_jump, cl_surrogate_report* rep);
 

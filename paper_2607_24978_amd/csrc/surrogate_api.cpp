@@ -365,6 +365,49 @@ void advance_homogeneous(const cl_lattice* h, cl_integrator integ, double dt, in
     }
 }
 
+// Corrector for the background over a jump: (a, b) re-integrated with the
+// integrator's sub-step pattern while the a-independent volume sums
+// S = (<pi^2>/2, <(grad f)^2>/2, <V>) move linearly in time from their values
+// at the start (S0) to those of the predicted endpoint (S1); rho and p follow
+// from S at each kick (K = S_K/a^6, G = S_G/a^2; Eqs. Friedmann1, rhoLocal).
+void correct_background(const cl_lattice* h, cl_integrator integ, double dt, int n, const double* S0,
+                        const double* S1, double& a, double& b) {
+    if (h->mode != CL_SELF_CONSISTENT) return;
+    const double al = h->alpha, mp = h->mp, T = dt * n;
+    double tau = 0.0;
+    auto accel = [&](double aa, double t) {
+        const double w = T > 0 ? t / T : 0.0;
+        const double SK = S0[0] + w * (S1[0] - S0[0]), SG = S0[1] + w * (S1[1] - S0[1]),
+                     SV = S0[2] + w * (S1[2] - S0[2]);
+        const double K = SK / std::pow(aa, 6.0), G = SG / (aa * aa);
+        const double rho = K + G + SV, pr = K - G / 3.0 - SV;
+        return std::pow(aa, 2.0 * al + 1.0) * ((2.0 * al - 1.0) * rho - 3.0 * pr) / (6.0 * mp * mp);
+    };
+    auto vv2 = [&](double hh) {
+        b += 0.5 * hh * accel(a, tau);
+        a += hh * b;
+        tau += hh;
+        b += 0.5 * hh * accel(a, tau);
+    };
+    const double w1 = 1.0 / (2.0 - std::cbrt(2.0)), w0 = 1.0 - 2.0 * w1;
+    for (int i = 0; i < n; ++i) {
+        if (integ == CL_VV4) {
+            vv2(w1 * dt);
+            vv2(w0 * dt);
+            vv2(w1 * dt);
+        } else {
+            vv2(dt);
+        }
+    }
+}
+
+// a-independent volume sums of an observation taken at scale factor a.
+void volume_sums(const cl_observables& o, double* S) {
+    S[0] = (o.EK[0] + o.EK[1]) * std::pow(o.a, 6.0);
+    S[1] = (o.EG[0] + o.EG[1]) * o.a * o.a;
+    S[2] = o.EV;
+}
+
 // Raw broadcast features of a lattice state: (a, H, <f_0>, <pi_0>).
 void raw_extra(const cl_observables& o, const cl::Scal& sc, double* e) {
     e[0] = o.a;
@@ -805,11 +848,11 @@ cl_status cl_surrogate_advance(cl_lattice* h, cl_surrogate* s, cl_integrator fal
     }
     int fallbacks = 0;
     double maxr = 0.0;
+    cl_observables o;
+    cl::Scal sc;
+    st = read_lattice(h, &o, &sc);
+    if (st) return st;
     for (int j = 0; j < n_jumps; ++j) {
-        cl_observables o;
-        cl::Scal sc;
-        st = read_lattice(h, &o, &sc);
-        if (st) return st;
         cl_scalars bg;
         cl_get_state(h, &bg);
         SHIP(hipMemcpyAsync(s->snap, h->buf[h->cur], bytes, hipMemcpyDeviceToDevice, h->stream));
@@ -833,15 +876,14 @@ cl_status cl_surrogate_advance(cl_lattice* h, cl_surrogate* s, cl_integrator fal
         st = forward(s, N, false);
         if (st) return st;
         SHIP(hipStreamSynchronize(s->stream));
-        // homogeneous modes and background over the jump, in FP64
+        // predictor: homogeneous modes and background over the jump, in FP64
         double f[2] = {o.mean[0], o.mean[1]}, pm[2] = {sc.mean_p[0], sc.mean_p[1]}, var[2] = {o.var[0], o.var[1]};
         double rho_hom_K = 0.0;
         for (int jf = 0; jf < h->nf; ++jf) rho_hom_K += pm[jf] * pm[jf] / (2.0 * std::pow(o.a, 6.0));
         const double rho_lat = o.EK[0] + o.EK[1] + o.EG[0] + o.EG[1] + o.EV;
         const double rho_r0 = std::max(0.0, rho_lat - rho_hom_K - hom_V(h, f, var));
         double a = bg.a, b = bg.b;
-        const double a_ref = a;
-        advance_homogeneous(h, fallback, dt, K, f, pm, a, b, var, rho_r0, a_ref);
+        advance_homogeneous(h, fallback, dt, K, f, pm, a, b, var, rho_r0, bg.a);
         cl::sg::UnpackArgs ua{};
         ua.state = h->buf[h->cur];
         ua.N = N;
@@ -857,15 +899,31 @@ cl_status cl_surrogate_advance(cl_lattice* h, cl_surrogate* s, cl_integrator fal
         ua.ystride = ystride(s);
         SHIP(cl::sg::launch_unpack_jump(ua, h->prec == CL_FP32, h->stream));
         SHIP(hipStreamSynchronize(h->stream));
-        cl_scalars nb{a, b, bg.eta + K * dt, bg.step + K};
-        st = cl_set_state(h, &nb);
+        const cl_scalars pred{a, b, bg.eta + K * dt, bg.step + K};
+        st = cl_set_state(h, &pred);
         if (st) return sfail(st, cl_last_error(h));
         cl_observables after;
-        st = cl_read_observables(h, &after);
-        if (st) return sfail(st, cl_last_error(h));
+        cl::Scal sca;
+        st = read_lattice(h, &after, &sca);
+        if (st) return st;
+        bool ok = !after.nonfinite;
+        if (ok && h->mode == CL_SELF_CONSISTENT) {
+            // corrector: background re-integrated against the start and endpoint sums
+            double S0[3], S1[3];
+            volume_sums(o, S0);
+            volume_sums(after, S1);
+            a = bg.a;
+            b = bg.b;
+            correct_background(h, fallback, dt, K, S0, S1, a, b);
+            const cl_scalars corr{a, b, bg.eta + K * dt, bg.step + K};
+            st = cl_set_state(h, &corr);
+            if (st) return sfail(st, cl_last_error(h));
+            st = read_lattice(h, &after, &sca);
+            if (st) return st;
+        }
         const double r = after.hubble_residual;
         if (std::isfinite(r)) maxr = std::max(maxr, r);
-        if (!(r <= threshold) || after.nonfinite) {
+        if (!ok || !(r <= threshold) || after.nonfinite) {
             // undo the jump and run the integrator instead
             SHIP(hipMemcpyAsync(h->buf[h->cur], s->snap, bytes, hipMemcpyDeviceToDevice, h->stream));
             SHIP(hipStreamSynchronize(h->stream));
@@ -874,10 +932,15 @@ cl_status cl_surrogate_advance(cl_lattice* h, cl_surrogate* s, cl_integrator fal
             std::vector<cl_observables> recs(K);
             st = cl_step(h, fallback, dt, K, recs.data());
             if (st) return sfail(st, cl_last_error(h));
-            after = recs.back();
             ++fallbacks;
+            st = read_lattice(h, &after, &sca);
+            if (st) return st;
+            if (per_jump) per_jump[j] = recs.back();
+        } else if (per_jump) {
+            per_jump[j] = after;
         }
-        if (per_jump) per_jump[j] = after;
+        o = after;
+        sc = sca;
     }
     if (rep) {
         rep->jumps = n_jumps;

@@ -104,6 +104,23 @@ def test_gradients_match_oracle():
     s.close()
 
 
+def test_training_sizes_rejected():
+    lib = _lib()
+    s = lib.Surrogate(n_fields=2, extra_inputs=4, layers=2)
+    with pytest.raises(lib.CLError):
+        s.dataset_reserve(16, 2)
+    x = np.zeros((s.cin, 16, 16, 16), np.float32)
+    with pytest.raises(lib.CLError):
+        s.loss_grad(x, np.zeros((s.cout, 16, 16, 16), np.float32))
+    with pytest.raises(lib.CLError):
+        s.train(epochs=1)
+    with pytest.raises(lib.CLError):
+        lib.Surrogate(n_fields=2, extra_inputs=6)   # 10 input channels
+    with pytest.raises(lib.CLError):
+        lib.Surrogate(hidden=64)
+    s.close()
+
+
 def seeded(w):
     lat = _lib().Lattice(w.N, w.dx, w.n_fields, w.precision)
     lat.set_background(w.alpha, w.expansion, w.mp, w.a0)
