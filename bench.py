@@ -229,6 +229,18 @@ def surrogate_run(epochs=4, pairs_per_seed=64, train_seeds=range(2000, 2008), ev
     seeds = list(train_seeds)
     s.dataset_reserve(wt.N, len(seeds) * pairs_per_seed)
     t0 = time.perf_counter()
+    tiles = {}
+
+    def tuned(lat, N, prec):
+        """The library's tile search once per lattice size and precision."""
+        if (N, prec) not in tiles:
+            lat.autotune(reps=3)
+            tiles[(N, prec)] = lat.get_tile()
+        else:
+            t = tiles[(N, prec)]
+            lat.set_tile(t["tz"], t["ty"], t["cx"], t["ry"], t["pd"])
+        return lat
+
     gap = (5000 - K) // pairs_per_seed   # start steps 0, gap, 2 gap, ... within the 5000-step run
     for seed in seeds:
         w = wt.with_(seed=seed)
@@ -236,6 +248,7 @@ def surrogate_run(epochs=4, pairs_per_seed=64, train_seeds=range(2000, 2008), ev
         lat.set_background(w.alpha, w.expansion, w.mp, w.a0)
         lat.set_potential(w.m2, w.lam, w.g2, w.V0)
         lat.seed(w.seed, w.fbar[:2], w.pbar[:2], w.cutoff_modes, w.amp)
+        tuned(lat, w.N, "fp64")
         for i in range(pairs_per_seed):
             if i and gap > K:
                 lat.step("vv4", w.dt, gap - K, record=False)
@@ -258,7 +271,7 @@ def surrogate_run(epochs=4, pairs_per_seed=64, train_seeds=range(2000, 2008), ev
             lat.set_background(w.alpha, w.expansion, w.mp, w.a0)
             lat.set_potential(w.m2, w.lam, w.g2, w.V0)
             lat.seed(w.seed, w.fbar[:2], w.pbar[:2], w.cutoff_modes, w.amp)
-            return lat
+            return tuned(lat, N, prec)
 
         res = {"N": N, "k_ir": k_ir, "dx": w.dx, "jumps": njumps, "steps": njumps * K}
         # every form makes one untimed jump first (graph capture, buffers), then njumps timed ones
@@ -295,19 +308,32 @@ def surrogate_run(epochs=4, pairs_per_seed=64, train_seeds=range(2000, 2008), ev
                               "fallbacks": srep["fallbacks"], "fallback_rate": srep["fallbacks"] / max(1, njumps),
                               "max_residual": srep["max_residual"], "error_vs_fp64_vv4": errs["max"],
                               "errors": errs, "field_error": _field_error(lat, ref)}
-        # the network alone: jumps that never fall back (threshold infinite), errors included
+        # the network alone: no residual gate (non-finite jumps still fall back), until the
+        # evolution breaks down
         lat.close()
         lat = lattice("fp32")
         s.advance(lat, "vv4", w.dt, 1, threshold=float("inf"))
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        recs, srep = s.advance(lat, "vv4", w.dt, njumps, threshold=float("inf"))
-        torch.cuda.synchronize()
-        sec = time.perf_counter() - t1
-        errs = _scalar_errors(recs, rr, 2)
-        forms["surrogate_no_gate"] = {"effective_site_updates_per_s": w.sites * njumps * K / sec, "seconds": sec,
-                                      "max_residual": srep["max_residual"], "error_vs_fp64_vv4": errs["max"],
-                                      "errors": errs, "field_error": _field_error(lat, ref)}
+        done, chunks, sec, fb, maxr = 0, [], 0.0, 0, 0.0
+        while done < njumps:
+            n = min(10, njumps - done)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            try:
+                recs, srep = s.advance(lat, "vv4", w.dt, n, threshold=float("inf"))
+            except _lib.CLError:
+                break
+            torch.cuda.synchronize()
+            sec += time.perf_counter() - t1
+            chunks.append(recs)
+            fb += srep["fallbacks"]
+            maxr = max(maxr, srep["max_residual"])
+            done += n
+        e = {"jumps_completed": done, "fallbacks_nonfinite": fb, "max_residual": maxr}
+        if done:
+            e["effective_site_updates_per_s"] = w.sites * done * K / sec
+            e["errors"] = _scalar_errors(np.concatenate(chunks), rr[:done], 2)
+            e["error_vs_fp64_vv4"] = e["errors"]["max"]
+        forms["surrogate_no_gate"] = e
         lat.close()
         ref.close()
         res["forms"] = forms

@@ -179,7 +179,8 @@ cl_status cl_read_observables(cl_lattice* h, cl_observables* out);
 /* Work decomposition of the lattice passes: each workgroup owns a tz x ty
  * tile of (z, y) and marches over cx x-planes; ry is the number of y rows per
  * thread (1 or 2) and pd the number of x-planes whose loads are kept in
- * flight ahead of the plane being computed (1 or 2; 0 selects 1).  tz, ty, cx
+ * flight ahead of the plane being computed (1, 2, or 4 with ry = 1; 0 selects
+ * 1).  tz, ty, cx
  * must divide N; tz is a multiple of 4 (FP32) or 2 (FP64) with at most 256
  * threads per workgroup.  An invalid tile returns CL_EINVAL and leaves the
  * current one in place. */

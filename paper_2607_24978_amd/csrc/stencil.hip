@@ -92,9 +92,11 @@ __device__ __forceinline__ void site_dV(const T (&f)[NF], const T (&m2)[2], cons
 }
 
 // Last workgroup of a pass: observables and the scale-factor kick/drift.
-// `tot` holds the lattice sums.  Runs on one thread.
+// `tot` holds the lattice sums.  Called by all 64 lanes of one wave: the
+// powers of a are evaluated on separate lanes, lane 0 writes the results.
 __device__ void finish_pass(const Phys& P, Scal* sc, double kt, double kb, double h_next, cl_observables* rec_out,
                             const double* tot) {
+    const int lane = threadIdx.x & 63;
     const int nf = P.nf;
     const double a = sc->a_next;  // scale factor of the state just produced
     const double a2 = a * a;
@@ -120,15 +122,27 @@ __device__ void finish_pass(const Phys& P, Scal* sc, double kt, double kb, doubl
     const double pr = K - G / 3.0 - EV;
     double acc = 0.0, r = 0.0;
     const double b_half = sc->b;
+    // lane 0: a^(2 alpha + 1), lane 1: a^(2 alpha)
+    const double pw1 = (P.expand && lane < 2) ? pow(a, lane == 0 ? 2.0 * P.alpha + 1.0 : 2.0 * P.alpha) : 0.0;
+    const double a_2al1 = __shfl(pw1, 0, 64), a_2al = __shfl(pw1, 1, 64);
     if (P.expand) {
-        acc = pow(a, 2.0 * P.alpha + 1.0) * ((2.0 * P.alpha - 1.0) * rho - 3.0 * pr) / (6.0 * P.mp * P.mp);
+        acc = a_2al1 * ((2.0 * P.alpha - 1.0) * rho - 3.0 * pr) / (6.0 * P.mp * P.mp);
     }
     const double bs = b_half + kb * acc;
     if (P.expand) {
-        const double rhs = pow(a, 2.0 * P.alpha) * rho / (3.0 * P.mp * P.mp);
+        const double rhs = a_2al * rho / (3.0 * P.mp * P.mp);
         const double H = bs / a;
         r = fabs(H * H - rhs) / rhs;
     }
+    const double b_new = b_half + kt * acc;
+    const double an = (h_next != 0.0 && P.expand) ? a + h_next * b_new : a;
+    const double abar = 0.5 * (a + an);
+    // lane 0: abar^(alpha - 3), lane 1: an^(1 + alpha), lane 2: an^(3 + alpha)
+    const double pw2 = (h_next != 0.0 && lane < 3)
+                           ? pow(lane == 0 ? abar : an, lane == 0 ? P.alpha - 3.0 : (lane == 1 ? 1.0 : 3.0) + P.alpha)
+                           : 0.0;
+    const double abar_al3 = __shfl(pw2, 0, 64), an_1al = __shfl(pw2, 1, 64), an_3al = __shfl(pw2, 2, 64);
+    if (lane != 0) return;
     if (rec_out) {
         cl_observables o;
         o.eta = sc->eta;
@@ -146,7 +160,6 @@ __device__ void finish_pass(const Phys& P, Scal* sc, double kt, double kb, doubl
         o.reserved = 0;
         *rec_out = o;
     }
-    const double b_new = b_half + kt * acc;
     sc->a = a;
     sc->b = b_new;
     sc->nonfinite |= bad;
@@ -155,11 +168,9 @@ __device__ void finish_pass(const Phys& P, Scal* sc, double kt, double kb, doubl
         sc->mean_p[j] = meanp[j];
     }
     if (h_next != 0.0) {
-        const double an = P.expand ? a + h_next * b_new : a;
-        const double abar = 0.5 * (a + an);
-        sc->cd = h_next * pow(abar, P.alpha - 3.0);
-        sc->kL = pow(an, 1.0 + P.alpha) / (P.dx * P.dx);
-        sc->kV = pow(an, 3.0 + P.alpha);
+        sc->cd = h_next * abar_al3;
+        sc->kL = an_1al / (P.dx * P.dx);
+        sc->kV = an_3al;
         sc->a_next = an;
         sc->eta += h_next;
         for (int j = 0; j < 2; ++j) sc->shift[j] = mean[j] + sc->cd * meanp[j];
@@ -173,28 +184,36 @@ __device__ void finish_pass(const Phys& P, Scal* sc, double kt, double kb, doubl
 // Block-wide reduction of NS per-thread FP64 sums into partial slot `slot`
 // of `nslots`, then a ticket; the last workgroup to arrive sums all slots in
 // a fixed order (thread t takes slots t, t+NT, ... with Neumaier
-// compensation, then a pairwise tree over threads), leaves the totals in
-// `tot` (shared memory) and returns true.  Deterministic for a fixed
-// nslots and NT.  Resets the ticket for the next pass.
+// compensation, all NS sums at once so that their loads overlap, then a
+// butterfly over the lanes of each wave and the waves in order), leaves the
+// totals in `tot` (shared memory) and returns true.  Deterministic for a
+// fixed nslots and NT.  Resets the ticket for the next pass.
 template <int NS>
 __device__ bool reduce_partials(double (&acc)[NS], int NT, double* partials, int slot, int nslots, unsigned* ticket,
                                 double* tot) {
     __shared__ double wsum[4][kMaxSums];
-    __shared__ double tree[256];
     __shared__ int am_last;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
+    const int nw = (NT + 63) / 64;
+    // butterfly over the lanes, level by level so that the NS exchanges of one
+    // level are in flight together (levels at or above NT are skipped: tiny
+    // lattices run workgroups of fewer than 64 threads)
+    double v[NS];
 #pragma unroll
-    for (int k = 0; k < NS; ++k) {
-        double v = acc[k];
-        for (int off = 32; off > 0; off >>= 1)
-            if (off < NT) v += __shfl_xor(v, off, 64);
-        if (lane == 0) wsum[wave][k] = v;
+    for (int k = 0; k < NS; ++k) v[k] = acc[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        if (off >= NT) continue;
+#pragma unroll
+        for (int k = 0; k < NS; ++k) v[k] += __shfl_xor(v[k], off, 64);
     }
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NS; ++k) wsum[wave][k] = v[k];
     __syncthreads();
     if (tid == 0) {
-        const int nw = (NT + 63) / 64;
         for (int k = 0; k < NS; ++k) {
             double s = wsum[0][k];
             for (int w = 1; w < nw; ++w) s += wsum[w][k];
@@ -206,25 +225,41 @@ __device__ bool reduce_partials(double (&acc)[NS], int NT, double* partials, int
     __syncthreads();
     if (!am_last) return false;
     __atomic_thread_fence(__ATOMIC_ACQUIRE);
-    for (int k = 0; k < NS; ++k) {
-        double s = 0.0, c = 0.0;
-        const double* src = partials + (size_t)k * nslots;
-        for (int i = tid; i < nslots; i += NT) {
-            const double x = src[i];
-            const double t = s + x;
-            c += (fabs(s) >= fabs(x)) ? (s - t) + x : (x - t) + s;
-            s = t;
+    double s[NS], c[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) s[k] = c[k] = 0.0;
+    for (int i = tid; i < nslots; i += NT) {
+        double x[NS];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) x[k] = partials[(size_t)k * nslots + i];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            const double t = s[k] + x[k];
+            c[k] += (fabs(s[k]) >= fabs(x[k])) ? (s[k] - t) + x[k] : (x[k] - t) + s[k];
+            s[k] = t;
         }
-        tree[tid] = s + c;
-        __syncthreads();
-        for (int w = NT / 2; w > 0; w >>= 1) {
-            if (tid < w) tree[tid] += tree[tid + w];
-            __syncthreads();
-        }
-        if (tid == 0) tot[k] = tree[0];
-        __syncthreads();
     }
-    if (tid == 0) *ticket = 0u;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) v[k] = s[k] + c[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        if (off >= NT) continue;
+#pragma unroll
+        for (int k = 0; k < NS; ++k) v[k] += __shfl_xor(v[k], off, 64);
+    }
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NS; ++k) wsum[wave][k] = v[k];
+    __syncthreads();
+    if (tid == 0) {
+        for (int k = 0; k < NS; ++k) {
+            double t = wsum[0][k];
+            for (int w = 1; w < nw; ++w) t += wsum[w][k];
+            tot[k] = t;
+        }
+        *ticket = 0u;
+    }
+    __syncthreads();
     return true;
 }
 
@@ -241,6 +276,15 @@ struct TileJob {
     const Scal* sc;
     const Phys* ph;
 };
+
+// Calls f(integral_constant<int, B>), ..., f(integral_constant<int, E - 1>).
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
 
 template <typename T, int NF, int RY, int HI, int PD>
 __device__ void march_tile(const TileJob& J, unsigned char* smem_raw, double (&acc)[kSumsPerField * NF + 1]) {
@@ -401,7 +445,6 @@ __device__ void march_tile(const TileJob& J, unsigned char* smem_raw, double (&a
 
 
     using S0 = std::integral_constant<int, 0>;
-    using S1 = std::integral_constant<int, PD - 1>;
     // Prologue: plane x0-1 (own only), plane x0 (own + halo into buffer 0),
     // then the loads of planes x0+1 .. x0+PD stay in flight into the loop.
     issue(S0{}, -1);
@@ -409,9 +452,10 @@ __device__ void march_tile(const TileJob& J, unsigned char* smem_raw, double (&a
     issue(S0{}, 0);
     consume(S0{}, cur, pc, 0);
     issue(S0{}, 1);
-    if constexpr (PD == 2) {
-        if (2 <= CX) issue(S1{}, 2);
-    }
+    static_for<1, PD>([&](auto Sc) {
+        constexpr int s_ = decltype(Sc)::value;
+        if (1 + s_ <= CX) issue(Sc, 1 + s_);
+    });
     __syncthreads();
 
     // One x-plane: plane x+1 arrives from set S (drift, stage), the loads of
@@ -508,10 +552,10 @@ __device__ void march_tile(const TileJob& J, unsigned char* smem_raw, double (&a
                 }
     };
     for (int i = 0; i < CX; i += PD) {
-        body(S0{}, i);
-        if constexpr (PD == 2) {
-            if (i + 1 < CX) body(S1{}, i + 1);
-        }
+        static_for<0, PD>([&](auto Sc) {
+            constexpr int s_ = decltype(Sc)::value;
+            if (i + s_ < CX) body(Sc, i + s_);
+        });
     }
 }
 
@@ -552,7 +596,7 @@ __global__ __launch_bounds__(256) void lattice_pass(PassArgs A) {
     march_tile<T, NF, RY, HI, PD>(J, smem_raw, acc);
     const int NT = (A.TZ / VecOf<T>::V) * (A.TY / RY);
     __shared__ double tot[kMaxSums];
-    if (reduce_partials<NS>(acc, NT, A.partials, bid, nblocks, A.ticket, tot) && threadIdx.x == 0)
+    if (reduce_partials<NS>(acc, NT, A.partials, bid, nblocks, A.ticket, tot) && threadIdx.x < 64)
         finish_pass(A.ph, A.sc, A.kt, A.kb, A.h_next, A.rec >= 0 ? A.obs + A.rec : nullptr, tot);
 }
 
@@ -635,7 +679,8 @@ bool finalize_tile(Tile& t, int N, cl_precision prec) {
     t.NT = BZ * RL;
     if (t.NT > 256 || !is_pow2(t.NT) || !is_pow2(BZ)) return false;
     if (t.RY != 1 && t.RY != 2) return false;
-    if (t.PD != 1 && t.PD != 2) return false;
+    if (t.PD != 1 && t.PD != 2 && t.PD != 4) return false;
+    if (t.PD == 4 && t.RY != 1) return false;  // the deep ring is built for one row per thread
     const int nhalo = 2 * BZ + 2 * t.TY;
     t.HI = (nhalo + t.NT - 1) / t.NT;
     if (t.HI > 2) return false;
@@ -706,7 +751,7 @@ __global__ __launch_bounds__(256) void ensemble_pass(EnsArgs E) {
 #pragma unroll
         for (int k = 0; k < NS; ++k) acc[k] = 0.0;
         march_tile<T, NF, 1, 1, 2>(J, smem_raw, acc);
-        if (reduce_partials<NS>(acc, 256, M.partials, I.tile, M.nitems, M.ticket, tot) && threadIdx.x == 0)
+        if (reduce_partials<NS>(acc, 256, M.partials, I.tile, M.nitems, M.ticket, tot) && threadIdx.x < 64)
             finish_pass(M.ph, M.sc, kt, kb, hn, E.rec >= 0 ? E.obs + (size_t)E.rec * E.nmembers + I.member : nullptr,
                         tot);
     }
@@ -766,7 +811,7 @@ void candidate_tiles(int N, cl_precision prec, int nf, Tile* out, int* count, in
                 const int TY = (NT / BZ) * RY;
                 if (TY > N) continue;
                 for (int CX = 2; CX <= N; CX *= 2)
-                    for (int PD : {1, 2}) {
+                    for (int PD : {1, 2, 4}) {
                         if (CX != N && (CX < 4 || CX > 256)) continue;
                         Tile t;
                         t.TZ = TZ;
@@ -791,6 +836,9 @@ static hipError_t launch_t(const PassArgs& a, const Tile& t, hipStream_t s, size
 
 template <typename T, int NF, int RY, int HI>
 static hipError_t launch_pd(const PassArgs& a, const Tile& t, hipStream_t s, size_t lds) {
+    if constexpr (RY == 1) {
+        if (t.PD == 4) return launch_t<T, NF, RY, HI, 4>(a, t, s, lds);
+    }
     return t.PD == 2 ? launch_t<T, NF, RY, HI, 2>(a, t, s, lds) : launch_t<T, NF, RY, HI, 1>(a, t, s, lds);
 }
 

@@ -144,6 +144,176 @@ __global__ __launch_bounds__(256) void conv_fwd(ConvArgs a) {
     }
 }
 
+// Register-blocked forward for 32 input channels and NB 16-wide output blocks
+// (the hidden layers, the last layer, and the input gradient through the
+// hidden layers).  A workgroup takes 4 x-planes
+// (one per wave) x RY y-rows x 16 z-sites; the input block with its halo
+// (6 x (RY+2) x 18 sites x 32 channels) is staged once in LDS.  For each dx
+// the wave holds the 9 (dy, dz) weight fragments of its output blocks in
+// registers, and every input fragment it reads from LDS feeds the
+// three output rows it is a neighbour of.
+template <int RY, int NB>
+__global__ __launch_bounds__(256) void conv32_fwd_tiled(ConvArgs a) {
+    constexpr int ZR = 18, YR = RY + 2, PL = 6;
+    __shared__ __align__(16) uint16_t tin[PL * YR * ZR * 32];
+    const uint16_t* __restrict__ in = reinterpret_cast<const uint16_t*>(a.in);
+    const uint16_t* __restrict__ wg = reinterpret_cast<const uint16_t*>(a.w);
+    const int N = a.N;
+    const int nzt = N / 16, nyt = N / RY;
+    int t = blockIdx.x;
+    const int tz = t % nzt;
+    t /= nzt;
+    const int ty = t % nyt;
+    const int tx = t / nyt;
+    const int x0 = tx * 4, y0 = ty * RY, z0 = tz * 16;
+    constexpr int CHUNKS = PL * YR * ZR * 4;  // 16-byte chunks (8 channels)
+    for (int i = threadIdx.x; i < CHUNKS; i += 256) {
+        const int c4 = i & 3;
+        int r = i >> 2;
+        const int zi = r % ZR;
+        r /= ZR;
+        const int yi = r % YR, pi = r / YR;
+        int xx = x0 - 1 + pi, yy = y0 - 1 + yi, zz = z0 - 1 + zi;
+        xx = xx < 0 ? xx + N : (xx >= N ? xx - N : xx);
+        yy = yy < 0 ? yy + N : (yy >= N ? yy - N : yy);
+        zz = zz < 0 ? zz + N : (zz >= N ? zz - N : zz);
+        const uint4 v = *reinterpret_cast<const uint4*>(in + static_cast<size_t>((xx * N + yy) * N + zz) * 32 + c4 * 8);
+        *reinterpret_cast<uint4*>(tin + static_cast<size_t>(i) * 8) = v;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int n = lane & 15, g = lane >> 4;
+    f32x4 acc[RY][NB];
+#pragma unroll
+    for (int r = 0; r < RY; ++r)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[r][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx) {
+        bf16x8 wa[9][NB];
+#pragma unroll
+        for (int j = 0; j < 9; ++j)
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+                wa[j][b] = load8(wg + static_cast<size_t>((dx * 9 + j) * NB * 16 + 16 * b + n) * 32 + 8 * g);
+        const uint16_t* pl = tin + (w + dx) * YR * ZR * 32;
+#pragma unroll
+        for (int yi = 0; yi < YR; ++yi)
+#pragma unroll
+            for (int dz = 0; dz < 3; ++dz) {
+                const bf16x8 xb = load8(pl + (yi * ZR + n + dz) * 32 + 8 * g);
+#pragma unroll
+                for (int dy = 0; dy < 3; ++dy) {
+                    const int r = yi - dy;  // output row fed by input row yi at this dy
+                    if (r < 0 || r >= RY) continue;
+#pragma unroll
+                    for (int b = 0; b < NB; ++b)
+                        acc[r][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[dy * 3 + dz][b], xb, acc[r][b], 0, 0, 0);
+                }
+            }
+    }
+    const int x = x0 + w;
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        const size_t site = static_cast<size_t>((x * N + y0 + r) * N + z0 + n);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int c0 = 16 * b + 4 * g;
+            if (c0 >= a.cout) continue;
+            float v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] = acc[r][b][q] + (a.bias ? a.bias[c0 + q] : 0.f);
+            if (a.z_out) *reinterpret_cast<float4*>(a.z_out + site * a.z_stride + c0) = make_float4(v[0], v[1], v[2], v[3]);
+            if (a.a_out) {
+                uint16_t h[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) h[q] = f2bf(a.gelu ? gelu(v[q]) : v[q]);
+                uint2 pk;
+                pk.x = static_cast<uint32_t>(h[0]) | (static_cast<uint32_t>(h[1]) << 16);
+                pk.y = static_cast<uint32_t>(h[2]) | (static_cast<uint32_t>(h[3]) << 16);
+                *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(a.a_out) + site * a.a_stride + c0) = pk;
+            }
+        }
+    }
+}
+
+// The same blocking for 8 input channels and 32 outputs (the first layer, and
+// the input gradient through the last one): one K = 32 step packs the
+// 8 channels of 4 stencil offsets, lane group g taking offset 4s + g, so the
+// whole weight set (7 steps x 2 output blocks) stays in registers.
+template <int RY>
+__global__ __launch_bounds__(256) void conv8_fwd_tiled(ConvArgs a) {
+    constexpr int ZR = 18, YR = RY + 2, PL = 6, KS = 7;
+    __shared__ __align__(16) uint16_t tin[PL * YR * ZR * 8];
+    const uint16_t* __restrict__ in = reinterpret_cast<const uint16_t*>(a.in);
+    const uint16_t* __restrict__ wg = reinterpret_cast<const uint16_t*>(a.w);
+    const int N = a.N;
+    const int nzt = N / 16, nyt = N / RY;
+    int t = blockIdx.x;
+    const int tz = t % nzt;
+    t /= nzt;
+    const int ty = t % nyt;
+    const int tx = t / nyt;
+    const int x0 = tx * 4, y0 = ty * RY, z0 = tz * 16;
+    for (int i = threadIdx.x; i < PL * YR * ZR; i += 256) {
+        const int zi = i % ZR, yi = (i / ZR) % YR, pi = i / (ZR * YR);
+        int xx = x0 - 1 + pi, yy = y0 - 1 + yi, zz = z0 - 1 + zi;
+        xx = xx < 0 ? xx + N : (xx >= N ? xx - N : xx);
+        yy = yy < 0 ? yy + N : (yy >= N ? yy - N : yy);
+        zz = zz < 0 ? zz + N : (zz >= N ? zz - N : zz);
+        *reinterpret_cast<uint4*>(tin + static_cast<size_t>(i) * 8) =
+            *reinterpret_cast<const uint4*>(in + static_cast<size_t>((xx * N + yy) * N + zz) * 8);
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int n = lane & 15, g = lane >> 4;
+    bf16x8 wa[KS][2];
+    int off[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+        const int o = 4 * s + g;  // 27 is the all-zero padding offset
+#pragma unroll
+        for (int b = 0; b < 2; ++b) wa[s][b] = load8(wg + static_cast<size_t>(o * 32 + 16 * b + n) * 8);
+        const int dx = o / 9, dy = (o / 3) % 3, dz = o % 3;
+        off[s] = o < 27 ? (((w + dx) * YR + dy) * ZR + n + dz) * 8 : -1;
+    }
+    __syncthreads();
+    f32x4 acc[RY][2];
+#pragma unroll
+    for (int r = 0; r < RY; ++r)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[r][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int r = 0; r < RY; ++r)
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const bf16x8 xb = off[s] >= 0 ? load8(tin + off[s] + r * ZR * 8) : zero8();
+#pragma unroll
+            for (int b = 0; b < 2; ++b) acc[r][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[s][b], xb, acc[r][b], 0, 0, 0);
+        }
+    const int x = x0 + w;
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        const size_t site = static_cast<size_t>((x * N + y0 + r) * N + z0 + n);
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int c0 = 16 * b + 4 * g;
+            float v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] = acc[r][b][q] + (a.bias ? a.bias[c0 + q] : 0.f);
+            if (a.z_out) *reinterpret_cast<float4*>(a.z_out + site * a.z_stride + c0) = make_float4(v[0], v[1], v[2], v[3]);
+            if (a.a_out) {
+                uint16_t h[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) h[q] = f2bf(a.gelu ? gelu(v[q]) : v[q]);
+                uint2 pk;
+                pk.x = static_cast<uint32_t>(h[0]) | (static_cast<uint32_t>(h[1]) << 16);
+                pk.y = static_cast<uint32_t>(h[2]) | (static_cast<uint32_t>(h[3]) << 16);
+                *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(a.a_out) + site * a.a_stride + c0) = pk;
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------- weight gradient
 // dW[o][co][ci] = sum_n dz[n][co] x[n + o][ci],  db[co] = sum_n dz[n][co].
 // A workgroup takes 32-site row segments; it stages dz^T and x^T (three
@@ -414,7 +584,15 @@ __global__ void unpack_jump(UnpackArgs a) {
 hipError_t launch_conv_fwd(const ConvArgs& a, int cin, int nb, int grid, hipStream_t s) {
     const int no = cin == 32 ? 27 : 28;
     const size_t lds = static_cast<size_t>(no) * nb * 16 * cin * 2;
-    if (cin == 32 && nb == 2) hipLaunchKernelGGL((conv_fwd<32, 2, 4>), dim3(grid), dim3(256), lds, s, a);
+    if (cin == 32 && a.N >= 16 && a.N % 16 == 0 && a.cout <= 16 * nb) {
+        // one workgroup per 4 x 8 x 16 block of output sites
+        const int tiles = (a.N / 4) * (a.N / 8) * (a.N / 16);
+        if (nb == 2) hipLaunchKernelGGL((conv32_fwd_tiled<8, 2>), dim3(tiles), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((conv32_fwd_tiled<8, 1>), dim3(tiles), dim3(256), 0, s, a);
+    } else if (cin == 8 && nb == 2 && a.N >= 16 && a.N % 16 == 0 && a.cout == 32) {
+        const int tiles = (a.N / 4) * (a.N / 8) * (a.N / 16);
+        hipLaunchKernelGGL((conv8_fwd_tiled<8>), dim3(tiles), dim3(256), 0, s, a);
+    } else if (cin == 32 && nb == 2) hipLaunchKernelGGL((conv_fwd<32, 2, 4>), dim3(grid), dim3(256), lds, s, a);
     else if (cin == 32 && nb == 1) hipLaunchKernelGGL((conv_fwd<32, 1, 4>), dim3(grid), dim3(256), lds, s, a);
     else if (cin == 8 && nb == 2) hipLaunchKernelGGL((conv_fwd<8, 2, 4>), dim3(grid), dim3(256), lds, s, a);
     else if (cin == 8 && nb == 1) hipLaunchKernelGGL((conv_fwd<8, 1, 4>), dim3(grid), dim3(256), lds, s, a);

@@ -899,14 +899,18 @@ cl_status cl_surrogate_advance(cl_lattice* h, cl_surrogate* s, cl_integrator fal
         ua.ystride = ystride(s);
         SHIP(cl::sg::launch_unpack_jump(ua, h->prec == CL_FP32, h->stream));
         SHIP(hipStreamSynchronize(h->stream));
-        const cl_scalars pred{a, b, bg.eta + K * dt, bg.step + K};
-        st = cl_set_state(h, &pred);
-        if (st) return sfail(st, cl_last_error(h));
-        cl_observables after;
-        cl::Scal sca;
-        st = read_lattice(h, &after, &sca);
-        if (st) return st;
-        bool ok = !after.nonfinite;
+        // a prediction that leaves the background non-finite or a <= 0 is rejected outright
+        bool ok = std::isfinite(a) && std::isfinite(b) && a > 0.0;
+        cl_observables after{};
+        cl::Scal sca{};
+        if (ok) {
+            const cl_scalars pred{a, b, bg.eta + K * dt, bg.step + K};
+            st = cl_set_state(h, &pred);
+            if (st) return sfail(st, cl_last_error(h));
+            st = read_lattice(h, &after, &sca);
+            if (st) return st;
+            ok = !after.nonfinite;
+        }
         if (ok && h->mode == CL_SELF_CONSISTENT) {
             // corrector: background re-integrated against the start and endpoint sums
             double S0[3], S1[3];
@@ -915,17 +919,21 @@ cl_status cl_surrogate_advance(cl_lattice* h, cl_surrogate* s, cl_integrator fal
             a = bg.a;
             b = bg.b;
             correct_background(h, fallback, dt, K, S0, S1, a, b);
-            const cl_scalars corr{a, b, bg.eta + K * dt, bg.step + K};
-            st = cl_set_state(h, &corr);
-            if (st) return sfail(st, cl_last_error(h));
-            st = read_lattice(h, &after, &sca);
-            if (st) return st;
+            ok = std::isfinite(a) && std::isfinite(b) && a > 0.0;
+            if (ok) {
+                const cl_scalars corr{a, b, bg.eta + K * dt, bg.step + K};
+                st = cl_set_state(h, &corr);
+                if (st) return sfail(st, cl_last_error(h));
+                st = read_lattice(h, &after, &sca);
+                if (st) return st;
+            }
         }
-        const double r = after.hubble_residual;
+        const double r = ok ? after.hubble_residual : std::nan("");
         if (std::isfinite(r)) maxr = std::max(maxr, r);
         if (!ok || !(r <= threshold) || after.nonfinite) {
-            // undo the jump and run the integrator instead
+            // undo the jump (state and scalar block) and run the integrator instead
             SHIP(hipMemcpyAsync(h->buf[h->cur], s->snap, bytes, hipMemcpyDeviceToDevice, h->stream));
+            SHIP(hipMemcpyAsync(h->sc, &sc, sizeof(cl::Scal), hipMemcpyHostToDevice, h->stream));
             SHIP(hipStreamSynchronize(h->stream));
             st = cl_set_state(h, &bg);
             if (st) return sfail(st, cl_last_error(h));

@@ -186,8 +186,21 @@ def test_fallback_gate_forced_and_save_load(tmp_path):
     assert recs[-1]["a"] == ref[-1]["a"]
     assert a.get_state() == b.get_state()
     # corrupted weights: huge outputs trip the gate as well
-    s2.set_params(s2.get_params() * 1e3)
+    theta = s2.get_params()
+    s2.set_params(theta * 1e3)
     _, rep = s2.advance(a, "vv4", w.dt, 2, threshold=1e-3)
     assert rep["fallbacks"] == 2
+    for _ in range(2):
+        b.step("vv4", w.dt, 16)
+    # overflowing outputs: non-finite jumps fall back even with no residual threshold
+    s2.set_params(theta * 1e30)
+    _, rep = s2.advance(a, "vv4", w.dt, 2, threshold=float("inf"))
+    assert rep["fallbacks"] == 2
+    for _ in range(2):
+        b.step("vv4", w.dt, 16)
+    fa, pa = a.get_fields()
+    fb, pb = b.get_fields()
+    assert np.all(np.isfinite(fa)) and np.array_equal(fa, fb) and np.array_equal(pa, pb)
+    assert a.get_state() == b.get_state()
     for x in (a, b, s, s2):
         x.close()
