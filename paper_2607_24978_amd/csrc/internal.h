@@ -73,9 +73,19 @@ struct PassArgs {
     double kt;      // kick multiplier for the stored momenta
     double kb;      // kick multiplier for the synchronised momenta (energies)
     double h_next;  // drift step of the following pass, 0: call ends here
-    Scal* sc;
-    double* partials;   // nsums(nf) * nblocks doubles
-    unsigned* ticket;   // zero between passes
+    // Scalar flow.  A pass leaves its per-workgroup sums in `partials`; the
+    // FP64 scalar step that consumes them (Friedmann update, observables,
+    // coefficients of the next pass) runs at the start of the next pass, in
+    // every workgroup alike, or in the closing finisher kernel.
+    const Scal* sc_in;  // scalars before the pending step (or the pass's own, has_prev == 0)
+    Scal* sc_out;       // where workgroup 0 leaves the scalars after the pending step
+    double* partials;   // this pass: nsums(nf) * nblocks doubles
+    const double* prev_partials;  // the previous pass's sums
+    int prev_nslots;    // workgroups of the previous pass
+    int has_prev;       // 1: finish the previous pass first
+    int prev_rec;       // observable slot of the previous pass, -1: none
+    int pad_;
+    double pkt, pkb, phn;  // kt, kb, h_next of the previous pass
     cl_observables* obs;
     Phys ph;
 };
@@ -119,6 +129,8 @@ hipError_t launch_ensemble_pass(const EnsArgs& a, cl_precision prec, int nf, int
 size_t ensemble_lds_bytes(cl_precision prec, int nf, int maxTY, int maxTZ);
 int ensemble_grid(cl_precision prec, int nf, size_t lds);
 hipError_t launch_pass(const PassArgs& a, const Tile& t, cl_precision prec, hipStream_t s);
+// One workgroup of t.NT threads: the pending scalar step of the last pass.
+hipError_t launch_finish(const PassArgs& a, const Tile& t, int nf, hipStream_t s);
 hipError_t launch_init_scalars(Scal* sc, double a, double b, double eta, const Phys& ph,
                                const double* shift, hipStream_t s);
 // Default tile for a lattice; valid for every N accepted by cl_create.
@@ -167,9 +179,9 @@ struct cl_lattice {
     int pass_flags = 1;                 // nontemporal stores
     int cur = 0;
     cl::Scal* sc = nullptr;
-    double* partials = nullptr;
-    size_t partials_cap = 0;  // doubles
-    unsigned* ticket = nullptr;
+    double* partials = nullptr;  // two halves, used by alternate passes
+    size_t partials_cap = 0;     // doubles (both halves)
+    cl::Scal* scb = nullptr;     // two scratch scalar blocks for the passes inside a call
     cl_observables* obs = nullptr;
     int obs_cap = 0;
     cl::Tile tile;

@@ -78,9 +78,11 @@ bool valid_N(int N, cl_precision prec) {
     return pow2 || (N % big == 0);
 }
 
+// Two halves of nsums * nblocks doubles: consecutive passes alternate, as a
+// pass reads the sums of the one before while writing its own.
 cl_status ensure_partials(cl_lattice* h, int nblocks = 0) {
     if (nblocks <= 0) nblocks = h->tile.nblocks();
-    const size_t need = static_cast<size_t>(cl::nsums(h->nf)) * nblocks;
+    const size_t need = 2 * static_cast<size_t>(cl::nsums(h->nf)) * nblocks;
     if (need <= h->partials_cap) return CL_OK;
     if (h->partials) hipFree(h->partials);
     h->partials = nullptr;
@@ -116,14 +118,61 @@ PassArgs base_args(cl_lattice* h, int in) {
     a.nbz = h->tile.nbz;
     a.nby = h->tile.nby;
     a.nbx = h->tile.nbx;
-    a.sc = h->sc;
+    a.sc_in = h->sc;
+    a.sc_out = nullptr;
     a.partials = h->partials;
-    a.ticket = h->ticket;
+    a.prev_partials = nullptr;
+    a.has_prev = 0;
+    a.prev_rec = -1;
     a.obs = h->obs;
     a.ph = make_phys(h);
     a.rec = -1;
     return a;
 }
+
+// A sequence of passes on the handle's stream.  Each pass runs the scalar
+// step of the one before it at its start; close() launches the step of the
+// last one, which leaves the scalars in h->sc.  Inside the sequence the
+// scalars travel through the two scratch blocks h->scb.
+struct PassSeq {
+    cl_lattice* h;
+    int p = 0;
+    PassArgs prev{};
+    explicit PassSeq(cl_lattice* hh) : h(hh) {}
+    double* part(int q) const { return h->partials + q * (h->partials_cap / 2); }
+    const Scal* scal_before(int q) const { return q == 0 ? h->sc : h->scb + (q & 1); }
+    void chain(PassArgs& a) const {
+        a.has_prev = 1;
+        a.sc_in = scal_before(p - 1);
+        a.prev_partials = part((p - 1) & 1);
+        a.prev_nslots = h->tile.nblocks();
+        a.pkt = prev.kt;
+        a.pkb = prev.kb;
+        a.phn = prev.h_next;
+        a.prev_rec = prev.rec;
+    }
+    hipError_t launch(PassArgs a) {
+        a.partials = part(p & 1);
+        if (p == 0) {
+            a.has_prev = 0;
+            a.sc_in = h->sc;
+        } else {
+            chain(a);
+            a.sc_out = h->scb + (p & 1);
+        }
+        const hipError_t e = cl::launch_pass(a, h->tile, h->prec, h->stream);
+        prev = a;
+        ++p;
+        return e;
+    }
+    hipError_t close() {
+        if (p == 0) return hipSuccess;
+        PassArgs f = prev;
+        chain(f);
+        f.sc_out = h->sc;
+        return cl::launch_finish(f, h->tile, h->nf, h->stream);
+    }
+};
 
 // Sub-step sizes of n full steps.
 void substeps(cl_integrator integ, double dt, int n, std::vector<double>& h, int& per_step) {
@@ -152,6 +201,7 @@ cl_status issue_steps(cl_lattice* h, cl_integrator integ, double dt, int n, int 
     int per = 1;
     substeps(integ, 1.0, n, c, per);
     const int M = static_cast<int>(c.size());
+    PassSeq seq(h);
     // Opening half kick (no drift): pi += h_1/2 F(f, a), a' += h_1/2 a''.
     PassArgs k = base_args(h, cur);
     k.drift = 0;
@@ -159,7 +209,7 @@ cl_status issue_steps(cl_lattice* h, cl_integrator integ, double dt, int n, int 
     k.kt = (0.5 * c[0]) * dt;
     k.kb = 0.0;
     k.h_next = c[0] * dt;
-    HIPCHECK(h, cl::launch_pass(k, h->tile, h->prec, h->stream));
+    HIPCHECK(h, seq.launch(k));
     cur ^= 1;
     for (int s = 0; s < M; ++s) {
         PassArgs d = base_args(h, cur);
@@ -169,9 +219,10 @@ cl_status issue_steps(cl_lattice* h, cl_integrator integ, double dt, int n, int 
         d.kt = (s + 1 < M ? 0.5 * (c[s] + c[s + 1]) : 0.5 * c[s]) * dt;
         d.h_next = s + 1 < M ? c[s + 1] * dt : 0.0;
         d.rec = ((s + 1) % per == 0) ? (s + 1) / per - 1 : -1;
-        HIPCHECK(h, cl::launch_pass(d, h->tile, h->prec, h->stream));
+        HIPCHECK(h, seq.launch(d));
         cur ^= 1;
     }
+    HIPCHECK(h, seq.close());
     return CL_OK;
 }
 
@@ -192,7 +243,9 @@ cl_status reduce_pass(cl_lattice* h, cl_observables* out) {
     r.kb = 0.0;
     r.h_next = 0.0;
     r.rec = 0;
-    HIPCHECK(h, cl::launch_pass(r, h->tile, h->prec, h->stream));
+    PassSeq seq(h);
+    HIPCHECK(h, seq.launch(r));
+    HIPCHECK(h, seq.close());
     HIPCHECK(h, hipMemcpyAsync(out, h->obs, sizeof(cl_observables), hipMemcpyDeviceToHost, h->stream));
     HIPCHECK(h, hipStreamSynchronize(h->stream));
     return CL_OK;
@@ -372,8 +425,7 @@ cl_status cl_create(int N, double dx, int n_fields, cl_precision prec, cl_lattic
     const char* nt = std::getenv("CL_PASS_FLAGS");
     if (nt && nt[0]) h->pass_flags = std::atoi(nt);
     if (hipMalloc(&h->sc, sizeof(Scal)) != hipSuccess) return bail(CL_ENOMEM, "scalar block");
-    if (hipMalloc(&h->ticket, 64) != hipSuccess) return bail(CL_ENOMEM, "ticket");
-    if (hipMemsetAsync(h->ticket, 0, 64, h->stream) != hipSuccess) return bail(CL_EDEVICE, "memset");
+    if (hipMalloc(&h->scb, 2 * sizeof(Scal)) != hipSuccess) return bail(CL_ENOMEM, "scalar blocks");
     h->tile = cl::default_tile(N, prec, n_fields);
     cached_tile(N, n_fields, prec, h->tile);
     if (ensure_partials(h) != CL_OK) return bail(CL_ENOMEM, h->err);
@@ -391,7 +443,7 @@ cl_status cl_destroy(cl_lattice* h) {
     free_buffers(h);
     if (h->sc) hipFree(h->sc);
     if (h->partials) hipFree(h->partials);
-    if (h->ticket) hipFree(h->ticket);
+    if (h->scb) hipFree(h->scb);
     if (h->obs) hipFree(h->obs);
     if (h->own_stream && h->stream) hipStreamDestroy(h->stream);
     delete h;
@@ -632,27 +684,25 @@ cl_status cl_autotune(cl_lattice* h, int reps, char* report, size_t cap) {
     HIPCHECK(h, hipEventCreate(&e1));
     std::string js = "{\"N\":" + std::to_string(h->N) + ",\"nf\":" + std::to_string(h->nf) + ",\"prec\":\"" +
                      prec_name(h->prec) + "\",\"reps\":" + std::to_string(reps) + ",\"candidates\":[";
-    // With a zero drift coefficient and zero kicks a pass copies (f, pi)
-    // exactly, so the timed passes ping-pong between the two state buffers
-    // like a real run (each pass reads what the previous one wrote) and an
-    // even number of them leaves the state bitwise unchanged.
+    // With a zero drift coefficient, zero kicks and no drift step to follow, a
+    // pass copies (f, pi) exactly and its scalar step leaves a, a' and the
+    // (zero) drift coefficient as they are.  So the timed passes chain like a
+    // real run -- each reads what the previous one wrote and runs its scalar
+    // step first -- and an even number of them leaves the state bitwise
+    // unchanged.
     Scal zero_drift = saved;
     zero_drift.cd = 0.0;
     const int pairs = (reps + 1) / 2;
+    const Tile keep = h->tile;
     int best = -1;
     float best_ms = 0.0f;
     for (int i = 0; i < nc; ++i) {
         const Tile& t = cands[i];
+        h->tile = t;
         HIPCHECK(h, hipMemcpyAsync(h->sc, &zero_drift, sizeof(Scal), hipMemcpyHostToDevice, h->stream));
         PassArgs a[2];
         for (int q = 0; q < 2; ++q) {
             a[q] = base_args(h, h->cur ^ q);
-            a[q].TZ = t.TZ;
-            a[q].TY = t.TY;
-            a[q].CX = t.CX;
-            a[q].nbz = t.nbz;
-            a[q].nby = t.nby;
-            a[q].nbx = t.nbx;
             a[q].drift = 1;
             a[q].write_out = 1;
             a[q].kt = 0.0;
@@ -660,15 +710,20 @@ cl_status cl_autotune(cl_lattice* h, int reps, char* report, size_t cap) {
             a[q].h_next = 0.0;
             a[q].rec = -1;
         }
+        PassSeq seq(h);
         // warm-up pair
-        if (cl::launch_pass(a[0], t, h->prec, h->stream) != hipSuccess) continue;
-        if (cl::launch_pass(a[1], t, h->prec, h->stream) != hipSuccess) continue;
+        if (seq.launch(a[0]) != hipSuccess || seq.launch(a[1]) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)seq.close();
+            continue;
+        }
         hipEventRecord(e0, h->stream);
         for (int r = 0; r < pairs; ++r) {
-            cl::launch_pass(a[0], t, h->prec, h->stream);
-            cl::launch_pass(a[1], t, h->prec, h->stream);
+            (void)seq.launch(a[0]);
+            (void)seq.launch(a[1]);
         }
         hipEventRecord(e1, h->stream);
+        HIPCHECK(h, seq.close());
         HIPCHECK(h, hipEventSynchronize(e1));
         float ms = 0.0f;
         hipEventElapsedTime(&ms, e0, e1);
@@ -684,6 +739,7 @@ cl_status cl_autotune(cl_lattice* h, int reps, char* report, size_t cap) {
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
+    h->tile = keep;
     HIPCHECK(h, hipMemcpyAsync(h->sc, &saved, sizeof(Scal), hipMemcpyHostToDevice, h->stream));
     HIPCHECK(h, hipStreamSynchronize(h->stream));
     if (best < 0) return fail(h, CL_EDEVICE, "no candidate tile launched");

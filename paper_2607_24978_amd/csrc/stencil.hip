@@ -94,7 +94,7 @@ __device__ __forceinline__ void site_dV(const T (&f)[NF], const T (&m2)[2], cons
 // Last workgroup of a pass: observables and the scale-factor kick/drift.
 // `tot` holds the lattice sums.  Called by all 64 lanes of one wave: the
 // powers of a are evaluated on separate lanes, lane 0 writes the results.
-__device__ void finish_pass(const Phys& P, Scal* sc, double kt, double kb, double h_next, cl_observables* rec_out,
+__device__ __forceinline__ void finish_pass(const Phys& P, Scal* sc, double kt, double kb, double h_next, cl_observables* rec_out,
                             const double* tot) {
     const int lane = threadIdx.x & 63;
     const int nf = P.nf;
@@ -181,28 +181,27 @@ __device__ void finish_pass(const Phys& P, Scal* sc, double kt, double kb, doubl
     }
 }
 
-// Block-wide reduction of NS per-thread FP64 sums into partial slot `slot`
-// of `nslots`, then a ticket; the last workgroup to arrive sums all slots in
-// a fixed order (thread t takes slots t, t+NT, ... with Neumaier
-// compensation, all NS sums at once so that their loads overlap, then a
-// butterfly over the lanes of each wave and the waves in order), leaves the
-// totals in `tot` (shared memory) and returns true.  Deterministic for a
-// fixed nslots and NT.  Resets the ticket for the next pass.
+// Word-wise copy of the scalar block by the threads of a workgroup (no
+// struct temporaries).
+__device__ __forceinline__ void copy_scal(Scal* dst, const Scal* src, int nthreads) {
+    static_assert(sizeof(Scal) % 8 == 0, "Scal is a whole number of 8-byte words");
+    const unsigned long long* s = reinterpret_cast<const unsigned long long*>(src);
+    unsigned long long* d = reinterpret_cast<unsigned long long*>(dst);
+    for (int i = threadIdx.x; i < static_cast<int>(sizeof(Scal) / 8); i += nthreads) d[i] = s[i];
+}
+
+// Sum over the workgroup of NS per-thread FP64 values: a butterfly over the
+// lanes of each wave, level by level so that the NS exchanges of one level
+// are in flight together (levels at or above NT are skipped: tiny lattices
+// run workgroups of fewer than 64 threads), then the waves in order by
+// thread 0 into out[] (shared memory).  Every thread calls; out[] is valid
+// for all threads on return.  The order depends on NT only.
 template <int NS>
-__device__ bool reduce_partials(double (&acc)[NS], int NT, double* partials, int slot, int nslots, unsigned* ticket,
-                                double* tot) {
+__device__ __forceinline__ void block_sum(double (&v)[NS], int NT, double* out) {
     __shared__ double wsum[4][kMaxSums];
-    __shared__ int am_last;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int nw = (NT + 63) / 64;
-    // butterfly over the lanes, level by level so that the NS exchanges of one
-    // level are in flight together (levels at or above NT are skipped: tiny
-    // lattices run workgroups of fewer than 64 threads)
-    double v[NS];
-#pragma unroll
-    for (int k = 0; k < NS; ++k) v[k] = acc[k];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         if (off >= NT) continue;
@@ -214,21 +213,27 @@ __device__ bool reduce_partials(double (&acc)[NS], int NT, double* partials, int
         for (int k = 0; k < NS; ++k) wsum[wave][k] = v[k];
     __syncthreads();
     if (tid == 0) {
+        const int nw = (NT + 63) / 64;
         for (int k = 0; k < NS; ++k) {
             double s = wsum[0][k];
             for (int w = 1; w < nw; ++w) s += wsum[w][k];
-            partials[(size_t)k * nslots + slot] = s;
+            out[k] = s;
         }
-        const unsigned t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        am_last = (t == (unsigned)(nslots - 1));
     }
     __syncthreads();
-    if (!am_last) return false;
-    __atomic_thread_fence(__ATOMIC_ACQUIRE);
+}
+
+// Totals of NS sums over `nslots` workgroup partials (partials[k * nslots +
+// slot]) in a fixed order: thread t takes slots t, t + NT, ... with Neumaier
+// compensation (all NS sums at once so that their loads overlap), then
+// block_sum.  Deterministic for a fixed nslots and NT.
+template <int NS>
+__device__ __forceinline__ void slots_sum(const double* partials, int NT, int nslots, double* tot) {
     double s[NS], c[NS];
 #pragma unroll
     for (int k = 0; k < NS; ++k) s[k] = c[k] = 0.0;
-    for (int i = tid; i < nslots; i += NT) {
+#pragma unroll 4
+    for (int i = threadIdx.x; i < nslots; i += NT) {
         double x[NS];
 #pragma unroll
         for (int k = 0; k < NS; ++k) x[k] = partials[(size_t)k * nslots + i];
@@ -240,26 +245,30 @@ __device__ bool reduce_partials(double (&acc)[NS], int NT, double* partials, int
         }
     }
 #pragma unroll
-    for (int k = 0; k < NS; ++k) v[k] = s[k] + c[k];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        if (off >= NT) continue;
-#pragma unroll
-        for (int k = 0; k < NS; ++k) v[k] += __shfl_xor(v[k], off, 64);
+    for (int k = 0; k < NS; ++k) s[k] += c[k];
+    block_sum<NS>(s, NT, tot);
+}
+
+// Ticketed form (used by the ensemble kernel, whose members finish inside
+// the persistent launch): the workgroup's sums go to partial slot `slot` of
+// `nslots`, then a ticket; the last workgroup to arrive forms the totals in
+// `tot` with slots_sum and returns true.  Resets the ticket for the next pass.
+template <int NS>
+__device__ __forceinline__ bool reduce_partials(double (&acc)[NS], int NT, double* partials, int slot, int nslots, unsigned* ticket,
+                                double* tot) {
+    __shared__ double part[kMaxSums];
+    __shared__ int am_last;
+    block_sum<NS>(acc, NT, part);
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < NS; ++k) partials[(size_t)k * nslots + slot] = part[k];
+        const unsigned t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        am_last = (t == (unsigned)(nslots - 1));
     }
-    if (lane == 0)
-#pragma unroll
-        for (int k = 0; k < NS; ++k) wsum[wave][k] = v[k];
     __syncthreads();
-    if (tid == 0) {
-        for (int k = 0; k < NS; ++k) {
-            double t = wsum[0][k];
-            for (int w = 1; w < nw; ++w) t += wsum[w][k];
-            tot[k] = t;
-        }
-        *ticket = 0u;
-    }
-    __syncthreads();
+    if (!am_last) return false;
+    __atomic_thread_fence(__ATOMIC_ACQUIRE);
+    slots_sum<NS>(partials, NT, nslots, tot);
+    if (threadIdx.x == 0) *ticket = 0u;
     return true;
 }
 
@@ -286,8 +295,9 @@ __device__ __forceinline__ void static_for(F&& f) {
     }
 }
 
-template <typename T, int NF, int RY, int HI, int PD>
-__device__ void march_tile(const TileJob& J, unsigned char* smem_raw, double (&acc)[kSumsPerField * NF + 1]) {
+template <typename T, int NF, int RY, int HI, int PD, typename Prelude>
+__device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem_raw, double (&acc)[kSumsPerField * NF + 1],
+                           Prelude&& prelude) {
     constexpr int V = VecOf<T>::V;
     constexpr int NS = kSumsPerField * NF + 1;
     const int N = J.N, TZ = J.TZ, TY = J.TY, CX = J.CX;
@@ -314,16 +324,12 @@ __device__ void march_tile(const TileJob& J, unsigned char* smem_raw, double (&a
     const bool nt_store = J.flags & 1;
     const bool nt_load = J.flags & 2;
 
-    const Scal* sc = J.sc;
-    const T cd = J.drift ? static_cast<T>(sc->cd) : T(0);
-    const T kL = static_cast<T>(sc->kL);
-    const T kV = static_cast<T>(sc->kV);
+    // Pass coefficients; set once the prelude has produced the scalars.
+    T cd = T(0), kL = T(0), kV = T(0);
     const T kt = static_cast<T>(J.kt);
     const T kb = static_cast<T>(J.kb);
     // Variance shift in the field precision: f - c is exact for f near c.
     T shift[NF];
-#pragma unroll
-    for (int j = 0; j < NF; ++j) shift[j] = static_cast<T>(sc->shift[j]);
     const T m2[2] = {static_cast<T>(J.ph->m2[0]), static_cast<T>(J.ph->m2[1])};
     const T lam[2] = {static_cast<T>(J.ph->lam[0]), static_cast<T>(J.ph->lam[1])};
     const T g2 = static_cast<T>(J.ph->g2);
@@ -448,6 +454,17 @@ __device__ void march_tile(const TileJob& J, unsigned char* smem_raw, double (&a
     // Prologue: plane x0-1 (own only), plane x0 (own + halo into buffer 0),
     // then the loads of planes x0+1 .. x0+PD stay in flight into the loop.
     issue(S0{}, -1);
+    // the scalars of this pass (the previous pass's scalar step may run here,
+    // while the first loads are in flight)
+    prelude();
+    {
+        const Scal* sc = J.sc;
+        cd = J.drift ? static_cast<T>(sc->cd) : T(0);
+        kL = static_cast<T>(sc->kL);
+        kV = static_cast<T>(sc->kV);
+#pragma unroll
+        for (int j = 0; j < NF; ++j) shift[j] = static_cast<T>(sc->shift[j]);
+    }
     consume(S0{}, prev, pn, -1);
     issue(S0{}, 0);
     consume(S0{}, cur, pc, 0);
@@ -587,17 +604,56 @@ __global__ __launch_bounds__(256) void lattice_pass(PassArgs A) {
     J.flags = A.flags;
     J.kt = A.kt;
     J.kb = A.kb;
-    J.sc = A.sc;
     J.ph = &A.ph;
+    __shared__ Scal s_sc;
+    __shared__ double tot[kMaxSums];
+    J.sc = &s_sc;
+    const int NT = (A.TZ / VecOf<T>::V) * (A.TY / RY);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double acc[NS];
 #pragma unroll
     for (int k = 0; k < NS; ++k) acc[k] = 0.0;
-    march_tile<T, NF, RY, HI, PD>(J, smem_raw, acc);
-    const int NT = (A.TZ / VecOf<T>::V) * (A.TY / RY);
+    // (the prelude takes copies of the arguments it needs: a reference to the
+    // kernel argument block would force a private copy of it)
+    const Phys* php = J.ph;
+    const Scal* sc_in = A.sc_in;
+    Scal* sc_out = bid == 0 ? A.sc_out : nullptr;
+    const double* prev_part = A.prev_partials;
+    const int prev_nslots = A.prev_nslots, has_prev = A.has_prev;
+    const double pkt = A.pkt, pkb = A.pkb, phn = A.phn;
+    cl_observables* prev_rec = (bid == 0 && A.prev_rec >= 0) ? A.obs + A.prev_rec : nullptr;
+    Scal* ssc = &s_sc;
+    double* stot = tot;
+    auto prelude = [=]() {
+        copy_scal(ssc, sc_in, NT);
+        if (has_prev) {
+            // the previous pass's scalar step, identically in every workgroup
+            slots_sum<NS>(prev_part, NT, prev_nslots, stot);
+            if (threadIdx.x < 64) finish_pass(*php, ssc, pkt, pkb, phn, prev_rec, stot);
+            __syncthreads();
+            if (sc_out) copy_scal(sc_out, ssc, NT);
+        } else {
+            __syncthreads();
+        }
+    };
+    march_tile<T, NF, RY, HI, PD>(J, smem_raw, acc, prelude);
+    block_sum<NS>(acc, NT, tot);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < NS; ++k) A.partials[(size_t)k * nblocks + bid] = tot[k];
+}
+
+// The pending scalar step of the last pass of a sequence (one workgroup of
+// the passes' NT threads, so that the sums are formed in the same order).
+template <int NS>
+__global__ __launch_bounds__(256) void finish_kernel(PassArgs A) {
+    __shared__ Scal s_sc;
     __shared__ double tot[kMaxSums];
-    if (reduce_partials<NS>(acc, NT, A.partials, bid, nblocks, A.ticket, tot) && threadIdx.x < 64)
-        finish_pass(A.ph, A.sc, A.kt, A.kb, A.h_next, A.rec >= 0 ? A.obs + A.rec : nullptr, tot);
+    copy_scal(&s_sc, A.sc_in, blockDim.x);
+    slots_sum<NS>(A.prev_partials, blockDim.x, A.prev_nslots, tot);
+    if (threadIdx.x < 64)
+        finish_pass(A.ph, &s_sc, A.pkt, A.pkb, A.phn, A.prev_rec >= 0 ? A.obs + A.prev_rec : nullptr, tot);
+    __syncthreads();
+    copy_scal(A.sc_out, &s_sc, blockDim.x);
 }
 
 __global__ void init_scalars_kernel(Scal* sc, double a, double b, double eta, double alpha, double dx,
@@ -750,7 +806,7 @@ __global__ __launch_bounds__(256) void ensemble_pass(EnsArgs E) {
         double acc[NS];
 #pragma unroll
         for (int k = 0; k < NS; ++k) acc[k] = 0.0;
-        march_tile<T, NF, 1, 1, 2>(J, smem_raw, acc);
+        march_tile<T, NF, 1, 1, 2>(J, smem_raw, acc, [] {});
         if (reduce_partials<NS>(acc, 256, M.partials, I.tile, M.nitems, M.ticket, tot) && threadIdx.x < 64)
             finish_pass(M.ph, M.sc, kt, kb, hn, E.rec >= 0 ? E.obs + (size_t)E.rec * E.nmembers + I.member : nullptr,
                         tot);
@@ -846,6 +902,12 @@ template <typename T, int NF>
 static hipError_t launch_nf(const PassArgs& a, const Tile& t, hipStream_t s, size_t lds) {
     if (t.RY == 1) return t.HI == 1 ? launch_pd<T, NF, 1, 1>(a, t, s, lds) : launch_pd<T, NF, 1, 2>(a, t, s, lds);
     return t.HI == 1 ? launch_pd<T, NF, 2, 1>(a, t, s, lds) : launch_pd<T, NF, 2, 2>(a, t, s, lds);
+}
+
+hipError_t launch_finish(const PassArgs& a, const Tile& t, int nf, hipStream_t s) {
+    if (nf == 1) hipLaunchKernelGGL((finish_kernel<kSumsPerField + 1>), dim3(1), dim3(t.NT), 0, s, a);
+    else hipLaunchKernelGGL((finish_kernel<2 * kSumsPerField + 1>), dim3(1), dim3(t.NT), 0, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_pass(const PassArgs& a, const Tile& t, cl_precision prec, hipStream_t s) {
