@@ -29,6 +29,11 @@ sys.path.insert(0, ROOT)
 import workloads as W  # noqa: E402
 
 METRIC = "site-updates/s + %HBM peak: FP64 vs FP32 vs surrogate at fixed error"
+
+
+def progress(msg: str):
+    """One progress line on stderr (the JSON result is the only stdout line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 HBM_PEAK_GBS = 8000.0
 
 
@@ -46,7 +51,8 @@ def kpass_bytes_per_site(precision: str, nf: int) -> int:
 def measured_traffic(workload: str, tile: dict):
     """HBM bytes per launch from the committed rocprofv3 counter record, or None
     when the kernel source changed since the counters were taken or the tile
-    differs."""
+    differs (the prefetch depth, which does not change the bytes a pass
+    touches, is not compared)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
@@ -55,9 +61,9 @@ def measured_traffic(workload: str, tile: dict):
     src = open(os.path.join(ROOT, rec["kernel_source"]), "rb").read()
     if hashlib.sha256(src).hexdigest()[:16] != rec["sha256_prefix"]:
         return None
-    key = [tile["tz"], tile["ty"], tile["cx"], tile["ry"], tile["pd"]]
+    key = [tile["tz"], tile["ty"], tile["cx"], tile["ry"]]
     for e in rec["entries"]:
-        if e["workload"] == workload and e["tile"] == key:
+        if e["workload"] == workload and e["tile"][:4] == key:
             return e["traffic_bytes_per_launch"]
     return None
 
@@ -68,11 +74,14 @@ def make(w, precision, stream, tune=True, tile=None):
     lat.set_stream(stream.cuda_stream)
     lat.set_background(w.alpha, w.expansion, w.mp, w.a0)
     lat.set_potential(w.m2, w.lam, w.g2, w.V0)
+    progress(f"seeding {w.N}^3 {precision}")
     lat.seed(w.seed, w.fbar[:w.n_fields], w.pbar[:w.n_fields], w.cutoff_modes, w.amp)
     if tile is not None:
         lat.set_tile(*tile)
     elif tune:
+        progress("autotuning the pass tile")
         lat.autotune(reps=3)  # the library's own tile search (state is left unchanged)
+    progress(f"tile {lat.get_tile()}")
     return lat
 
 
@@ -95,8 +104,10 @@ def timed_run(w, precision, steps, warmup, chunk, tune=True, tile=None):
     torch.cuda.synchronize()
     e0.record(stream)
     t0 = time.perf_counter()
-    for _ in range(ncalls):
+    for i in range(ncalls):
         recs.append(lat.step(w.integrator, w.dt, chunk))
+        if time.perf_counter() - t0 > 30 and i % 10 == 0:
+            progress(f"timed call {i + 1}/{ncalls}")
     e1.record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -406,6 +417,7 @@ def main():
     r32, sec32, ms32, dk32, calls32, tile32 = timed_run(w, "fp32", args.steps, args.warmup, chunk,
                                                        not args.no_tune, tile)
     value = w.sites * args.steps / sec32
+    progress(f"fp32 form: {value:.4g} site-updates/s")
     ms_per_step = 1e3 * sec32 / args.steps
     # dominant kernel: the fused drift-kick-reduce pass (plus one opening kick per call)
     alg = dk32 * bytes_per_site("fp32", w.n_fields) * w.sites + calls32 * kpass_bytes_per_site("fp32", 2) * w.sites
@@ -427,6 +439,7 @@ def main():
     }
     forms = {"fp32": {"site_updates_per_s": value, "hbm_frac": achieved / HBM_PEAK_GBS}}
     if not args.no_fp64:
+        progress("fp64 form")
         r64, sec64, ms64, dk64, calls64, _ = timed_run(w, "fp64", args.steps, args.warmup, chunk,
                                                         not args.no_tune)
         alg64 = dk64 * bytes_per_site("fp64", 2) * w.sites + calls64 * kpass_bytes_per_site("fp64", 2) * w.sites
@@ -435,13 +448,16 @@ def main():
         forms["fp32_vs_fp64_rel_dev"] = linear_regime_deviation(r32, r64, w.n_fields)
         forms["fp32_speedup_vs_fp64"] = value / forms["fp64"]["site_updates_per_s"]
     if not args.no_batched and args.workload == "c1":
+        progress("batched ensemble form")
         forms["batched"] = batched_run(1000, 500)
     if args.surrogate and args.workload == "c1":
+        progress("surrogate form (training pairs, training, evaluation)")
         forms["surrogate"] = surrogate_run(epochs=args.sg_epochs, pairs_per_seed=args.sg_pairs,
                                            jumps=args.sg_jumps, extra_inputs=args.sg_extra)
     line["forms"] = forms
     if not args.no_cpu:
         # the oracle on the 256^3 workload (the 1024^3 one does not fit a numpy run of ~30 s)
+        progress("oracle on the host (cpu_baseline)")
         line["cpu_baseline"] = cpu_baseline(W.C1, steps=1)
     print(json.dumps(line), flush=True)
 

@@ -15,6 +15,11 @@ constexpr int kMaxFields = 2;
 // sum (f - shift), sum (f - shift)^2, sum p_new}, then sum V.
 constexpr int kSumsPerField = 5;
 constexpr int kMaxSums = kSumsPerField * kMaxFields + 1;
+// Workgroups of a lattice pass: every workgroup of a pass sums the partials of
+// all workgroups of the pass before it, so their number is bounded (and kept
+// lower still for the tuned candidates).
+constexpr int kMaxPassBlocks = 4096;
+constexpr int kTunedPassBlocks = 1024;
 constexpr int nsums(int nf) { return kSumsPerField * nf + 1; }
 
 // Background state and the coefficients of the next pass, in device memory.
@@ -30,6 +35,7 @@ struct Scal {
     double shift[2];   // predicted mean of f after the next drift (variance shift)
     double mean_f[2];  // mean of f in the state produced last
     double mean_p[2];  // mean of the momenta written last
+    double pa1, pa0;   // a_next^(2 alpha + 1), a_next^(2 alpha) (for the next Friedmann step)
     int32_t nonfinite; // sticky: a lattice sum was NaN / Inf
     int32_t pad;
 };

@@ -122,9 +122,8 @@ __device__ __forceinline__ void finish_pass(const Phys& P, Scal* sc, double kt, 
     const double pr = K - G / 3.0 - EV;
     double acc = 0.0, r = 0.0;
     const double b_half = sc->b;
-    // lane 0: a^(2 alpha + 1), lane 1: a^(2 alpha)
-    const double pw1 = (P.expand && lane < 2) ? pow(a, lane == 0 ? 2.0 * P.alpha + 1.0 : 2.0 * P.alpha) : 0.0;
-    const double a_2al1 = __shfl(pw1, 0, 64), a_2al = __shfl(pw1, 1, 64);
+    // a^(2 alpha + 1) and a^(2 alpha), formed by the step that fixed a
+    const double a_2al1 = sc->pa1, a_2al = sc->pa0;
     if (P.expand) {
         acc = a_2al1 * ((2.0 * P.alpha - 1.0) * rho - 3.0 * pr) / (6.0 * P.mp * P.mp);
     }
@@ -137,11 +136,16 @@ __device__ __forceinline__ void finish_pass(const Phys& P, Scal* sc, double kt, 
     const double b_new = b_half + kt * acc;
     const double an = (h_next != 0.0 && P.expand) ? a + h_next * b_new : a;
     const double abar = 0.5 * (a + an);
-    // lane 0: abar^(alpha - 3), lane 1: an^(1 + alpha), lane 2: an^(3 + alpha)
-    const double pw2 = (h_next != 0.0 && lane < 3)
-                           ? pow(lane == 0 ? abar : an, lane == 0 ? P.alpha - 3.0 : (lane == 1 ? 1.0 : 3.0) + P.alpha)
-                           : 0.0;
-    const double abar_al3 = __shfl(pw2, 0, 64), an_1al = __shfl(pw2, 1, 64), an_3al = __shfl(pw2, 2, 64);
+    // lane 0: abar^(alpha - 3), lanes 1..4: an^(1 + alpha), an^(3 + alpha),
+    // an^(2 alpha + 1), an^(2 alpha)
+    double ex = P.alpha - 3.0;
+    if (lane == 1) ex = 1.0 + P.alpha;
+    if (lane == 2) ex = 3.0 + P.alpha;
+    if (lane == 3) ex = 2.0 * P.alpha + 1.0;
+    if (lane == 4) ex = 2.0 * P.alpha;
+    const double pw = (h_next != 0.0 && lane < 5) ? pow(lane == 0 ? abar : an, ex) : 0.0;
+    const double abar_al3 = __shfl(pw, 0, 64), an_1al = __shfl(pw, 1, 64), an_3al = __shfl(pw, 2, 64);
+    const double an_2al1 = __shfl(pw, 3, 64), an_2al = __shfl(pw, 4, 64);
     if (lane != 0) return;
     if (rec_out) {
         cl_observables o;
@@ -172,6 +176,8 @@ __device__ __forceinline__ void finish_pass(const Phys& P, Scal* sc, double kt, 
         sc->kL = an_1al / (P.dx * P.dx);
         sc->kV = an_3al;
         sc->a_next = an;
+        sc->pa1 = an_2al1;
+        sc->pa0 = an_2al;
         sc->eta += h_next;
         for (int j = 0; j < 2; ++j) sc->shift[j] = mean[j] + sc->cd * meanp[j];
     } else {
@@ -625,14 +631,27 @@ __global__ __launch_bounds__(256) void lattice_pass(PassArgs A) {
     Scal* ssc = &s_sc;
     double* stot = tot;
     auto prelude = [=]() {
-        copy_scal(ssc, sc_in, NT);
+        // the scalar block travels through registers so that its load overlaps
+        // those of the partial sums (2 NT >= its words: NT >= 16)
+        constexpr int NW = sizeof(Scal) / 8;
+        static_assert(NW <= 32, "two words per thread at the smallest workgroup");
+        const unsigned long long* src = reinterpret_cast<const unsigned long long*>(sc_in);
+        unsigned long long* dst = reinterpret_cast<unsigned long long*>(ssc);
+        const int t = threadIdx.x;
+        const unsigned long long w0 = t < NW ? src[t] : 0ull;
+        const unsigned long long w1 = t + NT < NW ? src[t + NT] : 0ull;
         if (has_prev) {
             // the previous pass's scalar step, identically in every workgroup
             slots_sum<NS>(prev_part, NT, prev_nslots, stot);
+            if (t < NW) dst[t] = w0;
+            if (t + NT < NW) dst[t + NT] = w1;
+            __syncthreads();
             if (threadIdx.x < 64) finish_pass(*php, ssc, pkt, pkb, phn, prev_rec, stot);
             __syncthreads();
             if (sc_out) copy_scal(sc_out, ssc, NT);
         } else {
+            if (t < NW) dst[t] = w0;
+            if (t + NT < NW) dst[t + NT] = w1;
             __syncthreads();
         }
     };
@@ -673,6 +692,8 @@ __global__ void init_scalars_kernel(Scal* sc, double a, double b, double eta, do
     s.mean_f[1] = s1;
     s.mean_p[0] = 0.0;
     s.mean_p[1] = 0.0;
+    s.pa1 = pow(a, 2.0 * alpha + 1.0);
+    s.pa0 = pow(a, 2.0 * alpha);
     s.nonfinite = 0;
     s.pad = 0;
     *sc = s;
@@ -744,6 +765,8 @@ bool finalize_tile(Tile& t, int N, cl_precision prec) {
     t.nbz = N / t.TZ;
     t.nby = N / t.TY;
     t.nbx = N / t.CX;
+    // every workgroup of a pass reads all partial sums of the pass before it
+    if (t.nblocks() > kMaxPassBlocks) return false;
     return true;
 }
 
@@ -756,9 +779,13 @@ Tile default_tile(int N, cl_precision prec, int nf) {
     int RL = 256 / BZ;
     while (RL > 1 && (RL > N || N % RL)) RL >>= 1;
     t.TY = RL * t.RY;
+    if ((N / t.TZ) * (N / t.TY) > kTunedPassBlocks && N % (2 * RL) == 0) {
+        t.RY = 2;  // two rows per thread: half the workgroups
+        t.TY = 2 * RL;
+    }
     const int tiles = (N / t.TZ) * (N / t.TY);
     t.CX = N;
-    while (t.CX > 4 && tiles * (N / t.CX) < 2048 && (t.CX % 2 == 0)) t.CX /= 2;
+    while (t.CX > 4 && tiles * (N / t.CX) < 512 && (t.CX % 2 == 0)) t.CX /= 2;
     (void)nf;
     finalize_tile(t, N, prec);
     return t;
@@ -857,29 +884,34 @@ hipError_t launch_ensemble_pass(const EnsArgs& a, cl_precision prec, int nf, int
 void candidate_tiles(int N, cl_precision prec, int nf, Tile* out, int* count, int cap) {
     const int V = prec == CL_FP32 ? 4 : 2;
     int n = 0;
-    for (int tzm : {64, 32, 16}) {
-        const int TZ = N < tzm * V ? N : tzm * V;
-        if (tzm != 64 && TZ == N) continue;  // same as the full-row candidate
-        const int BZ = TZ / V;
-        for (int RY : {1, 2})
-            for (int NT : {64, 128, 256}) {
-                if (NT < BZ) continue;
-                const int TY = (NT / BZ) * RY;
-                if (TY > N) continue;
-                for (int CX = 2; CX <= N; CX *= 2)
-                    for (int PD : {1, 2, 4}) {
-                        if (CX != N && (CX < 4 || CX > 256)) continue;
-                        Tile t;
-                        t.TZ = TZ;
-                        t.TY = TY;
-                        t.CX = CX;
-                        t.RY = RY;
-                        t.PD = PD;
-                        if (!finalize_tile(t, N, prec)) continue;
-                        if (pass_lds_bytes(t, prec, nf) > 60 * 1024) continue;
-                        if (n < cap) out[n++] = t;
-                    }
-            }
+    // candidates with at most kTunedPassBlocks workgroups; all valid ones
+    // (up to kMaxPassBlocks) only if there is none
+    for (int wide = 0; wide < 2 && n == 0; ++wide) {
+        for (int tzm : {64, 32, 16}) {
+            const int TZ = N < tzm * V ? N : tzm * V;
+            if (tzm != 64 && TZ == N) continue;  // same as the full-row candidate
+            const int BZ = TZ / V;
+            for (int RY : {1, 2})
+                for (int NT : {64, 128, 256}) {
+                    if (NT < BZ) continue;
+                    const int TY = (NT / BZ) * RY;
+                    if (TY > N) continue;
+                    for (int CX = 2; CX <= N; CX *= 2)
+                        for (int PD : {1, 2, 4}) {
+                            if (CX != N && (CX < 4 || CX > 256)) continue;
+                            Tile t;
+                            t.TZ = TZ;
+                            t.TY = TY;
+                            t.CX = CX;
+                            t.RY = RY;
+                            t.PD = PD;
+                            if (!finalize_tile(t, N, prec)) continue;
+                            if (pass_lds_bytes(t, prec, nf) > 60 * 1024) continue;
+                            if (t.nblocks() > kTunedPassBlocks && !wide) continue;
+                            if (n < cap) out[n++] = t;
+                        }
+                }
+        }
     }
     *count = n;
 }
