@@ -223,7 +223,17 @@ def _field_error(lat, ref_lat):
     return err
 
 
-def surrogate_run(epochs=4, pairs_per_seed=64, train_seeds=range(2000, 2008), eval_seed=3000, jumps=312,
+def surrogate_flops_per_site(extra_inputs: int, nf: int = 2, hidden: int = 32, layers: int = 5) -> int:
+    """Useful multiply-add flops of one network evaluation per lattice site
+    (2 x 27 x c_in x c_out summed over the layers, real channel counts)."""
+    ch = [2 * nf + extra_inputs] + [hidden] * (layers - 1) + [2 * nf]
+    return sum(2 * 27 * a * b for a, b in zip(ch[:-1], ch[1:]))
+
+
+MFMA_BF16_PEAK = 2.5e15
+
+
+def surrogate_run(epochs=12, pairs_per_seed=64, train_seeds=range(2000, 2008), eval_seed=3000, jumps=312,
                   extra_inputs=4, eval_256=True):
     """The learned surrogate on the two-field q = 100 workload: training pairs
     (state, state 16 VV4 steps later) from seeded 128^3 runs (k_IR = 0.5,
@@ -315,10 +325,14 @@ def surrogate_run(epochs=4, pairs_per_seed=64, train_seeds=range(2000, 2008), ev
         torch.cuda.synchronize()
         sec = time.perf_counter() - t1
         errs = _scalar_errors(recs, rr, 2)
+        flops = surrogate_flops_per_site(extra_inputs) * w.sites * njumps
         forms["surrogate"] = {"effective_site_updates_per_s": w.sites * njumps * K / sec, "seconds": sec,
                               "fallbacks": srep["fallbacks"], "fallback_rate": srep["fallbacks"] / max(1, njumps),
                               "max_residual": srep["max_residual"], "error_vs_fp64_vv4": errs["max"],
-                              "errors": errs, "field_error": _field_error(lat, ref)}
+                              "errors": errs, "field_error": _field_error(lat, ref),
+                              "network_ms_per_jump": 1e3 * srep["net_seconds"] / max(1, njumps),
+                              "network_tflops": flops / srep["net_seconds"] / 1e12,
+                              "mfma_frac": flops / srep["net_seconds"] / MFMA_BF16_PEAK}
         # the network alone: no residual gate (non-finite jumps still fall back), until the
         # evolution breaks down
         lat.close()
@@ -387,8 +401,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--tile", default=None, help="force the FP32 tile tz,ty,cx,ry,pd instead of autotuning")
-    ap.add_argument("--surrogate", action="store_true", help="also train and evaluate the learned surrogate")
-    ap.add_argument("--sg-epochs", type=int, default=4)
+    ap.add_argument("--no-surrogate", action="store_true", help="skip training and evaluating the learned surrogate")
+    ap.add_argument("--sg-epochs", type=int, default=12)
     ap.add_argument("--sg-pairs", type=int, default=64, help="training pairs per seed (8 seeds)")
     ap.add_argument("--sg-jumps", type=int, default=312)
     ap.add_argument("--sg-extra", type=int, default=4, help="broadcast inputs: 4 = (a, H, <phi>, <pi_phi>), 2 = (a, H)")
@@ -450,7 +464,7 @@ def main():
     if not args.no_batched and args.workload == "c1":
         progress("batched ensemble form")
         forms["batched"] = batched_run(1000, 500)
-    if args.surrogate and args.workload == "c1":
+    if not args.no_surrogate and args.workload == "c1":
         progress("surrogate form (training pairs, training, evaluation)")
         forms["surrogate"] = surrogate_run(epochs=args.sg_epochs, pairs_per_seed=args.sg_pairs,
                                            jumps=args.sg_jumps, extra_inputs=args.sg_extra)

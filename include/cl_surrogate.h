@@ -65,7 +65,8 @@ typedef struct {
     int jumps;
     int fallbacks;
     double max_residual;   /* largest Hubble residual seen after a network jump */
-    double seconds;
+    double seconds;        /* wall time of the call */
+    double net_seconds;    /* device time of the network evaluations (HIP events) */
 } cl_surrogate_report;
 
 /* Message for the last failing cl_surrogate_* call on this thread. */

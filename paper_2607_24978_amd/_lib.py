@@ -65,7 +65,8 @@ class cl_train_report(C.Structure):
 
 
 class cl_surrogate_report(C.Structure):
-    _fields_ = [("jumps", C.c_int), ("fallbacks", C.c_int), ("max_residual", C.c_double), ("seconds", C.c_double)]
+    _fields_ = [("jumps", C.c_int), ("fallbacks", C.c_int), ("max_residual", C.c_double), ("seconds", C.c_double),
+                ("net_seconds", C.c_double)]
 
 
 OBS_DTYPE = np.dtype([("eta", "f8"), ("a", "f8"), ("H", "f8"), ("EK", "f8", 2), ("EG", "f8", 2), ("EV", "f8"),
