@@ -206,6 +206,57 @@ def vv2(s: State, h: float, P: Params) -> State:
     return State(f, p, a, b, s.eta + h)
 
 
+# ---------------------------------------------------------------- Runge-Kutta
+# Low-storage ("2N") Runge-Kutta schemes (Sect. 4.1: the RK family of the
+# release, with one auxiliary field per degree of freedom).  With
+# y = (f, pi, a, a') and y' = F(y), one step of s stages is
+#     d <- A_i d + h F(y);   y <- y + B_i d      (i = 1..s, A_1 = 0).
+# Coefficients: RK2 -- the explicit midpoint rule written in this form;
+# RK3-3 -- Williamson (1980); RK4-5 -- Carpenter and Kennedy (1994), five
+# stages, fourth order.
+RK_SCHEMES = {
+    "rk2": ([0.0, -0.5], [0.5, 1.0]),
+    "rk3": ([0.0, -5.0 / 9.0, -153.0 / 128.0], [1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0]),
+    "rk4": ([0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
+             -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0],
+            [1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
+             1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+             2277821191437.0 / 14882151754819.0]),
+}
+
+
+def rhs(f, p, a: float, b: float, P: Params):
+    """Right-hand side of the first-order system for (f, pi, a, a'):
+    f' = a^(alpha-3) pi (the drift), pi' = force (the kick kernel),
+    a' = b, b' = A(a, E(f, pi, a)) (Eq. Friedmann1 times a; zero in static
+    space).  Canonical fields: the kernel does not depend on pi."""
+    df = a ** (P.alpha - 3.0) * p
+    dp = force(f, a, P)
+    if P.expansion == "static":
+        return df, dp, 0.0, 0.0
+    return df, dp, b, accel(a, energies(f, p, a, P), P)
+
+
+def rk_step(s: State, h: float, P: Params, scheme: str) -> State:
+    """One step of a low-storage Runge-Kutta scheme (see RK_SCHEMES)."""
+    A, B = RK_SCHEMES[scheme]
+    f, p, a, b = s.f.copy(), s.p.copy(), s.a, s.b
+    df = np.zeros_like(f)
+    dp = np.zeros_like(p)
+    da = db = 0.0
+    for Ai, Bi in zip(A, B):
+        rf, rp, ra, rb = rhs(f, p, a, b, P)
+        df = Ai * df + h * rf
+        dp = Ai * dp + h * rp
+        da = Ai * da + h * ra
+        db = Ai * db + h * rb
+        f = f + Bi * df
+        p = p + Bi * dp
+        a = a + Bi * da
+        b = b + Bi * db
+    return State(f, p, a, b, s.eta + h)
+
+
 def step(s: State, dt: float, P: Params, integrator: str = "leapfrog") -> State:
     """One full time step.  leapfrog is velocity Verlet of size dt (its field
     trajectory is the staggered leapfrog one); vv4 is the Yoshida triple jump
@@ -216,6 +267,8 @@ def step(s: State, dt: float, P: Params, integrator: str = "leapfrog") -> State:
         s = vv2(s, W1 * dt, P)
         s = vv2(s, W0 * dt, P)
         return vv2(s, W1 * dt, P)
+    if integrator in RK_SCHEMES:
+        return rk_step(s, dt, P, integrator)
     raise ValueError(integrator)
 
 

@@ -147,7 +147,7 @@ def rk4_homogeneous(f0, p0, a0, b0, T, h, alpha, mp, lam):
     return y
 
 
-@pytest.mark.parametrize("integrator,order", [("leapfrog", 2), ("vv4", 4)])
+@pytest.mark.parametrize("integrator,order", [("leapfrog", 2), ("vv4", 4), ("rk2", 2), ("rk3", 3), ("rk4", 4)])
 @pytest.mark.parametrize("alpha", [1.0, 0.0])
 def test_homogeneous_mode_against_rk4(integrator, order, alpha):
     """P3: a uniform lattice reduces to the ODE of (f, p, a, b); the oracle
@@ -160,7 +160,8 @@ def test_homogeneous_mode_against_rk4(integrator, order, alpha):
     T = 4.0
     ref = rk4_homogeneous(f0, p0, a0, b0, T, 1e-3, alpha, mp, lam)
     errs = []
-    for dt in (0.1, 0.05):
+    # the Runge-Kutta schemes reach their asymptotic rate at smaller steps
+    for dt in ((0.1, 0.05) if integrator in ("leapfrog", "vv4") else (0.05, 0.025)):
         s = L.State(np.full((1, N, N, N), f0), np.full((1, N, N, N), p0), a0, b0)
         for _ in range(int(round(T / dt))):
             s = L.step(s, dt, P, integrator)
@@ -171,7 +172,7 @@ def test_homogeneous_mode_against_rk4(integrator, order, alpha):
 
 
 # ---------------------------------------------------------------- P11
-@pytest.mark.parametrize("integrator,order", [("leapfrog", 2), ("vv4", 4)])
+@pytest.mark.parametrize("integrator,order", [("leapfrog", 2), ("vv4", 4), ("rk2", 2), ("rk3", 3), ("rk4", 4)])
 def test_closed_form_expansion(integrator, order):
     """P11: (i) vacuum energy V0 with alpha = 1 gives a = 1/(1 - H0 eta),
     H0^2 = V0/(3 mp^2); alpha = 0 gives a = exp(H0 t); (ii) kination
@@ -444,3 +445,62 @@ def test_hubble_constraint_converges_with_gradients(integrator, order):
     assert s.a > 1.5
     ratio = rs[0] / rs[1]
     assert abs(ratio / 2 ** order - 1) < 0.2, (rs, ratio)
+
+
+# ---------------------------------------------------------------- low-storage Runge-Kutta
+def butcher_from_low_storage(A, B):
+    """Explicit Butcher tableau (a, b, c) equivalent to the 2N recurrence
+    d_i = A_i d_(i-1) + h k_i, y_i = y_(i-1) + B_i d_i, k_i = F(y_(i-1)):
+    track y_i and d_i as combinations of h k_1 .. h k_s."""
+    s = len(A)
+    D = np.zeros((s, s))
+    Y = np.zeros((s + 1, s))
+    for i in range(s):
+        if i:
+            D[i] = A[i] * D[i - 1]
+        D[i, i] += 1.0
+        Y[i + 1] = Y[i] + B[i] * D[i]
+    a = Y[:s]
+    b = Y[s]
+    return a, b, a.sum(axis=1)
+
+
+@pytest.mark.parametrize("scheme,order", [("rk2", 2), ("rk3", 3), ("rk4", 4)])
+def test_low_storage_order_conditions(scheme, order):
+    """The published low-storage coefficients satisfy the Runge-Kutta order
+    conditions of their order (Butcher's rooted-tree conditions up to order
+    4), so a wrong digit in any of them fails here."""
+    A, B = L.RK_SCHEMES[scheme]
+    assert A[0] == 0.0
+    a, b, c = butcher_from_low_storage(A, B)
+    assert np.allclose(np.tril(a, -1), a)  # explicit
+    conds = [b.sum() - 1.0, b @ c - 0.5]
+    if order >= 3:
+        conds += [b @ c ** 2 - 1.0 / 3.0, b @ (a @ c) - 1.0 / 6.0]
+    if order >= 4:
+        conds += [b @ c ** 3 - 0.25, (b * c) @ (a @ c) - 0.125, b @ (a @ c ** 2) - 1.0 / 12.0,
+                  b @ (a @ (a @ c)) - 1.0 / 24.0]
+    assert np.max(np.abs(conds)) < 1e-13, conds
+
+
+def test_rk2_is_the_explicit_midpoint_rule():
+    """The two-stage low-storage scheme is exactly the explicit midpoint rule
+    y1 = y0 + h F(y0 + h/2 F(y0)), written out here for the (f, pi, a, a')
+    system of a two-field lattice in expanding space."""
+    w = W.C1.with_(N=8, k_ir=2.0)
+    P = L.Params(N=w.N, dx=w.dx, n_fields=2, m2=w.m2, lam=w.lam, g2=w.g2)
+    f, p = W.random_state(w.N, 2, seed=5, fbar=(1.0, 0.05), famp=0.05, pamp=0.05)
+    a, b, h = 1.3, 0.4, 0.02
+
+    def F(f, p, a, b):
+        E = L.energies(f, p, a, P)
+        return (a ** (P.alpha - 3.0) * p, L.force(f, a, P), b, L.accel(a, E, P))
+
+    k1 = F(f, p, a, b)
+    mid = (f + 0.5 * h * k1[0], p + 0.5 * h * k1[1], a + 0.5 * h * k1[2], b + 0.5 * h * k1[3])
+    k2 = F(*mid)
+    s = L.rk_step(L.State(f.copy(), p.copy(), a, b), h, P, "rk2")
+    assert np.max(np.abs(s.f - (f + h * k2[0]))) <= 1e-14 * np.max(np.abs(f))
+    assert np.max(np.abs(s.p - (p + h * k2[1]))) <= 1e-13 * np.max(np.abs(p + h * k2[1]))
+    assert abs(s.a - (a + h * k2[2])) <= 1e-15 * a
+    assert abs(s.b - (b + h * k2[3])) <= 1e-14 * abs(b)
