@@ -50,8 +50,15 @@ typedef enum { CL_FP64 = 0, CL_FP32 = 1 } cl_precision;
 typedef enum { CL_STATIC = 0, CL_SELF_CONSISTENT = 1 } cl_expansion;
 
 /* CL_LEAPFROG: staggered leapfrog, O(dt^2).  CL_VV4: 4th-order Yoshida
- * composition of velocity Verlet, O(dt^4) (Sect. 4.1). */
-typedef enum { CL_LEAPFROG = 0, CL_VV4 = 1 } cl_integrator;
+ * composition of velocity Verlet, O(dt^4) (Sect. 4.1).  CL_RK2, CL_RK3,
+ * CL_RK4: low-storage Runge-Kutta schemes of the (f, pi, a, a') system with
+ * one auxiliary array per field and momentum (Sect. 4.1, RK family): the
+ * explicit midpoint rule (2 stages, O(dt^2)), Williamson's RK3-3 (3 stages,
+ * O(dt^3)) and Carpenter-Kennedy's RK4-5 (5 stages, O(dt^4)).  A
+ * Runge-Kutta step costs one fused pass per stage, each moving 32 B per
+ * field and site in FP32 (64 B in FP64), against 16 (32) for a leapfrog pass;
+ * the auxiliary arrays are allocated by the first Runge-Kutta step. */
+typedef enum { CL_LEAPFROG = 0, CL_VV4 = 1, CL_RK2 = 2, CL_RK3 = 3, CL_RK4 = 4 } cl_integrator;
 
 /* V = sum_j (m2[j] f_j^2 / 2 + lambda[j] f_j^4 / 4) + g2 f_0^2 f_1^2 / 2 + V0,
  * in program variables (Eq. FieldSpaceTimeNaturalVariables).  With two fields
@@ -217,7 +224,8 @@ cl_status cl_copy_bandwidth(size_t bytes, int reps, double* gbps);
  * null stream or a common one.  The ensemble does not own the members. */
 cl_status cl_ensemble_create(int n_members, cl_lattice* const* members, cl_ensemble** out);
 cl_status cl_ensemble_set_dt(cl_ensemble* e, int member, double dt);
-/* out: NULL or n_steps * n_members records, step-major ([s][member]). */
+/* out: NULL or n_steps * n_members records, step-major ([s][member]).
+ * integ: CL_LEAPFROG or CL_VV4 (the Runge-Kutta schemes: CL_EUNSUPPORTED). */
 cl_status cl_ensemble_step(cl_ensemble* e, cl_integrator integ, int n_steps, cl_observables* out);
 /* Tile the ensemble kernel uses for one member (ry = 1, pd = 2).  A member
  * stepped on its own with this tile (cl_set_tile) gives bitwise the same

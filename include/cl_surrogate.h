@@ -118,8 +118,8 @@ cl_status cl_surrogate_load(cl_surrogate* s, const char* path);
  * linearly between the start and the predicted endpoint (corrector; the sums
  * do not depend on a, so one pass is converged).  If the Hubble-constraint
  * residual at the endpoint exceeds `threshold` (or any sum is non-finite) the
- * jump is undone and the integrator `fallback` runs jump_steps steps instead.
- * per_jump (nullable) receives one record per jump. */
+ * jump is undone and the integrator `fallback` (CL_LEAPFROG or CL_VV4) runs
+ * jump_steps steps instead.  per_jump (nullable) receives one record per jump. */
 cl_status cl_surrogate_advance(cl_lattice* h, cl_surrogate* s, cl_integrator fallback, double dt, int n_jumps,
                                double threshold, cl_observables* per_jump, cl_surrogate_report* rep);
 

@@ -36,6 +36,8 @@ struct Scal {
     double mean_f[2];  // mean of f in the state produced last
     double mean_p[2];  // mean of the momenta written last
     double pa1, pa0;   // a_next^(2 alpha + 1), a_next^(2 alpha) (for the next Friedmann step)
+    double pf;         // a_next^(alpha - 3) (the drift rate of a Runge-Kutta stage)
+    double da, db;     // low-storage Runge-Kutta registers of a and a'
     int32_t nonfinite; // sticky: a lattice sum was NaN / Inf
     int32_t pad;
 };
@@ -92,6 +94,14 @@ struct PassArgs {
     int prev_rec;       // observable slot of the previous pass, -1: none
     int pad_;
     double pkt, pkb, phn;  // kt, kb, h_next of the previous pass
+    // Runge-Kutta stage (rk = 1): d <- rkA d + rkh F(y); y <- y + rkB d for
+    // the fields (aux holds d_f, d_pi in the state layout) and, in the scalar
+    // step, for (a, a').  rk_first: rkA = 0, aux is not read.
+    int rk, rk_first;
+    int prev_rk, pad2_;  // prev_rk: the pending step is a Runge-Kutta stage's
+    double rkA, rkB, rkh, rkdeta;   // rkdeta: time advanced by this stage
+    double prkA, prkB, prkh, prkdeta;  // the previous pass's stage coefficients
+    void* aux;
     cl_observables* obs;
     Phys ph;
 };
@@ -182,6 +192,7 @@ struct cl_lattice {
     bool own_buffers = true;
     int device = 0;
     void* buf[2] = {nullptr, nullptr};  // ping-pong state buffers (row-interleaved layout)
+    void* aux = nullptr;                // Runge-Kutta registers of f and pi (same layout), on first use
     int pass_flags = 1;                 // nontemporal stores
     int cur = 0;
     cl::Scal* sc = nullptr;

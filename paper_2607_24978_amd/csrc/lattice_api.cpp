@@ -32,6 +32,8 @@ thread_local std::string g_err;
 
 size_t elem_size(cl_precision p) { return p == CL_FP32 ? 4 : 8; }
 size_t sites(const cl_lattice* h) { return static_cast<size_t>(h->N) * h->N * h->N; }
+// One state buffer: 2 n_f arrays of N^3 values.
+size_t state_bytes(const cl_lattice* h) { return 2 * static_cast<size_t>(h->nf) * sites(h) * elem_size(h->prec); }
 
 cl_status fail(cl_lattice* h, cl_status st, const std::string& msg) {
     if (h) h->err = msg; else g_err = msg;
@@ -124,6 +126,10 @@ PassArgs base_args(cl_lattice* h, int in) {
     a.prev_partials = nullptr;
     a.has_prev = 0;
     a.prev_rec = -1;
+    a.rk = a.rk_first = a.prev_rk = 0;
+    a.rkA = a.rkB = a.rkh = a.rkdeta = 0.0;
+    a.prkA = a.prkB = a.prkh = a.prkdeta = 0.0;
+    a.aux = h->aux;
     a.obs = h->obs;
     a.ph = make_phys(h);
     a.rec = -1;
@@ -150,6 +156,11 @@ struct PassSeq {
         a.pkb = prev.kb;
         a.phn = prev.h_next;
         a.prev_rec = prev.rec;
+        a.prev_rk = prev.rk;
+        a.prkA = prev.rkA;
+        a.prkB = prev.rkB;
+        a.prkh = prev.rkh;
+        a.prkdeta = prev.rkdeta;
     }
     hipError_t launch(PassArgs a) {
         a.partials = part(p & 1);
@@ -192,9 +203,81 @@ void substeps(cl_integrator integ, double dt, int n, std::vector<double>& h, int
     }
 }
 
+bool is_rk(cl_integrator integ) { return integ == CL_RK2 || integ == CL_RK3 || integ == CL_RK4; }
+
+// Low-storage Runge-Kutta coefficients (d <- A d + h F(y), y <- y + B d):
+// the explicit midpoint rule; Williamson (1980) RK3-3; Carpenter and
+// Kennedy (1994) five-stage fourth-order scheme.
+void rk_coefficients(cl_integrator integ, std::vector<double>& A, std::vector<double>& B) {
+    if (integ == CL_RK2) {
+        A = {0.0, -0.5};
+        B = {0.5, 1.0};
+    } else if (integ == CL_RK3) {
+        A = {0.0, -5.0 / 9.0, -153.0 / 128.0};
+        B = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
+    } else {
+        A = {0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
+             -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0};
+        B = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
+             1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+             2277821191437.0 / 14882151754819.0};
+    }
+}
+
+// Stage abscissae of a low-storage scheme: c_i = sum_j a_ij of the equivalent
+// Butcher tableau, tracked as the coefficients of y_i and d_i in h k_j.
+std::vector<double> rk_abscissae(const std::vector<double>& A, const std::vector<double>& B) {
+    const size_t s = A.size();
+    std::vector<double> c(s + 1, 0.0), D(s, 0.0), Y(s, 0.0);  // D, Y: coefficient rows
+    for (size_t i = 0; i < s; ++i) {
+        // d_i = A_i d_(i-1) + h k_i ; y_i = y_(i-1) + B_i d_i  (sum of coefficients suffices)
+        double dsum = (i ? A[i] * D[i - 1] : 0.0) + 1.0;
+        D[i] = dsum;
+        c[i + 1] = c[i] + B[i] * dsum;
+    }
+    c[s] = 1.0;  // a consistent scheme ends at y(t + h)
+    return c;
+}
+
+// Passes of n low-storage Runge-Kutta steps: one stage pass per stage, then
+// a reduction-only pass whose scalar step records the final state.  The
+// scalar step of stage 0 of step k records the end of step k - 1.
+cl_status issue_rk_steps(cl_lattice* h, cl_integrator integ, double dt, int n, int cur) {
+    std::vector<double> A, B;
+    rk_coefficients(integ, A, B);
+    const std::vector<double> c = rk_abscissae(A, B);
+    const int S = static_cast<int>(A.size());
+    PassSeq seq(h);
+    for (int k = 0; k < n; ++k)
+        for (int i = 0; i < S; ++i) {
+            PassArgs r = base_args(h, cur);
+            r.drift = 0;
+            r.write_out = 1;
+            r.kt = r.kb = r.h_next = 0.0;
+            r.rk = 1;
+            r.rk_first = i == 0;
+            r.rkA = A[i];
+            r.rkB = B[i];
+            r.rkh = dt;
+            r.rkdeta = (c[i + 1] - c[i]) * dt;
+            r.rec = (i == 0 && k > 0) ? k - 1 : -1;
+            HIPCHECK(h, seq.launch(r));
+            cur ^= 1;
+        }
+    PassArgs z = base_args(h, cur);
+    z.drift = 0;
+    z.write_out = 0;
+    z.kt = z.kb = z.h_next = 0.0;
+    z.rec = n - 1;
+    HIPCHECK(h, seq.launch(z));
+    HIPCHECK(h, seq.close());
+    return CL_OK;
+}
+
 // Issue the passes of n steps on the handle's stream.  Returns the final
 // buffer index.
 cl_status issue_steps(cl_lattice* h, cl_integrator integ, double dt, int n, int cur) {
+    if (is_rk(integ)) return issue_rk_steps(h, integ, dt, n, cur);
     // Sub-step sizes in units of dt; every kick and drift step is formed as
     // (coefficient) * dt, exactly as the ensemble kernel forms it per member.
     std::vector<double> c;
@@ -441,6 +524,7 @@ cl_status cl_destroy(cl_lattice* h) {
     if (h->stream) hipStreamSynchronize(h->stream);
     drop_graph(h);
     free_buffers(h);
+    if (h->aux) hipFree(h->aux);
     if (h->sc) hipFree(h->sc);
     if (h->partials) hipFree(h->partials);
     if (h->scb) hipFree(h->scb);
@@ -572,7 +656,7 @@ cl_status cl_set_state(cl_lattice* h, const cl_scalars* in) {
 
 cl_status cl_step(cl_lattice* h, cl_integrator integ, double dt, int n, cl_observables* per_step) {
     if (!h) return fail(nullptr, CL_EINVAL, "handle is NULL");
-    if (integ != CL_LEAPFROG && integ != CL_VV4) return fail(h, CL_EINVAL, "unknown integrator");
+    if (integ != CL_LEAPFROG && integ != CL_VV4 && !is_rk(integ)) return fail(h, CL_EINVAL, "unknown integrator");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(h, CL_EINVAL, "dt must be positive and finite");
     if (n < 0) return fail(h, CL_EINVAL, "n must be >= 0");
     if (n == 0) return CL_OK;
@@ -580,8 +664,15 @@ cl_status cl_step(cl_lattice* h, cl_integrator integ, double dt, int n, cl_obser
         return fail(h, CL_EUNSTABLE, "dt exceeds the Courant bound dt*sqrt(12)/dx < 2");
     cl_status st = ensure_obs(h, n);
     if (st) return st;
+    if (is_rk(integ) && !h->aux) {
+        // Runge-Kutta registers of (f, pi): one more state-sized buffer
+        if (hipMalloc(&h->aux, state_bytes(h)) != hipSuccess)
+            return fail(h, CL_ENOMEM, "Runge-Kutta registers (" + std::to_string(state_bytes(h)) + " bytes)");
+        drop_graph(h);
+    }
     const GraphKey key{static_cast<int>(integ), dt, n, h->cur};
-    const int passes = 1 + n * (integ == CL_VV4 ? 3 : 1);
+    const int stages = integ == CL_RK2 ? 2 : integ == CL_RK3 ? 3 : integ == CL_RK4 ? 5 : 0;
+    const int passes = is_rk(integ) ? n * stages : 1 + n * (integ == CL_VV4 ? 3 : 1);
     if (h->use_graph && n > 1) {
         hipGraphExec_t& gx = h->gexec[h->cur];
         if (!(gx && h->gkey[h->cur] == key)) {
@@ -953,6 +1044,8 @@ cl_status cl_ensemble_set_dt(cl_ensemble* e, int i, double dt) {
 
 cl_status cl_ensemble_step(cl_ensemble* e, cl_integrator integ, int n, cl_observables* out) {
     if (!e) return efail(CL_EINVAL, "ensemble is NULL");
+    if (integ == CL_RK2 || integ == CL_RK3 || integ == CL_RK4)
+        return efail(CL_EUNSUPPORTED, "ensembles run the symplectic schemes only");
     if (integ != CL_LEAPFROG && integ != CL_VV4) return efail(CL_EINVAL, "unknown integrator");
     if (n < 0) return efail(CL_EINVAL, "n must be >= 0");
     if (n == 0) return CL_OK;

@@ -136,16 +136,16 @@ __device__ __forceinline__ void finish_pass(const Phys& P, Scal* sc, double kt, 
     const double b_new = b_half + kt * acc;
     const double an = (h_next != 0.0 && P.expand) ? a + h_next * b_new : a;
     const double abar = 0.5 * (a + an);
-    // lane 0: abar^(alpha - 3), lanes 1..4: an^(1 + alpha), an^(3 + alpha),
-    // an^(2 alpha + 1), an^(2 alpha)
+    // lane 0: abar^(alpha - 3), lanes 1..5: an^(1 + alpha), an^(3 + alpha),
+    // an^(2 alpha + 1), an^(2 alpha), an^(alpha - 3)
     double ex = P.alpha - 3.0;
     if (lane == 1) ex = 1.0 + P.alpha;
     if (lane == 2) ex = 3.0 + P.alpha;
     if (lane == 3) ex = 2.0 * P.alpha + 1.0;
     if (lane == 4) ex = 2.0 * P.alpha;
-    const double pw = (h_next != 0.0 && lane < 5) ? pow(lane == 0 ? abar : an, ex) : 0.0;
+    const double pw = (h_next != 0.0 && lane < 6) ? pow(lane == 0 ? abar : an, ex) : 0.0;
     const double abar_al3 = __shfl(pw, 0, 64), an_1al = __shfl(pw, 1, 64), an_3al = __shfl(pw, 2, 64);
-    const double an_2al1 = __shfl(pw, 3, 64), an_2al = __shfl(pw, 4, 64);
+    const double an_2al1 = __shfl(pw, 3, 64), an_2al = __shfl(pw, 4, 64), an_al3 = __shfl(pw, 5, 64);
     if (lane != 0) return;
     if (rec_out) {
         cl_observables o;
@@ -178,12 +178,103 @@ __device__ __forceinline__ void finish_pass(const Phys& P, Scal* sc, double kt, 
         sc->a_next = an;
         sc->pa1 = an_2al1;
         sc->pa0 = an_2al;
+        sc->pf = an_al3;
         sc->eta += h_next;
         for (int j = 0; j < 2; ++j) sc->shift[j] = mean[j] + sc->cd * meanp[j];
     } else {
         sc->cd = 0.0;
         sc->a_next = a;
         for (int j = 0; j < 2; ++j) sc->shift[j] = mean[j];
+    }
+}
+
+// The scalar step after a low-storage Runge-Kutta stage.  The sums in `tot`
+// describe the stage's input state y_i at scale factor a = sc->a (momenta and
+// fields at the same time): record the observables of y_i (if rec_out), then
+// advance (a, a') by the same recurrence as the fields,
+//   d_a <- A d_a + h a',  d_b <- A d_b + h a''(a, E(y_i)),  a += B d_a, a' += B d_b,
+// and form the next stage's coefficients at the new a (all 64 lanes of one
+// wave call; the powers are spread over lanes; lane 0 writes).
+__device__ __forceinline__ void finish_rk(const Phys& P, Scal* sc, double rkA, double rkB, double h, double deta,
+                                          cl_observables* rec_out, const double* tot) {
+    const int lane = threadIdx.x & 63;
+    const int nf = P.nf;
+    const double a = sc->a, b = sc->b;
+    const double a2 = a * a;
+    const double a6 = a2 * a2 * a2;
+    double EK[2] = {0.0, 0.0}, EG[2] = {0.0, 0.0}, mean[2] = {0.0, 0.0};
+    double var[2] = {0.0, 0.0}, meanp[2] = {0.0, 0.0};
+    int bad = 0;
+    for (int j = 0; j < nf; ++j) {
+        const double* t = tot + kSumsPerField * j;
+        EK[j] = t[0] * P.inv_vol / (2.0 * a6);
+        EG[j] = t[1] * P.inv_vol / (2.0 * a2 * P.dx * P.dx);
+        const double m1 = t[2] * P.inv_vol;
+        const double c = P.fp32 ? static_cast<double>(static_cast<float>(sc->shift[j])) : sc->shift[j];
+        mean[j] = c + m1;
+        var[j] = t[3] * P.inv_vol - m1 * m1;
+        meanp[j] = t[4] * P.inv_vol;
+    }
+    const double EV = tot[kSumsPerField * nf] * P.inv_vol + P.V0;
+    for (int k = 0; k < nsums(nf); ++k) bad |= !isfinite(tot[k]);
+    const double K = EK[0] + EK[1], G = EG[0] + EG[1];
+    const double rho = K + G + EV;
+    const double pr = K - G / 3.0 - EV;
+    double acc = 0.0, r = 0.0;
+    if (P.expand) {
+        acc = sc->pa1 * ((2.0 * P.alpha - 1.0) * rho - 3.0 * pr) / (6.0 * P.mp * P.mp);
+        const double rhs = sc->pa0 * rho / (3.0 * P.mp * P.mp);
+        const double H = b / a;
+        r = fabs(H * H - rhs) / rhs;
+    }
+    const double da = rkA * sc->da + h * b;
+    const double db = rkA * sc->db + h * acc;
+    const double an = P.expand ? a + rkB * da : a;
+    const double bn = P.expand ? b + rkB * db : b;
+    // lanes 0..4: an^(alpha - 3), an^(1 + alpha), an^(3 + alpha), an^(2 alpha + 1), an^(2 alpha)
+    double ex = P.alpha - 3.0;
+    if (lane == 1) ex = 1.0 + P.alpha;
+    if (lane == 2) ex = 3.0 + P.alpha;
+    if (lane == 3) ex = 2.0 * P.alpha + 1.0;
+    if (lane == 4) ex = 2.0 * P.alpha;
+    const double pw = lane < 5 ? pow(an, ex) : 0.0;
+    const double an_al3 = __shfl(pw, 0, 64), an_1al = __shfl(pw, 1, 64), an_3al = __shfl(pw, 2, 64);
+    const double an_2al1 = __shfl(pw, 3, 64), an_2al = __shfl(pw, 4, 64);
+    if (lane != 0) return;
+    if (rec_out) {
+        cl_observables o;
+        o.eta = sc->eta;
+        o.a = a;
+        o.H = b / a;
+        for (int j = 0; j < 2; ++j) {
+            o.EK[j] = EK[j];
+            o.EG[j] = EG[j];
+            o.mean[j] = mean[j];
+            o.var[j] = var[j];
+        }
+        o.EV = EV;
+        o.hubble_residual = r;
+        o.nonfinite = bad;
+        o.reserved = 0;
+        *rec_out = o;
+    }
+    sc->a = an;
+    sc->a_next = an;
+    sc->b = bn;
+    sc->da = da;
+    sc->db = db;
+    sc->eta += deta;
+    sc->nonfinite |= bad;
+    sc->cd = 0.0;
+    sc->kL = an_1al / (P.dx * P.dx);
+    sc->kV = an_3al;
+    sc->pf = an_al3;
+    sc->pa1 = an_2al1;
+    sc->pa0 = an_2al;
+    for (int j = 0; j < 2; ++j) {
+        sc->mean_f[j] = mean[j];
+        sc->mean_p[j] = meanp[j];
+        sc->shift[j] = mean[j];
     }
 }
 
@@ -290,6 +381,10 @@ struct TileJob {
     double kt, kb;
     const Scal* sc;
     const Phys* ph;
+    // Runge-Kutta stage (march_tile<..., RK = true>)
+    void* aux;
+    double rkA, rkB, rkh;
+    int rk_first;
 };
 
 // Calls f(integral_constant<int, B>), ..., f(integral_constant<int, E - 1>).
@@ -301,7 +396,12 @@ __device__ __forceinline__ void static_for(F&& f) {
     }
 }
 
-template <typename T, int NF, int RY, int HI, int PD, typename Prelude>
+// RK = false: fused drift + kick (the symplectic schemes).  RK = true: one
+// low-storage Runge-Kutta stage -- no drift (the plane staged in LDS is the
+// stage's input f), F = h (a^(alpha-3) pi, a^(1+alpha) L f - a^(3+alpha) dV),
+// d <- A d + F and y <- y + B d with the registers d of (f, pi) in `aux`
+// (loaded one plane ahead), sums over the stage's input state.
+template <typename T, int NF, int RY, int HI, int PD, bool RK, typename Prelude>
 __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem_raw, double (&acc)[kSumsPerField * NF + 1],
                            Prelude&& prelude) {
     constexpr int V = VecOf<T>::V;
@@ -329,9 +429,18 @@ __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem
     }
     const bool nt_store = J.flags & 1;
     const bool nt_load = J.flags & 2;
+    T* auxf[NF];
+    T* auxp[NF];
+#pragma unroll
+    for (int j = 0; j < NF; ++j) {
+        auxf[j] = RK ? static_cast<T*>(J.aux) + j * N : nullptr;
+        auxp[j] = RK ? static_cast<T*>(J.aux) + (NF + j) * N : nullptr;
+    }
+    const bool rk_first = RK && J.rk_first;
+    const T rA = static_cast<T>(J.rkA), rB = static_cast<T>(J.rkB);
 
     // Pass coefficients; set once the prelude has produced the scalars.
-    T cd = T(0), kL = T(0), kV = T(0);
+    T cd = T(0), kL = T(0), kV = T(0), cF = T(0);
     const T kt = static_cast<T>(J.kt);
     const T kb = static_cast<T>(J.kb);
     // Variance shift in the field precision: f - c is exact for f near c.
@@ -465,12 +574,34 @@ __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem
     prelude();
     {
         const Scal* sc = J.sc;
-        cd = J.drift ? static_cast<T>(sc->cd) : T(0);
-        kL = static_cast<T>(sc->kL);
-        kV = static_cast<T>(sc->kV);
+        if constexpr (RK) {
+            // h folded into the coefficients (formed in FP64, rounded once)
+            cF = static_cast<T>(J.rkh * sc->pf);
+            kL = static_cast<T>(J.rkh * sc->kL);
+            kV = static_cast<T>(J.rkh * sc->kV);
+        } else {
+            cd = J.drift ? static_cast<T>(sc->cd) : T(0);
+            kL = static_cast<T>(sc->kL);
+            kV = static_cast<T>(sc->kV);
+        }
 #pragma unroll
         for (int j = 0; j < NF; ++j) shift[j] = static_cast<T>(sc->shift[j]);
     }
+    // Runge-Kutta registers of (f, pi) for the current plane and the next one.
+    T axc[RK ? 2 : 1][NF][RY][V], axn[RK ? 2 : 1][NF][RY][V];
+    auto aux_load = [&](int k, T (&dst)[RK ? 2 : 1][NF][RY][V]) {
+        if constexpr (RK) {
+            const size_t base = static_cast<size_t>(x0 + k) * static_cast<size_t>(N) * rs;
+#pragma unroll
+            for (int j = 0; j < NF; ++j)
+#pragma unroll
+                for (int r = 0; r < RY; ++r) {
+                    vload(auxf[j] + base + yrow[r], dst[0][j][r]);
+                    vload(auxp[j] + base + yrow[r], dst[RK ? 1 : 0][j][r]);
+                }
+        }
+    };
+    if (RK && !rk_first) aux_load(0, axc);
     consume(S0{}, prev, pn, -1);
     issue(S0{}, 0);
     consume(S0{}, cur, pc, 0);
@@ -488,6 +619,7 @@ __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem
         const int buf = i & 1;
         consume(Sc, nxt, pn, i + 1 < CX ? (buf ^ 1) : -1);
         if (i + 1 + PD <= CX) issue(Sc, i + 1 + PD);
+        if (RK && !rk_first && i + 1 < CX) aux_load(i + 1, axn);
 
         const T* L0 = lds + static_cast<size_t>(buf) * NF * PL;
         const size_t base = static_cast<size_t>(x) * plane;
@@ -508,7 +640,7 @@ __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem
                 zm0[j] = Lj[row * S + col - 1];
                 zp0[j] = Lj[row * S + col + V];
             }
-            T pnew[NF][V];
+            T pnew[NF][V], fnew[NF][V], dfo[NF][V], dpo[NF][V];
 #pragma unroll
             for (int v = 0; v < V; ++v) {
                 T fs[NF], dV[NF];
@@ -534,23 +666,47 @@ __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem
                     const T nb = ((prev[j][k][v] + xp) + (ym[j][v] + yp[j][v])) + (zm + zp);
                     const T F = fmad(kL, fmad(T(-6), f, nb), -(kV * dV[j]));
                     const T po = pc[j][k][v];
-                    const T p1 = fmad(kt, F, po);
-                    const T ps = fmad(kb, F, po);
-                    pnew[j][v] = p1;
                     const T gx = xp - f, gy = yp[j][v] - f, gz = zp - f;
                     const T d = f - shift[j];
                     T* q5 = part + kSumsPerField * j;
-                    q5[0] = fmad(ps, ps, q5[0]);
+                    if constexpr (RK) {
+                        const T Ff = cF * po;
+                        const T dfn = rk_first ? Ff : fmad(rA, axc[0][j][k][v], Ff);
+                        const T dpn = rk_first ? F : fmad(rA, axc[RK ? 1 : 0][j][k][v], F);
+                        dfo[j][v] = dfn;
+                        dpo[j][v] = dpn;
+                        fnew[j][v] = fmad(rB, dfn, f);
+                        pnew[j][v] = fmad(rB, dpn, po);
+                        q5[0] = fmad(po, po, q5[0]);
+                        q5[4] += po;
+                    } else {
+                        const T p1 = fmad(kt, F, po);
+                        const T ps = fmad(kb, F, po);
+                        pnew[j][v] = p1;
+                        q5[0] = fmad(ps, ps, q5[0]);
+                        q5[4] += p1;
+                    }
                     q5[1] = fmad(gz, gz, fmad(gy, gy, fmad(gx, gx, q5[1])));
                     q5[2] += d;
                     q5[3] = fmad(d, d, q5[3]);
-                    q5[4] += p1;
                 }
             }
             if (J.write_out) {
 #pragma unroll
                 for (int j = 0; j < NF; ++j) {
-                    if (nt_store) {
+                    if constexpr (RK) {
+                        if (nt_store) {
+                            vstore_nt(fout[j] + base + yrow[k], fnew[j]);
+                            vstore_nt(pout[j] + base + yrow[k], pnew[j]);
+                            vstore_nt(auxf[j] + base + yrow[k], dfo[j]);
+                            vstore_nt(auxp[j] + base + yrow[k], dpo[j]);
+                        } else {
+                            vstore(fout[j] + base + yrow[k], fnew[j]);
+                            vstore(pout[j] + base + yrow[k], pnew[j]);
+                            vstore(auxf[j] + base + yrow[k], dfo[j]);
+                            vstore(auxp[j] + base + yrow[k], dpo[j]);
+                        }
+                    } else if (nt_store) {
                         vstore_nt(fout[j] + base + yrow[k], cur[j][k]);
                         vstore_nt(pout[j] + base + yrow[k], pnew[j]);
                     } else {
@@ -572,6 +728,10 @@ __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem
                     prev[j][k][v] = cur[j][k][v];
                     cur[j][k][v] = nxt[j][k][v];
                     pc[j][k][v] = pn[j][k][v];
+                    if constexpr (RK) {
+                        axc[0][j][k][v] = axn[0][j][k][v];
+                        axc[RK ? 1 : 0][j][k][v] = axn[RK ? 1 : 0][j][k][v];
+                    }
                 }
     };
     for (int i = 0; i < CX; i += PD) {
@@ -582,7 +742,7 @@ __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem
     }
 }
 
-template <typename T, int NF, int RY, int HI, int PD>
+template <typename T, int NF, int RY, int HI, int PD, bool RK>
 __global__ __launch_bounds__(256) void lattice_pass(PassArgs A) {
     constexpr int NS = kSumsPerField * NF + 1;
     const int nblocks = A.nbz * A.nby * A.nbx;
@@ -611,6 +771,11 @@ __global__ __launch_bounds__(256) void lattice_pass(PassArgs A) {
     J.kt = A.kt;
     J.kb = A.kb;
     J.ph = &A.ph;
+    J.aux = A.aux;
+    J.rkA = A.rkA;
+    J.rkB = A.rkB;
+    J.rkh = A.rkh;
+    J.rk_first = A.rk_first;
     __shared__ Scal s_sc;
     __shared__ double tot[kMaxSums];
     J.sc = &s_sc;
@@ -627,6 +792,8 @@ __global__ __launch_bounds__(256) void lattice_pass(PassArgs A) {
     const double* prev_part = A.prev_partials;
     const int prev_nslots = A.prev_nslots, has_prev = A.has_prev;
     const double pkt = A.pkt, pkb = A.pkb, phn = A.phn;
+    const int prev_rk = A.prev_rk;
+    const double prkA = A.prkA, prkB = A.prkB, prkh = A.prkh, prkdeta = A.prkdeta;
     cl_observables* prev_rec = (bid == 0 && A.prev_rec >= 0) ? A.obs + A.prev_rec : nullptr;
     Scal* ssc = &s_sc;
     double* stot = tot;
@@ -646,7 +813,10 @@ __global__ __launch_bounds__(256) void lattice_pass(PassArgs A) {
             if (t < NW) dst[t] = w0;
             if (t + NT < NW) dst[t + NT] = w1;
             __syncthreads();
-            if (threadIdx.x < 64) finish_pass(*php, ssc, pkt, pkb, phn, prev_rec, stot);
+            if (threadIdx.x < 64) {
+                if (prev_rk) finish_rk(*php, ssc, prkA, prkB, prkh, prkdeta, prev_rec, stot);
+                else finish_pass(*php, ssc, pkt, pkb, phn, prev_rec, stot);
+            }
             __syncthreads();
             if (sc_out) copy_scal(sc_out, ssc, NT);
         } else {
@@ -655,7 +825,7 @@ __global__ __launch_bounds__(256) void lattice_pass(PassArgs A) {
             __syncthreads();
         }
     };
-    march_tile<T, NF, RY, HI, PD>(J, smem_raw, acc, prelude);
+    march_tile<T, NF, RY, HI, PD, RK>(J, smem_raw, acc, prelude);
     block_sum<NS>(acc, NT, tot);
     if (threadIdx.x == 0)
         for (int k = 0; k < NS; ++k) A.partials[(size_t)k * nblocks + bid] = tot[k];
@@ -669,8 +839,11 @@ __global__ __launch_bounds__(256) void finish_kernel(PassArgs A) {
     __shared__ double tot[kMaxSums];
     copy_scal(&s_sc, A.sc_in, blockDim.x);
     slots_sum<NS>(A.prev_partials, blockDim.x, A.prev_nslots, tot);
-    if (threadIdx.x < 64)
-        finish_pass(A.ph, &s_sc, A.pkt, A.pkb, A.phn, A.prev_rec >= 0 ? A.obs + A.prev_rec : nullptr, tot);
+    cl_observables* rec = A.prev_rec >= 0 ? A.obs + A.prev_rec : nullptr;
+    if (threadIdx.x < 64) {
+        if (A.prev_rk) finish_rk(A.ph, &s_sc, A.prkA, A.prkB, A.prkh, A.prkdeta, rec, tot);
+        else finish_pass(A.ph, &s_sc, A.pkt, A.pkb, A.phn, rec, tot);
+    }
     __syncthreads();
     copy_scal(A.sc_out, &s_sc, blockDim.x);
 }
@@ -694,6 +867,9 @@ __global__ void init_scalars_kernel(Scal* sc, double a, double b, double eta, do
     s.mean_p[1] = 0.0;
     s.pa1 = pow(a, 2.0 * alpha + 1.0);
     s.pa0 = pow(a, 2.0 * alpha);
+    s.pf = pow(a, alpha - 3.0);
+    s.da = 0.0;
+    s.db = 0.0;
     s.nonfinite = 0;
     s.pad = 0;
     *sc = s;
@@ -830,10 +1006,13 @@ __global__ __launch_bounds__(256) void ensemble_pass(EnsArgs E) {
         J.kb = kb;
         J.sc = M.sc;
         J.ph = &M.ph;
+        J.aux = nullptr;
+        J.rkA = J.rkB = J.rkh = 0.0;
+        J.rk_first = 0;
         double acc[NS];
 #pragma unroll
         for (int k = 0; k < NS; ++k) acc[k] = 0.0;
-        march_tile<T, NF, 1, 1, 2>(J, smem_raw, acc, [] {});
+        march_tile<T, NF, 1, 1, 2, false>(J, smem_raw, acc, [] {});
         if (reduce_partials<NS>(acc, 256, M.partials, I.tile, M.nitems, M.ticket, tot) && threadIdx.x < 64)
             finish_pass(M.ph, M.sc, kt, kb, hn, E.rec >= 0 ? E.obs + (size_t)E.rec * E.nmembers + I.member : nullptr,
                         tot);
@@ -916,18 +1095,20 @@ void candidate_tiles(int N, cl_precision prec, int nf, Tile* out, int* count, in
     *count = n;
 }
 
-template <typename T, int NF, int RY, int HI, int PD>
+template <typename T, int NF, int RY, int HI, int PD, bool RK>
 static hipError_t launch_t(const PassArgs& a, const Tile& t, hipStream_t s, size_t lds) {
-    hipLaunchKernelGGL((lattice_pass<T, NF, RY, HI, PD>), dim3(t.nblocks()), dim3(t.NT), lds, s, a);
+    hipLaunchKernelGGL((lattice_pass<T, NF, RY, HI, PD, RK>), dim3(t.nblocks()), dim3(t.NT), lds, s, a);
     return hipGetLastError();
 }
 
 template <typename T, int NF, int RY, int HI>
 static hipError_t launch_pd(const PassArgs& a, const Tile& t, hipStream_t s, size_t lds) {
+    // Runge-Kutta stages: prefetch depth 1 or 2 (a depth-4 tile runs them at 2)
+    if (a.rk) return t.PD == 1 ? launch_t<T, NF, RY, HI, 1, true>(a, t, s, lds) : launch_t<T, NF, RY, HI, 2, true>(a, t, s, lds);
     if constexpr (RY == 1) {
-        if (t.PD == 4) return launch_t<T, NF, RY, HI, 4>(a, t, s, lds);
+        if (t.PD == 4) return launch_t<T, NF, RY, HI, 4, false>(a, t, s, lds);
     }
-    return t.PD == 2 ? launch_t<T, NF, RY, HI, 2>(a, t, s, lds) : launch_t<T, NF, RY, HI, 1>(a, t, s, lds);
+    return t.PD == 2 ? launch_t<T, NF, RY, HI, 2, false>(a, t, s, lds) : launch_t<T, NF, RY, HI, 1, false>(a, t, s, lds);
 }
 
 template <typename T, int NF>

@@ -830,6 +830,8 @@ cl_status cl_surrogate_load(cl_surrogate* s, const char* path) {
 cl_status cl_surrogate_advance(cl_lattice* h, cl_surrogate* s, cl_integrator fallback, double dt, int n_jumps,
                                double threshold, cl_observables* per_jump, cl_surrogate_report* rep) {
     if (!h || !s) return sfail(CL_EINVAL, "NULL argument");
+    if (fallback != CL_LEAPFROG && fallback != CL_VV4)
+        return sfail(CL_EINVAL, "the fallback integrator must be leapfrog or VV4");
     if (h->nf != s->cfg.n_fields) return sfail(CL_EINVAL, "lattice fields do not match the surrogate");
     if (!valid_net_N(h->N)) return sfail(CL_EINVAL, "lattice N must be a power of two >= 16");
     if (!s->scaled) return sfail(CL_ESTATE, "surrogate has no normalisation (train or load it first)");
