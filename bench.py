@@ -372,6 +372,40 @@ def surrogate_run(epochs=12, pairs_per_seed=64, train_seeds=range(2000, 2008), e
     return out
 
 
+def rk_bytes_per_step(stages: int, precision: str, nf: int) -> int:
+    """Algorithmic bytes per site of one low-storage Runge-Kutta step: the
+    first stage reads f, pi and writes f, pi and their registers; every
+    later stage also reads the registers."""
+    e = 4 if precision == "fp32" else 8
+    return nf * e * (6 + 8 * (stages - 1))
+
+
+def rk_run(w, steps, r64, tile):
+    """RK4-5 (5 stages) in FP32 on the same workload and tile, from the same
+    seed: rate, HBM fraction and deviation from the FP64 VV4 run over the
+    same steps."""
+    import torch
+    stream = torch.cuda.Stream()
+    lat = make(w, "fp32", stream, tune=False,
+               tile=(tile["tz"], tile["ty"], tile["cx"], tile["ry"], tile["pd"]))
+    chunk = min(steps, 100)
+    recs = [lat.step("rk4", w.dt, chunk)]   # untimed first call (graph capture)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps // chunk - 1):
+        recs.append(lat.step("rk4", w.dt, chunk))
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    lat.close()
+    timed = (steps // chunk - 1) * chunk
+    r = np.concatenate(recs)
+    alg = rk_bytes_per_step(5, "fp32", w.n_fields) * w.sites * timed / sec / 1e9
+    return {"scheme": "rk4 (Carpenter-Kennedy 5-stage)", "steps": timed,
+            "site_updates_per_s": w.sites * timed / sec, "ms_per_step": 1e3 * sec / timed,
+            "hbm_frac": alg / HBM_PEAK_GBS, "bytes_per_site_step": rk_bytes_per_step(5, "fp32", w.n_fields),
+            "vs_fp64_vv4_rel_dev": linear_regime_deviation(r, r64[:len(r)], w.n_fields)}
+
+
 def cpu_baseline(w, steps=1):
     """The FP64 oracle as it stands, on the same 256^3 workload, for a bounded
     number of full steps on the host (numpy, single thread)."""
@@ -461,6 +495,9 @@ def main():
         forms["fp64"] = {"site_updates_per_s": w.sites * args.steps / sec64, "hbm_frac": ach64 / HBM_PEAK_GBS}
         forms["fp32_vs_fp64_rel_dev"] = linear_regime_deviation(r32, r64, w.n_fields)
         forms["fp32_speedup_vs_fp64"] = value / forms["fp64"]["site_updates_per_s"]
+        if args.workload == "c1":
+            progress("rk4 form")
+            forms["rk4_fp32"] = rk_run(w, 1000, r64, tile32)
     if not args.no_batched and args.workload == "c1":
         progress("batched ensemble form")
         forms["batched"] = batched_run(1000, 500)
