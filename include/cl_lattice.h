@@ -227,9 +227,9 @@ cl_status cl_ensemble_set_dt(cl_ensemble* e, int member, double dt);
 /* out: NULL or n_steps * n_members records, step-major ([s][member]).
  * integ: CL_LEAPFROG or CL_VV4 (the Runge-Kutta schemes: CL_EUNSUPPORTED). */
 cl_status cl_ensemble_step(cl_ensemble* e, cl_integrator integ, int n_steps, cl_observables* out);
-/* Tile the ensemble kernel uses for one member (ry = 1, pd = 2).  A member
- * stepped on its own with this tile (cl_set_tile) gives bitwise the same
- * result as inside the ensemble. */
+/* Tile the ensemble kernel uses for one member (two rows per thread where
+ * the lattice is tall enough).  A member stepped on its own with this tile
+ * (cl_set_tile) gives bitwise the same result as inside the ensemble. */
 cl_status cl_ensemble_get_tile(const cl_ensemble* e, int member, cl_tile* out);
 cl_status cl_ensemble_destroy(cl_ensemble* e);
 

@@ -110,10 +110,10 @@ struct PassArgs {
 // Refreshed from the member handles before every ensemble call.
 struct EnsMember {
     void* buf[2];        // state buffers; a pass reads buf[cur0 ^ parity]
-    int N, TZ, TY, CX;   // tile (TZ * TY / vector width == 256 threads)
+    int N, TZ, TY, CX;   // tile (TZ * TY / (vector width * RY) == 256 threads)
     int nbz, nby, nbx, nitems;
     int cur0;            // buffer holding the state when the call starts
-    int pad;
+    int RY;              // rows per thread (1 or 2)
     double dt;
     Phys ph;
     Scal* sc;

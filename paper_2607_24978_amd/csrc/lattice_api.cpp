@@ -941,9 +941,12 @@ bool ensemble_tile(int N, cl_precision prec, cl::EnsMember& t) {
     if (t.TZ % V || N % t.TZ) return false;
     const int BZ = t.TZ / V;
     if (256 % BZ) return false;
-    t.TY = 256 / BZ;
+    // two rows per thread where the lattice is tall enough: twice the work
+    // per plane against the same per-plane barriers and LDS round trips
+    t.RY = (2 * 256 / BZ <= N && N % (2 * 256 / BZ) == 0) ? 2 : 1;
+    t.TY = t.RY * 256 / BZ;
     if (t.TY > N || N % t.TY) return false;
-    int cx = 16384 / (t.TZ * t.TY);
+    int cx = 32768 / (t.TZ * t.TY);
     if (cx < 2) cx = 2;
     while (cx > N || N % cx) cx /= 2;
     if (cx < 1) return false;
@@ -1155,8 +1158,8 @@ cl_status cl_ensemble_get_tile(const cl_ensemble* e, int i, cl_tile* out) {
     out->tz = t.TZ;
     out->ty = t.TY;
     out->cx = t.CX;
-    out->ry = 1;
-    out->pd = 2;
+    out->ry = t.RY;
+    out->pd = t.RY == 1 ? 4 : 2;  // the prefetch depth does not change the results
     return CL_OK;
 }
 

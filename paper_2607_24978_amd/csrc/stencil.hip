@@ -1012,7 +1012,8 @@ __global__ __launch_bounds__(256) void ensemble_pass(EnsArgs E) {
         double acc[NS];
 #pragma unroll
         for (int k = 0; k < NS; ++k) acc[k] = 0.0;
-        march_tile<T, NF, 1, 1, 2, false>(J, smem_raw, acc, [] {});
+        if (M.RY == 2) march_tile<T, NF, 2, 1, 4, false>(J, smem_raw, acc, [] {});
+        else march_tile<T, NF, 1, 1, 4, false>(J, smem_raw, acc, [] {});
         if (reduce_partials<NS>(acc, 256, M.partials, I.tile, M.nitems, M.ticket, tot) && threadIdx.x < 64)
             finish_pass(M.ph, M.sc, kt, kb, hn, E.rec >= 0 ? E.obs + (size_t)E.rec * E.nmembers + I.member : nullptr,
                         tot);
