@@ -20,6 +20,8 @@ Contents
                 fpr_influct2; Sect. 4.3 DFT convention).
   surrogate  -- periodic 3D convolution net in FP64 (forward, backward,
                 MSE, Adam) used to check the learned-surrogate kernels.
+  spectrum   -- DFT power spectrum in spherical bins of arbitrary width
+                (Sect. 4.3, Eqs. discretePSaux, discretePST2).
 
 Parity unpinned (the paper is silent; the oracle and the library share a
 written reading instead of a paper value): the reduced Planck mass in
