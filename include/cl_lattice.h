@@ -183,6 +183,21 @@ cl_status cl_step(cl_lattice* h, cl_integrator integ, double dt, int n, cl_obser
 /* Observables of the current state (one reduction pass over the lattice). */
 cl_status cl_read_observables(cl_lattice* h, cl_observables* out);
 
+/* Power spectrum of one array of the current state (Sect. 4.3, Eqs.
+ * discretePSaux, discretePST2): field `field`, what = 0 for f, 1 for pi.  The
+ * DFT f(n~) = sum_n exp(-2 pi i n~.n / N) f(n) (n~_i in -N/2+1 .. N/2) is
+ * computed on the device in FP64; the modes are binned by |n~| into centred
+ * shells of width `width` (bin l: l w - w/2 <= |n~| < l w + w/2; w = 1 is the
+ * canonical binning), bins l = 0 .. nbins-1 (nbins <= 4096; modes beyond are
+ * dropped).  Outputs (host arrays of nbins, each may be NULL): counts[l] --
+ * modes in the bin (exact); sums[l] -- sum of |f(n~)|^2 over the bin (FP64,
+ * accumulated with atomics, so equal between calls to rounding only);
+ * delta[l] = (k_l / 2 pi) (dx / N^5) sums[l] with k_l = k_IR l w, the
+ * exact-multiplicity form of Eq. discretePST2.  N must be a power of two.
+ * Uses a device buffer of 16 N^3 bytes, allocated on first use. */
+cl_status cl_power_spectrum(cl_lattice* h, int field, int what, double width, int nbins, int64_t* counts,
+                            double* sums, double* delta);
+
 /* Work decomposition of the lattice passes: each workgroup owns a tz x ty
  * tile of (z, y) and marches over cx x-planes; ry is the number of y rows per
  * thread (1 or 2) and pd the number of x-planes whose loads are kept in

@@ -79,6 +79,7 @@ _P = C.c_void_p
 _SIGS = {
     "cl_last_error": (C.c_char_p, [_P]),
     "cl_version": (C.c_char_p, []),
+    "cl_power_spectrum": (C.c_int, [_P, C.c_int, C.c_int, C.c_double, C.c_int, _P, _P, _P]),
     "cl_create": (C.c_int, [C.c_int, C.c_double, C.c_int, C.c_int, C.POINTER(_P)]),
     "cl_destroy": (C.c_int, [_P]),
     "cl_set_stream": (C.c_int, [_P, _P]),
@@ -239,6 +240,18 @@ class Lattice:
         buf = C.create_string_buffer(1 << 16)
         _check(lib.cl_autotune(self.h, int(reps), buf, len(buf)), self.h)
         return json.loads(buf.value.decode())
+
+    def power_spectrum(self, field: int = 0, what: str = "f", width: float = 1.0, nbins: int | None = None):
+        """(k, counts, sums, delta) of the binned power spectrum of f_field or pi_field."""
+        if nbins is None:
+            nbins = int(np.ceil(np.sqrt(3.0) * (self.N // 2) / width)) + 1
+        counts = np.zeros(nbins, dtype=np.int64)
+        sums = np.zeros(nbins, dtype=np.float64)
+        delta = np.zeros(nbins, dtype=np.float64)
+        _check(lib.cl_power_spectrum(self.h, int(field), 0 if what == "f" else 1, float(width), int(nbins),
+                                     _P(counts.ctypes.data), _P(sums.ctypes.data), _P(delta.ctypes.data)), self.h)
+        k = 2.0 * np.pi / (self.N * self.dx) * width * np.arange(nbins)
+        return k, counts, sums, delta
 
     def read_observables(self):
         out = np.zeros(1, dtype=OBS_DTYPE)

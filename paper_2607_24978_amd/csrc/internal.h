@@ -147,6 +147,11 @@ int ensemble_grid(cl_precision prec, int nf, size_t lds);
 hipError_t launch_pass(const PassArgs& a, const Tile& t, cl_precision prec, hipStream_t s);
 // One workgroup of t.NT threads: the pending scalar step of the last pass.
 hipError_t launch_finish(const PassArgs& a, const Tile& t, int nf, hipStream_t s);
+// Power spectrum (spectrum.hip).
+hipError_t launch_spec_extract(const void* state, bool fp32, int N, int nf, int arr, double2* out, hipStream_t s);
+hipError_t launch_spec_fft(double2* data, const double2* tw, int N, int axis, hipStream_t s);
+hipError_t launch_spec_bin(const double2* F, int N, double width, int nbins, double* sums,
+                           unsigned long long* counts, hipStream_t s);
 hipError_t launch_init_scalars(Scal* sc, double a, double b, double eta, const Phys& ph,
                                const double* shift, hipStream_t s);
 // Default tile for a lattice; valid for every N accepted by cl_create.
@@ -193,6 +198,11 @@ struct cl_lattice {
     int device = 0;
     void* buf[2] = {nullptr, nullptr};  // ping-pong state buffers (row-interleaved layout)
     void* aux = nullptr;                // Runge-Kutta registers of f and pi (same layout), on first use
+    double2* spec = nullptr;            // power spectrum: N^3 complex FP64, on first use
+    double2* spec_tw = nullptr;         // its twiddle factors (N / 2)
+    double* spec_sums = nullptr;        // per-bin sums and counts (spec_cap bins)
+    unsigned long long* spec_counts = nullptr;
+    int spec_cap = 0;
     int pass_flags = 1;                 // nontemporal stores
     int cur = 0;
     cl::Scal* sc = nullptr;

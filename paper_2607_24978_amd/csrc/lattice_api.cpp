@@ -525,6 +525,8 @@ cl_status cl_destroy(cl_lattice* h) {
     drop_graph(h);
     free_buffers(h);
     if (h->aux) hipFree(h->aux);
+    for (void* q : {(void*)h->spec, (void*)h->spec_tw, (void*)h->spec_sums, (void*)h->spec_counts})
+        if (q) hipFree(q);
     if (h->sc) hipFree(h->sc);
     if (h->partials) hipFree(h->partials);
     if (h->scb) hipFree(h->scb);
@@ -720,6 +722,63 @@ cl_status cl_read_observables(cl_lattice* h, cl_observables* out) {
     cl_status st = reduce_pass(h, &o);
     if (st) return st;
     return reduce_pass(h, out);
+}
+
+cl_status cl_power_spectrum(cl_lattice* h, int field, int what, double width, int nbins, int64_t* counts,
+                            double* sums, double* delta) {
+    if (!h) return fail(nullptr, CL_EINVAL, "handle is NULL");
+    if (field < 0 || field >= h->nf) return fail(h, CL_EINVAL, "field index out of range");
+    if (what != 0 && what != 1) return fail(h, CL_EINVAL, "what must be 0 (f) or 1 (pi)");
+    if (!(width > 0.0) || !std::isfinite(width)) return fail(h, CL_EINVAL, "bin width must be positive");
+    if (nbins < 1 || nbins > 4096) return fail(h, CL_EINVAL, "nbins must be in [1, 4096]");
+    if ((h->N & (h->N - 1)) != 0) return fail(h, CL_EUNSUPPORTED, "the spectrum needs N a power of two");
+    const int N = h->N;
+    const size_t n3 = sites(h);
+    if (!h->spec) {
+        if (hipMalloc(&h->spec, n3 * sizeof(double2)) != hipSuccess) {
+            h->spec = nullptr;
+            return fail(h, CL_ENOMEM, "spectrum buffer (" + std::to_string(n3 * sizeof(double2)) + " bytes)");
+        }
+        // twiddles exp(-2 pi i k / N), formed in long double and rounded once
+        std::vector<double2> tw(N / 2);
+        const long double pi = 3.141592653589793238462643383279502884L;
+        for (int k = 0; k < N / 2; ++k) {
+            const long double t = -2.0L * pi * k / N;
+            tw[k] = make_double2(static_cast<double>(std::cos(t)), static_cast<double>(std::sin(t)));
+        }
+        HIPCHECK(h, hipMalloc(&h->spec_tw, (N / 2 > 0 ? N / 2 : 1) * sizeof(double2)));
+        HIPCHECK(h, hipMemcpyAsync(h->spec_tw, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice, h->stream));
+    }
+    if (h->spec_cap < nbins) {
+        if (h->spec_sums) hipFree(h->spec_sums);
+        if (h->spec_counts) hipFree(h->spec_counts);
+        h->spec_sums = nullptr;
+        h->spec_counts = nullptr;
+        h->spec_cap = 0;
+        HIPCHECK(h, hipMalloc(&h->spec_sums, nbins * sizeof(double)));
+        HIPCHECK(h, hipMalloc(&h->spec_counts, nbins * sizeof(unsigned long long)));
+        h->spec_cap = nbins;
+    }
+    const int arr = what == 0 ? field : h->nf + field;
+    HIPCHECK(h, cl::launch_spec_extract(h->buf[h->cur], h->prec == CL_FP32, N, h->nf, arr, h->spec, h->stream));
+    for (int axis = 0; axis < 3; ++axis) HIPCHECK(h, cl::launch_spec_fft(h->spec, h->spec_tw, N, axis, h->stream));
+    HIPCHECK(h, hipMemsetAsync(h->spec_sums, 0, nbins * sizeof(double), h->stream));
+    HIPCHECK(h, hipMemsetAsync(h->spec_counts, 0, nbins * sizeof(unsigned long long), h->stream));
+    HIPCHECK(h, cl::launch_spec_bin(h->spec, N, width, nbins, h->spec_sums, h->spec_counts, h->stream));
+    std::vector<double> s(nbins);
+    std::vector<unsigned long long> c(nbins);
+    HIPCHECK(h, hipMemcpyAsync(s.data(), h->spec_sums, nbins * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHECK(h, hipMemcpyAsync(c.data(), h->spec_counts, nbins * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                               h->stream));
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    const double k_ir = 2.0 * M_PI / (N * h->dx);
+    const double n5 = std::pow(static_cast<double>(N), 5.0);
+    for (int l = 0; l < nbins; ++l) {
+        if (counts) counts[l] = static_cast<int64_t>(c[l]);
+        if (sums) sums[l] = s[l];
+        if (delta) delta[l] = (k_ir * width * l) / (2.0 * M_PI) * h->dx / n5 * s[l];
+    }
+    return CL_OK;
 }
 
 cl_status cl_get_tile(const cl_lattice* h, cl_tile* out) {

@@ -1,0 +1,166 @@
+// Power spectrum of one lattice array (Sect. 4.3, Eqs. discretePSaux,
+// discretePST2): the forward DFT f(n~) = sum_n exp(-2 pi i n~.n / N) f(n) in
+// FP64 as three passes of radix-2 line transforms (z, then y, then x), and
+// the binning of |f(n~)|^2 into centred spherical shells of |n~|.
+//
+// Line transform: a workgroup stages L lines of N complex values in LDS
+// (L N = 4096 at most: 64 KB), loaded in bit-reversed order, and runs the
+// log2 N butterfly stages of an iterative decimation-in-time FFT with a
+// barrier between stages.  For the z axis the L lines are consecutive rows;
+// for the y and x axes they are L consecutive z positions of one y-z (x-z)
+// slab, so every global access moves L consecutive complex values.
+#include "internal.h"
+
+#include <hip/hip_runtime.h>
+#include <algorithm>
+#include <cstdint>
+
+namespace cl {
+
+struct SpecFftArgs {
+    double2* data;       // N^3 complex, site (x N + y) N + z
+    const double2* tw;   // exp(-2 pi i k / N), k < N / 2
+    int N, logN, L, axis;  // axis 0: z, 1: y, 2: x
+};
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+}
+
+// Global index of element e of line l of batch b.
+__device__ __forceinline__ size_t line_elem(const SpecFftArgs& a, int b, int l, int e) {
+    const size_t N = a.N;
+    if (a.axis == 0) return (static_cast<size_t>(b) * a.L + l) * N + e;
+    const int per = a.N / a.L;  // batches per slab
+    const size_t outer = b / per, z = static_cast<size_t>(b % per) * a.L + l;
+    if (a.axis == 1) return (outer * N + e) * N + z;      // x = outer, y = e
+    return (static_cast<size_t>(e) * N + outer) * N + z;  // x = e, y = outer
+}
+
+__global__ __launch_bounds__(256) void fft_lines(SpecFftArgs a) {
+    extern __shared__ double2 buf[];  // [L][N]
+    const int N = a.N, L = a.L, b = blockIdx.x;
+    const int total = L * N;
+    // load: consecutive threads take consecutive global addresses
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        int l, e;
+        if (a.axis == 0) {
+            l = idx / N;
+            e = idx % N;
+        } else {
+            e = idx / L;
+            l = idx % L;
+        }
+        const int r = static_cast<int>(__brev(static_cast<unsigned>(e)) >> (32 - a.logN));
+        buf[l * N + r] = a.data[line_elem(a, b, l, e)];
+    }
+    __syncthreads();
+    const int half = N / 2;
+    for (int m = 1; m < N; m <<= 1) {
+        const int tstride = N / (2 * m);
+        for (int t = threadIdx.x; t < L * half; t += blockDim.x) {
+            const int l = t / half, k = t % half;
+            const int pos = k % m, i = (k / m) * 2 * m + pos, j = i + m;
+            const double2 w = a.tw[pos * tstride];
+            double2* line = buf + l * N;
+            const double2 u = line[i];
+            const double2 v = cmul(line[j], w);
+            line[i] = make_double2(u.x + v.x, u.y + v.y);
+            line[j] = make_double2(u.x - v.x, u.y - v.y);
+        }
+        __syncthreads();
+    }
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        int l, e;
+        if (a.axis == 0) {
+            l = idx / N;
+            e = idx % N;
+        } else {
+            e = idx / L;
+            l = idx % L;
+        }
+        a.data[line_elem(a, b, l, e)] = buf[l * N + e];
+    }
+}
+
+// Array `arr` of the row-interleaved state -> complex (value, 0).
+template <typename T>
+__global__ void spec_extract(const T* __restrict__ state, int N, int nf, int arr, double2* __restrict__ out) {
+    const size_t n3 = static_cast<size_t>(N) * N * N;
+    for (size_t s = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; s < n3;
+         s += static_cast<size_t>(gridDim.x) * blockDim.x) {
+        const size_t z = s % N, row = s / N;
+        out[s] = make_double2(static_cast<double>(state[(row * 2 * nf + arr) * N + z]), 0.0);
+    }
+}
+
+// |F|^2 into centred shells l = floor(|n~| / w + 1/2) < nbins: per-workgroup
+// shared bins, then one global atomic per bin and workgroup.
+__global__ __launch_bounds__(256) void spec_bin(const double2* __restrict__ F, int N, double inv_w, int nbins,
+                                                double* __restrict__ sums, unsigned long long* __restrict__ counts) {
+    extern __shared__ unsigned char raw[];
+    double* s_sum = reinterpret_cast<double*>(raw);
+    unsigned* s_cnt = reinterpret_cast<unsigned*>(s_sum + nbins);
+    for (int i = threadIdx.x; i < nbins; i += blockDim.x) {
+        s_sum[i] = 0.0;
+        s_cnt[i] = 0u;
+    }
+    __syncthreads();
+    const size_t n3 = static_cast<size_t>(N) * N * N;
+    const int hN = N / 2;
+    for (size_t s = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; s < n3;
+         s += static_cast<size_t>(gridDim.x) * blockDim.x) {
+        const int z = static_cast<int>(s % N), y = static_cast<int>((s / N) % N), x = static_cast<int>(s / (static_cast<size_t>(N) * N));
+        const int nx = x <= hN ? x : x - N, ny = y <= hN ? y : y - N, nz = z <= hN ? z : z - N;
+        const double r = sqrt(static_cast<double>(nx * nx + ny * ny + nz * nz));
+        const int lb = static_cast<int>(floor(r * inv_w + 0.5));
+        if (lb < nbins) {
+            const double2 v = F[s];
+            atomicAdd(&s_sum[lb], fma(v.x, v.x, v.y * v.y));
+            atomicAdd(&s_cnt[lb], 1u);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nbins; i += blockDim.x) {
+        if (s_cnt[i]) {
+            atomicAdd(&sums[i], s_sum[i]);
+            atomicAdd(&counts[i], static_cast<unsigned long long>(s_cnt[i]));
+        }
+    }
+}
+
+int spec_lines_per_block(int N) { return N <= 64 ? N : 4096 / N; }
+
+hipError_t launch_spec_fft(double2* data, const double2* tw, int N, int axis, hipStream_t s) {
+    SpecFftArgs a;
+    a.data = data;
+    a.tw = tw;
+    a.N = N;
+    a.logN = 0;
+    while ((1 << a.logN) < N) ++a.logN;
+    a.L = spec_lines_per_block(N);
+    a.axis = axis;
+    const int batches = N * N / a.L;
+    const size_t lds = static_cast<size_t>(a.L) * N * sizeof(double2);
+    hipLaunchKernelGGL(fft_lines, dim3(batches), dim3(256), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_spec_extract(const void* state, bool fp32, int N, int nf, int arr, double2* out, hipStream_t s) {
+    const size_t n3 = static_cast<size_t>(N) * N * N;
+    const unsigned grid = static_cast<unsigned>(std::min<size_t>((n3 + 255) / 256, 8192));
+    if (fp32) hipLaunchKernelGGL(spec_extract<float>, dim3(grid), dim3(256), 0, s, static_cast<const float*>(state), N, nf, arr, out);
+    else hipLaunchKernelGGL(spec_extract<double>, dim3(grid), dim3(256), 0, s, static_cast<const double*>(state), N, nf, arr, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_spec_bin(const double2* F, int N, double width, int nbins, double* sums, unsigned long long* counts,
+                           hipStream_t s) {
+    const size_t n3 = static_cast<size_t>(N) * N * N;
+    const unsigned grid = static_cast<unsigned>(std::min<size_t>((n3 + 255) / 256, 2048));
+    const size_t lds = static_cast<size_t>(nbins) * (sizeof(double) + sizeof(unsigned));
+    hipLaunchKernelGGL(spec_bin, dim3(grid), dim3(256), lds, s, F, N, 1.0 / width, nbins, sums, counts);
+    return hipGetLastError();
+}
+
+}  // namespace cl
