@@ -406,6 +406,29 @@ def rk_run(w, steps, r64, tile):
             "vs_fp64_vv4_rel_dev": linear_regime_deviation(r, r64[:len(r)], w.n_fields)}
 
 
+def spectrum_run(w, reps=5):
+    """Cost of one power spectrum of f_0 on the workload's lattice: device
+    FFT in FP64 (extraction, three line-FFT passes, binning) plus the copy of
+    the bins; algorithmic bytes 4 (or 8) + 16 to extract, 32 per FFT pass,
+    16 to bin, per site."""
+    import torch
+    stream = torch.cuda.Stream()
+    lat = make(w, w.precision, stream, tune=False)
+    lat.power_spectrum(0, "f", 1.0)  # first call allocates
+    times = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        k, c, s, d = lat.power_spectrum(0, "f", 1.0)
+        times.append(time.perf_counter() - t0)
+    lat.close()
+    sec = float(np.median(times))
+    e = 4 if w.precision == "fp32" else 8
+    alg = (e + 16 + 3 * 32 + 16) * w.sites
+    return {"field": "f_0", "binning": "canonical (width 1)", "bins": int(len(k)), "ms": 1e3 * sec,
+            "hbm_frac": alg / sec / 1e9 / HBM_PEAK_GBS, "alg_bytes": alg}
+
+
 def cpu_baseline(w, steps=1):
     """The FP64 oracle as it stands, on the same 256^3 workload, for a bounded
     number of full steps on the host (numpy, single thread)."""
@@ -498,6 +521,9 @@ def main():
         if args.workload == "c1":
             progress("rk4 form")
             forms["rk4_fp32"] = rk_run(w, 1000, r64, tile32)
+    if args.workload == "c1":
+        progress("power spectrum form")
+        forms["spectrum"] = spectrum_run(w)
     if not args.no_batched and args.workload == "c1":
         progress("batched ensemble form")
         forms["batched"] = batched_run(1000, 500)
