@@ -492,7 +492,8 @@ __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem
 
     const size_t plane = static_cast<size_t>(N) * rs;
     // Raw (undrifted) loads of up to PD planes in flight: own values and halo
-    // items.  Set S of the ring holds planes x0+1+S, x0+1+S+PD, ...
+    // items, in a ring of PD register sets (the prologue below fixes which
+    // plane travels in which set).
     T rf[PD][NF][RY][V], rp[PD][NF][RY][V], hf[PD][NF][HI][V], hp[PD][NF][HI][V];
     // Issue the loads of plane x0+k (k may be -1) into set S; halo items only
     // when the plane will be staged in LDS (k < CX).
@@ -566,9 +567,20 @@ __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem
 
 
     using S0 = std::integral_constant<int, 0>;
+    using S1 = std::integral_constant<int, PD >= 2 ? 1 : 0>;
     // Prologue: plane x0-1 (own only), plane x0 (own + halo into buffer 0),
     // then the loads of planes x0+1 .. x0+PD stay in flight into the loop.
+    // With PD >= 2 plane k travels in set (k + 1) mod PD and planes
+    // x0-1 .. x0+PD-2 are all in flight while the prelude runs; with PD = 1
+    // plane k >= 1 travels in the one set.
     issue(S0{}, -1);
+    if constexpr (PD >= 2) {
+        issue(S1{}, 0);
+        static_for<2, PD>([&](auto Sc) {
+            constexpr int s_ = decltype(Sc)::value;
+            if (s_ - 1 <= CX) issue(Sc, s_ - 1);
+        });
+    }
     // the scalars of this pass (the previous pass's scalar step may run here,
     // while the first loads are in flight)
     prelude();
@@ -603,13 +615,15 @@ __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem
     };
     if (RK && !rk_first) aux_load(0, axc);
     consume(S0{}, prev, pn, -1);
-    issue(S0{}, 0);
-    consume(S0{}, cur, pc, 0);
-    issue(S0{}, 1);
-    static_for<1, PD>([&](auto Sc) {
-        constexpr int s_ = decltype(Sc)::value;
-        if (1 + s_ <= CX) issue(Sc, 1 + s_);
-    });
+    if constexpr (PD >= 2) {
+        consume(S1{}, cur, pc, 0);
+        if (PD - 1 <= CX) issue(S0{}, PD - 1);
+        if (PD <= CX) issue(S1{}, PD);
+    } else {
+        issue(S0{}, 0);
+        consume(S0{}, cur, pc, 0);
+        issue(S0{}, 1);
+    }
     __syncthreads();
 
     // One x-plane: plane x+1 arrives from set S (drift, stage), the loads of
@@ -737,7 +751,9 @@ __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem
     for (int i = 0; i < CX; i += PD) {
         static_for<0, PD>([&](auto Sc) {
             constexpr int s_ = decltype(Sc)::value;
-            if (i + s_ < CX) body(Sc, i + s_);
+            // body(i) takes plane i + 1: set (i + 2) mod PD (PD >= 2), the one set (PD = 1)
+            using Set = std::integral_constant<int, PD >= 2 ? (s_ + 2) % PD : 0>;
+            if (i + s_ < CX) body(Set{}, i + s_);
         });
     }
 }
