@@ -234,7 +234,7 @@ MFMA_BF16_PEAK = 2.5e15
 
 
 def surrogate_run(epochs=12, pairs_per_seed=64, train_seeds=range(2000, 2008), eval_seed=3000, jumps=312,
-                  extra_inputs=4, eval_256=True):
+                  extra_inputs=4, eval_256=True, ablation=False):
     """The learned surrogate on the two-field q = 100 workload: training pairs
     (state, state 16 VV4 steps later) from seeded 128^3 runs (k_IR = 0.5,
     dt = 0.05 dx), start steps spread over 5000 steps; training with the
@@ -365,10 +365,39 @@ def surrogate_run(epochs=12, pairs_per_seed=64, train_seeds=range(2000, 2008), e
         return res
 
     out["eval"] = [evaluate(128, 0.5, jumps)]
-    if eval_256:
+    if ablation:
+        # the literal 6-channel layout (fluctuations + a, H): trained and
+        # evaluated the same way at 128^3
+        s.close()
+        s = _lib.Surrogate(n_fields=2, extra_inputs=2, layers=5, jump_steps=K, init_seed=0)
+        s.dataset_reserve(wt.N, len(seeds) * pairs_per_seed)
+        for seed in seeds:
+            w = wt.with_(seed=seed)
+            lat = _lib.Lattice(w.N, w.dx, 2, "fp64")
+            lat.set_background(w.alpha, w.expansion, w.mp, w.a0)
+            lat.set_potential(w.m2, w.lam, w.g2, w.V0)
+            lat.seed(w.seed, w.fbar[:2], w.pbar[:2], w.cutoff_modes, w.amp)
+            tuned(lat, w.N, "fp64")
+            for i in range(pairs_per_seed):
+                if i and gap > K:
+                    lat.step("vv4", w.dt, gap - K, record=False)
+                s.record_input(lat)
+                lat.step("vv4", w.dt, K, record=False)
+                s.record_target(lat)
+            lat.close()
+        rep6 = s.train(epochs=epochs, lr=1e-3, lr_final=1e-5, shuffle_seed=0, holdout=pairs_per_seed // 2)
+        extra_inputs, saved = 2, extra_inputs
+        e6 = evaluate(128, 0.5, jumps)
+        extra_inputs = saved
+        out["ablation_6_channels"] = {"train": rep6, "eval": e6["forms"]["surrogate"],
+                                      "eval_no_gate": e6["forms"]["surrogate_no_gate"]}
+        s.close()
+        s = None
+    if eval_256 and s is not None:
         out["eval"].append(evaluate(256, 0.25, jumps))        # training dx, larger box
         out["eval"].append(evaluate(256, 0.5, min(jumps, 40)))  # half the training dx: out of distribution
-    s.close()
+    if s is not None:
+        s.close()
     return out
 
 
@@ -463,6 +492,7 @@ def main():
     ap.add_argument("--sg-pairs", type=int, default=64, help="training pairs per seed (8 seeds)")
     ap.add_argument("--sg-jumps", type=int, default=312)
     ap.add_argument("--sg-extra", type=int, default=4, help="broadcast inputs: 4 = (a, H, <phi>, <pi_phi>), 2 = (a, H)")
+    ap.add_argument("--sg-ablation", action="store_true", help="also train and evaluate the 6-channel input layout")
     ap.add_argument("--workload", choices=["c1", "c3"], default="c1",
                     help="c1: 256^3 two-field VV4 (default); c3: 1024^3 two-field leapfrog")
     args = ap.parse_args()
@@ -530,7 +560,8 @@ def main():
     if not args.no_surrogate and args.workload == "c1":
         progress("surrogate form (training pairs, training, evaluation)")
         forms["surrogate"] = surrogate_run(epochs=args.sg_epochs, pairs_per_seed=args.sg_pairs,
-                                           jumps=args.sg_jumps, extra_inputs=args.sg_extra)
+                                           jumps=args.sg_jumps, extra_inputs=args.sg_extra,
+                                           ablation=args.sg_ablation)
     line["forms"] = forms
     if not args.no_cpu:
         # the oracle on the 256^3 workload (the 1024^3 one does not fit a numpy run of ~30 s)
