@@ -137,6 +137,15 @@ cl_status cl_set_stream(cl_lattice* h, void* hip_stream);
  * them afterwards. */
 cl_status cl_attach_device_buffers(cl_lattice* h, void* state, void* state_pp);
 
+/* Device address of the buffer that holds the current state (library-owned
+ * or attached), in the row-interleaved layout above.  Every pass writes the
+ * other buffer, so the address may change with each cl_step; it stays valid
+ * until the next call that advances, attaches or destroys h.  Lets a caller
+ * read or overwrite the fields in place on the device; after writing them,
+ * call cl_set_state (a, a', eta) and cl_read_observables, which re-centres the
+ * variance sums on the new means. */
+cl_status cl_get_state_buffer(const cl_lattice* h, void** state);
+
 /* Background: alpha-time exponent alpha (Eq. FLRWmetric; 0 cosmic, 1
  * conformal), expansion mode, reduced Planck mass m_p in program units, and
  * the initial scale factor a0 used by cl_seed / cl_set_fields. */

@@ -7,9 +7,12 @@ script and a thin ctypes binding with the same call names.  The binding
 raises ImportError when the library has not been built.
 """
 import importlib
+import importlib.util
 
 
 def __getattr__(name):
     if name.startswith("_"):
         raise AttributeError(name)
+    if importlib.util.find_spec(__name__ + "." + name) is not None:
+        return importlib.import_module(__name__ + "." + name)  # a submodule (e.g. build)
     return getattr(importlib.import_module(__name__ + "._lib"), name)

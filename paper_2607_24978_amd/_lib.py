@@ -84,6 +84,7 @@ _SIGS = {
     "cl_destroy": (C.c_int, [_P]),
     "cl_set_stream": (C.c_int, [_P, _P]),
     "cl_attach_device_buffers": (C.c_int, [_P, _P, _P]),
+    "cl_get_state_buffer": (C.c_int, [_P, C.POINTER(_P)]),
     "cl_set_background": (C.c_int, [_P, C.c_double, C.c_int, C.c_double, C.c_double]),
     "cl_set_potential": (C.c_int, [_P, C.POINTER(cl_potential)]),
     "cl_seed": (C.c_int, [_P, C.c_uint64, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_double, C.c_double]),
@@ -185,6 +186,12 @@ class Lattice:
         """Borrow caller device memory (e.g. two torch tensors' data_ptr()) in the
         library's row-interleaved layout; the caller keeps it alive."""
         _check(lib.cl_attach_device_buffers(self.h, _P(state_ptr), _P(state_pp_ptr)), self.h)
+
+    def state_buffer(self) -> int:
+        """Device address of the buffer holding the current state."""
+        out = _P()
+        _check(lib.cl_get_state_buffer(self.h, C.byref(out)), self.h)
+        return out.value or 0
 
     def set_background(self, alpha=1.0, expansion="self", mp=1.0, a0=1.0):
         _check(lib.cl_set_background(self.h, float(alpha), EXPANSIONS[expansion], float(mp), float(a0)), self.h)

@@ -562,6 +562,13 @@ cl_status cl_attach_device_buffers(cl_lattice* h, void* state, void* state_pp) {
     return CL_OK;
 }
 
+cl_status cl_get_state_buffer(const cl_lattice* h, void** state) {
+    if (!h) return fail(nullptr, CL_EINVAL, "handle is NULL");
+    if (!state) return fail(const_cast<cl_lattice*>(h), CL_EINVAL, "state is NULL");
+    *state = h->buf[h->cur];
+    return CL_OK;
+}
+
 cl_status cl_set_background(cl_lattice* h, double alpha, cl_expansion mode, double m_p, double a0) {
     if (!h) return fail(nullptr, CL_EINVAL, "handle is NULL");
     if (!std::isfinite(alpha)) return fail(h, CL_EINVAL, "alpha must be finite");
