@@ -20,6 +20,9 @@ constexpr int kMaxSums = kSumsPerField * kMaxFields + 1;
 // lower still for the tuned candidates).
 constexpr int kMaxPassBlocks = 4096;
 constexpr int kTunedPassBlocks = 1024;
+// Largest lattice-pass workgroup (one row per thread); also the finishing
+// kernel's launch bound.
+constexpr int kMaxPassThreads = 512;
 constexpr int nsums(int nf) { return kSumsPerField * nf + 1; }
 
 // Background state and the coefficients of the next pass, in device memory.

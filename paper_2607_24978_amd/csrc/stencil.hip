@@ -295,7 +295,7 @@ __device__ __forceinline__ void copy_scal(Scal* dst, const Scal* src, int nthrea
 // for all threads on return.  The order depends on NT only.
 template <int NS>
 __device__ __forceinline__ void block_sum(double (&v)[NS], int NT, double* out) {
-    __shared__ double wsum[4][kMaxSums];
+    __shared__ double wsum[kMaxPassThreads / 64][kMaxSums];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -491,16 +491,17 @@ __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem
     }
 
     const size_t plane = static_cast<size_t>(N) * rs;
-    // Raw (undrifted) loads of up to PD planes in flight: own values and halo
-    // items, in a ring of PD register sets (the prologue below fixes which
-    // plane travels in which set).
-    T rf[PD][NF][RY][V], rp[PD][NF][RY][V], hf[PD][NF][HI][V], hp[PD][NF][HI][V];
-    // Issue the loads of plane x0+k (k may be -1) into set S; halo items only
-    // when the plane will be staged in LDS (k < CX).
-    auto issue = [&](auto Sc, int k) {
+    // Raw (undrifted) loads of up to PD planes in flight: own values in a ring
+    // of PD register sets, halo items in a ring of HPD sets, issued HPD planes
+    // ahead (2 with one row per thread, 1 with two: few threads hold halo
+    // items, and a deep halo ring would cost every thread its registers).
+    // The prologue below fixes which plane travels in which set.
+    constexpr int HPD = (PD >= 2 && RY == 1) ? 2 : 1;
+    T rf[PD][NF][RY][V], rp[PD][NF][RY][V], hf[HPD][NF][HI][V], hp[HPD][NF][HI][V];
+    // Own loads of plane x0+k (k may be -1) into set S.
+    auto issue_own = [&](auto Sc, int k) {
         constexpr int S_ = decltype(Sc)::value;
         const int x = (x0 + k + N) % N;
-        const bool halo = k >= 0 && k < CX;
         const size_t base = static_cast<size_t>(x) * plane;
 #pragma unroll
         for (int j = 0; j < NF; ++j) {
@@ -514,17 +515,25 @@ __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem
                     vload(pin[j] + base + yrow[r], rp[S_][j][r]);
                 }
             }
-            if (halo) {
+        }
+    };
+    // Halo loads of plane x0+k into halo set H, only for planes staged in
+    // LDS (0 <= k < CX).
+    auto issue_halo = [&](auto Hc, int k) {
+        constexpr int H_ = decltype(Hc)::value;
+        if (k < 0 || k >= CX) return;
+        const size_t base = static_cast<size_t>(x0 + k) * plane;
 #pragma unroll
-                for (int q = 0; q < HI; ++q) {
-                    if (h_goff[q] < 0) continue;
-                    if (h_vec[q]) {
-                        vload(fin[j] + base + h_goff[q], hf[S_][j][q]);
-                        vload(pin[j] + base + h_goff[q], hp[S_][j][q]);
-                    } else {
-                        hf[S_][j][q][0] = fin[j][base + h_goff[q]];
-                        hp[S_][j][q][0] = pin[j][base + h_goff[q]];
-                    }
+        for (int j = 0; j < NF; ++j) {
+#pragma unroll
+            for (int q = 0; q < HI; ++q) {
+                if (h_goff[q] < 0) continue;
+                if (h_vec[q]) {
+                    vload(fin[j] + base + h_goff[q], hf[H_][j][q]);
+                    vload(pin[j] + base + h_goff[q], hp[H_][j][q]);
+                } else {
+                    hf[H_][j][q][0] = fin[j][base + h_goff[q]];
+                    hp[H_][j][q][0] = pin[j][base + h_goff[q]];
                 }
             }
         }
@@ -532,8 +541,9 @@ __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem
     // Drift the raw plane of set S: own values into fd / po, and (if
     // stage_buf >= 0) the drifted own values and halo into LDS buffer stage_buf.
     T prev[NF][RY][V], cur[NF][RY][V], nxt[NF][RY][V], pc[NF][RY][V], pn[NF][RY][V];
-    auto consume = [&](auto Sc, T (&fd)[NF][RY][V], T (&po)[NF][RY][V], int stage_buf) {
+    auto consume = [&](auto Sc, auto Hc, T (&fd)[NF][RY][V], T (&po)[NF][RY][V], int stage_buf) {
         constexpr int S_ = decltype(Sc)::value;
+        constexpr int H_ = decltype(Hc)::value;
 #pragma unroll
         for (int j = 0; j < NF; ++j)
 #pragma unroll
@@ -556,10 +566,10 @@ __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem
                 if (h_vec[q]) {
                     T fv[V];
 #pragma unroll
-                    for (int v = 0; v < V; ++v) fv[v] = fmad(cd, hp[S_][j][q][v], hf[S_][j][q][v]);
+                    for (int v = 0; v < V; ++v) fv[v] = fmad(cd, hp[H_][j][q][v], hf[H_][j][q][v]);
                     vstore(Lj + h_lds[q], fv);
                 } else {
-                    Lj[h_lds[q]] = fmad(cd, hp[S_][j][q][0], hf[S_][j][q][0]);
+                    Lj[h_lds[q]] = fmad(cd, hp[H_][j][q][0], hf[H_][j][q][0]);
                 }
             }
         }
@@ -568,18 +578,22 @@ __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem
 
     using S0 = std::integral_constant<int, 0>;
     using S1 = std::integral_constant<int, PD >= 2 ? 1 : 0>;
+    using H1 = std::integral_constant<int, HPD >= 2 ? 1 : 0>;
     // Prologue: plane x0-1 (own only), plane x0 (own + halo into buffer 0),
     // then the loads of planes x0+1 .. x0+PD stay in flight into the loop.
-    // With PD >= 2 plane k travels in set (k + 1) mod PD and planes
-    // x0-1 .. x0+PD-2 are all in flight while the prelude runs; with PD = 1
-    // plane k >= 1 travels in the one set.
-    issue(S0{}, -1);
+    // With PD >= 2 the own values of plane k travel in set (k + 1) mod PD, its
+    // halo in halo set k mod HPD, and planes x0-1 .. x0+PD-2 (halo: x0 ..
+    // x0+HPD-1) are all in flight while the prelude runs; with PD = 1 plane
+    // k >= 1 travels in the one set.
+    issue_own(S0{}, -1);
     if constexpr (PD >= 2) {
-        issue(S1{}, 0);
+        issue_own(S1{}, 0);
+        issue_halo(S0{}, 0);
         static_for<2, PD>([&](auto Sc) {
             constexpr int s_ = decltype(Sc)::value;
-            if (s_ - 1 <= CX) issue(Sc, s_ - 1);
+            if (s_ - 1 <= CX) issue_own(Sc, s_ - 1);
         });
+        if constexpr (HPD >= 2) issue_halo(H1{}, 1);
     }
     // the scalars of this pass (the previous pass's scalar step may run here,
     // while the first loads are in flight)
@@ -614,25 +628,31 @@ __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem
         }
     };
     if (RK && !rk_first) aux_load(0, axc);
-    consume(S0{}, prev, pn, -1);
+    consume(S0{}, S0{}, prev, pn, -1);
     if constexpr (PD >= 2) {
-        consume(S1{}, cur, pc, 0);
-        if (PD - 1 <= CX) issue(S0{}, PD - 1);
-        if (PD <= CX) issue(S1{}, PD);
+        consume(S1{}, S0{}, cur, pc, 0);
+        if (PD - 1 <= CX) issue_own(S0{}, PD - 1);
+        if (PD <= CX) issue_own(S1{}, PD);
+        issue_halo(S0{}, HPD);
     } else {
-        issue(S0{}, 0);
-        consume(S0{}, cur, pc, 0);
-        issue(S0{}, 1);
+        issue_own(S0{}, 0);
+        issue_halo(S0{}, 0);
+        consume(S0{}, S0{}, cur, pc, 0);
+        issue_own(S0{}, 1);
+        issue_halo(S0{}, 1);
     }
     __syncthreads();
 
-    // One x-plane: plane x+1 arrives from set S (drift, stage), the loads of
-    // plane x+1+PD go out into the same set, then plane x is computed.
-    auto body = [&](auto Sc, int i) {
+    // One x-plane: plane x+1 arrives from set S and halo set H (drift,
+    // stage), the own loads of plane x+1+PD go out into the same set and the
+    // halo loads of plane x+1+HPD into the same halo set, then plane x is
+    // computed.
+    auto body = [&](auto Sc, auto Hc, int i) {
         const int x = x0 + i;
         const int buf = i & 1;
-        consume(Sc, nxt, pn, i + 1 < CX ? (buf ^ 1) : -1);
-        if (i + 1 + PD <= CX) issue(Sc, i + 1 + PD);
+        consume(Sc, Hc, nxt, pn, i + 1 < CX ? (buf ^ 1) : -1);
+        if (i + 1 + PD <= CX) issue_own(Sc, i + 1 + PD);
+        issue_halo(Hc, i + 1 + HPD);
         if (RK && !rk_first && i + 1 < CX) aux_load(i + 1, axn);
 
         const T* L0 = lds + static_cast<size_t>(buf) * NF * PL;
@@ -751,15 +771,19 @@ __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem
     for (int i = 0; i < CX; i += PD) {
         static_for<0, PD>([&](auto Sc) {
             constexpr int s_ = decltype(Sc)::value;
-            // body(i) takes plane i + 1: set (i + 2) mod PD (PD >= 2), the one set (PD = 1)
+            // body(i) takes plane i + 1: set (i + 2) mod PD and halo set
+            // (i + 1) mod HPD (PD >= 2, so i is even here), the one set (PD = 1)
             using Set = std::integral_constant<int, PD >= 2 ? (s_ + 2) % PD : 0>;
-            if (i + s_ < CX) body(Set{}, i + s_);
+            using HSet = std::integral_constant<int, HPD >= 2 ? (s_ + 1) % 2 : 0>;
+            if (i + s_ < CX) body(Set{}, HSet{}, i + s_);
         });
     }
 }
 
-template <typename T, int NF, int RY, int HI, int PD, bool RK>
-__global__ __launch_bounds__(256) void lattice_pass(PassArgs A) {
+// NTB: the launch bound (256, or 512 for the tall one-row-per-thread tiles,
+// whose register footprint fits two waves per SIMD).
+template <typename T, int NF, int RY, int HI, int PD, bool RK, int NTB>
+__global__ __launch_bounds__(NTB) void lattice_pass(PassArgs A) {
     constexpr int NS = kSumsPerField * NF + 1;
     const int nblocks = A.nbz * A.nby * A.nbx;
     // XCD-aware order: consecutive workgroup ids land on different XCDs
@@ -850,7 +874,7 @@ __global__ __launch_bounds__(256) void lattice_pass(PassArgs A) {
 // The pending scalar step of the last pass of a sequence (one workgroup of
 // the passes' NT threads, so that the sums are formed in the same order).
 template <int NS>
-__global__ __launch_bounds__(256) void finish_kernel(PassArgs A) {
+__global__ __launch_bounds__(kMaxPassThreads) void finish_kernel(PassArgs A) {
     __shared__ Scal s_sc;
     __shared__ double tot[kMaxSums];
     copy_scal(&s_sc, A.sc_in, blockDim.x);
@@ -946,14 +970,16 @@ bool finalize_tile(Tile& t, int N, cl_precision prec) {
     const int BZ = t.TZ / V;
     const int RL = t.TY / t.RY;
     t.NT = BZ * RL;
-    if (t.NT > 256 || !is_pow2(t.NT) || !is_pow2(BZ)) return false;
+    if (t.NT > kMaxPassThreads || !is_pow2(t.NT) || !is_pow2(BZ)) return false;
     if (t.RY != 1 && t.RY != 2) return false;
+    if (t.NT > 256 && t.RY != 1) return false;  // two rows per thread do not fit two waves per SIMD
     if (t.PD != 1 && t.PD != 2 && t.PD != 4) return false;
     if (t.PD == 4 && t.RY != 1) return false;  // the deep ring is built for one row per thread
     const int nhalo = 2 * BZ + 2 * t.TY;
     t.HI = (nhalo + t.NT - 1) / t.NT;
     if (t.HI > 2) return false;
     if (t.HI < 1) t.HI = 1;
+    if (t.NT > 256 && t.HI != 1) return false;  // the wide instance takes one halo item per thread
     t.nbz = N / t.TZ;
     t.nby = N / t.TY;
     t.nbx = N / t.CX;
@@ -1088,8 +1114,8 @@ void candidate_tiles(int N, cl_precision prec, int nf, Tile* out, int* count, in
             if (tzm != 64 && TZ == N) continue;  // same as the full-row candidate
             const int BZ = TZ / V;
             for (int RY : {1, 2})
-                for (int NT : {64, 128, 256}) {
-                    if (NT < BZ) continue;
+                for (int NT : {64, 128, 256, 512}) {
+                    if (NT < BZ || (NT > 256 && RY != 1)) continue;
                     const int TY = (NT / BZ) * RY;
                     if (TY > N) continue;
                     for (int CX = 2; CX <= N; CX *= 2)
@@ -1112,24 +1138,33 @@ void candidate_tiles(int N, cl_precision prec, int nf, Tile* out, int* count, in
     *count = n;
 }
 
-template <typename T, int NF, int RY, int HI, int PD, bool RK>
+template <typename T, int NF, int RY, int HI, int PD, bool RK, int NTB>
 static hipError_t launch_t(const PassArgs& a, const Tile& t, hipStream_t s, size_t lds) {
-    hipLaunchKernelGGL((lattice_pass<T, NF, RY, HI, PD, RK>), dim3(t.nblocks()), dim3(t.NT), lds, s, a);
+    hipLaunchKernelGGL((lattice_pass<T, NF, RY, HI, PD, RK, NTB>), dim3(t.nblocks()), dim3(t.NT), lds, s, a);
     return hipGetLastError();
 }
 
-template <typename T, int NF, int RY, int HI>
+template <typename T, int NF, int RY, int HI, int NTB = 256>
 static hipError_t launch_pd(const PassArgs& a, const Tile& t, hipStream_t s, size_t lds) {
-    // Runge-Kutta stages: prefetch depth 1 or 2 (a depth-4 tile runs them at 2)
-    if (a.rk) return t.PD == 1 ? launch_t<T, NF, RY, HI, 1, true>(a, t, s, lds) : launch_t<T, NF, RY, HI, 2, true>(a, t, s, lds);
-    if constexpr (RY == 1) {
-        if (t.PD == 4) return launch_t<T, NF, RY, HI, 4, false>(a, t, s, lds);
+    // Runge-Kutta stages: prefetch depth 1 or 2 (a depth-4 tile runs them at
+    // 2; the wide workgroups at 1, where the stage fits two waves per SIMD)
+    if (a.rk) {
+        if constexpr (NTB > 256) return launch_t<T, NF, RY, HI, 1, true, NTB>(a, t, s, lds);
+        else
+            return t.PD == 1 ? launch_t<T, NF, RY, HI, 1, true, NTB>(a, t, s, lds)
+                             : launch_t<T, NF, RY, HI, 2, true, NTB>(a, t, s, lds);
     }
-    return t.PD == 2 ? launch_t<T, NF, RY, HI, 2, false>(a, t, s, lds) : launch_t<T, NF, RY, HI, 1, false>(a, t, s, lds);
+    if constexpr (RY == 1) {
+        if (t.PD == 4) return launch_t<T, NF, RY, HI, 4, false, NTB>(a, t, s, lds);
+    }
+    return t.PD == 2 ? launch_t<T, NF, RY, HI, 2, false, NTB>(a, t, s, lds)
+                     : launch_t<T, NF, RY, HI, 1, false, NTB>(a, t, s, lds);
 }
 
 template <typename T, int NF>
 static hipError_t launch_nf(const PassArgs& a, const Tile& t, hipStream_t s, size_t lds) {
+    // (more than 256 threads: one row per thread, and 2 BZ + 2 TY <= NT)
+    if (t.NT > 256) return launch_pd<T, NF, 1, 1, kMaxPassThreads>(a, t, s, lds);
     if (t.RY == 1) return t.HI == 1 ? launch_pd<T, NF, 1, 1>(a, t, s, lds) : launch_pd<T, NF, 1, 2>(a, t, s, lds);
     return t.HI == 1 ? launch_pd<T, NF, 2, 1>(a, t, s, lds) : launch_pd<T, NF, 2, 2>(a, t, s, lds);
 }
