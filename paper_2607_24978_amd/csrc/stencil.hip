@@ -401,7 +401,7 @@ __device__ __forceinline__ void static_for(F&& f) {
 // stage's input f), F = h (a^(alpha-3) pi, a^(1+alpha) L f - a^(3+alpha) dV),
 // d <- A d + F and y <- y + B d with the registers d of (f, pi) in `aux`
 // (loaded one plane ahead), sums over the stage's input state.
-template <typename T, int NF, int RY, int HI, int PD, bool RK, typename Prelude>
+template <typename T, int NF, int RY, int HI, int PD, bool RK, int HPD, typename Prelude>
 __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem_raw, double (&acc)[kSumsPerField * NF + 1],
                            Prelude&& prelude) {
     constexpr int V = VecOf<T>::V;
@@ -492,48 +492,48 @@ __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem
 
     const size_t plane = static_cast<size_t>(N) * rs;
     // Raw (undrifted) loads of up to PD planes in flight: own values in a ring
-    // of PD register sets, halo items in a ring of HPD sets, issued HPD planes
-    // ahead (2 with one row per thread, 1 with two: few threads hold halo
-    // items, and a deep halo ring would cost every thread its registers).
+    // of PD register sets, halo items in a ring of HPD sets (HPD = PD, or 2 <
+    // PD where registers are short: few threads hold halo items, and a deep
+    // halo ring costs every thread its registers), issued HPD planes ahead.
     // The prologue below fixes which plane travels in which set.
-    constexpr int HPD = (PD >= 2 && RY == 1) ? 2 : 1;
+    static_assert(HPD == PD || (HPD == 2 && PD == 4), "halo ring depth");
     T rf[PD][NF][RY][V], rp[PD][NF][RY][V], hf[HPD][NF][HI][V], hp[HPD][NF][HI][V];
-    // Own loads of plane x0+k (k may be -1) into set S.
-    auto issue_own = [&](auto Sc, int k) {
+    // Loads of plane x0+ko (own values, into set S; ko may be -1) and of the
+    // halo items of plane x0+kh (into halo set H, only for planes staged in
+    // LDS, 0 <= kh < CX), field by field; kNone skips either part.
+    constexpr int kNone = -1000000;
+    auto issue = [&](auto Sc, auto Hc, int ko, int kh) {
         constexpr int S_ = decltype(Sc)::value;
-        const int x = (x0 + k + N) % N;
-        const size_t base = static_cast<size_t>(x) * plane;
+        constexpr int H_ = decltype(Hc)::value;
+        const bool own = ko != kNone;
+        const bool halo = kh >= 0 && kh < CX;
 #pragma unroll
         for (int j = 0; j < NF; ++j) {
+            if (own) {
+                const size_t obase = static_cast<size_t>((x0 + ko + N) % N) * plane;
 #pragma unroll
-            for (int r = 0; r < RY; ++r) {
-                if (nt_load) {
-                    vload_nt(fin[j] + base + yrow[r], rf[S_][j][r]);
-                    vload_nt(pin[j] + base + yrow[r], rp[S_][j][r]);
-                } else {
-                    vload(fin[j] + base + yrow[r], rf[S_][j][r]);
-                    vload(pin[j] + base + yrow[r], rp[S_][j][r]);
+                for (int r = 0; r < RY; ++r) {
+                    if (nt_load) {
+                        vload_nt(fin[j] + obase + yrow[r], rf[S_][j][r]);
+                        vload_nt(pin[j] + obase + yrow[r], rp[S_][j][r]);
+                    } else {
+                        vload(fin[j] + obase + yrow[r], rf[S_][j][r]);
+                        vload(pin[j] + obase + yrow[r], rp[S_][j][r]);
+                    }
                 }
             }
-        }
-    };
-    // Halo loads of plane x0+k into halo set H, only for planes staged in
-    // LDS (0 <= k < CX).
-    auto issue_halo = [&](auto Hc, int k) {
-        constexpr int H_ = decltype(Hc)::value;
-        if (k < 0 || k >= CX) return;
-        const size_t base = static_cast<size_t>(x0 + k) * plane;
+            if (halo) {
+                const size_t hbase = static_cast<size_t>((x0 + kh + N) % N) * plane;
 #pragma unroll
-        for (int j = 0; j < NF; ++j) {
-#pragma unroll
-            for (int q = 0; q < HI; ++q) {
-                if (h_goff[q] < 0) continue;
-                if (h_vec[q]) {
-                    vload(fin[j] + base + h_goff[q], hf[H_][j][q]);
-                    vload(pin[j] + base + h_goff[q], hp[H_][j][q]);
-                } else {
-                    hf[H_][j][q][0] = fin[j][base + h_goff[q]];
-                    hp[H_][j][q][0] = pin[j][base + h_goff[q]];
+                for (int q = 0; q < HI; ++q) {
+                    if (h_goff[q] < 0) continue;
+                    if (h_vec[q]) {
+                        vload(fin[j] + hbase + h_goff[q], hf[H_][j][q]);
+                        vload(pin[j] + hbase + h_goff[q], hp[H_][j][q]);
+                    } else {
+                        hf[H_][j][q][0] = fin[j][hbase + h_goff[q]];
+                        hp[H_][j][q][0] = pin[j][hbase + h_goff[q]];
+                    }
                 }
             }
         }
@@ -578,22 +578,30 @@ __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem
 
     using S0 = std::integral_constant<int, 0>;
     using S1 = std::integral_constant<int, PD >= 2 ? 1 : 0>;
-    using H1 = std::integral_constant<int, HPD >= 2 ? 1 : 0>;
+    // halo set of plane k: its own set (k + 1) mod PD when HPD = PD, else k mod 2
+    auto hs = [](auto Kc) {
+        constexpr int k = decltype(Kc)::value;
+        return std::integral_constant<int, HPD == PD ? (k + 1) % PD : k % HPD>{};
+    };
+    using K0 = std::integral_constant<int, 0>;
+    using K1 = std::integral_constant<int, 1>;
+    using K2 = std::integral_constant<int, 2>;
     // Prologue: plane x0-1 (own only), plane x0 (own + halo into buffer 0),
     // then the loads of planes x0+1 .. x0+PD stay in flight into the loop.
-    // With PD >= 2 the own values of plane k travel in set (k + 1) mod PD, its
-    // halo in halo set k mod HPD, and planes x0-1 .. x0+PD-2 (halo: x0 ..
-    // x0+HPD-1) are all in flight while the prelude runs; with PD = 1 plane
-    // k >= 1 travels in the one set.
-    issue_own(S0{}, -1);
+    // With PD >= 2 the own values of plane k travel in set (k + 1) mod PD and
+    // planes x0-1 .. x0+PD-2 are in flight while the prelude runs, with their
+    // halo when HPD = PD; with HPD = 2 < PD only the halo of x0 is, and that
+    // of x0+1, x0+2 goes out once plane x0 is staged (after the prelude,
+    // whose sums need registers too).  With PD = 1 plane k >= 1 travels in
+    // the one set.
+    issue(S0{}, S0{}, -1, kNone);
     if constexpr (PD >= 2) {
-        issue_own(S1{}, 0);
-        issue_halo(S0{}, 0);
+        issue(S1{}, hs(K0{}), 0, 0);
         static_for<2, PD>([&](auto Sc) {
             constexpr int s_ = decltype(Sc)::value;
-            if (s_ - 1 <= CX) issue_own(Sc, s_ - 1);
+            using Km = std::integral_constant<int, s_ - 1>;
+            if (s_ - 1 <= CX) issue(Sc, hs(Km{}), s_ - 1, HPD == PD ? s_ - 1 : kNone);
         });
-        if constexpr (HPD >= 2) issue_halo(H1{}, 1);
     }
     // the scalars of this pass (the previous pass's scalar step may run here,
     // while the first loads are in flight)
@@ -630,16 +638,20 @@ __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem
     if (RK && !rk_first) aux_load(0, axc);
     consume(S0{}, S0{}, prev, pn, -1);
     if constexpr (PD >= 2) {
-        consume(S1{}, S0{}, cur, pc, 0);
-        if (PD - 1 <= CX) issue_own(S0{}, PD - 1);
-        if (PD <= CX) issue_own(S1{}, PD);
-        issue_halo(S0{}, HPD);
+        consume(S1{}, hs(K0{}), cur, pc, 0);
+        if constexpr (HPD == PD) {
+            using Ka = std::integral_constant<int, PD - 1>;
+            using Kb = std::integral_constant<int, PD>;
+            if (PD - 1 <= CX) issue(S0{}, hs(Ka{}), PD - 1, PD - 1);
+            if (PD <= CX) issue(S1{}, hs(Kb{}), PD, PD);
+        } else {
+            issue(S0{}, hs(K1{}), PD - 1 <= CX ? PD - 1 : kNone, 1);
+            issue(S1{}, hs(K2{}), PD <= CX ? PD : kNone, 2);
+        }
     } else {
-        issue_own(S0{}, 0);
-        issue_halo(S0{}, 0);
+        issue(S0{}, S0{}, 0, 0);
         consume(S0{}, S0{}, cur, pc, 0);
-        issue_own(S0{}, 1);
-        issue_halo(S0{}, 1);
+        issue(S0{}, S0{}, 1, 1);
     }
     __syncthreads();
 
@@ -651,8 +663,11 @@ __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem
         const int x = x0 + i;
         const int buf = i & 1;
         consume(Sc, Hc, nxt, pn, i + 1 < CX ? (buf ^ 1) : -1);
-        if (i + 1 + PD <= CX) issue_own(Sc, i + 1 + PD);
-        issue_halo(Hc, i + 1 + HPD);
+        if constexpr (HPD == PD) {
+            if (i + 1 + PD <= CX) issue(Sc, Hc, i + 1 + PD, i + 1 + PD);
+        } else {
+            issue(Sc, Hc, i + 1 + PD <= CX ? i + 1 + PD : kNone, i + 1 + HPD);
+        }
         if (RK && !rk_first && i + 1 < CX) aux_load(i + 1, axn);
 
         const T* L0 = lds + static_cast<size_t>(buf) * NF * PL;
@@ -772,9 +787,9 @@ __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem
         static_for<0, PD>([&](auto Sc) {
             constexpr int s_ = decltype(Sc)::value;
             // body(i) takes plane i + 1: set (i + 2) mod PD and halo set
-            // (i + 1) mod HPD (PD >= 2, so i is even here), the one set (PD = 1)
+            // hs(i + 1) (i is a multiple of PD here), the one set (PD = 1)
             using Set = std::integral_constant<int, PD >= 2 ? (s_ + 2) % PD : 0>;
-            using HSet = std::integral_constant<int, HPD >= 2 ? (s_ + 1) % 2 : 0>;
+            using HSet = decltype(hs(std::integral_constant<int, s_ + 1>{}));
             if (i + s_ < CX) body(Set{}, HSet{}, i + s_);
         });
     }
@@ -865,7 +880,8 @@ __global__ __launch_bounds__(NTB) void lattice_pass(PassArgs A) {
             __syncthreads();
         }
     };
-    march_tile<T, NF, RY, HI, PD, RK>(J, smem_raw, acc, prelude);
+    // wide workgroups keep the halo ring at depth 2 (two waves per SIMD)
+    march_tile<T, NF, RY, HI, PD, RK, (NTB > 256 && PD > 2) ? 2 : PD>(J, smem_raw, acc, prelude);
     block_sum<NS>(acc, NT, tot);
     if (threadIdx.x == 0)
         for (int k = 0; k < NS; ++k) A.partials[(size_t)k * nblocks + bid] = tot[k];
@@ -1054,8 +1070,8 @@ __global__ __launch_bounds__(256) void ensemble_pass(EnsArgs E) {
         double acc[NS];
 #pragma unroll
         for (int k = 0; k < NS; ++k) acc[k] = 0.0;
-        if (M.RY == 2) march_tile<T, NF, 2, 1, 4, false>(J, smem_raw, acc, [] {});
-        else march_tile<T, NF, 1, 1, 4, false>(J, smem_raw, acc, [] {});
+        if (M.RY == 2) march_tile<T, NF, 2, 1, 4, false, 4>(J, smem_raw, acc, [] {});
+        else march_tile<T, NF, 1, 1, 4, false, 4>(J, smem_raw, acc, [] {});
         if (reduce_partials<NS>(acc, 256, M.partials, I.tile, M.nitems, M.ticket, tot) && threadIdx.x < 64)
             finish_pass(M.ph, M.sc, kt, kb, hn, E.rec >= 0 ? E.obs + (size_t)E.rec * E.nmembers + I.member : nullptr,
                         tot);
