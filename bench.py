@@ -170,6 +170,8 @@ def batched_run(steps, warmup, solo_steps=100):
     ens = _lib.Ensemble(lats)
     for i, w in enumerate(ws):
         ens.set_dt(i, w.dt)
+    tune = ens.autotune(reps=3)  # the library's decomposition search (states unchanged)
+    progress(f"ensemble layout {tune['best']}")
     chunk = min(steps, 500)
     ens.step("leapfrog", chunk)  # warm-up call captures the graph
     for _ in range(max(0, warmup - chunk) // chunk):
@@ -190,7 +192,8 @@ def batched_run(steps, warmup, solo_steps=100):
     return {"members": len(ws), "sites": sites, "steps": nsteps, "site_updates_per_s": sites * nsteps / sec,
             "ms_per_step": 1e3 * sec / nsteps, "hbm_frac": achieved / HBM_PEAK_GBS,
             "solo_site_updates_per_s": sites * solo_steps / solo_s,
-            "batched_speedup_vs_solo": (sites * nsteps / sec) / (sites * solo_steps / solo_s), "finite": ok}
+            "batched_speedup_vs_solo": (sites * nsteps / sec) / (sites * solo_steps / solo_s), "finite": ok,
+            "layout": tune["best"]}
 
 
 def _scalar_errors(rec, ref, nf):

@@ -255,6 +255,14 @@ cl_status cl_ensemble_step(cl_ensemble* e, cl_integrator integ, int n_steps, cl_
  * the lattice is tall enough).  A member stepped on its own with this tile
  * (cl_set_tile) gives bitwise the same result as inside the ensemble. */
 cl_status cl_ensemble_get_tile(const cl_ensemble* e, int member, cl_tile* out);
+/* Ensemble autotuner: times `reps` passes of every distinct work
+ * decomposition (about 8k to 128k sites per work item, with and without two
+ * rows per thread) on the members' current states, which are left unchanged
+ * (fields bitwise, scalar blocks restored), and keeps the fastest.  Writes a
+ * JSON report (NUL-terminated, truncated to report_cap) if report is not
+ * NULL.  The decomposition changes the order of the lattice sums, not the
+ * site updates. */
+cl_status cl_ensemble_autotune(cl_ensemble* e, int reps, char* report, size_t report_cap);
 cl_status cl_ensemble_destroy(cl_ensemble* e);
 
 #ifdef __cplusplus

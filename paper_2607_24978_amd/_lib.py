@@ -7,6 +7,7 @@ ImportError -- there is no fallback.
 from __future__ import annotations
 
 import ctypes as C
+import json
 import os
 
 import numpy as np
@@ -103,6 +104,7 @@ _SIGS = {
     "cl_ensemble_step": (C.c_int, [_P, C.c_int, C.c_int, _P]),
     "cl_ensemble_destroy": (C.c_int, [_P]),
     "cl_ensemble_get_tile": (C.c_int, [_P, C.c_int, C.POINTER(cl_tile)]),
+    "cl_ensemble_autotune": (C.c_int, [_P, C.c_int, C.c_char_p, C.c_size_t]),
     "cl_surrogate_last_error": (C.c_char_p, []),
     "cl_surrogate_create": (C.c_int, [C.POINTER(cl_surrogate_cfg), C.POINTER(_P)]),
     "cl_surrogate_destroy": (C.c_int, [_P]),
@@ -393,6 +395,13 @@ class Ensemble:
         t = cl_tile()
         _check(lib.cl_ensemble_get_tile(self.e, int(i), C.byref(t)))
         return dict(tz=t.tz, ty=t.ty, cx=t.cx, ry=t.ry, pd=t.pd)
+
+    def autotune(self, reps: int = 3) -> dict:
+        """Time every distinct work decomposition on the current states (left
+        unchanged) and keep the fastest; returns the library's JSON report."""
+        buf = C.create_string_buffer(16384)
+        _check(lib.cl_ensemble_autotune(self.e, int(reps), buf, len(buf)))
+        return json.loads(buf.value.decode())
 
     def close(self):
         if getattr(self, "e", None):

@@ -984,6 +984,9 @@ struct cl_ensemble {
     size_t lds = 0;
     hipGraphExec_t gexec = nullptr;
     int g_integ = -1, g_n = -1;
+    size_t partials_cap = 0, items_cap = 0;  // allocated slots
+    int item_sites = 0;                      // layout parameters in use
+    bool two_rows = true;
 };
 
 namespace {
@@ -999,9 +1002,13 @@ cl_status efail(cl_status st, const std::string& msg) {
         if (e_ != hipSuccess) return efail(CL_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+// Default layout: about 32k sites per work item, two rows per thread where
+// the lattice is tall enough.
+constexpr int kEnsItemSites = 32768;
+
 // Tile of one member: 256 threads, full rows when N <= 64 vectors, about
-// 16k sites per work item.
-bool ensemble_tile(int N, cl_precision prec, cl::EnsMember& t) {
+// item_sites sites per work item.
+bool ensemble_tile(int N, cl_precision prec, cl::EnsMember& t, int item_sites, bool two_rows) {
     const int V = prec == CL_FP32 ? 4 : 2;
     t.TZ = N < 64 * V ? N : 64 * V;
     if (t.TZ % V || N % t.TZ) return false;
@@ -1009,10 +1016,10 @@ bool ensemble_tile(int N, cl_precision prec, cl::EnsMember& t) {
     if (256 % BZ) return false;
     // two rows per thread where the lattice is tall enough: twice the work
     // per plane against the same per-plane barriers and LDS round trips
-    t.RY = (2 * 256 / BZ <= N && N % (2 * 256 / BZ) == 0) ? 2 : 1;
+    t.RY = (two_rows && 2 * 256 / BZ <= N && N % (2 * 256 / BZ) == 0) ? 2 : 1;
     t.TY = t.RY * 256 / BZ;
     if (t.TY > N || N % t.TY) return false;
-    int cx = 32768 / (t.TZ * t.TY);
+    int cx = item_sites / (t.TZ * t.TY);
     if (cx < 2) cx = 2;
     while (cx > N || N % cx) cx /= 2;
     if (cx < 1) return false;
@@ -1023,6 +1030,88 @@ bool ensemble_tile(int N, cl_precision prec, cl::EnsMember& t) {
     t.nitems = t.nbz * t.nby * t.nbx;
     // halo items must fit one per thread
     return 2 * BZ + 2 * t.TY <= 256;
+}
+
+// Work decomposition of all members for one (item size, rows per thread)
+// choice: member tiles, the flat item list, partial-sum slots, LDS size and
+// grid.  Device storage grows as needed; a captured graph is dropped.
+cl_status ens_layout(cl_ensemble* e, int item_sites, bool two_rows) {
+    const int n = static_cast<int>(e->m.size());
+    std::vector<cl::EnsMember> table(n);
+    std::vector<size_t> offs(n);
+    std::vector<cl::EnsItem> items;
+    size_t poff = 0;
+    int maxTY = 0, maxTZ = 0;
+    for (int i = 0; i < n; ++i) {
+        cl::EnsMember t{};
+        const int N = e->m[i]->N;
+        if (!ensemble_tile(N, e->prec, t, item_sites, two_rows))
+            return efail(CL_EUNSUPPORTED, "member " + std::to_string(i) + ": N = " + std::to_string(N) +
+                                              " is too small for an ensemble tile (N >= 32 needed)");
+        for (int k = 0; k < t.nitems; ++k) items.push_back({i, k});
+        offs[i] = poff;
+        poff += static_cast<size_t>(cl::nsums(e->nf)) * t.nitems;
+        maxTY = std::max(maxTY, t.TY);
+        maxTZ = std::max(maxTZ, t.TZ);
+        table[i] = t;
+    }
+    if (e->gexec) hipGraphExecDestroy(e->gexec);
+    e->gexec = nullptr;
+    EHIP(hipStreamSynchronize(e->stream));
+    if (poff > e->partials_cap) {
+        if (e->d_partials) hipFree(e->d_partials);
+        e->d_partials = nullptr;
+        e->partials_cap = 0;
+        if (hipMalloc(&e->d_partials, poff * sizeof(double)) != hipSuccess) {
+            e->d_partials = nullptr;
+            return efail(CL_ENOMEM, "ensemble partial sums");
+        }
+        e->partials_cap = poff;
+    }
+    if (items.size() > e->items_cap) {
+        if (e->d_items) hipFree(e->d_items);
+        e->d_items = nullptr;
+        e->items_cap = 0;
+        if (hipMalloc(&e->d_items, items.size() * sizeof(cl::EnsItem)) != hipSuccess) {
+            e->d_items = nullptr;
+            return efail(CL_ENOMEM, "ensemble work items");
+        }
+        e->items_cap = items.size();
+    }
+    for (int i = 0; i < n; ++i) {
+        table[i].partials = e->d_partials + offs[i];
+        table[i].ticket = e->d_tickets + i;
+    }
+    EHIP(hipMemcpyAsync(e->d_items, items.data(), items.size() * sizeof(cl::EnsItem), hipMemcpyHostToDevice,
+                        e->stream));
+    EHIP(hipStreamSynchronize(e->stream));
+    e->table = table;
+    e->nitems = static_cast<int>(items.size());
+    e->lds = cl::ensemble_lds_bytes(e->prec, e->nf, maxTY, maxTZ);
+    e->grid = std::min(cl::ensemble_grid(e->prec, e->nf, e->lds), e->nitems);
+    e->item_sites = item_sites;
+    e->two_rows = two_rows;
+    return CL_OK;
+}
+
+// The member table as the kernel reads it: the layout plus each member's
+// buffers, current buffer, physics and scalar block, uploaded on the stream.
+cl_status ens_upload_table(cl_ensemble* e, bool with_dt) {
+    const int nm = static_cast<int>(e->m.size());
+    for (int i = 0; i < nm; ++i) {
+        cl::EnsMember t = e->table[i];
+        cl_lattice* h = e->m[i];
+        t.buf[0] = h->buf[0];
+        t.buf[1] = h->buf[1];
+        t.N = h->N;
+        t.cur0 = h->cur;
+        t.dt = with_dt ? e->dt[i] : 1.0;
+        t.ph = make_phys(h);
+        t.sc = h->sc;
+        e->staging[i] = t;
+    }
+    EHIP(hipMemcpyAsync(e->d_table, e->staging, nm * sizeof(cl::EnsMember), hipMemcpyHostToDevice, e->stream));
+    return CL_OK;
 }
 
 void ens_free(cl_ensemble* e) {
@@ -1052,9 +1141,6 @@ cl_status cl_ensemble_create(int n, cl_lattice* const* members, cl_ensemble** ou
     };
     e->prec = members[0] ? members[0]->prec : CL_FP32;
     e->nf = members[0] ? members[0]->nf : 1;
-    std::vector<cl::EnsItem> items;
-    size_t poff = 0;
-    int maxTY = 0, maxTZ = 0;
     for (int i = 0; i < n; ++i) {
         cl_lattice* h = members[i];
         if (!h) return bail(CL_EINVAL, "member " + std::to_string(i) + " is NULL");
@@ -1062,41 +1148,25 @@ cl_status cl_ensemble_create(int n, cl_lattice* const* members, cl_ensemble** ou
             if (members[k] == h) return bail(CL_EINVAL, "a lattice appears twice in the ensemble");
         if (h->prec != e->prec || h->nf != e->nf)
             return bail(CL_EINVAL, "all members need the same precision and number of fields");
-        cl::EnsMember t{};
-        if (!ensemble_tile(h->N, h->prec, t))
-            return bail(CL_EUNSUPPORTED, "member " + std::to_string(i) + ": N = " + std::to_string(h->N) +
-                                             " is too small for an ensemble tile (N >= 32 needed)");
-        for (int k = 0; k < t.nitems; ++k) items.push_back({i, k});
-        t.partials = reinterpret_cast<double*>(poff);  // offset, fixed up below
-        poff += static_cast<size_t>(cl::nsums(e->nf)) * t.nitems;
-        maxTY = std::max(maxTY, t.TY);
-        maxTZ = std::max(maxTZ, t.TZ);
-        e->table.push_back(t);
         e->m.push_back(h);
     }
     e->dt.assign(n, 0.0);
-    e->nitems = static_cast<int>(items.size());
     if (hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking) != hipSuccess)
         return bail(CL_EDEVICE, "hipStreamCreate failed");
-    if (hipMalloc(&e->d_partials, poff * sizeof(double)) != hipSuccess ||
-        hipMalloc(&e->d_tickets, n * sizeof(unsigned)) != hipSuccess ||
+    if (hipMalloc(&e->d_tickets, n * sizeof(unsigned)) != hipSuccess ||
         hipMalloc(&e->d_counter, 64) != hipSuccess ||
-        hipMalloc(&e->d_items, items.size() * sizeof(cl::EnsItem)) != hipSuccess ||
         hipMalloc(&e->d_table, n * sizeof(cl::EnsMember)) != hipSuccess ||
         hipHostMalloc(&e->staging, n * sizeof(cl::EnsMember)) != hipSuccess)
         return bail(CL_ENOMEM, "ensemble device tables");
-    for (int i = 0; i < n; ++i) {
-        e->table[i].partials = e->d_partials + reinterpret_cast<size_t>(e->table[i].partials);
-        e->table[i].ticket = e->d_tickets + i;
-    }
     if (hipMemsetAsync(e->d_tickets, 0, n * sizeof(unsigned), e->stream) != hipSuccess ||
         hipMemsetAsync(e->d_counter, 0, 64, e->stream) != hipSuccess ||
-        hipMemcpyAsync(e->d_items, items.data(), items.size() * sizeof(cl::EnsItem), hipMemcpyHostToDevice,
-                       e->stream) != hipSuccess ||
         hipStreamSynchronize(e->stream) != hipSuccess)
         return bail(CL_EDEVICE, "ensemble table upload");
-    e->lds = cl::ensemble_lds_bytes(e->prec, e->nf, maxTY, maxTZ);
-    e->grid = std::min(cl::ensemble_grid(e->prec, e->nf, e->lds), e->nitems);
+    const cl_status st = ens_layout(e, kEnsItemSites, true);
+    if (st) {
+        const std::string msg = g_err;
+        return bail(st, msg);
+    }
     *out = e;
     return CL_OK;
 }
@@ -1123,19 +1193,8 @@ cl_status cl_ensemble_step(cl_ensemble* e, cl_integrator integ, int n, cl_observ
         if (!(e->dt[i] > 0.0)) return efail(CL_ESTATE, "dt of member " + std::to_string(i) + " not set");
     // members' own queued work finishes first
     for (cl_lattice* h : e->m) EHIP(hipStreamSynchronize(h->stream));
-    for (int i = 0; i < nm; ++i) {
-        cl::EnsMember& t = e->table[i];
-        cl_lattice* h = e->m[i];
-        t.buf[0] = h->buf[0];
-        t.buf[1] = h->buf[1];
-        t.N = h->N;
-        t.cur0 = h->cur;
-        t.dt = e->dt[i];
-        t.ph = make_phys(h);
-        t.sc = h->sc;
-        e->staging[i] = t;
-    }
-    EHIP(hipMemcpyAsync(e->d_table, e->staging, nm * sizeof(cl::EnsMember), hipMemcpyHostToDevice, e->stream));
+    cl_status ust = ens_upload_table(e, true);
+    if (ust) return ust;
     const size_t need = static_cast<size_t>(n) * nm;
     if (need > e->obs_cap) {
         if (e->d_obs) hipFree(e->d_obs);
@@ -1226,6 +1285,107 @@ cl_status cl_ensemble_get_tile(const cl_ensemble* e, int i, cl_tile* out) {
     out->cx = t.CX;
     out->ry = t.RY;
     out->pd = t.RY == 1 ? 4 : 2;  // the prefetch depth does not change the results
+    return CL_OK;
+}
+
+cl_status cl_ensemble_autotune(cl_ensemble* e, int reps, char* report, size_t cap) {
+    if (!e) return efail(CL_EINVAL, "ensemble is NULL");
+    if (reps < 1) reps = 3;
+    for (cl_lattice* h : e->m) EHIP(hipStreamSynchronize(h->stream));
+    const int nm = static_cast<int>(e->m.size());
+    // Passes without drift, with zero kicks and no scale-factor step copy
+    // every member's (f, pi) exactly, so pairs of them leave the fields where
+    // they were; their scalar steps rewrite the scalar blocks, which are
+    // restored afterwards.
+    std::vector<Scal> saved(nm);
+    for (int i = 0; i < nm; ++i) EHIP(hipMemcpy(&saved[i], e->m[i]->sc, sizeof(Scal), hipMemcpyDeviceToHost));
+    const int keep_sites = e->item_sites;
+    const bool keep_rows = e->two_rows;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    EHIP(hipEventCreate(&e0));
+    EHIP(hipEventCreate(&e1));
+    std::string js = "{\"members\":" + std::to_string(nm) + ",\"reps\":" + std::to_string(reps) + ",\"candidates\":[";
+    std::vector<std::vector<int>> seen;
+    int best_sites = keep_sites;
+    bool best_rows = keep_rows;
+    float best_ms = -1.0f;
+    cl_status st = CL_OK;
+    bool first = true;
+    const int pairs = (reps + 1) / 2;
+    for (int sites : {8192, 16384, 32768, 65536, 131072}) {
+        for (bool rows : {true, false}) {
+            st = ens_layout(e, sites, rows);
+            if (st) break;
+            std::vector<int> sig;  // skip layouts equal to one already timed
+            for (const cl::EnsMember& t : e->table) sig.insert(sig.end(), {t.TZ, t.TY, t.CX, t.RY});
+            if (std::find(seen.begin(), seen.end(), sig) != seen.end()) continue;
+            seen.push_back(sig);
+            st = ens_upload_table(e, false);
+            if (st) break;
+            cl::EnsArgs a{};
+            a.members = e->d_table;
+            a.items = e->d_items;
+            a.nitems = e->nitems;
+            a.nmembers = nm;
+            a.drift = 0;
+            a.write_out = 1;
+            a.flags = 1;
+            a.rec = -1;
+            a.counter = e->d_counter;
+            a.obs = nullptr;
+            a.lds_bytes = static_cast<int>(e->lds);
+            a.ckt = a.ckb = a.chn = 0.0;
+            auto pair = [&]() {
+                hipError_t r = hipSuccess;
+                for (int q = 0; q < 2 && r == hipSuccess; ++q) {
+                    a.parity = q;
+                    r = cl::launch_ensemble_pass(a, e->prec, e->nf, e->grid, e->stream);
+                }
+                return r;
+            };
+            hipError_t r = pair();  // warm-up
+            if (r == hipSuccess) r = hipEventRecord(e0, e->stream);
+            for (int k = 0; k < pairs && r == hipSuccess; ++k) r = pair();
+            if (r == hipSuccess) r = hipEventRecord(e1, e->stream);
+            if (r == hipSuccess) r = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (r == hipSuccess) r = hipEventElapsedTime(&ms, e0, e1);
+            if (r != hipSuccess) {
+                st = efail(CL_EDEVICE, std::string("ensemble autotune: ") + hipGetErrorString(r));
+                break;
+            }
+            ms /= 2 * pairs;
+            char item[128];
+            std::snprintf(item, sizeof item, "%s{\"item_sites\":%d,\"two_rows\":%s,\"us\":%.2f}", first ? "" : ",",
+                          sites, rows ? "true" : "false", ms * 1e3);
+            js += item;
+            first = false;
+            if (best_ms < 0.0f || ms < best_ms) {
+                best_ms = ms;
+                best_sites = sites;
+                best_rows = rows;
+            }
+        }
+        if (st) break;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    for (int i = 0; i < nm; ++i) EHIP(hipMemcpy(e->m[i]->sc, &saved[i], sizeof(Scal), hipMemcpyHostToDevice));
+    if (st) {
+        const std::string msg = g_err;
+        (void)ens_layout(e, keep_sites, keep_rows);
+        return efail(st, msg);
+    }
+    st = ens_layout(e, best_sites, best_rows);
+    if (st) return st;
+    char tail[128];
+    std::snprintf(tail, sizeof tail, "],\"best\":{\"item_sites\":%d,\"two_rows\":%s,\"us\":%.2f}}", best_sites,
+                  best_rows ? "true" : "false", best_ms * 1e3);
+    js += tail;
+    if (report && cap) {
+        std::strncpy(report, js.c_str(), cap - 1);
+        report[cap - 1] = '\0';
+    }
     return CL_OK;
 }
 

@@ -57,6 +57,45 @@ def test_ensemble_equals_solo_bitwise(integrator):
         assert np.array_equal(f, fields[i][0]) and np.array_equal(p, fields[i][1]), i
 
 
+def test_ensemble_autotune_keeps_state_and_solo_equality():
+    """The ensemble autotuner times distinct decompositions on the members'
+    states without changing them (fields and background bitwise), and with
+    the decomposition it keeps every member still equals its solo run bitwise:
+    the solo lattice takes the same calls, three leapfrog steps in the
+    default ensemble tile and five VV4 steps in the tuned one."""
+    ws = small_members()
+    lats = [member_lattice(w) for w in ws]
+    ens = _lib().Ensemble(lats)
+    for i, w in enumerate(ws):
+        ens.set_dt(i, w.dt)
+    tiles0 = [ens.get_tile(i) for i in range(len(ws))]
+    r0 = ens.step("leapfrog", 3)
+    before = [(lat.get_fields(), lat.get_state()) for lat in lats]
+    rep = ens.autotune(reps=2)
+    after = [(lat.get_fields(), lat.get_state()) for lat in lats]
+    assert len(rep["candidates"]) >= 2 and rep["best"]["us"] > 0
+    assert {c["item_sites"] for c in rep["candidates"]} <= {8192, 16384, 32768, 65536, 131072}
+    for (fb, sb), (fa, sa) in zip(before, after):
+        assert np.array_equal(fb[0], fa[0]) and np.array_equal(fb[1], fa[1])
+        assert sb == sa
+    r = ens.step("vv4", 5)
+    fields = [lat.get_fields() for lat in lats]
+    tiles = [ens.get_tile(i) for i in range(len(ws))]
+    ens.close()
+    for lat in lats:
+        lat.close()
+    for i, w in enumerate(ws):
+        solo = member_lattice(w, tiles0[i])
+        rs0 = solo.step("leapfrog", w.dt, 3)
+        solo.set_tile(**tiles[i])
+        rs = solo.step("vv4", w.dt, 5)
+        f, p = solo.get_fields()
+        solo.close()
+        assert rs0.tobytes() == np.ascontiguousarray(r0[:, i]).tobytes(), i
+        assert np.array_equal(f, fields[i][0]) and np.array_equal(p, fields[i][1]), (i, tiles[i])
+        assert rs.tobytes() == np.ascontiguousarray(r[:, i]).tobytes(), i
+
+
 def test_ensemble_fp64_matches_oracle():
     ws = [W.C0.with_(N=32, seed=1000 + r, amp=30.0) for r in range(2)] + [W.C0.with_(N=64, seed=7, amp=30.0)]
     lats = [member_lattice(w) for w in ws]
@@ -103,15 +142,17 @@ def test_ensemble_errors():
 
 
 def test_config2_ensemble_sampled_members():
-    """The 96-member uneven ensemble (48 x 32^3, 32 x 64^3, 16 x 128^3, FP32):
-    every record finite, a(eta) grows, and sampled members equal their solo
-    runs bitwise."""
+    """The 96-member uneven ensemble (48 x 32^3, 32 x 64^3, 16 x 128^3, FP32)
+    in the decomposition its autotuner picks, as benchmarked: every record
+    finite, a(eta) grows, and sampled members equal their solo runs
+    bitwise."""
     ws = W.ensemble_members()
     assert len(ws) == 96
     lats = [member_lattice(w) for w in ws]
     ens = _lib().Ensemble(lats)
     for i, w in enumerate(ws):
         ens.set_dt(i, w.dt)
+    ens.autotune(reps=3)
     n = 20
     r = ens.step("leapfrog", n)
     assert not np.any(r["nonfinite"])
