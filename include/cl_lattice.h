@@ -51,14 +51,17 @@ typedef enum { CL_STATIC = 0, CL_SELF_CONSISTENT = 1 } cl_expansion;
 
 /* CL_LEAPFROG: staggered leapfrog, O(dt^2).  CL_VV4: 4th-order Yoshida
  * composition of velocity Verlet, O(dt^4) (Sect. 4.1).  CL_RK2, CL_RK3,
- * CL_RK4: low-storage Runge-Kutta schemes of the (f, pi, a, a') system with
- * one auxiliary array per field and momentum (Sect. 4.1, RK family): the
- * explicit midpoint rule (2 stages, O(dt^2)), Williamson's RK3-3 (3 stages,
- * O(dt^3)) and Carpenter-Kennedy's RK4-5 (5 stages, O(dt^4)).  A
+ * CL_RK34, CL_RK4: low-storage Runge-Kutta schemes of the (f, pi, a, a')
+ * system with one auxiliary array per field and momentum (Sect. 4.1, RK
+ * family): the explicit midpoint rule (2 stages, O(dt^2)), Williamson's
+ * RK3-3 (3 stages, O(dt^3)), an RK3-4 (4 stages, O(dt^3); the paper names
+ * the scheme without coefficients: ours meets the order-3 conditions and
+ * minimises the order-4 error terms) and Carpenter-Kennedy's RK4-5 (5
+ * stages, O(dt^4)).  A
  * Runge-Kutta step costs one fused pass per stage, each moving 32 B per
  * field and site in FP32 (64 B in FP64), against 16 (32) for a leapfrog pass;
  * the auxiliary arrays are allocated by the first Runge-Kutta step. */
-typedef enum { CL_LEAPFROG = 0, CL_VV4 = 1, CL_RK2 = 2, CL_RK3 = 3, CL_RK4 = 4 } cl_integrator;
+typedef enum { CL_LEAPFROG = 0, CL_VV4 = 1, CL_RK2 = 2, CL_RK3 = 3, CL_RK4 = 4, CL_RK34 = 5 } cl_integrator;
 
 /* V = sum_j (m2[j] f_j^2 / 2 + lambda[j] f_j^4 / 4) + g2 f_0^2 f_1^2 / 2 + V0,
  * in program variables (Eq. FieldSpaceTimeNaturalVariables).  With two fields

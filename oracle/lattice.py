@@ -217,6 +217,11 @@ def vv2(s: State, h: float, P: Params) -> State:
 RK_SCHEMES = {
     "rk2": ([0.0, -0.5], [0.5, 1.0]),
     "rk3": ([0.0, -5.0 / 9.0, -153.0 / 128.0], [1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0]),
+    # RK3-4: the paper names a four-stage third-order low-storage scheme
+    # without coefficients; this member of the 2N family satisfies the order-3
+    # conditions and minimises the order-4 error terms.
+    "rk34": ([0.0, -0.35643988236064206, -0.9681295617245512, -1.7681569348912718],
+             [0.16095368082904207, 0.32750970610000874, 0.759520141721668, 1.0254284658050152]),
     "rk4": ([0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
              -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0],
             [1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,

@@ -147,7 +147,7 @@ def rk4_homogeneous(f0, p0, a0, b0, T, h, alpha, mp, lam):
     return y
 
 
-@pytest.mark.parametrize("integrator,order", [("leapfrog", 2), ("vv4", 4), ("rk2", 2), ("rk3", 3), ("rk4", 4)])
+@pytest.mark.parametrize("integrator,order", [("leapfrog", 2), ("vv4", 4), ("rk2", 2), ("rk3", 3), ("rk34", 3), ("rk4", 4)])
 @pytest.mark.parametrize("alpha", [1.0, 0.0])
 def test_homogeneous_mode_against_rk4(integrator, order, alpha):
     """P3: a uniform lattice reduces to the ODE of (f, p, a, b); the oracle
@@ -168,11 +168,22 @@ def test_homogeneous_mode_against_rk4(integrator, order, alpha):
         got = np.array([s.f[0, 0, 0, 0], s.p[0, 0, 0, 0], s.a, s.b])
         errs.append(np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 1e-3)))
     ratio = errs[0] / errs[1]
-    assert abs(ratio / 2 ** order - 1) < 0.15, (errs, ratio)
+    assert_order(integrator, order, ratio, 0.15, errs)
+
+
+def assert_order(integrator, order, ratio, tol, info):
+    """Error ratio on halving the step equals 2^order.  RK3-4 was chosen to
+    minimise its order-4 error terms, so where its order-3 term is small the
+    h^4 term still dominates at these steps: for it the pin asks for at least
+    order 3 (a wrong coefficient drops the order and fails either way)."""
+    if integrator == "rk34":
+        assert ratio / 2 ** order > 1 - tol, (info, ratio)
+    else:
+        assert abs(ratio / 2 ** order - 1) < tol, (info, ratio)
 
 
 # ---------------------------------------------------------------- P11
-@pytest.mark.parametrize("integrator,order", [("leapfrog", 2), ("vv4", 4), ("rk2", 2), ("rk3", 3), ("rk4", 4)])
+@pytest.mark.parametrize("integrator,order", [("leapfrog", 2), ("vv4", 4), ("rk2", 2), ("rk3", 3), ("rk34", 3), ("rk4", 4)])
 def test_closed_form_expansion(integrator, order):
     """P11: (i) vacuum energy V0 with alpha = 1 gives a = 1/(1 - H0 eta),
     H0^2 = V0/(3 mp^2); alpha = 0 gives a = exp(H0 t); (ii) kination
@@ -191,9 +202,12 @@ def test_closed_form_expansion(integrator, order):
     Hk = math.sqrt(pbar ** 2 / 6)
     cases.append((L.Params(N=N, dx=1.0, alpha=1.0, lam=(0.0, 0.0)), pbar, 3.0,
                   lambda e: math.sqrt(1.0 + 2.0 * Hk * e)))
+    # RK3-4's order-3 error term is small in the first case, whose error
+    # changes sign near dt = 0.04: its pairs are taken where h^3 dominates
+    steps = (0.00625, 0.003125) if integrator == "rk34" else (0.05, 0.025)
     for P, pb, T, exact in cases:
         errs = []
-        for dt in (0.05, 0.025):
+        for dt in steps:
             f = np.zeros((1, N, N, N))
             p = np.full((1, N, N, N), pb)
             E = L.energies(f, p, 1.0, P)
@@ -203,7 +217,7 @@ def test_closed_form_expansion(integrator, order):
                 s = L.step(s, dt, P, integrator)
             errs.append(abs(s.a - exact(s.eta)))
         ratio = errs[0] / errs[1]
-        assert abs(ratio / 2 ** order - 1) < 0.15, (P, errs, ratio)
+        assert_order(integrator, order, ratio, 0.15, (P, errs))
 
 
 # ---------------------------------------------------------------- P4
@@ -465,7 +479,7 @@ def butcher_from_low_storage(A, B):
     return a, b, a.sum(axis=1)
 
 
-@pytest.mark.parametrize("scheme,order", [("rk2", 2), ("rk3", 3), ("rk4", 4)])
+@pytest.mark.parametrize("scheme,order", [("rk2", 2), ("rk3", 3), ("rk34", 3), ("rk4", 4)])
 def test_low_storage_order_conditions(scheme, order):
     """The published low-storage coefficients satisfy the Runge-Kutta order
     conditions of their order (Butcher's rooted-tree conditions up to order
