@@ -404,37 +404,43 @@ def surrogate_run(epochs=12, pairs_per_seed=64, train_seeds=range(2000, 2008), e
     return out
 
 
-def rk_bytes_per_step(stages: int, precision: str, nf: int) -> int:
-    """Algorithmic bytes per site of one low-storage Runge-Kutta step: the
+def rk_bytes_per_step(stages: int, precision: str, nf: int, classic: bool = False) -> int:
+    """Algorithmic bytes per site of one Runge-Kutta step.  Low storage: the
     first stage reads f, pi and writes f, pi and their registers; every
-    later stage also reads the registers."""
+    later stage also reads the registers.  Standard RK4: stage 1 reads the
+    state and writes the next stage input and the stage sum; stages 2 and 3
+    also read the step's start and the sum; stage 4 writes no sum."""
     e = 4 if precision == "fp32" else 8
+    if classic:
+        return nf * e * 2 * (3 + 5 + 5 + 4)
     return nf * e * (6 + 8 * (stages - 1))
 
 
-def rk_run(w, steps, r64, tile):
-    """RK4-5 (5 stages) in FP32 on the same workload and tile, from the same
-    seed: rate, HBM fraction and deviation from the FP64 VV4 run over the
-    same steps."""
+def rk_run(w, steps, r64, tile, scheme="rk4"):
+    """A fourth-order Runge-Kutta scheme (RK4-5, 5 stages, or the standard
+    RK4) in FP32 on the same workload and tile, from the same seed: rate,
+    HBM fraction and deviation from the FP64 VV4 run over the same steps."""
     import torch
     stream = torch.cuda.Stream()
     lat = make(w, "fp32", stream, tune=False,
                tile=(tile["tz"], tile["ty"], tile["cx"], tile["ry"], tile["pd"]))
     chunk = min(steps, 100)
-    recs = [lat.step("rk4", w.dt, chunk)]   # untimed first call (graph capture)
+    recs = [lat.step(scheme, w.dt, chunk)]   # untimed first call (graph capture)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps // chunk - 1):
-        recs.append(lat.step("rk4", w.dt, chunk))
+        recs.append(lat.step(scheme, w.dt, chunk))
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
     lat.close()
     timed = (steps // chunk - 1) * chunk
     r = np.concatenate(recs)
-    alg = rk_bytes_per_step(5, "fp32", w.n_fields) * w.sites * timed / sec / 1e9
-    return {"scheme": "rk4 (Carpenter-Kennedy 5-stage)", "steps": timed,
-            "site_updates_per_s": w.sites * timed / sec, "ms_per_step": 1e3 * sec / timed,
-            "hbm_frac": alg / HBM_PEAK_GBS, "bytes_per_site_step": rk_bytes_per_step(5, "fp32", w.n_fields),
+    classic = scheme == "rk4_classic"
+    per_site = rk_bytes_per_step(5, "fp32", w.n_fields, classic)
+    alg = per_site * w.sites * timed / sec / 1e9
+    return {"scheme": "standard RK4 (4 stages, 3 auxiliary arrays)" if classic else "rk4 (Carpenter-Kennedy 5-stage)",
+            "steps": timed, "site_updates_per_s": w.sites * timed / sec, "ms_per_step": 1e3 * sec / timed,
+            "hbm_frac": alg / HBM_PEAK_GBS, "bytes_per_site_step": per_site,
             "vs_fp64_vv4_rel_dev": linear_regime_deviation(r, r64[:len(r)], w.n_fields)}
 
 
@@ -554,6 +560,8 @@ def main():
         if args.workload == "c1":
             progress("rk4 form")
             forms["rk4_fp32"] = rk_run(w, 1000, r64, tile32)
+            progress("standard rk4 form")
+            forms["rk4_classic_fp32"] = rk_run(w, 1000, r64, tile32, scheme="rk4_classic")
     if args.workload == "c1":
         progress("power spectrum form")
         forms["spectrum"] = spectrum_run(w)

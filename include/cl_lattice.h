@@ -57,11 +57,21 @@ typedef enum { CL_STATIC = 0, CL_SELF_CONSISTENT = 1 } cl_expansion;
  * RK3-3 (3 stages, O(dt^3)), an RK3-4 (4 stages, O(dt^3); the paper names
  * the scheme without coefficients: ours meets the order-3 conditions and
  * minimises the order-4 error terms) and Carpenter-Kennedy's RK4-5 (5
- * stages, O(dt^4)).  A
+ * stages, O(dt^4)).  CL_RK4_CLASSIC: the standard four-stage RK4 with
+ * three auxiliary arrays per degree of freedom (Sect. 4.1: the RK
+ * family's standard O(dt^4) method), each stage one fused pass.  A
  * Runge-Kutta step costs one fused pass per stage, each moving 32 B per
  * field and site in FP32 (64 B in FP64), against 16 (32) for a leapfrog pass;
  * the auxiliary arrays are allocated by the first Runge-Kutta step. */
-typedef enum { CL_LEAPFROG = 0, CL_VV4 = 1, CL_RK2 = 2, CL_RK3 = 3, CL_RK4 = 4, CL_RK34 = 5 } cl_integrator;
+typedef enum {
+    CL_LEAPFROG = 0,
+    CL_VV4 = 1,
+    CL_RK2 = 2,
+    CL_RK3 = 3,
+    CL_RK4 = 4,
+    CL_RK34 = 5,
+    CL_RK4_CLASSIC = 6
+} cl_integrator;
 
 /* V = sum_j (m2[j] f_j^2 / 2 + lambda[j] f_j^4 / 4) + g2 f_0^2 f_1^2 / 2 + V0,
  * in program variables (Eq. FieldSpaceTimeNaturalVariables).  With two fields

@@ -13,8 +13,9 @@ Contents
                 velocity-Verlet / leapfrog / 4th-order Yoshida time steps
                 (Sect. 2.1 Eqs. singletEOM, Friedmann1, Friedmann2, rhoLocal,
                 energy-contrib; Sect. 4.1 Eqs. SchemeContVirgin1-4), and the
-                low-storage Runge-Kutta steps RK2, RK3-3, RK4-5 of the
-                (f, pi, a, a') system (Sect. 4.1, RK family).
+                low-storage Runge-Kutta steps RK2, RK3-3, RK3-4, RK4-5
+                and the standard RK4 of the (f, pi, a, a') system (Sect.
+                4.1, RK family).
   seed       -- counter-based RNG and the vacuum-fluctuation initial
                 condition (Sect. 2.3 Eqs. QuantumFlucts, fpr_influct,
                 fpr_influct2; Sect. 4.3 DFT convention).

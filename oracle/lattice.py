@@ -262,6 +262,24 @@ def rk_step(s: State, h: float, P: Params, scheme: str) -> State:
     return State(f, p, a, b, s.eta + h)
 
 
+def rk4_classic_step(s: State, h: float, P: Params) -> State:
+    """One step of the standard fourth-order Runge-Kutta method (the RK
+    family's O(dt^4) standard scheme, Sect. 4.1) for (f, pi, a, a'):
+    k1 = F(y), k2 = F(y + h/2 k1), k3 = F(y + h/2 k2), k4 = F(y + h k3),
+    y + h/6 (k1 + 2 k2 + 2 k3 + k4)."""
+    y = (s.f, s.p, s.a, s.b)
+
+    def shifted(c, k):
+        return tuple(yi + c * h * ki for yi, ki in zip(y, k))
+
+    k1 = rhs(*y, P)
+    k2 = rhs(*shifted(0.5, k1), P)
+    k3 = rhs(*shifted(0.5, k2), P)
+    k4 = rhs(*shifted(1.0, k3), P)
+    f, p, a, b = (yi + h / 6.0 * (q1 + 2.0 * q2 + 2.0 * q3 + q4) for yi, q1, q2, q3, q4 in zip(y, k1, k2, k3, k4))
+    return State(f, p, a, b, s.eta + h)
+
+
 def step(s: State, dt: float, P: Params, integrator: str = "leapfrog") -> State:
     """One full time step.  leapfrog is velocity Verlet of size dt (its field
     trajectory is the staggered leapfrog one); vv4 is the Yoshida triple jump
@@ -274,6 +292,8 @@ def step(s: State, dt: float, P: Params, integrator: str = "leapfrog") -> State:
         return vv2(s, W1 * dt, P)
     if integrator in RK_SCHEMES:
         return rk_step(s, dt, P, integrator)
+    if integrator == "rk4_classic":
+        return rk4_classic_step(s, dt, P)
     raise ValueError(integrator)
 
 

@@ -151,7 +151,7 @@ def _dptr(a: np.ndarray):
 
 
 PRECISIONS = {"fp64": CL_FP64, "fp32": CL_FP32}
-INTEGRATORS = {"leapfrog": CL_LEAPFROG, "vv4": CL_VV4, "rk2": 2, "rk3": 3, "rk4": 4, "rk34": 5}
+INTEGRATORS = {"leapfrog": CL_LEAPFROG, "vv4": CL_VV4, "rk2": 2, "rk3": 3, "rk4": 4, "rk34": 5, "rk4_classic": 6}
 EXPANSIONS = {"static": CL_STATIC, "self": CL_SELF_CONSISTENT}
 
 

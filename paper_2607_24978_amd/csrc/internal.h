@@ -40,7 +40,8 @@ struct Scal {
     double mean_p[2];  // mean of the momenta written last
     double pa1, pa0;   // a_next^(2 alpha + 1), a_next^(2 alpha) (for the next Friedmann step)
     double pf;         // a_next^(alpha - 3) (the drift rate of a Runge-Kutta stage)
-    double da, db;     // low-storage Runge-Kutta registers of a and a'
+    double da, db;     // Runge-Kutta registers of a and a' (low-storage d; classic: the weighted sum of stages)
+    double a0, b0;     // classic Runge-Kutta: a and a' at the start of the step
     int32_t nonfinite; // sticky: a lattice sum was NaN / Inf
     int32_t pad;
 };
@@ -97,14 +98,20 @@ struct PassArgs {
     int prev_rec;       // observable slot of the previous pass, -1: none
     int pad_;
     double pkt, pkb, phn;  // kt, kb, h_next of the previous pass
-    // Runge-Kutta stage (rk = 1): d <- rkA d + rkh F(y); y <- y + rkB d for
-    // the fields (aux holds d_f, d_pi in the state layout) and, in the scalar
-    // step, for (a, a').  rk_first: rkA = 0, aux is not read.
+    // Runge-Kutta stage, for the fields (registers in `aux`, state layout) and,
+    // in the scalar step, for (a, a').  rk = 1, low storage: d <- rkA d +
+    // rkh F(y); y <- y + rkB d (rk_first: rkA = 0, aux is not read).  rk = 2,
+    // classic: k = rkh F(Y) at the stage input Y; output y0 + rkA s + rkB k,
+    // s <- rkC s + rkD k with y0 the state at the start of the step (in `y0`;
+    // the stage input itself when rk_first) and s the weighted sum of the
+    // stages in `aux` (not read when rk_first, not written when rk_last).
     int rk, rk_first;
-    int prev_rk, pad2_;  // prev_rk: the pending step is a Runge-Kutta stage's
-    double rkA, rkB, rkh, rkdeta;   // rkdeta: time advanced by this stage
-    double prkA, prkB, prkh, prkdeta;  // the previous pass's stage coefficients
+    int prev_rk, prev_rk_first;  // the pending step is a Runge-Kutta stage's
+    int rk_last, pad3_;
+    double rkA, rkB, rkC, rkD, rkh, rkdeta;      // rkdeta: time advanced by this stage
+    double prkA, prkB, prkC, prkD, prkh, prkdeta;  // the previous pass's stage coefficients
     void* aux;
+    const void* y0;
     cl_observables* obs;
     Phys ph;
 };
@@ -201,6 +208,7 @@ struct cl_lattice {
     int device = 0;
     void* buf[2] = {nullptr, nullptr};  // ping-pong state buffers (row-interleaved layout)
     void* aux = nullptr;                // Runge-Kutta registers of f and pi (same layout), on first use
+    void* aux2 = nullptr;               // classic RK4: the third stage buffer, on first use
     double2* spec = nullptr;            // power spectrum: N^3 complex FP64, on first use
     double2* spec_tw = nullptr;         // its twiddle factors (N / 2)
     double* spec_sums = nullptr;        // per-bin sums and counts (spec_cap bins)

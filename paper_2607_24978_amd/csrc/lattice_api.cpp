@@ -126,10 +126,11 @@ PassArgs base_args(cl_lattice* h, int in) {
     a.prev_partials = nullptr;
     a.has_prev = 0;
     a.prev_rec = -1;
-    a.rk = a.rk_first = a.prev_rk = 0;
-    a.rkA = a.rkB = a.rkh = a.rkdeta = 0.0;
-    a.prkA = a.prkB = a.prkh = a.prkdeta = 0.0;
+    a.rk = a.rk_first = a.prev_rk = a.prev_rk_first = a.rk_last = 0;
+    a.rkA = a.rkB = a.rkC = a.rkD = a.rkh = a.rkdeta = 0.0;
+    a.prkA = a.prkB = a.prkC = a.prkD = a.prkh = a.prkdeta = 0.0;
     a.aux = h->aux;
+    a.y0 = nullptr;
     a.obs = h->obs;
     a.ph = make_phys(h);
     a.rec = -1;
@@ -157,8 +158,11 @@ struct PassSeq {
         a.phn = prev.h_next;
         a.prev_rec = prev.rec;
         a.prev_rk = prev.rk;
+        a.prev_rk_first = prev.rk_first;
         a.prkA = prev.rkA;
         a.prkB = prev.rkB;
+        a.prkC = prev.rkC;
+        a.prkD = prev.rkD;
         a.prkh = prev.rkh;
         a.prkdeta = prev.rkdeta;
     }
@@ -204,7 +208,7 @@ void substeps(cl_integrator integ, double dt, int n, std::vector<double>& h, int
 }
 
 bool is_rk(cl_integrator integ) {
-    return integ == CL_RK2 || integ == CL_RK3 || integ == CL_RK34 || integ == CL_RK4;
+    return integ == CL_RK2 || integ == CL_RK3 || integ == CL_RK34 || integ == CL_RK4 || integ == CL_RK4_CLASSIC;
 }
 
 // Low-storage Runge-Kutta coefficients (d <- A d + h F(y), y <- y + B d):
@@ -246,10 +250,60 @@ std::vector<double> rk_abscissae(const std::vector<double>& A, const std::vector
     return c;
 }
 
+// Passes of n classic RK4 steps (the standard scheme, three auxiliary arrays
+// per degree of freedom): with y0 in buffer A = buf[cur], the stages read
+// Y1 = y0 (A), Y2 (B = buf[cur^1]), Y3 (aux2), Y4 (B) and write Y2 = y0 + k1/2
+// (to B), Y3 = y0 + k2/2 (aux2), Y4 = y0 + k3 (B) and finally
+// y0 + (k1 + 2 k2 + 2 k3)/6 + k4/6 in place into A, reading y0 only at each
+// thread's own sites; the weighted sum s of the k's lives in aux.  Then a
+// reduction-only pass records the final state, as for the low-storage schemes.
+cl_status issue_rk4_classic_steps(cl_lattice* h, double dt, int n, int cur) {
+    void* A = h->buf[cur];
+    void* B = h->buf[cur ^ 1];
+    void* X = h->aux2;
+    // per stage: input, output; output = y0 + P s + Q k, s <- R s + S k
+    void* in[4] = {A, B, X, B};
+    void* out[4] = {B, X, B, A};
+    const double P[4] = {0.0, 0.0, 0.0, 1.0}, Q[4] = {0.5, 0.5, 1.0, 1.0 / 6.0};
+    const double R[4] = {0.0, 1.0, 1.0, 0.0}, S[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 0.0};
+    const double deta[4] = {0.5, 0.0, 0.5, 0.0};  // time of each output past the input's
+    PassSeq seq(h);
+    for (int k = 0; k < n; ++k)
+        for (int i = 0; i < 4; ++i) {
+            PassArgs r = base_args(h, cur);
+            r.in = in[i];
+            r.out = out[i];
+            r.y0 = A;
+            r.drift = 0;
+            r.write_out = 1;
+            r.kt = r.kb = r.h_next = 0.0;
+            r.rk = 2;
+            r.rk_first = i == 0;
+            r.rk_last = i == 3;
+            r.rkA = P[i];
+            r.rkB = Q[i];
+            r.rkC = R[i];
+            r.rkD = S[i];
+            r.rkh = dt;
+            r.rkdeta = deta[i] * dt;
+            r.rec = (i == 0 && k > 0) ? k - 1 : -1;
+            HIPCHECK(h, seq.launch(r));
+        }
+    PassArgs z = base_args(h, cur);
+    z.drift = 0;
+    z.write_out = 0;
+    z.kt = z.kb = z.h_next = 0.0;
+    z.rec = n - 1;
+    HIPCHECK(h, seq.launch(z));
+    HIPCHECK(h, seq.close());
+    return CL_OK;
+}
+
 // Passes of n low-storage Runge-Kutta steps: one stage pass per stage, then
 // a reduction-only pass whose scalar step records the final state.  The
 // scalar step of stage 0 of step k records the end of step k - 1.
 cl_status issue_rk_steps(cl_lattice* h, cl_integrator integ, double dt, int n, int cur) {
+    if (integ == CL_RK4_CLASSIC) return issue_rk4_classic_steps(h, dt, n, cur);
     std::vector<double> A, B;
     rk_coefficients(integ, A, B);
     const std::vector<double> c = rk_abscissae(A, B);
@@ -532,6 +586,7 @@ cl_status cl_destroy(cl_lattice* h) {
     drop_graph(h);
     free_buffers(h);
     if (h->aux) hipFree(h->aux);
+    if (h->aux2) hipFree(h->aux2);
     for (void* q : {(void*)h->spec, (void*)h->spec_tw, (void*)h->spec_sums, (void*)h->spec_counts})
         if (q) hipFree(q);
     if (h->sc) hipFree(h->sc);
@@ -682,13 +737,25 @@ cl_status cl_step(cl_lattice* h, cl_integrator integ, double dt, int n, cl_obser
     if (st) return st;
     if (is_rk(integ) && !h->aux) {
         // Runge-Kutta registers of (f, pi): one more state-sized buffer
-        if (hipMalloc(&h->aux, state_bytes(h)) != hipSuccess)
+        if (hipMalloc(&h->aux, state_bytes(h)) != hipSuccess) {
+            h->aux = nullptr;
             return fail(h, CL_ENOMEM, "Runge-Kutta registers (" + std::to_string(state_bytes(h)) + " bytes)");
+        }
+        drop_graph(h);
+    }
+    if (integ == CL_RK4_CLASSIC && !h->aux2) {
+        // the classic scheme's third stage buffer
+        if (hipMalloc(&h->aux2, state_bytes(h)) != hipSuccess) {
+            h->aux2 = nullptr;
+            return fail(h, CL_ENOMEM, "RK4 stage buffer (" + std::to_string(state_bytes(h)) + " bytes)");
+        }
         drop_graph(h);
     }
     const GraphKey key{static_cast<int>(integ), dt, n, h->cur};
+    // passes that move the state to the other buffer (the classic RK4 step
+    // ends where it started)
     const int stages = integ == CL_RK2 ? 2 : integ == CL_RK3 ? 3 : integ == CL_RK34 ? 4 : integ == CL_RK4 ? 5 : 0;
-    const int passes = is_rk(integ) ? n * stages : 1 + n * (integ == CL_VV4 ? 3 : 1);
+    const int passes = integ == CL_RK4_CLASSIC ? 0 : is_rk(integ) ? n * stages : 1 + n * (integ == CL_VV4 ? 3 : 1);
     if (h->use_graph && n > 1) {
         hipGraphExec_t& gx = h->gexec[h->cur];
         if (!(gx && h->gkey[h->cur] == key)) {

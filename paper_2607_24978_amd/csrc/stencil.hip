@@ -188,15 +188,19 @@ __device__ __forceinline__ void finish_pass(const Phys& P, Scal* sc, double kt, 
     }
 }
 
-// The scalar step after a low-storage Runge-Kutta stage.  The sums in `tot`
-// describe the stage's input state y_i at scale factor a = sc->a (momenta and
-// fields at the same time): record the observables of y_i (if rec_out), then
-// advance (a, a') by the same recurrence as the fields,
-//   d_a <- A d_a + h a',  d_b <- A d_b + h a''(a, E(y_i)),  a += B d_a, a' += B d_b,
+// The scalar step after a Runge-Kutta stage.  The sums in `tot` describe the
+// stage's input state y_i at scale factor a = sc->a (momenta and fields at
+// the same time): record the observables of y_i (if rec_out), then advance
+// (a, a') by the same recurrence as the fields -- low storage (mode 1):
+//   d_a <- A d_a + h a',  d_b <- A d_b + h a''(a, E(y_i)),  a += B d_a, a' += B d_b;
+// classic (mode 2), with k = h (a', a'') at the stage input, (a0, b0) the
+// start of the step and s the weighted stage sum (first: a0 = a, s = 0):
+//   (a, a') <- (a0, b0) + A s + B k,  s <- C s + D k --
 // and form the next stage's coefficients at the new a (all 64 lanes of one
 // wave call; the powers are spread over lanes; lane 0 writes).
-__device__ __forceinline__ void finish_rk(const Phys& P, Scal* sc, double rkA, double rkB, double h, double deta,
-                                          cl_observables* rec_out, const double* tot) {
+__device__ __forceinline__ void finish_rk(const Phys& P, Scal* sc, int mode, int first, double rkA, double rkB,
+                                          double rkC, double rkD, double h, double deta, cl_observables* rec_out,
+                                          const double* tot) {
     const int lane = threadIdx.x & 63;
     const int nf = P.nf;
     const double a = sc->a, b = sc->b;
@@ -227,10 +231,20 @@ __device__ __forceinline__ void finish_rk(const Phys& P, Scal* sc, double rkA, d
         const double H = b / a;
         r = fabs(H * H - rhs) / rhs;
     }
-    const double da = rkA * sc->da + h * b;
-    const double db = rkA * sc->db + h * acc;
-    const double an = P.expand ? a + rkB * da : a;
-    const double bn = P.expand ? b + rkB * db : b;
+    double da, db, an, bn;
+    const double a0 = (mode == 2 && !first) ? sc->a0 : a, b0 = (mode == 2 && !first) ? sc->b0 : b;
+    if (mode == 2) {
+        const double sa = first ? 0.0 : sc->da, sb = first ? 0.0 : sc->db;
+        an = P.expand ? a0 + rkA * sa + rkB * (h * b) : a;
+        bn = P.expand ? b0 + rkA * sb + rkB * (h * acc) : b;
+        da = rkC * sa + rkD * (h * b);
+        db = rkC * sb + rkD * (h * acc);
+    } else {
+        da = rkA * sc->da + h * b;
+        db = rkA * sc->db + h * acc;
+        an = P.expand ? a + rkB * da : a;
+        bn = P.expand ? b + rkB * db : b;
+    }
     // lanes 0..4: an^(alpha - 3), an^(1 + alpha), an^(3 + alpha), an^(2 alpha + 1), an^(2 alpha)
     double ex = P.alpha - 3.0;
     if (lane == 1) ex = 1.0 + P.alpha;
@@ -263,6 +277,8 @@ __device__ __forceinline__ void finish_rk(const Phys& P, Scal* sc, double rkA, d
     sc->b = bn;
     sc->da = da;
     sc->db = db;
+    sc->a0 = a0;
+    sc->b0 = b0;
     sc->eta += deta;
     sc->nonfinite |= bad;
     sc->cd = 0.0;
@@ -381,10 +397,11 @@ struct TileJob {
     double kt, kb;
     const Scal* sc;
     const Phys* ph;
-    // Runge-Kutta stage (march_tile<..., RK = true>)
+    // Runge-Kutta stage (march_tile<..., RK = 1 low storage, 2 classic>)
     void* aux;
-    double rkA, rkB, rkh;
-    int rk_first;
+    const void* step0;  // classic: the state at the start of the step
+    double rkA, rkB, rkC, rkD, rkh;
+    int rk_first, rk_last;
 };
 
 // Calls f(integral_constant<int, B>), ..., f(integral_constant<int, E - 1>).
@@ -396,12 +413,15 @@ __device__ __forceinline__ void static_for(F&& f) {
     }
 }
 
-// RK = false: fused drift + kick (the symplectic schemes).  RK = true: one
+// RK = 0: fused drift + kick (the symplectic schemes).  RK = 1: one
 // low-storage Runge-Kutta stage -- no drift (the plane staged in LDS is the
 // stage's input f), F = h (a^(alpha-3) pi, a^(1+alpha) L f - a^(3+alpha) dV),
 // d <- A d + F and y <- y + B d with the registers d of (f, pi) in `aux`
-// (loaded one plane ahead), sums over the stage's input state.
-template <typename T, int NF, int RY, int HI, int PD, bool RK, int HPD, typename Prelude>
+// (loaded one plane ahead), sums over the stage's input state.  RK = 2: one
+// classic Runge-Kutta stage -- the same F at the stage input Y, output
+// y0 + A s + B F and s <- C s + D F with the step's start y0 (in `step0`) and
+// the weighted stage sum s (in `aux`), both loaded one plane ahead.
+template <typename T, int NF, int RY, int HI, int PD, int RK, int HPD, typename Prelude>
 __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem_raw, double (&acc)[kSumsPerField * NF + 1],
                            Prelude&& prelude) {
     constexpr int V = VecOf<T>::V;
@@ -437,7 +457,16 @@ __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem
         auxp[j] = RK ? static_cast<T*>(J.aux) + (NF + j) * N : nullptr;
     }
     const bool rk_first = RK && J.rk_first;
+    const bool rk_last = RK == 2 && J.rk_last;
     const T rA = static_cast<T>(J.rkA), rB = static_cast<T>(J.rkB);
+    const T rC = static_cast<T>(J.rkC), rD = static_cast<T>(J.rkD);
+    const T* y0f[NF];
+    const T* y0p[NF];
+#pragma unroll
+    for (int j = 0; j < NF; ++j) {
+        y0f[j] = RK == 2 ? static_cast<const T*>(J.step0) + j * N : nullptr;
+        y0p[j] = RK == 2 ? static_cast<const T*>(J.step0) + (NF + j) * N : nullptr;
+    }
 
     // Pass coefficients; set once the prelude has produced the scalars.
     T cd = T(0), kL = T(0), kV = T(0), cF = T(0);
@@ -622,8 +651,10 @@ __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem
         for (int j = 0; j < NF; ++j) shift[j] = static_cast<T>(sc->shift[j]);
     }
     // Runge-Kutta registers of (f, pi) for the current plane and the next one.
+    // (classic stages: also the step's start y0 of (f, pi))
     T axc[RK ? 2 : 1][NF][RY][V], axn[RK ? 2 : 1][NF][RY][V];
-    auto aux_load = [&](int k, T (&dst)[RK ? 2 : 1][NF][RY][V]) {
+    T y0c[RK == 2 ? 2 : 1][NF][RY][V], y0n[RK == 2 ? 2 : 1][NF][RY][V];
+    auto aux_load = [&](int k, T (&dst)[RK ? 2 : 1][NF][RY][V], T (&ydst)[RK == 2 ? 2 : 1][NF][RY][V]) {
         if constexpr (RK) {
             const size_t base = static_cast<size_t>(x0 + k) * static_cast<size_t>(N) * rs;
 #pragma unroll
@@ -632,10 +663,14 @@ __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem
                 for (int r = 0; r < RY; ++r) {
                     vload(auxf[j] + base + yrow[r], dst[0][j][r]);
                     vload(auxp[j] + base + yrow[r], dst[RK ? 1 : 0][j][r]);
+                    if constexpr (RK == 2) {
+                        vload(y0f[j] + base + yrow[r], ydst[0][j][r]);
+                        vload(y0p[j] + base + yrow[r], ydst[1][j][r]);
+                    }
                 }
         }
     };
-    if (RK && !rk_first) aux_load(0, axc);
+    if (RK && !rk_first) aux_load(0, axc, y0c);
     consume(S0{}, S0{}, prev, pn, -1);
     if constexpr (PD >= 2) {
         consume(S1{}, hs(K0{}), cur, pc, 0);
@@ -668,7 +703,7 @@ __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem
         } else {
             issue(Sc, Hc, i + 1 + PD <= CX ? i + 1 + PD : kNone, i + 1 + HPD);
         }
-        if (RK && !rk_first && i + 1 < CX) aux_load(i + 1, axn);
+        if (RK && !rk_first && i + 1 < CX) aux_load(i + 1, axn, y0n);
 
         const T* L0 = lds + static_cast<size_t>(buf) * NF * PL;
         const size_t base = static_cast<size_t>(x) * plane;
@@ -718,7 +753,7 @@ __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem
                     const T gx = xp - f, gy = yp[j][v] - f, gz = zp - f;
                     const T d = f - shift[j];
                     T* q5 = part + kSumsPerField * j;
-                    if constexpr (RK) {
+                    if constexpr (RK == 1) {
                         const T Ff = cF * po;
                         const T dfn = rk_first ? Ff : fmad(rA, axc[0][j][k][v], Ff);
                         const T dpn = rk_first ? F : fmad(rA, axc[RK ? 1 : 0][j][k][v], F);
@@ -726,6 +761,18 @@ __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem
                         dpo[j][v] = dpn;
                         fnew[j][v] = fmad(rB, dfn, f);
                         pnew[j][v] = fmad(rB, dpn, po);
+                        q5[0] = fmad(po, po, q5[0]);
+                        q5[4] += po;
+                    } else if constexpr (RK == 2) {
+                        const T Ff = cF * po;
+                        const T sf = rk_first ? T(0) : axc[0][j][k][v];
+                        const T sp = rk_first ? T(0) : axc[1][j][k][v];
+                        const T yf = rk_first ? f : y0c[0][j][k][v];
+                        const T yp = rk_first ? po : y0c[RK == 2 ? 1 : 0][j][k][v];
+                        fnew[j][v] = fmad(rB, Ff, fmad(rA, sf, yf));
+                        pnew[j][v] = fmad(rB, F, fmad(rA, sp, yp));
+                        dfo[j][v] = fmad(rD, Ff, rC * sf);
+                        dpo[j][v] = fmad(rD, F, rC * sp);
                         q5[0] = fmad(po, po, q5[0]);
                         q5[4] += po;
                     } else {
@@ -747,13 +794,17 @@ __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem
                         if (nt_store) {
                             vstore_nt(fout[j] + base + yrow[k], fnew[j]);
                             vstore_nt(pout[j] + base + yrow[k], pnew[j]);
-                            vstore_nt(auxf[j] + base + yrow[k], dfo[j]);
-                            vstore_nt(auxp[j] + base + yrow[k], dpo[j]);
+                            if (!rk_last) {
+                                vstore_nt(auxf[j] + base + yrow[k], dfo[j]);
+                                vstore_nt(auxp[j] + base + yrow[k], dpo[j]);
+                            }
                         } else {
                             vstore(fout[j] + base + yrow[k], fnew[j]);
                             vstore(pout[j] + base + yrow[k], pnew[j]);
-                            vstore(auxf[j] + base + yrow[k], dfo[j]);
-                            vstore(auxp[j] + base + yrow[k], dpo[j]);
+                            if (!rk_last) {
+                                vstore(auxf[j] + base + yrow[k], dfo[j]);
+                                vstore(auxp[j] + base + yrow[k], dpo[j]);
+                            }
                         }
                     } else if (nt_store) {
                         vstore_nt(fout[j] + base + yrow[k], cur[j][k]);
@@ -781,6 +832,10 @@ __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem
                         axc[0][j][k][v] = axn[0][j][k][v];
                         axc[RK ? 1 : 0][j][k][v] = axn[RK ? 1 : 0][j][k][v];
                     }
+                    if constexpr (RK == 2) {
+                        y0c[0][j][k][v] = y0n[0][j][k][v];
+                        y0c[RK == 2 ? 1 : 0][j][k][v] = y0n[RK == 2 ? 1 : 0][j][k][v];
+                    }
                 }
     };
     for (int i = 0; i < CX; i += PD) {
@@ -797,7 +852,7 @@ __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem
 
 // NTB: the launch bound (256, or 512 for the tall one-row-per-thread tiles,
 // whose register footprint fits two waves per SIMD).
-template <typename T, int NF, int RY, int HI, int PD, bool RK, int NTB>
+template <typename T, int NF, int RY, int HI, int PD, int RK, int NTB>
 __global__ __launch_bounds__(NTB) void lattice_pass(PassArgs A) {
     constexpr int NS = kSumsPerField * NF + 1;
     const int nblocks = A.nbz * A.nby * A.nbx;
@@ -827,10 +882,14 @@ __global__ __launch_bounds__(NTB) void lattice_pass(PassArgs A) {
     J.kb = A.kb;
     J.ph = &A.ph;
     J.aux = A.aux;
+    J.step0 = A.y0;
     J.rkA = A.rkA;
     J.rkB = A.rkB;
+    J.rkC = A.rkC;
+    J.rkD = A.rkD;
     J.rkh = A.rkh;
     J.rk_first = A.rk_first;
+    J.rk_last = A.rk_last;
     __shared__ Scal s_sc;
     __shared__ double tot[kMaxSums];
     J.sc = &s_sc;
@@ -848,7 +907,8 @@ __global__ __launch_bounds__(NTB) void lattice_pass(PassArgs A) {
     const int prev_nslots = A.prev_nslots, has_prev = A.has_prev;
     const double pkt = A.pkt, pkb = A.pkb, phn = A.phn;
     const int prev_rk = A.prev_rk;
-    const double prkA = A.prkA, prkB = A.prkB, prkh = A.prkh, prkdeta = A.prkdeta;
+    const double prkA = A.prkA, prkB = A.prkB, prkC = A.prkC, prkD = A.prkD, prkh = A.prkh, prkdeta = A.prkdeta;
+    const int prev_rk_first = A.prev_rk_first;
     cl_observables* prev_rec = (bid == 0 && A.prev_rec >= 0) ? A.obs + A.prev_rec : nullptr;
     Scal* ssc = &s_sc;
     double* stot = tot;
@@ -869,7 +929,7 @@ __global__ __launch_bounds__(NTB) void lattice_pass(PassArgs A) {
             if (t + NT < NW) dst[t + NT] = w1;
             __syncthreads();
             if (threadIdx.x < 64) {
-                if (prev_rk) finish_rk(*php, ssc, prkA, prkB, prkh, prkdeta, prev_rec, stot);
+                if (prev_rk) finish_rk(*php, ssc, prev_rk, prev_rk_first, prkA, prkB, prkC, prkD, prkh, prkdeta, prev_rec, stot);
                 else finish_pass(*php, ssc, pkt, pkb, phn, prev_rec, stot);
             }
             __syncthreads();
@@ -897,7 +957,9 @@ __global__ __launch_bounds__(kMaxPassThreads) void finish_kernel(PassArgs A) {
     slots_sum<NS>(A.prev_partials, blockDim.x, A.prev_nslots, tot);
     cl_observables* rec = A.prev_rec >= 0 ? A.obs + A.prev_rec : nullptr;
     if (threadIdx.x < 64) {
-        if (A.prev_rk) finish_rk(A.ph, &s_sc, A.prkA, A.prkB, A.prkh, A.prkdeta, rec, tot);
+        if (A.prev_rk)
+            finish_rk(A.ph, &s_sc, A.prev_rk, A.prev_rk_first, A.prkA, A.prkB, A.prkC, A.prkD, A.prkh, A.prkdeta, rec,
+                      tot);
         else finish_pass(A.ph, &s_sc, A.pkt, A.pkb, A.phn, rec, tot);
     }
     __syncthreads();
@@ -1065,13 +1127,14 @@ __global__ __launch_bounds__(256) void ensemble_pass(EnsArgs E) {
         J.sc = M.sc;
         J.ph = &M.ph;
         J.aux = nullptr;
-        J.rkA = J.rkB = J.rkh = 0.0;
-        J.rk_first = 0;
+        J.step0 = nullptr;
+        J.rkA = J.rkB = J.rkC = J.rkD = J.rkh = 0.0;
+        J.rk_first = J.rk_last = 0;
         double acc[NS];
 #pragma unroll
         for (int k = 0; k < NS; ++k) acc[k] = 0.0;
-        if (M.RY == 2) march_tile<T, NF, 2, 1, 4, false, 4>(J, smem_raw, acc, [] {});
-        else march_tile<T, NF, 1, 1, 4, false, 4>(J, smem_raw, acc, [] {});
+        if (M.RY == 2) march_tile<T, NF, 2, 1, 4, 0, 4>(J, smem_raw, acc, [] {});
+        else march_tile<T, NF, 1, 1, 4, 0, 4>(J, smem_raw, acc, [] {});
         if (reduce_partials<NS>(acc, 256, M.partials, I.tile, M.nitems, M.ticket, tot) && threadIdx.x < 64)
             finish_pass(M.ph, M.sc, kt, kb, hn, E.rec >= 0 ? E.obs + (size_t)E.rec * E.nmembers + I.member : nullptr,
                         tot);
@@ -1154,7 +1217,7 @@ void candidate_tiles(int N, cl_precision prec, int nf, Tile* out, int* count, in
     *count = n;
 }
 
-template <typename T, int NF, int RY, int HI, int PD, bool RK, int NTB>
+template <typename T, int NF, int RY, int HI, int PD, int RK, int NTB>
 static hipError_t launch_t(const PassArgs& a, const Tile& t, hipStream_t s, size_t lds) {
     hipLaunchKernelGGL((lattice_pass<T, NF, RY, HI, PD, RK, NTB>), dim3(t.nblocks()), dim3(t.NT), lds, s, a);
     return hipGetLastError();
@@ -1164,17 +1227,19 @@ template <typename T, int NF, int RY, int HI, int NTB = 256>
 static hipError_t launch_pd(const PassArgs& a, const Tile& t, hipStream_t s, size_t lds) {
     // Runge-Kutta stages: prefetch depth 1 or 2 (a depth-4 tile runs them at
     // 2; the wide workgroups at 1, where the stage fits two waves per SIMD)
+    // classic stages (two more register sets per plane) always at depth 1
+    if (a.rk == 2) return launch_t<T, NF, RY, HI, 1, 2, NTB>(a, t, s, lds);
     if (a.rk) {
-        if constexpr (NTB > 256) return launch_t<T, NF, RY, HI, 1, true, NTB>(a, t, s, lds);
+        if constexpr (NTB > 256) return launch_t<T, NF, RY, HI, 1, 1, NTB>(a, t, s, lds);
         else
-            return t.PD == 1 ? launch_t<T, NF, RY, HI, 1, true, NTB>(a, t, s, lds)
-                             : launch_t<T, NF, RY, HI, 2, true, NTB>(a, t, s, lds);
+            return t.PD == 1 ? launch_t<T, NF, RY, HI, 1, 1, NTB>(a, t, s, lds)
+                             : launch_t<T, NF, RY, HI, 2, 1, NTB>(a, t, s, lds);
     }
     if constexpr (RY == 1) {
-        if (t.PD == 4) return launch_t<T, NF, RY, HI, 4, false, NTB>(a, t, s, lds);
+        if (t.PD == 4) return launch_t<T, NF, RY, HI, 4, 0, NTB>(a, t, s, lds);
     }
-    return t.PD == 2 ? launch_t<T, NF, RY, HI, 2, false, NTB>(a, t, s, lds)
-                     : launch_t<T, NF, RY, HI, 1, false, NTB>(a, t, s, lds);
+    return t.PD == 2 ? launch_t<T, NF, RY, HI, 2, 0, NTB>(a, t, s, lds)
+                     : launch_t<T, NF, RY, HI, 1, 0, NTB>(a, t, s, lds);
 }
 
 template <typename T, int NF>

@@ -11,7 +11,7 @@ from test_gpu_parity import compare_records, make_lattice, oracle_seed, params, 
 
 pytestmark = pytest.mark.gpu
 
-SCHEMES = ["rk2", "rk3", "rk34", "rk4"]
+SCHEMES = ["rk2", "rk3", "rk34", "rk4", "rk4_classic"]
 
 
 @pytest.mark.parametrize("scheme", SCHEMES)

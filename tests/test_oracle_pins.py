@@ -147,7 +147,8 @@ def rk4_homogeneous(f0, p0, a0, b0, T, h, alpha, mp, lam):
     return y
 
 
-@pytest.mark.parametrize("integrator,order", [("leapfrog", 2), ("vv4", 4), ("rk2", 2), ("rk3", 3), ("rk34", 3), ("rk4", 4)])
+@pytest.mark.parametrize("integrator,order", [("leapfrog", 2), ("vv4", 4), ("rk2", 2), ("rk3", 3), ("rk34", 3), ("rk4", 4),
+                                               ("rk4_classic", 4)])
 @pytest.mark.parametrize("alpha", [1.0, 0.0])
 def test_homogeneous_mode_against_rk4(integrator, order, alpha):
     """P3: a uniform lattice reduces to the ODE of (f, p, a, b); the oracle
@@ -183,7 +184,8 @@ def assert_order(integrator, order, ratio, tol, info):
 
 
 # ---------------------------------------------------------------- P11
-@pytest.mark.parametrize("integrator,order", [("leapfrog", 2), ("vv4", 4), ("rk2", 2), ("rk3", 3), ("rk34", 3), ("rk4", 4)])
+@pytest.mark.parametrize("integrator,order", [("leapfrog", 2), ("vv4", 4), ("rk2", 2), ("rk3", 3), ("rk34", 3), ("rk4", 4),
+                                               ("rk4_classic", 4)])
 def test_closed_form_expansion(integrator, order):
     """P11: (i) vacuum energy V0 with alpha = 1 gives a = 1/(1 - H0 eta),
     H0^2 = V0/(3 mp^2); alpha = 0 gives a = exp(H0 t); (ii) kination
