@@ -24,7 +24,11 @@ W0 = 1.0 - 2.0 * W1
 class Params:
     """Lattice, background and potential parameters (Sect. 2, Eq. FLRWmetric,
     Eq. FieldSpaceTimeNaturalVariables).  expansion is "self" (Friedmann
-    equations) or "static" (a == 1, b == 0)."""
+    equations) or "static" (a == 1, b == 0).  dim: spatial dimension of the
+    lattice (Sect. 3, scalar dynamics in 1+1 and 2+1 dimensions: the same
+    equations with the Laplacian and the gradient energy summed over dim
+    directions and volume averages over N^dim sites); fields then have shape
+    [n_fields] + [N] * dim."""
     N: int
     dx: float
     n_fields: int = 1
@@ -35,6 +39,7 @@ class Params:
     lam: tuple = (1.0, 0.0)
     g2: float = 0.0
     V0: float = 0.0
+    dim: int = 3
 
 
 @dataclass
@@ -91,18 +96,20 @@ def shift(g, axis: int, step: int):
 
 
 def laplacian(g, dx: float):
-    """7-point periodic Laplacian of one field:
+    """(2d+1)-point periodic Laplacian of one field on a d-dimensional
+    lattice (d = g.ndim; 7 points in three dimensions):
     L[g](n) = sum_i [g(n + e_i) + g(n - e_i) - 2 g(n)] / dx^2."""
     out = np.zeros_like(g)
-    for ax in range(3):
+    for ax in range(g.ndim):
         out = out + shift(g, ax, +1) + shift(g, ax, -1) - 2.0 * g
     return out / dx ** 2
 
 
 def grad_sq_sum(g):
-    """sum_i (g(n + e_i) - g(n))^2 at every site (forward differences)."""
+    """sum_i (g(n + e_i) - g(n))^2 at every site (forward differences, over
+    the g.ndim directions of the lattice)."""
     out = np.zeros_like(g)
-    for ax in range(3):
+    for ax in range(g.ndim):
         out = out + (shift(g, ax, +1) - g) ** 2
     return out
 
@@ -120,13 +127,14 @@ def force(f, a: float, P: Params):
 
 # ---------------------------------------------------------------- energies
 def energies(f, p, a: float, P: Params):
-    """Volume averages (Sect. 4.3, <g>_V = N^-3 sum_n g(n)) of the scalar
+    """Volume averages (Sect. 4.3, <g>_V = N^-3 sum_n g(n); N^-dim on a
+    reduced lattice) of the scalar
     energy contributions of Eq. energy-contrib:
       K_j = f_j'^2 / (2 a^(2 alpha)) = pi_j^2 / (2 a^6),
       G_j = sum_i (d_i f_j)^2 / (2 a^2), with forward differences,
       V   = potential.
     Returns (EK[n], EG[n], EV)."""
-    N3 = float(P.N) ** 3
+    N3 = float(P.N) ** P.dim
     EK = [float(np.sum(p[j] ** 2)) / (2.0 * a ** 6 * N3) for j in range(P.n_fields)]
     EG = [float(np.sum(grad_sq_sum(f[j]))) / (2.0 * a ** 2 * P.dx ** 2 * N3)
           for j in range(P.n_fields)]
