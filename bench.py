@@ -444,6 +444,37 @@ def rk_run(w, steps, r64, tile, scheme="rk4"):
             "vs_fp64_vv4_rel_dev": linear_regime_deviation(r, r64[:len(r)], w.n_fields)}
 
 
+def lowdim_run(w, steps, warmup, chunk=500):
+    """The reduced (2+1)-dimensional form: the 4096^2 two-field FP32 VV4
+    lattice (seeded noise state), steps in calls of `chunk`: rate and the
+    fraction of the HBM peak at 32 B per site and pass (three passes per
+    step plus one opening kick per call)."""
+    import torch
+    from paper_2607_24978_amd import _lib
+    lat = _lib.Lattice(w.N, w.dx, w.n_fields, "fp32", dim=2)
+    lat.set_potential(w.m2, w.lam, w.g2, w.V0)
+    f, p = W.random_state(w.N, w.n_fields, w.seed, fbar=w.fbar[:w.n_fields], famp=1e-3, pamp=1e-3, dim=2)
+    lat.set_fields(f, p)
+    del f, p
+    chunk = min(chunk, steps)
+    lat.step(w.integrator, w.dt, chunk)
+    for _ in range(max(0, warmup - chunk) // chunk):
+        lat.step(w.integrator, w.dt, chunk)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    calls = steps // chunk
+    for _ in range(calls):
+        r = lat.step(w.integrator, w.dt, chunk)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    lat.close()
+    sites = w.N ** 2
+    n = calls * chunk
+    alg = (3 * n * 32 + calls * 24) * sites
+    return {"workload": w.name, "steps": n, "site_updates_per_s": sites * n / sec, "ms_per_step": 1e3 * sec / n,
+            "hbm_frac": alg / sec / 1e9 / HBM_PEAK_GBS, "finite": not bool(np.any(r["nonfinite"]))}
+
+
 def spectrum_run(w, reps=5):
     """Cost of one power spectrum of f_0 on the workload's lattice: device
     FFT in FP64 (extraction, three line-FFT passes, binning) plus the copy of
@@ -565,6 +596,9 @@ def main():
     if args.workload == "c1":
         progress("power spectrum form")
         forms["spectrum"] = spectrum_run(w)
+    if args.workload == "c1":
+        progress("reduced 2+1 form")
+        forms["lowdim_2d"] = lowdim_run(W.C4, 2000, 200)
     if not args.no_batched and args.workload == "c1":
         progress("batched ensemble form")
         forms["batched"] = batched_run(1000, 500)

@@ -132,6 +132,19 @@ const char* cl_version(void);
  * lambda = 1 for field 0, fields zero.  On failure *out is NULL. */
 cl_status cl_create(int N, double dx, int n_fields, cl_precision prec, cl_lattice** out);
 
+/* Reduced lattice (Sect. 3, scalar dynamics in 1+1 and 2+1 dimensions):
+ * dim = 1 or 2 spatial directions of N sites (N a multiple of 4, at least
+ * 8), the same field and Friedmann equations with the Laplacian and the
+ * gradient energy summed over dim directions and volume averages over N^dim
+ * sites; dim = 3 is cl_create.  Host arrays of cl_set_fields / cl_get_fields
+ * hold n_fields * N^dim values per kind (the last index fastest); on the
+ * device, array a of row x (dim = 2) starts at (x * 2 * n_fields + a) * N.
+ * Reduced lattices step with CL_LEAPFROG and CL_VV4 and support
+ * cl_read_observables, cl_get_state / cl_set_state and the buffer calls;
+ * cl_seed, the Runge-Kutta schemes, tiles, the autotuner, the power
+ * spectrum, ensembles and the surrogate return CL_EUNSUPPORTED. */
+cl_status cl_create_dim(int dim, int N, double dx, int n_fields, cl_precision prec, cl_lattice** out);
+
 /* Free everything the library allocated for h.  cl_destroy(NULL) is a no-op. */
 cl_status cl_destroy(cl_lattice* h);
 

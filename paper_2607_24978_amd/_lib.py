@@ -82,6 +82,7 @@ _SIGS = {
     "cl_version": (C.c_char_p, []),
     "cl_power_spectrum": (C.c_int, [_P, C.c_int, C.c_int, C.c_double, C.c_int, _P, _P, _P]),
     "cl_create": (C.c_int, [C.c_int, C.c_double, C.c_int, C.c_int, C.POINTER(_P)]),
+    "cl_create_dim": (C.c_int, [C.c_int, C.c_int, C.c_double, C.c_int, C.c_int, C.POINTER(_P)]),
     "cl_destroy": (C.c_int, [_P]),
     "cl_set_stream": (C.c_int, [_P, _P]),
     "cl_attach_device_buffers": (C.c_int, [_P, _P, _P]),
@@ -156,13 +157,18 @@ EXPANSIONS = {"static": CL_STATIC, "self": CL_SELF_CONSISTENT}
 
 
 class Lattice:
-    """One lattice handle (cl_create ... cl_destroy)."""
+    """One lattice handle (cl_create / cl_create_dim ... cl_destroy); dim = 1
+    or 2 gives a reduced lattice of N^dim sites."""
 
-    def __init__(self, N: int, dx: float, n_fields: int = 1, precision: str = "fp64"):
+    def __init__(self, N: int, dx: float, n_fields: int = 1, precision: str = "fp64", dim: int = 3):
         h = _P()
-        _check(lib.cl_create(int(N), float(dx), int(n_fields), PRECISIONS[precision], C.byref(h)))
+        if dim == 3:
+            _check(lib.cl_create(int(N), float(dx), int(n_fields), PRECISIONS[precision], C.byref(h)))
+        else:
+            _check(lib.cl_create_dim(int(dim), int(N), float(dx), int(n_fields), PRECISIONS[precision], C.byref(h)))
         self.h = h
         self.N, self.dx, self.n_fields, self.precision = int(N), float(dx), int(n_fields), precision
+        self.dim = int(dim)
 
     def close(self):
         if self.h:
@@ -208,13 +214,13 @@ class Lattice:
         _check(lib.cl_seed(self.h, C.c_uint64(seed), _dptr(fb), _dptr(pb), float(cutoff), float(amp)), self.h)
 
     def set_fields(self, f: np.ndarray, p: np.ndarray):
-        shape = (self.n_fields, self.N, self.N, self.N)
+        shape = (self.n_fields,) + (self.N,) * self.dim
         f = np.ascontiguousarray(f, dtype=np.float64).reshape(shape)
         p = np.ascontiguousarray(p, dtype=np.float64).reshape(shape)
         _check(lib.cl_set_fields(self.h, _dptr(f), _dptr(p)), self.h)
 
     def get_fields(self):
-        shape = (self.n_fields, self.N, self.N, self.N)
+        shape = (self.n_fields,) + (self.N,) * self.dim
         f = np.empty(shape)
         p = np.empty(shape)
         _check(lib.cl_get_fields(self.h, _dptr(f), _dptr(p)), self.h)

@@ -96,7 +96,7 @@ struct PassArgs {
     int prev_nslots;    // workgroups of the previous pass
     int has_prev;       // 1: finish the previous pass first
     int prev_rec;       // observable slot of the previous pass, -1: none
-    int pad_;
+    int dim;            // spatial dimension of the lattice (1, 2 or 3)
     double pkt, pkb, phn;  // kt, kb, h_next of the previous pass
     // Runge-Kutta stage, for the fields (registers in `aux`, state layout) and,
     // in the scalar step, for (a, a').  rk = 1, low storage: d <- rkA d +
@@ -209,6 +209,7 @@ struct cl_lattice {
     void* buf[2] = {nullptr, nullptr};  // ping-pong state buffers (row-interleaved layout)
     void* aux = nullptr;                // Runge-Kutta registers of f and pi (same layout), on first use
     void* aux2 = nullptr;               // classic RK4: the third stage buffer, on first use
+    int dim = 3;                        // spatial dimension (reduced lattices: 1 or 2)
     double2* spec = nullptr;            // power spectrum: N^3 complex FP64, on first use
     double2* spec_tw = nullptr;         // its twiddle factors (N / 2)
     double* spec_sums = nullptr;        // per-bin sums and counts (spec_cap bins)

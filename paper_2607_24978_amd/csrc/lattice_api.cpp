@@ -31,7 +31,13 @@ namespace {
 thread_local std::string g_err;
 
 size_t elem_size(cl_precision p) { return p == CL_FP32 ? 4 : 8; }
-size_t sites(const cl_lattice* h) { return static_cast<size_t>(h->N) * h->N * h->N; }
+size_t sites(const cl_lattice* h) {
+    size_t n = 1;
+    for (int d = 0; d < h->dim; ++d) n *= static_cast<size_t>(h->N);
+    return n;
+}
+// rows of N values along z (N^2 in three dimensions, N or 1 on reduced lattices)
+size_t rows(const cl_lattice* h) { return sites(h) / static_cast<size_t>(h->N); }
 // One state buffer: 2 n_f arrays of N^3 values.
 size_t state_bytes(const cl_lattice* h) { return 2 * static_cast<size_t>(h->nf) * sites(h) * elem_size(h->prec); }
 
@@ -131,6 +137,7 @@ PassArgs base_args(cl_lattice* h, int in) {
     a.prkA = a.prkB = a.prkC = a.prkD = a.prkh = a.prkdeta = 0.0;
     a.aux = h->aux;
     a.y0 = nullptr;
+    a.dim = h->dim;
     a.obs = h->obs;
     a.ph = make_phys(h);
     a.rec = -1;
@@ -440,7 +447,7 @@ cl_status upload(cl_lattice* h, const double* f, const double* p) {
             const int arr = which * h->nf + j;
             char* dst = static_cast<char*>(h->buf[h->cur]) + arr * N * sizeof(T);
             HIPCHECK(h, hipMemcpy2DAsync(dst, 2 * h->nf * N * sizeof(T), tmp.data(), N * sizeof(T), N * sizeof(T),
-                                         N * N, hipMemcpyHostToDevice, h->stream));
+                                         rows(h), hipMemcpyHostToDevice, h->stream));
             HIPCHECK(h, hipStreamSynchronize(h->stream));
         }
     }
@@ -464,7 +471,7 @@ cl_status download(cl_lattice* h, double* f, double* p) {
             const int arr = which * h->nf + j;
             const char* src = static_cast<const char*>(h->buf[h->cur]) + arr * N * sizeof(T);
             HIPCHECK(h, hipMemcpy2DAsync(tmp.data(), N * sizeof(T), src, 2 * h->nf * N * sizeof(T), N * sizeof(T),
-                                         N * N, hipMemcpyDeviceToHost, h->stream));
+                                         rows(h), hipMemcpyDeviceToHost, h->stream));
             HIPCHECK(h, hipStreamSynchronize(h->stream));
             double* d = dst + j * n;
             for (size_t i = 0; i < n; ++i) d[i] = static_cast<double>(tmp[i]);
@@ -532,17 +539,25 @@ const char* cl_version(void) { return "cl_lattice 0.1 (gfx950)"; }
 const char* cl_last_error(const cl_lattice* h) { return h ? h->err.c_str() : g_err.c_str(); }
 
 cl_status cl_create(int N, double dx, int n_fields, cl_precision prec, cl_lattice** out) {
+    return cl_create_dim(3, N, dx, n_fields, prec, out);
+}
+
+cl_status cl_create_dim(int dim, int N, double dx, int n_fields, cl_precision prec, cl_lattice** out) {
     if (!out) return fail(nullptr, CL_EINVAL, "out is NULL");
     *out = nullptr;
     if (prec != CL_FP32 && prec != CL_FP64) return fail(nullptr, CL_EINVAL, "precision must be CL_FP32 or CL_FP64");
-    if (!valid_N(N, prec))
+    if (dim < 1 || dim > 3) return fail(nullptr, CL_EINVAL, "dim must be 1, 2 or 3");
+    if (dim == 3 && !valid_N(N, prec))
         return fail(nullptr, CL_EINVAL,
                     "N must be a power of two in [8, 1024] or a multiple of 256 (FP32) / 128 (FP64) up to 1600");
+    if (dim < 3 && (N < 8 || N % 4 || (dim == 2 && N > 32768) || (dim == 1 && N > (1 << 28))))
+        return fail(nullptr, CL_EINVAL, "reduced lattice: N must be a multiple of 4, at least 8 (and N^dim < 2^30)");
     if (!(dx > 0.0) || !std::isfinite(dx)) return fail(nullptr, CL_EINVAL, "dx must be positive and finite");
     if (n_fields != 1 && n_fields != 2) return fail(nullptr, CL_EINVAL, "n_fields must be 1 or 2");
     cl_lattice* h = new (std::nothrow) cl_lattice;
     if (!h) return fail(nullptr, CL_ENOMEM, "handle");
     h->N = N;
+    h->dim = dim;
     h->dx = dx;
     h->nf = n_fields;
     h->prec = prec;
@@ -570,8 +585,20 @@ cl_status cl_create(int N, double dx, int n_fields, cl_precision prec, cl_lattic
     if (nt && nt[0]) h->pass_flags = std::atoi(nt);
     if (hipMalloc(&h->sc, sizeof(Scal)) != hipSuccess) return bail(CL_ENOMEM, "scalar block");
     if (hipMalloc(&h->scb, 2 * sizeof(Scal)) != hipSuccess) return bail(CL_ENOMEM, "scalar blocks");
-    h->tile = cl::default_tile(N, prec, n_fields);
-    cached_tile(N, n_fields, prec, h->tile);
+    if (dim == 3) {
+        h->tile = cl::default_tile(N, prec, n_fields);
+        cached_tile(N, n_fields, prec, h->tile);
+    } else {
+        // grid-stride pass: 256 threads per workgroup, each on V sites
+        const size_t groups = sites(h) / (prec == CL_FP32 ? 4 : 2);
+        Tile t;
+        t.TZ = N;
+        t.TY = t.CX = t.RY = t.PD = t.HI = 1;
+        t.NT = 256;
+        t.nbz = static_cast<int>(std::min<size_t>((groups + 255) / 256, cl::kTunedPassBlocks));
+        t.nby = t.nbx = 1;
+        h->tile = t;
+    }
     if (ensure_partials(h) != CL_OK) return bail(CL_ENOMEM, h->err);
     double zero[2] = {0.0, 0.0};
     if (init_scalars(h, 1.0, 0.0, 0.0, zero) != CL_OK) return bail(CL_EDEVICE, h->err);
@@ -676,6 +703,8 @@ cl_status cl_get_fields(cl_lattice* h, double* f, double* p) {
 cl_status cl_seed(cl_lattice* h, uint64_t seed, const double* fbar, const double* pbar, double cutoff,
                   double amp) {
     if (!h) return fail(nullptr, CL_EINVAL, "handle is NULL");
+    if (h->dim != 3)
+        return fail(h, CL_EUNSUPPORTED, "the seed is three-dimensional; set reduced lattices with cl_set_fields");
     if (!fbar || !pbar) return fail(h, CL_EINVAL, "fbar / pbar must not be NULL");
     if (h->N & (h->N - 1)) return fail(h, CL_EUNSUPPORTED, "cl_seed needs N to be a power of two");
     if (!std::isfinite(amp) || amp < 0.0) return fail(h, CL_EINVAL, "amp must be finite and >= 0");
@@ -728,6 +757,8 @@ cl_status cl_set_state(cl_lattice* h, const cl_scalars* in) {
 cl_status cl_step(cl_lattice* h, cl_integrator integ, double dt, int n, cl_observables* per_step) {
     if (!h) return fail(nullptr, CL_EINVAL, "handle is NULL");
     if (integ != CL_LEAPFROG && integ != CL_VV4 && !is_rk(integ)) return fail(h, CL_EINVAL, "unknown integrator");
+    if (h->dim != 3 && is_rk(integ))
+        return fail(h, CL_EUNSUPPORTED, "reduced lattices run the symplectic schemes only");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(h, CL_EINVAL, "dt must be positive and finite");
     if (n < 0) return fail(h, CL_EINVAL, "n must be >= 0");
     if (n == 0) return CL_OK;
@@ -808,6 +839,7 @@ cl_status cl_read_observables(cl_lattice* h, cl_observables* out) {
 cl_status cl_power_spectrum(cl_lattice* h, int field, int what, double width, int nbins, int64_t* counts,
                             double* sums, double* delta) {
     if (!h) return fail(nullptr, CL_EINVAL, "handle is NULL");
+    if (h->dim != 3) return fail(h, CL_EUNSUPPORTED, "the power spectrum is three-dimensional");
     if (field < 0 || field >= h->nf) return fail(h, CL_EINVAL, "field index out of range");
     if (what != 0 && what != 1) return fail(h, CL_EINVAL, "what must be 0 (f) or 1 (pi)");
     if (!(width > 0.0) || !std::isfinite(width)) return fail(h, CL_EINVAL, "bin width must be positive");
@@ -875,6 +907,7 @@ cl_status cl_get_tile(const cl_lattice* h, cl_tile* out) {
 
 cl_status cl_set_tile(cl_lattice* h, const cl_tile* t) {
     if (!h) return fail(nullptr, CL_EINVAL, "handle is NULL");
+    if (h->dim != 3) return fail(h, CL_EUNSUPPORTED, "reduced lattices have no tile choice");
     if (!t) return fail(h, CL_EINVAL, "tile is NULL");
     Tile c;
     c.TZ = t->tz;
@@ -898,6 +931,7 @@ cl_status cl_set_tile(cl_lattice* h, const cl_tile* t) {
 
 cl_status cl_autotune(cl_lattice* h, int reps, char* report, size_t cap) {
     if (!h) return fail(nullptr, CL_EINVAL, "handle is NULL");
+    if (h->dim != 3) return fail(h, CL_EUNSUPPORTED, "reduced lattices have no tile choice");
     if (reps < 1) reps = 3;
     std::vector<Tile> cands(1024);
     int nc = 0;
@@ -1222,6 +1256,7 @@ cl_status cl_ensemble_create(int n, cl_lattice* const* members, cl_ensemble** ou
             if (members[k] == h) return bail(CL_EINVAL, "a lattice appears twice in the ensemble");
         if (h->prec != e->prec || h->nf != e->nf)
             return bail(CL_EINVAL, "all members need the same precision and number of fields");
+        if (h->dim != 3) return bail(CL_EUNSUPPORTED, "ensemble members are three-dimensional lattices");
         e->m.push_back(h);
     }
     e->dt.assign(n, 0.0);

@@ -1256,7 +1256,167 @@ hipError_t launch_finish(const PassArgs& a, const Tile& t, int nf, hipStream_t s
     return hipGetLastError();
 }
 
+// Pass over a reduced (1+1)- or (2+1)-dimensional lattice (Sect. 3, scalar
+// dynamics in 1+1 and 2+1 dimensions): the same drift, kick and lattice sums
+// as lattice_pass with the Laplacian and the gradient terms summed over D
+// directions.  Layout: D = 2 has N rows (x) of N values (z), array a of row x
+// at (x 2NF + a) N; D = 1 is one such row.  Grid-stride over groups of V
+// consecutive z values; the x-neighbour rows and the two z-neighbours of a
+// group are loaded directly (the rows of neighbouring groups share them in
+// the caches).  The previous pass's scalar step runs first, as in
+// lattice_pass.
+template <typename T, int NF, int D>
+__global__ __launch_bounds__(256) void lowdim_pass(PassArgs A) {
+    constexpr int NS = kSumsPerField * NF + 1;
+    constexpr int V = VecOf<T>::V;
+    const int NT = 256;
+    const int nblocks = gridDim.x;
+    const int bid = blockIdx.x;
+    __shared__ Scal s_sc;
+    __shared__ double tot[kMaxSums];
+    {
+        constexpr int NW = sizeof(Scal) / 8;
+        const unsigned long long* src = reinterpret_cast<const unsigned long long*>(A.sc_in);
+        unsigned long long* dst = reinterpret_cast<unsigned long long*>(&s_sc);
+        const int t = threadIdx.x;
+        const unsigned long long w0 = t < NW ? src[t] : 0ull;
+        if (A.has_prev) slots_sum<NS>(A.prev_partials, NT, A.prev_nslots, tot);
+        if (t < NW) dst[t] = w0;
+        __syncthreads();
+        if (A.has_prev) {
+            cl_observables* rec = (bid == 0 && A.prev_rec >= 0) ? A.obs + A.prev_rec : nullptr;
+            if (threadIdx.x < 64) finish_pass(A.ph, &s_sc, A.pkt, A.pkb, A.phn, rec, tot);
+            __syncthreads();
+            if (bid == 0) copy_scal(A.sc_out, &s_sc, NT);
+        }
+    }
+    const T cd = A.drift ? static_cast<T>(s_sc.cd) : T(0);
+    const T kL = static_cast<T>(s_sc.kL), kV = static_cast<T>(s_sc.kV);
+    const T kt = static_cast<T>(A.kt), kb = static_cast<T>(A.kb);
+    T shift[NF];
+#pragma unroll
+    for (int j = 0; j < NF; ++j) shift[j] = static_cast<T>(s_sc.shift[j]);
+    const T m2[2] = {static_cast<T>(A.ph.m2[0]), static_cast<T>(A.ph.m2[1])};
+    const T lam[2] = {static_cast<T>(A.ph.lam[0]), static_cast<T>(A.ph.lam[1])};
+    const T g2 = static_cast<T>(A.ph.g2);
+    const T hm2[2] = {T(0.5) * m2[0], T(0.5) * m2[1]};
+    const T qlam[2] = {T(0.25) * lam[0], T(0.25) * lam[1]};
+    const T hg2 = T(0.5) * g2;
+    const int N = A.N;
+    const int rows = D == 2 ? N : 1;
+    const int per_row = N / V;
+    const size_t rs = static_cast<size_t>(2 * NF) * N;  // row stride
+    const T* in = static_cast<const T*>(A.in);
+    T* out = static_cast<T*>(A.out);
+    double acc[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) acc[k] = 0.0;
+    const long groups = static_cast<long>(rows) * per_row;
+    for (long g = static_cast<long>(bid) * NT + threadIdx.x; g < groups; g += static_cast<long>(nblocks) * NT) {
+        const int x = static_cast<int>(g / per_row);
+        const int zc = static_cast<int>(g % per_row) * V;
+        const size_t row = static_cast<size_t>(x) * rs;
+        const int zm_i = (zc - 1 + N) % N, zp_i = (zc + V) % N;
+        T part[NS];
+#pragma unroll
+        for (int q = 0; q < NS; ++q) part[q] = T(0);
+        T f[NF][V], po[NF][V], zm0[NF], zp0[NF], xm[NF][V], xp[NF][V];
+#pragma unroll
+        for (int j = 0; j < NF; ++j) {
+            const T* fr = in + row + static_cast<size_t>(j) * N;
+            const T* pr = in + row + static_cast<size_t>(NF + j) * N;
+            T fv[V];
+            vload(fr + zc, fv);
+            vload(pr + zc, po[j]);
+#pragma unroll
+            for (int v = 0; v < V; ++v) f[j][v] = fmad(cd, po[j][v], fv[v]);
+            zm0[j] = fmad(cd, pr[zm_i], fr[zm_i]);
+            zp0[j] = fmad(cd, pr[zp_i], fr[zp_i]);
+            if constexpr (D == 2) {
+                const size_t rm = static_cast<size_t>((x - 1 + N) % N) * rs, rp = static_cast<size_t>((x + 1) % N) * rs;
+                T a[V], b[V], c[V], d[V];
+                vload(in + rm + static_cast<size_t>(j) * N + zc, a);
+                vload(in + rm + static_cast<size_t>(NF + j) * N + zc, b);
+                vload(in + rp + static_cast<size_t>(j) * N + zc, c);
+                vload(in + rp + static_cast<size_t>(NF + j) * N + zc, d);
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    xm[j][v] = fmad(cd, b[v], a[v]);
+                    xp[j][v] = fmad(cd, d[v], c[v]);
+                }
+            }
+        }
+        T pnew[NF][V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            T fs[NF], dV[NF];
+#pragma unroll
+            for (int j = 0; j < NF; ++j) fs[j] = f[j][v];
+            site_dV<T, NF>(fs, m2, lam, g2, dV);
+            {
+                T Vs = T(0);
+#pragma unroll
+                for (int j = 0; j < NF; ++j) {
+                    const T f2 = fs[j] * fs[j];
+                    Vs = fmad(f2, fmad(qlam[j], f2, hm2[j]), Vs);
+                }
+                if constexpr (NF == 2) Vs = fmad(hg2 * (fs[0] * fs[0]), fs[1] * fs[1], Vs);
+                part[NS - 1] += Vs;
+            }
+#pragma unroll
+            for (int j = 0; j < NF; ++j) {
+                const T fc = fs[j];
+                const T zm = v == 0 ? zm0[j] : f[j][v - 1];
+                const T zp = v == V - 1 ? zp0[j] : f[j][v + 1];
+                T nb = zm + zp;
+                T g = (zp - fc) * (zp - fc);
+                if constexpr (D == 2) {
+                    nb = (xm[j][v] + xp[j][v]) + nb;
+                    g = fmad(xp[j][v] - fc, xp[j][v] - fc, g);
+                }
+                const T F = fmad(kL, fmad(T(-2 * D), fc, nb), -(kV * dV[j]));
+                const T p0 = po[j][v];
+                const T p1 = fmad(kt, F, p0);
+                const T ps = fmad(kb, F, p0);
+                const T dd = fc - shift[j];
+                T* q5 = part + kSumsPerField * j;
+                pnew[j][v] = p1;
+                q5[0] = fmad(ps, ps, q5[0]);
+                q5[1] += g;
+                q5[2] += dd;
+                q5[3] = fmad(dd, dd, q5[3]);
+                q5[4] += p1;
+            }
+        }
+        if (A.write_out) {
+#pragma unroll
+            for (int j = 0; j < NF; ++j) {
+                vstore(out + row + static_cast<size_t>(j) * N + zc, f[j]);
+                vstore(out + row + static_cast<size_t>(NF + j) * N + zc, pnew[j]);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NS; ++q) acc[q] += static_cast<double>(part[q]);
+    }
+    block_sum<NS>(acc, NT, tot);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < NS; ++k) A.partials[(size_t)k * nblocks + bid] = tot[k];
+}
+
+template <typename T, int NF>
+static hipError_t launch_lowdim(const PassArgs& a, int grid, hipStream_t s) {
+    if (a.dim == 1) hipLaunchKernelGGL((lowdim_pass<T, NF, 1>), dim3(grid), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((lowdim_pass<T, NF, 2>), dim3(grid), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_pass(const PassArgs& a, const Tile& t, cl_precision prec, hipStream_t s) {
+    if (a.dim < 3) {
+        // one workgroup of 256 threads per tile slot (t.NT == 256)
+        if (prec == CL_FP32)
+            return a.ph.nf == 1 ? launch_lowdim<float, 1>(a, t.nblocks(), s) : launch_lowdim<float, 2>(a, t.nblocks(), s);
+        return a.ph.nf == 1 ? launch_lowdim<double, 1>(a, t.nblocks(), s) : launch_lowdim<double, 2>(a, t.nblocks(), s);
+    }
     const size_t lds = pass_lds_bytes(t, prec, a.ph.nf);
     if (prec == CL_FP32)
         return a.ph.nf == 1 ? launch_nf<float, 1>(a, t, s, lds) : launch_nf<float, 2>(a, t, s, lds);

@@ -595,6 +595,7 @@ cl_status cl_surrogate_dataset_reserve(cl_surrogate* s, int N, int max_pairs) {
 
 static cl_status record(cl_surrogate* s, cl_lattice* h, bool input) {
     if (!s || !h) return sfail(CL_EINVAL, "NULL argument");
+    if (h->dim != 3) return sfail(CL_EUNSUPPORTED, "the surrogate works on three-dimensional lattices");
     if (!s->ds_fluct) return sfail(CL_ESTATE, "no dataset reserved");
     if (h->N != s->dsN || h->nf != s->cfg.n_fields) return sfail(CL_EINVAL, "lattice does not match the dataset");
     if (input == s->pending) return sfail(CL_ESTATE, input ? "input already recorded" : "no input recorded");
@@ -830,6 +831,7 @@ cl_status cl_surrogate_load(cl_surrogate* s, const char* path) {
 cl_status cl_surrogate_advance(cl_lattice* h, cl_surrogate* s, cl_integrator fallback, double dt, int n_jumps,
                                double threshold, cl_observables* per_jump, cl_surrogate_report* rep) {
     if (!h || !s) return sfail(CL_EINVAL, "NULL argument");
+    if (h->dim != 3) return sfail(CL_EUNSUPPORTED, "the surrogate works on three-dimensional lattices");
     if (fallback != CL_LEAPFROG && fallback != CL_VV4)
         return sfail(CL_EINVAL, "the fallback integrator must be leapfrog or VV4");
     if (h->nf != s->cfg.n_fields) return sfail(CL_EINVAL, "lattice fields do not match the surrogate");

@@ -101,14 +101,25 @@ def ensemble_members() -> list[Workload]:
 
 
 def random_state(N: int, n_fields: int, seed: int, fbar=(1.0, 0.0), pbar=(0.0, 0.0),
-                 famp: float = 1e-2, pamp: float = 1e-2):
-    """Seeded random field state (f, p), each of shape [n_fields, N, N, N] FP64,
-    z fastest.  Homogeneous values plus independent uniform noise of the given
-    amplitudes.  Used for single-pass checks that do not need a physical seed."""
+                 famp: float = 1e-2, pamp: float = 1e-2, dim: int = 3):
+    """Seeded random field state (f, p), each of shape [n_fields] + [N] * dim
+    FP64, last index fastest.  Homogeneous values plus independent uniform
+    noise of the given amplitudes.  Used for checks that do not need a
+    physical seed (and for the reduced lattices, which take their fields
+    from the caller)."""
     rng = np.random.default_rng(seed)
-    f = np.empty((n_fields, N, N, N))
-    p = np.empty((n_fields, N, N, N))
+    shape = (N,) * dim
+    f = np.empty((n_fields,) + shape)
+    p = np.empty((n_fields,) + shape)
     for j in range(n_fields):
-        f[j] = fbar[j] + famp * rng.uniform(-1.0, 1.0, (N, N, N))
-        p[j] = pbar[j] + pamp * rng.uniform(-1.0, 1.0, (N, N, N))
+        f[j] = fbar[j] + famp * rng.uniform(-1.0, 1.0, shape)
+        p[j] = pbar[j] + pamp * rng.uniform(-1.0, 1.0, shape)
     return f, p
+
+
+# Reduced (2+1)-dimensional lattice of the two-field preheating physics:
+# 4096^2 sites, FP32 fields, VV4, dt = 0.05 dx, k_IR = 0.5 * 256 / 4096 (the
+# same dx as the 256^3 workload); seeded noise states.
+C4 = Workload(name="lphi4-2field-q100-4096^2-fp32-vv4", N=4096, k_ir=0.5 * 256 / 4096, n_fields=2,
+              lam=(1.0, 0.0), g2=100.0, fbar=(1.0, 0.0), integrator="vv4",
+              dt_over_dx=0.05, steps=2000, seed=51, precision="fp32")
