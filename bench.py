@@ -498,6 +498,46 @@ def spectrum_run(w, reps=5):
             "hbm_frac": alg / sec / 1e9 / HBM_PEAK_GBS, "alg_bytes": alg}
 
 
+def oracle_worker(seed: int, start_at: float):
+    """One process of the all-cores oracle baseline: seed the 256^3
+    workload, wait for the common start time, time one full step, print it."""
+    from oracle import lattice as L
+    from oracle import seed as S
+    w = W.C1
+    P = L.Params(N=w.N, dx=w.dx, n_fields=w.n_fields, alpha=w.alpha, mp=w.mp, expansion=w.expansion,
+                 m2=w.m2, lam=w.lam, g2=w.g2, V0=w.V0)
+    s = S.seed_state(P, w.k_ir, w.fbar[:w.n_fields], w.pbar[:w.n_fields], seed, cutoff=w.cutoff_modes)
+    while time.time() < start_at:
+        time.sleep(0.01)
+    t0 = time.perf_counter()
+    L.step(s, w.dt, P, w.integrator)
+    print(json.dumps({"seconds": time.perf_counter() - t0}), flush=True)
+
+
+def cpu_all_cores(procs):
+    """The same oracle step (256^3 workload) in `procs` concurrent worker
+    processes (one thread each, started as child programs), all timed from a
+    common start: the aggregate rate of the untuned oracle over the host's
+    cores."""
+    import subprocess
+    w = W.C1
+    start_at = time.time() + 25.0  # every worker has seeded by then
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    ps = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--oracle-worker", str(w.seed + i),
+                            "--start-at", repr(start_at)], stdout=subprocess.PIPE, env=env, text=True)
+          for i in range(procs)]
+    secs = []
+    for p in ps:
+        out, _ = p.communicate(timeout=300)
+        if p.returncode == 0 and out.strip():
+            secs.append(json.loads(out.strip().splitlines()[-1])["seconds"])
+    if len(secs) != procs:
+        return None
+    return {"value": sum(w.sites / t for t in secs), "unit": "site-updates/s", "cores": procs, "kind": "oracle",
+            "sample": f"one full {w.integrator} step of the {w.N}^3 workload in each of {procs} concurrent "
+                      f"single-thread processes, slowest {max(secs):.1f} s"}
+
+
 def cpu_baseline(w, steps=1):
     """The FP64 oracle as it stands, on the same 256^3 workload, for a bounded
     number of full steps on the host (numpy, single thread)."""
@@ -533,9 +573,15 @@ def main():
     ap.add_argument("--sg-jumps", type=int, default=312)
     ap.add_argument("--sg-extra", type=int, default=4, help="broadcast inputs: 4 = (a, H, <phi>, <pi_phi>), 2 = (a, H)")
     ap.add_argument("--sg-ablation", action="store_true", help="also train and evaluate the 6-channel input layout")
+    ap.add_argument("--oracle-worker", type=int, default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--start-at", type=float, default=0.0, help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-procs", type=int, default=16, help="processes of the all-cores oracle baseline (0: skip)")
     ap.add_argument("--workload", choices=["c1", "c3"], default="c1",
                     help="c1: 256^3 two-field VV4 (default); c3: 1024^3 two-field leapfrog")
     args = ap.parse_args()
+    if args.oracle_worker is not None:
+        oracle_worker(args.oracle_worker, args.start_at)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
@@ -612,6 +658,10 @@ def main():
         # the oracle on the 256^3 workload (the 1024^3 one does not fit a numpy run of ~30 s)
         progress("oracle on the host (cpu_baseline)")
         line["cpu_baseline"] = cpu_baseline(W.C1, steps=1)
+        procs = min(args.cpu_procs, os.cpu_count() or 1)
+        if procs > 1:
+            progress(f"oracle on {procs} host cores")
+            line["cpu_baseline"]["all_cores"] = cpu_all_cores(procs)
     print(json.dumps(line), flush=True)
 
 
