@@ -594,8 +594,13 @@ cl_status cl_create_dim(int dim, int N, double dx, int n_fields, cl_precision pr
         Tile t;
         t.TZ = N;
         t.TY = t.CX = t.RY = t.PD = t.HI = 1;
+        if (dim == 2) {
+            // rows marched per work item: enough items for the grid, at most 32
+            t.CX = 1;
+            while (t.CX < 32 && N % (2 * t.CX) == 0 && groups / (2 * t.CX) >= 256u * cl::kTunedPassBlocks) t.CX *= 2;
+        }
         t.NT = 256;
-        t.nbz = static_cast<int>(std::min<size_t>((groups + 255) / 256, cl::kTunedPassBlocks));
+        t.nbz = static_cast<int>(std::min<size_t>((groups / t.CX + 255) / 256, cl::kTunedPassBlocks));
         t.nby = t.nbx = 1;
         h->tile = t;
     }

@@ -1403,10 +1403,183 @@ __global__ __launch_bounds__(256) void lowdim_pass(PassArgs A) {
         for (int k = 0; k < NS; ++k) A.partials[(size_t)k * nblocks + bid] = tot[k];
 }
 
+// (2+1)-dimensional pass as a march: a work item is V consecutive z values
+// of CX consecutive rows; its thread walks the rows keeping the drifted f of
+// rows x-1, x, x+1 and pi of x, x+1 in registers, with the loads of row x+2
+// in flight, so a row leaves HBM about once (the z-neighbours of a group
+// come from the caches).  Items are dealt z-fastest, so a wave's loads are
+// contiguous.  Sums, scalar step and writes as in lowdim_pass.
+template <typename T, int NF>
+__global__ __launch_bounds__(256) void lowdim2_march(PassArgs A) {
+    constexpr int NS = kSumsPerField * NF + 1;
+    constexpr int V = VecOf<T>::V;
+    const int NT = 256;
+    const int nblocks = gridDim.x;
+    const int bid = blockIdx.x;
+    __shared__ Scal s_sc;
+    __shared__ double tot[kMaxSums];
+    {
+        constexpr int NW = sizeof(Scal) / 8;
+        const unsigned long long* src = reinterpret_cast<const unsigned long long*>(A.sc_in);
+        unsigned long long* dst = reinterpret_cast<unsigned long long*>(&s_sc);
+        const int t = threadIdx.x;
+        const unsigned long long w0 = t < NW ? src[t] : 0ull;
+        if (A.has_prev) slots_sum<NS>(A.prev_partials, NT, A.prev_nslots, tot);
+        if (t < NW) dst[t] = w0;
+        __syncthreads();
+        if (A.has_prev) {
+            cl_observables* rec = (bid == 0 && A.prev_rec >= 0) ? A.obs + A.prev_rec : nullptr;
+            if (threadIdx.x < 64) finish_pass(A.ph, &s_sc, A.pkt, A.pkb, A.phn, rec, tot);
+            __syncthreads();
+            if (bid == 0) copy_scal(A.sc_out, &s_sc, NT);
+        }
+    }
+    const T cd = A.drift ? static_cast<T>(s_sc.cd) : T(0);
+    const T kL = static_cast<T>(s_sc.kL), kV = static_cast<T>(s_sc.kV);
+    const T kt = static_cast<T>(A.kt), kb = static_cast<T>(A.kb);
+    T shift[NF];
+#pragma unroll
+    for (int j = 0; j < NF; ++j) shift[j] = static_cast<T>(s_sc.shift[j]);
+    const T m2[2] = {static_cast<T>(A.ph.m2[0]), static_cast<T>(A.ph.m2[1])};
+    const T lam[2] = {static_cast<T>(A.ph.lam[0]), static_cast<T>(A.ph.lam[1])};
+    const T g2 = static_cast<T>(A.ph.g2);
+    const T hm2[2] = {T(0.5) * m2[0], T(0.5) * m2[1]};
+    const T qlam[2] = {T(0.25) * lam[0], T(0.25) * lam[1]};
+    const T hg2 = T(0.5) * g2;
+    const int N = A.N, CX = A.CX;
+    const int per_row = N / V;
+    const size_t rs = static_cast<size_t>(2 * NF) * N;
+    const T* in = static_cast<const T*>(A.in);
+    T* out = static_cast<T*>(A.out);
+    double acc[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) acc[k] = 0.0;
+    // raw row loads: own V values of f and pi and the two z-neighbours
+    struct Row {
+        T f[NF][V], p[NF][V], zmf[NF], zmp[NF], zpf[NF], zpp[NF];
+    };
+    auto load_row = [&](Row& R, int x, int zc) {
+        const size_t row = static_cast<size_t>((x + N) % N) * rs;
+        const int zm_i = (zc - 1 + N) % N, zp_i = (zc + V) % N;
+#pragma unroll
+        for (int j = 0; j < NF; ++j) {
+            const T* fr = in + row + static_cast<size_t>(j) * N;
+            const T* pr = in + row + static_cast<size_t>(NF + j) * N;
+            vload(fr + zc, R.f[j]);
+            vload(pr + zc, R.p[j]);
+            R.zmf[j] = fr[zm_i];
+            R.zmp[j] = pr[zm_i];
+            R.zpf[j] = fr[zp_i];
+            R.zpp[j] = pr[zp_i];
+        }
+    };
+    // drifted f of a row (own values and the z-neighbours)
+    struct Drift {
+        T f[NF][V], zm[NF], zp[NF];
+    };
+    auto drift = [&](const Row& R, Drift& D) {
+#pragma unroll
+        for (int j = 0; j < NF; ++j) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) D.f[j][v] = fmad(cd, R.p[j][v], R.f[j][v]);
+            D.zm[j] = fmad(cd, R.zmp[j], R.zmf[j]);
+            D.zp[j] = fmad(cd, R.zpp[j], R.zpf[j]);
+        }
+    };
+    const long items = static_cast<long>(per_row) * (N / CX);
+    for (long it = static_cast<long>(bid) * NT + threadIdx.x; it < items; it += static_cast<long>(nblocks) * NT) {
+        const int zc = static_cast<int>(it % per_row) * V;
+        const int x0 = static_cast<int>(it / per_row) * CX;
+        Row ra, rb;
+        Drift dprev, dcur, dnxt;
+        T pcur[NF][V], pnxt[NF][V];
+        load_row(ra, x0 - 1, zc);
+        load_row(rb, x0, zc);
+        drift(ra, dprev);
+        drift(rb, dcur);
+#pragma unroll
+        for (int j = 0; j < NF; ++j)
+#pragma unroll
+            for (int v = 0; v < V; ++v) pcur[j][v] = rb.p[j][v];
+        load_row(ra, x0 + 1, zc);
+        for (int i = 0; i < CX; ++i) {
+            const int x = x0 + i;
+            // row x+1 arrives (ra), the loads of row x+2 go out (rb)
+            drift(ra, dnxt);
+#pragma unroll
+            for (int j = 0; j < NF; ++j)
+#pragma unroll
+                for (int v = 0; v < V; ++v) pnxt[j][v] = ra.p[j][v];
+            if (i + 1 < CX) load_row(rb, x + 2, zc);
+            T part[NS];
+#pragma unroll
+            for (int q = 0; q < NS; ++q) part[q] = T(0);
+            T pnew[NF][V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                T fs[NF], dV[NF];
+#pragma unroll
+                for (int j = 0; j < NF; ++j) fs[j] = dcur.f[j][v];
+                site_dV<T, NF>(fs, m2, lam, g2, dV);
+                {
+                    T Vs = T(0);
+#pragma unroll
+                    for (int j = 0; j < NF; ++j) {
+                        const T f2 = fs[j] * fs[j];
+                        Vs = fmad(f2, fmad(qlam[j], f2, hm2[j]), Vs);
+                    }
+                    if constexpr (NF == 2) Vs = fmad(hg2 * (fs[0] * fs[0]), fs[1] * fs[1], Vs);
+                    part[NS - 1] += Vs;
+                }
+#pragma unroll
+                for (int j = 0; j < NF; ++j) {
+                    const T fc = fs[j];
+                    const T zm = v == 0 ? dcur.zm[j] : dcur.f[j][v - 1];
+                    const T zp = v == V - 1 ? dcur.zp[j] : dcur.f[j][v + 1];
+                    const T xm = dprev.f[j][v], xp = dnxt.f[j][v];
+                    const T nb = (xm + xp) + (zm + zp);
+                    const T F = fmad(kL, fmad(T(-4), fc, nb), -(kV * dV[j]));
+                    const T p0 = pcur[j][v];
+                    const T p1 = fmad(kt, F, p0);
+                    const T ps = fmad(kb, F, p0);
+                    const T dd = fc - shift[j];
+                    T* q5 = part + kSumsPerField * j;
+                    pnew[j][v] = p1;
+                    q5[0] = fmad(ps, ps, q5[0]);
+                    q5[1] = fmad(xp - fc, xp - fc, (zp - fc) * (zp - fc)) + q5[1];
+                    q5[2] += dd;
+                    q5[3] = fmad(dd, dd, q5[3]);
+                    q5[4] += p1;
+                }
+            }
+            if (A.write_out) {
+                const size_t row = static_cast<size_t>(x) * rs;
+#pragma unroll
+                for (int j = 0; j < NF; ++j) {
+                    vstore(out + row + static_cast<size_t>(j) * N + zc, dcur.f[j]);
+                    vstore(out + row + static_cast<size_t>(NF + j) * N + zc, pnew[j]);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < NS; ++q) acc[q] += static_cast<double>(part[q]);
+            dprev = dcur;
+            dcur = dnxt;
+#pragma unroll
+            for (int j = 0; j < NF; ++j)
+#pragma unroll
+                for (int v = 0; v < V; ++v) pcur[j][v] = pnxt[j][v];
+            ra = rb;
+        }
+    }
+    block_sum<NS>(acc, NT, tot);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < NS; ++k) A.partials[(size_t)k * nblocks + bid] = tot[k];
+}
+
 template <typename T, int NF>
 static hipError_t launch_lowdim(const PassArgs& a, int grid, hipStream_t s) {
     if (a.dim == 1) hipLaunchKernelGGL((lowdim_pass<T, NF, 1>), dim3(grid), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((lowdim_pass<T, NF, 2>), dim3(grid), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((lowdim2_march<T, NF>), dim3(grid), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
