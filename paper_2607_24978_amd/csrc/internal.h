@@ -151,9 +151,9 @@ struct EnsArgs {
 };
 
 // Kernel launchers (stencil.hip).  Return the HIP error of the launch.
-hipError_t launch_ensemble_pass(const EnsArgs& a, cl_precision prec, int nf, int grid, hipStream_t s);
+hipError_t launch_ensemble_pass(const EnsArgs& a, cl_precision prec, int nf, int grid, int maxry, hipStream_t s);
 size_t ensemble_lds_bytes(cl_precision prec, int nf, int maxTY, int maxTZ);
-int ensemble_grid(cl_precision prec, int nf, size_t lds);
+int ensemble_grid(cl_precision prec, int nf, size_t lds, int maxry);
 hipError_t launch_pass(const PassArgs& a, const Tile& t, cl_precision prec, hipStream_t s);
 // One workgroup of t.NT threads: the pending scalar step of the last pass.
 hipError_t launch_finish(const PassArgs& a, const Tile& t, int nf, hipStream_t s);

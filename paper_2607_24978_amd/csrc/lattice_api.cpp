@@ -1100,6 +1100,7 @@ struct cl_ensemble {
     size_t partials_cap = 0, items_cap = 0;  // allocated slots
     int item_sites = 0;                      // layout parameters in use
     bool two_rows = true;
+    int maxry = 1;                           // largest rows per thread among the members
 };
 
 namespace {
@@ -1201,7 +1202,9 @@ cl_status ens_layout(cl_ensemble* e, int item_sites, bool two_rows) {
     e->table = table;
     e->nitems = static_cast<int>(items.size());
     e->lds = cl::ensemble_lds_bytes(e->prec, e->nf, maxTY, maxTZ);
-    e->grid = std::min(cl::ensemble_grid(e->prec, e->nf, e->lds), e->nitems);
+    e->maxry = 1;
+    for (const cl::EnsMember& t : e->table) e->maxry = std::max(e->maxry, t.RY);
+    e->grid = std::min(cl::ensemble_grid(e->prec, e->nf, e->lds, e->maxry), e->nitems);
     e->item_sites = item_sites;
     e->two_rows = two_rows;
     return CL_OK;
@@ -1346,7 +1349,7 @@ cl_status cl_ensemble_step(cl_ensemble* e, cl_integrator integ, int n, cl_observ
         a.ckt = 0.5 * c[0];
         a.ckb = 0.0;
         a.chn = c[0];
-        if (err == hipSuccess) err = cl::launch_ensemble_pass(a, e->prec, e->nf, e->grid, e->stream);
+        if (err == hipSuccess) err = cl::launch_ensemble_pass(a, e->prec, e->nf, e->grid, e->maxry, e->stream);
         for (int s = 0; s < M && err == hipSuccess; ++s) {
             a.parity = (s + 1) & 1;
             a.drift = 1;
@@ -1354,7 +1357,7 @@ cl_status cl_ensemble_step(cl_ensemble* e, cl_integrator integ, int n, cl_observ
             a.ckt = s + 1 < M ? 0.5 * (c[s] + c[s + 1]) : 0.5 * c[s];
             a.chn = s + 1 < M ? c[s + 1] : 0.0;
             a.rec = ((s + 1) % per == 0) ? (s + 1) / per - 1 : -1;
-            err = cl::launch_ensemble_pass(a, e->prec, e->nf, e->grid, e->stream);
+            err = cl::launch_ensemble_pass(a, e->prec, e->nf, e->grid, e->maxry, e->stream);
         }
         hipError_t e2 = hipStreamEndCapture(e->stream, &g);
         if (err != hipSuccess || e2 != hipSuccess) {
@@ -1452,7 +1455,7 @@ cl_status cl_ensemble_autotune(cl_ensemble* e, int reps, char* report, size_t ca
                 hipError_t r = hipSuccess;
                 for (int q = 0; q < 2 && r == hipSuccess; ++q) {
                     a.parity = q;
-                    r = cl::launch_ensemble_pass(a, e->prec, e->nf, e->grid, e->stream);
+                    r = cl::launch_ensemble_pass(a, e->prec, e->nf, e->grid, e->maxry, e->stream);
                 }
                 return r;
             };

@@ -1091,8 +1091,11 @@ Tile default_tile(int N, cl_precision prec, int nf) {
 // work counter until none is left.  Each member has its own partial slots
 // and ticket; the workgroup that finishes a member's last tile sums that
 // member's slots in fixed order and advances its scale factor.  The last
-// workgroup to leave resets the counters for the next pass.
-template <typename T, int NF>
+// workgroup to leave resets the counters for the next pass.  MAXRY: the
+// largest rows per thread among the members; with one row everywhere the
+// kernel has only that path, with its halo ring at depth 2, and fits two
+// waves per SIMD.
+template <typename T, int NF, int MAXRY>
 __global__ __launch_bounds__(256) void ensemble_pass(EnsArgs E) {
     constexpr int NS = kSumsPerField * NF + 1;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1133,8 +1136,12 @@ __global__ __launch_bounds__(256) void ensemble_pass(EnsArgs E) {
         double acc[NS];
 #pragma unroll
         for (int k = 0; k < NS; ++k) acc[k] = 0.0;
-        if (M.RY == 2) march_tile<T, NF, 2, 1, 4, 0, 4>(J, smem_raw, acc, [] {});
-        else march_tile<T, NF, 1, 1, 4, 0, 4>(J, smem_raw, acc, [] {});
+        if constexpr (MAXRY == 2) {
+            if (M.RY == 2) march_tile<T, NF, 2, 1, 4, 0, 4>(J, smem_raw, acc, [] {});
+            else march_tile<T, NF, 1, 1, 4, 0, 4>(J, smem_raw, acc, [] {});
+        } else {
+            march_tile<T, NF, 1, 1, 4, 0, 2>(J, smem_raw, acc, [] {});
+        }
         if (reduce_partials<NS>(acc, 256, M.partials, I.tile, M.nitems, M.ticket, tot) && threadIdx.x < 64)
             finish_pass(M.ph, M.sc, kt, kb, hn, E.rec >= 0 ? E.obs + (size_t)E.rec * E.nmembers + I.member : nullptr,
                         tot);
@@ -1154,32 +1161,42 @@ size_t ensemble_lds_bytes(cl_precision prec, int nf, int maxTY, int maxTZ) {
     return 2ull * nf * (maxTY + 2) * (maxTZ + 2 * V) * es;
 }
 
-template <typename T, int NF>
+template <typename T, int NF, int MAXRY>
 static int grid_for(size_t lds) {
     int per_cu = 0, dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 256;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ensemble_pass<T, NF>, 256, lds) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ensemble_pass<T, NF, MAXRY>, 256, lds) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     return per_cu * cus;
 }
 
-int ensemble_grid(cl_precision prec, int nf, size_t lds) {
-    if (prec == CL_FP32) return nf == 1 ? grid_for<float, 1>(lds) : grid_for<float, 2>(lds);
-    return nf == 1 ? grid_for<double, 1>(lds) : grid_for<double, 2>(lds);
+template <int MAXRY>
+static int grid_ry(cl_precision prec, int nf, size_t lds) {
+    if (prec == CL_FP32) return nf == 1 ? grid_for<float, 1, MAXRY>(lds) : grid_for<float, 2, MAXRY>(lds);
+    return nf == 1 ? grid_for<double, 1, MAXRY>(lds) : grid_for<double, 2, MAXRY>(lds);
 }
 
-hipError_t launch_ensemble_pass(const EnsArgs& a, cl_precision prec, int nf, int grid, hipStream_t s) {
+int ensemble_grid(cl_precision prec, int nf, size_t lds, int maxry) {
+    return maxry == 2 ? grid_ry<2>(prec, nf, lds) : grid_ry<1>(prec, nf, lds);
+}
+
+template <int MAXRY>
+static hipError_t launch_ens_ry(const EnsArgs& a, cl_precision prec, int nf, int grid, hipStream_t s) {
     const size_t lds = static_cast<size_t>(a.lds_bytes);
     if (prec == CL_FP32) {
-        if (nf == 1) hipLaunchKernelGGL((ensemble_pass<float, 1>), dim3(grid), dim3(256), lds, s, a);
-        else hipLaunchKernelGGL((ensemble_pass<float, 2>), dim3(grid), dim3(256), lds, s, a);
+        if (nf == 1) hipLaunchKernelGGL((ensemble_pass<float, 1, MAXRY>), dim3(grid), dim3(256), lds, s, a);
+        else hipLaunchKernelGGL((ensemble_pass<float, 2, MAXRY>), dim3(grid), dim3(256), lds, s, a);
     } else {
-        if (nf == 1) hipLaunchKernelGGL((ensemble_pass<double, 1>), dim3(grid), dim3(256), lds, s, a);
-        else hipLaunchKernelGGL((ensemble_pass<double, 2>), dim3(grid), dim3(256), lds, s, a);
+        if (nf == 1) hipLaunchKernelGGL((ensemble_pass<double, 1, MAXRY>), dim3(grid), dim3(256), lds, s, a);
+        else hipLaunchKernelGGL((ensemble_pass<double, 2, MAXRY>), dim3(grid), dim3(256), lds, s, a);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_ensemble_pass(const EnsArgs& a, cl_precision prec, int nf, int grid, int maxry, hipStream_t s) {
+    return maxry == 2 ? launch_ens_ry<2>(a, prec, nf, grid, s) : launch_ens_ry<1>(a, prec, nf, grid, s);
 }
 
 void candidate_tiles(int N, cl_precision prec, int nf, Tile* out, int* count, int cap) {
