@@ -236,6 +236,25 @@ def surrogate_flops_per_site(extra_inputs: int, nf: int = 2, hidden: int = 32, l
 MFMA_BF16_PEAK = 2.5e15
 
 
+def surrogate_forward_profile(N=256, reps=5):
+    """Forward passes of the 8-input surrogate network (random weights,
+    seeded random inputs of shape [8, N, N, N]) for a kernel-level profile of
+    the BF16 MFMA convolutions: the host copies of each call are outside the
+    kernels, whose durations a trace reports; useful flops per call are
+    surrogate_flops_per_site * N^3."""
+    from paper_2607_24978_amd import _lib
+    s = _lib.Surrogate(n_fields=2, extra_inputs=4, init_seed=7)
+    x = np.random.default_rng(5).standard_normal((8, N, N, N)).astype(np.float32)
+    s.forward(x)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        y = s.forward(x)
+    sec = time.perf_counter() - t0
+    s.close()
+    return {"N": N, "calls": reps, "flops_per_call": surrogate_flops_per_site(4) * N ** 3,
+            "wall_s_per_call_incl_host_copies": sec / reps, "finite": bool(np.all(np.isfinite(y)))}
+
+
 def surrogate_run(epochs=12, pairs_per_seed=64, train_seeds=range(2000, 2008), eval_seed=3000, jumps=312,
                   extra_inputs=4, eval_256=True, ablation=False):
     """The learned surrogate on the two-field q = 100 workload: training pairs
@@ -575,6 +594,8 @@ def main():
     ap.add_argument("--sg-ablation", action="store_true", help="also train and evaluate the 6-channel input layout")
     ap.add_argument("--oracle-worker", type=int, default=None, help=argparse.SUPPRESS)
     ap.add_argument("--start-at", type=float, default=0.0, help=argparse.SUPPRESS)
+    ap.add_argument("--sg-forward-profile", action="store_true",
+                    help="only run surrogate forward passes at 256^3 (for a kernel profile) and print their figures")
     ap.add_argument("--cpu-procs", type=int, default=16, help="processes of the all-cores oracle baseline (0: skip)")
     ap.add_argument("--workload", choices=["c1", "c3"], default="c1",
                     help="c1: 256^3 two-field VV4 (default); c3: 1024^3 two-field leapfrog")
@@ -587,6 +608,9 @@ def main():
         sys.exit(2)
     import torch
     torch.cuda.set_device(0)
+    if args.sg_forward_profile:
+        print(json.dumps(surrogate_forward_profile()), flush=True)
+        return
 
     from paper_2607_24978_amd import _lib
     w = W.C1 if args.workload == "c1" else W.C3
