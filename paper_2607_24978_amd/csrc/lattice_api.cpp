@@ -1101,6 +1101,7 @@ struct cl_ensemble {
     int item_sites = 0;                      // layout parameters in use
     bool two_rows = true;
     int maxry = 1;                           // largest rows per thread among the members
+    bool broken = false;                     // a layout change failed half way: no further steps
 };
 
 namespace {
@@ -1172,6 +1173,8 @@ cl_status ens_layout(cl_ensemble* e, int item_sites, bool two_rows) {
     if (e->gexec) hipGraphExecDestroy(e->gexec);
     e->gexec = nullptr;
     EHIP(hipStreamSynchronize(e->stream));
+    // from here on the old layout's device storage may be gone
+    e->broken = true;
     if (poff > e->partials_cap) {
         if (e->d_partials) hipFree(e->d_partials);
         e->d_partials = nullptr;
@@ -1207,6 +1210,7 @@ cl_status ens_layout(cl_ensemble* e, int item_sites, bool two_rows) {
     e->grid = std::min(cl::ensemble_grid(e->prec, e->nf, e->lds, e->maxry), e->nitems);
     e->item_sites = item_sites;
     e->two_rows = two_rows;
+    e->broken = false;
     return CL_OK;
 }
 
@@ -1300,6 +1304,7 @@ cl_status cl_ensemble_set_dt(cl_ensemble* e, int i, double dt) {
 
 cl_status cl_ensemble_step(cl_ensemble* e, cl_integrator integ, int n, cl_observables* out) {
     if (!e) return efail(CL_EINVAL, "ensemble is NULL");
+    if (e->broken) return efail(CL_ESTATE, "the ensemble's work layout could not be rebuilt; destroy it");
     if (is_rk(integ)) return efail(CL_EUNSUPPORTED, "ensembles run the symplectic schemes only");
     if (integ != CL_LEAPFROG && integ != CL_VV4) return efail(CL_EINVAL, "unknown integrator");
     if (n < 0) return efail(CL_EINVAL, "n must be >= 0");
@@ -1406,6 +1411,7 @@ cl_status cl_ensemble_get_tile(const cl_ensemble* e, int i, cl_tile* out) {
 
 cl_status cl_ensemble_autotune(cl_ensemble* e, int reps, char* report, size_t cap) {
     if (!e) return efail(CL_EINVAL, "ensemble is NULL");
+    if (e->broken) return efail(CL_ESTATE, "the ensemble's work layout could not be rebuilt; destroy it");
     if (reps < 1) reps = 3;
     for (cl_lattice* h : e->m) EHIP(hipStreamSynchronize(h->stream));
     const int nm = static_cast<int>(e->m.size());
