@@ -20,19 +20,20 @@ namespace cl {
 struct SpecFftArgs {
     double2* data;       // N^3 complex, site (x N + y) N + z
     const double2* tw;   // exp(-2 pi i k / N), k < N / 2
-    int N, logN, L, axis;  // axis 0: z, 1: y, 2: x
+    int N, logN, L, logL, axis;  // axis 0: z, 1: y, 2: x (N, L powers of two)
 };
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
 }
 
-// Global index of element e of line l of batch b.
-__device__ __forceinline__ size_t line_elem(const SpecFftArgs& a, int b, int l, int e) {
+// Global index of element e of line l of batch b: for the y and x axes the
+// batch fixes the outer coordinate and the first z of its L lines
+// (`outer`, `z0`, formed once per workgroup).
+__device__ __forceinline__ size_t line_elem(const SpecFftArgs& a, int b, size_t outer, size_t z0, int l, int e) {
     const size_t N = a.N;
     if (a.axis == 0) return (static_cast<size_t>(b) * a.L + l) * N + e;
-    const int per = a.N / a.L;  // batches per slab
-    const size_t outer = b / per, z = static_cast<size_t>(b % per) * a.L + l;
+    const size_t z = z0 + l;
     if (a.axis == 1) return (outer * N + e) * N + z;      // x = outer, y = e
     return (static_cast<size_t>(e) * N + outer) * N + z;  // x = e, y = outer
 }
@@ -40,28 +41,33 @@ __device__ __forceinline__ size_t line_elem(const SpecFftArgs& a, int b, int l, 
 __global__ __launch_bounds__(256) void fft_lines(SpecFftArgs a) {
     extern __shared__ double2 buf[];  // [L][N]
     const int N = a.N, L = a.L, b = blockIdx.x;
+    const int logN = a.logN, logL = a.logL;
     const int total = L * N;
-    // load: consecutive threads take consecutive global addresses
+    const int logper = logN - logL;  // batches per slab: N / L
+    const size_t outer = static_cast<size_t>(b) >> logper;
+    const size_t z0 = static_cast<size_t>(b & ((1 << logper) - 1)) << logL;
+    // load: consecutive threads take consecutive global addresses (powers of
+    // two: shifts and masks instead of divisions)
     for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
         int l, e;
         if (a.axis == 0) {
-            l = idx / N;
-            e = idx % N;
+            l = idx >> logN;
+            e = idx & (N - 1);
         } else {
-            e = idx / L;
-            l = idx % L;
+            e = idx >> logL;
+            l = idx & (L - 1);
         }
-        const int r = static_cast<int>(__brev(static_cast<unsigned>(e)) >> (32 - a.logN));
-        buf[l * N + r] = a.data[line_elem(a, b, l, e)];
+        const int r = static_cast<int>(__brev(static_cast<unsigned>(e)) >> (32 - logN));
+        buf[l * N + r] = a.data[line_elem(a, b, outer, z0, l, e)];
     }
     __syncthreads();
     const int half = N / 2;
-    for (int m = 1; m < N; m <<= 1) {
-        const int tstride = N / (2 * m);
+    for (int m = 1, lm = 0; m < N; m <<= 1, ++lm) {
+        const int tshift = logN - 1 - lm;  // twiddle stride N / (2 m)
         for (int t = threadIdx.x; t < L * half; t += blockDim.x) {
-            const int l = t / half, k = t % half;
-            const int pos = k % m, i = (k / m) * 2 * m + pos, j = i + m;
-            const double2 w = a.tw[pos * tstride];
+            const int l = t >> (logN - 1), k = t & (half - 1);
+            const int pos = k & (m - 1), i = ((k >> lm) << (lm + 1)) + pos, j = i + m;
+            const double2 w = a.tw[pos << tshift];
             double2* line = buf + l * N;
             const double2 u = line[i];
             const double2 v = cmul(line[j], w);
@@ -73,13 +79,13 @@ __global__ __launch_bounds__(256) void fft_lines(SpecFftArgs a) {
     for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
         int l, e;
         if (a.axis == 0) {
-            l = idx / N;
-            e = idx % N;
+            l = idx >> logN;
+            e = idx & (N - 1);
         } else {
-            e = idx / L;
-            l = idx % L;
+            e = idx >> logL;
+            l = idx & (L - 1);
         }
-        a.data[line_elem(a, b, l, e)] = buf[l * N + e];
+        a.data[line_elem(a, b, outer, z0, l, e)] = buf[l * N + e];
     }
 }
 
@@ -139,6 +145,8 @@ hipError_t launch_spec_fft(double2* data, const double2* tw, int N, int axis, hi
     a.logN = 0;
     while ((1 << a.logN) < N) ++a.logN;
     a.L = spec_lines_per_block(N);
+    a.logL = 0;
+    while ((1 << a.logL) < a.L) ++a.logL;
     a.axis = axis;
     const int batches = N * N / a.L;
     const size_t lds = static_cast<size_t>(a.L) * N * sizeof(double2);
