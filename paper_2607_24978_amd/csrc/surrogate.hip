@@ -167,7 +167,14 @@ __global__ __launch_bounds__(256) void conv32_fwd_tiled(ConvArgs a) {
     const int tx = t / nyt;
     const int x0 = tx * 4, y0 = ty * RY, z0 = tz * 16;
     constexpr int CHUNKS = PL * YR * ZR * 4;  // 16-byte chunks (8 channels)
-    for (int i = threadIdx.x; i < CHUNKS; i += 256) {
+    constexpr int ITER = (CHUNKS + 255) / 256;
+    // all loads of the tile first, then all LDS stores: the loads are in
+    // flight together instead of one round trip per chunk
+    uint4 v[ITER];
+#pragma unroll
+    for (int k = 0; k < ITER; ++k) {
+        // past the last chunk a thread re-reads it (in bounds) and stores nothing
+        const int i = min(static_cast<int>(threadIdx.x) + k * 256, CHUNKS - 1);
         const int c4 = i & 3;
         int r = i >> 2;
         const int zi = r % ZR;
@@ -177,8 +184,12 @@ __global__ __launch_bounds__(256) void conv32_fwd_tiled(ConvArgs a) {
         xx = xx < 0 ? xx + N : (xx >= N ? xx - N : xx);
         yy = yy < 0 ? yy + N : (yy >= N ? yy - N : yy);
         zz = zz < 0 ? zz + N : (zz >= N ? zz - N : zz);
-        const uint4 v = *reinterpret_cast<const uint4*>(in + static_cast<size_t>((xx * N + yy) * N + zz) * 32 + c4 * 8);
-        *reinterpret_cast<uint4*>(tin + static_cast<size_t>(i) * 8) = v;
+        v[k] = *reinterpret_cast<const uint4*>(in + static_cast<size_t>((xx * N + yy) * N + zz) * 32 + c4 * 8);
+    }
+#pragma unroll
+    for (int k = 0; k < ITER; ++k) {
+        const int i = threadIdx.x + k * 256;
+        if (i < CHUNKS) *reinterpret_cast<uint4*>(tin + static_cast<size_t>(i) * 8) = v[k];
     }
     __syncthreads();
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -255,14 +266,25 @@ __global__ __launch_bounds__(256) void conv8_fwd_tiled(ConvArgs a) {
     const int ty = t % nyt;
     const int tx = t / nyt;
     const int x0 = tx * 4, y0 = ty * RY, z0 = tz * 16;
-    for (int i = threadIdx.x; i < PL * YR * ZR; i += 256) {
+    constexpr int SITES = PL * YR * ZR;
+    constexpr int ITER = (SITES + 255) / 256;
+    // all loads of the tile first, then all LDS stores (past the last site a
+    // thread re-reads it, in bounds, and stores nothing)
+    uint4 v[ITER];
+#pragma unroll
+    for (int k = 0; k < ITER; ++k) {
+        const int i = min(static_cast<int>(threadIdx.x) + k * 256, SITES - 1);
         const int zi = i % ZR, yi = (i / ZR) % YR, pi = i / (ZR * YR);
         int xx = x0 - 1 + pi, yy = y0 - 1 + yi, zz = z0 - 1 + zi;
         xx = xx < 0 ? xx + N : (xx >= N ? xx - N : xx);
         yy = yy < 0 ? yy + N : (yy >= N ? yy - N : yy);
         zz = zz < 0 ? zz + N : (zz >= N ? zz - N : zz);
-        *reinterpret_cast<uint4*>(tin + static_cast<size_t>(i) * 8) =
-            *reinterpret_cast<const uint4*>(in + static_cast<size_t>((xx * N + yy) * N + zz) * 8);
+        v[k] = *reinterpret_cast<const uint4*>(in + static_cast<size_t>((xx * N + yy) * N + zz) * 8);
+    }
+#pragma unroll
+    for (int k = 0; k < ITER; ++k) {
+        const int i = static_cast<int>(threadIdx.x) + k * 256;
+        if (i < SITES) *reinterpret_cast<uint4*>(tin + static_cast<size_t>(i) * 8) = v[k];
     }
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int n = lane & 15, g = lane >> 4;
