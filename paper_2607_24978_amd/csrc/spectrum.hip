@@ -47,9 +47,10 @@ __global__ __launch_bounds__(256) void fft_lines(SpecFftArgs a) {
     const size_t outer = static_cast<size_t>(b) >> logper;
     const size_t z0 = static_cast<size_t>(b & ((1 << logper) - 1)) << logL;
     // load: consecutive threads take consecutive global addresses (powers of
-    // two: shifts and masks instead of divisions)
-    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-        int l, e;
+    // two: shifts and masks instead of divisions).  Full batches (N >= 64:
+    // L N = 4096 = 16 elements per thread) issue all of a thread's loads
+    // before its LDS stores.
+    auto split = [&](int idx, int& l, int& e) {
         if (a.axis == 0) {
             l = idx >> logN;
             e = idx & (N - 1);
@@ -57,8 +58,30 @@ __global__ __launch_bounds__(256) void fft_lines(SpecFftArgs a) {
             e = idx >> logL;
             l = idx & (L - 1);
         }
-        const int r = static_cast<int>(__brev(static_cast<unsigned>(e)) >> (32 - logN));
-        buf[l * N + r] = a.data[line_elem(a, b, outer, z0, l, e)];
+    };
+    constexpr int kIter = 4096 / 256;
+    if (total == kIter * 256 && blockDim.x == 256) {
+        double2 v[kIter];
+#pragma unroll
+        for (int k = 0; k < kIter; ++k) {
+            int l, e;
+            split(static_cast<int>(threadIdx.x) + k * 256, l, e);
+            v[k] = a.data[line_elem(a, b, outer, z0, l, e)];
+        }
+#pragma unroll
+        for (int k = 0; k < kIter; ++k) {
+            int l, e;
+            split(static_cast<int>(threadIdx.x) + k * 256, l, e);
+            const int r = static_cast<int>(__brev(static_cast<unsigned>(e)) >> (32 - logN));
+            buf[l * N + r] = v[k];
+        }
+    } else {
+        for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+            int l, e;
+            split(idx, l, e);
+            const int r = static_cast<int>(__brev(static_cast<unsigned>(e)) >> (32 - logN));
+            buf[l * N + r] = a.data[line_elem(a, b, outer, z0, l, e)];
+        }
     }
     __syncthreads();
     const int half = N / 2;
