@@ -520,3 +520,129 @@ def test_rk2_is_the_explicit_midpoint_rule():
     assert np.max(np.abs(s.p - (p + h * k2[1]))) <= 1e-13 * np.max(np.abs(p + h * k2[1]))
     assert abs(s.a - (a + h * k2[2])) <= 1e-15 * a
     assert abs(s.b - (b + h * k2[3])) <= 1e-14 * abs(b)
+
+
+# ---------------------------------------------------------------- two-field coupling, seed masses, moments
+@pytest.mark.parametrize("integrator", ["leapfrog", "vv4"])
+@pytest.mark.parametrize("moving", [0, 1])
+def test_coupled_field_dispersion(integrator, moving):
+    """P1 for the phi^2 chi^2 coupling (Sect. 5.1, lphi4 shape; Eq. singletEOM
+    with V = g^2 f_0^2 f_1^2 / 2): in static space with no self couplings and
+    no bare masses, one field held at the homogeneous value 1 gives the other
+    an effective mass g^2, so a single tiny cos-mode of the other field obeys
+    the lattice dispersion w^2 = g^2 + sum_i (2/dx)^2 sin^2(k_i dx/2).  Both
+    directions are checked (moving = 0: phi oscillates in a chi background;
+    moving = 1: chi in a phi background), so the coupling term of each
+    component of dV/df is pinned, and with the static energy pin (P4) the
+    factor 1/2 of the potential term as well.  The amplitude is small enough
+    that the quadratic back-reaction on the background (of order g^2 A^2 t^2)
+    stays below round-off."""
+    N, dx, g2, A = 8, 0.7, 2.5, 1e-10
+    nvec = (1, 2, 3)
+    P = L.Params(N=N, dx=dx, n_fields=2, expansion="static", m2=(0.0, 0.0), lam=(0.0, 0.0), g2=g2)
+    g = cos_mode(N, dx, nvec)
+    w2 = lattice_omega2(N, dx, nvec, g2)
+    dt, n = 0.2, 2000
+    f = np.zeros((2, N, N, N))
+    f[moving] = A * g
+    f[1 - moving] = 1.0
+    s = L.State(f, np.zeros((2, N, N, N)), 1.0, 0.0)
+    for _ in range(n):
+        s = L.step(s, dt, P, integrator)
+    if integrator == "leapfrog":
+        M = np.linalg.matrix_power(kdk_matrix(dt, w2), n)
+        theta = 2.0 * math.asin(math.sqrt(w2) * dt / 2.0)
+        assert abs(M[0, 0] - math.cos(n * theta)) < 1e-11
+    else:
+        M1 = kdk_matrix(L.W1 * dt, w2)
+        M0 = kdk_matrix(L.W0 * dt, w2)
+        M = np.linalg.matrix_power(M1 @ M0 @ M1, n)
+    assert np.max(np.abs(s.f[moving] / A - M[0, 0] * g)) <= 1e-11
+    assert np.max(np.abs(s.p[moving] / A - M[1, 0] * g)) <= 1e-11 * math.sqrt(w2)
+    assert np.max(np.abs(s.f[1 - moving] - 1.0)) <= 1e-14
+
+
+def _seed_mode_statistics(s, j, fbar_j, m2_j, k_ir, dx, H, N):
+    """Normalised Fourier statistics of field j of a seeded state against the
+    vacuum spectrum of Eq. QuantumFlucts with mass m2_j (a = 1, alpha = 1):
+    returns (mean |df|^2 / S_k, mean |dp|^2 / ((w^2 + H^2) S_k),
+    mean Re(df* dp) / (-H S_k), independent pairs)."""
+    Fk = np.fft.fftn(s.f[j] - fbar_j)
+    Pk = np.fft.fftn(s.p[j] - np.mean(s.p[j]))
+    kk = np.fft.fftfreq(N) * N
+    KX, KY, KZ = np.meshgrid(kk, kk, kk, indexing="ij")
+    n2 = KX ** 2 + KY ** 2 + KZ ** 2
+    inside = (n2 > 0) & (n2 <= (N / 4) ** 2)
+    assert np.max(np.abs(Fk[~inside])) <= 1e-12 * np.max(np.abs(Fk))
+    w = np.sqrt(k_ir ** 2 * n2[inside] + m2_j)
+    Sk = 1.0 / (2 * w * dx ** 3)
+    zf = np.mean(np.abs(Fk[inside]) ** 2 / Sk)
+    zp = np.mean(np.abs(Pk[inside]) ** 2 / ((w ** 2 + H ** 2) * Sk))
+    cross = np.mean(np.real(np.conj(Fk[inside]) * Pk[inside]) / (-H * Sk))
+    return zf, zp, cross, inside.sum() / 2
+
+
+def test_two_field_seed_statistics():
+    """P10 for both fields of the two-field potential
+    V = lambda phi^4/4 + g^2 phi^2 chi^2/2: each field's fluctuations follow
+    Eq. QuantumFlucts with its own effective mass d^2V/df_j^2 at the
+    homogeneous values (Eq. QuantumFlucts, m^2 = V''), i.e.
+    m_phi^2 = 3 lambda phi0^2 + g^2 chi0^2 and m_chi^2 = g^2 phi0^2; the
+    homogeneous Hubble rate of the -H df term comes from
+    rho = lambda phi0^4/4 + g^2 phi0^2 chi0^2/2.  A non-zero chi0 makes both
+    coupling terms of the masses visible; a factor 2 in either changes
+    S_k by far more than the sampling error."""
+    N, k_ir, lam, g2 = 48, 0.2, 1.0, 100.0
+    dx = 2 * math.pi / (k_ir * N)
+    phi0, chi0 = 1.0, 0.3
+    P = L.Params(N=N, dx=dx, n_fields=2, lam=(lam, 0.0), g2=g2)
+    s, imag = S.seed_state(P, k_ir, (phi0, chi0), (0.0, 0.0), seed=123, return_imag=True)
+    assert imag <= 1e-14 * max(np.max(np.abs(s.f[0] - phi0)), np.max(np.abs(s.f[1] - chi0)))
+    rho = lam * phi0 ** 4 / 4 + g2 * phi0 ** 2 * chi0 ** 2 / 2
+    H = math.sqrt(rho / 3)
+    masses = (3 * lam * phi0 ** 2 + g2 * chi0 ** 2, g2 * phi0 ** 2)
+    for j, (fb, m2) in enumerate(zip((phi0, chi0), masses)):
+        zf, zp, cross, M = _seed_mode_statistics(s, j, fb, m2, k_ir, dx, H, N)
+        tol = 5 / math.sqrt(M)
+        assert abs(zf - 1) < tol, (j, zf, tol)
+        assert abs(zp - 1) < tol, (j, zp, tol)
+        # the cross term has a large variance relative to its mean (w >> H)
+        assert abs(cross - 1) < 8 * math.sqrt(m2 + (k_ir * N / 4) ** 2) / H / math.sqrt(M), (j, cross)
+        # a mass off by the coupling factor 2 would be rejected at this size
+        w_lo = np.sqrt(m2)
+        w_hi = np.sqrt(m2 + (g2 * (chi0 ** 2 if j == 0 else phi0 ** 2)))
+        assert w_hi / w_lo - 1 > 3 * tol
+
+
+def test_two_field_seed_independent_streams():
+    """The two fields draw from independent random streams (the field index
+    is part of the counter): their Fourier amplitudes are uncorrelated."""
+    N, k_ir = 16, 0.3
+    P = L.Params(N=N, dx=2 * math.pi / (k_ir * N), n_fields=2, lam=(1.0, 0.0), g2=1.0)
+    s = S.seed_state(P, k_ir, (1.0, 0.0), (0.0, 0.0), seed=77)
+    a = np.fft.fftn(s.f[0] - 1.0).ravel()
+    b = np.fft.fftn(s.f[1]).ravel()
+    keep = np.abs(a) > 0
+    c = np.abs(np.vdot(a[keep], b[keep])) / (np.linalg.norm(a[keep]) * np.linalg.norm(b[keep]))
+    assert c < 5 / math.sqrt(keep.sum() / 2)
+
+
+@pytest.mark.parametrize("nvec,half", [((1, 0, 0), True), ((2, 3, 5), True), ((8, 0, 0), False),
+                                       ((8, 8, 8), False), ((3, 8, 0), True)])
+def test_moments_plane_wave(nvec, half):
+    """Volume mean and variance (Sect. 4.3 volume averages,
+    <(f - <f>)^2>_V) of m + A cos(k.x): mean m, variance A^2/2 for a mode
+    with a component off {0, N/2}, and A^2 for a mode made only of 0 and
+    N/2 components (cos = +-1 on every site).  A large offset m makes a
+    variance taken about zero, or divided by N^3 - 1, fail."""
+    N = 16
+    g = cos_mode(N, 1.0, nvec)
+    for m, A in ((3.0, 0.25), (-1.5, 2.0)):
+        f = np.stack([m + A * g, -m + 0.5 * A * g])
+        P = L.Params(N=N, dx=1.0, n_fields=2)
+        means, vars_ = L.moments(f, P)
+        v = A ** 2 / 2 if half else A ** 2
+        assert abs(means[0] - m) <= 1e-14 * abs(m)
+        assert abs(means[1] + m) <= 1e-14 * abs(m)
+        assert abs(vars_[0] - v) <= 1e-13 * v
+        assert abs(vars_[1] - v / 4) <= 1e-13 * v
