@@ -39,7 +39,7 @@ typedef enum {
     CL_ENOMEM = -2,       /* host or device allocation failed */
     CL_EDEVICE = -3,      /* a HIP runtime call failed */
     CL_ESTATE = -4,       /* call not valid in the handle's current state */
-    CL_EUNSTABLE = -5,    /* non-finite values appeared, or the time step exceeds the Courant bound */
+    CL_EUNSTABLE = -5,    /* non-finite values appeared, or the time step exceeds the scheme's stability bound */
     CL_EUNSUPPORTED = -6  /* valid request this build does not support */
 } cl_status;
 
@@ -209,10 +209,17 @@ cl_status cl_set_state(cl_lattice* h, const cl_scalars* in);
 
 /* Advance n full time steps of size dt with the given integrator, starting
  * and ending in a synchronised state.  If per_step is not NULL it receives n
- * records, one after each full step.  Returns CL_EUNSTABLE if dt exceeds the
- * leapfrog Courant bound dt * sqrt(12) / dx < 2 or if a lattice sum became
- * non-finite (the records then show where).  The work is issued on the
- * handle's stream and the call returns after it completes. */
+ * records, one after each full step.  Returns CL_EUNSTABLE if a lattice sum
+ * became non-finite (the records then show where) or if w_max dt reaches the
+ * integrator's stability limit on a harmonic mode, with
+ * w_max^2 = 4 dim / dx^2 a^(2 alpha - 2) + a^(2 alpha) max_j d^2V/df_j^2
+ * (the fastest lattice mode of Eq. singletEOM; the curvature of V taken at
+ * the field means of the last synchronised state).  Limits: leapfrog 2,
+ * VV4 1.5735, RK3-3 sqrt(3), RK3-4 2.823, RK4-5 3.341, classic RK4 2 sqrt(2)
+ * (ends of the stability intervals on the imaginary axis); RK2, which has
+ * none, is held to at most 1 % growth per step of the fastest mode
+ * (w_max dt < 0.532).  The work is issued on the handle's stream and the
+ * call returns after it completes. */
 cl_status cl_step(cl_lattice* h, cl_integrator integ, double dt, int n, cl_observables* per_step);
 
 /* Observables of the current state (one reduction pass over the lattice). */

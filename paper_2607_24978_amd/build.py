@@ -20,8 +20,8 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libcl_lattice.so")
 
-SOURCES = ["stencil.hip", "ensemble.hip", "surrogate.hip", "spectrum.hip", "lattice_api.cpp", "ensemble_api.cpp",
-           "surrogate_api.cpp", "host_seed.cpp"]
+SOURCES = ["stencil.hip", "surrogate.hip", "spectrum.hip", "lattice_api.cpp", "surrogate_api.cpp",
+           "host_seed.cpp"]
 
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -51,7 +51,10 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    missing = [s for s in SOURCES if not os.path.exists(os.path.join(CSRC, s))]
+    if missing:
+        raise RuntimeError(f"missing sources: {missing}")
+    srcs = list(SOURCES)
     with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"

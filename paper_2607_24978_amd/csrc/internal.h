@@ -150,6 +150,19 @@ struct EnsArgs {
     cl_observables* obs;  // [rec][member]
 };
 
+// Scratch of a sequence of lattice passes: the workgroup partial sums (two
+// halves of `half` doubles, used by alternate passes), two scalar blocks that
+// carry the background state between the passes of one call, and the ring of
+// per-step observable records.  The handle's own buffers by default; the
+// allocation-free entry point passes a fixed device array instead.
+struct Work {
+    double* partials;
+    size_t half;
+    Scal* scb;
+    cl_observables* obs;
+    int obs_cap;
+};
+
 // Kernel launchers (stencil.hip).  Return the HIP error of the launch.
 hipError_t launch_ensemble_pass(const EnsArgs& a, cl_precision prec, int nf, int grid, int maxry, hipStream_t s);
 size_t ensemble_lds_bytes(cl_precision prec, int nf, int maxTY, int maxTZ);
@@ -173,6 +186,14 @@ size_t pass_lds_bytes(const Tile& t, cl_precision prec, int nf);
 // All valid tiles the autotuner tries for a lattice.
 void candidate_tiles(int N, cl_precision prec, int nf, Tile* out, int* count, int cap);
 hipError_t launch_copy(const void* in, void* out, size_t bytes, hipStream_t s);
+
+// Allocation-free stepping (lattice_api.cpp): checks the arguments as
+// cl_step does, issues the passes of n steps of a symplectic scheme directly
+// on the handle's stream (no graph) with the scratch `w`, copies the n
+// records to per_step (if not NULL) and waits.  Allocates nothing.
+cl_status step_in_work(cl_lattice* h, cl_integrator integ, double dt, int n, cl_observables* per_step, const Work& w);
+// Records the failure message on h (or the handle-less message) and returns st.
+cl_status set_error(cl_lattice* h, cl_status st, const char* msg);
 
 // Host seed (host_seed.cpp): fills f, p (n_fields * N^3 FP64 each).
 // Returns an empty string on success, an error message otherwise.
@@ -225,6 +246,10 @@ struct cl_lattice {
     int obs_cap = 0;
     cl::Tile tile;
     int64_t step = 0;
+    // background last seen on the host (after a call synchronised with the
+    // device): scale factor and field means, for the time-step stability check
+    double host_a = 1.0;
+    double host_mean[2] = {0.0, 0.0};
     hipGraphExec_t gexec[2] = {nullptr, nullptr};  // one per starting buffer
     GraphKey gkey[2];
     bool use_graph = true;

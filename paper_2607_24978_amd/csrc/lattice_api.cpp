@@ -16,6 +16,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <algorithm>
+#include <array>
 #include <cstring>
 #include <new>
 #include <string>
@@ -69,6 +70,12 @@ Phys make_phys(const cl_lattice* h) {
     p.expand = h->mode == CL_SELF_CONSISTENT ? 1 : 0;
     p.fp32 = h->prec == CL_FP32 ? 1 : 0;
     return p;
+}
+
+// Background last seen on the host (the time-step stability check uses it).
+void note_background(cl_lattice* h, double a, const double* mean) {
+    h->host_a = a;
+    for (int j = 0; j < 2; ++j) h->host_mean[j] = mean ? mean[j] : 0.0;
 }
 
 void drop_graph(cl_lattice* h) {
@@ -144,17 +151,24 @@ PassArgs base_args(cl_lattice* h, int in) {
     return a;
 }
 
+cl::Work handle_work(cl_lattice* h) {
+    return cl::Work{h->partials, h->partials_cap / 2, h->scb, h->obs, h->obs_cap};
+}
+
 // A sequence of passes on the handle's stream.  Each pass runs the scalar
 // step of the one before it at its start; close() launches the step of the
 // last one, which leaves the scalars in h->sc.  Inside the sequence the
-// scalars travel through the two scratch blocks h->scb.
+// scalars travel through the two scratch blocks of the work area, and the
+// partial sums alternate between its two halves.
 struct PassSeq {
     cl_lattice* h;
+    cl::Work w;
     int p = 0;
     PassArgs prev{};
-    explicit PassSeq(cl_lattice* hh) : h(hh) {}
-    double* part(int q) const { return h->partials + q * (h->partials_cap / 2); }
-    const Scal* scal_before(int q) const { return q == 0 ? h->sc : h->scb + (q & 1); }
+    explicit PassSeq(cl_lattice* hh) : h(hh), w(handle_work(hh)) {}
+    PassSeq(cl_lattice* hh, const cl::Work& ww) : h(hh), w(ww) {}
+    double* part(int q) const { return w.partials + q * w.half; }
+    const Scal* scal_before(int q) const { return q == 0 ? h->sc : w.scb + (q & 1); }
     void chain(PassArgs& a) const {
         a.has_prev = 1;
         a.sc_in = scal_before(p - 1);
@@ -175,12 +189,13 @@ struct PassSeq {
     }
     hipError_t launch(PassArgs a) {
         a.partials = part(p & 1);
+        a.obs = w.obs;
         if (p == 0) {
             a.has_prev = 0;
             a.sc_in = h->sc;
         } else {
             chain(a);
-            a.sc_out = h->scb + (p & 1);
+            a.sc_out = w.scb + (p & 1);
         }
         const hipError_t e = cl::launch_pass(a, h->tile, h->prec, h->stream);
         prev = a;
@@ -196,22 +211,23 @@ struct PassSeq {
     }
 };
 
+// Yoshida triple-jump weights of the 4th-order composition (Sect. 4.1):
+// w1 = 1 / (2 - 2^(1/3)), w0 = 1 - 2 w1.
+double yoshida_w1() { return 1.0 / (2.0 - std::cbrt(2.0)); }
+
+// Drift steps per full step, and the size of drift step s in units of dt.
+int substeps_per_step(cl_integrator integ) { return integ == CL_VV4 ? 3 : 1; }
+double substep(cl_integrator integ, int s) {
+    if (integ != CL_VV4) return 1.0;
+    const double w1 = yoshida_w1();
+    return s % 3 == 1 ? 1.0 - 2.0 * w1 : w1;
+}
+
 // Sub-step sizes of n full steps.
 void substeps(cl_integrator integ, double dt, int n, std::vector<double>& h, int& per_step) {
-    h.clear();
-    if (integ == CL_VV4) {
-        const double w1 = 1.0 / (2.0 - std::cbrt(2.0));
-        const double w0 = 1.0 - 2.0 * w1;
-        per_step = 3;
-        for (int i = 0; i < n; ++i) {
-            h.push_back(w1 * dt);
-            h.push_back(w0 * dt);
-            h.push_back(w1 * dt);
-        }
-    } else {
-        per_step = 1;
-        h.assign(n, dt);
-    }
+    per_step = substeps_per_step(integ);
+    h.resize(static_cast<size_t>(n) * per_step);
+    for (size_t s = 0; s < h.size(); ++s) h[s] = substep(integ, static_cast<int>(s)) * dt;
 }
 
 bool is_rk(cl_integrator integ) {
@@ -257,6 +273,154 @@ std::vector<double> rk_abscissae(const std::vector<double>& A, const std::vector
     return c;
 }
 
+// ---------------------------------------------------------------- stability
+// A scheme advances a harmonic mode y'' = -w^2 y of frequency w stably while
+// y = w dt stays below a limit of its own: 2 for leapfrog (the kick-drift-kick
+// matrix has trace 2 - y^2); for the 4th-order Yoshida composition, the y
+// where the trace of the product of its three kick-drift-kick matrices
+// reaches -2 (about 1.5735); for a Runge-Kutta scheme, the end of the
+// interval of the imaginary axis where its stability polynomial
+// R(z) = sum_k b^T A^(k-1) 1 z^k has |R| <= 1 (RK3-3: sqrt 3, RK3-4: 2.823,
+// RK4-5: 3.341, classic RK4: 2 sqrt 2).  The explicit midpoint rule has no
+// such interval (|R(iy)|^2 = 1 + y^4 / 4): it is held to a growth of at most
+// 1 % per step of the fastest mode (y <= 0.532).
+
+// |tr| of the Yoshida product at y (w = 1, step y).
+double vv4_trace(double y) {
+    const double w1 = yoshida_w1(), w0 = 1.0 - 2.0 * w1;
+    double M[2][2] = {{1.0, 0.0}, {0.0, 1.0}};
+    for (double c : {w1, w0, w1}) {
+        const double h = c * y;
+        // kick(h/2) drift(h) kick(h/2) on (f, p)
+        const double K[2][2] = {{1.0 - 0.5 * h * h, h}, {-h * (1.0 - 0.25 * h * h), 1.0 - 0.5 * h * h}};
+        double R[2][2];
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j) R[i][j] = K[i][0] * M[0][j] + K[i][1] * M[1][j];
+        std::memcpy(M, R, sizeof M);
+    }
+    return std::fabs(M[0][0] + M[1][1]);
+}
+
+// |R(iy)| of a stability polynomial with coefficients g[0..s].
+double rk_amplification(const std::vector<double>& g, double y) {
+    double re = 0.0, im = 0.0;
+    double pr = 1.0, pi = 0.0;  // (iy)^k
+    for (double c : g) {
+        re += c * pr;
+        im += c * pi;
+        const double nr = -pi * y, ni = pr * y;
+        pr = nr;
+        pi = ni;
+    }
+    return std::hypot(re, im);
+}
+
+// Stability polynomial of a low-storage scheme: its Butcher tableau is
+// tracked as the coefficients of y_i and d_i in h k_1 .. h k_s.
+std::vector<double> rk_polynomial(cl_integrator integ) {
+    if (integ == CL_RK4_CLASSIC) return {1.0, 1.0, 0.5, 1.0 / 6.0, 1.0 / 24.0};
+    std::vector<double> A, B;
+    rk_coefficients(integ, A, B);
+    const size_t s = A.size();
+    std::vector<std::vector<double>> a(s, std::vector<double>(s, 0.0));
+    std::vector<double> D(s, 0.0), Y(s, 0.0);
+    for (size_t i = 0; i < s; ++i) {
+        a[i] = Y;  // stage i is evaluated at y_(i-1)
+        for (size_t j = 0; j < s; ++j) D[j] *= (i ? A[i] : 0.0);
+        D[i] += 1.0;
+        for (size_t j = 0; j < s; ++j) Y[j] += B[i] * D[j];
+    }
+    // g_0 = 1, g_k = b^T a^(k-1) 1 with b = Y
+    std::vector<double> g{1.0}, v(s, 1.0);
+    for (size_t k = 1; k <= s; ++k) {
+        double dot = 0.0;
+        for (size_t j = 0; j < s; ++j) dot += Y[j] * v[j];
+        g.push_back(dot);
+        std::vector<double> nv(s, 0.0);
+        for (size_t i = 0; i < s; ++i)
+            for (size_t j = 0; j < s; ++j) nv[i] += a[i][j] * v[j];
+        v = nv;
+    }
+    return g;
+}
+
+// First y > 0 where stable(y) fails, by a scan of step 1e-3 and bisection.
+template <typename F>
+double first_failure(F stable) {
+    double lo = 0.0;
+    for (double y = 1e-3; y < 8.0; y += 1e-3) {
+        if (!stable(y)) {
+            double hi = y;
+            for (int it = 0; it < 60; ++it) {
+                const double m = 0.5 * (lo + hi);
+                (stable(m) ? lo : hi) = m;
+            }
+            return lo;
+        }
+        lo = y;
+    }
+    return lo;
+}
+
+double stability_limit(cl_integrator integ) {
+    static const std::array<double, 7> all = [] {
+        std::array<double, 7> L{};
+        L[CL_LEAPFROG] = 2.0;
+        L[CL_VV4] = first_failure([](double y) { return vv4_trace(y) < 2.0; });
+        for (cl_integrator r : {CL_RK2, CL_RK3, CL_RK4, CL_RK34, CL_RK4_CLASSIC}) {
+            const std::vector<double> g = rk_polynomial(r);
+            double y = first_failure([&](double t) { return rk_amplification(g, t) <= 1.0 + 1e-12; });
+            if (y < 0.1) y = first_failure([&](double t) { return rk_amplification(g, t) <= 1.01; });
+            L[r] = y;
+        }
+        return L;
+    }();
+    return all[static_cast<int>(integ)];
+}
+
+// Fastest frequency of the lattice in the kick-drift dynamics
+// f'' = a^(2 alpha - 2) Lap f - a^(2 alpha) V''(f) f (Eq. singletEOM with
+// pi = a^(3 - alpha) f'): the largest Laplacian eigenvalue 4 dim / dx^2 plus
+// the largest effective mass d^2V/df_j^2 at the homogeneous field values last
+// seen on the host (the fluctuations about them are not included).
+double omega_max(const cl_lattice* h) {
+    const double a = h->mode == CL_SELF_CONSISTENT ? h->host_a : 1.0;
+    double m2 = 0.0;
+    for (int j = 0; j < h->nf; ++j) {
+        const double f = h->host_mean[j];
+        double m = h->pot.m2[j] + 3.0 * h->pot.lambda[j] * f * f;
+        if (h->nf == 2) m += h->pot.g2 * h->host_mean[1 - j] * h->host_mean[1 - j];
+        m2 = std::max(m2, m);
+    }
+    const double w2 = 4.0 * h->dim / (h->dx * h->dx) * std::pow(a, 2.0 * h->alpha - 2.0) +
+                      std::pow(a, 2.0 * h->alpha) * m2;
+    return std::sqrt(w2);
+}
+
+const char* integ_name(cl_integrator integ) {
+    switch (integ) {
+        case CL_LEAPFROG: return "leapfrog";
+        case CL_VV4: return "VV4";
+        case CL_RK2: return "RK2";
+        case CL_RK3: return "RK3-3";
+        case CL_RK4: return "RK4-5";
+        case CL_RK34: return "RK3-4";
+        default: return "RK4";
+    }
+}
+
+// CL_OK, or CL_EUNSTABLE with a message if dt exceeds the scheme's limit.
+cl_status check_stability(cl_lattice* h, cl_integrator integ, double dt, const std::string& who) {
+    const double y = omega_max(h) * dt, lim = stability_limit(integ);
+    if (y < lim) return CL_OK;
+    char msg[256];
+    std::snprintf(msg, sizeof msg,
+                  "dt exceeds the stability bound of %s%s: omega_max dt = %.4g >= %.4g (omega_max^2 = 4 d / dx^2 "
+                  "a^(2 alpha - 2) + a^(2 alpha) max V'' at the field means)",
+                  integ_name(integ), who.c_str(), y, lim);
+    return fail(h, CL_EUNSTABLE, msg);
+}
+
 // Passes of n classic RK4 steps (the standard scheme, three auxiliary arrays
 // per degree of freedom): with y0 in buffer A = buf[cur], the stages read
 // Y1 = y0 (A), Y2 (B = buf[cur^1]), Y3 (aux2), Y4 (B) and write Y2 = y0 + k1/2
@@ -264,7 +428,7 @@ std::vector<double> rk_abscissae(const std::vector<double>& A, const std::vector
 // y0 + (k1 + 2 k2 + 2 k3)/6 + k4/6 in place into A, reading y0 only at each
 // thread's own sites; the weighted sum s of the k's lives in aux.  Then a
 // reduction-only pass records the final state, as for the low-storage schemes.
-cl_status issue_rk4_classic_steps(cl_lattice* h, double dt, int n, int cur) {
+cl_status issue_rk4_classic_steps(cl_lattice* h, double dt, int n, int cur, const cl::Work& w) {
     void* A = h->buf[cur];
     void* B = h->buf[cur ^ 1];
     void* X = h->aux2;
@@ -274,7 +438,7 @@ cl_status issue_rk4_classic_steps(cl_lattice* h, double dt, int n, int cur) {
     const double P[4] = {0.0, 0.0, 0.0, 1.0}, Q[4] = {0.5, 0.5, 1.0, 1.0 / 6.0};
     const double R[4] = {0.0, 1.0, 1.0, 0.0}, S[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 0.0};
     const double deta[4] = {0.5, 0.0, 0.5, 0.0};  // time of each output past the input's
-    PassSeq seq(h);
+    PassSeq seq(h, w);
     for (int k = 0; k < n; ++k)
         for (int i = 0; i < 4; ++i) {
             PassArgs r = base_args(h, cur);
@@ -309,13 +473,13 @@ cl_status issue_rk4_classic_steps(cl_lattice* h, double dt, int n, int cur) {
 // Passes of n low-storage Runge-Kutta steps: one stage pass per stage, then
 // a reduction-only pass whose scalar step records the final state.  The
 // scalar step of stage 0 of step k records the end of step k - 1.
-cl_status issue_rk_steps(cl_lattice* h, cl_integrator integ, double dt, int n, int cur) {
-    if (integ == CL_RK4_CLASSIC) return issue_rk4_classic_steps(h, dt, n, cur);
+cl_status issue_rk_steps(cl_lattice* h, cl_integrator integ, double dt, int n, int cur, const cl::Work& w) {
+    if (integ == CL_RK4_CLASSIC) return issue_rk4_classic_steps(h, dt, n, cur, w);
     std::vector<double> A, B;
     rk_coefficients(integ, A, B);
     const std::vector<double> c = rk_abscissae(A, B);
     const int S = static_cast<int>(A.size());
-    PassSeq seq(h);
+    PassSeq seq(h, w);
     for (int k = 0; k < n; ++k)
         for (int i = 0; i < S; ++i) {
             PassArgs r = base_args(h, cur);
@@ -342,33 +506,32 @@ cl_status issue_rk_steps(cl_lattice* h, cl_integrator integ, double dt, int n, i
     return CL_OK;
 }
 
-// Issue the passes of n steps on the handle's stream.  Returns the final
-// buffer index.
-cl_status issue_steps(cl_lattice* h, cl_integrator integ, double dt, int n, int cur) {
-    if (is_rk(integ)) return issue_rk_steps(h, integ, dt, n, cur);
+// Issue the passes of n steps on the handle's stream, with the scratch w.
+cl_status issue_steps(cl_lattice* h, cl_integrator integ, double dt, int n, int cur, const cl::Work& w) {
+    if (is_rk(integ)) return issue_rk_steps(h, integ, dt, n, cur, w);
     // Sub-step sizes in units of dt; every kick and drift step is formed as
     // (coefficient) * dt, exactly as the ensemble kernel forms it per member.
-    std::vector<double> c;
-    int per = 1;
-    substeps(integ, 1.0, n, c, per);
-    const int M = static_cast<int>(c.size());
-    PassSeq seq(h);
+    const int per = substeps_per_step(integ);
+    const int M = n * per;
+    PassSeq seq(h, w);
     // Opening half kick (no drift): pi += h_1/2 F(f, a), a' += h_1/2 a''.
     PassArgs k = base_args(h, cur);
     k.drift = 0;
     k.write_out = 1;
-    k.kt = (0.5 * c[0]) * dt;
+    k.kt = (0.5 * substep(integ, 0)) * dt;
     k.kb = 0.0;
-    k.h_next = c[0] * dt;
+    k.h_next = substep(integ, 0) * dt;
     HIPCHECK(h, seq.launch(k));
     cur ^= 1;
     for (int s = 0; s < M; ++s) {
+        const double cs = substep(integ, s);
+        const double cn = s + 1 < M ? substep(integ, s + 1) : 0.0;
         PassArgs d = base_args(h, cur);
         d.drift = 1;
         d.write_out = 1;
-        d.kb = (0.5 * c[s]) * dt;
-        d.kt = (s + 1 < M ? 0.5 * (c[s] + c[s + 1]) : 0.5 * c[s]) * dt;
-        d.h_next = s + 1 < M ? c[s + 1] * dt : 0.0;
+        d.kb = (0.5 * cs) * dt;
+        d.kt = (s + 1 < M ? 0.5 * (cs + cn) : 0.5 * cs) * dt;
+        d.h_next = s + 1 < M ? cn * dt : 0.0;
         d.rec = ((s + 1) % per == 0) ? (s + 1) / per - 1 : -1;
         HIPCHECK(h, seq.launch(d));
         cur ^= 1;
@@ -423,6 +586,7 @@ cl_status reset_background(cl_lattice* h, const double* mean) {
     st = init_scalars(h, h->a0, b0, 0.0, o.mean);
     if (st) return st;
     h->step = 0;
+    note_background(h, h->a0, o.mean);
     HIPCHECK(h, hipStreamSynchronize(h->stream));
     return CL_OK;
 }
@@ -530,7 +694,60 @@ void free_buffers(cl_lattice* h) {
     }
 }
 
+// Argument checks shared by cl_step and the allocation-free entry point.
+cl_status check_step(cl_lattice* h, cl_integrator integ, double dt, int n) {
+    if (!h) return fail(nullptr, CL_EINVAL, "handle is NULL");
+    if (integ != CL_LEAPFROG && integ != CL_VV4 && !is_rk(integ)) return fail(h, CL_EINVAL, "unknown integrator");
+    if (h->dim != 3 && is_rk(integ))
+        return fail(h, CL_EUNSUPPORTED, "reduced lattices run the symplectic schemes only");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(h, CL_EINVAL, "dt must be positive and finite");
+    if (n < 0) return fail(h, CL_EINVAL, "n must be >= 0");
+    if (n == 0) return CL_OK;
+    return check_stability(h, integ, dt, "");
+}
+
+// After the passes of n steps were issued: the state moved to the other
+// buffer if the number of passes is odd; copy the records, wait, and note
+// the background on the host.
+cl_status finish_step(cl_lattice* h, cl_integrator integ, int n, cl_observables* per_step, const cl::Work& w) {
+    // passes that move the state to the other buffer (the classic RK4 step
+    // ends where it started)
+    const int stages = integ == CL_RK2 ? 2 : integ == CL_RK3 ? 3 : integ == CL_RK34 ? 4 : integ == CL_RK4 ? 5 : 0;
+    const int passes = integ == CL_RK4_CLASSIC ? 0 : is_rk(integ) ? n * stages : 1 + n * substeps_per_step(integ);
+    if (passes % 2) h->cur ^= 1;
+    if (per_step)
+        HIPCHECK(h, hipMemcpyAsync(per_step, w.obs, static_cast<size_t>(n) * sizeof(cl_observables),
+                                   hipMemcpyDeviceToHost, h->stream));
+    Scal s;
+    HIPCHECK(h, hipMemcpyAsync(&s, h->sc, sizeof(Scal), hipMemcpyDeviceToHost, h->stream));
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    h->step += n;
+    note_background(h, s.a, s.mean_f);
+    if (s.nonfinite) return fail(h, CL_EUNSTABLE, "non-finite lattice sums (unstable evolution)");
+    return CL_OK;
+}
+
 }  // namespace
+
+namespace cl {
+
+cl_status set_error(cl_lattice* h, cl_status st, const char* msg) { return fail(h, st, msg); }
+
+cl_status step_in_work(cl_lattice* h, cl_integrator integ, double dt, int n, cl_observables* per_step,
+                       const Work& w) {
+    cl_status st = check_step(h, integ, dt, n);
+    if (st || n == 0) return st;
+    if (is_rk(integ))
+        return fail(h, CL_EUNSUPPORTED, "the allocation-free step runs the symplectic schemes only");
+    if (n > w.obs_cap) return fail(h, CL_EINVAL, "n exceeds the record capacity of the work area");
+    if (static_cast<size_t>(nsums(h->nf)) * h->tile.nblocks() > w.half)
+        return fail(h, CL_EINVAL, "the lattice's tile has more workgroups than the work area holds");
+    st = issue_steps(h, integ, dt, n, h->cur, w);
+    if (st) return st;
+    return finish_step(h, integ, n, per_step, w);
+}
+
+}  // namespace cl
 
 extern "C" {
 
@@ -756,20 +973,14 @@ cl_status cl_set_state(cl_lattice* h, const cl_scalars* in) {
     if (st) return st;
     HIPCHECK(h, hipStreamSynchronize(h->stream));
     h->step = in->step;
+    note_background(h, in->a, s.mean_f);
     return CL_OK;
 }
 
 cl_status cl_step(cl_lattice* h, cl_integrator integ, double dt, int n, cl_observables* per_step) {
-    if (!h) return fail(nullptr, CL_EINVAL, "handle is NULL");
-    if (integ != CL_LEAPFROG && integ != CL_VV4 && !is_rk(integ)) return fail(h, CL_EINVAL, "unknown integrator");
-    if (h->dim != 3 && is_rk(integ))
-        return fail(h, CL_EUNSUPPORTED, "reduced lattices run the symplectic schemes only");
-    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(h, CL_EINVAL, "dt must be positive and finite");
-    if (n < 0) return fail(h, CL_EINVAL, "n must be >= 0");
-    if (n == 0) return CL_OK;
-    if (dt * std::sqrt(12.0) / h->dx >= 2.0)
-        return fail(h, CL_EUNSTABLE, "dt exceeds the Courant bound dt*sqrt(12)/dx < 2");
-    cl_status st = ensure_obs(h, n);
+    cl_status st = check_step(h, integ, dt, n);
+    if (st || n == 0) return st;
+    st = ensure_obs(h, n);
     if (st) return st;
     if (is_rk(integ) && !h->aux) {
         // Runge-Kutta registers of (f, pi): one more state-sized buffer
@@ -788,10 +999,7 @@ cl_status cl_step(cl_lattice* h, cl_integrator integ, double dt, int n, cl_obser
         drop_graph(h);
     }
     const GraphKey key{static_cast<int>(integ), dt, n, h->cur};
-    // passes that move the state to the other buffer (the classic RK4 step
-    // ends where it started)
-    const int stages = integ == CL_RK2 ? 2 : integ == CL_RK3 ? 3 : integ == CL_RK34 ? 4 : integ == CL_RK4 ? 5 : 0;
-    const int passes = integ == CL_RK4_CLASSIC ? 0 : is_rk(integ) ? n * stages : 1 + n * (integ == CL_VV4 ? 3 : 1);
+    const cl::Work w = handle_work(h);
     if (h->use_graph && n > 1) {
         hipGraphExec_t& gx = h->gexec[h->cur];
         if (!(gx && h->gkey[h->cur] == key)) {
@@ -799,7 +1007,7 @@ cl_status cl_step(cl_lattice* h, cl_integrator integ, double dt, int n, cl_obser
             gx = nullptr;
             hipGraph_t g = nullptr;
             HIPCHECK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-            st = issue_steps(h, integ, dt, n, h->cur);
+            st = issue_steps(h, integ, dt, n, h->cur, w);
             hipError_t e = hipStreamEndCapture(h->stream, &g);
             if (st) {
                 if (g) hipGraphDestroy(g);
@@ -816,19 +1024,10 @@ cl_status cl_step(cl_lattice* h, cl_integrator integ, double dt, int n, cl_obser
         }
         HIPCHECK(h, hipGraphLaunch(gx, h->stream));
     } else {
-        st = issue_steps(h, integ, dt, n, h->cur);
+        st = issue_steps(h, integ, dt, n, h->cur, w);
         if (st) return st;
     }
-    if (passes % 2) h->cur ^= 1;
-    if (per_step)
-        HIPCHECK(h, hipMemcpyAsync(per_step, h->obs, static_cast<size_t>(n) * sizeof(cl_observables),
-                                   hipMemcpyDeviceToHost, h->stream));
-    Scal s;
-    HIPCHECK(h, hipMemcpyAsync(&s, h->sc, sizeof(Scal), hipMemcpyDeviceToHost, h->stream));
-    HIPCHECK(h, hipStreamSynchronize(h->stream));
-    h->step += n;
-    if (s.nonfinite) return fail(h, CL_EUNSTABLE, "non-finite lattice sums (unstable evolution)");
-    return CL_OK;
+    return finish_step(h, integ, n, per_step, w);
 }
 
 cl_status cl_read_observables(cl_lattice* h, cl_observables* out) {
@@ -1296,8 +1495,10 @@ cl_status cl_ensemble_set_dt(cl_ensemble* e, int i, double dt) {
     if (!e) return efail(CL_EINVAL, "ensemble is NULL");
     if (i < 0 || i >= static_cast<int>(e->m.size())) return efail(CL_EINVAL, "member index out of range");
     if (!(dt > 0.0) || !std::isfinite(dt)) return efail(CL_EINVAL, "dt must be positive and finite");
-    if (dt * std::sqrt(12.0) / e->m[i]->dx >= 2.0)
-        return efail(CL_EUNSTABLE, "dt exceeds the Courant bound dt*sqrt(12)/dx < 2 of member " + std::to_string(i));
+    // the loosest bound (leapfrog); cl_ensemble_step checks the scheme's own
+    if (!(omega_max(e->m[i]) * dt < stability_limit(CL_LEAPFROG)))
+        return efail(CL_EUNSTABLE, "dt exceeds the leapfrog stability bound omega_max dt < 2 of member " +
+                                       std::to_string(i));
     e->dt[i] = dt;
     return CL_OK;
 }
@@ -1310,8 +1511,13 @@ cl_status cl_ensemble_step(cl_ensemble* e, cl_integrator integ, int n, cl_observ
     if (n < 0) return efail(CL_EINVAL, "n must be >= 0");
     if (n == 0) return CL_OK;
     const int nm = static_cast<int>(e->m.size());
-    for (int i = 0; i < nm; ++i)
+    for (int i = 0; i < nm; ++i) {
         if (!(e->dt[i] > 0.0)) return efail(CL_ESTATE, "dt of member " + std::to_string(i) + " not set");
+        const double y = omega_max(e->m[i]) * e->dt[i];
+        if (!(y < stability_limit(integ)))
+            return efail(CL_EUNSTABLE, "dt of member " + std::to_string(i) + " exceeds the stability bound of " +
+                                           integ_name(integ) + ": omega_max dt = " + std::to_string(y));
+    }
     // members' own queued work finishes first
     for (cl_lattice* h : e->m) EHIP(hipStreamSynchronize(h->stream));
     cl_status ust = ens_upload_table(e, true);
@@ -1388,9 +1594,12 @@ cl_status cl_ensemble_step(cl_ensemble* e, cl_integrator integ, int n, cl_observ
     }
     EHIP(hipMemcpyAsync(dst, e->d_obs, need * sizeof(cl_observables), hipMemcpyDeviceToHost, e->stream));
     EHIP(hipStreamSynchronize(e->stream));
-    for (cl_lattice* h : e->m) {
+    for (int i = 0; i < nm; ++i) {
+        cl_lattice* h = e->m[i];
         if (passes % 2) h->cur ^= 1;
         h->step += n;
+        const cl_observables& last = dst[static_cast<size_t>(n - 1) * nm + i];
+        note_background(h, last.a, last.mean);
     }
     for (size_t k = 0; k < need; ++k)
         if (dst[k].nonfinite) return efail(CL_EUNSTABLE, "non-finite lattice sums in an ensemble member");

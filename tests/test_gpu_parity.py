@@ -332,6 +332,32 @@ def test_errors_and_instability():
     lat.close()
 
 
+def test_scheme_stability_bounds():
+    """Each scheme's own limit on w_max dt, with w_max^2 = 12/dx^2 + a^2 V''
+    at the field means (a = 1, V'' = 3 lambda phi0^2 here): at w_max dt = 1.8
+    leapfrog (limit 2) and RK4-5 (3.34) run, while VV4 (1.5735), RK3-3
+    (sqrt 3) and RK2 (0.532, its growth cap) are refused before any pass."""
+    lib = _lib()
+    w = W.C0.with_(N=16)
+    s0 = oracle_seed(w)
+    wmax = math.sqrt(12.0 / w.dx ** 2 + 3.0)
+    dt = 1.8 / wmax
+    for scheme, ok in (("leapfrog", True), ("rk4", True), ("vv4", False), ("rk3", False), ("rk2", False)):
+        lat = make_lattice(w)
+        lat.set_fields(s0.f, s0.p)
+        if ok:
+            r = lat.step(scheme, dt, 2)
+            assert not np.any(r["nonfinite"])
+        else:
+            with pytest.raises(lib.CLError) as e:
+                lat.step(scheme, dt, 2)
+            assert e.value.status == lib.CL_EUNSTABLE, scheme
+            assert lat.get_state()["step"] == 0
+            # just inside the limit the same scheme runs
+            lat.step(scheme, {"vv4": 1.55, "rk3": 1.7, "rk2": 0.5}[scheme] / wmax, 2)
+        lat.close()
+
+
 def test_attached_torch_buffers_layout_and_results():
     """Borrowed device memory (two torch tensors) gives bitwise the same run
     as library-owned buffers, and holds the documented row-interleaved
