@@ -222,6 +222,25 @@ cl_status cl_set_state(cl_lattice* h, const cl_scalars* in);
  * call returns after it completes. */
 cl_status cl_step(cl_lattice* h, cl_integrator integ, double dt, int n, cl_observables* per_step);
 
+/* cl_step without any allocation, for callers that cannot allocate memory
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The passes and results are those of cl_step; the passes are
+ * issued directly on the handle's stream (no graph is built), and their
+ * scratch -- the workgroup partial sums, the two scalar blocks that carry
+ * the background between passes and the per-step record ring -- lives in a
+ * fixed device array of the library (about 1.2 MB, held by every device the
+ * library runs on until the process ends) instead of buffers the handle
+ * allocates on first use.  Its address on a device is looked up on the
+ * first call on that device.  Limits: n <= 4096 steps per call (CL_EINVAL
+ * beyond), integrators CL_LEAPFROG and CL_VV4 (the Runge-Kutta schemes need
+ * state-sized registers: CL_EUNSUPPORTED).  Every call on one device shares
+ * that array and leaves it holding its own last contents (nothing in it is
+ * read before it is written within a call), so calls that overlap in time on
+ * one device -- from several threads, or on several streams -- race and
+ * must not be issued.  On success nothing is allocated, host or device; a
+ * failure stores its message in the handle as every call does. */
+cl_status cl_step_noalloc(cl_lattice* h, cl_integrator integ, double dt, int n, cl_observables* per_step);
+
 /* Observables of the current state (one reduction pass over the lattice). */
 cl_status cl_read_observables(cl_lattice* h, cl_observables* out);
 

@@ -95,6 +95,7 @@ _SIGS = {
     "cl_get_state": (C.c_int, [_P, C.POINTER(cl_scalars)]),
     "cl_set_state": (C.c_int, [_P, C.POINTER(cl_scalars)]),
     "cl_step": (C.c_int, [_P, C.c_int, C.c_double, C.c_int, _P]),
+    "cl_step_noalloc": (C.c_int, [_P, C.c_int, C.c_double, C.c_int, _P]),
     "cl_read_observables": (C.c_int, [_P, _P]),
     "cl_get_tile": (C.c_int, [_P, C.POINTER(cl_tile)]),
     "cl_set_tile": (C.c_int, [_P, C.POINTER(cl_tile)]),
@@ -239,6 +240,12 @@ class Lattice:
         out = np.zeros(max(n, 0), dtype=OBS_DTYPE) if record else None
         ptr = _P(out.ctypes.data) if record and n > 0 else None
         _check(lib.cl_step(self.h, INTEGRATORS[integrator], float(dt), int(n), ptr), self.h)
+        return out
+
+    def step_noalloc(self, integrator: str, dt: float, n: int, record: bool = True):
+        out = np.zeros(max(n, 0), dtype=OBS_DTYPE) if record else None
+        ptr = _P(out.ctypes.data) if record and n > 0 else None
+        _check(lib.cl_step_noalloc(self.h, INTEGRATORS[integrator], float(dt), int(n), ptr), self.h)
         return out
 
     def get_tile(self) -> dict:
