@@ -88,10 +88,40 @@ cl_status cl_surrogate_set_params(cl_surrogate* s, const float* theta);
 cl_status cl_surrogate_forward(cl_surrogate* s, int N, const float* x, float* y);
 
 /* Mean-squared error of the network on (x, t) over every output element and
- * its gradient with respect to all parameters (layout above).  N a power of
- * two >= 32 (as for every training call). */
+ * its gradient with respect to all parameters (layout above); if grad_x is
+ * not NULL it receives the gradient with respect to the input x (c_in
+ * channels, the layout of x).  N a power of two >= 32 (as for every
+ * training call).  Backward pass: output gradient and the GELU-scaled layer
+ * gradients rounded to BF16, weight gradients as FP32 sums over sites of
+ * their products with the BF16 layer inputs, input gradients as FP32
+ * convolutions with the flipped, transposed BF16 weights. */
 cl_status cl_surrogate_loss_grad(cl_surrogate* s, int N, const float* x, const float* t, double* loss,
-                                 float* grad);
+                                 float* grad, float* grad_x);
+
+/* One Adam step (beta = 0.9, 0.999, eps = 1e-8, bias-corrected with the
+ * handle's step count, which set_params resets) of the FP32 master weights
+ * with a caller-supplied gradient (host FP32, parameter layout) and step
+ * size lr, in FP32 on the device; the BF16 copies the kernels use are
+ * refreshed.  With cl_surrogate_loss_grad it makes a training loop of the
+ * caller's own -- for instance one that all-reduces the gradients of
+ * several devices before the step. */
+cl_status cl_surrogate_apply_grad(cl_surrogate* s, const float* grad, double lr);
+
+/* Normalisation of the network's inputs and outputs: the fluctuation of
+ * field channel c about its volume mean enters divided by in_scale[c], the
+ * output times out_scale[c] is the increment of that fluctuation over one
+ * jump; broadcast feature k enters as (value - extra_mean[k]) / extra_std[k].
+ * Fixed from the training pairs by the first cl_surrogate_train, saved and
+ * loaded with the parameters, or set here (scales and spreads > 0). */
+typedef struct {
+    double in_scale[4];
+    double out_scale[4];
+    double extra_mean[4];
+    double extra_std[4];
+} cl_surrogate_norm;
+
+cl_status cl_surrogate_get_normalisation(const cl_surrogate* s, cl_surrogate_norm* out);
+cl_status cl_surrogate_set_normalisation(cl_surrogate* s, const cl_surrogate_norm* in);
 
 /* Training data: pairs (state, state jump_steps later) of lattices of size
  * N (a power of two >= 32), recorded on the device from lattice handles (FP32
@@ -112,14 +142,19 @@ cl_status cl_surrogate_load(cl_surrogate* s, const char* path);
 /* Advance the lattice by n_jumps applications of the network, each standing
  * for jump_steps steps of size dt.  One jump: snapshot the state; the network
  * predicts the fluctuation increment; the homogeneous modes and (a, a') are
- * advanced by the FP64 equations of motion over the jump (predictor, with the
- * fluctuations' energy redshifting as radiation); then (a, a') are
- * re-integrated with the volume sums <pi^2>, <(grad f)^2>, <V> interpolated
- * linearly between the start and the predicted endpoint (corrector; the sums
- * do not depend on a, so one pass is converged).  If the Hubble-constraint
- * residual at the endpoint exceeds `threshold` (or any sum is non-finite) the
- * jump is undone and the integrator `fallback` (CL_LEAPFROG or CL_VV4) runs
- * jump_steps steps instead.  per_jump (nullable) receives one record per jump. */
+ * advanced over the jump by the FP64 equations of motion of a uniform
+ * lattice with the integrator's sub-step pattern (predictor: force and
+ * potential averaged over Gaussian fluctuations of the start variances, the
+ * rest of the fluctuations' energy redshifting as radiation); the new state
+ * is the predicted means plus the old fluctuations plus the increment; then
+ * (a, a') are re-integrated from the start (corrector) with rho and p from the
+ * a-independent volume sums <pi^2>/2, <(grad f)^2>/2, <V>, split into their
+ * homogeneous part along the predictor's trajectory and the fluctuations'
+ * share, which moves linearly from its start value to that of the new state.
+ * If the Hubble-constraint residual at the endpoint exceeds `threshold` (or
+ * any sum is non-finite) the jump is undone and the integrator `fallback`
+ * (CL_LEAPFROG or CL_VV4) runs jump_steps steps instead.  per_jump (nullable)
+ * receives one record per jump. */
 cl_status cl_surrogate_advance(cl_lattice* h, cl_surrogate* s, cl_integrator fallback, double dt, int n_jumps,
                                double threshold, cl_observables* per_jump, cl_surrogate_report* rep);
 

@@ -65,6 +65,11 @@ class cl_train_report(C.Structure):
                 ("holdout_loss", C.c_double), ("holdout_zero", C.c_double), ("seconds", C.c_double)]
 
 
+class cl_surrogate_norm(C.Structure):
+    _fields_ = [("in_scale", C.c_double * 4), ("out_scale", C.c_double * 4), ("extra_mean", C.c_double * 4),
+                ("extra_std", C.c_double * 4)]
+
+
 class cl_surrogate_report(C.Structure):
     _fields_ = [("jumps", C.c_int), ("fallbacks", C.c_int), ("max_residual", C.c_double), ("seconds", C.c_double),
                 ("net_seconds", C.c_double)]
@@ -115,7 +120,10 @@ _SIGS = {
     "cl_surrogate_set_params": (C.c_int, [_P, C.POINTER(C.c_float)]),
     "cl_surrogate_forward": (C.c_int, [_P, C.c_int, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
     "cl_surrogate_loss_grad": (C.c_int, [_P, C.c_int, C.POINTER(C.c_float), C.POINTER(C.c_float),
-                                         C.POINTER(C.c_double), C.POINTER(C.c_float)]),
+                                         C.POINTER(C.c_double), C.POINTER(C.c_float), C.POINTER(C.c_float)]),
+    "cl_surrogate_apply_grad": (C.c_int, [_P, C.POINTER(C.c_float), C.c_double]),
+    "cl_surrogate_get_normalisation": (C.c_int, [_P, C.POINTER(cl_surrogate_norm)]),
+    "cl_surrogate_set_normalisation": (C.c_int, [_P, C.POINTER(cl_surrogate_norm)]),
     "cl_surrogate_dataset_reserve": (C.c_int, [_P, C.c_int, C.c_int]),
     "cl_surrogate_record_input": (C.c_int, [_P, _P]),
     "cl_surrogate_record_target": (C.c_int, [_P, _P]),
@@ -342,13 +350,33 @@ class Surrogate:
         _scheck(lib.cl_surrogate_forward(self.s, N, _fptr(x), _fptr(y)))
         return y
 
-    def loss_grad(self, x, t):
+    def loss_grad(self, x, t, input_grad: bool = False):
+        """(loss, parameter gradient) -- and the input gradient with input_grad."""
         x = np.ascontiguousarray(x, dtype=np.float32)
         t = np.ascontiguousarray(t, dtype=np.float32)
         loss = C.c_double()
         g = np.empty(self.num_params(), dtype=np.float32)
-        _scheck(lib.cl_surrogate_loss_grad(self.s, x.shape[-1], _fptr(x), _fptr(t), C.byref(loss), _fptr(g)))
-        return loss.value, g
+        gx = np.empty_like(x) if input_grad else None
+        _scheck(lib.cl_surrogate_loss_grad(self.s, x.shape[-1], _fptr(x), _fptr(t), C.byref(loss), _fptr(g),
+                                           _fptr(gx) if input_grad else None))
+        return (loss.value, g, gx) if input_grad else (loss.value, g)
+
+    def apply_grad(self, grad, lr: float):
+        grad = np.ascontiguousarray(grad, dtype=np.float32)
+        _scheck(lib.cl_surrogate_apply_grad(self.s, _fptr(grad), float(lr)))
+
+    def get_normalisation(self) -> dict:
+        n = cl_surrogate_norm()
+        _scheck(lib.cl_surrogate_get_normalisation(self.s, C.byref(n)))
+        return {k: list(getattr(n, k)) for k, _ in cl_surrogate_norm._fields_}
+
+    def set_normalisation(self, in_scale, out_scale, extra_mean=(0.0,) * 4, extra_std=(1.0,) * 4):
+        n = cl_surrogate_norm()
+        for k, v in (("in_scale", in_scale), ("out_scale", out_scale), ("extra_mean", extra_mean),
+                     ("extra_std", extra_std)):
+            vals = list(v) + [1.0 if k != "extra_mean" else 0.0] * (4 - len(v))
+            setattr(n, k, (C.c_double * 4)(*vals))
+        _scheck(lib.cl_surrogate_set_normalisation(self.s, C.byref(n)))
 
     def dataset_reserve(self, N: int, max_pairs: int):
         _scheck(lib.cl_surrogate_dataset_reserve(self.s, int(N), int(max_pairs)))

@@ -211,8 +211,10 @@ cl_status forward(cl_surrogate* s, int N, bool training) {
 
 int ystride(const cl_surrogate* s) { return 4 * ((s->L.back().cout + 3) / 4); }
 
-// MSE and gradient of every parameter into s->grad; returns the loss.
-cl_status loss_and_backward(cl_surrogate* s, int N, double* loss) {
+// MSE and gradient of every parameter into s->grad; returns the loss.  With
+// input_grad the gradient with respect to the network input is left in s->dA
+// (FP32 [site][32], the first c_in channels).
+cl_status loss_and_backward(cl_surrogate* s, int N, double* loss, bool input_grad = false) {
     const int nl = static_cast<int>(s->L.size());
     const size_t n3 = static_cast<size_t>(N) * N * N;
     const int co = s->L.back().cout;
@@ -251,7 +253,7 @@ cl_status loss_and_backward(cl_surrogate* s, int N, double* loss) {
         r.gW = s->grad + ly.w_off;
         r.gb = s->grad + ly.b_off;
         SHIP(cl::sg::launch_wgrad_reduce(r, s->stream));
-        if (l > 0) {
+        if (l > 0 || input_grad) {
             // input gradient: a convolution of dz with the flipped, transposed weights
             ConvArgs a{};
             a.in = dz;
@@ -276,6 +278,21 @@ cl_status loss_and_backward(cl_surrogate* s, int N, double* loss) {
     for (double x : lp) sum += x;
     *loss = sum / (static_cast<double>(n3) * co);
     return CL_OK;
+}
+
+// One Adam step (Kingma and Ba) of the FP32 master weights with the gradient
+// in s->grad, bias-corrected with the handle's step count, then the BF16
+// copies are refreshed.
+cl_status adam_step(cl_surrogate* s, double lr) {
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    s->adam_t += 1;
+    // bias corrections 1 - beta^t formed in FP64 from the FP32 betas and
+    // rounded once: in FP32, 1 - beta2^t cancels to a few significant bits
+    const float c1 = static_cast<float>(1.0 - std::pow(static_cast<double>(b1), s->adam_t));
+    const float c2 = static_cast<float>(1.0 - std::pow(static_cast<double>(b2), s->adam_t));
+    SHIP(cl::sg::launch_adam(s->theta, s->grad, s->m, s->v, static_cast<int>(s->nparams), static_cast<float>(lr), b1,
+                             b2, eps, c1, c2, s->stream));
+    return prepare(s);
 }
 
 bool valid_net_N(int N) { return N >= 16 && (N & (N - 1)) == 0; }
@@ -322,18 +339,29 @@ double hom_V(const cl_lattice* h, const double* f, const double* var) {
     return V;
 }
 
+// Homogeneous volume sums at one kick of a': (sum_j pbar_j^2 / 2, Hartree
+// average of V).
+struct HomSums {
+    double K, V;
+};
+
 // Advance (fbar, pbar, a, b) over n steps of dt with the integrator's
 // sub-step pattern; the fluctuations' kinetic + gradient energy rides along
-// as radiation, rho_r ~ a^-4, p_r = rho_r / 3.
+// as radiation, rho_r ~ a^-4, p_r = rho_r / 3.  The homogeneous sums at
+// every kick of b are appended to `hom` (for the corrector).
 void advance_homogeneous(const cl_lattice* h, cl_integrator integ, double dt, int n, double* f, double* pm, double& a,
-                         double& b, const double* var, double rho_r0, double a_ref) {
+                         double& b, const double* var, double rho_r0, double a_ref, std::vector<HomSums>& hom) {
     const double al = h->alpha, mp = h->mp;
     const bool expand = h->mode == CL_SELF_CONSISTENT;
     auto accel = [&](double aa) {
         if (!expand) return 0.0;
-        double K = 0.0;
-        for (int j = 0; j < h->nf; ++j) K += pm[j] * pm[j] / (2.0 * std::pow(aa, 6.0));
+        double K = 0.0, SK = 0.0;
+        for (int j = 0; j < h->nf; ++j) {
+            K += pm[j] * pm[j] / (2.0 * std::pow(aa, 6.0));
+            SK += 0.5 * pm[j] * pm[j];
+        }
         const double V = hom_V(h, f, var);
+        hom.push_back({SK, V});
         const double rr = rho_r0 * std::pow(a_ref / aa, 4.0);
         const double rho = K + V + rr, pr = K - V + rr / 3.0;
         return std::pow(aa, 2.0 * al + 1.0) * ((2.0 * al - 1.0) * rho - 3.0 * pr) / (6.0 * mp * mp);
@@ -344,8 +372,11 @@ void advance_homogeneous(const cl_lattice* h, cl_integrator integ, double dt, in
         for (int j = 0; j < h->nf; ++j) pm[j] -= hh * std::pow(aa, 3.0 + al) * dv[j];
     };
     auto vv2 = [&](double hh) {
+        // the scale-factor half kick takes the energies at the synchronised
+        // momenta (before the field half kick), as the lattice step does
+        const double A0 = accel(a);
         kick(0.5 * hh, a);
-        b += 0.5 * hh * accel(a);
+        b += 0.5 * hh * A0;
         const double an = expand ? a + hh * b : a;
         const double abar = 0.5 * (a + an);
         for (int j = 0; j < h->nf; ++j) f[j] += hh * std::pow(abar, al - 3.0) * pm[j];
@@ -366,19 +397,26 @@ void advance_homogeneous(const cl_lattice* h, cl_integrator integ, double dt, in
 }
 
 // Corrector for the background over a jump: (a, b) re-integrated with the
-// integrator's sub-step pattern while the a-independent volume sums
-// S = (<pi^2>/2, <(grad f)^2>/2, <V>) move linearly in time from their values
-// at the start (S0) to those of the predicted endpoint (S1); rho and p follow
-// from S at each kick (K = S_K/a^6, G = S_G/a^2; Eqs. Friedmann1, rhoLocal).
+// integrator's sub-step pattern, with rho and p at each kick from the
+// a-independent volume sums S = (<pi^2>/2, <(grad f)^2>/2, <V>)
+// (K = S_K/a^6, G = S_G/a^2; Eqs. Friedmann1, rhoLocal).  S is the
+// homogeneous part along the predictor's trajectory (hom, one entry per kick
+// in the same order) plus the fluctuations' share, which moves linearly in
+// time from its value at the start (S0 - hom.front()) to that of the
+// predicted endpoint (S1 - hom.back()).
 void correct_background(const cl_lattice* h, cl_integrator integ, double dt, int n, const double* S0,
-                        const double* S1, double& a, double& b) {
-    if (h->mode != CL_SELF_CONSISTENT) return;
+                        const double* S1, const std::vector<HomSums>& hom, double& a, double& b) {
+    if (h->mode != CL_SELF_CONSISTENT || hom.empty()) return;
     const double al = h->alpha, mp = h->mp, T = dt * n;
+    const double R0[3] = {S0[0] - hom.front().K, S0[1], S0[2] - hom.front().V};
+    const double R1[3] = {S1[0] - hom.back().K, S1[1], S1[2] - hom.back().V};
+    size_t k = 0;
     double tau = 0.0;
     auto accel = [&](double aa, double t) {
         const double w = T > 0 ? t / T : 0.0;
-        const double SK = S0[0] + w * (S1[0] - S0[0]), SG = S0[1] + w * (S1[1] - S0[1]),
-                     SV = S0[2] + w * (S1[2] - S0[2]);
+        const HomSums& H = hom[std::min(k++, hom.size() - 1)];
+        const double SK = H.K + R0[0] + w * (R1[0] - R0[0]), SG = R0[1] + w * (R1[1] - R0[1]),
+                     SV = H.V + R0[2] + w * (R1[2] - R0[2]);
         const double K = SK / std::pow(aa, 6.0), G = SG / (aa * aa);
         const double rho = K + G + SV, pr = K - G / 3.0 - SV;
         return std::pow(aa, 2.0 * al + 1.0) * ((2.0 * al - 1.0) * rho - 3.0 * pr) / (6.0 * mp * mp);
@@ -556,7 +594,8 @@ cl_status cl_surrogate_forward(cl_surrogate* s, int N, const float* x, float* y)
     return CL_OK;
 }
 
-cl_status cl_surrogate_loss_grad(cl_surrogate* s, int N, const float* x, const float* t, double* loss, float* grad) {
+cl_status cl_surrogate_loss_grad(cl_surrogate* s, int N, const float* x, const float* t, double* loss, float* grad,
+                                 float* grad_x) {
     if (!s || !x || !t || !loss || !grad) return sfail(CL_EINVAL, "NULL argument");
     if (!valid_train_N(N)) return sfail(CL_EINVAL, "N must be a power of two >= 32");
     cl_status st = ensure_bufs(s, N, true);
@@ -568,10 +607,59 @@ cl_status cl_surrogate_loss_grad(cl_surrogate* s, int N, const float* x, const f
     SHIP(hipMemcpyAsync(s->target, t, n3 * co * sizeof(float), hipMemcpyHostToDevice, s->stream));
     st = forward(s, N, true);
     if (st) return st;
-    st = loss_and_backward(s, N, loss);
+    st = loss_and_backward(s, N, loss, grad_x != nullptr);
     if (st) return st;
     SHIP(hipMemcpyAsync(grad, s->grad, s->nparams * sizeof(float), hipMemcpyDeviceToHost, s->stream));
+    std::vector<float> gx;
+    if (grad_x) {
+        gx.resize(n3 * 32);
+        SHIP(hipMemcpyAsync(gx.data(), s->dA, gx.size() * 4, hipMemcpyDeviceToHost, s->stream));
+    }
     SHIP(hipStreamSynchronize(s->stream));
+    if (grad_x)
+        for (int c = 0; c < cin0(s); ++c)
+            for (size_t i = 0; i < n3; ++i) grad_x[c * n3 + i] = gx[i * 32 + c];
+    return CL_OK;
+}
+
+cl_status cl_surrogate_apply_grad(cl_surrogate* s, const float* grad, double lr) {
+    if (!s || !grad) return sfail(CL_EINVAL, "NULL argument");
+    if (!(lr >= 0.0) || !std::isfinite(lr)) return sfail(CL_EINVAL, "lr must be finite and >= 0");
+    for (int64_t i = 0; i < s->nparams; ++i)
+        if (!std::isfinite(grad[i])) return sfail(CL_EINVAL, "non-finite gradient");
+    SHIP(hipMemcpyAsync(s->grad, grad, s->nparams * sizeof(float), hipMemcpyHostToDevice, s->stream));
+    cl_status st = adam_step(s, lr);
+    if (st) return st;
+    SHIP(hipStreamSynchronize(s->stream));
+    return CL_OK;
+}
+
+cl_status cl_surrogate_get_normalisation(const cl_surrogate* s, cl_surrogate_norm* out) {
+    if (!s || !out) return sfail(CL_EINVAL, "NULL argument");
+    if (!s->scaled) return sfail(CL_ESTATE, "no normalisation fixed yet");
+    for (int k = 0; k < 4; ++k) {
+        out->in_scale[k] = s->in_scale[k];
+        out->out_scale[k] = s->out_scale[k];
+        out->extra_mean[k] = s->ex_mean[k];
+        out->extra_std[k] = s->ex_std[k];
+    }
+    return CL_OK;
+}
+
+cl_status cl_surrogate_set_normalisation(cl_surrogate* s, const cl_surrogate_norm* in) {
+    if (!s || !in) return sfail(CL_EINVAL, "NULL argument");
+    for (int k = 0; k < 4; ++k)
+        if (!(in->in_scale[k] > 0.0) || !(in->out_scale[k] > 0.0) || !(in->extra_std[k] > 0.0) ||
+            !std::isfinite(in->in_scale[k]) || !std::isfinite(in->out_scale[k]) || !std::isfinite(in->extra_std[k]) ||
+            !std::isfinite(in->extra_mean[k]))
+            return sfail(CL_EINVAL, "scales must be positive and finite, means finite");
+    for (int k = 0; k < 4; ++k) {
+        s->in_scale[k] = in->in_scale[k];
+        s->out_scale[k] = in->out_scale[k];
+        s->ex_mean[k] = in->extra_mean[k];
+        s->ex_std[k] = in->extra_std[k];
+    }
+    s->scaled = true;
     return CL_OK;
 }
 
@@ -723,7 +811,6 @@ cl_status cl_surrogate_train(cl_surrogate* s, const cl_train_cfg* cfg, cl_train_
     const int total = cfg->epochs * ntrain;
     double first = -1.0, epoch_sum = 0.0;
     int step = 0;
-    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
     for (int ep = 0; ep < cfg->epochs; ++ep) {
         std::shuffle(order.begin(), order.end(), rng);
         epoch_sum = 0.0;
@@ -739,12 +826,7 @@ cl_status cl_surrogate_train(cl_surrogate* s, const cl_train_cfg* cfg, cl_train_
             if (first < 0) first = loss;
             epoch_sum += loss;
             const double lr = cfg->lr_final + 0.5 * (cfg->lr - cfg->lr_final) * (1.0 + std::cos(M_PI * step / total));
-            s->adam_t += 1;
-            const float c1 = 1.0f - std::pow(b1, static_cast<float>(s->adam_t));
-            const float c2 = 1.0f - std::pow(b2, static_cast<float>(s->adam_t));
-            SHIP(cl::sg::launch_adam(s->theta, s->grad, s->m, s->v, static_cast<int>(s->nparams), static_cast<float>(lr),
-                                     b1, b2, eps, c1, c2, s->stream));
-            st = prepare(s);
+            st = adam_step(s, lr);
             if (st) return st;
         }
     }
@@ -905,7 +987,8 @@ cl_status cl_surrogate_advance(cl_lattice* h, cl_surrogate* s, cl_integrator fal
         const double rho_lat = o.EK[0] + o.EK[1] + o.EG[0] + o.EG[1] + o.EV;
         const double rho_r0 = std::max(0.0, rho_lat - rho_hom_K - hom_V(h, f, var));
         double a = bg.a, b = bg.b;
-        advance_homogeneous(h, fallback, dt, K, f, pm, a, b, var, rho_r0, bg.a);
+        std::vector<HomSums> hom;
+        advance_homogeneous(h, fallback, dt, K, f, pm, a, b, var, rho_r0, bg.a, hom);
         cl::sg::UnpackArgs ua{};
         ua.state = h->buf[h->cur];
         ua.N = N;
@@ -940,7 +1023,7 @@ cl_status cl_surrogate_advance(cl_lattice* h, cl_surrogate* s, cl_integrator fal
             volume_sums(after, S1);
             a = bg.a;
             b = bg.b;
-            correct_background(h, fallback, dt, K, S0, S1, a, b);
+            correct_background(h, fallback, dt, K, S0, S1, hom, a, b);
             ok = std::isfinite(a) && std::isfinite(b) && a > 0.0;
             if (ok) {
                 const cl_scalars corr{a, b, bg.eta + K * dt, bg.step + K};
