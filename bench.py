@@ -519,6 +519,36 @@ def spectrum_run(w, reps=5):
             "hbm_frac": alg / sec / 1e9 / HBM_PEAK_GBS, "alg_bytes": alg}
 
 
+def cpu_model() -> str:
+    """CPU model name of the host (from /proc/cpuinfo)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def c3_run(warmup=50, steps=200, tune=True):
+    """The 1024^3 two-field FP32 leapfrog workload (1.07e9 sites, 17.2 GB of
+    state): library seed, autotuned tile, `warmup` untimed steps, then `steps`
+    timed steps in one call, with the roofline of its fused pass."""
+    w = W.C3
+    r, sec, ms, dk, calls, tile = timed_run(w, "fp32", steps, warmup, steps, tune)
+    alg = dk * bytes_per_site("fp32", w.n_fields) * w.sites + calls * kpass_bytes_per_site("fp32", 2) * w.sites
+    launches = dk + calls
+    avg_ms = ms / launches
+    achieved = alg / launches / (avg_ms * 1e-3) / 1e9
+    return {"workload": w.name, "N": w.N, "k_ir": w.k_ir, "integrator": w.integrator, "dt": w.dt,
+            "warmup": warmup, "steps": steps, "tile": tile, "site_updates_per_s": w.sites * steps / sec,
+            "ms_per_step": 1e3 * sec / steps, "finite": not bool(np.any(r["nonfinite"])),
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(w.name, tile),
+                         "kernel": "lattice_pass<float,2>", "avg_launch_us": avg_ms * 1e3,
+                         "alg_bytes_per_launch": alg / launches}}
+
+
 def oracle_worker(seed: int, start_at: float):
     """One process of the all-cores oracle baseline: seed the 256^3
     workload, wait for the common start time, time one full step, print it."""
@@ -573,8 +603,8 @@ def cpu_baseline(w, steps=1):
     dt = time.perf_counter() - t0
     return {"value": w.sites * steps / dt, "unit": "site-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"{steps} full {w.integrator} step(s) of the {w.N}^3 {w.n_fields}-field workload "
-                      f"in FP64 numpy on one host core ({platform.processor() or platform.machine()}, "
-                      f"{os.cpu_count()} logical CPUs visible), {dt:.1f} s"}
+                      f"in FP64 numpy on one host core ({cpu_model()}, "
+                      f"{os.cpu_count()} logical CPUs visible), {dt:.1f} s", "cpu_model": cpu_model()}
 
 
 def main():
@@ -599,6 +629,7 @@ def main():
     ap.add_argument("--sg-forward-profile", action="store_true",
                     help="only run surrogate forward passes at 256^3 (for a kernel profile) and print their figures")
     ap.add_argument("--cpu-procs", type=int, default=16, help="processes of the all-cores oracle baseline (0: skip)")
+    ap.add_argument("--no-c3", action="store_true", help="skip the 1024^3 leapfrog leg of the default run")
     ap.add_argument("--workload", choices=["c1", "c3"], default="c1",
                     help="c1: 256^3 two-field VV4 (default); c3: 1024^3 two-field leapfrog")
     args = ap.parse_args()
@@ -665,6 +696,9 @@ def main():
             forms["rk4_fp32"] = rk_run(w, 1000, r64, tile32)
             progress("standard rk4 form")
             forms["rk4_classic_fp32"] = rk_run(w, 1000, r64, tile32, scheme="rk4_classic")
+    if args.workload == "c1" and not args.no_c3:
+        progress("1024^3 two-field leapfrog form (50 warm-up + 200 timed steps)")
+        forms["c3_1024"] = c3_run()
     if args.workload == "c1":
         progress("power spectrum form")
         forms["spectrum"] = spectrum_run(w)

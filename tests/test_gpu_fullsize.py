@@ -198,3 +198,51 @@ def test_config3_fullsize_periodic_images():
     f = np.stack([host[:, :, j, :] for j in range(nf)])
     p = np.stack([host[:, :, nf + j, :] for j in range(nf)])
     check_fields(f, p, s, w, steps, "leapfrog", recs)
+
+
+def linear_regime_max_dev(r32, r64, nf):
+    """Largest relative deviation of the FP32 run's volume averages from the
+    FP64 run's over the linear regime -- the steps while every field's
+    variance stays within 1e4 of its initial value.  a, H, EG and var are
+    taken relative to themselves; EK and EV, which pass through zero as the
+    homogeneous field oscillates, relative to rho of the same step; the mean
+    of the field whose homogeneous value is zero relative to its spread."""
+    v0 = r64["var"][0, :nf]
+    lin = np.all(r64["var"][:, :nf] <= 1e4 * v0, axis=1)
+    end = int(np.argmin(lin)) if not np.all(lin) else len(lin)
+    rho = r64["EK"][:end, :nf].sum(1) + r64["EG"][:end, :nf].sum(1) + r64["EV"][:end]
+    dev = {}
+    for k in ("a", "H", "EV"):
+        scale = rho if k == "EV" else np.abs(r64[k][:end])
+        dev[k] = float(np.max(np.abs(r32[k][:end] - r64[k][:end]) / scale))
+    for j in range(nf):
+        for k in ("EK", "EG", "var"):
+            scale = rho if k == "EK" else np.abs(r64[k][:end, j])
+            dev[f"{k}{j}"] = float(np.max(np.abs(r32[k][:end, j] - r64[k][:end, j]) / scale))
+        spread = np.sqrt(np.max(r64["var"][:end, j]))
+        scale = max(float(np.max(np.abs(r64["mean"][:end, j]))), spread)
+        dev[f"mean{j}"] = float(np.max(np.abs(r32["mean"][:end, j] - r64["mean"][:end, j])) / scale)
+    return end, dev
+
+
+def test_config1_full_length_fp32_vs_fp64():
+    """The 256^3 two-field workload at its stated length: 5000 VV4 steps
+    with FP32 fields and again in all-FP64, both from the library seed, in
+    calls of 500 steps; the FP32 volume averages stay within 1e-4 of the
+    FP64 run's through the linear regime.  (The FP64 form itself is tied to
+    the oracle at 1e-11 on shorter runs.)"""
+    w = W.C1
+    recs = {}
+    for prec in ("fp32", "fp64"):
+        lat = make_lattice(w, precision=prec)
+        lat.seed(w.seed, w.fbar[:2], w.pbar[:2], w.cutoff_modes, w.amp)
+        t = time.time()
+        recs[prec] = np.concatenate([lat.step("vv4", w.dt, 500) for _ in range(w.steps // 500)])
+        say(f"{prec}: {w.steps} vv4 steps 256^3 in {time.time() - t:.1f} s, a = {recs[prec]['a'][-1]:.4f}")
+        lat.close()
+        assert len(recs[prec]) == w.steps
+        assert not np.any(recs[prec]["nonfinite"])
+    end, dev = linear_regime_max_dev(recs["fp32"], recs["fp64"], 2)
+    say(f"linear regime: {end} of {w.steps} steps; deviations {dev}")
+    assert end >= 1000
+    assert max(dev.values()) <= 1e-4, dev
