@@ -244,6 +244,48 @@ cl_status cl_step_noalloc(cl_lattice* h, cl_integrator integ, double dt, int n, 
 /* Observables of the current state (one reduction pass over the lattice). */
 cl_status cl_read_observables(cl_lattice* h, cl_observables* out);
 
+/* Gravitational waves (Sect. 2.2 Eq. EoMGWs, Sect. 4.2): with on != 0 the
+ * state also carries the five components v_11, v_12, v_13, v_22, v_23 of a
+ * traceless tensor (v_33 = -v_11 - v_22) and their momenta
+ * u = a^(3-alpha) v', starting at zero.  Each step advances them with the
+ * fields' own kick-drift scheme: drift v' = a^(alpha-3) u, kick
+ * u' = a^(1+alpha) (Lap v + (2/m_p^2) S), where S is the traceless part of the
+ * fields' anisotropic stress (Eq. anitensor) evaluated on the lattice as the
+ * sum over fields of [D+_i f D+_j f + D-_i f D-_j f] / (2 dx^2) (forward and
+ * backward differences) at the time level of the kick.  The physical waves
+ * are the transverse-traceless projection of v in Fourier space
+ * (cl_gw_spectrum).  The fields, momenta and background are kept; a step
+ * then moves 2 (n_fields + 5) arrays per site (FP32: 16 (n_fields + 5) bytes
+ * per site and pass).  Only the symplectic schemes run with the tensor;
+ * ensembles and the surrogate take lattices without it.  Needs
+ * library-owned buffers (attach buffers of 2 (n_fields + 5) N^3 values
+ * afterwards if wanted: the layout is the one of cl_attach_device_buffers
+ * with n_fields + 5 arrays of each kind, fields first, then v_11 .. v_23).
+ * on == 0 drops the tensor.  Three-dimensional lattices only. */
+cl_status cl_gw_enable(cl_lattice* h, int on);
+
+/* Host FP64 copies of the tensor components and their momenta, component
+ * major: [c][(x*N + y)*N + z] for c = 11, 12, 13, 22, 23 (5 N^3 values each;
+ * either pointer of cl_gw_get may be NULL).  CL_ESTATE if the waves are off. */
+cl_status cl_gw_set(cl_lattice* h, const double* v, const double* u);
+cl_status cl_gw_get(cl_lattice* h, double* v, double* u);
+
+/* Energy spectrum of the gravitational waves of the current state (Sect.
+ * 4.2): the DFT of every component of u on the device (FP64), per mode the
+ * projection h'_ij = a^(alpha-3) Lambda_ij,lm(k^) u_lm with
+ * Lambda_ij,lm = P_il P_jm - P_ij P_lm / 2, P = 1 - k^ k^, and k^ the unit
+ * lattice momentum (sin(pi n_i / N))_i (the mode n = 0 carries none), and
+ * |h'_ij|^2 summed over centred shells of |n| of width `width` as the scalar
+ * spectrum bins them.  Outputs (each may be NULL): counts[l] -- modes in bin
+ * l; rho[l] = m_p^2 / (4 a^(2 alpha) N^6) sum over the bin of |h'_ij(n)|^2,
+ * the bin's share of rho_GW = m_p^2 <h'_ij h'_ij> / (4 a^(2 alpha));
+ * omega[l] = l rho[l] / rho_tot, the discretised (d rho_GW / d log k) / rho_tot
+ * at k_l = l width k_IR with rho_tot the lattice energy density; *rho_gw --
+ * rho_GW over every mode (bins beyond nbins included).  nbins <= 4096, N a
+ * power of two; uses 80 N^3 bytes of device memory, allocated on first use. */
+cl_status cl_gw_spectrum(cl_lattice* h, double width, int nbins, int64_t* counts, double* rho, double* omega,
+                         double* rho_gw);
+
 /* Power spectrum of one array of the current state (Sect. 4.3, Eqs.
  * discretePSaux, discretePST2): field `field`, what = 0 for f, 1 for pi.  The
  * DFT f(n~) = sum_n exp(-2 pi i n~.n / N) f(n) (n~_i in -N/2+1 .. N/2) is

@@ -101,6 +101,10 @@ _SIGS = {
     "cl_set_state": (C.c_int, [_P, C.POINTER(cl_scalars)]),
     "cl_step": (C.c_int, [_P, C.c_int, C.c_double, C.c_int, _P]),
     "cl_step_noalloc": (C.c_int, [_P, C.c_int, C.c_double, C.c_int, _P]),
+    "cl_gw_enable": (C.c_int, [_P, C.c_int]),
+    "cl_gw_set": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "cl_gw_get": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "cl_gw_spectrum": (C.c_int, [_P, C.c_double, C.c_int, _P, _P, _P, C.POINTER(C.c_double)]),
     "cl_read_observables": (C.c_int, [_P, _P]),
     "cl_get_tile": (C.c_int, [_P, C.POINTER(cl_tile)]),
     "cl_set_tile": (C.c_int, [_P, C.POINTER(cl_tile)]),
@@ -282,6 +286,36 @@ class Lattice:
                                      _P(counts.ctypes.data), _P(sums.ctypes.data), _P(delta.ctypes.data)), self.h)
         k = 2.0 * np.pi / (self.N * self.dx) * width * np.arange(nbins)
         return k, counts, sums, delta
+
+    def gw_enable(self, on: bool = True):
+        """Carry (or drop) the five traceless tensor components of the
+        gravitational waves in the state (cl_gw_enable)."""
+        _check(lib.cl_gw_enable(self.h, 1 if on else 0), self.h)
+
+    def gw_set(self, v: np.ndarray, u: np.ndarray):
+        shape = (5, self.N, self.N, self.N)
+        v = np.ascontiguousarray(v, dtype=np.float64).reshape(shape)
+        u = np.ascontiguousarray(u, dtype=np.float64).reshape(shape)
+        _check(lib.cl_gw_set(self.h, _dptr(v), _dptr(u)), self.h)
+
+    def gw_get(self):
+        shape = (5, self.N, self.N, self.N)
+        v = np.empty(shape)
+        u = np.empty(shape)
+        _check(lib.cl_gw_get(self.h, _dptr(v), _dptr(u)), self.h)
+        return v, u
+
+    def gw_spectrum(self, width: float = 1.0, nbins: int | None = None):
+        """(counts, rho_l, omega_l, rho_GW) of the gravitational waves (cl_gw_spectrum)."""
+        if nbins is None:
+            nbins = int(np.ceil(np.sqrt(3.0) * (self.N // 2) / width)) + 1
+        counts = np.zeros(nbins, dtype=np.int64)
+        rho = np.zeros(nbins, dtype=np.float64)
+        omega = np.zeros(nbins, dtype=np.float64)
+        tot = C.c_double()
+        _check(lib.cl_gw_spectrum(self.h, float(width), int(nbins), _P(counts.ctypes.data), _P(rho.ctypes.data),
+                                  _P(omega.ctypes.data), C.byref(tot)), self.h)
+        return counts, rho, omega, tot.value
 
     def read_observables(self):
         out = np.zeros(1, dtype=OBS_DTYPE)

@@ -97,6 +97,7 @@ struct PassArgs {
     int has_prev;       // 1: finish the previous pass first
     int prev_rec;       // observable slot of the previous pass, -1: none
     int dim;            // spatial dimension of the lattice (1, 2 or 3)
+    int ng;             // gravitational-wave tensor components carried in the state (0 or 5)
     double pkt, pkb, phn;  // kt, kb, h_next of the previous pass
     // Runge-Kutta stage, for the fields (registers in `aux`, state layout) and,
     // in the scalar step, for (a, a').  rk = 1, low storage: d <- rkA d +
@@ -175,6 +176,10 @@ hipError_t launch_spec_extract(const void* state, bool fp32, int N, int nf, int 
 hipError_t launch_spec_fft(double2* data, const double2* tw, int N, int axis, hipStream_t s);
 hipError_t launch_spec_bin(const double2* F, int N, double width, int nbins, double* sums,
                            unsigned long long* counts, hipStream_t s);
+// Gravitational-wave spectrum: projected |U|^2 per centred shell (sums has
+// nbins + 1 slots, the last for the modes beyond the bins).
+hipError_t launch_gw_bin(const double2* U, int N, double width, int nbins, double* sums, unsigned long long* counts,
+                         hipStream_t s);
 hipError_t launch_init_scalars(Scal* sc, double a, double b, double eta, const Phys& ph,
                                const double* shift, hipStream_t s);
 // Default tile for a lattice; valid for every N accepted by cl_create.
@@ -182,7 +187,9 @@ Tile default_tile(int N, cl_precision prec, int nf);
 // Fill nbz/nby/nbx and check that the tile divides the lattice and fits the
 // kernel's limits.  Returns false if not.
 bool finalize_tile(Tile& t, int N, cl_precision prec);
-size_t pass_lds_bytes(const Tile& t, cl_precision prec, int nf);
+// LDS of a pass for `arrays` stencil arrays (the fields, plus the tensor
+// components when gravitational waves are on).
+size_t pass_lds_bytes(const Tile& t, cl_precision prec, int arrays);
 // All valid tiles the autotuner tries for a lattice.
 void candidate_tiles(int N, cl_precision prec, int nf, Tile* out, int* count, int cap);
 hipError_t launch_copy(const void* in, void* out, size_t bytes, hipStream_t s);
@@ -231,7 +238,9 @@ struct cl_lattice {
     void* aux = nullptr;                // Runge-Kutta registers of f and pi (same layout), on first use
     void* aux2 = nullptr;               // classic RK4: the third stage buffer, on first use
     int dim = 3;                        // spatial dimension (reduced lattices: 1 or 2)
+    int ng = 0;                         // gravitational-wave tensor components in the state (0 or 5)
     double2* spec = nullptr;            // power spectrum: N^3 complex FP64, on first use
+    double2* gw_spec = nullptr;         // gravitational-wave spectrum: 5 N^3 complex FP64, on first use
     double2* spec_tw = nullptr;         // its twiddle factors (N / 2)
     double* spec_sums = nullptr;        // per-bin sums and counts (spec_cap bins)
     unsigned long long* spec_counts = nullptr;

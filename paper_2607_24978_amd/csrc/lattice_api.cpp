@@ -39,8 +39,11 @@ size_t sites(const cl_lattice* h) {
 }
 // rows of N values along z (N^2 in three dimensions, N or 1 on reduced lattices)
 size_t rows(const cl_lattice* h) { return sites(h) / static_cast<size_t>(h->N); }
-// One state buffer: 2 n_f arrays of N^3 values.
-size_t state_bytes(const cl_lattice* h) { return 2 * static_cast<size_t>(h->nf) * sites(h) * elem_size(h->prec); }
+// Stencil arrays per row: the fields plus the gravitational-wave tensor
+// components (each with its momentum: 2 na arrays per row).
+int arrays(const cl_lattice* h) { return h->nf + h->ng; }
+// One state buffer: 2 na arrays of N^3 values.
+size_t state_bytes(const cl_lattice* h) { return 2 * static_cast<size_t>(arrays(h)) * sites(h) * elem_size(h->prec); }
 
 cl_status fail(cl_lattice* h, cl_status st, const std::string& msg) {
     if (h) h->err = msg; else g_err = msg;
@@ -145,6 +148,7 @@ PassArgs base_args(cl_lattice* h, int in) {
     a.aux = h->aux;
     a.y0 = nullptr;
     a.dim = h->dim;
+    a.ng = h->ng;
     a.obs = h->obs;
     a.ph = make_phys(h);
     a.rec = -1;
@@ -591,10 +595,11 @@ cl_status reset_background(cl_lattice* h, const double* mean) {
     return CL_OK;
 }
 
-// Host SoA arrays (field-major, N^3 each) <-> device row-interleaved state:
-// array a of row r sits at (r * 2nf + a) * N.
+// Host SoA arrays (N^3 each) <-> device row-interleaved state: array a of
+// row r sits at (r * 2 na + a) * N.  `count` consecutive host arrays go to
+// (come from) device arrays first .. first + count - 1 of the current state.
 template <typename T>
-cl_status upload(cl_lattice* h, const double* f, const double* p) {
+cl_status upload_arrays(cl_lattice* h, const double* src, int first, int count) {
     const size_t n = sites(h);
     const size_t N = static_cast<size_t>(h->N);
     std::vector<T> tmp;
@@ -603,23 +608,19 @@ cl_status upload(cl_lattice* h, const double* f, const double* p) {
     } catch (const std::bad_alloc&) {
         return fail(h, CL_ENOMEM, "host staging buffer");
     }
-    for (int which = 0; which < 2; ++which) {
-        const double* src = which == 0 ? f : p;
-        for (int j = 0; j < h->nf; ++j) {
-            const double* s = src + j * n;
-            for (size_t i = 0; i < n; ++i) tmp[i] = static_cast<T>(s[i]);
-            const int arr = which * h->nf + j;
-            char* dst = static_cast<char*>(h->buf[h->cur]) + arr * N * sizeof(T);
-            HIPCHECK(h, hipMemcpy2DAsync(dst, 2 * h->nf * N * sizeof(T), tmp.data(), N * sizeof(T), N * sizeof(T),
-                                         rows(h), hipMemcpyHostToDevice, h->stream));
-            HIPCHECK(h, hipStreamSynchronize(h->stream));
-        }
+    for (int k = 0; k < count; ++k) {
+        const double* s = src + k * n;
+        for (size_t i = 0; i < n; ++i) tmp[i] = static_cast<T>(s[i]);
+        char* dst = static_cast<char*>(h->buf[h->cur]) + (first + k) * N * sizeof(T);
+        HIPCHECK(h, hipMemcpy2DAsync(dst, 2 * arrays(h) * N * sizeof(T), tmp.data(), N * sizeof(T), N * sizeof(T),
+                                     rows(h), hipMemcpyHostToDevice, h->stream));
+        HIPCHECK(h, hipStreamSynchronize(h->stream));
     }
     return CL_OK;
 }
 
 template <typename T>
-cl_status download(cl_lattice* h, double* f, double* p) {
+cl_status download_arrays(cl_lattice* h, double* dst, int first, int count) {
     const size_t n = sites(h);
     const size_t N = static_cast<size_t>(h->N);
     std::vector<T> tmp;
@@ -628,20 +629,28 @@ cl_status download(cl_lattice* h, double* f, double* p) {
     } catch (const std::bad_alloc&) {
         return fail(h, CL_ENOMEM, "host staging buffer");
     }
-    for (int which = 0; which < 2; ++which) {
-        double* dst = which == 0 ? f : p;
-        if (!dst) continue;
-        for (int j = 0; j < h->nf; ++j) {
-            const int arr = which * h->nf + j;
-            const char* src = static_cast<const char*>(h->buf[h->cur]) + arr * N * sizeof(T);
-            HIPCHECK(h, hipMemcpy2DAsync(tmp.data(), N * sizeof(T), src, 2 * h->nf * N * sizeof(T), N * sizeof(T),
-                                         rows(h), hipMemcpyDeviceToHost, h->stream));
-            HIPCHECK(h, hipStreamSynchronize(h->stream));
-            double* d = dst + j * n;
-            for (size_t i = 0; i < n; ++i) d[i] = static_cast<double>(tmp[i]);
-        }
+    for (int k = 0; k < count; ++k) {
+        const char* src = static_cast<const char*>(h->buf[h->cur]) + (first + k) * N * sizeof(T);
+        HIPCHECK(h, hipMemcpy2DAsync(tmp.data(), N * sizeof(T), src, 2 * arrays(h) * N * sizeof(T), N * sizeof(T),
+                                     rows(h), hipMemcpyDeviceToHost, h->stream));
+        HIPCHECK(h, hipStreamSynchronize(h->stream));
+        double* d = dst + k * n;
+        for (size_t i = 0; i < n; ++i) d[i] = static_cast<double>(tmp[i]);
     }
     return CL_OK;
+}
+
+// Fields f_j are arrays 0 .. nf-1, momenta pi_j arrays na .. na+nf-1.
+template <typename T>
+cl_status upload(cl_lattice* h, const double* f, const double* p) {
+    cl_status st = upload_arrays<T>(h, f, 0, h->nf);
+    return st ? st : upload_arrays<T>(h, p, arrays(h), h->nf);
+}
+
+template <typename T>
+cl_status download(cl_lattice* h, double* f, double* p) {
+    cl_status st = f ? download_arrays<T>(h, f, 0, h->nf) : CL_OK;
+    return st || !p ? st : download_arrays<T>(h, p, arrays(h), h->nf);
 }
 
 void host_means(const cl_lattice* h, const double* f, double* mean) {
@@ -686,6 +695,40 @@ bool cached_tile(int N, int nf, cl_precision prec, Tile& t) {
     return found;
 }
 
+// Tile of a pass that carries the gravitational-wave tensor: one row per
+// thread, 16 threads along z, 128-thread workgroups (seven stencil arrays of
+// registers per thread; 40 KB of LDS in FP32), prefetch depth 1, and enough
+// x-chunks for about a thousand workgroups.
+Tile gw_tile(int N, cl_precision prec) {
+    const int V = prec == CL_FP32 ? 4 : 2;
+    Tile t;
+    t.TZ = std::min(N, 16 * V);
+    const int BZ = t.TZ / V;
+    int TY = 128 / BZ;
+    while (TY > 1 && (TY > N || N % TY)) TY >>= 1;
+    t.TY = TY;
+    t.RY = 1;
+    t.PD = 1;
+    const int tiles = (N / t.TZ) * (N / t.TY);
+    t.CX = N;
+    while (t.CX > 4 && tiles * (N / t.CX) < 1024 && t.CX % 2 == 0) t.CX /= 2;
+    cl::finalize_tile(t, N, prec);
+    return t;
+}
+
+// The tile a lattice starts from: the tuned cache entry or the default.
+Tile start_tile(const cl_lattice* h) {
+    if (h->ng) return gw_tile(h->N, h->prec);
+    Tile t = cl::default_tile(h->N, h->prec, h->nf);
+    cached_tile(h->N, h->nf, h->prec, t);
+    return t;
+}
+
+// A tile the pass with the gravitational-wave tensor can run.
+bool gw_tile_ok(const Tile& t, cl_precision prec, int na) {
+    return t.RY == 1 && t.PD == 1 && t.NT <= 256 && cl::pass_lds_bytes(t, prec, na) <= 64 * 1024;
+}
+
 void free_buffers(cl_lattice* h) {
     if (!h->own_buffers) return;
     for (auto& b : h->buf) {
@@ -700,6 +743,8 @@ cl_status check_step(cl_lattice* h, cl_integrator integ, double dt, int n) {
     if (integ != CL_LEAPFROG && integ != CL_VV4 && !is_rk(integ)) return fail(h, CL_EINVAL, "unknown integrator");
     if (h->dim != 3 && is_rk(integ))
         return fail(h, CL_EUNSUPPORTED, "reduced lattices run the symplectic schemes only");
+    if (h->ng && is_rk(integ))
+        return fail(h, CL_EUNSUPPORTED, "with gravitational waves on, the symplectic schemes only");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(h, CL_EINVAL, "dt must be positive and finite");
     if (n < 0) return fail(h, CL_EINVAL, "n must be >= 0");
     if (n == 0) return CL_OK;
@@ -803,8 +848,7 @@ cl_status cl_create_dim(int dim, int N, double dx, int n_fields, cl_precision pr
     if (hipMalloc(&h->sc, sizeof(Scal)) != hipSuccess) return bail(CL_ENOMEM, "scalar block");
     if (hipMalloc(&h->scb, 2 * sizeof(Scal)) != hipSuccess) return bail(CL_ENOMEM, "scalar blocks");
     if (dim == 3) {
-        h->tile = cl::default_tile(N, prec, n_fields);
-        cached_tile(N, n_fields, prec, h->tile);
+        h->tile = start_tile(h);
     } else {
         // grid-stride pass: 256 threads per workgroup, each on V sites
         const size_t groups = sites(h) / (prec == CL_FP32 ? 4 : 2);
@@ -836,7 +880,7 @@ cl_status cl_destroy(cl_lattice* h) {
     free_buffers(h);
     if (h->aux) hipFree(h->aux);
     if (h->aux2) hipFree(h->aux2);
-    for (void* q : {(void*)h->spec, (void*)h->spec_tw, (void*)h->spec_sums, (void*)h->spec_counts})
+    for (void* q : {(void*)h->spec, (void*)h->gw_spec, (void*)h->spec_tw, (void*)h->spec_sums, (void*)h->spec_counts})
         if (q) hipFree(q);
     if (h->sc) hipFree(h->sc);
     if (h->partials) hipFree(h->partials);
@@ -1040,15 +1084,101 @@ cl_status cl_read_observables(cl_lattice* h, cl_observables* out) {
     return reduce_pass(h, out);
 }
 
-cl_status cl_power_spectrum(cl_lattice* h, int field, int what, double width, int nbins, int64_t* counts,
-                            double* sums, double* delta) {
-    if (!h) return fail(nullptr, CL_EINVAL, "handle is NULL");
+}  // extern "C"
+
+namespace {
+
+// Twiddle factors exp(-2 pi i k / N) of the line FFTs, formed in long double
+// and rounded once; allocated on first use.
+cl_status ensure_twiddles(cl_lattice* h) {
+    if (h->spec_tw) return CL_OK;
+    const int N = h->N;
+    std::vector<double2> tw(N / 2);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int k = 0; k < N / 2; ++k) {
+        const long double t = -2.0L * pi * k / N;
+        tw[k] = make_double2(static_cast<double>(std::cos(t)), static_cast<double>(std::sin(t)));
+    }
+    HIPCHECK(h, hipMalloc(&h->spec_tw, (N / 2 > 0 ? N / 2 : 1) * sizeof(double2)));
+    HIPCHECK(h, hipMemcpyAsync(h->spec_tw, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice, h->stream));
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    return CL_OK;
+}
+
+// Per-bin sums and counts for `slots` bins.
+cl_status ensure_bins(cl_lattice* h, int slots) {
+    if (h->spec_cap >= slots) return CL_OK;
+    if (h->spec_sums) (void)hipFree(h->spec_sums);
+    if (h->spec_counts) (void)hipFree(h->spec_counts);
+    h->spec_sums = nullptr;
+    h->spec_counts = nullptr;
+    h->spec_cap = 0;
+    HIPCHECK(h, hipMalloc(&h->spec_sums, slots * sizeof(double)));
+    HIPCHECK(h, hipMalloc(&h->spec_counts, slots * sizeof(unsigned long long)));
+    h->spec_cap = slots;
+    return CL_OK;
+}
+
+cl_status check_spectrum_args(cl_lattice* h, double width, int nbins) {
     if (h->dim != 3) return fail(h, CL_EUNSUPPORTED, "the power spectrum is three-dimensional");
-    if (field < 0 || field >= h->nf) return fail(h, CL_EINVAL, "field index out of range");
-    if (what != 0 && what != 1) return fail(h, CL_EINVAL, "what must be 0 (f) or 1 (pi)");
     if (!(width > 0.0) || !std::isfinite(width)) return fail(h, CL_EINVAL, "bin width must be positive");
     if (nbins < 1 || nbins > 4096) return fail(h, CL_EINVAL, "nbins must be in [1, 4096]");
     if ((h->N & (h->N - 1)) != 0) return fail(h, CL_EUNSUPPORTED, "the spectrum needs N a power of two");
+    return CL_OK;
+}
+
+// Device state buffers of the other layout (na_new stencil arrays per row):
+// the fields and momenta of the current state are copied over, every other
+// array starts at zero.
+cl_status relayout(cl_lattice* h, int ng_new) {
+    const size_t N = static_cast<size_t>(h->N), es = elem_size(h->prec);
+    const int na_old = arrays(h), na_new = h->nf + ng_new;
+    const size_t bytes = 2 * static_cast<size_t>(na_new) * sites(h) * es;
+    void* nb[2] = {nullptr, nullptr};
+    for (int pp = 0; pp < 2; ++pp) {
+        if (hipMalloc(&nb[pp], bytes) != hipSuccess) {
+            if (nb[0]) (void)hipFree(nb[0]);
+            return fail(h, CL_ENOMEM, "device state buffers (2 x " + std::to_string(bytes) + " bytes)");
+        }
+        HIPCHECK(h, hipMemsetAsync(nb[pp], 0, bytes, h->stream));
+    }
+    for (int which = 0; which < 2; ++which)
+        for (int j = 0; j < h->nf; ++j) {
+            const char* src = static_cast<const char*>(h->buf[h->cur]) + (which * na_old + j) * N * es;
+            char* dst = static_cast<char*>(nb[0]) + (which * na_new + j) * N * es;
+            HIPCHECK(h, hipMemcpy2DAsync(dst, 2 * na_new * N * es, src, 2 * na_old * N * es, N * es, rows(h),
+                                         hipMemcpyDeviceToDevice, h->stream));
+        }
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    free_buffers(h);
+    h->buf[0] = nb[0];
+    h->buf[1] = nb[1];
+    h->cur = 0;
+    h->ng = ng_new;
+    // Runge-Kutta registers have the state's layout
+    for (void** q : {&h->aux, &h->aux2})
+        if (*q) {
+            (void)hipFree(*q);
+            *q = nullptr;
+        }
+    h->tile = start_tile(h);
+    cl_status st = ensure_partials(h);
+    if (st) return st;
+    drop_graph(h);
+    return CL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cl_status cl_power_spectrum(cl_lattice* h, int field, int what, double width, int nbins, int64_t* counts,
+                            double* sums, double* delta) {
+    if (!h) return fail(nullptr, CL_EINVAL, "handle is NULL");
+    cl_status st = check_spectrum_args(h, width, nbins);
+    if (st) return st;
+    if (field < 0 || field >= h->nf) return fail(h, CL_EINVAL, "field index out of range");
+    if (what != 0 && what != 1) return fail(h, CL_EINVAL, "what must be 0 (f) or 1 (pi)");
     const int N = h->N;
     const size_t n3 = sites(h);
     if (!h->spec) {
@@ -1056,28 +1186,10 @@ cl_status cl_power_spectrum(cl_lattice* h, int field, int what, double width, in
             h->spec = nullptr;
             return fail(h, CL_ENOMEM, "spectrum buffer (" + std::to_string(n3 * sizeof(double2)) + " bytes)");
         }
-        // twiddles exp(-2 pi i k / N), formed in long double and rounded once
-        std::vector<double2> tw(N / 2);
-        const long double pi = 3.141592653589793238462643383279502884L;
-        for (int k = 0; k < N / 2; ++k) {
-            const long double t = -2.0L * pi * k / N;
-            tw[k] = make_double2(static_cast<double>(std::cos(t)), static_cast<double>(std::sin(t)));
-        }
-        HIPCHECK(h, hipMalloc(&h->spec_tw, (N / 2 > 0 ? N / 2 : 1) * sizeof(double2)));
-        HIPCHECK(h, hipMemcpyAsync(h->spec_tw, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice, h->stream));
     }
-    if (h->spec_cap < nbins) {
-        if (h->spec_sums) hipFree(h->spec_sums);
-        if (h->spec_counts) hipFree(h->spec_counts);
-        h->spec_sums = nullptr;
-        h->spec_counts = nullptr;
-        h->spec_cap = 0;
-        HIPCHECK(h, hipMalloc(&h->spec_sums, nbins * sizeof(double)));
-        HIPCHECK(h, hipMalloc(&h->spec_counts, nbins * sizeof(unsigned long long)));
-        h->spec_cap = nbins;
-    }
-    const int arr = what == 0 ? field : h->nf + field;
-    HIPCHECK(h, cl::launch_spec_extract(h->buf[h->cur], h->prec == CL_FP32, N, h->nf, arr, h->spec, h->stream));
+    if ((st = ensure_twiddles(h)) || (st = ensure_bins(h, nbins))) return st;
+    const int arr = what == 0 ? field : arrays(h) + field;
+    HIPCHECK(h, cl::launch_spec_extract(h->buf[h->cur], h->prec == CL_FP32, N, arrays(h), arr, h->spec, h->stream));
     for (int axis = 0; axis < 3; ++axis) HIPCHECK(h, cl::launch_spec_fft(h->spec, h->spec_tw, N, axis, h->stream));
     HIPCHECK(h, hipMemsetAsync(h->spec_sums, 0, nbins * sizeof(double), h->stream));
     HIPCHECK(h, hipMemsetAsync(h->spec_counts, 0, nbins * sizeof(unsigned long long), h->stream));
@@ -1095,6 +1207,90 @@ cl_status cl_power_spectrum(cl_lattice* h, int field, int what, double width, in
         if (sums) sums[l] = s[l];
         if (delta) delta[l] = (k_ir * width * l) / (2.0 * M_PI) * h->dx / n5 * s[l];
     }
+    return CL_OK;
+}
+
+cl_status cl_gw_enable(cl_lattice* h, int on) {
+    if (!h) return fail(nullptr, CL_EINVAL, "handle is NULL");
+    if (h->dim != 3) return fail(h, CL_EUNSUPPORTED, "gravitational waves need a three-dimensional lattice");
+    const int ng_new = on ? 5 : 0;
+    if (ng_new == h->ng) return CL_OK;
+    if (!h->own_buffers)
+        return fail(h, CL_ESTATE, "switch gravitational waves on before attaching device buffers");
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    return relayout(h, ng_new);
+}
+
+cl_status cl_gw_set(cl_lattice* h, const double* v, const double* u) {
+    if (!h) return fail(nullptr, CL_EINVAL, "handle is NULL");
+    if (!h->ng) return fail(h, CL_ESTATE, "gravitational waves are off");
+    if (!v || !u) return fail(h, CL_EINVAL, "tensor arrays must not be NULL");
+    if (h->prec == CL_FP32) {
+        cl_status st = upload_arrays<float>(h, v, h->nf, h->ng);
+        return st ? st : upload_arrays<float>(h, u, arrays(h) + h->nf, h->ng);
+    }
+    cl_status st = upload_arrays<double>(h, v, h->nf, h->ng);
+    return st ? st : upload_arrays<double>(h, u, arrays(h) + h->nf, h->ng);
+}
+
+cl_status cl_gw_get(cl_lattice* h, double* v, double* u) {
+    if (!h) return fail(nullptr, CL_EINVAL, "handle is NULL");
+    if (!h->ng) return fail(h, CL_ESTATE, "gravitational waves are off");
+    if (!v && !u) return fail(h, CL_EINVAL, "both output arrays are NULL");
+    cl_status st = CL_OK;
+    if (v) st = h->prec == CL_FP32 ? download_arrays<float>(h, v, h->nf, h->ng) : download_arrays<double>(h, v, h->nf, h->ng);
+    if (st || !u) return st;
+    return h->prec == CL_FP32 ? download_arrays<float>(h, u, arrays(h) + h->nf, h->ng)
+                              : download_arrays<double>(h, u, arrays(h) + h->nf, h->ng);
+}
+
+cl_status cl_gw_spectrum(cl_lattice* h, double width, int nbins, int64_t* counts, double* rho, double* omega,
+                         double* rho_gw) {
+    if (!h) return fail(nullptr, CL_EINVAL, "handle is NULL");
+    if (!h->ng) return fail(h, CL_ESTATE, "gravitational waves are off");
+    cl_status st = check_spectrum_args(h, width, nbins);
+    if (st) return st;
+    const int N = h->N;
+    const size_t n3 = sites(h);
+    if (!h->gw_spec) {
+        if (hipMalloc(&h->gw_spec, 5 * n3 * sizeof(double2)) != hipSuccess) {
+            h->gw_spec = nullptr;
+            return fail(h, CL_ENOMEM, "gravitational-wave spectrum buffer (" + std::to_string(5 * n3 * sizeof(double2)) +
+                                          " bytes)");
+        }
+    }
+    if ((st = ensure_twiddles(h)) || (st = ensure_bins(h, nbins + 1))) return st;
+    for (int c = 0; c < 5; ++c) {
+        double2* dst = h->gw_spec + c * n3;
+        HIPCHECK(h, cl::launch_spec_extract(h->buf[h->cur], h->prec == CL_FP32, N, arrays(h), arrays(h) + h->nf + c,
+                                            dst, h->stream));
+        for (int axis = 0; axis < 3; ++axis) HIPCHECK(h, cl::launch_spec_fft(dst, h->spec_tw, N, axis, h->stream));
+    }
+    HIPCHECK(h, hipMemsetAsync(h->spec_sums, 0, (nbins + 1) * sizeof(double), h->stream));
+    HIPCHECK(h, hipMemsetAsync(h->spec_counts, 0, nbins * sizeof(unsigned long long), h->stream));
+    HIPCHECK(h, cl::launch_gw_bin(h->gw_spec, N, width, nbins, h->spec_sums, h->spec_counts, h->stream));
+    std::vector<double> s(nbins + 1);
+    std::vector<unsigned long long> c(nbins);
+    HIPCHECK(h, hipMemcpyAsync(s.data(), h->spec_sums, (nbins + 1) * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHECK(h, hipMemcpyAsync(c.data(), h->spec_counts, nbins * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                               h->stream));
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    cl_observables o;
+    st = cl_read_observables(h, &o);
+    if (st) return st;
+    // h' = a^(alpha-3) u; rho_GW = m_p^2 <h'_ij h'_ij> / (4 a^(2 alpha)), <.> = N^-6 sum over modes
+    const double a = o.a;
+    const double scale = h->mp * h->mp / (4.0 * std::pow(a, 2.0 * h->alpha)) * std::pow(a, 2.0 * (h->alpha - 3.0)) /
+                         std::pow(static_cast<double>(N), 6.0);
+    const double rho_tot = o.EK[0] + o.EK[1] + o.EG[0] + o.EG[1] + o.EV;
+    double total = 0.0;
+    for (int l = 0; l <= nbins; ++l) total += s[l];
+    for (int l = 0; l < nbins; ++l) {
+        if (counts) counts[l] = static_cast<int64_t>(c[l]);
+        if (rho) rho[l] = scale * s[l];
+        if (omega) omega[l] = l * scale * s[l] / rho_tot;
+    }
+    if (rho_gw) *rho_gw = scale * total;
     return CL_OK;
 }
 
@@ -1120,7 +1316,9 @@ cl_status cl_set_tile(cl_lattice* h, const cl_tile* t) {
     c.RY = t->ry;
     c.PD = t->pd == 0 ? 1 : t->pd;
     if (!cl::finalize_tile(c, h->N, h->prec)) return fail(h, CL_EINVAL, "tile does not fit this lattice");
-    if (cl::pass_lds_bytes(c, h->prec, h->nf) > 60 * 1024) return fail(h, CL_EINVAL, "tile needs too much LDS");
+    if (cl::pass_lds_bytes(c, h->prec, arrays(h)) > 60 * 1024) return fail(h, CL_EINVAL, "tile needs too much LDS");
+    if (h->ng && !gw_tile_ok(c, h->prec, arrays(h)))
+        return fail(h, CL_EINVAL, "with gravitational waves on, tiles take one row per thread, depth 1, <= 256 threads");
     HIPCHECK(h, hipStreamSynchronize(h->stream));
     const Tile old = h->tile;
     h->tile = c;
@@ -1140,6 +1338,20 @@ cl_status cl_autotune(cl_lattice* h, int reps, char* report, size_t cap) {
     std::vector<Tile> cands(1024);
     int nc = 0;
     cl::candidate_tiles(h->N, h->prec, h->nf, cands.data(), &nc, static_cast<int>(cands.size()));
+    if (h->ng) {
+        // the pass with the tensor: one-row, depth-1 tiles of at most 256 threads
+        std::vector<Tile> keep;
+        for (int i = 0; i < nc; ++i) {
+            Tile c = cands[i];
+            c.PD = 1;
+            if (c.RY != 1 || !cl::finalize_tile(c, h->N, h->prec) || !gw_tile_ok(c, h->prec, arrays(h))) continue;
+            bool dup = false;
+            for (const Tile& k : keep) dup = dup || (k.TZ == c.TZ && k.TY == c.TY && k.CX == c.CX);
+            if (!dup) keep.push_back(c);
+        }
+        nc = static_cast<int>(keep.size());
+        for (int i = 0; i < nc; ++i) cands[i] = keep[i];
+    }
     if (nc == 0) return fail(h, CL_EUNSUPPORTED, "no candidate tile");
     int maxb = 0;
     for (int i = 0; i < nc; ++i) maxb = std::max(maxb, cands[i].nblocks());
@@ -1468,6 +1680,7 @@ cl_status cl_ensemble_create(int n, cl_lattice* const* members, cl_ensemble** ou
         if (h->prec != e->prec || h->nf != e->nf)
             return bail(CL_EINVAL, "all members need the same precision and number of fields");
         if (h->dim != 3) return bail(CL_EUNSUPPORTED, "ensemble members are three-dimensional lattices");
+        if (h->ng) return bail(CL_EUNSUPPORTED, "ensemble members carry no gravitational-wave tensor");
         e->m.push_back(h);
     }
     e->dt.assign(n, 0.0);

@@ -158,6 +158,90 @@ __global__ __launch_bounds__(256) void spec_bin(const double2* __restrict__ F, i
     }
 }
 
+// Gravitational-wave spectrum (Sect. 4.2): U holds the DFTs of the five
+// evolved tensor components (11, 12, 13, 22, 23; 33 = -11 - 22), N^3 each.
+// Per mode: the transverse-traceless projection
+// Lambda_ij,lm T_lm = (P T P)_ij - P_ij tr(P T) / 2 with P = 1 - k^ k^ and
+// k^ the unit lattice momentum (sin(pi n_i / N)), then sum_ij |.|^2 into the
+// centred shell of |n~| (slot nbins collects the modes beyond the last bin);
+// the mode n~ = 0 carries no waves.
+__global__ __launch_bounds__(256) void gw_bin(const double2* __restrict__ U, int N, double inv_w, int nbins,
+                                              double* __restrict__ sums, unsigned long long* __restrict__ counts) {
+    extern __shared__ unsigned char raw[];
+    double* s_sum = reinterpret_cast<double*>(raw);
+    unsigned* s_cnt = reinterpret_cast<unsigned*>(s_sum + nbins + 1);
+    for (int i = threadIdx.x; i <= nbins; i += blockDim.x) {
+        s_sum[i] = 0.0;
+        if (i < nbins) s_cnt[i] = 0u;
+    }
+    __syncthreads();
+    const size_t n3 = static_cast<size_t>(N) * N * N;
+    const int hN = N / 2;
+    const double pin = M_PI / N;
+    for (size_t s = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; s < n3;
+         s += static_cast<size_t>(gridDim.x) * blockDim.x) {
+        const int z = static_cast<int>(s % N), y = static_cast<int>((s / N) % N),
+                  x = static_cast<int>(s / (static_cast<size_t>(N) * N));
+        const int n[3] = {x <= hN ? x : x - N, y <= hN ? y : y - N, z <= hN ? z : z - N};
+        const double r = sqrt(static_cast<double>(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]));
+        const int lb = min(static_cast<int>(floor(r * inv_w + 0.5)), nbins);
+        double pw = 0.0;
+        if (n[0] | n[1] | n[2]) {
+            double k[3], kk = 0.0;
+            for (int i = 0; i < 3; ++i) {
+                k[i] = sin(pin * n[i]);
+                kk += k[i] * k[i];
+            }
+            const double inv = 1.0 / sqrt(kk);
+            for (int i = 0; i < 3; ++i) k[i] *= inv;
+            double P[3][3];
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) P[i][j] = (i == j ? 1.0 : 0.0) - k[i] * k[j];
+            const double2 c11 = U[s], c12 = U[n3 + s], c13 = U[2 * n3 + s], c22 = U[3 * n3 + s],
+                          c23 = U[4 * n3 + s];
+            const double2 c33 = make_double2(-c11.x - c22.x, -c11.y - c22.y);
+            const double2 T[3][3] = {{c11, c12, c13}, {c12, c22, c23}, {c13, c23, c33}};
+            double2 PT[3][3], tr = make_double2(0.0, 0.0);
+            for (int i = 0; i < 3; ++i)
+                for (int m = 0; m < 3; ++m) {
+                    double2 a = make_double2(0.0, 0.0);
+                    for (int l = 0; l < 3; ++l) {
+                        a.x = fma(P[i][l], T[l][m].x, a.x);
+                        a.y = fma(P[i][l], T[l][m].y, a.y);
+                    }
+                    PT[i][m] = a;
+                    tr.x = fma(P[i][m], T[i][m].x, tr.x);
+                    tr.y = fma(P[i][m], T[i][m].y, tr.y);
+                }
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) {
+                    double hx = -0.5 * P[i][j] * tr.x, hy = -0.5 * P[i][j] * tr.y;
+                    for (int m = 0; m < 3; ++m) {
+                        hx = fma(PT[i][m].x, P[m][j], hx);
+                        hy = fma(PT[i][m].y, P[m][j], hy);
+                    }
+                    pw = fma(hx, hx, fma(hy, hy, pw));
+                }
+        }
+        atomicAdd(&s_sum[lb], pw);
+        if (lb < nbins) atomicAdd(&s_cnt[lb], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i <= nbins; i += blockDim.x) {
+        if (s_sum[i] != 0.0) atomicAdd(&sums[i], s_sum[i]);
+        if (i < nbins && s_cnt[i]) atomicAdd(&counts[i], static_cast<unsigned long long>(s_cnt[i]));
+    }
+}
+
+hipError_t launch_gw_bin(const double2* U, int N, double width, int nbins, double* sums, unsigned long long* counts,
+                         hipStream_t s) {
+    const size_t n3 = static_cast<size_t>(N) * N * N;
+    const unsigned grid = static_cast<unsigned>(std::min<size_t>((n3 + 255) / 256, 2048));
+    const size_t lds = static_cast<size_t>(nbins + 1) * sizeof(double) + static_cast<size_t>(nbins) * sizeof(unsigned);
+    hipLaunchKernelGGL(gw_bin, dim3(grid), dim3(256), lds, s, U, N, 1.0 / width, nbins, sums, counts);
+    return hipGetLastError();
+}
+
 int spec_lines_per_block(int N) { return N <= 64 ? N : 4096 / N; }
 
 hipError_t launch_spec_fft(double2* data, const double2* tw, int N, int axis, hipStream_t s) {

@@ -421,11 +421,21 @@ __device__ __forceinline__ void static_for(F&& f) {
 // classic Runge-Kutta stage -- the same F at the stage input Y, output
 // y0 + A s + B F and s <- C s + D F with the step's start y0 (in `step0`) and
 // the weighted stage sum s (in `aux`), both loaded one plane ahead.
-template <typename T, int NF, int RY, int HI, int PD, int RK, int HPD, typename Prelude>
+// NG > 0 (symplectic schemes only): the state also holds the NG = 5
+// components v_11, v_12, v_13, v_22, v_23 of the traceless tensor whose
+// transverse-traceless part is the gravitational-wave field (Sect. 4.2), and
+// their momenta u = a^(3-alpha) v': each row holds f_0.., v_11.., pi_0..,
+// u_11.. .  They drift with the fields' coefficient and are kicked by
+// kL (L[v] + (1/m_p^2) S) where S is the traceless part of the sum over
+// fields of the products of forward and of backward differences of the
+// drifted fields (no lattice sums for them).
+template <typename T, int NF, int RY, int HI, int PD, int RK, int HPD, int NG, typename Prelude>
 __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem_raw, double (&acc)[kSumsPerField * NF + 1],
                            Prelude&& prelude) {
     constexpr int V = VecOf<T>::V;
     constexpr int NS = kSumsPerField * NF + 1;
+    constexpr int NA = NF + NG;  // stencil arrays (fields and tensor components)
+    static_assert(NG == 0 || (NG == 5 && RK == 0), "tensor components with the symplectic schemes only");
     const int N = J.N, TZ = J.TZ, TY = J.TY, CX = J.CX;
     const int z0 = J.z0, y0 = J.y0, x0 = J.x0;
     const int BZ = TZ / V;
@@ -434,18 +444,18 @@ __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem
     const int tid = threadIdx.x;
     const int tz = tid % BZ;
     const int tr = tid / BZ;
-    // Row-interleaved state: array a of row (x, y) starts at ((x*N + y)*2NF + a)*N.
-    const int rs = 2 * NF * N;  // row stride (elements)
-    const T* fin[NF];
-    const T* pin[NF];
-    T* fout[NF];
-    T* pout[NF];
+    // Row-interleaved state: array a of row (x, y) starts at ((x*N + y)*2NA + a)*N.
+    const int rs = 2 * NA * N;  // row stride (elements)
+    const T* fin[NA];
+    const T* pin[NA];
+    T* fout[NA];
+    T* pout[NA];
 #pragma unroll
-    for (int j = 0; j < NF; ++j) {
+    for (int j = 0; j < NA; ++j) {
         fin[j] = static_cast<const T*>(J.in) + j * N;
-        pin[j] = static_cast<const T*>(J.in) + (NF + j) * N;
+        pin[j] = static_cast<const T*>(J.in) + (NA + j) * N;
         fout[j] = static_cast<T*>(J.out) + j * N;
-        pout[j] = static_cast<T*>(J.out) + (NF + j) * N;
+        pout[j] = static_cast<T*>(J.out) + (NA + j) * N;
     }
     const bool nt_store = J.flags & 1;
     const bool nt_load = J.flags & 2;
@@ -480,6 +490,8 @@ __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem
     const T hm2[2] = {T(0.5) * m2[0], T(0.5) * m2[1]};
     const T qlam[2] = {T(0.25) * lam[0], T(0.25) * lam[1]};
     const T hg2 = T(0.5) * g2;
+    // tensor source weight: 2 / m_p^2 times the 1/2 of the difference average
+    const T cS = static_cast<T>(1.0 / (J.ph->mp * J.ph->mp));
 
     T* lds = reinterpret_cast<T*>(smem_raw);
     const int S = TZ + 2 * V;        // LDS row stride (interior starts at column V)
@@ -526,7 +538,7 @@ __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem
     // halo ring costs every thread its registers), issued HPD planes ahead.
     // The prologue below fixes which plane travels in which set.
     static_assert(HPD == PD || (HPD == 2 && PD == 4), "halo ring depth");
-    T rf[PD][NF][RY][V], rp[PD][NF][RY][V], hf[HPD][NF][HI][V], hp[HPD][NF][HI][V];
+    T rf[PD][NA][RY][V], rp[PD][NA][RY][V], hf[HPD][NA][HI][V], hp[HPD][NA][HI][V];
     // Loads of plane x0+ko (own values, into set S; ko may be -1) and of the
     // halo items of plane x0+kh (into halo set H, only for planes staged in
     // LDS, 0 <= kh < CX), field by field; kNone skips either part.
@@ -537,7 +549,7 @@ __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem
         const bool own = ko != kNone;
         const bool halo = kh >= 0 && kh < CX;
 #pragma unroll
-        for (int j = 0; j < NF; ++j) {
+        for (int j = 0; j < NA; ++j) {
             if (own) {
                 const size_t obase = static_cast<size_t>((x0 + ko + N) % N) * plane;
 #pragma unroll
@@ -569,12 +581,12 @@ __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem
     };
     // Drift the raw plane of set S: own values into fd / po, and (if
     // stage_buf >= 0) the drifted own values and halo into LDS buffer stage_buf.
-    T prev[NF][RY][V], cur[NF][RY][V], nxt[NF][RY][V], pc[NF][RY][V], pn[NF][RY][V];
-    auto consume = [&](auto Sc, auto Hc, T (&fd)[NF][RY][V], T (&po)[NF][RY][V], int stage_buf) {
+    T prev[NA][RY][V], cur[NA][RY][V], nxt[NA][RY][V], pc[NA][RY][V], pn[NA][RY][V];
+    auto consume = [&](auto Sc, auto Hc, T (&fd)[NA][RY][V], T (&po)[NA][RY][V], int stage_buf) {
         constexpr int S_ = decltype(Sc)::value;
         constexpr int H_ = decltype(Hc)::value;
 #pragma unroll
-        for (int j = 0; j < NF; ++j)
+        for (int j = 0; j < NA; ++j)
 #pragma unroll
             for (int r = 0; r < RY; ++r)
 #pragma unroll
@@ -583,9 +595,9 @@ __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem
                     fd[j][r][v] = fmad(cd, rp[S_][j][r][v], rf[S_][j][r][v]);
                 }
         if (stage_buf < 0) return;
-        T* L0 = lds + static_cast<size_t>(stage_buf) * NF * PL;
+        T* L0 = lds + static_cast<size_t>(stage_buf) * NA * PL;
 #pragma unroll
-        for (int j = 0; j < NF; ++j) {
+        for (int j = 0; j < NA; ++j) {
             T* Lj = L0 + j * PL;
 #pragma unroll
             for (int r = 0; r < RY; ++r) vstore(Lj + (tr + r * RL + 1) * S + V + tz * V, fd[j][r]);
@@ -705,7 +717,7 @@ __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem
         }
         if (RK && !rk_first && i + 1 < CX) aux_load(i + 1, axn, y0n);
 
-        const T* L0 = lds + static_cast<size_t>(buf) * NF * PL;
+        const T* L0 = lds + static_cast<size_t>(buf) * NA * PL;
         const size_t base = static_cast<size_t>(x) * plane;
         // Per-plane partial sums in the field precision, promoted once.
         T part[NS];
@@ -715,16 +727,16 @@ __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem
         for (int k = 0; k < RY; ++k) {
             const int row = tr + k * RL + 1;
             const int col = V + tz * V;
-            T ym[NF][V], yp[NF][V], zm0[NF], zp0[NF];
+            T ym[NA][V], yp[NA][V], zm0[NA], zp0[NA];
 #pragma unroll
-            for (int j = 0; j < NF; ++j) {
+            for (int j = 0; j < NA; ++j) {
                 const T* Lj = L0 + j * PL;
                 vload(Lj + (row - 1) * S + col, ym[j]);
                 vload(Lj + (row + 1) * S + col, yp[j]);
                 zm0[j] = Lj[row * S + col - 1];
                 zp0[j] = Lj[row * S + col + V];
             }
-            T pnew[NF][V], fnew[NF][V], dfo[NF][V], dpo[NF][V];
+            T pnew[NA][V], fnew[NF][V], dfo[NF][V], dpo[NF][V];
 #pragma unroll
             for (int v = 0; v < V; ++v) {
                 T fs[NF], dV[NF];
@@ -786,10 +798,41 @@ __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem
                     q5[2] += d;
                     q5[3] = fmad(d, d, q5[3]);
                 }
+                if constexpr (NG > 0) {
+                    // sum over fields of D+_a f D+_b f + D-_a f D-_b f
+                    T sxx = T(0), syy = T(0), szz = T(0), sxy = T(0), sxz = T(0), syz = T(0);
+#pragma unroll
+                    for (int j = 0; j < NF; ++j) {
+                        const T f = cur[j][k][v];
+                        const T zm = v == 0 ? zm0[j] : cur[j][k][v - 1];
+                        const T zp = v == V - 1 ? zp0[j] : cur[j][k][v + 1];
+                        const T ax = nxt[j][k][v] - f, bx = f - prev[j][k][v];
+                        const T ay = yp[j][v] - f, by = f - ym[j][v];
+                        const T az = zp - f, bz = f - zm;
+                        sxx = fmad(ax, ax, fmad(bx, bx, sxx));
+                        syy = fmad(ay, ay, fmad(by, by, syy));
+                        szz = fmad(az, az, fmad(bz, bz, szz));
+                        sxy = fmad(ax, ay, fmad(bx, by, sxy));
+                        sxz = fmad(ax, az, fmad(bx, bz, sxz));
+                        syz = fmad(ay, az, fmad(by, bz, syz));
+                    }
+                    const T tr3 = (sxx + syy + szz) * static_cast<T>(1.0 / 3.0);
+                    const T src[5] = {sxx - tr3, sxy, sxz, syy - tr3, syz};
+#pragma unroll
+                    for (int c = 0; c < NG; ++c) {
+                        const int j = NF + c;
+                        const T w = cur[j][k][v];
+                        const T zm = v == 0 ? zm0[j] : cur[j][k][v - 1];
+                        const T zp = v == V - 1 ? zp0[j] : cur[j][k][v + 1];
+                        const T nb = ((prev[j][k][v] + nxt[j][k][v]) + (ym[j][v] + yp[j][v])) + (zm + zp);
+                        const T F = kL * fmad(cS, src[c], fmad(T(-6), w, nb));
+                        pnew[j][v] = fmad(kt, F, pc[j][k][v]);
+                    }
+                }
             }
             if (J.write_out) {
 #pragma unroll
-                for (int j = 0; j < NF; ++j) {
+                for (int j = 0; j < NA; ++j) {
                     if constexpr (RK) {
                         if (nt_store) {
                             vstore_nt(fout[j] + base + yrow[k], fnew[j]);
@@ -820,7 +863,7 @@ __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem
         for (int q = 0; q < NS; ++q) acc[q] += static_cast<double>(part[q]);
         __syncthreads();
 #pragma unroll
-        for (int j = 0; j < NF; ++j)
+        for (int j = 0; j < NA; ++j)
 #pragma unroll
             for (int k = 0; k < RY; ++k)
 #pragma unroll
@@ -852,7 +895,7 @@ __device__ __forceinline__ void march_tile(const TileJob& J, unsigned char* smem
 
 // NTB: the launch bound (256, or 512 for the tall one-row-per-thread tiles,
 // whose register footprint fits two waves per SIMD).
-template <typename T, int NF, int RY, int HI, int PD, int RK, int NTB>
+template <typename T, int NF, int RY, int HI, int PD, int RK, int NTB, int NG = 0>
 __global__ __launch_bounds__(NTB) void lattice_pass(PassArgs A) {
     constexpr int NS = kSumsPerField * NF + 1;
     const int nblocks = A.nbz * A.nby * A.nbx;
@@ -941,7 +984,7 @@ __global__ __launch_bounds__(NTB) void lattice_pass(PassArgs A) {
         }
     };
     // wide workgroups keep the halo ring at depth 2 (two waves per SIMD)
-    march_tile<T, NF, RY, HI, PD, RK, (NTB > 256 && PD > 2) ? 2 : PD>(J, smem_raw, acc, prelude);
+    march_tile<T, NF, RY, HI, PD, RK, (NTB > 256 && PD > 2) ? 2 : PD, NG>(J, smem_raw, acc, prelude);
     block_sum<NS>(acc, NT, tot);
     if (threadIdx.x == 0)
         for (int k = 0; k < NS; ++k) A.partials[(size_t)k * nblocks + bid] = tot[k];
@@ -1137,10 +1180,10 @@ __global__ __launch_bounds__(256) void ensemble_pass(EnsArgs E) {
 #pragma unroll
         for (int k = 0; k < NS; ++k) acc[k] = 0.0;
         if constexpr (MAXRY == 2) {
-            if (M.RY == 2) march_tile<T, NF, 2, 1, 4, 0, 4>(J, smem_raw, acc, [] {});
-            else march_tile<T, NF, 1, 1, 4, 0, 4>(J, smem_raw, acc, [] {});
+            if (M.RY == 2) march_tile<T, NF, 2, 1, 4, 0, 4, 0>(J, smem_raw, acc, [] {});
+            else march_tile<T, NF, 1, 1, 4, 0, 4, 0>(J, smem_raw, acc, [] {});
         } else {
-            march_tile<T, NF, 1, 1, 4, 0, 2>(J, smem_raw, acc, [] {});
+            march_tile<T, NF, 1, 1, 4, 0, 2, 0>(J, smem_raw, acc, [] {});
         }
         if (reduce_partials<NS>(acc, 256, M.partials, I.tile, M.nitems, M.ticket, tot) && threadIdx.x < 64)
             finish_pass(M.ph, M.sc, kt, kb, hn, E.rec >= 0 ? E.obs + (size_t)E.rec * E.nmembers + I.member : nullptr,
@@ -1261,6 +1304,16 @@ static hipError_t launch_pd(const PassArgs& a, const Tile& t, hipStream_t s, siz
 
 template <typename T, int NF>
 static hipError_t launch_nf(const PassArgs& a, const Tile& t, hipStream_t s, size_t lds) {
+    if (a.ng) {
+        // with the gravitational-wave tensor: one row per thread, depth 1,
+        // at most 256 threads (seven stencil arrays of registers per thread)
+        if (a.ng != 5 || a.rk || t.RY != 1 || t.PD != 1 || t.NT > 256) return hipErrorInvalidValue;
+        if (t.HI == 1)
+            hipLaunchKernelGGL((lattice_pass<T, NF, 1, 1, 1, 0, 256, 5>), dim3(t.nblocks()), dim3(t.NT), lds, s, a);
+        else
+            hipLaunchKernelGGL((lattice_pass<T, NF, 1, 2, 1, 0, 256, 5>), dim3(t.nblocks()), dim3(t.NT), lds, s, a);
+        return hipGetLastError();
+    }
     // (more than 256 threads: one row per thread, and 2 BZ + 2 TY <= NT)
     if (t.NT > 256) return launch_pd<T, NF, 1, 1, kMaxPassThreads>(a, t, s, lds);
     if (t.RY == 1) return t.HI == 1 ? launch_pd<T, NF, 1, 1>(a, t, s, lds) : launch_pd<T, NF, 1, 2>(a, t, s, lds);
@@ -1607,7 +1660,7 @@ hipError_t launch_pass(const PassArgs& a, const Tile& t, cl_precision prec, hipS
             return a.ph.nf == 1 ? launch_lowdim<float, 1>(a, t.nblocks(), s) : launch_lowdim<float, 2>(a, t.nblocks(), s);
         return a.ph.nf == 1 ? launch_lowdim<double, 1>(a, t.nblocks(), s) : launch_lowdim<double, 2>(a, t.nblocks(), s);
     }
-    const size_t lds = pass_lds_bytes(t, prec, a.ph.nf);
+    const size_t lds = pass_lds_bytes(t, prec, a.ph.nf + a.ng);
     if (prec == CL_FP32)
         return a.ph.nf == 1 ? launch_nf<float, 1>(a, t, s, lds) : launch_nf<float, 2>(a, t, s, lds);
     return a.ph.nf == 1 ? launch_nf<double, 1>(a, t, s, lds) : launch_nf<double, 2>(a, t, s, lds);

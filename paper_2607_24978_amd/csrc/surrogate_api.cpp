@@ -684,6 +684,7 @@ cl_status cl_surrogate_dataset_reserve(cl_surrogate* s, int N, int max_pairs) {
 static cl_status record(cl_surrogate* s, cl_lattice* h, bool input) {
     if (!s || !h) return sfail(CL_EINVAL, "NULL argument");
     if (h->dim != 3) return sfail(CL_EUNSUPPORTED, "the surrogate works on three-dimensional lattices");
+    if (h->ng) return sfail(CL_EUNSUPPORTED, "the surrogate takes lattices without the gravitational-wave tensor");
     if (!s->ds_fluct) return sfail(CL_ESTATE, "no dataset reserved");
     if (h->N != s->dsN || h->nf != s->cfg.n_fields) return sfail(CL_EINVAL, "lattice does not match the dataset");
     if (input == s->pending) return sfail(CL_ESTATE, input ? "input already recorded" : "no input recorded");
@@ -914,6 +915,7 @@ cl_status cl_surrogate_advance(cl_lattice* h, cl_surrogate* s, cl_integrator fal
                                double threshold, cl_observables* per_jump, cl_surrogate_report* rep) {
     if (!h || !s) return sfail(CL_EINVAL, "NULL argument");
     if (h->dim != 3) return sfail(CL_EUNSUPPORTED, "the surrogate works on three-dimensional lattices");
+    if (h->ng) return sfail(CL_EUNSUPPORTED, "the surrogate takes lattices without the gravitational-wave tensor");
     if (fallback != CL_LEAPFROG && fallback != CL_VV4)
         return sfail(CL_EINVAL, "the fallback integrator must be leapfrog or VV4");
     if (h->nf != s->cfg.n_fields) return sfail(CL_EINVAL, "lattice fields do not match the surrogate");
