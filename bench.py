@@ -519,6 +519,54 @@ def spectrum_run(w, reps=5):
             "hbm_frac": alg / sec / 1e9 / HBM_PEAK_GBS, "alg_bytes": alg}
 
 
+def gw_run(w, steps=200, warmup=20, tune=True):
+    """The 256^3 two-field FP32 VV4 workload with the gravitational-wave
+    tensor carried in the fused pass (five traceless components and their
+    momenta: 16 (n_fields + 5) bytes per site and pass), timed on the stream
+    the passes run on; then the cost of one binned wave spectrum."""
+    import torch
+    from paper_2607_24978_amd import _lib
+    stream = torch.cuda.Stream()
+    lat = _lib.Lattice(w.N, w.dx, w.n_fields, "fp32")
+    lat.set_stream(stream.cuda_stream)
+    lat.set_background(w.alpha, w.expansion, w.mp, w.a0)
+    lat.set_potential(w.m2, w.lam, w.g2, w.V0)
+    lat.gw_enable(True)
+    lat.seed(w.seed, w.fbar[:w.n_fields], w.pbar[:w.n_fields], w.cutoff_modes, w.amp)
+    if tune:
+        lat.autotune(reps=3)
+    tile = lat.get_tile()
+    lat.step(w.integrator, w.dt, warmup)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    t0 = time.perf_counter()
+    r = lat.step(w.integrator, w.dt, steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    per = 3 if w.integrator == "vv4" else 1
+    launches = steps * per + 1
+    bps = 16 * (w.n_fields + 5)
+    alg = (steps * per * bps + 12 * (w.n_fields + 5)) * w.sites
+    achieved = alg / launches / (ms / launches * 1e-3) / 1e9
+    lat.gw_spectrum()  # first call allocates
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 3
+    for _ in range(reps):
+        counts, rho, omega, tot = lat.gw_spectrum()
+    spec_ms = 1e3 * (time.perf_counter() - t0) / reps
+    lat.close()
+    return {"workload": w.name + "+gw", "steps": steps, "tile": tile, "bytes_per_site_pass": bps,
+            "site_updates_per_s": w.sites * steps / sec, "ms_per_step": 1e3 * sec / steps,
+            "hbm_frac": achieved / HBM_PEAK_GBS, "achieved_GBps": achieved, "finite": not bool(np.any(r["nonfinite"])),
+            "spectrum_ms": spec_ms, "rho_gw": tot, "omega_gw_max": float(np.max(omega)),
+            "rho_gw_over_rho": tot / float(r["EK"][-1].sum() + r["EG"][-1].sum() + r["EV"][-1])}
+
+
 def cpu_model() -> str:
     """CPU model name of the host (from /proc/cpuinfo)."""
     try:
@@ -702,6 +750,9 @@ def main():
     if args.workload == "c1":
         progress("power spectrum form")
         forms["spectrum"] = spectrum_run(w)
+    if args.workload == "c1":
+        progress("gravitational-wave form")
+        forms["gw"] = gw_run(w)
     if args.workload == "c1":
         progress("reduced 2+1 form")
         forms["lowdim_2d"] = lowdim_run(W.C4, 2000, 200)

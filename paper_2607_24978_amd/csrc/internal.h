@@ -127,9 +127,9 @@ struct EnsMember {
     int RY;              // rows per thread (1 or 2)
     double dt;
     Phys ph;
-    Scal* sc;
-    double* partials;    // nsums(nf) * nitems, slot = logical tile id
-    unsigned* ticket;
+    Scal* sc;            // the member's scalar block (start and end of a call)
+    Scal* scb;           // two scratch scalar blocks for the passes inside a call
+    double* partials;    // two halves of nsums(nf) * nitems, slot = logical tile id
 };
 
 struct EnsItem {
@@ -138,18 +138,26 @@ struct EnsItem {
 };
 
 // One pass over every member, in one persistent launch.  Kick and drift
-// steps are given in units of each member's dt.
+// steps are given in units of each member's dt.  As in a single lattice's
+// pass sequence, pass p leaves per-tile partial sums (half p mod 2) and the
+// scalar step that consumes them runs at the start of pass p + 1, in every
+// work item of the member alike (the item of tile 0 keeps the result and the
+// record), or in the closing finisher.
 struct EnsArgs {
     const EnsMember* members;
     const EnsItem* items;
     int nitems, nmembers;
-    int parity;  // pass index parity within the call
+    int parity;  // pass index within the call
     int drift, write_out, flags, rec;
     int lds_bytes;  // dynamic shared memory: the largest member tile
     double ckt, ckb, chn;
+    int prev_rec;                // record of the previous pass, -1: none
+    double pckt, pckb, pchn;     // its kick and drift coefficients (units of dt); pass 0: unused
     unsigned* counter;    // [0] work items handed out, [1] workgroups finished
     cl_observables* obs;  // [rec][member]
 };
+// One workgroup per member: the scalar step of the last pass of a call.
+hipError_t launch_ensemble_finish(const EnsArgs& a, int nf, hipStream_t s);
 
 // Scratch of a sequence of lattice passes: the workgroup partial sums (two
 // halves of `half` doubles, used by alternate passes), two scalar blocks that

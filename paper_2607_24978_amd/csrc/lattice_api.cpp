@@ -1498,7 +1498,7 @@ struct cl_ensemble {
     cl::EnsItem* d_items = nullptr;
     int nitems = 0;
     double* d_partials = nullptr;
-    unsigned* d_tickets = nullptr;
+    cl::Scal* d_scb = nullptr;      // two scratch scalar blocks per member
     unsigned* d_counter = nullptr;
     cl_observables* d_obs = nullptr;
     size_t obs_cap = 0;
@@ -1576,7 +1576,7 @@ cl_status ens_layout(cl_ensemble* e, int item_sites, bool two_rows) {
                                               " is too small for an ensemble tile (N >= 32 needed)");
         for (int k = 0; k < t.nitems; ++k) items.push_back({i, k});
         offs[i] = poff;
-        poff += static_cast<size_t>(cl::nsums(e->nf)) * t.nitems;
+        poff += 2 * static_cast<size_t>(cl::nsums(e->nf)) * t.nitems;  // two halves
         maxTY = std::max(maxTY, t.TY);
         maxTZ = std::max(maxTZ, t.TZ);
         table[i] = t;
@@ -1608,7 +1608,7 @@ cl_status ens_layout(cl_ensemble* e, int item_sites, bool two_rows) {
     }
     for (int i = 0; i < n; ++i) {
         table[i].partials = e->d_partials + offs[i];
-        table[i].ticket = e->d_tickets + i;
+        table[i].scb = e->d_scb + 2 * i;
     }
     EHIP(hipMemcpyAsync(e->d_items, items.data(), items.size() * sizeof(cl::EnsItem), hipMemcpyHostToDevice,
                         e->stream));
@@ -1649,7 +1649,7 @@ void ens_free(cl_ensemble* e) {
     if (e->stream) hipStreamSynchronize(e->stream);
     if (e->gexec) hipGraphExecDestroy(e->gexec);
     if (e->staging) hipHostFree(e->staging);
-    for (void* p : {(void*)e->d_table, (void*)e->d_items, (void*)e->d_partials, (void*)e->d_tickets,
+    for (void* p : {(void*)e->d_table, (void*)e->d_items, (void*)e->d_partials, (void*)e->d_scb,
                     (void*)e->d_counter, (void*)e->d_obs})
         if (p) hipFree(p);
     if (e->stream) hipStreamDestroy(e->stream);
@@ -1686,12 +1686,12 @@ cl_status cl_ensemble_create(int n, cl_lattice* const* members, cl_ensemble** ou
     e->dt.assign(n, 0.0);
     if (hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking) != hipSuccess)
         return bail(CL_EDEVICE, "hipStreamCreate failed");
-    if (hipMalloc(&e->d_tickets, n * sizeof(unsigned)) != hipSuccess ||
+    if (hipMalloc(&e->d_scb, 2 * n * sizeof(cl::Scal)) != hipSuccess ||
         hipMalloc(&e->d_counter, 64) != hipSuccess ||
         hipMalloc(&e->d_table, n * sizeof(cl::EnsMember)) != hipSuccess ||
         hipHostMalloc(&e->staging, n * sizeof(cl::EnsMember)) != hipSuccess)
         return bail(CL_ENOMEM, "ensemble device tables");
-    if (hipMemsetAsync(e->d_tickets, 0, n * sizeof(unsigned), e->stream) != hipSuccess ||
+    if (hipMemsetAsync(e->d_scb, 0, 2 * n * sizeof(cl::Scal), e->stream) != hipSuccess ||
         hipMemsetAsync(e->d_counter, 0, 64, e->stream) != hipSuccess ||
         hipStreamSynchronize(e->stream) != hipSuccess)
         return bail(CL_EDEVICE, "ensemble table upload");
@@ -1766,22 +1766,40 @@ cl_status cl_ensemble_step(cl_ensemble* e, cl_integrator integ, int n, cl_observ
         hipGraph_t g = nullptr;
         EHIP(hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal));
         hipError_t err = hipSuccess;
-        // opening half kick
+        // Pass 0 is the opening half kick, pass s + 1 drift step s; each pass
+        // runs the scalar step of the one before it at its start, and the
+        // finisher that of the last.
+        auto follow = [&](cl::EnsArgs& next, const cl::EnsArgs& prev) {
+            next.prev_rec = prev.rec;
+            next.pckt = prev.ckt;
+            next.pckb = prev.ckb;
+            next.pchn = prev.chn;
+        };
         a.parity = 0;
         a.drift = 0;
         a.rec = -1;
         a.ckt = 0.5 * c[0];
         a.ckb = 0.0;
         a.chn = c[0];
+        a.prev_rec = -1;
+        a.pckt = a.pckb = a.pchn = 0.0;
         if (err == hipSuccess) err = cl::launch_ensemble_pass(a, e->prec, e->nf, e->grid, e->maxry, e->stream);
         for (int s = 0; s < M && err == hipSuccess; ++s) {
-            a.parity = (s + 1) & 1;
-            a.drift = 1;
-            a.ckb = 0.5 * c[s];
-            a.ckt = s + 1 < M ? 0.5 * (c[s] + c[s + 1]) : 0.5 * c[s];
-            a.chn = s + 1 < M ? c[s + 1] : 0.0;
-            a.rec = ((s + 1) % per == 0) ? (s + 1) / per - 1 : -1;
-            err = cl::launch_ensemble_pass(a, e->prec, e->nf, e->grid, e->maxry, e->stream);
+            cl::EnsArgs d = a;
+            follow(d, a);
+            d.parity = s + 1;
+            d.drift = 1;
+            d.ckb = 0.5 * c[s];
+            d.ckt = s + 1 < M ? 0.5 * (c[s] + c[s + 1]) : 0.5 * c[s];
+            d.chn = s + 1 < M ? c[s + 1] : 0.0;
+            d.rec = ((s + 1) % per == 0) ? (s + 1) / per - 1 : -1;
+            err = cl::launch_ensemble_pass(d, e->prec, e->nf, e->grid, e->maxry, e->stream);
+            a = d;
+        }
+        if (err == hipSuccess) {
+            cl::EnsArgs f = a;
+            follow(f, a);
+            err = cl::launch_ensemble_finish(f, e->nf, e->stream);
         }
         hipError_t e2 = hipStreamEndCapture(e->stream, &g);
         if (err != hipSuccess || e2 != hipSuccess) {
@@ -1875,10 +1893,12 @@ cl_status cl_ensemble_autotune(cl_ensemble* e, int reps, char* report, size_t ca
             a.write_out = 1;
             a.flags = 1;
             a.rec = -1;
+            a.prev_rec = -1;  // no records: the scalar steps of these passes are not kept
             a.counter = e->d_counter;
             a.obs = nullptr;
             a.lds_bytes = static_cast<int>(e->lds);
             a.ckt = a.ckb = a.chn = 0.0;
+            a.pckt = a.pckb = a.pchn = 0.0;
             auto pair = [&]() {
                 hipError_t r = hipSuccess;
                 for (int q = 0; q < 2 && r == hipSuccess; ++q) {

@@ -362,29 +362,6 @@ __device__ __forceinline__ void slots_sum(const double* partials, int NT, int ns
     block_sum<NS>(s, NT, tot);
 }
 
-// Ticketed form (used by the ensemble kernel, whose members finish inside
-// the persistent launch): the workgroup's sums go to partial slot `slot` of
-// `nslots`, then a ticket; the last workgroup to arrive forms the totals in
-// `tot` with slots_sum and returns true.  Resets the ticket for the next pass.
-template <int NS>
-__device__ __forceinline__ bool reduce_partials(double (&acc)[NS], int NT, double* partials, int slot, int nslots, unsigned* ticket,
-                                double* tot) {
-    __shared__ double part[kMaxSums];
-    __shared__ int am_last;
-    block_sum<NS>(acc, NT, part);
-    if (threadIdx.x == 0) {
-        for (int k = 0; k < NS; ++k) partials[(size_t)k * nslots + slot] = part[k];
-        const unsigned t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        am_last = (t == (unsigned)(nslots - 1));
-    }
-    __syncthreads();
-    if (!am_last) return false;
-    __atomic_thread_fence(__ATOMIC_ACQUIRE);
-    slots_sum<NS>(partials, NT, nslots, tot);
-    if (threadIdx.x == 0) *ticket = 0u;
-    return true;
-}
-
 // Everything one workgroup does for one tile: march over CX x-planes of the
 // TZ x TY tile at (z0, y0, x0), drifting, kicking and writing the new state
 // and accumulating the per-thread lattice sums into `acc`.
@@ -1132,18 +1109,29 @@ Tile default_tile(int N, cl_precision prec, int nf) {
 
 // Persistent ensemble pass: workgroups take tiles of all members from one
 // work counter until none is left.  Each member has its own partial slots
-// and ticket; the workgroup that finishes a member's last tile sums that
-// member's slots in fixed order and advances its scale factor.  The last
+// (two halves, alternate passes); a work item first runs the member's scalar
+// step of the previous pass from those slots in fixed order (as the solo
+// pass does, so there is no cross-workgroup ticket and no device-scope
+// release per item), then marches its tile and leaves its sums.  The last
 // workgroup to leave resets the counters for the next pass.  MAXRY: the
 // largest rows per thread among the members; with one row everywhere the
 // kernel has only that path, with its halo ring at depth 2, and fits two
 // waves per SIMD.
+// Scalar blocks of an ensemble member inside a call: pass p starts from the
+// scalars pass p - 1 used (the member's own block for p = 1 and p = 0) and
+// leaves its own in scratch block p mod 2.
+__device__ __forceinline__ const Scal* ens_scal_before(const EnsMember& M, int pass) {
+    return pass <= 0 ? M.sc : M.scb + (pass & 1);
+}
+
 template <typename T, int NF, int MAXRY>
 __global__ __launch_bounds__(256) void ensemble_pass(EnsArgs E) {
     constexpr int NS = kSumsPerField * NF + 1;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double tot[kMaxSums];
+    __shared__ Scal s_sc;
     __shared__ int item_s;
+    const int pass = E.parity;
     for (;;) {
         __syncthreads();  // the previous tile no longer reads shared memory
         if (threadIdx.x == 0)
@@ -1154,10 +1142,10 @@ __global__ __launch_bounds__(256) void ensemble_pass(EnsArgs E) {
         if (it >= E.nitems) break;
         const EnsItem I = E.items[it];
         const EnsMember& M = E.members[I.member];
-        const double kt = E.ckt * M.dt, kb = E.ckb * M.dt, hn = E.chn * M.dt;
+        const double kt = E.ckt * M.dt, kb = E.ckb * M.dt;
         TileJob J;
-        J.in = M.buf[M.cur0 ^ E.parity];
-        J.out = M.buf[M.cur0 ^ E.parity ^ 1];
+        J.in = M.buf[M.cur0 ^ (pass & 1)];
+        J.out = M.buf[M.cur0 ^ (pass & 1) ^ 1];
         J.N = M.N;
         J.TZ = M.TZ;
         J.TY = M.TY;
@@ -1170,24 +1158,46 @@ __global__ __launch_bounds__(256) void ensemble_pass(EnsArgs E) {
         J.flags = E.flags;
         J.kt = kt;
         J.kb = kb;
-        J.sc = M.sc;
+        J.sc = &s_sc;
         J.ph = &M.ph;
         J.aux = nullptr;
         J.step0 = nullptr;
         J.rkA = J.rkB = J.rkC = J.rkD = J.rkh = 0.0;
         J.rk_first = J.rk_last = 0;
+        const size_t half = static_cast<size_t>(NS) * M.nitems;
+        // the member's scalars for this pass: the previous pass's scalar step
+        // (deferred), identically in every item of the member
+        auto prelude = [&]() {
+            copy_scal(&s_sc, ens_scal_before(M, pass - 1), 256);
+            if (pass > 0) {
+                slots_sum<NS>(M.partials + ((pass - 1) & 1) * half, 256, M.nitems, tot);
+                __syncthreads();
+                if (threadIdx.x < 64) {
+                    cl_observables* rec = (I.tile == 0 && E.prev_rec >= 0)
+                                              ? E.obs + (size_t)E.prev_rec * E.nmembers + I.member
+                                              : nullptr;
+                    finish_pass(M.ph, &s_sc, E.pckt * M.dt, E.pckb * M.dt, E.pchn * M.dt, rec, tot);
+                }
+                __syncthreads();
+                if (I.tile == 0) copy_scal(M.scb + (pass & 1), &s_sc, 256);
+            } else {
+                __syncthreads();
+            }
+        };
         double acc[NS];
 #pragma unroll
         for (int k = 0; k < NS; ++k) acc[k] = 0.0;
         if constexpr (MAXRY == 2) {
-            if (M.RY == 2) march_tile<T, NF, 2, 1, 4, 0, 4, 0>(J, smem_raw, acc, [] {});
-            else march_tile<T, NF, 1, 1, 4, 0, 4, 0>(J, smem_raw, acc, [] {});
+            if (M.RY == 2) march_tile<T, NF, 2, 1, 4, 0, 4, 0>(J, smem_raw, acc, prelude);
+            else march_tile<T, NF, 1, 1, 4, 0, 4, 0>(J, smem_raw, acc, prelude);
         } else {
-            march_tile<T, NF, 1, 1, 4, 0, 2, 0>(J, smem_raw, acc, [] {});
+            march_tile<T, NF, 1, 1, 4, 0, 2, 0>(J, smem_raw, acc, prelude);
         }
-        if (reduce_partials<NS>(acc, 256, M.partials, I.tile, M.nitems, M.ticket, tot) && threadIdx.x < 64)
-            finish_pass(M.ph, M.sc, kt, kb, hn, E.rec >= 0 ? E.obs + (size_t)E.rec * E.nmembers + I.member : nullptr,
-                        tot);
+        block_sum<NS>(acc, 256, tot);
+        if (threadIdx.x == 0) {
+            double* part = M.partials + (pass & 1) * half;
+            for (int k = 0; k < NS; ++k) part[(size_t)k * M.nitems + I.tile] = tot[k];
+        }
     }
     if (threadIdx.x == 0) {
         const unsigned done = __hip_atomic_fetch_add(&E.counter[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1196,6 +1206,34 @@ __global__ __launch_bounds__(256) void ensemble_pass(EnsArgs E) {
             __hip_atomic_store(&E.counter[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
+}
+
+// The scalar step of the last pass of an ensemble call, member blockIdx.x:
+// E.parity is that pass's index, E.prev_rec / E.pck* its record and
+// coefficients.
+template <int NS>
+__global__ __launch_bounds__(256) void ensemble_finish(EnsArgs E) {
+    __shared__ Scal s_sc;
+    __shared__ double tot[kMaxSums];
+    const int m = blockIdx.x;
+    const EnsMember& M = E.members[m];
+    const int pass = E.parity;
+    const size_t half = static_cast<size_t>(NS) * M.nitems;
+    copy_scal(&s_sc, ens_scal_before(M, pass), 256);
+    slots_sum<NS>(M.partials + (pass & 1) * half, 256, M.nitems, tot);
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        cl_observables* rec = E.prev_rec >= 0 ? E.obs + (size_t)E.prev_rec * E.nmembers + m : nullptr;
+        finish_pass(M.ph, &s_sc, E.pckt * M.dt, E.pckb * M.dt, E.pchn * M.dt, rec, tot);
+    }
+    __syncthreads();
+    copy_scal(M.sc, &s_sc, 256);
+}
+
+hipError_t launch_ensemble_finish(const EnsArgs& a, int nf, hipStream_t s) {
+    if (nf == 1) hipLaunchKernelGGL((ensemble_finish<kSumsPerField + 1>), dim3(a.nmembers), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((ensemble_finish<2 * kSumsPerField + 1>), dim3(a.nmembers), dim3(256), 0, s, a);
+    return hipGetLastError();
 }
 
 size_t ensemble_lds_bytes(cl_precision prec, int nf, int maxTY, int maxTZ) {
