@@ -255,6 +255,32 @@ def surrogate_forward_profile(N=256, reps=5):
             "wall_s_per_call_incl_host_copies": sec / reps, "finite": bool(np.all(np.isfinite(y)))}
 
 
+def surrogate_train_profile(N=128, pairs=4, epochs=5):
+    """Training steps of the 8-input surrogate at N^3 (pairs recorded from a
+    seeded two-field VV4 run) for a kernel-level profile of one training
+    step: forward with pre-activations, MSE gradient, weight gradients and
+    their reduction, input gradients through the hidden layers, GELU
+    derivative, Adam and the BF16 weight refresh."""
+    from paper_2607_24978_amd import _lib
+    K = 16
+    w = W.C1.with_(N=N, precision="fp64")
+    s = _lib.Surrogate(n_fields=2, extra_inputs=4, layers=5, jump_steps=K, init_seed=0)
+    s.dataset_reserve(N, pairs)
+    lat = _lib.Lattice(w.N, w.dx, 2, "fp64")
+    lat.set_background(w.alpha, w.expansion, w.mp, w.a0)
+    lat.set_potential(w.m2, w.lam, w.g2, w.V0)
+    lat.seed(w.seed, w.fbar[:2], w.pbar[:2], w.cutoff_modes, w.amp)
+    for _ in range(pairs):
+        s.record_input(lat)
+        lat.step("vv4", w.dt, K, record=False)
+        s.record_target(lat)
+    lat.close()
+    rep = s.train(epochs=epochs, lr=1e-3, lr_final=1e-5, shuffle_seed=0, holdout=0)
+    s.close()
+    return {"N": N, "steps": rep["steps"], "steps_per_s": rep["steps"] / rep["seconds"],
+            "flops_per_step": 3 * surrogate_flops_per_site(4) * N ** 3}
+
+
 def surrogate_run(epochs=12, pairs_per_seed=64, train_seeds=range(2000, 2008), eval_seed=3000, jumps=312,
                   extra_inputs=4, eval_256=True, ablation=False):
     """The learned surrogate on the two-field q = 100 workload: training pairs
@@ -352,11 +378,29 @@ def surrogate_run(epochs=12, pairs_per_seed=64, train_seeds=range(2000, 2008), e
         flops = surrogate_flops_per_site(extra_inputs) * w.sites * njumps
         forms["surrogate"] = {"effective_site_updates_per_s": w.sites * njumps * K / sec, "seconds": sec,
                               "fallbacks": srep["fallbacks"], "fallback_rate": srep["fallbacks"] / max(1, njumps),
+                              "accepted_fraction": 1.0 - srep["fallbacks"] / max(1, njumps),
+                              "fluct_gate_rejects": srep["fluct_rejects"],
                               "max_residual": srep["max_residual"], "error_vs_fp64_vv4": errs["max"],
                               "errors": errs, "field_error": _field_error(lat, ref),
                               "network_ms_per_jump": 1e3 * srep["net_seconds"] / max(1, njumps),
                               "network_tflops": flops / srep["net_seconds"] / 1e12,
                               "mfma_frac": flops / srep["net_seconds"] / MFMA_BF16_PEAK}
+        lat.close()
+        # the Hubble-residual gate alone (second gate off)
+        lat = lattice("fp32")
+        s.set_gate(0.0)
+        s.advance(lat, "vv4", w.dt, 1, threshold=1e-3)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        recs, srep = s.advance(lat, "vv4", w.dt, njumps, threshold=1e-3)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t1
+        s.set_gate(0.25)
+        errs = _scalar_errors(recs, rr, 2)
+        forms["surrogate_hubble_gate_only"] = {"effective_site_updates_per_s": w.sites * njumps * K / sec,
+                                               "accepted_fraction": 1.0 - srep["fallbacks"] / max(1, njumps),
+                                               "max_residual": srep["max_residual"],
+                                               "error_vs_fp64_vv4": errs["max"], "errors": errs}
         # the network alone: no residual gate (non-finite jumps still fall back), until the
         # evolution breaks down
         lat.close()
@@ -676,6 +720,8 @@ def main():
     ap.add_argument("--start-at", type=float, default=0.0, help=argparse.SUPPRESS)
     ap.add_argument("--sg-forward-profile", action="store_true",
                     help="only run surrogate forward passes at 256^3 (for a kernel profile) and print their figures")
+    ap.add_argument("--sg-train-profile", action="store_true",
+                    help="only run a few surrogate training steps at 128^3 (for a kernel profile) and print their figures")
     ap.add_argument("--cpu-procs", type=int, default=16, help="processes of the all-cores oracle baseline (0: skip)")
     ap.add_argument("--no-c3", action="store_true", help="skip the 1024^3 leapfrog leg of the default run")
     ap.add_argument("--workload", choices=["c1", "c3"], default="c1",
@@ -691,6 +737,9 @@ def main():
     torch.cuda.set_device(0)
     if args.sg_forward_profile:
         print(json.dumps(surrogate_forward_profile()), flush=True)
+        return
+    if args.sg_train_profile:
+        print(json.dumps(surrogate_train_profile()), flush=True)
         return
 
     from paper_2607_24978_amd import _lib

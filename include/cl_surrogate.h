@@ -67,6 +67,8 @@ typedef struct {
     double max_residual;   /* largest Hubble residual seen after a network jump */
     double seconds;        /* wall time of the call */
     double net_seconds;    /* device time of the network evaluations (HIP events) */
+    int fluct_rejects;     /* jumps the second gate (fluctuations) rejected */
+    int reserved;
 } cl_surrogate_report;
 
 /* Message for the last failing cl_surrogate_* call on this thread. */
@@ -151,10 +153,25 @@ cl_status cl_surrogate_load(cl_surrogate* s, const char* path);
  * a-independent volume sums <pi^2>/2, <(grad f)^2>/2, <V>, split into their
  * homogeneous part along the predictor's trajectory and the fluctuations'
  * share, which moves linearly from its start value to that of the new state.
- * If the Hubble-constraint residual at the endpoint exceeds `threshold` (or
- * any sum is non-finite) the jump is undone and the integrator `fallback`
- * (CL_LEAPFROG or CL_VV4) runs jump_steps steps instead.  per_jump (nullable)
- * receives one record per jump. */
+ * The endpoint's residual of the Hubble constraint (Eq. Friedmann2, the
+ * accuracy monitor of Sect. 2.1) is evaluated from those sums at the
+ * corrected a.  The jump is undone and the integrator `fallback` (CL_LEAPFROG
+ * or CL_VV4) runs jump_steps steps instead if any sum is non-finite, if the
+ * residual exceeds `threshold`, or if the second gate (cl_surrogate_set_gate)
+ * fails.  One reduction of the lattice per jump; the predictor runs on the
+ * host while the device evaluates the network.  per_jump (nullable) receives
+ * one record per jump. */
+/* Second gate of cl_surrogate_advance (an energy residual of the
+ * fluctuations, which the Hubble residual -- set by the homogeneous energy --
+ * hardly sees): a jump is also undone if any field's variance, or the energy
+ * of the fluctuations (lattice rho minus the homogeneous kinetic energy and
+ * the Gaussian-averaged potential of the means), changes over the jump by
+ * more than the relative tolerance fluct_tol against its start value
+ * (the energy redshifted as radiation over the jump).  Their physical change
+ * over one jump of 16 steps is a few per cent; default 0.25; <= 0 switches
+ * the gate off. */
+cl_status cl_surrogate_set_gate(cl_surrogate* s, double fluct_tol);
+
 cl_status cl_surrogate_advance(cl_lattice* h, cl_surrogate* s, cl_integrator fallback, double dt, int n_jumps,
                                double threshold, cl_observables* per_jump, cl_surrogate_report* rep);
 

@@ -72,7 +72,7 @@ class cl_surrogate_norm(C.Structure):
 
 class cl_surrogate_report(C.Structure):
     _fields_ = [("jumps", C.c_int), ("fallbacks", C.c_int), ("max_residual", C.c_double), ("seconds", C.c_double),
-                ("net_seconds", C.c_double)]
+                ("net_seconds", C.c_double), ("fluct_rejects", C.c_int), ("reserved", C.c_int)]
 
 
 OBS_DTYPE = np.dtype([("eta", "f8"), ("a", "f8"), ("H", "f8"), ("EK", "f8", 2), ("EG", "f8", 2), ("EV", "f8"),
@@ -135,6 +135,7 @@ _SIGS = {
     "cl_surrogate_train": (C.c_int, [_P, C.POINTER(cl_train_cfg), C.POINTER(cl_train_report)]),
     "cl_surrogate_save": (C.c_int, [_P, C.c_char_p]),
     "cl_surrogate_load": (C.c_int, [_P, C.c_char_p]),
+    "cl_surrogate_set_gate": (C.c_int, [_P, C.c_double]),
     "cl_surrogate_advance": (C.c_int, [_P, _P, C.c_int, C.c_double, C.c_int, C.c_double, _P,
                                        C.POINTER(cl_surrogate_report)]),
 }
@@ -437,6 +438,10 @@ class Surrogate:
 
     def load(self, path: str):
         _scheck(lib.cl_surrogate_load(self.s, path.encode()))
+
+    def set_gate(self, fluct_tol: float):
+        """Tolerance of the second (fluctuation) gate of advance(); <= 0 switches it off."""
+        _scheck(lib.cl_surrogate_set_gate(self.s, float(fluct_tol)))
 
     def advance(self, lat: "Lattice", fallback: str, dt: float, n_jumps: int, threshold: float = 1e-3):
         out = np.zeros(max(n_jumps, 0), dtype=OBS_DTYPE)

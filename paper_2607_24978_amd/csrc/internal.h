@@ -209,6 +209,10 @@ hipError_t launch_copy(const void* in, void* out, size_t bytes, hipStream_t s);
 cl_status step_in_work(cl_lattice* h, cl_integrator integ, double dt, int n, cl_observables* per_step, const Work& w);
 // Records the failure message on h (or the handle-less message) and returns st.
 cl_status set_error(cl_lattice* h, cl_status st, const char* msg);
+// Overwrite the background of h on its stream without waiting: a, a', eta,
+// the step count and the field means (the variance shift); the pass
+// coefficients follow from a.
+cl_status set_background_async(cl_lattice* h, double a, double b, double eta, int64_t step, const double* mean);
 
 // Host seed (host_seed.cpp): fills f, p (n_fields * N^3 FP64 each).
 // Returns an empty string on success, an error message otherwise.

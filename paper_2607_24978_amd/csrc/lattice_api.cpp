@@ -778,6 +778,14 @@ namespace cl {
 
 cl_status set_error(cl_lattice* h, cl_status st, const char* msg) { return fail(h, st, msg); }
 
+cl_status set_background_async(cl_lattice* h, double a, double b, double eta, int64_t step, const double* mean) {
+    cl_status st = init_scalars(h, a, b, eta, mean);
+    if (st) return st;
+    h->step = step;
+    note_background(h, a, mean);
+    return CL_OK;
+}
+
 cl_status step_in_work(cl_lattice* h, cl_integrator integ, double dt, int n, cl_observables* per_step,
                        const Work& w) {
     cl_status st = check_step(h, integ, dt, n);

@@ -89,6 +89,10 @@ struct cl_surrogate {
     // inference snapshot
     void* snap = nullptr;
     size_t snap_bytes = 0;
+    // second gate: largest relative change over a jump of each field's
+    // variance and of the fluctuations' energy (against its redshifted start
+    // value); <= 0 switches it off
+    double fluct_tol = 0.25;
 };
 
 namespace {
@@ -911,6 +915,13 @@ cl_status cl_surrogate_load(cl_surrogate* s, const char* path) {
     return cl_surrogate_set_params(s, th.data());
 }
 
+cl_status cl_surrogate_set_gate(cl_surrogate* s, double fluct_tol) {
+    if (!s) return sfail(CL_EINVAL, "NULL surrogate");
+    if (std::isnan(fluct_tol)) return sfail(CL_EINVAL, "fluct_tol is NaN");
+    s->fluct_tol = fluct_tol;
+    return CL_OK;
+}
+
 cl_status cl_surrogate_advance(cl_lattice* h, cl_surrogate* s, cl_integrator fallback, double dt, int n_jumps,
                                double threshold, cl_observables* per_jump, cl_surrogate_report* rep) {
     if (!h || !s) return sfail(CL_EINVAL, "NULL argument");
@@ -924,6 +935,7 @@ cl_status cl_surrogate_advance(cl_lattice* h, cl_surrogate* s, cl_integrator fal
     if (!(dt > 0.0) || n_jumps < 0) return sfail(CL_EINVAL, "dt > 0 and n_jumps >= 0 needed");
     const auto t0 = std::chrono::steady_clock::now();
     const int N = h->N, K = s->cfg.jump_steps;
+    const bool expand = h->mode == CL_SELF_CONSISTENT;
     cl_status st = ensure_bufs(s, N, false);
     if (st) return st;
     const size_t bytes = static_cast<size_t>(2 * h->nf) * N * N * N * (h->prec == CL_FP32 ? 4 : 8);
@@ -934,30 +946,33 @@ cl_status cl_surrogate_advance(cl_lattice* h, cl_surrogate* s, cl_integrator fal
         SHIP(hipMalloc(&s->snap, bytes));
         s->snap_bytes = bytes;
     }
-    int fallbacks = 0;
+    int fallbacks = 0, fluct_rejects = 0;
     double maxr = 0.0, net_ms = 0.0;
     cl_observables o;
     cl::Scal sc;
     st = read_lattice(h, &o, &sc);
     if (st) return st;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    SHIP(hipEventCreate(&ev0));
-    if (hipEventCreate(&ev1) != hipSuccess) {
-        hipEventDestroy(ev0);
-        return sfail(CL_EDEVICE, "hipEventCreate");
-    }
-    struct EvGuard {
-        hipEvent_t a, b;
-        ~EvGuard() {
-            hipEventDestroy(a);
-            hipEventDestroy(b);
+    cl_scalars bg;
+    st = cl_get_state(h, &bg);
+    if (st) return sfail(st, cl_last_error(h));
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // network start / end (timing), packed input ready
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            for (auto& x : ev)
+                if (x) hipEventDestroy(x);
+            return sfail(CL_EDEVICE, "hipEventCreate");
         }
-    } ev_guard{ev0, ev1};
+    struct EvGuard {
+        hipEvent_t* e;
+        ~EvGuard() {
+            for (int i = 0; i < 3; ++i) hipEventDestroy(e[i]);
+        }
+    } ev_guard{ev};
+    const double al = h->alpha, mp2 = h->mp * h->mp;
     for (int j = 0; j < n_jumps; ++j) {
-        cl_scalars bg;
-        cl_get_state(h, &bg);
         SHIP(hipMemcpyAsync(s->snap, h->buf[h->cur], bytes, hipMemcpyDeviceToDevice, h->stream));
-        // network input from the current state
+        // network input from the current state, then the network on the
+        // surrogate's stream while the host runs the predictor
         cl::sg::PackArgs pa{};
         pa.state = h->buf[h->cur];
         pa.N = N;
@@ -973,15 +988,13 @@ cl_status cl_surrogate_advance(cl_lattice* h, cl_surrogate* s, cl_integrator fal
         for (int k = 0; k < pa.nextra; ++k) pa.extra[k] = static_cast<float>((e[k] - s->ex_mean[k]) / s->ex_std[k]);
         pa.x_out = s->x0;
         SHIP(cl::sg::launch_pack_state(pa, h->prec == CL_FP32, h->stream));
-        SHIP(hipStreamSynchronize(h->stream));
-        SHIP(hipEventRecord(ev0, s->stream));
+        SHIP(hipEventRecord(ev[2], h->stream));
+        SHIP(hipStreamWaitEvent(s->stream, ev[2], 0));
+        SHIP(hipEventRecord(ev[0], s->stream));
         st = forward(s, N, false);
         if (st) return st;
-        SHIP(hipEventRecord(ev1, s->stream));
-        SHIP(hipEventSynchronize(ev1));
-        float ms = 0.0f;
-        SHIP(hipEventElapsedTime(&ms, ev0, ev1));
-        net_ms += ms;
+        SHIP(hipEventRecord(ev[1], s->stream));
+        SHIP(hipStreamWaitEvent(h->stream, ev[1], 0));
         // predictor: homogeneous modes and background over the jump, in FP64
         double f[2] = {o.mean[0], o.mean[1]}, pm[2] = {sc.mean_p[0], sc.mean_p[1]}, var[2] = {o.var[0], o.var[1]};
         double rho_hom_K = 0.0;
@@ -1005,39 +1018,85 @@ cl_status cl_surrogate_advance(cl_lattice* h, cl_surrogate* s, cl_integrator fal
         ua.y = s->y;
         ua.ystride = ystride(s);
         SHIP(cl::sg::launch_unpack_jump(ua, h->prec == CL_FP32, h->stream));
-        SHIP(hipStreamSynchronize(h->stream));
+        const double eta1 = bg.eta + K * dt;
+        const int64_t step1 = bg.step + K;
         // a prediction that leaves the background non-finite or a <= 0 is rejected outright
         bool ok = std::isfinite(a) && std::isfinite(b) && a > 0.0;
         cl_observables after{};
         cl::Scal sca{};
+        const double a_pred = a;
         if (ok) {
-            const cl_scalars pred{a, b, bg.eta + K * dt, bg.step + K};
-            st = cl_set_state(h, &pred);
+            // one reduction of the new state (at the predicted a; the sums
+            // that the corrector needs do not depend on a)
+            st = cl::set_background_async(h, a_pred, b, eta1, step1, f);
             if (st) return sfail(st, cl_last_error(h));
             st = read_lattice(h, &after, &sca);
             if (st) return st;
             ok = !after.nonfinite;
+        } else {
+            SHIP(hipStreamSynchronize(h->stream));
         }
-        if (ok && h->mode == CL_SELF_CONSISTENT) {
+        float ms = 0.0f;
+        SHIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+        net_ms += ms;
+        double S1[3] = {0.0, 0.0, 0.0};
+        if (ok) volume_sums(after, S1);
+        if (ok && expand) {
             // corrector: background re-integrated against the start and endpoint sums
-            double S0[3], S1[3];
+            double S0[3];
             volume_sums(o, S0);
-            volume_sums(after, S1);
             a = bg.a;
             b = bg.b;
             correct_background(h, fallback, dt, K, S0, S1, hom, a, b);
             ok = std::isfinite(a) && std::isfinite(b) && a > 0.0;
-            if (ok) {
-                const cl_scalars corr{a, b, bg.eta + K * dt, bg.step + K};
-                st = cl_set_state(h, &corr);
-                if (st) return sfail(st, cl_last_error(h));
-                st = read_lattice(h, &after, &sca);
-                if (st) return st;
-            }
         }
-        const double r = ok ? after.hubble_residual : std::nan("");
-        if (std::isfinite(r)) maxr = std::max(maxr, r);
-        if (!ok || !(r <= threshold) || after.nonfinite) {
+        // the endpoint's observables at the corrected a, and its Hubble residual
+        double r = std::nan("");
+        cl_observables rec = after;
+        if (ok) {
+            const double sK = std::pow(a_pred / a, 6.0), sG = (a_pred / a) * (a_pred / a);
+            for (int jf = 0; jf < 2; ++jf) {
+                rec.EK[jf] = after.EK[jf] * sK;
+                rec.EG[jf] = after.EG[jf] * sG;
+            }
+            rec.a = a;
+            rec.H = expand ? b / a : 0.0;
+            rec.eta = eta1;
+            if (expand) {
+                const double rho = S1[0] / std::pow(a, 6.0) + S1[1] / (a * a) + S1[2];
+                const double rhs = std::pow(a, 2.0 * al) * rho / (3.0 * mp2);
+                r = std::fabs((b / a) * (b / a) - rhs) / rhs;
+            } else {
+                r = 0.0;
+            }
+            rec.hubble_residual = r;
+            maxr = std::max(maxr, r);
+        }
+        // second gate: the fluctuations' variance and energy may move only so
+        // far over one jump (their physical change over 16 steps is a few per cent)
+        bool fluct_ok = true;
+        if (ok && s->fluct_tol > 0.0) {
+            for (int jf = 0; jf < h->nf; ++jf)
+                if (o.var[jf] > 0.0 && !(std::fabs(after.var[jf] / o.var[jf] - 1.0) <= s->fluct_tol)) fluct_ok = false;
+            double pm1[2] = {sca.mean_p[0], sca.mean_p[1]}, f1[2] = {after.mean[0], after.mean[1]},
+                   v1[2] = {after.var[0], after.var[1]};
+            double K1 = 0.0;
+            for (int jf = 0; jf < h->nf; ++jf) K1 += pm1[jf] * pm1[jf] / (2.0 * std::pow(a, 6.0));
+            const double rho1 = rec.EK[0] + rec.EK[1] + rec.EG[0] + rec.EG[1] + rec.EV;
+            const double fl1 = rho1 - K1 - hom_V(h, f1, v1);
+            const double fl_pred = rho_r0 * std::pow(bg.a / a, 4.0);
+            if (fl_pred > 0.0 && !(std::fabs(fl1 / fl_pred - 1.0) <= s->fluct_tol)) fluct_ok = false;
+            if (!fluct_ok) ++fluct_rejects;
+        }
+        if (ok && r <= threshold && fluct_ok) {
+            // accept: the corrected background goes to the device
+            st = cl::set_background_async(h, a, b, eta1, step1, after.mean);
+            if (st) return sfail(st, cl_last_error(h));
+            if (per_jump) per_jump[j] = rec;
+            o = rec;
+            sc = sca;
+            bg = cl_scalars{a, b, eta1, step1};
+        } else {
             // undo the jump (state and scalar block) and run the integrator instead
             SHIP(hipMemcpyAsync(h->buf[h->cur], s->snap, bytes, hipMemcpyDeviceToDevice, h->stream));
             SHIP(hipMemcpyAsync(h->sc, &sc, sizeof(cl::Scal), hipMemcpyHostToDevice, h->stream));
@@ -1048,21 +1107,21 @@ cl_status cl_surrogate_advance(cl_lattice* h, cl_surrogate* s, cl_integrator fal
             st = cl_step(h, fallback, dt, K, recs.data());
             if (st) return sfail(st, cl_last_error(h));
             ++fallbacks;
-            st = read_lattice(h, &after, &sca);
-            if (st) return st;
-            if (per_jump) per_jump[j] = recs.back();
-        } else if (per_jump) {
-            per_jump[j] = after;
+            o = recs.back();
+            SHIP(hipMemcpyAsync(&sc, h->sc, sizeof(cl::Scal), hipMemcpyDeviceToHost, h->stream));
+            SHIP(hipStreamSynchronize(h->stream));
+            bg = cl_scalars{sc.a, sc.b, sc.eta, h->step};
+            if (per_jump) per_jump[j] = o;
         }
-        o = after;
-        sc = sca;
     }
+    SHIP(hipStreamSynchronize(h->stream));
     if (rep) {
         rep->jumps = n_jumps;
         rep->fallbacks = fallbacks;
         rep->max_residual = maxr;
         rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         rep->net_seconds = 1e-3 * net_ms;
+        rep->fluct_rejects = fluct_rejects;
     }
     return CL_OK;
 }

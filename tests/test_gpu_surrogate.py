@@ -331,6 +331,7 @@ def test_accepted_jump_exact_against_oracle():
     sg.set_params(theta)
     out_scale = [2e-4, 1e-4, 3e-3, 1e-3]
     sg.set_normalisation([1e-2] * 4, out_scale)
+    sg.set_gate(0.0)  # arithmetic parity: no gating
     recs, rep = sg.advance(lat, "vv4", w.dt, 2, threshold=float("inf"))
     assert rep["fallbacks"] == 0
     f, p = lat.get_fields()
@@ -380,6 +381,7 @@ def test_accepted_jump_network_against_oracle():
     out_scale = [1e-3 * r for r in rms]
     ex_mean, ex_std = [1.0, 0.3, 1.0, 0.0], [0.5, 0.2, 0.5, 0.1]
     sg.set_normalisation(in_scale, out_scale, ex_mean, ex_std)
+    sg.set_gate(0.0)  # arithmetic parity: no gating
     recs, rep = sg.advance(lat, "vv4", w.dt, 1, threshold=float("inf"))
     assert rep["fallbacks"] == 0
     f, p = lat.get_fields()
@@ -405,3 +407,35 @@ def test_accepted_jump_network_against_oracle():
     assert abs(recs["r"][0] - r) <= 1e-8
     lat.close()
     sg.close()
+
+
+def test_fluctuation_gate():
+    """The second gate sees what the Hubble residual does not: with the
+    residual gate off (threshold = inf), a network whose increments are
+    twice the fluctuations (variance changed far beyond 25 %) is refused and
+    the integrator runs instead -- bitwise the integrator's result -- while
+    increments of 1e-3 of the fluctuations pass."""
+    lib = _lib()
+    chans = [8, 32, 4]
+    for scale, expect_fallback in ((2.0, True), (1e-3, False)):
+        w, P, s0, lat = _jump_lattice()
+        sg = lib.Surrogate(n_fields=2, extra_inputs=4, layers=2, jump_steps=16, init_seed=8)
+        rng = np.random.default_rng(4)
+        params = [(Wt, rng.uniform(-0.1, 0.1, b.shape)) for Wt, b in unflatten(sg.get_params(), chans)]
+        sg.set_params(np.concatenate([np.concatenate([Wt.ravel(), b]) for Wt, b in params]).astype(np.float32))
+        rms = [float(np.std(c)) for c in (s0.f[0], s0.f[1], s0.p[0], s0.p[1])]
+        y_rms = float(np.std(sg.forward(np.zeros((8, 16, 16, 16), np.float32) + 0.3)))
+        sg.set_normalisation(rms, [scale * r / max(y_rms, 1e-6) for r in rms])
+        sg.set_gate(0.25)
+        recs, rep = sg.advance(lat, "vv4", w.dt, 1, threshold=float("inf"))
+        assert rep["fallbacks"] == (1 if expect_fallback else 0), (scale, rep)
+        assert rep["fluct_rejects"] == (1 if expect_fallback else 0), (scale, rep)
+        if expect_fallback:
+            ref = _lib().Lattice(w.N, w.dx, 2, "fp64")
+            ref.set_potential(w.m2, w.lam, w.g2, w.V0)
+            ref.set_fields(s0.f, s0.p)
+            ref.step("vv4", w.dt, 16)
+            assert np.array_equal(lat.get_fields()[0], ref.get_fields()[0])
+            ref.close()
+        lat.close()
+        sg.close()
