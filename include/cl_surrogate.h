@@ -94,9 +94,12 @@ cl_status cl_surrogate_forward(cl_surrogate* s, int N, const float* x, float* y)
  * not NULL it receives the gradient with respect to the input x (c_in
  * channels, the layout of x).  N a power of two >= 32 (as for every
  * training call).  Backward pass: output gradient and the GELU-scaled layer
- * gradients rounded to BF16, weight gradients as FP32 sums over sites of
- * their products with the BF16 layer inputs, input gradients as FP32
- * convolutions with the flipped, transposed BF16 weights. */
+ * gradients rounded to BF16 (GELU' taken at the pre-activations as kept by
+ * the forward pass, rounded to BF16), weight gradients as FP32 sums over
+ * sites of their products with the BF16 layer inputs, input gradients as FP32
+ * convolutions with the flipped, transposed BF16 weights.  GELU and GELU'
+ * evaluate the normal distribution function through a rational-exponential
+ * erfc approximation of relative error below 1.2e-7. */
 cl_status cl_surrogate_loss_grad(cl_surrogate* s, int N, const float* x, const float* t, double* loss,
                                  float* grad, float* grad_x);
 

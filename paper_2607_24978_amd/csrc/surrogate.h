@@ -15,7 +15,12 @@ struct ConvArgs {
     const void* w;       // BF16 [o][nb*16][cin]
     const float* bias;   // [>= cout] or null
     float* z_out;        // FP32 [site][z_stride] (pre-activation) or null
+    void* zh_out;        // BF16 [site][zh_stride] pre-activation (kept for the backward pass) or null
+    int zh_stride;
     void* a_out;         // BF16 [site][a_stride] (GELU(z) if gelu, else z) or null
+    const void* gz;      // BF16 [site][gz_stride] or null: a_out = z * GELU'(gz) (input gradient
+                         // through the activation of the layer below)
+    int gz_stride;
     int N;
     int nsites;          // N^3, a multiple of 16
     int cout;            // output channels stored (multiple of 4)
@@ -26,11 +31,20 @@ struct ConvArgs {
 struct WgradArgs {
     const void* dz;      // BF16 [site][cout_stride]
     const void* x;       // BF16 [site][cin]
-    float* partials;     // [grid][partial_stride]
+    float* partials;     // [WgradShape::parts][partial_stride]
     int N, nsites;
     int cout_stride;
-    int partial_stride;  // >= 27*coutp*cinp + coutp
+    int partial_stride;  // WgradShape::stride
+    int L;               // x planes per workgroup (WgradShape::L)
 };
+
+// Launch shape of the weight-gradient kernel on an N^3 lattice (N a multiple
+// of 32): workgroups, x planes each marches over, partial-sum slots written
+// and their stride (27*coutp*cinp + coutp floats).
+struct WgradShape {
+    int grid, L, parts, stride;
+};
+WgradShape wgrad_shape(int N, int cin, int cout_stride);
 
 struct WgradReduceArgs {
     const float* partials;
@@ -82,9 +96,8 @@ struct UnpackArgs {
 };
 
 hipError_t launch_conv_fwd(const ConvArgs& a, int cin, int nb, int grid, hipStream_t s);
-hipError_t launch_conv_wgrad(const WgradArgs& a, int cin, int nb, int grid, hipStream_t s);
+hipError_t launch_conv_wgrad(const WgradArgs& a, int cin, hipStream_t s);
 hipError_t launch_wgrad_reduce(const WgradReduceArgs& a, hipStream_t s);
-hipError_t launch_gelu_backward(const float* da, const float* z, void* dz, size_t n, hipStream_t s);
 hipError_t launch_mse_grad(const float* y, int ystride, const float* t, int cout, size_t nsites, double scale,
                            void* dy, double* partial, int grid, hipStream_t s);
 hipError_t launch_adam(float* theta, const float* grad, float* m, float* v, int n, float lr, float b1, float b2,

@@ -27,6 +27,8 @@ namespace sg {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+// staging registers: a plain vector type, which (unlike uint4) is promoted to VGPRs
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint16_t f2bf(float f) {
     // round to nearest, ties to even (finite values)
@@ -37,6 +39,18 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __builtin_bit_cast(float, static_cast<uint32_t>(h) << 16); }
 
+// 4 BF16 values packed in two words <-> FP32
+__device__ __forceinline__ uint2 pack4(const uint16_t* h) {
+    return make_uint2(static_cast<uint32_t>(h[0]) | (static_cast<uint32_t>(h[1]) << 16),
+                      static_cast<uint32_t>(h[2]) | (static_cast<uint32_t>(h[3]) << 16));
+}
+__device__ __forceinline__ void unpack4(uint2 u, float* f) {
+    f[0] = __builtin_bit_cast(float, u.x << 16);
+    f[1] = __builtin_bit_cast(float, u.x & 0xFFFF0000u);
+    f[2] = __builtin_bit_cast(float, u.y << 16);
+    f[3] = __builtin_bit_cast(float, u.y & 0xFFFF0000u);
+}
+
 __device__ __forceinline__ bf16x8 load8(const uint16_t* p) {
     const uint4 v = *reinterpret_cast<const uint4*>(p);
     return __builtin_bit_cast(bf16x8, v);
@@ -44,10 +58,39 @@ __device__ __forceinline__ bf16x8 load8(const uint16_t* p) {
 
 __device__ __forceinline__ bf16x8 zero8() { return __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0)); }
 
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+// GELU(z) = z Phi(z) and GELU'(z) = Phi(z) + z phi(z) (Phi, phi: standard
+// normal distribution and density).  The epilogues evaluate them for every
+// output, so Phi goes through erfc(x), x = |z|/sqrt 2, in the Chebyshev-fitted
+// form t exp(-x^2 + P(t)), t = 1/(1 + x/2), of Press et al. (Numerical Recipes,
+// erfcc; relative error below 1.2e-7 for all x >= 0, so also in the negative
+// tail where Phi is small), with the hardware reciprocal and exp2: one rcp, two
+// exp2 and ten FMAs instead of the library's branchy erff and expf.
+__device__ __forceinline__ float phi_cdf(float z, float* dens) {
+    const float x = fabsf(z) * 0.70710678118654752f;
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.5f, x, 1.0f));
+    float p = 0.17087277f;
+    p = fmaf(p, t, -0.82215223f);
+    p = fmaf(p, t, 1.48851587f);
+    p = fmaf(p, t, -1.13520398f);
+    p = fmaf(p, t, 0.27886807f);
+    p = fmaf(p, t, -0.18628806f);
+    p = fmaf(p, t, 0.09678418f);
+    p = fmaf(p, t, 0.37409196f);
+    p = fmaf(p, t, 1.00002368f);
+    p = fmaf(p, t, -1.26551223f);
+    constexpr float kLog2e = 1.4426950408889634f;
+    const float mx2 = -x * x;
+    const float half_erfc = 0.5f * t * __builtin_amdgcn_exp2f((mx2 + p) * kLog2e);
+    if (dens) *dens = 0.39894228040143268f * __builtin_amdgcn_exp2f(mx2 * kLog2e);
+    return z >= 0.f ? 1.0f - half_erfc : half_erfc;
+}
+
+__device__ __forceinline__ float gelu(float z) { return z * phi_cdf(z, nullptr); }
 
 __device__ __forceinline__ float gelu_grad(float z) {
-    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+    float d;
+    const float c = phi_cdf(z, &d);
+    return c + z * d;
 }
 
 // Periodic neighbour of site (x, y, z) at stencil offset o.
@@ -130,10 +173,21 @@ __global__ __launch_bounds__(256) void conv_fwd(ConvArgs a) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) v[r] = acc[q][b][r] + (a.bias ? a.bias[c0 + r] : 0.f);
                 if (a.z_out) *reinterpret_cast<float4*>(a.z_out + site * a.z_stride + c0) = make_float4(v[0], v[1], v[2], v[3]);
+                if (a.zh_out) {
+                    const uint16_t zh[4] = {f2bf(v[0]), f2bf(v[1]), f2bf(v[2]), f2bf(v[3])};
+                    *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(a.zh_out) + site * a.zh_stride + c0) = pack4(zh);
+                }
                 if (a.a_out) {
                     uint16_t h[4];
+                    if (a.gz) {
+                        float zv[4];
+                        unpack4(*reinterpret_cast<const uint2*>(reinterpret_cast<const uint16_t*>(a.gz) + site * a.gz_stride + c0), zv);
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) h[r] = f2bf(a.gelu ? gelu(v[r]) : v[r]);
+                        for (int r = 0; r < 4; ++r) h[r] = f2bf(v[r] * gelu_grad(zv[r]));
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) h[r] = f2bf(a.gelu ? gelu(v[r]) : v[r]);
+                    }
                     uint2 pk;
                     pk.x = static_cast<uint32_t>(h[0]) | (static_cast<uint32_t>(h[1]) << 16);
                     pk.y = static_cast<uint32_t>(h[2]) | (static_cast<uint32_t>(h[3]) << 16);
@@ -153,7 +207,7 @@ __global__ __launch_bounds__(256) void conv_fwd(ConvArgs a) {
 // registers, and every input fragment it reads from LDS feeds the
 // three output rows it is a neighbour of.
 template <int RY, int NB>
-__global__ __launch_bounds__(256) void conv32_fwd_tiled(ConvArgs a) {
+__global__ __launch_bounds__(256, 2) void conv32_fwd_tiled(ConvArgs a) {
     constexpr int ZR = 18, YR = RY + 2, PL = 6;
     __shared__ __align__(16) uint16_t tin[PL * YR * ZR * 32];
     const uint16_t* __restrict__ in = reinterpret_cast<const uint16_t*>(a.in);
@@ -168,9 +222,18 @@ __global__ __launch_bounds__(256) void conv32_fwd_tiled(ConvArgs a) {
     const int x0 = tx * 4, y0 = ty * RY, z0 = tz * 16;
     constexpr int CHUNKS = PL * YR * ZR * 4;  // 16-byte chunks (8 channels)
     constexpr int ITER = (CHUNKS + 255) / 256;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int n = lane & 15, g = lane >> 4;
+    // the weights of dx = 0 first: they do not depend on the block and are in
+    // flight with its loads
+    bf16x8 wa[9][NB];
+#pragma unroll
+    for (int j = 0; j < 9; ++j)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) wa[j][b] = load8(wg + static_cast<size_t>(j * NB * 16 + 16 * b + n) * 32 + 8 * g);
     // all loads of the tile first, then all LDS stores: the loads are in
     // flight together instead of one round trip per chunk
-    uint4 v[ITER];
+    u32x4 v[ITER];
 #pragma unroll
     for (int k = 0; k < ITER; ++k) {
         // past the last chunk a thread re-reads it (in bounds) and stores nothing
@@ -184,16 +247,16 @@ __global__ __launch_bounds__(256) void conv32_fwd_tiled(ConvArgs a) {
         xx = xx < 0 ? xx + N : (xx >= N ? xx - N : xx);
         yy = yy < 0 ? yy + N : (yy >= N ? yy - N : yy);
         zz = zz < 0 ? zz + N : (zz >= N ? zz - N : zz);
-        v[k] = *reinterpret_cast<const uint4*>(in + static_cast<size_t>((xx * N + yy) * N + zz) * 32 + c4 * 8);
+        v[k] = *reinterpret_cast<const u32x4*>(in + static_cast<size_t>((xx * N + yy) * N + zz) * 32 + c4 * 8);
     }
+    __builtin_amdgcn_sched_barrier(0);  // every load issued before the first store waits
 #pragma unroll
     for (int k = 0; k < ITER; ++k) {
         const int i = threadIdx.x + k * 256;
-        if (i < CHUNKS) *reinterpret_cast<uint4*>(tin + static_cast<size_t>(i) * 8) = v[k];
+        if (i < CHUNKS) *reinterpret_cast<u32x4*>(tin + static_cast<size_t>(i) * 8) = v[k];
     }
     __syncthreads();
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int n = lane & 15, g = lane >> 4;
+    uint2 zg[RY][NB];
     f32x4 acc[RY][NB];
 #pragma unroll
     for (int r = 0; r < RY; ++r)
@@ -201,12 +264,26 @@ __global__ __launch_bounds__(256) void conv32_fwd_tiled(ConvArgs a) {
         for (int b = 0; b < NB; ++b) acc[r][b] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int dx = 0; dx < 3; ++dx) {
-        bf16x8 wa[9][NB];
+        // the next dx's weights load during this dx's MFMAs
+        bf16x8 wn[9][NB];
+        if (dx < 2) {
 #pragma unroll
-        for (int j = 0; j < 9; ++j)
+            for (int j = 0; j < 9; ++j)
 #pragma unroll
-            for (int b = 0; b < NB; ++b)
-                wa[j][b] = load8(wg + static_cast<size_t>((dx * 9 + j) * NB * 16 + 16 * b + n) * 32 + 8 * g);
+                for (int b = 0; b < NB; ++b)
+                    wn[j][b] = load8(wg + static_cast<size_t>(((dx + 1) * 9 + j) * NB * 16 + 16 * b + n) * 32 + 8 * g);
+        } else if (a.gz) {
+            // the pre-activations the input gradient's epilogue needs (the
+            // registers of the weight prefetch are free in the last dx)
+#pragma unroll
+            for (int r = 0; r < RY; ++r)
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+                    zg[r][b] = *reinterpret_cast<const uint2*>(reinterpret_cast<const uint16_t*>(a.gz) +
+                                                               static_cast<size_t>(((x0 + w) * N + y0 + r) * N + z0 + n) *
+                                                                   a.gz_stride + 16 * b + 4 * g);
+        }
+        __builtin_amdgcn_sched_barrier(0);  // keep them ahead of the MFMAs
         const uint16_t* pl = tin + (w + dx) * YR * ZR * 32;
 #pragma unroll
         for (int yi = 0; yi < YR; ++yi)
@@ -222,8 +299,51 @@ __global__ __launch_bounds__(256) void conv32_fwd_tiled(ConvArgs a) {
                         acc[r][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[dy * 3 + dz][b], xb, acc[r][b], 0, 0, 0);
                 }
             }
+        if (dx < 2) {
+#pragma unroll
+            for (int j = 0; j < 9; ++j)
+#pragma unroll
+                for (int b = 0; b < NB; ++b) wa[j][b] = wn[j][b];
+        }
     }
+    // this lane's bias values, all loaded before the first store (which the
+    // compiler cannot prove does not alias them)
+    float bias[NB][4];
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = 16 * b + 4 * g + q;
+            bias[b][q] = (a.bias && c < a.cout) ? a.bias[c] : 0.f;
+        }
+    // epilogue: every output value first, then all stores back to back (each
+    // from registers of its own, so that no store waits for an earlier one)
     const int x = x0 + w;
+    f32x4 zf[RY][NB];
+    uint2 zh[RY][NB], ao[RY][NB];
+#pragma unroll
+    for (int r = 0; r < RY; ++r)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            float v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] = acc[r][b][q] + bias[b][q];
+            zf[r][b] = f32x4{v[0], v[1], v[2], v[3]};
+            const uint16_t hz[4] = {f2bf(v[0]), f2bf(v[1]), f2bf(v[2]), f2bf(v[3])};
+            zh[r][b] = pack4(hz);
+            uint16_t h[4];
+            if (a.gz) {
+                float zv[4];
+                unpack4(zg[r][b], zv);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) h[q] = f2bf(v[q] * gelu_grad(zv[q]));
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) h[q] = f2bf(a.gelu ? gelu(v[q]) : v[q]);
+            }
+            ao[r][b] = pack4(h);
+        }
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
         const size_t site = static_cast<size_t>((x * N + y0 + r) * N + z0 + n);
@@ -231,19 +351,9 @@ __global__ __launch_bounds__(256) void conv32_fwd_tiled(ConvArgs a) {
         for (int b = 0; b < NB; ++b) {
             const int c0 = 16 * b + 4 * g;
             if (c0 >= a.cout) continue;
-            float v[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) v[q] = acc[r][b][q] + (a.bias ? a.bias[c0 + q] : 0.f);
-            if (a.z_out) *reinterpret_cast<float4*>(a.z_out + site * a.z_stride + c0) = make_float4(v[0], v[1], v[2], v[3]);
-            if (a.a_out) {
-                uint16_t h[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) h[q] = f2bf(a.gelu ? gelu(v[q]) : v[q]);
-                uint2 pk;
-                pk.x = static_cast<uint32_t>(h[0]) | (static_cast<uint32_t>(h[1]) << 16);
-                pk.y = static_cast<uint32_t>(h[2]) | (static_cast<uint32_t>(h[3]) << 16);
-                *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(a.a_out) + site * a.a_stride + c0) = pk;
-            }
+            if (a.z_out) *reinterpret_cast<f32x4*>(a.z_out + site * a.z_stride + c0) = zf[r][b];
+            if (a.zh_out) *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(a.zh_out) + site * a.zh_stride + c0) = zh[r][b];
+            if (a.a_out) *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(a.a_out) + site * a.a_stride + c0) = ao[r][b];
         }
     }
 }
@@ -253,7 +363,7 @@ __global__ __launch_bounds__(256) void conv32_fwd_tiled(ConvArgs a) {
 // 8 channels of 4 stencil offsets, lane group g taking offset 4s + g, so the
 // whole weight set (7 steps x 2 output blocks) stays in registers.
 template <int RY>
-__global__ __launch_bounds__(256) void conv8_fwd_tiled(ConvArgs a) {
+__global__ __launch_bounds__(256, 2) void conv8_fwd_tiled(ConvArgs a) {
     constexpr int ZR = 18, YR = RY + 2, PL = 6, KS = 7;
     __shared__ __align__(16) uint16_t tin[PL * YR * ZR * 8];
     const uint16_t* __restrict__ in = reinterpret_cast<const uint16_t*>(a.in);
@@ -268,26 +378,11 @@ __global__ __launch_bounds__(256) void conv8_fwd_tiled(ConvArgs a) {
     const int x0 = tx * 4, y0 = ty * RY, z0 = tz * 16;
     constexpr int SITES = PL * YR * ZR;
     constexpr int ITER = (SITES + 255) / 256;
-    // all loads of the tile first, then all LDS stores (past the last site a
-    // thread re-reads it, in bounds, and stores nothing)
-    uint4 v[ITER];
-#pragma unroll
-    for (int k = 0; k < ITER; ++k) {
-        const int i = min(static_cast<int>(threadIdx.x) + k * 256, SITES - 1);
-        const int zi = i % ZR, yi = (i / ZR) % YR, pi = i / (ZR * YR);
-        int xx = x0 - 1 + pi, yy = y0 - 1 + yi, zz = z0 - 1 + zi;
-        xx = xx < 0 ? xx + N : (xx >= N ? xx - N : xx);
-        yy = yy < 0 ? yy + N : (yy >= N ? yy - N : yy);
-        zz = zz < 0 ? zz + N : (zz >= N ? zz - N : zz);
-        v[k] = *reinterpret_cast<const uint4*>(in + static_cast<size_t>((xx * N + yy) * N + zz) * 8);
-    }
-#pragma unroll
-    for (int k = 0; k < ITER; ++k) {
-        const int i = static_cast<int>(threadIdx.x) + k * 256;
-        if (i < SITES) *reinterpret_cast<uint4*>(tin + static_cast<size_t>(i) * 8) = v[k];
-    }
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int n = lane & 15, g = lane >> 4;
+    // the weights (they do not depend on the tile) and all loads of the tile
+    // first, then all LDS stores (past the last site a thread re-reads it, in
+    // bounds, and stores nothing)
     bf16x8 wa[KS][2];
     int off[KS];
 #pragma unroll
@@ -297,6 +392,35 @@ __global__ __launch_bounds__(256) void conv8_fwd_tiled(ConvArgs a) {
         for (int b = 0; b < 2; ++b) wa[s][b] = load8(wg + static_cast<size_t>(o * 32 + 16 * b + n) * 8);
         const int dx = o / 9, dy = (o / 3) % 3, dz = o % 3;
         off[s] = o < 27 ? (((w + dx) * YR + dy) * ZR + n + dz) * 8 : -1;
+    }
+    u32x4 v[ITER];
+#pragma unroll
+    for (int k = 0; k < ITER; ++k) {
+        const int i = min(static_cast<int>(threadIdx.x) + k * 256, SITES - 1);
+        const int zi = i % ZR, yi = (i / ZR) % YR, pi = i / (ZR * YR);
+        int xx = x0 - 1 + pi, yy = y0 - 1 + yi, zz = z0 - 1 + zi;
+        xx = xx < 0 ? xx + N : (xx >= N ? xx - N : xx);
+        yy = yy < 0 ? yy + N : (yy >= N ? yy - N : yy);
+        zz = zz < 0 ? zz + N : (zz >= N ? zz - N : zz);
+        v[k] = *reinterpret_cast<const u32x4*>(in + static_cast<size_t>((xx * N + yy) * N + zz) * 8);
+    }
+    // pre-activations for the input gradient's epilogue, in flight with the tile
+    const int x = x0 + w;
+    uint2 zg[RY][2];
+    if (a.gz) {
+#pragma unroll
+        for (int r = 0; r < RY; ++r)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                zg[r][b] = *reinterpret_cast<const uint2*>(reinterpret_cast<const uint16_t*>(a.gz) +
+                                                           static_cast<size_t>((x * N + y0 + r) * N + z0 + n) * a.gz_stride +
+                                                           16 * b + 4 * g);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < ITER; ++k) {
+        const int i = static_cast<int>(threadIdx.x) + k * 256;
+        if (i < SITES) *reinterpret_cast<u32x4*>(tin + static_cast<size_t>(i) * 8) = v[k];
     }
     __syncthreads();
     f32x4 acc[RY][2];
@@ -312,168 +436,300 @@ __global__ __launch_bounds__(256) void conv8_fwd_tiled(ConvArgs a) {
 #pragma unroll
             for (int b = 0; b < 2; ++b) acc[r][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[s][b], xb, acc[r][b], 0, 0, 0);
         }
-    const int x = x0 + w;
+    float bias[2][4];
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bias[b][q] = a.bias ? a.bias[16 * b + 4 * g + q] : 0.f;
+    // every output value first, then all stores back to back
+    f32x4 zf[RY][2];
+    uint2 zh[RY][2], ao[RY][2];
+#pragma unroll
+    for (int r = 0; r < RY; ++r)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            float v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] = acc[r][b][q] + bias[b][q];
+            zf[r][b] = f32x4{v[0], v[1], v[2], v[3]};
+            const uint16_t hz[4] = {f2bf(v[0]), f2bf(v[1]), f2bf(v[2]), f2bf(v[3])};
+            zh[r][b] = pack4(hz);
+            uint16_t h[4];
+            if (a.gz) {
+                float zv[4];
+                unpack4(zg[r][b], zv);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) h[q] = f2bf(v[q] * gelu_grad(zv[q]));
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) h[q] = f2bf(a.gelu ? gelu(v[q]) : v[q]);
+            }
+            ao[r][b] = pack4(h);
+        }
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
         const size_t site = static_cast<size_t>((x * N + y0 + r) * N + z0 + n);
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
             const int c0 = 16 * b + 4 * g;
-            float v[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) v[q] = acc[r][b][q] + (a.bias ? a.bias[c0 + q] : 0.f);
-            if (a.z_out) *reinterpret_cast<float4*>(a.z_out + site * a.z_stride + c0) = make_float4(v[0], v[1], v[2], v[3]);
-            if (a.a_out) {
-                uint16_t h[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) h[q] = f2bf(a.gelu ? gelu(v[q]) : v[q]);
-                uint2 pk;
-                pk.x = static_cast<uint32_t>(h[0]) | (static_cast<uint32_t>(h[1]) << 16);
-                pk.y = static_cast<uint32_t>(h[2]) | (static_cast<uint32_t>(h[3]) << 16);
-                *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(a.a_out) + site * a.a_stride + c0) = pk;
-            }
+            if (a.z_out) *reinterpret_cast<f32x4*>(a.z_out + site * a.z_stride + c0) = zf[r][b];
+            if (a.zh_out) *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(a.zh_out) + site * a.zh_stride + c0) = zh[r][b];
+            if (a.a_out) *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(a.a_out) + site * a.a_stride + c0) = ao[r][b];
         }
     }
 }
 
 // ---------------------------------------------------------------- weight gradient
-// dW[o][co][ci] = sum_n dz[n][co] x[n + o][ci],  db[co] = sum_n dz[n][co].
-// A workgroup takes 32-site row segments; it stages dz^T and x^T (three
-// copies shifted by dz = -1, 0, +1 so that every 8-site fragment is a
-// 16-byte aligned read) of the 3 x 3 neighbour rows in LDS, then MFMAs with
-// K = 32 sites.  Wave w owns offsets o = w, w+4, ...; each workgroup writes
-// its partial sums, reduced later in a fixed order.
-template <int CIN, int NB>
-__global__ __launch_bounds__(256) void conv_wgrad(WgradArgs a) {
-    constexpr int NBI = CIN == 32 ? 2 : 1;         // 16-wide input-channel blocks
-    constexpr int CINP = NBI * 16;
-    constexpr int COUTP = NB * 16;
-    constexpr int MAXO = 7;                         // offsets per wave (27 over 4 waves)
-    __shared__ __align__(16) uint16_t dzT[COUTP][32];
-    __shared__ __align__(16) uint16_t xT[3][CINP][9][32];
-    __shared__ float dbs[COUTP];
+// dW[o][co][ci] = sum_n dz[n][co] x[n + o][ci],  db[co] = sum_n dz[n][co],
+// as MFMA products with K = 32 sites (one 32-site z segment of a row).  The
+// MFMA operands need 8 consecutive sites of one channel per lane, the
+// transpose of the channels-last layout: the staging threads load 8 sites x
+// 8 channels, transpose them in registers and store channel-major rows in LDS
+// with 16-byte writes.
+//
+// A workgroup owns BY y-rows x 32 z-sites and marches along x over L planes
+// (a.L).  Step t has in LDS the x plane X0 - 1 + t (BY + 2 rows, each channel
+// row holding z0 - 8 .. z0 + 39 so that the z halo sits at slots 7 and 40)
+// and the dz plane X0 + t; the next step's planes are loaded from global
+// memory before the MFMAs and stored to the other LDS buffer after them, one
+// barrier per step.  Wave w takes one (output block b, input block c) pair and
+// all 27 offsets (when the layer has only two pairs, two waves share a pair,
+// each over half the rows, and write separate partial sums).  It keeps the dz
+// fragments of planes X0 + t - 2 .. X0 + t in registers; every x fragment it
+// reads (three shifts in z built from three aligned chunks) feeds each
+// (dx, dy) offset whose segment lies in its rows.
+template <int CIN, int COS, int BY>
+__global__ __launch_bounds__(256, 2) void conv_wgrad(WgradArgs a) {
+    constexpr int NBI = CIN == 32 ? 2 : 1, NB = COS == 32 ? 2 : 1;
+    constexpr int NP = NB * NBI, WPP = 4 / NP, RW = BY / WPP;
+    constexpr int CINP = 16 * NBI, COUTP = 16 * NB;
+    constexpr int XR = BY + 2, ZS = 48;
+    constexpr int CGX = CIN / 8, CGD = COS / 8;
+    constexpr int NX = XR * 4 * CGX;  // 8 x 8 transposes of x per plane
+    constexpr int ND = BY * 4 * CGD;  // of dz
+    constexpr int NE = XR * 2 * CGX;  // z-halo loads of x (8 channels of one site)
+    static_assert(NP * WPP == 4 && RW * WPP == BY, "wave split");
+    static_assert(NX + ND + NE <= 256, "staging tasks exceed the workgroup");
+    __shared__ __align__(16) uint16_t xs[2][XR][CIN][ZS];
+    __shared__ __align__(16) uint16_t ds[2][BY][COS][32];
+    __shared__ float dbs[ND][8];
     const uint16_t* __restrict__ dz = reinterpret_cast<const uint16_t*>(a.dz);
     const uint16_t* __restrict__ x = reinterpret_cast<const uint16_t*>(a.x);
-    const int N = a.N;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int n = lane & 15, g = lane >> 4;
-    f32x4 acc[MAXO][NB][NBI];
-#pragma unroll
-    for (int i = 0; i < MAXO; ++i)
-#pragma unroll
-        for (int b = 0; b < NB; ++b)
-#pragma unroll
-            for (int c = 0; c < NBI; ++c) acc[i][b][c] = f32x4{0.f, 0.f, 0.f, 0.f};
-    float dbacc = 0.f;
-    const int nseg = a.nsites / 32;
-    for (int seg = blockIdx.x; seg < nseg; seg += gridDim.x) {
-        const int site0 = seg * 32;
-        const int z0 = site0 % N, y = (site0 / N) % N, xx = site0 / (N * N);
-        __syncthreads();
-        // dz^T: thread t -> (site t/8 ... ) load 8 channels of one site
-        for (int it = threadIdx.x; it < 32 * (COUTP / 8); it += 256) {
-            const int s = it / (COUTP / 8), c8 = (it % (COUTP / 8)) * 8;
-            uint16_t v[8];
-            if (c8 < a.cout_stride) {
-                const uint4 u = *reinterpret_cast<const uint4*>(dz + static_cast<size_t>(site0 + s) * a.cout_stride + c8);
-                __builtin_memcpy(v, &u, 16);
-            } else {
-                for (int j = 0; j < 8; ++j) v[j] = 0;
-            }
-            for (int j = 0; j < 8; ++j) dzT[c8 + j][s] = v[j];
-        }
-        // x^T for the 9 rows (dx, dy) and 34 z positions, stored as 3 shifted copies
-        for (int it = threadIdx.x; it < 9 * 34 * (CINP / 8); it += 256) {
-            const int c8 = (it % (CINP / 8)) * 8;
-            const int rest = it / (CINP / 8);
-            const int zi = rest % 34, row = rest / 34;
-            const int dxr = row / 3 - 1, dyr = row % 3 - 1;
-            int xr = xx + dxr, yr = y + dyr, zr = z0 + zi - 1;
-            xr = (xr + N) % N;
-            yr = (yr + N) % N;
-            zr = (zr + N) % N;
-            uint16_t v[8];
-            if (c8 < CIN) {
-                const uint4 u = *reinterpret_cast<const uint4*>(x + static_cast<size_t>((xr * N + yr) * N + zr) * CIN + c8);
-                __builtin_memcpy(v, &u, 16);
-            } else {
-                for (int j = 0; j < 8; ++j) v[j] = 0;
-            }
-            // position zi (z0 - 1 + zi) goes to copy dzs at index zi - 1 - dzs... copy k holds z0 + k - 1 + i at i
-            for (int k = 0; k < 3; ++k) {
-                const int i = zi - k;  // copy k: element i is z = z0 + (k - 1) + i
-                if (i >= 0 && i < 32)
-                    for (int j = 0; j < 8; ++j) xT[k][c8 + j][row][i] = v[j];
-            }
-        }
-        __syncthreads();
-        if (threadIdx.x < COUTP) {
-            float s = 0.f;
-            for (int i = 0; i < 32; ++i) s += bf2f(dzT[threadIdx.x][i]);
-            dbacc += s;
-        }
-        // A fragments: dz^T[co = 16b + n][sites 8g..8g+7]
-        bf16x8 fa[NB];
-#pragma unroll
-        for (int b = 0; b < NB; ++b) fa[b] = load8(&dzT[16 * b + n][8 * g]);
-#pragma unroll
-        for (int i = 0; i < MAXO; ++i) {
-            const int o = wave + 4 * i;
-            if (o >= 27) break;
-            const int row = (o / 9) * 3 + (o / 3) % 3, k = o % 3;
-#pragma unroll
-            for (int c = 0; c < NBI; ++c) {
-                const bf16x8 fb = load8(&xT[k][16 * c + n][row][8 * g]);
-#pragma unroll
-                for (int b = 0; b < NB; ++b)
-                    acc[i][b][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[b], fb, acc[i][b][c], 0, 0, 0);
-            }
-        }
+    const int N = a.N, L = a.L;
+    const int nyb = N / BY, nzb = N / 32;
+    int blk = blockIdx.x;
+    const int y0 = (blk % nyb) * BY;
+    blk /= nyb;
+    const int z0 = (blk % nzb) * 32;
+    const int X0 = (blk / nzb) * L;
+
+    // staging task of this thread, fixed over the march
+    const int tid = threadIdx.x;
+    int kind = -1, trow = 0, tk = 0, tcg = 0;
+    if (tid < NX) {
+        kind = 0;
+        trow = tid / (4 * CGX);
+        tk = (tid / CGX) % 4;
+        tcg = tid % CGX;
+    } else if (tid < NX + ND) {
+        const int u = tid - NX;
+        kind = 1;
+        trow = u / (4 * CGD);
+        tk = (u / CGD) % 4;
+        tcg = u % CGD;
+    } else if (tid >= 256 - NE) {
+        const int u = tid - (256 - NE);
+        kind = 2;
+        trow = u / (2 * CGX);
+        tk = (u / CGX) % 2;
+        tcg = u % CGX;
     }
-    // partial sums of this workgroup: [o][co][ci] then [co] for the bias
-    float* out = a.partials + static_cast<size_t>(blockIdx.x) * a.partial_stride;
+    const int xrow_y = (y0 - 1 + trow + N) % N;  // x rows (kinds 0 and 2)
+    const int zedge = tk == 0 ? (z0 - 1 + N) % N : (z0 + 32) % N;
+    uint4 pre[8];
+    float dbacc[8];
 #pragma unroll
-    for (int i = 0; i < MAXO; ++i) {
-        const int o = wave + 4 * i;
-        if (o >= 27) break;
+    for (int j = 0; j < 8; ++j) dbacc[j] = 0.f;
+
+    // global loads of the x plane px and the dz plane qd (periodic in x)
+    auto load_stage = [&](int px, int qd) {
+        px = px < 0 ? px + N : (px >= N ? px - N : px);
+        qd = qd >= N ? qd - N : qd;
+        if (kind == 0) {
+            const uint16_t* src = x + (static_cast<size_t>(px * N + xrow_y) * N + z0 + 8 * tk) * CIN + 8 * tcg;
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
+            for (int j = 0; j < 8; ++j) pre[j] = *reinterpret_cast<const uint4*>(src + j * CIN);
+        } else if (kind == 1) {
+            const uint16_t* src = dz + (static_cast<size_t>(qd * N + y0 + trow) * N + z0 + 8 * tk) * COS + 8 * tcg;
 #pragma unroll
-            for (int c = 0; c < NBI; ++c)
+            for (int j = 0; j < 8; ++j) pre[j] = *reinterpret_cast<const uint4*>(src + j * COS);
+        } else if (kind == 2) {
+            pre[0] = *reinterpret_cast<const uint4*>(x + (static_cast<size_t>(px * N + xrow_y) * N + zedge) * CIN + 8 * tcg);
+        }
+    };
+    // word d of site j: channels 2d (low half) and 2d + 1 (high half)
+    auto word = [&](int j, int d) -> uint32_t {
+        return d == 0 ? pre[j].x : d == 1 ? pre[j].y : d == 2 ? pre[j].z : pre[j].w;
+    };
+    // channel ch of sites 2i, 2i + 1 packed in one word
+    auto tword = [&](int ch, int i) -> uint32_t {
+        const uint32_t lo = word(2 * i, ch >> 1), hi = word(2 * i + 1, ch >> 1);
+        return (ch & 1) ? ((lo >> 16) | (hi & 0xFFFF0000u)) : ((lo & 0xFFFFu) | (hi << 16));
+    };
+    auto store_stage = [&](int buf, bool dz_counts) {
+        if (kind == 0) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int co = 16 * b + 4 * g + r, ci = 16 * c + n;
-                    out[(o * COUTP + co) * CINP + ci] = acc[i][b][c][r];
+            for (int ch = 0; ch < 8; ++ch)
+                *reinterpret_cast<uint4*>(&xs[buf][trow][8 * tcg + ch][8 + 8 * tk]) =
+                    make_uint4(tword(ch, 0), tword(ch, 1), tword(ch, 2), tword(ch, 3));
+        } else if (kind == 1) {
+#pragma unroll
+            for (int ch = 0; ch < 8; ++ch) {
+                const uint4 v = make_uint4(tword(ch, 0), tword(ch, 1), tword(ch, 2), tword(ch, 3));
+                *reinterpret_cast<uint4*>(&ds[buf][trow][8 * tcg + ch][8 * tk]) = v;
+                if (dz_counts) {
+                    float s = 0.f;
+                    const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        s += bf2f(static_cast<uint16_t>(wv[i] & 0xFFFFu));
+                        s += bf2f(static_cast<uint16_t>(wv[i] >> 16));
+                    }
+                    dbacc[ch] += s;
                 }
+            }
+        } else if (kind == 2) {
+            const int slot = tk == 0 ? 7 : 40;
+#pragma unroll
+            for (int ch = 0; ch < 8; ++ch) {
+                const uint32_t wd = word(0, ch >> 1);
+                xs[buf][trow][8 * tcg + ch][slot] = static_cast<uint16_t>((ch & 1) ? (wd >> 16) : (wd & 0xFFFFu));
+            }
+        }
+    };
+
+    const int lane = tid & 63, w = tid >> 6;
+    const int n = lane & 15, g = lane >> 4;
+    const int pr = w % NP, h = w / NP;
+    const int b = pr / NBI, c = pr % NBI;
+    const bool bl = CIN == 32 || n < 8;   // lane holds a real input channel
+    const bool al = COS == 32 || n < 8;   // lane holds a real dz channel
+    f32x4 acc[27];
+#pragma unroll
+    for (int o = 0; o < 27; ++o) acc[o] = f32x4{0.f, 0.f, 0.f, 0.f};
+    bf16x8 Ap[RW], Ac[RW], An[RW];
+#pragma unroll
+    for (int r = 0; r < RW; ++r) Ap[r] = Ac[r] = An[r] = zero8();
+
+    load_stage(X0 - 1, X0);
+    store_stage(0, true);
+    __syncthreads();
+    for (int t = 0; t < L + 2; ++t) {
+        const int buf = t & 1;
+        const bool more = t + 1 < L + 2;
+        if (more) load_stage(X0 + t, X0 + t + 1);
+        const bool qvalid = t < L;  // dz plane X0 + t lies in this chunk
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            Ap[r] = Ac[r];
+            Ac[r] = An[r];
+            An[r] = (qvalid && al) ? load8(&ds[buf][h * RW + r][16 * b + n][8 * g]) : zero8();
+        }
+#pragma unroll
+        for (int yi = 0; yi < RW + 2; ++yi) {
+            bf16x8 bm = zero8(), b0 = zero8(), bp = zero8();
+            if (bl) {
+                const uint16_t* base = &xs[buf][h * RW + yi][16 * c + n][8 * g];
+                const uint4 c0 = *reinterpret_cast<const uint4*>(base);
+                const uint4 c1 = *reinterpret_cast<const uint4*>(base + 8);
+                const uint4 c2 = *reinterpret_cast<const uint4*>(base + 16);
+                // z - 1: element 7 of c0, then elements 0..6 of c1; z + 1: 1..7 of c1, 0 of c2
+                const uint4 m = make_uint4((c0.w >> 16) | (c1.x << 16), (c1.x >> 16) | (c1.y << 16),
+                                           (c1.y >> 16) | (c1.z << 16), (c1.z >> 16) | (c1.w << 16));
+                const uint4 p = make_uint4((c1.x >> 16) | (c1.y << 16), (c1.y >> 16) | (c1.z << 16),
+                                           (c1.z >> 16) | (c1.w << 16), (c1.w >> 16) | (c2.x << 16));
+                bm = __builtin_bit_cast(bf16x8, m);
+                b0 = __builtin_bit_cast(bf16x8, c1);
+                bp = __builtin_bit_cast(bf16x8, p);
+            }
+#pragma unroll
+            for (int dy = -1; dy <= 1; ++dy) {
+                const int ry = yi - 1 - dy;  // segment row fed by this x row at dy
+                if (ry < 0 || ry >= RW) continue;
+#pragma unroll
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const bf16x8 af = dx == 1 ? Ap[ry] : (dx == 0 ? Ac[ry] : An[ry]);
+                    const int o = 9 * (dx + 1) + 3 * (dy + 1);
+                    acc[o] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bm, acc[o], 0, 0, 0);
+                    acc[o + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, b0, acc[o + 1], 0, 0, 0);
+                    acc[o + 2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bp, acc[o + 2], 0, 0, 0);
+                }
+            }
+        }
+        if (more) store_stage(buf ^ 1, t + 1 < L);
+        __syncthreads();
     }
-    if (threadIdx.x < COUTP) out[27 * COUTP * CINP + threadIdx.x] = dbacc;
+
+    // partial sums: [o][co][ci] then [co] for the bias, one slot per wave group
+    float* out = a.partials + static_cast<size_t>(blockIdx.x * WPP + h) * a.partial_stride;
+#pragma unroll
+    for (int o = 0; o < 27; ++o)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) out[(o * COUTP + 16 * b + 4 * g + r) * CINP + 16 * c + n] = acc[o][r];
+    if (kind == 1) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) dbs[tid - NX][j] = dbacc[j];
+    }
+    __syncthreads();
+    if (tid < COUTP) {
+        float s = 0.f;
+        if (tid < COS)
+            for (int u = tid / 8; u < ND; u += CGD) s += dbs[u][tid % 8];
+        out[27 * COUTP * CINP + tid] = s;
+        if (WPP == 2) a.partials[static_cast<size_t>(blockIdx.x * WPP + 1) * a.partial_stride + 27 * COUTP * CINP + tid] = 0.f;
+    }
 }
 
-// Fixed-order sum of the workgroup partials, then scatter into the flat
-// gradient layout W[co][ci][dx][dy][dz] (FP32), b[co].
-__global__ void wgrad_reduce(WgradReduceArgs a) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;  // element of one partial
+// Fixed-order sum of the partials, then scatter into the flat gradient layout
+// W[co][ci][dx][dy][dz] (FP32), b[co].  A block takes 64 consecutive
+// elements; its four waves sum contiguous quarters of the partials in FP64
+// (16 loads in flight per lane) and are combined in wave order.
+__global__ __launch_bounds__(256) void wgrad_reduce(WgradReduceArgs a) {
+    __shared__ double red[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int e = blockIdx.x * 64 + lane;
     const int nW = 27 * a.coutp * a.cinp;
-    if (e >= nW + a.coutp) return;
+    const int q = (a.nparts + 3) / 4;
+    const int p0 = w * q, p1 = min(a.nparts, p0 + q);
     double s = 0.0;
-    for (int p = 0; p < a.nparts; ++p) s += static_cast<double>(a.partials[static_cast<size_t>(p) * a.partial_stride + e]);
+    if (e < nW + a.coutp) {
+        const float* src = a.partials + e;
+        const size_t st = static_cast<size_t>(a.partial_stride);
+        int p = p0;
+        for (; p + 16 <= p1; p += 16) {
+            float v[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) v[j] = src[static_cast<size_t>(p + j) * st];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) s += static_cast<double>(v[j]);
+        }
+        for (; p < p1; ++p) s += static_cast<double>(src[static_cast<size_t>(p) * st]);
+    }
+    red[w][lane] = s;
+    __syncthreads();
+    if (w != 0 || e >= nW + a.coutp) return;
+    const double tot = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
     if (e < nW) {
         const int o = e / (a.coutp * a.cinp), co = (e / a.cinp) % a.coutp, ci = e % a.cinp;
-        if (co < a.cout && ci < a.cin) a.gW[(static_cast<size_t>(co) * a.cin + ci) * 27 + o] = static_cast<float>(s);
+        if (co < a.cout && ci < a.cin) a.gW[(static_cast<size_t>(co) * a.cin + ci) * 27 + o] = static_cast<float>(tot);
     } else {
         const int co = e - nW;
-        if (co < a.cout) a.gb[co] = static_cast<float>(s);
+        if (co < a.cout) a.gb[co] = static_cast<float>(tot);
     }
 }
 
 // ---------------------------------------------------------------- elementwise
-// d(pre-activation) = d(activation) * GELU'(z), to BF16 channels-last.
-__global__ void gelu_backward(const float* __restrict__ da, const float* __restrict__ z, uint16_t* __restrict__ dz,
-                              size_t n) {
-    const size_t i = (static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x);
-    if (i < n) dz[i] = f2bf(da[i] * gelu_grad(z[i]));
-}
-
 // MSE against the target: y is [site][ystride] FP32 (cout channels used),
 // t is [c][site] FP32; writes d loss / d y as BF16 [site][8] (channels >= cout
 // zero) and per-workgroup partial sums of squares.
@@ -622,23 +878,33 @@ hipError_t launch_conv_fwd(const ConvArgs& a, int cin, int nb, int grid, hipStre
     return hipGetLastError();
 }
 
-hipError_t launch_conv_wgrad(const WgradArgs& a, int cin, int nb, int grid, hipStream_t s) {
-    if (cin == 32 && nb == 2) hipLaunchKernelGGL((conv_wgrad<32, 2>), dim3(grid), dim3(256), 0, s, a);
-    else if (cin == 32 && nb == 1) hipLaunchKernelGGL((conv_wgrad<32, 1>), dim3(grid), dim3(256), 0, s, a);
-    else if (cin == 8 && nb == 2) hipLaunchKernelGGL((conv_wgrad<8, 2>), dim3(grid), dim3(256), 0, s, a);
+WgradShape wgrad_shape(int N, int cin, int cout_stride) {
+    // x chunks double (L halves, kept >= 8) until about 512 workgroups
+    const int base = (N / 4) * (N / 32);
+    int L = N;
+    while (base * (N / L) < 512 && L / 2 >= 8 && N % (L / 2) == 0) L /= 2;
+    const int nbi = cin == 32 ? 2 : 1, nb = cout_stride == 32 ? 2 : 1;
+    WgradShape sh;
+    sh.L = L;
+    sh.grid = base * (N / L);
+    sh.parts = sh.grid * (4 / (nb * nbi));
+    sh.stride = 27 * (16 * nb) * (16 * nbi) + 16 * nb;
+    return sh;
+}
+
+hipError_t launch_conv_wgrad(const WgradArgs& a, int cin, hipStream_t s) {
+    if (a.N % 32 || a.L < 1 || a.N % a.L) return hipErrorInvalidValue;
+    const int grid = (a.N / 4) * (a.N / 32) * (a.N / a.L);
+    if (cin == 32 && a.cout_stride == 32) hipLaunchKernelGGL((conv_wgrad<32, 32, 4>), dim3(grid), dim3(256), 0, s, a);
+    else if (cin == 32 && a.cout_stride == 8) hipLaunchKernelGGL((conv_wgrad<32, 8, 4>), dim3(grid), dim3(256), 0, s, a);
+    else if (cin == 8 && a.cout_stride == 32) hipLaunchKernelGGL((conv_wgrad<8, 32, 4>), dim3(grid), dim3(256), 0, s, a);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
 hipError_t launch_wgrad_reduce(const WgradReduceArgs& a, hipStream_t s) {
     const int n = 27 * a.coutp * a.cinp + a.coutp;
-    hipLaunchKernelGGL(wgrad_reduce, dim3((n + 255) / 256), dim3(256), 0, s, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_gelu_backward(const float* da, const float* z, void* dz, size_t n, hipStream_t s) {
-    hipLaunchKernelGGL(gelu_backward, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, da, z,
-                       static_cast<uint16_t*>(dz), n);
+    hipLaunchKernelGGL(wgrad_reduce, dim3((n + 63) / 64), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

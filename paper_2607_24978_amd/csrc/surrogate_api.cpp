@@ -66,16 +66,15 @@ struct cl_surrogate {
     int bufN = 0;
     uint16_t* x0 = nullptr;               // [n3][8]
     std::vector<uint16_t*> act;           // [layers-1] x [n3][32]
-    std::vector<float*> zpre;             // [layers-1] x [n3][32]
+    std::vector<uint16_t*> zpre;          // [layers-1] x [n3][32] BF16 pre-activations
     float* y = nullptr;                   // [n3][4..8]
     float* dA = nullptr;                  // [n3][32]
-    uint16_t* dZ = nullptr;               // [n3][32]
+    uint16_t* dZ[2] = {nullptr, nullptr}; // [n3][32], layer gradients (ping-pong)
     uint16_t* dy = nullptr;               // [n3][8]
     float* target = nullptr;              // [c][n3]
     float* wpart = nullptr;               // wgrad partials
-    int wgrid = 0, wstride = 0;
     double* lpart = nullptr;              // loss partials
-    int lgrid = 256;
+    int lgrid = 2048;  // loss workgroups (8 per CU: the loop over sites is latency-bound)
     // dataset
     int dsN = 0, ds_cap = 0, ds_n = 0;
     bool pending = false;
@@ -109,7 +108,8 @@ void free_bufs(cl_surrogate* s) {
     for (auto p : s->zpre) f(p);
     f(s->y);
     f(s->dA);
-    f(s->dZ);
+    f(s->dZ[0]);
+    f(s->dZ[1]);
     f(s->dy);
     f(s->target);
     f(s->wpart);
@@ -118,7 +118,7 @@ void free_bufs(cl_surrogate* s) {
     s->act.clear();
     s->zpre.clear();
     s->y = s->dA = s->target = s->wpart = nullptr;
-    s->dZ = s->dy = nullptr;
+    s->dZ[0] = s->dZ[1] = s->dy = nullptr;
     s->lpart = nullptr;
     s->bufN = 0;
 }
@@ -135,20 +135,26 @@ cl_status ensure_bufs(cl_surrogate* s, int N, bool training) {
         s->act.push_back(dalloc<uint16_t>(n3 * 32));
         ok = ok && s->act.back();
         if (training) {
-            s->zpre.push_back(dalloc<float>(n3 * 32));
+            s->zpre.push_back(dalloc<uint16_t>(n3 * 32));
             ok = ok && s->zpre.back();
         }
     }
     if (training) {
         s->dA = dalloc<float>(n3 * 32);
-        s->dZ = dalloc<uint16_t>(n3 * 32);
+        s->dZ[0] = dalloc<uint16_t>(n3 * 32);
+        s->dZ[1] = dalloc<uint16_t>(n3 * 32);
         s->dy = dalloc<uint16_t>(n3 * 8);
         s->target = dalloc<float>(n3 * 8);
-        s->wgrid = 512;
-        s->wstride = 27 * 32 * 32 + 32;
-        s->wpart = dalloc<float>(static_cast<size_t>(s->wgrid) * s->wstride);
+        // weight-gradient partial sums: the largest of the three layer shapes
+        size_t wp = 0;
+        const int shapes[3][2] = {{32, 32}, {32, 8}, {8, 32}};  // (input channels, dz stride)
+        for (const auto& sh : shapes) {
+            const cl::sg::WgradShape w = cl::sg::wgrad_shape(N, sh[0], sh[1]);
+            wp = std::max(wp, static_cast<size_t>(w.parts) * w.stride);
+        }
+        s->wpart = dalloc<float>(wp);
         s->lpart = dalloc<double>(s->lgrid);
-        ok = ok && s->dA && s->dZ && s->dy && s->target && s->wpart && s->lpart;
+        ok = ok && s->dA && s->dZ[0] && s->dZ[1] && s->dy && s->target && s->wpart && s->lpart;
     }
     if (!ok) {
         free_bufs(s);
@@ -195,8 +201,9 @@ cl_status forward(cl_surrogate* s, int N, bool training) {
         a.nsites = n3;
         a.cout = ly.coutp == 16 ? 4 * ((ly.cout + 3) / 4) : 32;
         if (l + 1 < nl) {
-            a.z_out = training ? s->zpre[l] : nullptr;
-            a.z_stride = 32;
+            a.z_out = nullptr;
+            a.zh_out = training ? s->zpre[l] : nullptr;
+            a.zh_stride = 32;
             a.a_out = s->act[l];
             a.a_stride = 32;
             a.gelu = 1;
@@ -224,18 +231,11 @@ cl_status loss_and_backward(cl_surrogate* s, int N, double* loss, bool input_gra
     const int co = s->L.back().cout;
     SHIP(cl::sg::launch_mse_grad(s->y, ystride(s), s->target, co, n3, 1.0 / (static_cast<double>(n3) * co), s->dy,
                                  s->lpart, s->lgrid, s->stream));
+    const void* dz = s->dy;  // d loss / d z of layer l (BF16 channels-last)
+    int dz_stride = 8;
     for (int l = nl - 1; l >= 0; --l) {
         const Layer& ly = s->L[l];
-        const void* dz = nullptr;
-        int dz_stride = 0;
-        if (l == nl - 1) {
-            dz = s->dy;
-            dz_stride = 8;
-        } else {
-            SHIP(cl::sg::launch_gelu_backward(s->dA, s->zpre[l], s->dZ, n3 * 32, s->stream));
-            dz = s->dZ;
-            dz_stride = 32;
-        }
+        const cl::sg::WgradShape sh = cl::sg::wgrad_shape(N, ly.cinp, dz_stride);
         cl::sg::WgradArgs w{};
         w.dz = dz;
         w.x = l == 0 ? static_cast<const void*>(s->x0) : static_cast<const void*>(s->act[l - 1]);
@@ -243,14 +243,14 @@ cl_status loss_and_backward(cl_surrogate* s, int N, double* loss, bool input_gra
         w.N = N;
         w.nsites = static_cast<int>(n3);
         w.cout_stride = dz_stride;
-        w.partial_stride = s->wstride;
-        const int grid = std::min(s->wgrid, static_cast<int>(n3 / 32));
-        SHIP(cl::sg::launch_conv_wgrad(w, ly.cinp, ly.nb, grid, s->stream));
+        w.partial_stride = sh.stride;
+        w.L = sh.L;
+        SHIP(cl::sg::launch_conv_wgrad(w, ly.cinp, s->stream));
         cl::sg::WgradReduceArgs r{};
         r.partials = s->wpart;
-        r.nparts = grid;
-        r.partial_stride = s->wstride;
-        r.coutp = ly.coutp;
+        r.nparts = sh.parts;
+        r.partial_stride = sh.stride;
+        r.coutp = dz_stride == 32 ? 32 : 16;
         r.cinp = ly.cinp == 32 ? 32 : 16;
         r.cout = ly.cout;
         r.cin = ly.cin;
@@ -258,7 +258,9 @@ cl_status loss_and_backward(cl_surrogate* s, int N, double* loss, bool input_gra
         r.gb = s->grad + ly.b_off;
         SHIP(cl::sg::launch_wgrad_reduce(r, s->stream));
         if (l > 0 || input_grad) {
-            // input gradient: a convolution of dz with the flipped, transposed weights
+            // input gradient: a convolution of dz with the flipped, transposed
+            // weights; below a hidden layer it is multiplied by GELU'(z) of
+            // that layer in the epilogue and becomes the next dz (BF16)
             ConvArgs a{};
             a.in = dz;
             a.w = ly.wd;
@@ -266,13 +268,24 @@ cl_status loss_and_backward(cl_surrogate* s, int N, double* loss, bool input_gra
             a.N = N;
             a.nsites = static_cast<int>(n3);
             a.cout = 32;
-            a.z_out = s->dA;
-            a.z_stride = 32;
-            a.a_out = nullptr;
             a.gelu = 0;
+            uint16_t* next = s->dZ[(nl - 1 - l) & 1];
+            if (l > 0) {
+                a.z_out = nullptr;
+                a.a_out = next;
+                a.a_stride = 32;
+                a.gz = s->zpre[l - 1];
+                a.gz_stride = 32;
+            } else {
+                a.z_out = s->dA;
+                a.z_stride = 32;
+                a.a_out = nullptr;
+            }
             const int groups = static_cast<int>(n3 / 16);
             const int grid2 = std::max(1, std::min(1024, (groups + 15) / 16));
             SHIP(cl::sg::launch_conv_fwd(a, ly.cinp_d, 2, grid2, s->stream));
+            dz = next;
+            dz_stride = 32;
         }
     }
     std::vector<double> lp(s->lgrid);

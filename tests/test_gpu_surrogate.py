@@ -74,8 +74,9 @@ def test_forward_matches_oracle(layers, extra, tolf):
 
 def emulated_backward(params, x, t):
     """FP64 forward and backward with the GPU's BF16 roundings (the layer
-    inputs and weights, the output gradient 2 (y - t) / n and the
-    GELU-scaled layer gradients rounded to BF16), together with the same
+    inputs and weights, the output gradient 2 (y - t) / n, the
+    pre-activations GELU' is evaluated at and the GELU-scaled layer
+    gradients rounded to BF16), together with the same
     computation on absolute values -- the scale of the rounding error of
     every gradient element (the forward's accumulated scale enters at the
     output and at every layer input)."""
@@ -104,7 +105,7 @@ def emulated_backward(params, x, t):
         dA_abs = SG.conv3d_grad_input(dz_abs, np.abs(Wb[l]))
         if l == 0:
             return loss, grads, gabs, dA, dA_abs
-        g = SG.gelu_grad(zs[l - 1])
+        g = SG.gelu_grad(SG.bf16_round(zs[l - 1]).astype(np.float64))  # pre-activations kept in BF16
         dz = SG.bf16_round(dA * g).astype(np.float64)
         dz_abs = dA_abs * np.abs(g) + np.abs(dz)
 
