@@ -39,6 +39,15 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __builtin_bit_cast(float, static_cast<uint32_t>(h) << 16); }
 
+// Two FP32 values to packed BF16 (round to nearest even) with the hardware
+// conversion; the same rounding as f2bf.
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t cvt2(float lo, float hi) {
+    const bf16x2 v = {static_cast<__bf16>(lo), static_cast<__bf16>(hi)};
+    return __builtin_bit_cast(uint32_t, v);
+}
+__device__ __forceinline__ uint2 cvt4(const float* f) { return make_uint2(cvt2(f[0], f[1]), cvt2(f[2], f[3])); }
+
 // 4 BF16 values packed in two words <-> FP32
 __device__ __forceinline__ uint2 pack4(const uint16_t* h) {
     return make_uint2(static_cast<uint32_t>(h[0]) | (static_cast<uint32_t>(h[1]) << 16),
@@ -234,20 +243,31 @@ __global__ __launch_bounds__(256, 2) void conv32_fwd_tiled(ConvArgs a) {
     // all loads of the tile first, then all LDS stores: the loads are in
     // flight together instead of one round trip per chunk
     u32x4 v[ITER];
+    if (x0 >= 1 && x0 + PL - 1 <= N && y0 >= 1 && y0 + YR - 1 <= N && z0 >= 1 && z0 + ZR - 1 <= N) {
+        // no periodic image in the block: offsets from its first site
+        const uint16_t* base = in + static_cast<size_t>(((x0 - 1) * N + y0 - 1) * N + z0 - 1) * 32;
 #pragma unroll
-    for (int k = 0; k < ITER; ++k) {
-        // past the last chunk a thread re-reads it (in bounds) and stores nothing
-        const int i = min(static_cast<int>(threadIdx.x) + k * 256, CHUNKS - 1);
-        const int c4 = i & 3;
-        int r = i >> 2;
-        const int zi = r % ZR;
-        r /= ZR;
-        const int yi = r % YR, pi = r / YR;
-        int xx = x0 - 1 + pi, yy = y0 - 1 + yi, zz = z0 - 1 + zi;
-        xx = xx < 0 ? xx + N : (xx >= N ? xx - N : xx);
-        yy = yy < 0 ? yy + N : (yy >= N ? yy - N : yy);
-        zz = zz < 0 ? zz + N : (zz >= N ? zz - N : zz);
-        v[k] = *reinterpret_cast<const u32x4*>(in + static_cast<size_t>((xx * N + yy) * N + zz) * 32 + c4 * 8);
+        for (int k = 0; k < ITER; ++k) {
+            // past the last chunk a thread re-reads it (in bounds) and stores nothing
+            const int i = min(static_cast<int>(threadIdx.x) + k * 256, CHUNKS - 1);
+            const int r = i >> 2, zi = r % ZR, yi = (r / ZR) % YR, pi = r / (ZR * YR);
+            v[k] = *reinterpret_cast<const u32x4*>(base + ((pi * N + yi) * N + zi) * 32 + (i & 3) * 8);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < ITER; ++k) {
+            const int i = min(static_cast<int>(threadIdx.x) + k * 256, CHUNKS - 1);
+            const int c4 = i & 3;
+            int r = i >> 2;
+            const int zi = r % ZR;
+            r /= ZR;
+            const int yi = r % YR, pi = r / YR;
+            int xx = x0 - 1 + pi, yy = y0 - 1 + yi, zz = z0 - 1 + zi;
+            xx = xx < 0 ? xx + N : (xx >= N ? xx - N : xx);
+            yy = yy < 0 ? yy + N : (yy >= N ? yy - N : yy);
+            zz = zz < 0 ? zz + N : (zz >= N ? zz - N : zz);
+            v[k] = *reinterpret_cast<const u32x4*>(in + static_cast<size_t>((xx * N + yy) * N + zz) * 32 + c4 * 8);
+        }
     }
     __builtin_amdgcn_sched_barrier(0);  // every load issued before the first store waits
 #pragma unroll
@@ -329,19 +349,23 @@ __global__ __launch_bounds__(256, 2) void conv32_fwd_tiled(ConvArgs a) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) v[q] = acc[r][b][q] + bias[b][q];
             zf[r][b] = f32x4{v[0], v[1], v[2], v[3]};
-            const uint16_t hz[4] = {f2bf(v[0]), f2bf(v[1]), f2bf(v[2]), f2bf(v[3])};
-            zh[r][b] = pack4(hz);
-            uint16_t h[4];
-            if (a.gz) {
-                float zv[4];
-                unpack4(zg[r][b], zv);
+            if (a.zh_out) zh[r][b] = cvt4(v);
+            if (a.a_out) {
+                float h[4];
+                if (a.gz) {
+                    float zv[4];
+                    unpack4(zg[r][b], zv);
 #pragma unroll
-                for (int q = 0; q < 4; ++q) h[q] = f2bf(v[q] * gelu_grad(zv[q]));
-            } else {
+                    for (int q = 0; q < 4; ++q) h[q] = v[q] * gelu_grad(zv[q]);
+                } else if (a.gelu) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) h[q] = f2bf(a.gelu ? gelu(v[q]) : v[q]);
+                    for (int q = 0; q < 4; ++q) h[q] = gelu(v[q]);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) h[q] = v[q];
+                }
+                ao[r][b] = cvt4(h);
             }
-            ao[r][b] = pack4(h);
         }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -452,19 +476,23 @@ __global__ __launch_bounds__(256, 2) void conv8_fwd_tiled(ConvArgs a) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) v[q] = acc[r][b][q] + bias[b][q];
             zf[r][b] = f32x4{v[0], v[1], v[2], v[3]};
-            const uint16_t hz[4] = {f2bf(v[0]), f2bf(v[1]), f2bf(v[2]), f2bf(v[3])};
-            zh[r][b] = pack4(hz);
-            uint16_t h[4];
-            if (a.gz) {
-                float zv[4];
-                unpack4(zg[r][b], zv);
+            if (a.zh_out) zh[r][b] = cvt4(v);
+            if (a.a_out) {
+                float h[4];
+                if (a.gz) {
+                    float zv[4];
+                    unpack4(zg[r][b], zv);
 #pragma unroll
-                for (int q = 0; q < 4; ++q) h[q] = f2bf(v[q] * gelu_grad(zv[q]));
-            } else {
+                    for (int q = 0; q < 4; ++q) h[q] = v[q] * gelu_grad(zv[q]);
+                } else if (a.gelu) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) h[q] = f2bf(a.gelu ? gelu(v[q]) : v[q]);
+                    for (int q = 0; q < 4; ++q) h[q] = gelu(v[q]);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) h[q] = v[q];
+                }
+                ao[r][b] = cvt4(h);
             }
-            ao[r][b] = pack4(h);
         }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll

@@ -46,10 +46,13 @@ def emulated_forward(params, x):
     return h, absacc
 
 
-@pytest.mark.parametrize("layers,extra,tolf", [(2, 2, 2 ** -7), (5, 4, 2 ** -5)])
-def test_forward_matches_oracle(layers, extra, tolf):
+@pytest.mark.parametrize("layers,extra,tolf,N", [(2, 2, 2 ** -7, 16), (5, 4, 2 ** -5, 16), (3, 4, 2 ** -6, 64)])
+def test_forward_matches_oracle(layers, extra, tolf, N):
+    """Every output of the network against the FP64 forward on the same
+    BF16-rounded operands.  At 16^3 every tile of the convolutions touches a
+    periodic image; at 64^3 most tiles lie inside the lattice (the kernels'
+    path without wrap-around)."""
     lib = _lib()
-    N = 16
     s = lib.Surrogate(n_fields=2, extra_inputs=extra, layers=layers, init_seed=3)
     chans = [s.cin] + [32] * (layers - 1) + [s.cout]
     rng = np.random.default_rng(5)
@@ -110,16 +113,17 @@ def emulated_backward(params, x, t):
         dz_abs = dA_abs * np.abs(g) + np.abs(dz)
 
 
-def test_gradients_match_oracle_elementwise():
+@pytest.mark.parametrize("N", [32, 64])
+def test_gradients_match_oracle_elementwise(N):
     """Every weight, bias and input gradient element of a 3-layer network at
-    32^3 against the FP64 oracle's backward pass on the same BF16-rounded
+    N^3 (at 64^3 most convolution tiles lie inside the lattice, at 32^3 none
+    does) against the FP64 oracle's backward pass on the same BF16-rounded
     operands: |g_gpu - g_oracle| <= 2^-6 g_abs, where g_abs is the same
     backward pass on absolute values (the convolution-of-absolute-values
     bound of the forward check, carried through the backward pass).  A
     wrong element, a transposed weight or a dropped bias gradient breaks
     the bound; it is not vacuous (the typical error is far below it)."""
     lib = _lib()
-    N = 32
     layers = 3
     s = lib.Surrogate(n_fields=2, extra_inputs=4, layers=layers, init_seed=11)
     chans = [s.cin] + [32] * (layers - 1) + [s.cout]
