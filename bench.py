@@ -724,6 +724,10 @@ def main():
                     help="only run a few surrogate training steps at 128^3 (for a kernel profile) and print their figures")
     ap.add_argument("--cpu-procs", type=int, default=16, help="processes of the all-cores oracle baseline (0: skip)")
     ap.add_argument("--no-c3", action="store_true", help="skip the 1024^3 leapfrog leg of the default run")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the power-spectrum, gravitational-wave and 2+1 legs of the default run")
+    ap.add_argument("--profile-leg", choices=["gw", "batched"], default=None,
+                    help="only run that leg (for a kernel profile; --steps / --warmup set its length) and print it")
     ap.add_argument("--workload", choices=["c1", "c3"], default="c1",
                     help="c1: 256^3 two-field VV4 (default); c3: 1024^3 two-field leapfrog")
     args = ap.parse_args()
@@ -740,6 +744,14 @@ def main():
         return
     if args.sg_train_profile:
         print(json.dumps(surrogate_train_profile()), flush=True)
+        return
+    if args.profile_leg == "gw":
+        print(json.dumps(gw_run(W.C1, steps=args.steps or 200, warmup=args.warmup or 20, tune=not args.no_tune)),
+              flush=True)
+        return
+    if args.profile_leg == "batched":
+        # one solo step per member only: the solo comparison is not what is profiled
+        print(json.dumps(batched_run(args.steps or 1000, args.warmup or 500, solo_steps=1)), flush=True)
         return
 
     from paper_2607_24978_amd import _lib
@@ -796,13 +808,13 @@ def main():
     if args.workload == "c1" and not args.no_c3:
         progress("1024^3 two-field leapfrog form (50 warm-up + 200 timed steps)")
         forms["c3_1024"] = c3_run()
-    if args.workload == "c1":
+    if args.workload == "c1" and not args.no_forms:
         progress("power spectrum form")
         forms["spectrum"] = spectrum_run(w)
-    if args.workload == "c1":
+    if args.workload == "c1" and not args.no_forms:
         progress("gravitational-wave form")
         forms["gw"] = gw_run(w)
-    if args.workload == "c1":
+    if args.workload == "c1" and not args.no_forms:
         progress("reduced 2+1 form")
         forms["lowdim_2d"] = lowdim_run(W.C4, 2000, 200)
     if not args.no_batched and args.workload == "c1":
