@@ -1,12 +1,12 @@
 // Power spectrum of one lattice array (Sect. 4.3, Eqs. discretePSaux,
 // discretePST2): the forward DFT f(n~) = sum_n exp(-2 pi i n~.n / N) f(n) in
-// FP64 as three passes of radix-2 line transforms (z, then y, then x), and
+// FP64 as three passes of line transforms (z, then y, then x), and
 // the binning of |f(n~)|^2 into centred spherical shells of |n~|.
 //
 // Line transform: a workgroup stages L lines of N complex values in LDS
-// (L N = 4096 at most: 64 KB), loaded in bit-reversed order, and runs the
-// log2 N butterfly stages of an iterative decimation-in-time FFT with a
-// barrier between stages.  For the z axis the L lines are consecutive rows;
+// (L N = 2048, 32 KB, for 64 <= N <= 2048), loaded in bit-reversed order, and runs the
+// log2 N butterfly stages of an iterative decimation-in-time FFT, three
+// stages per pass over LDS (radix-8 passes) with a barrier between passes.  For the z axis the L lines are consecutive rows;
 // for the y and x axes they are L consecutive z positions of one y-z (x-z)
 // slab, so every global access moves L consecutive complex values.
 #include "internal.h"
@@ -38,8 +38,80 @@ __device__ __forceinline__ size_t line_elem(const SpecFftArgs& a, int b, size_t 
     return (static_cast<size_t>(e) * N + outer) * N + z;  // x = e, y = outer
 }
 
+// LDS slot of element i (= l N + e) of a batch: one 16-byte pad after every
+// 16 elements, so that the bit-reversed stores (positions 16 apart) and the
+// first pass's groups (8 apart) fall in different banks.
+__device__ __forceinline__ int slot(int i) { return i + (i >> 4); }
+
+// Element idx of a batch -> (line l, element e): the z axis takes whole
+// lines in turn, the y and x axes the L lines' element e side by side.
+__device__ __forceinline__ void line_split(const SpecFftArgs& a, int idx, int& l, int& e) {
+    if (a.axis == 0) {
+        l = idx >> a.logN;
+        e = idx & (a.N - 1);
+    } else {
+        e = idx >> a.logL;
+        l = idx & (a.L - 1);
+    }
+}
+
+// A batch of K * 256 elements into LDS, bit-reversed along each line: every
+// global load of a thread first, then its LDS stores.
+template <int K>
+__device__ __forceinline__ void load_lines(const SpecFftArgs& a, int b, size_t outer, size_t z0, double2* buf) {
+    double2 v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        int l, e;
+        line_split(a, static_cast<int>(threadIdx.x) + k * 256, l, e);
+        v[k] = a.data[line_elem(a, b, outer, z0, l, e)];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        int l, e;
+        line_split(a, static_cast<int>(threadIdx.x) + k * 256, l, e);
+        const int r = static_cast<int>(__brev(static_cast<unsigned>(e)) >> (32 - a.logN));
+        buf[slot(l * a.N + r)] = v[k];
+    }
+}
+
+// S consecutive decimation-in-time stages (half-sizes m, 2m, .., 2^(S-1) m
+// with m = 2^lm) in one pass over the L lines in LDS: each thread takes
+// groups of 2^S elements i0 + j m (i0 = block of 2^S m + position < m),
+// applies the stages' butterflies to them in registers -- the same
+// butterflies, twiddles and operation order as S separate radix-2 stages --
+// and writes them back.
+template <int S>
+__device__ __forceinline__ void fft_pass(double2* buf, const double2* __restrict__ tw, int logN, int L, int lm) {
+    constexpr int R = 1 << S;
+    const int N = 1 << logN, m = 1 << lm;
+    const int groups = L << (logN - S);
+    for (int t = threadIdx.x; t < groups; t += blockDim.x) {
+        const int l = t >> (logN - S), q = t & ((N >> S) - 1);
+        const int pos = q & (m - 1), i0 = ((q >> lm) << (lm + S)) + pos;
+        const int base = l * N + i0;
+        double2 x[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) x[j] = buf[slot(base + j * m)];
+#pragma unroll
+        for (int k = 0; k < S; ++k) {
+            const int hk = 1 << k, sh = logN - 1 - lm - k;
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                if (j & hk) continue;
+                const double2 w = tw[(pos + (j & (hk - 1)) * m) << sh];
+                const double2 u = x[j], v = cmul(x[j + hk], w);
+                x[j] = make_double2(u.x + v.x, u.y + v.y);
+                x[j + hk] = make_double2(u.x - v.x, u.y - v.y);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < R; ++j) buf[slot(base + j * m)] = x[j];
+    }
+}
+
 __global__ __launch_bounds__(256) void fft_lines(SpecFftArgs a) {
-    extern __shared__ double2 buf[];  // [L][N]
+    extern __shared__ double2 buf[];  // [L][N] plus one pad slot per 16 (slot())
     const int N = a.N, L = a.L, b = blockIdx.x;
     const int logN = a.logN, logL = a.logL;
     const int total = L * N;
@@ -47,57 +119,27 @@ __global__ __launch_bounds__(256) void fft_lines(SpecFftArgs a) {
     const size_t outer = static_cast<size_t>(b) >> logper;
     const size_t z0 = static_cast<size_t>(b & ((1 << logper) - 1)) << logL;
     // load: consecutive threads take consecutive global addresses (powers of
-    // two: shifts and masks instead of divisions).  Full batches (N >= 64:
-    // L N = 4096 = 16 elements per thread) issue all of a thread's loads
+    // two: shifts and masks instead of divisions).  Full batches (L N = 2048
+    // or 4096: 8 or 16 elements per thread) issue all of a thread's loads
     // before its LDS stores.
-    auto split = [&](int idx, int& l, int& e) {
-        if (a.axis == 0) {
-            l = idx >> logN;
-            e = idx & (N - 1);
-        } else {
-            e = idx >> logL;
-            l = idx & (L - 1);
-        }
-    };
-    constexpr int kIter = 4096 / 256;
-    if (total == kIter * 256 && blockDim.x == 256) {
-        double2 v[kIter];
-#pragma unroll
-        for (int k = 0; k < kIter; ++k) {
-            int l, e;
-            split(static_cast<int>(threadIdx.x) + k * 256, l, e);
-            v[k] = a.data[line_elem(a, b, outer, z0, l, e)];
-        }
-#pragma unroll
-        for (int k = 0; k < kIter; ++k) {
-            int l, e;
-            split(static_cast<int>(threadIdx.x) + k * 256, l, e);
-            const int r = static_cast<int>(__brev(static_cast<unsigned>(e)) >> (32 - logN));
-            buf[l * N + r] = v[k];
-        }
-    } else {
+    if (total == 2048 && blockDim.x == 256) load_lines<8>(a, b, outer, z0, buf);
+    else if (total == 4096 && blockDim.x == 256) load_lines<16>(a, b, outer, z0, buf);
+    else
         for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
             int l, e;
-            split(idx, l, e);
+            line_split(a, idx, l, e);
             const int r = static_cast<int>(__brev(static_cast<unsigned>(e)) >> (32 - logN));
-            buf[l * N + r] = a.data[line_elem(a, b, outer, z0, l, e)];
+            buf[slot(l * N + r)] = a.data[line_elem(a, b, outer, z0, l, e)];
         }
-    }
     __syncthreads();
-    const int half = N / 2;
-    for (int m = 1, lm = 0; m < N; m <<= 1, ++lm) {
-        const int tshift = logN - 1 - lm;  // twiddle stride N / (2 m)
-        for (int t = threadIdx.x; t < L * half; t += blockDim.x) {
-            const int l = t >> (logN - 1), k = t & (half - 1);
-            const int pos = k & (m - 1), i = ((k >> lm) << (lm + 1)) + pos, j = i + m;
-            const double2 w = a.tw[pos << tshift];
-            double2* line = buf + l * N;
-            const double2 u = line[i];
-            const double2 v = cmul(line[j], w);
-            line[i] = make_double2(u.x + v.x, u.y + v.y);
-            line[j] = make_double2(u.x - v.x, u.y - v.y);
-        }
+    // the log2 N butterfly stages, up to three per pass over LDS
+    for (int lm = 0; lm < logN;) {
+        const int s = logN - lm >= 3 ? 3 : logN - lm;
+        if (s == 3) fft_pass<3>(buf, a.tw, logN, L, lm);
+        else if (s == 2) fft_pass<2>(buf, a.tw, logN, L, lm);
+        else fft_pass<1>(buf, a.tw, logN, L, lm);
         __syncthreads();
+        lm += s;
     }
     for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
         int l, e;
@@ -108,7 +150,7 @@ __global__ __launch_bounds__(256) void fft_lines(SpecFftArgs a) {
             e = idx >> logL;
             l = idx & (L - 1);
         }
-        a.data[line_elem(a, b, outer, z0, l, e)] = buf[l * N + e];
+        a.data[line_elem(a, b, outer, z0, l, e)] = buf[slot(l * N + e)];
     }
 }
 
@@ -242,7 +284,9 @@ hipError_t launch_gw_bin(const double2* U, int N, double width, int nbins, doubl
     return hipGetLastError();
 }
 
-int spec_lines_per_block(int N) { return N <= 64 ? N : 4096 / N; }
+// Lines per workgroup: L N = 2048 complex values (32 KB of LDS, five
+// workgroups per CU) where N allows it, whole slabs below.
+int spec_lines_per_block(int N) { return N <= 32 ? N : (N <= 2048 ? 2048 / N : 1); }
 
 hipError_t launch_spec_fft(double2* data, const double2* tw, int N, int axis, hipStream_t s) {
     SpecFftArgs a;
@@ -256,7 +300,7 @@ hipError_t launch_spec_fft(double2* data, const double2* tw, int N, int axis, hi
     while ((1 << a.logL) < a.L) ++a.logL;
     a.axis = axis;
     const int batches = N * N / a.L;
-    const size_t lds = static_cast<size_t>(a.L) * N * sizeof(double2);
+    const size_t lds = static_cast<size_t>(a.L) * N * 17 / 16 * sizeof(double2);  // with the pad slots
     hipLaunchKernelGGL(fft_lines, dim3(batches), dim3(256), lds, s, a);
     return hipGetLastError();
 }
