@@ -68,14 +68,16 @@ def hartree_potential(fbar, var, P):
     return float(gaussian_average(lambda f: L.potential(f, P), fbar, var, P))
 
 
-def predictor(fbar, pbar, a, b, var, rho_r0, a_ref, dt, n, integrator, P: L.Params, record=None):
+def predictor(fbar, pbar, a, b, var, rho_r0, a_ref, dt, n, integrator, P: L.Params, record=None, trace=None):
     """Step 2: (fbar, pbar, a, b) after n steps of dt (leapfrog = VV2(dt),
     vv4 = VV2(w1 dt) VV2(w0 dt) VV2(w1 dt)), each VV2 sub-step in the order
     of the lattice step: half kick of p and b (b's from the energies before
     the kick, at the synchronised momenta), drift of a and f with the
     midpoint a, half kick of p and b (b's from the energies after it).
     If `record` is a list, the homogeneous sums (sum_j p_j^2 / 2, Hartree
-    average of V) at every evaluation of b's kick are appended to it."""
+    average of V) at every evaluation of b's kick are appended to it.  If
+    `trace` is a list, every field half kick appends ("kick", h/2, a, f) and
+    every drift ("drift", h abar^(alpha-3)), in order."""
     f = np.array(fbar, dtype=np.float64)
     p = np.array(pbar, dtype=np.float64)
     al, nf = P.alpha, P.n_fields
@@ -95,11 +97,17 @@ def predictor(fbar, pbar, a, b, var, rho_r0, a_ref, dt, n, integrator, P: L.Para
     def vv2(h):
         nonlocal f, p, a, b
         A0 = accel(a)  # energies at the synchronised momenta, as the lattice step takes them
+        if trace is not None:
+            trace.append(("kick", 0.5 * h, a, f.copy()))
         p = p - 0.5 * h * a ** (3.0 + al) * hartree_force(f, var, P)
         b = b + 0.5 * h * A0
         a_new = a + h * b if expand else a
+        if trace is not None:
+            trace.append(("drift", h * (0.5 * (a + a_new)) ** (al - 3.0)))
         f = f + h * (0.5 * (a + a_new)) ** (al - 3.0) * p
         a = a_new
+        if trace is not None:
+            trace.append(("kick", 0.5 * h, a, f.copy()))
         p = p - 0.5 * h * a ** (3.0 + al) * hartree_force(f, var, P)
         b = b + 0.5 * h * accel(a)
 
