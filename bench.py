@@ -386,6 +386,25 @@ def surrogate_run(epochs=12, pairs_per_seed=64, train_seeds=range(2000, 2008), e
                               "network_tflops": flops / srep["net_seconds"] / 1e12,
                               "mfma_frac": flops / srep["net_seconds"] / MFMA_BF16_PEAK}
         lat.close()
+        # the linear propagation of the fluctuations instead of the network,
+        # with the same gates and fallback
+        lat = lattice("fp32")
+        s.set_jump("linear")
+        s.advance(lat, "vv4", w.dt, 1, threshold=1e-3)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        recs, srep = s.advance(lat, "vv4", w.dt, njumps, threshold=1e-3)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t1
+        s.set_jump("network")
+        errs = _scalar_errors(recs, rr, 2)
+        forms["linear_jump"] = {"effective_site_updates_per_s": w.sites * njumps * K / sec, "seconds": sec,
+                                "accepted_fraction": 1.0 - srep["fallbacks"] / max(1, njumps),
+                                "fluct_gate_rejects": srep["fluct_rejects"], "max_residual": srep["max_residual"],
+                                "error_vs_fp64_vv4": errs["max"], "errors": errs,
+                                "field_error": _field_error(lat, ref),
+                                "propagation_ms_per_jump": 1e3 * srep["net_seconds"] / max(1, njumps)}
+        lat.close()
         # the Hubble-residual gate alone (second gate off)
         lat = lattice("fp32")
         s.set_gate(0.0)

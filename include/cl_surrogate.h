@@ -175,6 +175,28 @@ cl_status cl_surrogate_load(cl_surrogate* s, const char* path);
  * the gate off. */
 cl_status cl_surrogate_set_gate(cl_surrogate* s, double fluct_tol);
 
+/* How cl_surrogate_advance forms a jump's new fluctuations.
+ * CL_JUMP_NETWORK (default): the network's predicted increment.
+ * CL_JUMP_LINEAR: no network; every lattice Fourier mode of the fluctuations
+ * is advanced by the integrator's own kick-drift-kick sub-steps of the
+ * equations of motion (Sect. 2.1, Eq. singletEOM in program variables)
+ * linearised about the FP64 background the predictor integrates: the
+ * 7-point Laplacian's eigenvalue kappa^2 = sum_i (2/dx)^2 sin^2(pi n_i / N)
+ * and the mass matrix d2V/df_i df_j at the predicted homogeneous values,
+ * Hartree-averaged over Gaussian fluctuations of the start variances.  The
+ * fluctuations go through the library's FP64 FFT (two real channels per
+ * complex transform), so the jump costs a few lattice passes however many
+ * steps it stands for.  Exact up to rounding for free fields on a static
+ * background; otherwise its error is the fluctuations' self-interaction over
+ * the jump, which the gates catch as it grows.  Needs no training or
+ * normalisation.  The propagation over a jump depends on a mode only through
+ * kappa^2, even in each mode index and symmetric in their order, so one
+ * transfer matrix per sorted triple of folded indices is built per jump
+ * (C(N/2+3, 3) entries of 128 bytes: 47 MB at N = 256); N <= 1024
+ * (CL_EUNSUPPORTED above). */
+typedef enum { CL_JUMP_NETWORK = 0, CL_JUMP_LINEAR = 1 } cl_jump_mode;
+cl_status cl_surrogate_set_jump(cl_surrogate* s, cl_jump_mode mode);
+
 cl_status cl_surrogate_advance(cl_lattice* h, cl_surrogate* s, cl_integrator fallback, double dt, int n_jumps,
                                double threshold, cl_observables* per_jump, cl_surrogate_report* rep);
 

@@ -136,6 +136,7 @@ _SIGS = {
     "cl_surrogate_save": (C.c_int, [_P, C.c_char_p]),
     "cl_surrogate_load": (C.c_int, [_P, C.c_char_p]),
     "cl_surrogate_set_gate": (C.c_int, [_P, C.c_double]),
+    "cl_surrogate_set_jump": (C.c_int, [_P, C.c_int]),
     "cl_surrogate_advance": (C.c_int, [_P, _P, C.c_int, C.c_double, C.c_int, C.c_double, _P,
                                        C.POINTER(cl_surrogate_report)]),
 }
@@ -438,6 +439,14 @@ class Surrogate:
 
     def load(self, path: str):
         _scheck(lib.cl_surrogate_load(self.s, path.encode()))
+
+    JUMP_MODES = {"network": 0, "linear": 1}
+
+    def set_jump(self, mode: str):
+        """cl_surrogate_set_jump: "network" (the learned increment) or
+        "linear" (the fluctuations' modes advanced by the linearised
+        equations through the device FFT)."""
+        _scheck(lib.cl_surrogate_set_jump(self.s, self.JUMP_MODES[mode]))
 
     def set_gate(self, fluct_tol: float):
         """Tolerance of the second (fluctuation) gate of advance(); <= 0 switches it off."""

@@ -20,7 +20,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libcl_lattice.so")
 
-SOURCES = ["stencil.hip", "surrogate.hip", "spectrum.hip", "noalloc.hip", "lattice_api.cpp", "surrogate_api.cpp",
+SOURCES = ["stencil.hip", "surrogate.hip", "spectrum.hip", "noalloc.hip", "propagator.hip", "lattice_api.cpp", "surrogate_api.cpp",
            "host_seed.cpp"]
 
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

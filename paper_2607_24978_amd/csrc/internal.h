@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 #include "../../include/cl_lattice.h"
 
@@ -181,13 +182,55 @@ hipError_t launch_pass(const PassArgs& a, const Tile& t, cl_precision prec, hipS
 hipError_t launch_finish(const PassArgs& a, const Tile& t, int nf, hipStream_t s);
 // Power spectrum (spectrum.hip).
 hipError_t launch_spec_extract(const void* state, bool fp32, int N, int nf, int arr, double2* out, hipStream_t s);
-hipError_t launch_spec_fft(double2* data, const double2* tw, int N, int axis, hipStream_t s);
+// One axis pass of the line FFT (in place); inverse: conjugate twiddles, no 1/N.
+hipError_t launch_spec_fft(double2* data, const double2* tw, int N, int axis, hipStream_t s, bool inverse = false);
 hipError_t launch_spec_bin(const double2* F, int N, double width, int nbins, double* sums,
                            unsigned long long* counts, hipStream_t s);
 // Gravitational-wave spectrum: projected |U|^2 per centred shell (sums has
 // nbins + 1 slots, the last for the modes beyond the bins).
 hipError_t launch_gw_bin(const double2* U, int N, double width, int nbins, double* sums, unsigned long long* counts,
                          hipStream_t s);
+// Linear propagation of the fluctuations over a jump (propagator.hip): the
+// 2 nf channels f_0..f_{nf-1}, pi_0..pi_{nf-1} of a site minus their means,
+// packed pairwise into nf complex arrays (channel 2q real, 2q+1 imaginary).
+struct PropPackArgs {
+    const void* state;
+    int N, nf;
+    double mean[4];
+    double2* z[2];
+};
+// One kick-drift-kick sub-step of a mode: half kicks pi -= (ck kappa^2 + M) f
+// at its start (0) and end (1), M = (h/2) a^(3+alpha) d2V (m00, m01, m11), and
+// the drift f += cd pi between them.
+struct PropStep {
+    double ck0, m0[3], cd, ck1, m1[3];
+};
+struct PropModeArgs {
+    const double2* in[2];  // forward transforms of the packed arrays
+    double2* out[2];       // propagated modes, packed again, times `scale`
+    int N, nf;
+    const double* kap2;    // [N]: (2/dx)^2 sin^2(pi n / N)
+    const PropStep* steps;
+    int nsteps;
+    double scale;          // 1 / N^3 (the inverse transform's normalisation)
+    double* table;         // [prop_table_entries(N)][16]: transfer matrices (workspace)
+    const uint32_t* triples;  // prop_triples(N) on the device
+    size_t ntriples;
+};
+// Entries of the transfer-matrix table: sorted triples i0 <= i1 <= i2 of
+// folded mode indices (each in [0, N/2]), and the list of them in table
+// order, packed 10 bits each (N <= 1024).
+size_t prop_table_entries(int N);
+std::vector<uint32_t> prop_triples(int N);
+struct PropUnpackArgs {
+    void* state;
+    int N, nf;
+    double mean[4];        // new means of the channels
+    const double2* z[2];   // inverse transforms: the propagated fluctuations
+};
+hipError_t launch_prop_pack(const PropPackArgs& a, bool fp32, hipStream_t s);
+hipError_t launch_prop_modes(const PropModeArgs& a, hipStream_t s);
+hipError_t launch_prop_unpack(const PropUnpackArgs& a, bool fp32, hipStream_t s);
 hipError_t launch_init_scalars(Scal* sc, double a, double b, double eta, const Phys& ph,
                                const double* shift, hipStream_t s);
 // Default tile for a lattice; valid for every N accepted by cl_create.
@@ -213,6 +256,8 @@ cl_status set_error(cl_lattice* h, cl_status st, const char* msg);
 // the step count and the field means (the variance shift); the pass
 // coefficients follow from a.
 cl_status set_background_async(cl_lattice* h, double a, double b, double eta, int64_t step, const double* mean);
+// The line FFT's twiddle table of the lattice (allocated on first use).
+cl_status spectral_twiddles(cl_lattice* h, const double2** tw);
 
 // Host seed (host_seed.cpp): fills f, p (n_fields * N^3 FP64 each).
 // Returns an empty string on success, an error message otherwise.

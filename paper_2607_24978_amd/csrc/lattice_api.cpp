@@ -1113,6 +1113,19 @@ cl_status ensure_twiddles(cl_lattice* h) {
     return CL_OK;
 }
 
+}  // namespace
+
+namespace cl {
+cl_status spectral_twiddles(cl_lattice* h, const double2** tw) {
+    const cl_status st = ensure_twiddles(h);
+    if (st) return st;
+    *tw = h->spec_tw;
+    return CL_OK;
+}
+}  // namespace cl
+
+namespace {
+
 // Per-bin sums and counts for `slots` bins.
 cl_status ensure_bins(cl_lattice* h, int slots) {
     if (h->spec_cap >= slots) return CL_OK;

@@ -21,6 +21,7 @@ struct SpecFftArgs {
     double2* data;       // N^3 complex, site (x N + y) N + z
     const double2* tw;   // exp(-2 pi i k / N), k < N / 2
     int N, logN, L, logL, axis;  // axis 0: z, 1: y, 2: x (N, L powers of two)
+    int inverse;         // 1: exp(+2 pi i k / N) (conjugate twiddles), no scaling
 };
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
@@ -82,7 +83,8 @@ __device__ __forceinline__ void load_lines(const SpecFftArgs& a, int b, size_t o
 // butterflies, twiddles and operation order as S separate radix-2 stages --
 // and writes them back.
 template <int S>
-__device__ __forceinline__ void fft_pass(double2* buf, const double2* __restrict__ tw, int logN, int L, int lm) {
+__device__ __forceinline__ void fft_pass(double2* buf, const double2* __restrict__ tw, int logN, int L, int lm,
+                                         bool inverse) {
     constexpr int R = 1 << S;
     const int N = 1 << logN, m = 1 << lm;
     const int groups = L << (logN - S);
@@ -99,7 +101,8 @@ __device__ __forceinline__ void fft_pass(double2* buf, const double2* __restrict
 #pragma unroll
             for (int j = 0; j < R; ++j) {
                 if (j & hk) continue;
-                const double2 w = tw[(pos + (j & (hk - 1)) * m) << sh];
+                double2 w = tw[(pos + (j & (hk - 1)) * m) << sh];
+                if (inverse) w.y = -w.y;
                 const double2 u = x[j], v = cmul(x[j + hk], w);
                 x[j] = make_double2(u.x + v.x, u.y + v.y);
                 x[j + hk] = make_double2(u.x - v.x, u.y - v.y);
@@ -135,9 +138,9 @@ __global__ __launch_bounds__(256) void fft_lines(SpecFftArgs a) {
     // the log2 N butterfly stages, up to three per pass over LDS
     for (int lm = 0; lm < logN;) {
         const int s = logN - lm >= 3 ? 3 : logN - lm;
-        if (s == 3) fft_pass<3>(buf, a.tw, logN, L, lm);
-        else if (s == 2) fft_pass<2>(buf, a.tw, logN, L, lm);
-        else fft_pass<1>(buf, a.tw, logN, L, lm);
+        if (s == 3) fft_pass<3>(buf, a.tw, logN, L, lm, a.inverse != 0);
+        else if (s == 2) fft_pass<2>(buf, a.tw, logN, L, lm, a.inverse != 0);
+        else fft_pass<1>(buf, a.tw, logN, L, lm, a.inverse != 0);
         __syncthreads();
         lm += s;
     }
@@ -288,8 +291,9 @@ hipError_t launch_gw_bin(const double2* U, int N, double width, int nbins, doubl
 // workgroups per CU) where N allows it, whole slabs below.
 int spec_lines_per_block(int N) { return N <= 32 ? N : (N <= 2048 ? 2048 / N : 1); }
 
-hipError_t launch_spec_fft(double2* data, const double2* tw, int N, int axis, hipStream_t s) {
+hipError_t launch_spec_fft(double2* data, const double2* tw, int N, int axis, hipStream_t s, bool inverse) {
     SpecFftArgs a;
+    a.inverse = inverse ? 1 : 0;
     a.data = data;
     a.tw = tw;
     a.N = N;

@@ -92,6 +92,16 @@ struct cl_surrogate {
     // variance and of the fluctuations' energy (against its redshifted start
     // value); <= 0 switches it off
     double fluct_tol = 0.25;
+    // jump: network increment or linear propagation of the fluctuations
+    cl_jump_mode jump_mode = CL_JUMP_NETWORK;
+    int propN = 0;                              // lattice size of the buffers below
+    double2* pz[2] = {nullptr, nullptr};        // packed fluctuations, forward transforms
+    double2* pw[2] = {nullptr, nullptr};        // propagated modes, inverse transforms
+    double* kap2 = nullptr;                     // [N] lattice Laplacian eigenvalue per index
+    double* ptable = nullptr;                   // transfer matrices per distinct kappa^2
+    uint32_t* ptriples = nullptr;               // the sorted index triples of the table
+    cl::PropStep* psteps = nullptr;             // sub-step coefficients of one jump
+    int psteps_cap = 0;
 };
 
 namespace {
@@ -366,8 +376,23 @@ struct HomSums {
 // sub-step pattern; the fluctuations' kinetic + gradient energy rides along
 // as radiation, rho_r ~ a^-4, p_r = rho_r / 3.  The homogeneous sums at
 // every kick of b are appended to `hom` (for the corrector).
+// Hartree-averaged mass matrix d2V/df_i df_j (m00, m01, m11) at the
+// homogeneous values f over Gaussian fluctuations of variance var.
+void mass_matrix(const cl_lattice* h, const double* f, const double* var, double* M) {
+    const cl_potential& p = h->pot;
+    M[0] = p.m2[0] + 3.0 * p.lambda[0] * (f[0] * f[0] + var[0]);
+    M[1] = 0.0;
+    M[2] = 0.0;
+    if (h->nf == 2) {
+        M[0] += p.g2 * (f[1] * f[1] + var[1]);
+        M[1] = 2.0 * p.g2 * f[0] * f[1];
+        M[2] = p.m2[1] + 3.0 * p.lambda[1] * (f[1] * f[1] + var[1]) + p.g2 * (f[0] * f[0] + var[0]);
+    }
+}
+
 void advance_homogeneous(const cl_lattice* h, cl_integrator integ, double dt, int n, double* f, double* pm, double& a,
-                         double& b, const double* var, double rho_r0, double a_ref, std::vector<HomSums>& hom) {
+                         double& b, const double* var, double rho_r0, double a_ref, std::vector<HomSums>& hom,
+                         std::vector<cl::PropStep>* modes = nullptr) {
     const double al = h->alpha, mp = h->mp;
     const bool expand = h->mode == CL_SELF_CONSISTENT;
     auto accel = [&](double aa) {
@@ -388,9 +413,19 @@ void advance_homogeneous(const cl_lattice* h, cl_integrator integ, double dt, in
         mean_force(h, f, var, dv);
         for (int j = 0; j < h->nf; ++j) pm[j] -= hh * std::pow(aa, 3.0 + al) * dv[j];
     };
+    // a mode's coefficients for a half kick at (a, f): (h/2) a^(1+alpha) for
+    // kappa^2 and (h/2) a^(3+alpha) times the mass matrix
+    auto mode_kick = [&](double hh, double aa, double& ck, double* m) {
+        double M[3];
+        mass_matrix(h, f, var, M);
+        ck = 0.5 * hh * std::pow(aa, 1.0 + al);
+        for (int i = 0; i < 3; ++i) m[i] = 0.5 * hh * std::pow(aa, 3.0 + al) * M[i];
+    };
     auto vv2 = [&](double hh) {
         // the scale-factor half kick takes the energies at the synchronised
         // momenta (before the field half kick), as the lattice step does
+        cl::PropStep ms{};
+        if (modes) mode_kick(hh, a, ms.ck0, ms.m0);
         const double A0 = accel(a);
         kick(0.5 * hh, a);
         b += 0.5 * hh * A0;
@@ -398,6 +433,11 @@ void advance_homogeneous(const cl_lattice* h, cl_integrator integ, double dt, in
         const double abar = 0.5 * (a + an);
         for (int j = 0; j < h->nf; ++j) f[j] += hh * std::pow(abar, al - 3.0) * pm[j];
         a = an;
+        if (modes) {
+            ms.cd = hh * std::pow(abar, al - 3.0);
+            mode_kick(hh, a, ms.ck1, ms.m1);
+            modes->push_back(ms);
+        }
         kick(0.5 * hh, a);
         b += 0.5 * hh * accel(a);
     };
@@ -558,7 +598,9 @@ cl_status cl_surrogate_destroy(cl_surrogate* s) {
         if (ly.bias) hipFree(ly.bias);
     }
     for (void* p : {(void*)s->theta, (void*)s->grad, (void*)s->m, (void*)s->v, (void*)s->ds_fluct,
-                    (void*)s->ds_incr, s->snap})
+                    (void*)s->ds_incr, s->snap, (void*)s->pz[0], (void*)s->pz[1], (void*)s->pw[0],
+                    (void*)s->pw[1], (void*)s->kap2, (void*)s->ptable, (void*)s->ptriples,
+                    (void*)s->psteps})
         if (p) hipFree(p);
     if (s->stream) hipStreamDestroy(s->stream);
     delete s;
@@ -935,6 +977,66 @@ cl_status cl_surrogate_set_gate(cl_surrogate* s, double fluct_tol) {
     return CL_OK;
 }
 
+cl_status cl_surrogate_set_jump(cl_surrogate* s, cl_jump_mode mode) {
+    if (!s) return sfail(CL_EINVAL, "NULL surrogate");
+    if (mode != CL_JUMP_NETWORK && mode != CL_JUMP_LINEAR) return sfail(CL_EINVAL, "unknown jump mode");
+    s->jump_mode = mode;
+    return CL_OK;
+}
+
+namespace {
+
+// Buffers of the linear propagation for an N^3 lattice of nf fields: nf
+// packed complex arrays in and out, the Laplacian eigenvalues per index, the
+// sub-step table.
+cl_status ensure_prop_bufs(cl_surrogate* s, const cl_lattice* h, int nsteps) {
+    const int N = h->N;
+    // the table's index triples are packed 10 bits per index
+    if (N > 1024) return sfail(CL_EUNSUPPORTED, "the linear jump supports N <= 1024");
+    const size_t n3 = static_cast<size_t>(N) * N * N;
+    if (s->propN != N) {
+        for (double2** p : {&s->pz[0], &s->pz[1], &s->pw[0], &s->pw[1]}) {
+            if (*p) hipFree(*p);
+            *p = nullptr;
+        }
+        if (s->kap2) hipFree(s->kap2);
+        if (s->ptable) hipFree(s->ptable);
+        if (s->ptriples) hipFree(s->ptriples);
+        s->kap2 = nullptr;
+        s->ptable = nullptr;
+        s->ptriples = nullptr;
+        s->propN = 0;
+        for (int q = 0; q < h->nf; ++q) {
+            s->pz[q] = dalloc<double2>(n3);
+            s->pw[q] = dalloc<double2>(n3);
+            if (!s->pz[q] || !s->pw[q]) return sfail(CL_ENOMEM, "propagator buffers");
+        }
+        s->kap2 = dalloc<double>(N);
+        s->ptable = dalloc<double>(cl::prop_table_entries(N) * 16);
+        s->ptriples = dalloc<uint32_t>(cl::prop_table_entries(N));
+        if (!s->kap2 || !s->ptable || !s->ptriples) return sfail(CL_ENOMEM, "propagator buffers");
+        const std::vector<uint32_t> tri = cl::prop_triples(N);
+        SHIP(hipMemcpy(s->ptriples, tri.data(), tri.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+        std::vector<double> k2(N);
+        const long double pi = 3.141592653589793238462643383279502884L;
+        for (int n = 0; n < N; ++n) {
+            const double sn = static_cast<double>(std::sin(pi * n / N));
+            k2[n] = 4.0 / (h->dx * h->dx) * sn * sn;
+        }
+        SHIP(hipMemcpy(s->kap2, k2.data(), N * sizeof(double), hipMemcpyHostToDevice));
+        s->propN = N;
+    }
+    if (s->psteps_cap < nsteps) {
+        if (s->psteps) hipFree(s->psteps);
+        s->psteps = dalloc<cl::PropStep>(nsteps);
+        s->psteps_cap = s->psteps ? nsteps : 0;
+        if (!s->psteps) return sfail(CL_ENOMEM, "propagator sub-step table");
+    }
+    return CL_OK;
+}
+
+}  // namespace
+
 cl_status cl_surrogate_advance(cl_lattice* h, cl_surrogate* s, cl_integrator fallback, double dt, int n_jumps,
                                double threshold, cl_observables* per_jump, cl_surrogate_report* rep) {
     if (!h || !s) return sfail(CL_EINVAL, "NULL argument");
@@ -944,13 +1046,21 @@ cl_status cl_surrogate_advance(cl_lattice* h, cl_surrogate* s, cl_integrator fal
         return sfail(CL_EINVAL, "the fallback integrator must be leapfrog or VV4");
     if (h->nf != s->cfg.n_fields) return sfail(CL_EINVAL, "lattice fields do not match the surrogate");
     if (!valid_net_N(h->N)) return sfail(CL_EINVAL, "lattice N must be a power of two >= 16");
-    if (!s->scaled) return sfail(CL_ESTATE, "surrogate has no normalisation (train or load it first)");
+    const bool linear = s->jump_mode == CL_JUMP_LINEAR;
+    if (!linear && !s->scaled) return sfail(CL_ESTATE, "surrogate has no normalisation (train or load it first)");
     if (!(dt > 0.0) || n_jumps < 0) return sfail(CL_EINVAL, "dt > 0 and n_jumps >= 0 needed");
     const auto t0 = std::chrono::steady_clock::now();
     const int N = h->N, K = s->cfg.jump_steps;
     const bool expand = h->mode == CL_SELF_CONSISTENT;
-    cl_status st = ensure_bufs(s, N, false);
+    cl_status st = linear ? CL_OK : ensure_bufs(s, N, false);
     if (st) return st;
+    const double2* tw = nullptr;
+    const int sub = fallback == CL_VV4 ? 3 : 1;  // sub-steps per step
+    if (linear) {
+        if ((st = ensure_prop_bufs(s, h, sub * K))) return st;
+        st = cl::spectral_twiddles(h, &tw);
+        if (st) return sfail(st, cl_last_error(h));
+    }
     const size_t bytes = static_cast<size_t>(2 * h->nf) * N * N * N * (h->prec == CL_FP32 ? 4 : 8);
     if (s->snap_bytes < bytes) {
         if (s->snap) hipFree(s->snap);
@@ -984,6 +1094,7 @@ cl_status cl_surrogate_advance(cl_lattice* h, cl_surrogate* s, cl_integrator fal
     const double al = h->alpha, mp2 = h->mp * h->mp;
     for (int j = 0; j < n_jumps; ++j) {
         SHIP(hipMemcpyAsync(s->snap, h->buf[h->cur], bytes, hipMemcpyDeviceToDevice, h->stream));
+        if (!linear) {
         // network input from the current state, then the network on the
         // surrogate's stream while the host runs the predictor
         cl::sg::PackArgs pa{};
@@ -1008,6 +1119,7 @@ cl_status cl_surrogate_advance(cl_lattice* h, cl_surrogate* s, cl_integrator fal
         if (st) return st;
         SHIP(hipEventRecord(ev[1], s->stream));
         SHIP(hipStreamWaitEvent(h->stream, ev[1], 0));
+        }
         // predictor: homogeneous modes and background over the jump, in FP64
         double f[2] = {o.mean[0], o.mean[1]}, pm[2] = {sc.mean_p[0], sc.mean_p[1]}, var[2] = {o.var[0], o.var[1]};
         double rho_hom_K = 0.0;
@@ -1016,21 +1128,69 @@ cl_status cl_surrogate_advance(cl_lattice* h, cl_surrogate* s, cl_integrator fal
         const double rho_r0 = std::max(0.0, rho_lat - rho_hom_K - hom_V(h, f, var));
         double a = bg.a, b = bg.b;
         std::vector<HomSums> hom;
-        advance_homogeneous(h, fallback, dt, K, f, pm, a, b, var, rho_r0, bg.a, hom);
-        cl::sg::UnpackArgs ua{};
-        ua.state = h->buf[h->cur];
-        ua.N = N;
-        ua.nf = h->nf;
-        for (int jf = 0; jf < h->nf; ++jf) {
-            ua.old_mean[jf] = o.mean[jf];
-            ua.old_mean[h->nf + jf] = sc.mean_p[jf];
-            ua.new_mean[jf] = f[jf];
-            ua.new_mean[h->nf + jf] = pm[jf];
+        std::vector<cl::PropStep> msteps;
+        advance_homogeneous(h, fallback, dt, K, f, pm, a, b, var, rho_r0, bg.a, hom, linear ? &msteps : nullptr);
+        if (linear) {
+            // fluctuations -> modes -> K steps of the linearised equations -> sites
+            SHIP(hipEventRecord(ev[0], h->stream));
+            cl::PropPackArgs pk{};
+            pk.state = h->buf[h->cur];
+            pk.N = N;
+            pk.nf = h->nf;
+            for (int jf = 0; jf < h->nf; ++jf) {
+                pk.mean[jf] = o.mean[jf];
+                pk.mean[h->nf + jf] = sc.mean_p[jf];
+            }
+            for (int q = 0; q < h->nf; ++q) pk.z[q] = s->pz[q];
+            SHIP(cl::launch_prop_pack(pk, h->prec == CL_FP32, h->stream));
+            for (int q = 0; q < h->nf; ++q)
+                for (int axis = 0; axis < 3; ++axis) SHIP(cl::launch_spec_fft(s->pz[q], tw, N, axis, h->stream));
+            SHIP(hipMemcpyAsync(s->psteps, msteps.data(), msteps.size() * sizeof(cl::PropStep), hipMemcpyHostToDevice,
+                                h->stream));
+            cl::PropModeArgs pmd{};
+            for (int q = 0; q < h->nf; ++q) {
+                pmd.in[q] = s->pz[q];
+                pmd.out[q] = s->pw[q];
+            }
+            pmd.N = N;
+            pmd.nf = h->nf;
+            pmd.kap2 = s->kap2;
+            pmd.steps = s->psteps;
+            pmd.nsteps = static_cast<int>(msteps.size());
+            pmd.scale = 1.0 / (static_cast<double>(N) * N * N);
+            pmd.table = s->ptable;
+            pmd.triples = s->ptriples;
+            pmd.ntriples = cl::prop_table_entries(N);
+            SHIP(cl::launch_prop_modes(pmd, h->stream));
+            for (int q = 0; q < h->nf; ++q)
+                for (int axis = 0; axis < 3; ++axis) SHIP(cl::launch_spec_fft(s->pw[q], tw, N, axis, h->stream, true));
+            cl::PropUnpackArgs pu{};
+            pu.state = h->buf[h->cur];
+            pu.N = N;
+            pu.nf = h->nf;
+            for (int jf = 0; jf < h->nf; ++jf) {
+                pu.mean[jf] = f[jf];
+                pu.mean[h->nf + jf] = pm[jf];
+            }
+            for (int q = 0; q < h->nf; ++q) pu.z[q] = s->pw[q];
+            SHIP(cl::launch_prop_unpack(pu, h->prec == CL_FP32, h->stream));
+            SHIP(hipEventRecord(ev[1], h->stream));
+        } else {
+            cl::sg::UnpackArgs ua{};
+            ua.state = h->buf[h->cur];
+            ua.N = N;
+            ua.nf = h->nf;
+            for (int jf = 0; jf < h->nf; ++jf) {
+                ua.old_mean[jf] = o.mean[jf];
+                ua.old_mean[h->nf + jf] = sc.mean_p[jf];
+                ua.new_mean[jf] = f[jf];
+                ua.new_mean[h->nf + jf] = pm[jf];
+            }
+            for (int c = 0; c < 2 * h->nf; ++c) ua.out_scale[c] = s->out_scale[c];
+            ua.y = s->y;
+            ua.ystride = ystride(s);
+            SHIP(cl::sg::launch_unpack_jump(ua, h->prec == CL_FP32, h->stream));
         }
-        for (int c = 0; c < 2 * h->nf; ++c) ua.out_scale[c] = s->out_scale[c];
-        ua.y = s->y;
-        ua.ystride = ystride(s);
-        SHIP(cl::sg::launch_unpack_jump(ua, h->prec == CL_FP32, h->stream));
         const double eta1 = bg.eta + K * dt;
         const int64_t step1 = bg.step + K;
         // a prediction that leaves the background non-finite or a <= 0 is rejected outright
