@@ -275,7 +275,7 @@ def surrogate_train_profile(N=128, pairs=4, epochs=5):
         lat.step("vv4", w.dt, K, record=False)
         s.record_target(lat)
     lat.close()
-    rep = s.train(epochs=epochs, lr=1e-3, lr_final=1e-5, shuffle_seed=0, holdout=0)
+    rep = s.train(epochs=epochs, lr=5e-4, lr_final=5e-6, shuffle_seed=0, holdout=0)
     s.close()
     return {"N": N, "steps": rep["steps"], "steps_per_s": rep["steps"] / rep["seconds"],
             "flops_per_step": 3 * surrogate_flops_per_site(4) * N ** 3}
@@ -330,7 +330,7 @@ def surrogate_run(epochs=12, pairs_per_seed=64, train_seeds=range(2000, 2008), e
     torch.cuda.synchronize()
     out["pairs"] = s.dataset_size()
     out["datagen_s"] = time.perf_counter() - t0
-    rep = s.train(epochs=epochs, lr=1e-3, lr_final=1e-5, shuffle_seed=0, holdout=pairs_per_seed // 2)
+    rep = s.train(epochs=epochs, lr=5e-4, lr_final=5e-6, shuffle_seed=0, holdout=pairs_per_seed // 2)
     out["train"] = rep
     out["train_steps_per_s"] = rep["steps"] / rep["seconds"]
 
@@ -396,7 +396,6 @@ def surrogate_run(epochs=12, pairs_per_seed=64, train_seeds=range(2000, 2008), e
         recs, srep = s.advance(lat, "vv4", w.dt, njumps, threshold=1e-3)
         torch.cuda.synchronize()
         sec = time.perf_counter() - t1
-        s.set_jump("network")
         errs = _scalar_errors(recs, rr, 2)
         forms["linear_jump"] = {"effective_site_updates_per_s": w.sites * njumps * K / sec, "seconds": sec,
                                 "accepted_fraction": 1.0 - srep["fallbacks"] / max(1, njumps),
@@ -404,6 +403,25 @@ def surrogate_run(epochs=12, pairs_per_seed=64, train_seeds=range(2000, 2008), e
                                 "error_vs_fp64_vv4": errs["max"], "errors": errs,
                                 "field_error": _field_error(lat, ref),
                                 "propagation_ms_per_jump": 1e3 * srep["net_seconds"] / max(1, njumps)}
+        lat.close()
+        # ... with the Hubble-residual gate alone (a resonance may grow a
+        # variance by more than the second gate's 25 % within one jump)
+        lat = lattice("fp32")
+        s.set_gate(0.0)
+        s.advance(lat, "vv4", w.dt, 1, threshold=1e-3)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        recs, srep = s.advance(lat, "vv4", w.dt, njumps, threshold=1e-3)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t1
+        s.set_gate(0.25)
+        s.set_jump("network")
+        errs = _scalar_errors(recs, rr, 2)
+        forms["linear_jump_hubble_gate_only"] = {"effective_site_updates_per_s": w.sites * njumps * K / sec,
+                                                 "accepted_fraction": 1.0 - srep["fallbacks"] / max(1, njumps),
+                                                 "max_residual": srep["max_residual"],
+                                                 "error_vs_fp64_vv4": errs["max"], "errors": errs,
+                                                 "field_error": _field_error(lat, ref)}
         lat.close()
         # the Hubble-residual gate alone (second gate off)
         lat = lattice("fp32")
@@ -472,7 +490,7 @@ def surrogate_run(epochs=12, pairs_per_seed=64, train_seeds=range(2000, 2008), e
                 lat.step("vv4", w.dt, K, record=False)
                 s.record_target(lat)
             lat.close()
-        rep6 = s.train(epochs=epochs, lr=1e-3, lr_final=1e-5, shuffle_seed=0, holdout=pairs_per_seed // 2)
+        rep6 = s.train(epochs=epochs, lr=5e-4, lr_final=5e-6, shuffle_seed=0, holdout=pairs_per_seed // 2)
         extra_inputs, saved = 2, extra_inputs
         e6 = evaluate(128, 0.5, jumps)
         extra_inputs = saved
@@ -745,8 +763,9 @@ def main():
     ap.add_argument("--no-c3", action="store_true", help="skip the 1024^3 leapfrog leg of the default run")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the power-spectrum, gravitational-wave and 2+1 legs of the default run")
-    ap.add_argument("--profile-leg", choices=["gw", "batched"], default=None,
-                    help="only run that leg (for a kernel profile; --steps / --warmup set its length) and print it")
+    ap.add_argument("--profile-leg", choices=["gw", "batched", "surrogate"], default=None,
+                    help="only run that leg (for a kernel profile; --steps / --warmup set the length of gw and "
+                         "batched) and print it")
     ap.add_argument("--workload", choices=["c1", "c3"], default="c1",
                     help="c1: 256^3 two-field VV4 (default); c3: 1024^3 two-field leapfrog")
     args = ap.parse_args()
@@ -767,6 +786,10 @@ def main():
     if args.profile_leg == "gw":
         print(json.dumps(gw_run(W.C1, steps=args.steps or 200, warmup=args.warmup or 20, tune=not args.no_tune)),
               flush=True)
+        return
+    if args.profile_leg == "surrogate":
+        print(json.dumps(surrogate_run(epochs=args.sg_epochs, pairs_per_seed=args.sg_pairs, jumps=args.sg_jumps,
+                                       extra_inputs=args.sg_extra, ablation=args.sg_ablation)), flush=True)
         return
     if args.profile_leg == "batched":
         # one solo step per member only: the solo comparison is not what is profiled
