@@ -28,9 +28,10 @@ def _free_static(N=32, precision="fp64"):
     return P, L.State(f, p, 1.0, 0.0), lat
 
 
-def test_free_fields_static_equal_the_integrator():
-    """Free fields, static background: two linear jumps of 16 VV4 steps equal
-    32 VV4 steps of the library's integrator and of the lattice oracle (the
+@pytest.mark.parametrize("integrator", ["vv4", "leapfrog"])
+def test_free_fields_static_equal_the_integrator(integrator):
+    """Free fields, static background: two linear jumps of 16 steps equal 32
+    steps of the library's integrator and of the lattice oracle (the
     equations are linear, the propagation exact up to rounding)."""
     from oracle import lattice as L
     lib = _lib()
@@ -43,12 +44,12 @@ def test_free_fields_static_equal_the_integrator():
     sg = lib.Surrogate(n_fields=2, extra_inputs=2, layers=2, jump_steps=16, init_seed=1)
     sg.set_jump("linear")
     sg.set_gate(0.0)
-    recs, rep = sg.advance(lat, "vv4", dt, 2, threshold=float("inf"))
+    recs, rep = sg.advance(lat, integrator, dt, 2, threshold=float("inf"))
     assert rep["fallbacks"] == 0
-    ref.step("vv4", dt, 32, record=False)
+    ref.step(integrator, dt, 32, record=False)
     f, p = lat.get_fields()
     fr, pr = ref.get_fields()
-    so, _ = L.run(s0.copy(), dt, 32, P, "vv4")
+    so, _ = L.run(s0.copy(), dt, 32, P, integrator)
     for got, want, scale in ((f, fr, np.max(np.abs(fr))), (p, pr, np.max(np.abs(pr))),
                              (f, so.f, np.max(np.abs(so.f))), (p, so.p, np.max(np.abs(so.p)))):
         err = np.max(np.abs(got - want))
