@@ -1,0 +1,89 @@
+// Device building blocks of the FP64 line FFT: L lines of N complex values
+// (N a power of two) sit in LDS in bit-reversed order along each line, and
+// the log2 N butterfly stages of an iterative decimation-in-time transform
+// run over them, three stages per pass over LDS.  Used by the spectrum's
+// axis passes and by the propagator's fused first and last passes.
+#ifndef CL_FFT_LDS_H
+#define CL_FFT_LDS_H
+
+#include <hip/hip_runtime.h>
+
+namespace cl {
+
+// Lines per workgroup: L N = 2048 complex values (32 KB of LDS plus the pad
+// slots) where N allows it, whole slabs below.
+__host__ __device__ inline int fft_lines_per_block(int N) { return N <= 32 ? N : (N <= 2048 ? 2048 / N : 1); }
+
+// LDS bytes of a batch of L lines of N values, with the pad slots of slot().
+inline size_t fft_lds_bytes(int N, int L) { return static_cast<size_t>(L) * N * 17 / 16 * sizeof(double2); }
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+}
+
+// LDS slot of element i (= l N + e) of a batch: one 16-byte pad after every
+// 16 elements, so that the bit-reversed stores (positions 16 apart) and the
+// first pass's groups (8 apart) fall in different banks.
+__device__ __forceinline__ int slot(int i) { return i + (i >> 4); }
+
+// Bit-reversed position of element e of a line of 2^logN values.
+__device__ __forceinline__ int bitrev(int e, int logN) {
+    return static_cast<int>(__brev(static_cast<unsigned>(e)) >> (32 - logN));
+}
+
+// S consecutive decimation-in-time stages (half-sizes m, 2m, .., 2^(S-1) m
+// with m = 2^lm) in one pass over the L lines in LDS: each thread takes
+// groups of 2^S elements i0 + j m (i0 = block of 2^S m + position < m),
+// applies the stages' butterflies to them in registers -- the same
+// butterflies, twiddles and operation order as S separate radix-2 stages --
+// and writes them back.  tw[k] = exp(-2 pi i k / N), k < N / 2; inverse:
+// conjugate twiddles.
+template <int S>
+__device__ __forceinline__ void fft_pass(double2* buf, const double2* __restrict__ tw, int logN, int L, int lm,
+                                         bool inverse) {
+    constexpr int R = 1 << S;
+    const int N = 1 << logN, m = 1 << lm;
+    const int groups = L << (logN - S);
+    for (int t = threadIdx.x; t < groups; t += blockDim.x) {
+        const int l = t >> (logN - S), q = t & ((N >> S) - 1);
+        const int pos = q & (m - 1), i0 = ((q >> lm) << (lm + S)) + pos;
+        const int base = l * N + i0;
+        double2 x[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) x[j] = buf[slot(base + j * m)];
+#pragma unroll
+        for (int k = 0; k < S; ++k) {
+            const int hk = 1 << k, sh = logN - 1 - lm - k;
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                if (j & hk) continue;
+                double2 w = tw[(pos + (j & (hk - 1)) * m) << sh];
+                if (inverse) w.y = -w.y;
+                const double2 u = x[j], v = cmul(x[j + hk], w);
+                x[j] = make_double2(u.x + v.x, u.y + v.y);
+                x[j + hk] = make_double2(u.x - v.x, u.y - v.y);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < R; ++j) buf[slot(base + j * m)] = x[j];
+    }
+}
+
+// Every stage of the transform of the L bit-reversed lines in LDS, up to
+// three per pass, a barrier after each pass (the caller has placed one after
+// its stores).  The result is in natural order.
+__device__ __forceinline__ void fft_lds_stages(double2* buf, const double2* __restrict__ tw, int logN, int L,
+                                               bool inverse) {
+    for (int lm = 0; lm < logN;) {
+        const int s = logN - lm >= 3 ? 3 : logN - lm;
+        if (s == 3) fft_pass<3>(buf, tw, logN, L, lm, inverse);
+        else if (s == 2) fft_pass<2>(buf, tw, logN, L, lm, inverse);
+        else fft_pass<1>(buf, tw, logN, L, lm, inverse);
+        __syncthreads();
+        lm += s;
+    }
+}
+
+}  // namespace cl
+
+#endif  // CL_FFT_LDS_H

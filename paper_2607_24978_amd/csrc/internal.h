@@ -192,16 +192,20 @@ hipError_t launch_gw_bin(const double2* U, int N, double width, int nbins, doubl
                          hipStream_t s);
 // Linear propagation of the fluctuations over a jump (propagator.hip): the
 // 2 nf channels f_0..f_{nf-1}, pi_0..pi_{nf-1} of a site minus their means,
-// packed pairwise into nf complex arrays (channel 2q real, 2q+1 imaginary).
-struct PropPackArgs {
-    const void* state;
+// packed pairwise into nf complex arrays (channel 2q real, 2q+1 imaginary),
+// go through the three axis passes of the line FFT.  The z pass is fused
+// with the packing (forward) and with the unpacking (inverse): one
+// workgroup takes fft_lines_per_block(N) consecutive rows of array q =
+// blockIdx.y.
+struct PropZArgs {
+    const void* state;  // forward: the state read (row-interleaved)
+    void* out;          // inverse: the state written (may not alias `state`)
+    double2* z[2];      // the packed complex arrays
+    const double2* tw;  // exp(-2 pi i k / N), k < N / 2
     int N, nf;
-    double mean[4];
-    double2* z[2];
+    int logN, L;        // filled by the launchers
+    double mean[4];     // forward: subtracted; inverse: added back
 };
-// One kick-drift-kick sub-step of a mode: half kicks pi -= (ck kappa^2 + M) f
-// at its start (0) and end (1), M = (h/2) a^(3+alpha) d2V (m00, m01, m11), and
-// the drift f += cd pi between them.
 struct PropStep {
     double ck0, m0[3], cd, ck1, m1[3];
 };
@@ -222,15 +226,10 @@ struct PropModeArgs {
 // order, packed 10 bits each (N <= 1024).
 size_t prop_table_entries(int N);
 std::vector<uint32_t> prop_triples(int N);
-struct PropUnpackArgs {
-    void* state;
-    int N, nf;
-    double mean[4];        // new means of the channels
-    const double2* z[2];   // inverse transforms: the propagated fluctuations
-};
-hipError_t launch_prop_pack(const PropPackArgs& a, bool fp32, hipStream_t s);
+// Packing + forward z pass; inverse z pass + unpacking into `out`.
+hipError_t launch_prop_pack_fftz(const PropZArgs& a, bool fp32, hipStream_t s);
+hipError_t launch_prop_ifftz_unpack(const PropZArgs& a, bool fp32, hipStream_t s);
 hipError_t launch_prop_modes(const PropModeArgs& a, hipStream_t s);
-hipError_t launch_prop_unpack(const PropUnpackArgs& a, bool fp32, hipStream_t s);
 hipError_t launch_init_scalars(Scal* sc, double a, double b, double eta, const Phys& ph,
                                const double* shift, hipStream_t s);
 // Default tile for a lattice; valid for every N accepted by cl_create.
@@ -256,6 +255,11 @@ cl_status set_error(cl_lattice* h, cl_status st, const char* msg);
 // the step count and the field means (the variance shift); the pass
 // coefficients follow from a.
 cl_status set_background_async(cl_lattice* h, double a, double b, double eta, int64_t step, const double* mean);
+// One reduction pass of the current state, its observables and the scalar
+// block copied to the host, one wait.  The variance sums are taken about the
+// shift the scalar block holds (set_background_async's means), so the
+// caller sets it at the state's expected means first.
+cl_status observe_once(cl_lattice* h, cl_observables* o, Scal* sc);
 // The line FFT's twiddle table of the lattice (allocated on first use).
 cl_status spectral_twiddles(cl_lattice* h, const double2** tw);
 

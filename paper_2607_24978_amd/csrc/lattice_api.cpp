@@ -551,7 +551,8 @@ cl_status init_scalars(cl_lattice* h, double a, double b, double eta, const doub
 }
 
 // One reduction-only pass over the current state into obs[0].
-cl_status reduce_pass(cl_lattice* h, cl_observables* out) {
+// sc_out (nullable): the scalar block after the pass, copied before the wait
+cl_status reduce_pass(cl_lattice* h, cl_observables* out, Scal* sc_out = nullptr) {
     cl_status st = ensure_obs(h, 1);
     if (st) return st;
     PassArgs r = base_args(h, h->cur);
@@ -565,6 +566,7 @@ cl_status reduce_pass(cl_lattice* h, cl_observables* out) {
     HIPCHECK(h, seq.launch(r));
     HIPCHECK(h, seq.close());
     HIPCHECK(h, hipMemcpyAsync(out, h->obs, sizeof(cl_observables), hipMemcpyDeviceToHost, h->stream));
+    if (sc_out) HIPCHECK(h, hipMemcpyAsync(sc_out, h->sc, sizeof(Scal), hipMemcpyDeviceToHost, h->stream));
     HIPCHECK(h, hipStreamSynchronize(h->stream));
     return CL_OK;
 }
@@ -785,6 +787,8 @@ cl_status set_background_async(cl_lattice* h, double a, double b, double eta, in
     note_background(h, a, mean);
     return CL_OK;
 }
+
+cl_status observe_once(cl_lattice* h, cl_observables* o, Scal* sc) { return reduce_pass(h, o, sc); }
 
 cl_status step_in_work(cl_lattice* h, cl_integrator integ, double dt, int n, cl_observables* per_step,
                        const Work& w) {

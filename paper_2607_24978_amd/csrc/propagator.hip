@@ -19,7 +19,10 @@
 // pi_0..pi_{nf-1}, are packed pairwise into nf complex arrays (channel 2q in
 // the real and 2q+1 in the imaginary part of array q), each transformed with
 // the line FFT; a mode's channels are recovered from the array at k and at
-// -k (Hermitian symmetry of real fields).
+// -k (Hermitian symmetry of real fields).  The packing is fused with the
+// forward z pass and the unpacking with the inverse z pass (the inverse runs
+// x, y, z), so the state is read once and written once per jump.
+#include "fft_lds.h"
 #include "internal.h"
 
 #include <hip/hip_runtime.h>
@@ -29,25 +32,79 @@
 namespace cl {
 namespace {
 
-// state channel c of site (row, z) in the row-interleaved layout
-template <typename T>
-__device__ __forceinline__ size_t chan_index(size_t row, int c, int na, size_t N, size_t z) {
-    return (row * na + c) * N + z;
+// Element idx = l N + e of a batch of L consecutive rows starting at row0:
+// channel c of site (row0 + l, z = e) in the row-interleaved state.
+__device__ __forceinline__ size_t chan_index(size_t row0, int idx, int logN, int c, int na) {
+    const size_t N = size_t{1} << logN;
+    return ((row0 + (idx >> logN)) * na + c) * N + (idx & (N - 1));
 }
 
-template <typename T>
-__global__ void prop_pack(PropPackArgs a) {
-    const size_t N = a.N, n3 = N * N * N;
-    const int na = 2 * a.nf;
+// Fluctuations of channels 2q, 2q+1 of L rows -> LDS, bit-reversed along z
+// (every global load of a thread before its LDS stores), forward z
+// transform, out to z[q].  K = L N / 256 elements per thread (K = 1: L N <=
+// 256, the rest of the threads idle).
+template <typename T, int K>
+__global__ __launch_bounds__(256) void prop_pack_fftz(PropZArgs a) {
+    extern __shared__ double2 buf[];
+    const int N = a.N, logN = a.logN, L = a.L, total = L * N;
+    const int q = blockIdx.y, na = 2 * a.nf;
+    const size_t row0 = static_cast<size_t>(blockIdx.x) * L;
     const T* st = static_cast<const T*>(a.state);
-    for (size_t s = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; s < n3;
-         s += static_cast<size_t>(gridDim.x) * blockDim.x) {
-        const size_t z = s % N, row = s / N;
-        for (int q = 0; q < a.nf; ++q) {
-            const double re = static_cast<double>(st[chan_index<T>(row, 2 * q, na, N, z)]) - a.mean[2 * q];
-            const double im = static_cast<double>(st[chan_index<T>(row, 2 * q + 1, na, N, z)]) - a.mean[2 * q + 1];
-            a.z[q][s] = make_double2(re, im);
+    const double m0 = a.mean[2 * q], m1 = a.mean[2 * q + 1];
+    T re[K], im[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int idx = static_cast<int>(threadIdx.x) + k * 256;
+        if (K > 1 || idx < total) {
+            const size_t i = chan_index(row0, idx, logN, 2 * q, na);
+            re[k] = st[i];
+            im[k] = st[i + N];
         }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int idx = static_cast<int>(threadIdx.x) + k * 256;
+        if (K > 1 || idx < total) {
+            const int l = idx >> logN, e = idx & (N - 1);
+            buf[slot(l * N + bitrev(e, logN))] =
+                make_double2(static_cast<double>(re[k]) - m0, static_cast<double>(im[k]) - m1);
+        }
+    }
+    __syncthreads();
+    fft_lds_stages(buf, a.tw, logN, L, false);
+    double2* out = a.z[q] + row0 * N;
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) out[idx] = buf[slot(idx)];
+}
+
+// Rows of z[q] -> LDS bit-reversed, inverse z transform, then the means
+// added back and channels 2q, 2q+1 of the rows written to `out`.
+template <typename T, int K>
+__global__ __launch_bounds__(256) void prop_ifftz_unpack(PropZArgs a) {
+    extern __shared__ double2 buf[];
+    const int N = a.N, logN = a.logN, L = a.L, total = L * N;
+    const int q = blockIdx.y, na = 2 * a.nf;
+    const size_t row0 = static_cast<size_t>(blockIdx.x) * L;
+    const double2* in = a.z[q] + row0 * N;
+    double2 v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int idx = static_cast<int>(threadIdx.x) + k * 256;
+        if (K > 1 || idx < total) v[k] = in[idx];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int idx = static_cast<int>(threadIdx.x) + k * 256;
+        if (K > 1 || idx < total) buf[slot((idx >> logN) * N + bitrev(idx & (N - 1), logN))] = v[k];
+    }
+    __syncthreads();
+    fft_lds_stages(buf, a.tw, logN, L, true);
+    T* st = static_cast<T*>(a.out);
+    const double m0 = a.mean[2 * q], m1 = a.mean[2 * q + 1];
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        const double2 w = buf[slot(idx)];
+        const size_t i = chan_index(row0, idx, logN, 2 * q, na);
+        st[i] = static_cast<T>(m0 + w.x);
+        st[i + N] = static_cast<T>(m1 + w.y);
     }
 }
 
@@ -59,24 +116,25 @@ __device__ __forceinline__ size_t triple_index(size_t i0, size_t i1, size_t i2) 
 
 // The transfer matrix of the jump for kappa^2 = kap2[i0] + kap2[i1] +
 // kap2[i2], one thread per sorted triple (a.triples lists them in index
-// order, packed 10 bits each): the 2 nf x 2 nf real matrix that maps a mode's
+// order, packed 10 bits each): the 2 NF x 2 NF real matrix that maps a mode's
 // (f, pi) at the start to the end, built by applying every sub-step to the
 // unit vectors (the same operations as on a mode's values; the columns are
-// independent chains).  Layout T[row][col], rows and columns in the channel
-// order f_0.., pi_0...
-__global__ void prop_transfer(PropModeArgs a) {
+// independent chains).  Layout T[row][col] with a stride of 16 per entry,
+// rows and columns in the channel order f_0.., pi_0...
+template <int NF>
+__global__ __launch_bounds__(256) void prop_transfer(PropModeArgs a) {
+    constexpr int NC = 2 * NF;
     const size_t t = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (t >= a.ntriples) return;
     const uint32_t tr = a.triples[t];
     const double kap2 = a.kap2[tr & 1023u] + a.kap2[(tr >> 10) & 1023u] + a.kap2[(tr >> 20) & 1023u];
-    const int nf = a.nf, nc = 2 * nf;
-    double F[4][2], P[4][2];  // [column][field]
+    double F[NC][NF], P[NC][NF];  // [column][field]
 #pragma unroll
-    for (int col = 0; col < 4; ++col)
+    for (int col = 0; col < NC; ++col)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            F[col][j] = (col < nf && j == col) ? 1.0 : 0.0;
-            P[col][j] = (col >= nf && j == col - nf) ? 1.0 : 0.0;
+        for (int j = 0; j < NF; ++j) {
+            F[col][j] = (col == j) ? 1.0 : 0.0;
+            P[col][j] = (col == NF + j) ? 1.0 : 0.0;
         }
     for (int i = 0; i < a.nsteps; ++i) {
         const PropStep& c = a.steps[i];
@@ -84,28 +142,30 @@ __global__ void prop_transfer(PropModeArgs a) {
         for (int half = 0; half < 2; ++half) {
             const double ck = half ? c.ck1 : c.ck0;
             const double* mm = half ? c.m1 : c.m0;  // (h/2) a^(3+alpha) d2V: m00, m01, m11
-            const double g0 = ck * kap2 + mm[0], g1 = ck * kap2 + mm[2];
+            const double g0 = ck * kap2 + mm[0];
 #pragma unroll
-            for (int col = 0; col < 4; ++col) {
-                const double f0 = F[col][0], f1 = F[col][1];
-                if (nf == 1) {
-                    P[col][0] -= g0 * f0;
+            for (int col = 0; col < NC; ++col) {
+                if (NF == 1) {
+                    P[col][0] -= g0 * F[col][0];
                 } else {
+                    const double g1 = ck * kap2 + mm[2];
+                    const double f0 = F[col][0], f1 = F[col][NF - 1];
                     P[col][0] -= g0 * f0 + mm[1] * f1;
-                    P[col][1] -= g1 * f1 + mm[1] * f0;
+                    P[col][NF - 1] -= g1 * f1 + mm[1] * f0;
                 }
-                if (!half) {
-                    F[col][0] += c.cd * P[col][0];
-                    F[col][1] += c.cd * P[col][1];
-                }
+                if (!half)
+#pragma unroll
+                    for (int j = 0; j < NF; ++j) F[col][j] += c.cd * P[col][j];
             }
         }
     }
     double* T = a.table + t * 16;
-    for (int col = 0; col < nc; ++col)
-        for (int j = 0; j < nf; ++j) {
-            T[j * nc + col] = F[col][j];
-            T[(nf + j) * nc + col] = P[col][j];
+#pragma unroll
+    for (int col = 0; col < NC; ++col)
+#pragma unroll
+        for (int j = 0; j < NF; ++j) {
+            T[j * NC + col] = F[col][j];
+            T[(NF + j) * NC + col] = P[col][j];
         }
 }
 
@@ -115,9 +175,13 @@ __global__ void prop_transfer(PropModeArgs a) {
 // Y = (A(k) - conj A(-k)) / (2 i) of every packed array A (Hermitian symmetry
 // of real fields) go through the matrix; then A'(k) = X' + i Y' and
 // A'(-k) = conj X' + i conj Y', times the inverse transform's 1/N^3.  Every
-// mode is read and written once.
-__global__ void prop_modes(PropModeArgs a) {
-    const int N = a.N, nf = a.nf, nc = 2 * nf;
+// mode is read and written once (the planes i2 = 0 and N/2, which are their
+// own mirrors, twice with the same values).  A thread issues the matrix's
+// and all its pairs' loads before the first use.
+template <int NF>
+__global__ __launch_bounds__(256) void prop_modes(PropModeArgs a) {
+    constexpr int NC = 2 * NF;
+    const int N = a.N;
     const size_t M = static_cast<size_t>(N) / 2 + 1;
     const size_t t = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (t >= M * M * M) return;
@@ -126,73 +190,112 @@ __global__ void prop_modes(PropModeArgs a) {
     if (s0 > s1) { const int x = s0; s0 = s1; s1 = x; }
     if (s1 > s2) { const int x = s1; s1 = s2; s2 = x; }
     if (s0 > s1) { const int x = s0; s0 = s1; s1 = x; }
-    const double* T = a.table + triple_index(s0, s1, s2) * 16;
-    double Tm[16];
+    const double2* T2 = reinterpret_cast<const double2*>(a.table + triple_index(s0, s1, s2) * 16);
+    double2 Tv[NC * NC / 2];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) Tm[e] = e < nc * nc ? T[e] : 0.0;
+    for (int e = 0; e < NC * NC / 2; ++e) Tv[e] = T2[e];
     // representatives (sx, sy, +) of the pairs; an index equal to its mirror
     // (0 or N/2) has one sign only
     const bool x1 = i0 == 0 || 2 * i0 == N, y1 = i1 == 0 || 2 * i1 == N;
-    for (int sx = 0; sx < 2; ++sx) {
-        if (sx && x1) break;
-        for (int sy = 0; sy < 2; ++sy) {
-            if (sy && y1) break;
-            const int kx = sx ? (N - i0) & (N - 1) : i0, ky = sy ? (N - i1) & (N - 1) : i1, kz = i2;
-            const size_t k = (static_cast<size_t>(kx) * N + ky) * N + kz;
-            const size_t m = (static_cast<size_t>((N - kx) & (N - 1)) * N + ((N - ky) & (N - 1))) * N + ((N - kz) & (N - 1));
-            double2 ch[4];
-            for (int q = 0; q < nf; ++q) {
-                const double2 p = a.in[q][k], r = a.in[q][m];
-                ch[2 * q] = make_double2(0.5 * (p.x + r.x), 0.5 * (p.y - r.y));
-                ch[2 * q + 1] = make_double2(0.5 * (p.y + r.y), -0.5 * (p.x - r.x));
-            }
-            double2 out[4];
+    size_t k[4], m[4];
+    bool on[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                double2 v = make_double2(0.0, 0.0);
+    for (int p = 0; p < 4; ++p) {
+        const int sx = p >> 1, sy = p & 1;
+        on[p] = !(sx && x1) && !(sy && y1);
+        const int kx = sx ? (N - i0) & (N - 1) : i0, ky = sy ? (N - i1) & (N - 1) : i1, kz = i2;
+        k[p] = (static_cast<size_t>(kx) * N + ky) * N + kz;
+        m[p] = (static_cast<size_t>((N - kx) & (N - 1)) * N + ((N - ky) & (N - 1))) * N + ((N - kz) & (N - 1));
+    }
+    double2 vk[4][NF], vm[4][NF];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    if (i >= nc || j >= nc) continue;
-                    const double tij = Tm[i * nc + j];
-                    v.x += tij * ch[j].x;
-                    v.y += tij * ch[j].y;
-                }
-                out[i] = v;
+    for (int p = 0; p < 4; ++p)
+        if (on[p])
+#pragma unroll
+            for (int q = 0; q < NF; ++q) {
+                vk[p][q] = a.in[q][k[p]];
+                vm[p][q] = a.in[q][m[p]];
             }
-            for (int q = 0; q < nf; ++q) {
-                const double2 x = out[2 * q], y = out[2 * q + 1];
-                a.out[q][k] = make_double2(a.scale * (x.x - y.y), a.scale * (x.y + y.x));
-                a.out[q][m] = make_double2(a.scale * (x.x + y.y), a.scale * (y.x - x.y));
+    double Tm[NC * NC];
+#pragma unroll
+    for (int e = 0; e < NC * NC / 2; ++e) {
+        Tm[2 * e] = Tv[e].x;
+        Tm[2 * e + 1] = Tv[e].y;
+    }
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        if (!on[p]) continue;
+        double2 ch[NC];
+#pragma unroll
+        for (int q = 0; q < NF; ++q) {
+            const double2 u = vk[p][q], r = vm[p][q];
+            ch[2 * q] = make_double2(0.5 * (u.x + r.x), 0.5 * (u.y - r.y));
+            ch[2 * q + 1] = make_double2(0.5 * (u.y + r.y), -0.5 * (u.x - r.x));
+        }
+        double2 out[NC];
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            double2 v = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int j = 0; j < NC; ++j) {
+                const double tij = Tm[i * NC + j];
+                v.x += tij * ch[j].x;
+                v.y += tij * ch[j].y;
             }
+            out[i] = v;
+        }
+#pragma unroll
+        for (int q = 0; q < NF; ++q) {
+            const double2 x = out[2 * q], y = out[2 * q + 1];
+            a.out[q][k[p]] = make_double2(a.scale * (x.x - y.y), a.scale * (x.y + y.x));
+            a.out[q][m[p]] = make_double2(a.scale * (x.x + y.y), a.scale * (y.x - x.y));
         }
     }
 }
 
+template <typename T, int K>
+void launch_zk(bool inverse, const PropZArgs& a, dim3 grid, size_t lds, hipStream_t s) {
+    if (inverse) hipLaunchKernelGGL((prop_ifftz_unpack<T, K>), grid, dim3(256), lds, s, a);
+    else hipLaunchKernelGGL((prop_pack_fftz<T, K>), grid, dim3(256), lds, s, a);
+}
+
+// K = L N / 256 exactly (L N a power of two), or 1 for L N <= 256
 template <typename T>
-__global__ void prop_unpack(PropUnpackArgs a) {
-    const size_t N = a.N, n3 = N * N * N;
-    const int na = 2 * a.nf;
-    T* st = static_cast<T*>(a.state);
-    for (size_t s = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; s < n3;
-         s += static_cast<size_t>(gridDim.x) * blockDim.x) {
-        const size_t z = s % N, row = s / N;
-        for (int q = 0; q < a.nf; ++q) {
-            const double2 v = a.z[q][s];
-            st[chan_index<T>(row, 2 * q, na, N, z)] = static_cast<T>(a.mean[2 * q] + v.x);
-            st[chan_index<T>(row, 2 * q + 1, na, N, z)] = static_cast<T>(a.mean[2 * q + 1] + v.y);
-        }
+hipError_t launch_z(bool inverse, const PropZArgs& a, hipStream_t s) {
+    const int total = a.L * a.N;
+    const dim3 grid(static_cast<unsigned>(a.N) * a.N / a.L, a.nf);
+    const size_t lds = fft_lds_bytes(a.N, a.L);
+    switch (total) {
+        case 2048: launch_zk<T, 8>(inverse, a, grid, lds, s); break;
+        case 1024: launch_zk<T, 4>(inverse, a, grid, lds, s); break;
+        case 512: launch_zk<T, 2>(inverse, a, grid, lds, s); break;
+        default: launch_zk<T, 1>(inverse, a, grid, lds, s); break;
     }
+    return hipGetLastError();
 }
 
-unsigned grid_for(size_t n) { return static_cast<unsigned>(n < 256 * 8192 ? (n + 255) / 256 : 8192); }
+// Completes the z-pass shape (log2 N, rows per workgroup) and checks it:
+// N a power of two <= 1024, L N <= 2048 elements (K <= 8 per thread).
+bool z_shape(PropZArgs& a) {
+    if (a.N < 2 || a.N > 1024 || (a.N & (a.N - 1)) != 0 || (a.nf != 1 && a.nf != 2)) return false;
+    a.logN = 0;
+    while ((1 << a.logN) < a.N) ++a.logN;
+    a.L = fft_lines_per_block(a.N);
+    return a.L * a.N <= 2048;
+}
 
 }  // namespace
 
-hipError_t launch_prop_pack(const PropPackArgs& a, bool fp32, hipStream_t s) {
-    const size_t n3 = static_cast<size_t>(a.N) * a.N * a.N;
-    if (fp32) hipLaunchKernelGGL(prop_pack<float>, dim3(grid_for(n3)), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL(prop_pack<double>, dim3(grid_for(n3)), dim3(256), 0, s, a);
-    return hipGetLastError();
+hipError_t launch_prop_pack_fftz(const PropZArgs& args, bool fp32, hipStream_t s) {
+    PropZArgs a = args;
+    if (!z_shape(a)) return hipErrorInvalidValue;
+    return fp32 ? launch_z<float>(false, a, s) : launch_z<double>(false, a, s);
+}
+
+hipError_t launch_prop_ifftz_unpack(const PropZArgs& args, bool fp32, hipStream_t s) {
+    PropZArgs a = args;
+    if (!z_shape(a)) return hipErrorInvalidValue;
+    return fp32 ? launch_z<float>(true, a, s) : launch_z<double>(true, a, s);
 }
 
 size_t prop_table_entries(int N) {
@@ -211,16 +314,17 @@ std::vector<uint32_t> prop_triples(int N) {
 }
 
 hipError_t launch_prop_modes(const PropModeArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(prop_transfer, dim3(static_cast<unsigned>((a.ntriples + 255) / 256)), dim3(256), 0, s, a);
+    if (a.nf != 1 && a.nf != 2) return hipErrorInvalidValue;
+    const unsigned tgrid = static_cast<unsigned>((a.ntriples + 255) / 256);
     const size_t M = a.N / 2 + 1;
-    hipLaunchKernelGGL(prop_modes, dim3(static_cast<unsigned>((M * M * M + 255) / 256)), dim3(256), 0, s, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_prop_unpack(const PropUnpackArgs& a, bool fp32, hipStream_t s) {
-    const size_t n3 = static_cast<size_t>(a.N) * a.N * a.N;
-    if (fp32) hipLaunchKernelGGL(prop_unpack<float>, dim3(grid_for(n3)), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL(prop_unpack<double>, dim3(grid_for(n3)), dim3(256), 0, s, a);
+    const unsigned mgrid = static_cast<unsigned>((M * M * M + 255) / 256);
+    if (a.nf == 1) {
+        hipLaunchKernelGGL(prop_transfer<1>, dim3(tgrid), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(prop_modes<1>, dim3(mgrid), dim3(256), 0, s, a);
+    } else {
+        hipLaunchKernelGGL(prop_transfer<2>, dim3(tgrid), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(prop_modes<2>, dim3(mgrid), dim3(256), 0, s, a);
+    }
     return hipGetLastError();
 }
 

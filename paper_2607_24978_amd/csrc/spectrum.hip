@@ -9,6 +9,7 @@
 // stages per pass over LDS (radix-8 passes) with a barrier between passes.  For the z axis the L lines are consecutive rows;
 // for the y and x axes they are L consecutive z positions of one y-z (x-z)
 // slab, so every global access moves L consecutive complex values.
+#include "fft_lds.h"
 #include "internal.h"
 
 #include <hip/hip_runtime.h>
@@ -24,10 +25,6 @@ struct SpecFftArgs {
     int inverse;         // 1: exp(+2 pi i k / N) (conjugate twiddles), no scaling
 };
 
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-    return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
-}
-
 // Global index of element e of line l of batch b: for the y and x axes the
 // batch fixes the outer coordinate and the first z of its L lines
 // (`outer`, `z0`, formed once per workgroup).
@@ -38,11 +35,6 @@ __device__ __forceinline__ size_t line_elem(const SpecFftArgs& a, int b, size_t 
     if (a.axis == 1) return (outer * N + e) * N + z;      // x = outer, y = e
     return (static_cast<size_t>(e) * N + outer) * N + z;  // x = e, y = outer
 }
-
-// LDS slot of element i (= l N + e) of a batch: one 16-byte pad after every
-// 16 elements, so that the bit-reversed stores (positions 16 apart) and the
-// first pass's groups (8 apart) fall in different banks.
-__device__ __forceinline__ int slot(int i) { return i + (i >> 4); }
 
 // Element idx of a batch -> (line l, element e): the z axis takes whole
 // lines in turn, the y and x axes the L lines' element e side by side.
@@ -71,45 +63,8 @@ __device__ __forceinline__ void load_lines(const SpecFftArgs& a, int b, size_t o
     for (int k = 0; k < K; ++k) {
         int l, e;
         line_split(a, static_cast<int>(threadIdx.x) + k * 256, l, e);
-        const int r = static_cast<int>(__brev(static_cast<unsigned>(e)) >> (32 - a.logN));
+        const int r = bitrev(e, a.logN);
         buf[slot(l * a.N + r)] = v[k];
-    }
-}
-
-// S consecutive decimation-in-time stages (half-sizes m, 2m, .., 2^(S-1) m
-// with m = 2^lm) in one pass over the L lines in LDS: each thread takes
-// groups of 2^S elements i0 + j m (i0 = block of 2^S m + position < m),
-// applies the stages' butterflies to them in registers -- the same
-// butterflies, twiddles and operation order as S separate radix-2 stages --
-// and writes them back.
-template <int S>
-__device__ __forceinline__ void fft_pass(double2* buf, const double2* __restrict__ tw, int logN, int L, int lm,
-                                         bool inverse) {
-    constexpr int R = 1 << S;
-    const int N = 1 << logN, m = 1 << lm;
-    const int groups = L << (logN - S);
-    for (int t = threadIdx.x; t < groups; t += blockDim.x) {
-        const int l = t >> (logN - S), q = t & ((N >> S) - 1);
-        const int pos = q & (m - 1), i0 = ((q >> lm) << (lm + S)) + pos;
-        const int base = l * N + i0;
-        double2 x[R];
-#pragma unroll
-        for (int j = 0; j < R; ++j) x[j] = buf[slot(base + j * m)];
-#pragma unroll
-        for (int k = 0; k < S; ++k) {
-            const int hk = 1 << k, sh = logN - 1 - lm - k;
-#pragma unroll
-            for (int j = 0; j < R; ++j) {
-                if (j & hk) continue;
-                double2 w = tw[(pos + (j & (hk - 1)) * m) << sh];
-                if (inverse) w.y = -w.y;
-                const double2 u = x[j], v = cmul(x[j + hk], w);
-                x[j] = make_double2(u.x + v.x, u.y + v.y);
-                x[j + hk] = make_double2(u.x - v.x, u.y - v.y);
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < R; ++j) buf[slot(base + j * m)] = x[j];
     }
 }
 
@@ -131,19 +86,12 @@ __global__ __launch_bounds__(256) void fft_lines(SpecFftArgs a) {
         for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
             int l, e;
             line_split(a, idx, l, e);
-            const int r = static_cast<int>(__brev(static_cast<unsigned>(e)) >> (32 - logN));
+            const int r = bitrev(e, logN);
             buf[slot(l * N + r)] = a.data[line_elem(a, b, outer, z0, l, e)];
         }
     __syncthreads();
     // the log2 N butterfly stages, up to three per pass over LDS
-    for (int lm = 0; lm < logN;) {
-        const int s = logN - lm >= 3 ? 3 : logN - lm;
-        if (s == 3) fft_pass<3>(buf, a.tw, logN, L, lm, a.inverse != 0);
-        else if (s == 2) fft_pass<2>(buf, a.tw, logN, L, lm, a.inverse != 0);
-        else fft_pass<1>(buf, a.tw, logN, L, lm, a.inverse != 0);
-        __syncthreads();
-        lm += s;
-    }
+    fft_lds_stages(buf, a.tw, logN, L, a.inverse != 0);
     for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
         int l, e;
         if (a.axis == 0) {
@@ -287,10 +235,6 @@ hipError_t launch_gw_bin(const double2* U, int N, double width, int nbins, doubl
     return hipGetLastError();
 }
 
-// Lines per workgroup: L N = 2048 complex values (32 KB of LDS, five
-// workgroups per CU) where N allows it, whole slabs below.
-int spec_lines_per_block(int N) { return N <= 32 ? N : (N <= 2048 ? 2048 / N : 1); }
-
 hipError_t launch_spec_fft(double2* data, const double2* tw, int N, int axis, hipStream_t s, bool inverse) {
     SpecFftArgs a;
     a.inverse = inverse ? 1 : 0;
@@ -299,12 +243,12 @@ hipError_t launch_spec_fft(double2* data, const double2* tw, int N, int axis, hi
     a.N = N;
     a.logN = 0;
     while ((1 << a.logN) < N) ++a.logN;
-    a.L = spec_lines_per_block(N);
+    a.L = fft_lines_per_block(N);
     a.logL = 0;
     while ((1 << a.logL) < a.L) ++a.logL;
     a.axis = axis;
     const int batches = N * N / a.L;
-    const size_t lds = static_cast<size_t>(a.L) * N * 17 / 16 * sizeof(double2);  // with the pad slots
+    const size_t lds = fft_lds_bytes(N, a.L);
     hipLaunchKernelGGL(fft_lines, dim3(batches), dim3(256), lds, s, a);
     return hipGetLastError();
 }

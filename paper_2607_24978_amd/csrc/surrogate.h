@@ -88,7 +88,8 @@ struct SampleArgs {
 };
 
 struct UnpackArgs {
-    void* state;
+    const void* state;   // the state before the jump
+    void* out;           // the state after it (may not alias `state`)
     int N, nf;
     double old_mean[4], new_mean[4], out_scale[4];
     const float* y;      // FP32 [site][ystride]

@@ -876,13 +876,14 @@ __global__ void unpack_jump(UnpackArgs a) {
     const size_t N = a.N, n3 = N * N * N;
     if (s >= n3) return;
     const size_t z = s % N, row = s / N;
-    T* st = static_cast<T*>(a.state);
+    const T* st = static_cast<const T*>(a.state);
+    T* out = static_cast<T*>(a.out);
     const int na = 2 * a.nf;
     for (int c = 0; c < na; ++c) {
         const size_t i = (row * na + c) * N + z;
         const double old = static_cast<double>(st[i]);
         const double v = a.new_mean[c] + (old - a.old_mean[c]) + a.out_scale[c] * static_cast<double>(a.y[s * a.ystride + c]);
-        st[i] = static_cast<T>(v);
+        out[i] = static_cast<T>(v);
     }
 }
 

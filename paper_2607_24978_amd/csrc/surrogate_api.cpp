@@ -85,22 +85,21 @@ struct cl_surrogate {
     bool scaled = false;
     double in_scale[4] = {1, 1, 1, 1}, out_scale[4] = {1, 1, 1, 1};
     double ex_mean[4] = {0, 0, 0, 0}, ex_std[4] = {1, 1, 1, 1};
-    // inference snapshot
-    void* snap = nullptr;
-    size_t snap_bytes = 0;
     // second gate: largest relative change over a jump of each field's
     // variance and of the fluctuations' energy (against its redshifted start
     // value); <= 0 switches it off
     double fluct_tol = 0.25;
     // jump: network increment or linear propagation of the fluctuations
     cl_jump_mode jump_mode = CL_JUMP_NETWORK;
-    int propN = 0;                              // lattice size of the buffers below
+    int propN = 0;                              // lattice size and spacing of the buffers below
+    double propdx = 0.0;
     double2* pz[2] = {nullptr, nullptr};        // packed fluctuations, forward transforms
     double2* pw[2] = {nullptr, nullptr};        // propagated modes, inverse transforms
     double* kap2 = nullptr;                     // [N] lattice Laplacian eigenvalue per index
     double* ptable = nullptr;                   // transfer matrices per distinct kappa^2
     uint32_t* ptriples = nullptr;               // the sorted index triples of the table
     cl::PropStep* psteps = nullptr;             // sub-step coefficients of one jump
+    cl::PropStep* psteps_host = nullptr;        // their pinned host staging copy
     int psteps_cap = 0;
 };
 
@@ -598,10 +597,11 @@ cl_status cl_surrogate_destroy(cl_surrogate* s) {
         if (ly.bias) hipFree(ly.bias);
     }
     for (void* p : {(void*)s->theta, (void*)s->grad, (void*)s->m, (void*)s->v, (void*)s->ds_fluct,
-                    (void*)s->ds_incr, s->snap, (void*)s->pz[0], (void*)s->pz[1], (void*)s->pw[0],
+                    (void*)s->ds_incr, (void*)s->pz[0], (void*)s->pz[1], (void*)s->pw[0],
                     (void*)s->pw[1], (void*)s->kap2, (void*)s->ptable, (void*)s->ptriples,
                     (void*)s->psteps})
         if (p) hipFree(p);
+    if (s->psteps_host) hipHostFree(s->psteps_host);
     if (s->stream) hipStreamDestroy(s->stream);
     delete s;
     return CL_OK;
@@ -994,7 +994,7 @@ cl_status ensure_prop_bufs(cl_surrogate* s, const cl_lattice* h, int nsteps) {
     // the table's index triples are packed 10 bits per index
     if (N > 1024) return sfail(CL_EUNSUPPORTED, "the linear jump supports N <= 1024");
     const size_t n3 = static_cast<size_t>(N) * N * N;
-    if (s->propN != N) {
+    if (s->propN != N || s->propdx != h->dx) {
         for (double2** p : {&s->pz[0], &s->pz[1], &s->pw[0], &s->pw[1]}) {
             if (*p) hipFree(*p);
             *p = nullptr;
@@ -1006,6 +1006,7 @@ cl_status ensure_prop_bufs(cl_surrogate* s, const cl_lattice* h, int nsteps) {
         s->ptable = nullptr;
         s->ptriples = nullptr;
         s->propN = 0;
+        s->propdx = 0.0;
         for (int q = 0; q < h->nf; ++q) {
             s->pz[q] = dalloc<double2>(n3);
             s->pw[q] = dalloc<double2>(n3);
@@ -1025,12 +1026,18 @@ cl_status ensure_prop_bufs(cl_surrogate* s, const cl_lattice* h, int nsteps) {
         }
         SHIP(hipMemcpy(s->kap2, k2.data(), N * sizeof(double), hipMemcpyHostToDevice));
         s->propN = N;
+        s->propdx = h->dx;
     }
     if (s->psteps_cap < nsteps) {
         if (s->psteps) hipFree(s->psteps);
+        if (s->psteps_host) hipHostFree(s->psteps_host);
+        s->psteps_host = nullptr;
         s->psteps = dalloc<cl::PropStep>(nsteps);
-        s->psteps_cap = s->psteps ? nsteps : 0;
-        if (!s->psteps) return sfail(CL_ENOMEM, "propagator sub-step table");
+        if (s->psteps &&
+            hipHostMalloc(reinterpret_cast<void**>(&s->psteps_host), nsteps * sizeof(cl::PropStep)) != hipSuccess)
+            s->psteps_host = nullptr;
+        s->psteps_cap = s->psteps && s->psteps_host ? nsteps : 0;
+        if (!s->psteps_cap) return sfail(CL_ENOMEM, "propagator sub-step table");
     }
     return CL_OK;
 }
@@ -1061,14 +1068,6 @@ cl_status cl_surrogate_advance(cl_lattice* h, cl_surrogate* s, cl_integrator fal
         st = cl::spectral_twiddles(h, &tw);
         if (st) return sfail(st, cl_last_error(h));
     }
-    const size_t bytes = static_cast<size_t>(2 * h->nf) * N * N * N * (h->prec == CL_FP32 ? 4 : 8);
-    if (s->snap_bytes < bytes) {
-        if (s->snap) hipFree(s->snap);
-        s->snap = nullptr;
-        s->snap_bytes = 0;
-        SHIP(hipMalloc(&s->snap, bytes));
-        s->snap_bytes = bytes;
-    }
     int fallbacks = 0, fluct_rejects = 0;
     double maxr = 0.0, net_ms = 0.0;
     cl_observables o;
@@ -1092,13 +1091,18 @@ cl_status cl_surrogate_advance(cl_lattice* h, cl_surrogate* s, cl_integrator fal
         }
     } ev_guard{ev};
     const double al = h->alpha, mp2 = h->mp * h->mp;
+    const bool fp32 = h->prec == CL_FP32;
     for (int j = 0; j < n_jumps; ++j) {
-        SHIP(hipMemcpyAsync(s->snap, h->buf[h->cur], bytes, hipMemcpyDeviceToDevice, h->stream));
+        // the jump writes the other state buffer; the current one is the
+        // snapshot until the jump is kept
+        const int cur0 = h->cur;
+        void* const src = h->buf[cur0];
+        void* const dst = h->buf[cur0 ^ 1];
         if (!linear) {
         // network input from the current state, then the network on the
         // surrogate's stream while the host runs the predictor
         cl::sg::PackArgs pa{};
-        pa.state = h->buf[h->cur];
+        pa.state = src;
         pa.N = N;
         pa.nf = h->nf;
         double e[4];
@@ -1111,7 +1115,7 @@ cl_status cl_surrogate_advance(cl_lattice* h, cl_surrogate* s, cl_integrator fal
         pa.nextra = s->cfg.extra_inputs;
         for (int k = 0; k < pa.nextra; ++k) pa.extra[k] = static_cast<float>((e[k] - s->ex_mean[k]) / s->ex_std[k]);
         pa.x_out = s->x0;
-        SHIP(cl::sg::launch_pack_state(pa, h->prec == CL_FP32, h->stream));
+        SHIP(cl::sg::launch_pack_state(pa, fp32, h->stream));
         SHIP(hipEventRecord(ev[2], h->stream));
         SHIP(hipStreamWaitEvent(s->stream, ev[2], 0));
         SHIP(hipEventRecord(ev[0], s->stream));
@@ -1119,6 +1123,23 @@ cl_status cl_surrogate_advance(cl_lattice* h, cl_surrogate* s, cl_integrator fal
         if (st) return st;
         SHIP(hipEventRecord(ev[1], s->stream));
         SHIP(hipStreamWaitEvent(h->stream, ev[1], 0));
+        } else {
+            // fluctuations -> modes (packing fused with the z pass, then y and
+            // x) while the host runs the predictor
+            SHIP(hipEventRecord(ev[0], h->stream));
+            cl::PropZArgs pk{};
+            pk.state = src;
+            pk.N = N;
+            pk.nf = h->nf;
+            pk.tw = tw;
+            for (int jf = 0; jf < h->nf; ++jf) {
+                pk.mean[jf] = o.mean[jf];
+                pk.mean[h->nf + jf] = sc.mean_p[jf];
+            }
+            for (int q = 0; q < h->nf; ++q) pk.z[q] = s->pz[q];
+            SHIP(cl::launch_prop_pack_fftz(pk, fp32, h->stream));
+            for (int q = 0; q < h->nf; ++q)
+                for (int axis = 1; axis < 3; ++axis) SHIP(cl::launch_spec_fft(s->pz[q], tw, N, axis, h->stream));
         }
         // predictor: homogeneous modes and background over the jump, in FP64
         double f[2] = {o.mean[0], o.mean[1]}, pm[2] = {sc.mean_p[0], sc.mean_p[1]}, var[2] = {o.var[0], o.var[1]};
@@ -1131,22 +1152,13 @@ cl_status cl_surrogate_advance(cl_lattice* h, cl_surrogate* s, cl_integrator fal
         std::vector<cl::PropStep> msteps;
         advance_homogeneous(h, fallback, dt, K, f, pm, a, b, var, rho_r0, bg.a, hom, linear ? &msteps : nullptr);
         if (linear) {
-            // fluctuations -> modes -> K steps of the linearised equations -> sites
-            SHIP(hipEventRecord(ev[0], h->stream));
-            cl::PropPackArgs pk{};
-            pk.state = h->buf[h->cur];
-            pk.N = N;
-            pk.nf = h->nf;
-            for (int jf = 0; jf < h->nf; ++jf) {
-                pk.mean[jf] = o.mean[jf];
-                pk.mean[h->nf + jf] = sc.mean_p[jf];
-            }
-            for (int q = 0; q < h->nf; ++q) pk.z[q] = s->pz[q];
-            SHIP(cl::launch_prop_pack(pk, h->prec == CL_FP32, h->stream));
-            for (int q = 0; q < h->nf; ++q)
-                for (int axis = 0; axis < 3; ++axis) SHIP(cl::launch_spec_fft(s->pz[q], tw, N, axis, h->stream));
-            SHIP(hipMemcpyAsync(s->psteps, msteps.data(), msteps.size() * sizeof(cl::PropStep), hipMemcpyHostToDevice,
-                                h->stream));
+            // K steps of the linearised equations per mode, then back to sites
+            // (x, y, then the z pass fused with the unpacking into dst)
+            if (msteps.size() > static_cast<size_t>(s->psteps_cap))
+                return sfail(CL_ESTATE, "propagator sub-step table too small");
+            std::copy(msteps.begin(), msteps.end(), s->psteps_host);
+            SHIP(hipMemcpyAsync(s->psteps, s->psteps_host, msteps.size() * sizeof(cl::PropStep),
+                                hipMemcpyHostToDevice, h->stream));
             cl::PropModeArgs pmd{};
             for (int q = 0; q < h->nf; ++q) {
                 pmd.in[q] = s->pz[q];
@@ -1163,21 +1175,23 @@ cl_status cl_surrogate_advance(cl_lattice* h, cl_surrogate* s, cl_integrator fal
             pmd.ntriples = cl::prop_table_entries(N);
             SHIP(cl::launch_prop_modes(pmd, h->stream));
             for (int q = 0; q < h->nf; ++q)
-                for (int axis = 0; axis < 3; ++axis) SHIP(cl::launch_spec_fft(s->pw[q], tw, N, axis, h->stream, true));
-            cl::PropUnpackArgs pu{};
-            pu.state = h->buf[h->cur];
+                for (int axis = 2; axis >= 1; --axis) SHIP(cl::launch_spec_fft(s->pw[q], tw, N, axis, h->stream, true));
+            cl::PropZArgs pu{};
+            pu.out = dst;
             pu.N = N;
             pu.nf = h->nf;
+            pu.tw = tw;
             for (int jf = 0; jf < h->nf; ++jf) {
                 pu.mean[jf] = f[jf];
                 pu.mean[h->nf + jf] = pm[jf];
             }
             for (int q = 0; q < h->nf; ++q) pu.z[q] = s->pw[q];
-            SHIP(cl::launch_prop_unpack(pu, h->prec == CL_FP32, h->stream));
+            SHIP(cl::launch_prop_ifftz_unpack(pu, fp32, h->stream));
             SHIP(hipEventRecord(ev[1], h->stream));
         } else {
             cl::sg::UnpackArgs ua{};
-            ua.state = h->buf[h->cur];
+            ua.state = src;
+            ua.out = dst;
             ua.N = N;
             ua.nf = h->nf;
             for (int jf = 0; jf < h->nf; ++jf) {
@@ -1189,7 +1203,7 @@ cl_status cl_surrogate_advance(cl_lattice* h, cl_surrogate* s, cl_integrator fal
             for (int c = 0; c < 2 * h->nf; ++c) ua.out_scale[c] = s->out_scale[c];
             ua.y = s->y;
             ua.ystride = ystride(s);
-            SHIP(cl::sg::launch_unpack_jump(ua, h->prec == CL_FP32, h->stream));
+            SHIP(cl::sg::launch_unpack_jump(ua, fp32, h->stream));
         }
         const double eta1 = bg.eta + K * dt;
         const int64_t step1 = bg.step + K;
@@ -1200,11 +1214,13 @@ cl_status cl_surrogate_advance(cl_lattice* h, cl_surrogate* s, cl_integrator fal
         const double a_pred = a;
         if (ok) {
             // one reduction of the new state (at the predicted a; the sums
-            // that the corrector needs do not depend on a)
+            // that the corrector needs do not depend on a), its variances
+            // about the predicted means
+            h->cur = cur0 ^ 1;
             st = cl::set_background_async(h, a_pred, b, eta1, step1, f);
             if (st) return sfail(st, cl_last_error(h));
-            st = read_lattice(h, &after, &sca);
-            if (st) return st;
+            st = cl::observe_once(h, &after, &sca);
+            if (st) return sfail(st, cl_last_error(h));
             ok = !after.nonfinite;
         } else {
             SHIP(hipStreamSynchronize(h->stream));
@@ -1270,8 +1286,9 @@ cl_status cl_surrogate_advance(cl_lattice* h, cl_surrogate* s, cl_integrator fal
             sc = sca;
             bg = cl_scalars{a, b, eta1, step1};
         } else {
-            // undo the jump (state and scalar block) and run the integrator instead
-            SHIP(hipMemcpyAsync(h->buf[h->cur], s->snap, bytes, hipMemcpyDeviceToDevice, h->stream));
+            // undo the jump (back to the untouched buffer, the scalar block
+            // as it was) and run the integrator instead
+            h->cur = cur0;
             SHIP(hipMemcpyAsync(h->sc, &sc, sizeof(cl::Scal), hipMemcpyHostToDevice, h->stream));
             SHIP(hipStreamSynchronize(h->stream));
             st = cl_set_state(h, &bg);
