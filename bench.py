@@ -281,6 +281,32 @@ def surrogate_train_profile(N=128, pairs=4, epochs=5):
             "flops_per_step": 3 * surrogate_flops_per_site(4) * N ** 3}
 
 
+def linear_jump_profile(N=256, jumps=10, k_ir=0.25):
+    """Linear jumps (CL_JUMP_LINEAR, 16 VV4 steps each, default gates) on the
+    seeded two-field FP32 workload at N^3 (k_IR = 0.25: the training grid
+    spacing of the surrogate study at 256^3) for a kernel-level profile of
+    one jump: packing fused with the forward z pass, the FP32 y and x
+    passes, the transfer table, the modes, the inverse x and y passes, the
+    inverse z pass fused with the unpacking, and the gates' reduction."""
+    from paper_2607_24978_amd import _lib
+    K = 16
+    w = W.C1.with_(N=N, k_ir=k_ir, seed=3000)
+    lat = _lib.Lattice(w.N, w.dx, 2, "fp32")
+    lat.set_background(w.alpha, w.expansion, w.mp, w.a0)
+    lat.set_potential(w.m2, w.lam, w.g2, w.V0)
+    lat.seed(w.seed, w.fbar[:2], w.pbar[:2], w.cutoff_modes, w.amp)
+    sg = _lib.Surrogate(n_fields=2, extra_inputs=2, layers=2, jump_steps=K, init_seed=1)
+    sg.set_jump("linear")
+    sg.advance(lat, "vv4", w.dt, 1)
+    _, rep = sg.advance(lat, "vv4", w.dt, jumps)
+    lat.close()
+    sg.close()
+    sites = float(N) ** 3
+    return {"N": N, "jumps": jumps, "fallbacks": rep["fallbacks"], "seconds": rep["seconds"],
+            "device_ms_per_jump": 1e3 * rep["net_seconds"] / jumps,
+            "effective_site_updates_per_s": jumps * K * sites / rep["seconds"]}
+
+
 def surrogate_run(epochs=12, pairs_per_seed=64, train_seeds=range(2000, 2008), eval_seed=3000, jumps=312,
                   extra_inputs=4, eval_256=True, ablation=False):
     """The learned surrogate on the two-field q = 100 workload: training pairs
@@ -757,6 +783,8 @@ def main():
     ap.add_argument("--start-at", type=float, default=0.0, help=argparse.SUPPRESS)
     ap.add_argument("--sg-forward-profile", action="store_true",
                     help="only run surrogate forward passes at 256^3 (for a kernel profile) and print their figures")
+    ap.add_argument("--sg-linear-profile", action="store_true",
+                    help="only run linear jumps at 256^3 (for a kernel profile) and print their figures")
     ap.add_argument("--sg-train-profile", action="store_true",
                     help="only run a few surrogate training steps at 128^3 (for a kernel profile) and print their figures")
     ap.add_argument("--cpu-procs", type=int, default=16, help="processes of the all-cores oracle baseline (0: skip)")
@@ -782,6 +810,9 @@ def main():
         return
     if args.sg_train_profile:
         print(json.dumps(surrogate_train_profile()), flush=True)
+        return
+    if args.sg_linear_profile:
+        print(json.dumps(linear_jump_profile()), flush=True)
         return
     if args.profile_leg == "gw":
         print(json.dumps(gw_run(W.C1, steps=args.steps or 200, warmup=args.warmup or 20, tune=not args.no_tune)),

@@ -184,16 +184,20 @@ cl_status cl_surrogate_set_gate(cl_surrogate* s, double fluct_tol);
  * 7-point Laplacian's eigenvalue kappa^2 = sum_i (2/dx)^2 sin^2(pi n_i / N)
  * and the mass matrix d2V/df_i df_j at the predicted homogeneous values,
  * Hartree-averaged over Gaussian fluctuations of the start variances.  The
- * fluctuations go through the library's FP64 FFT (two real channels per
- * complex transform), so the jump costs a few lattice passes however many
- * steps it stands for.  Exact up to rounding for free fields on a static
- * background; otherwise its error is the fluctuations' self-interaction over
- * the jump, which the gates catch as it grows.  Needs no training or
- * normalisation.  The propagation over a jump depends on a mode only through
- * kappa^2, even in each mode index and symmetric in their order, so one
- * transfer matrix per sorted triple of folded indices is built per jump
- * (C(N/2+3, 3) entries of 128 bytes: 47 MB at N = 256); N <= 1024
- * (CL_EUNSUPPORTED above). */
+ * fluctuations go through the library's line FFT (two real channels per
+ * complex transform) in the lattice's precision -- FP64 for FP64 lattices,
+ * FP32 for FP32 lattices, where its rounding relative to the fluctuations
+ * stays below that of the FP32 state -- so the jump costs a few lattice
+ * passes however many steps it stands for.  Exact up to rounding for free
+ * fields on a static background; otherwise its error is the fluctuations'
+ * self-interaction over the jump, which the gates catch as it grows.  Needs
+ * no training or normalisation.  The propagation over a jump depends on a
+ * mode only through kappa^2, even in each mode index and symmetric in their
+ * order, so one FP64 transfer matrix per sorted triple of folded indices is
+ * built per jump (C(N/2+3, 3) entries of 128 bytes: 47 MB at N = 256); N <=
+ * 1024 (CL_EUNSUPPORTED above).  The jump's result is written to the
+ * lattice's second state buffer, which becomes the current one if the jump
+ * is kept (as after an integrator pass). */
 typedef enum { CL_JUMP_NETWORK = 0, CL_JUMP_LINEAR = 1 } cl_jump_mode;
 cl_status cl_surrogate_set_jump(cl_surrogate* s, cl_jump_mode mode);
 

@@ -14,15 +14,25 @@ namespace cl {
 // slots) where N allows it, whole slabs below.
 __host__ __device__ inline int fft_lines_per_block(int N) { return N <= 32 ? N : (N <= 2048 ? 2048 / N : 1); }
 
-// LDS bytes of a batch of L lines of N values, with the pad slots of slot().
-inline size_t fft_lds_bytes(int N, int L) { return static_cast<size_t>(L) * N * 17 / 16 * sizeof(double2); }
+// The same for FP32 values (8 bytes): L N = 4096 (32 KB), so that a global
+// access of the y and x passes still moves 16 consecutive values (128 bytes).
+__host__ __device__ inline int fft_lines_per_block_f32(int N) { return N <= 64 ? N : (N <= 4096 ? 4096 / N : 1); }
+
+// LDS bytes of a batch of L lines of N values of `vbytes` bytes each, with
+// the pad slots of slot().
+inline size_t fft_lds_bytes(int N, int L, size_t vbytes = sizeof(double2)) {
+    return static_cast<size_t>(L) * N * 17 / 16 * vbytes;
+}
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
 }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
 
-// LDS slot of element i (= l N + e) of a batch: one 16-byte pad after every
-// 16 elements, so that the bit-reversed stores (positions 16 apart) and the
+// LDS slot of element i (= l N + e) of a batch: one pad slot after every 16
+// elements, so that the bit-reversed stores (positions 16 apart) and the
 // first pass's groups (8 apart) fall in different banks.
 __device__ __forceinline__ int slot(int i) { return i + (i >> 4); }
 
@@ -37,9 +47,9 @@ __device__ __forceinline__ int bitrev(int e, int logN) {
 // applies the stages' butterflies to them in registers -- the same
 // butterflies, twiddles and operation order as S separate radix-2 stages --
 // and writes them back.  tw[k] = exp(-2 pi i k / N), k < N / 2; inverse:
-// conjugate twiddles.
-template <int S>
-__device__ __forceinline__ void fft_pass(double2* buf, const double2* __restrict__ tw, int logN, int L, int lm,
+// conjugate twiddles.  V2: double2 (FP64) or float2 (FP32).
+template <int S, typename V2>
+__device__ __forceinline__ void fft_pass(V2* buf, const V2* __restrict__ tw, int logN, int L, int lm,
                                          bool inverse) {
     constexpr int R = 1 << S;
     const int N = 1 << logN, m = 1 << lm;
@@ -48,7 +58,7 @@ __device__ __forceinline__ void fft_pass(double2* buf, const double2* __restrict
         const int l = t >> (logN - S), q = t & ((N >> S) - 1);
         const int pos = q & (m - 1), i0 = ((q >> lm) << (lm + S)) + pos;
         const int base = l * N + i0;
-        double2 x[R];
+        V2 x[R];
 #pragma unroll
         for (int j = 0; j < R; ++j) x[j] = buf[slot(base + j * m)];
 #pragma unroll
@@ -57,11 +67,13 @@ __device__ __forceinline__ void fft_pass(double2* buf, const double2* __restrict
 #pragma unroll
             for (int j = 0; j < R; ++j) {
                 if (j & hk) continue;
-                double2 w = tw[(pos + (j & (hk - 1)) * m) << sh];
+                V2 w = tw[(pos + (j & (hk - 1)) * m) << sh];
                 if (inverse) w.y = -w.y;
-                const double2 u = x[j], v = cmul(x[j + hk], w);
-                x[j] = make_double2(u.x + v.x, u.y + v.y);
-                x[j + hk] = make_double2(u.x - v.x, u.y - v.y);
+                const V2 u = x[j], v = cmul(x[j + hk], w);
+                x[j].x = u.x + v.x;
+                x[j].y = u.y + v.y;
+                x[j + hk].x = u.x - v.x;
+                x[j + hk].y = u.y - v.y;
             }
         }
 #pragma unroll
@@ -72,8 +84,8 @@ __device__ __forceinline__ void fft_pass(double2* buf, const double2* __restrict
 // Every stage of the transform of the L bit-reversed lines in LDS, up to
 // three per pass, a barrier after each pass (the caller has placed one after
 // its stores).  The result is in natural order.
-__device__ __forceinline__ void fft_lds_stages(double2* buf, const double2* __restrict__ tw, int logN, int L,
-                                               bool inverse) {
+template <typename V2>
+__device__ __forceinline__ void fft_lds_stages(V2* buf, const V2* __restrict__ tw, int logN, int L, bool inverse) {
     for (int lm = 0; lm < logN;) {
         const int s = logN - lm >= 3 ? 3 : logN - lm;
         if (s == 3) fft_pass<3>(buf, tw, logN, L, lm, inverse);

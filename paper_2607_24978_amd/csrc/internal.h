@@ -184,6 +184,8 @@ hipError_t launch_finish(const PassArgs& a, const Tile& t, int nf, hipStream_t s
 hipError_t launch_spec_extract(const void* state, bool fp32, int N, int nf, int arr, double2* out, hipStream_t s);
 // One axis pass of the line FFT (in place); inverse: conjugate twiddles, no 1/N.
 hipError_t launch_spec_fft(double2* data, const double2* tw, int N, int axis, hipStream_t s, bool inverse = false);
+// The same in FP32 (complex float values and twiddles).
+hipError_t launch_fft_f32(float2* data, const float2* tw, int N, int axis, hipStream_t s, bool inverse);
 hipError_t launch_spec_bin(const double2* F, int N, double width, int nbins, double* sums,
                            unsigned long long* counts, hipStream_t s);
 // Gravitational-wave spectrum: projected |U|^2 per centred shell (sums has
@@ -195,13 +197,14 @@ hipError_t launch_gw_bin(const double2* U, int N, double width, int nbins, doubl
 // packed pairwise into nf complex arrays (channel 2q real, 2q+1 imaginary),
 // go through the three axis passes of the line FFT.  The z pass is fused
 // with the packing (forward) and with the unpacking (inverse): one
-// workgroup takes fft_lines_per_block(N) consecutive rows of array q =
-// blockIdx.y.
+// workgroup takes the line FFT's batch of consecutive rows of array q =
+// blockIdx.y.  The complex arrays and the transforms are in the state's
+// precision (double2 for FP64 lattices, float2 for FP32).
 struct PropZArgs {
     const void* state;  // forward: the state read (row-interleaved)
     void* out;          // inverse: the state written (may not alias `state`)
-    double2* z[2];      // the packed complex arrays
-    const double2* tw;  // exp(-2 pi i k / N), k < N / 2
+    void* z[2];         // the packed complex arrays
+    const void* tw;     // exp(-2 pi i k / N), k < N / 2
     int N, nf;
     int logN, L;        // filled by the launchers
     double mean[4];     // forward: subtracted; inverse: added back
@@ -210,8 +213,8 @@ struct PropStep {
     double ck0, m0[3], cd, ck1, m1[3];
 };
 struct PropModeArgs {
-    const double2* in[2];  // forward transforms of the packed arrays
-    double2* out[2];       // propagated modes, packed again, times `scale`
+    const void* in[2];     // forward transforms of the packed arrays (state precision)
+    void* out[2];          // propagated modes, packed again, times `scale`
     int N, nf;
     const double* kap2;    // [N]: (2/dx)^2 sin^2(pi n / N)
     const PropStep* steps;
@@ -229,7 +232,9 @@ std::vector<uint32_t> prop_triples(int N);
 // Packing + forward z pass; inverse z pass + unpacking into `out`.
 hipError_t launch_prop_pack_fftz(const PropZArgs& a, bool fp32, hipStream_t s);
 hipError_t launch_prop_ifftz_unpack(const PropZArgs& a, bool fp32, hipStream_t s);
-hipError_t launch_prop_modes(const PropModeArgs& a, hipStream_t s);
+// Transfer matrices (FP64) and their application to every mode; fp32: the
+// arrays hold float2 values (converted to FP64 for the product).
+hipError_t launch_prop_modes(const PropModeArgs& a, bool fp32, hipStream_t s);
 hipError_t launch_init_scalars(Scal* sc, double a, double b, double eta, const Phys& ph,
                                const double* shift, hipStream_t s);
 // Default tile for a lattice; valid for every N accepted by cl_create.

@@ -21,7 +21,11 @@
 // the line FFT; a mode's channels are recovered from the array at k and at
 // -k (Hermitian symmetry of real fields).  The packing is fused with the
 // forward z pass and the unpacking with the inverse z pass (the inverse runs
-// x, y, z), so the state is read once and written once per jump.
+// x, y, z), so the state is read once and written once per jump.  The
+// transforms run in the state's precision: FP32 lattices use float2 values,
+// whose rounding (relative to the fluctuations, from which the means are
+// removed) is far below that of the FP32 state itself; the transfer matrices
+// and their product with a mode are FP64 for both.
 #include "fft_lds.h"
 #include "internal.h"
 
@@ -31,6 +35,14 @@
 
 namespace cl {
 namespace {
+
+template <typename V2>
+__device__ __forceinline__ V2 make_v2(double x, double y) {
+    V2 v;
+    v.x = static_cast<decltype(v.x)>(x);
+    v.y = static_cast<decltype(v.y)>(y);
+    return v;
+}
 
 // Element idx = l N + e of a batch of L consecutive rows starting at row0:
 // channel c of site (row0 + l, z = e) in the row-interleaved state.
@@ -43,9 +55,10 @@ __device__ __forceinline__ size_t chan_index(size_t row0, int idx, int logN, int
 // (every global load of a thread before its LDS stores), forward z
 // transform, out to z[q].  K = L N / 256 elements per thread (K = 1: L N <=
 // 256, the rest of the threads idle).
-template <typename T, int K>
+template <typename T, typename V2, int K>
 __global__ __launch_bounds__(256) void prop_pack_fftz(PropZArgs a) {
-    extern __shared__ double2 buf[];
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    V2* buf = reinterpret_cast<V2*>(lds_raw);
     const int N = a.N, logN = a.logN, L = a.L, total = L * N;
     const int q = blockIdx.y, na = 2 * a.nf;
     const size_t row0 = static_cast<size_t>(blockIdx.x) * L;
@@ -67,25 +80,26 @@ __global__ __launch_bounds__(256) void prop_pack_fftz(PropZArgs a) {
         if (K > 1 || idx < total) {
             const int l = idx >> logN, e = idx & (N - 1);
             buf[slot(l * N + bitrev(e, logN))] =
-                make_double2(static_cast<double>(re[k]) - m0, static_cast<double>(im[k]) - m1);
+                make_v2<V2>(static_cast<double>(re[k]) - m0, static_cast<double>(im[k]) - m1);
         }
     }
     __syncthreads();
-    fft_lds_stages(buf, a.tw, logN, L, false);
-    double2* out = a.z[q] + row0 * N;
+    fft_lds_stages(buf, static_cast<const V2*>(a.tw), logN, L, false);
+    V2* out = static_cast<V2*>(a.z[q]) + row0 * N;
     for (int idx = threadIdx.x; idx < total; idx += blockDim.x) out[idx] = buf[slot(idx)];
 }
 
 // Rows of z[q] -> LDS bit-reversed, inverse z transform, then the means
 // added back and channels 2q, 2q+1 of the rows written to `out`.
-template <typename T, int K>
+template <typename T, typename V2, int K>
 __global__ __launch_bounds__(256) void prop_ifftz_unpack(PropZArgs a) {
-    extern __shared__ double2 buf[];
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    V2* buf = reinterpret_cast<V2*>(lds_raw);
     const int N = a.N, logN = a.logN, L = a.L, total = L * N;
     const int q = blockIdx.y, na = 2 * a.nf;
     const size_t row0 = static_cast<size_t>(blockIdx.x) * L;
-    const double2* in = a.z[q] + row0 * N;
-    double2 v[K];
+    const V2* in = static_cast<const V2*>(a.z[q]) + row0 * N;
+    V2 v[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int idx = static_cast<int>(threadIdx.x) + k * 256;
@@ -97,11 +111,11 @@ __global__ __launch_bounds__(256) void prop_ifftz_unpack(PropZArgs a) {
         if (K > 1 || idx < total) buf[slot((idx >> logN) * N + bitrev(idx & (N - 1), logN))] = v[k];
     }
     __syncthreads();
-    fft_lds_stages(buf, a.tw, logN, L, true);
+    fft_lds_stages(buf, static_cast<const V2*>(a.tw), logN, L, true);
     T* st = static_cast<T*>(a.out);
     const double m0 = a.mean[2 * q], m1 = a.mean[2 * q + 1];
     for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-        const double2 w = buf[slot(idx)];
+        const V2 w = buf[slot(idx)];
         const size_t i = chan_index(row0, idx, logN, 2 * q, na);
         st[i] = static_cast<T>(m0 + w.x);
         st[i + N] = static_cast<T>(m1 + w.y);
@@ -178,7 +192,7 @@ __global__ __launch_bounds__(256) void prop_transfer(PropModeArgs a) {
 // mode is read and written once (the planes i2 = 0 and N/2, which are their
 // own mirrors, twice with the same values).  A thread issues the matrix's
 // and all its pairs' loads before the first use.
-template <int NF>
+template <int NF, typename V2>
 __global__ __launch_bounds__(256) void prop_modes(PropModeArgs a) {
     constexpr int NC = 2 * NF;
     const int N = a.N;
@@ -207,14 +221,14 @@ __global__ __launch_bounds__(256) void prop_modes(PropModeArgs a) {
         k[p] = (static_cast<size_t>(kx) * N + ky) * N + kz;
         m[p] = (static_cast<size_t>((N - kx) & (N - 1)) * N + ((N - ky) & (N - 1))) * N + ((N - kz) & (N - 1));
     }
-    double2 vk[4][NF], vm[4][NF];
+    V2 vk[4][NF], vm[4][NF];
 #pragma unroll
     for (int p = 0; p < 4; ++p)
         if (on[p])
 #pragma unroll
             for (int q = 0; q < NF; ++q) {
-                vk[p][q] = a.in[q][k[p]];
-                vm[p][q] = a.in[q][m[p]];
+                vk[p][q] = static_cast<const V2*>(a.in[q])[k[p]];
+                vm[p][q] = static_cast<const V2*>(a.in[q])[m[p]];
             }
     double Tm[NC * NC];
 #pragma unroll
@@ -228,9 +242,9 @@ __global__ __launch_bounds__(256) void prop_modes(PropModeArgs a) {
         double2 ch[NC];
 #pragma unroll
         for (int q = 0; q < NF; ++q) {
-            const double2 u = vk[p][q], r = vm[p][q];
-            ch[2 * q] = make_double2(0.5 * (u.x + r.x), 0.5 * (u.y - r.y));
-            ch[2 * q + 1] = make_double2(0.5 * (u.y + r.y), -0.5 * (u.x - r.x));
+            const double ux = vk[p][q].x, uy = vk[p][q].y, rx = vm[p][q].x, ry = vm[p][q].y;
+            ch[2 * q] = make_double2(0.5 * (ux + rx), 0.5 * (uy - ry));
+            ch[2 * q + 1] = make_double2(0.5 * (uy + ry), -0.5 * (ux - rx));
         }
         double2 out[NC];
 #pragma unroll
@@ -247,35 +261,39 @@ __global__ __launch_bounds__(256) void prop_modes(PropModeArgs a) {
 #pragma unroll
         for (int q = 0; q < NF; ++q) {
             const double2 x = out[2 * q], y = out[2 * q + 1];
-            a.out[q][k[p]] = make_double2(a.scale * (x.x - y.y), a.scale * (x.y + y.x));
-            a.out[q][m[p]] = make_double2(a.scale * (x.x + y.y), a.scale * (y.x - x.y));
+            V2* o = static_cast<V2*>(a.out[q]);
+            o[k[p]] = make_v2<V2>(a.scale * (x.x - y.y), a.scale * (x.y + y.x));
+            o[m[p]] = make_v2<V2>(a.scale * (x.x + y.y), a.scale * (y.x - x.y));
         }
     }
 }
 
-template <typename T, int K>
+template <typename T, typename V2, int K>
 void launch_zk(bool inverse, const PropZArgs& a, dim3 grid, size_t lds, hipStream_t s) {
-    if (inverse) hipLaunchKernelGGL((prop_ifftz_unpack<T, K>), grid, dim3(256), lds, s, a);
-    else hipLaunchKernelGGL((prop_pack_fftz<T, K>), grid, dim3(256), lds, s, a);
+    if (inverse) hipLaunchKernelGGL((prop_ifftz_unpack<T, V2, K>), grid, dim3(256), lds, s, a);
+    else hipLaunchKernelGGL((prop_pack_fftz<T, V2, K>), grid, dim3(256), lds, s, a);
 }
 
 // K = L N / 256 exactly (L N a power of two), or 1 for L N <= 256
-template <typename T>
+template <typename T, typename V2>
 hipError_t launch_z(bool inverse, const PropZArgs& a, hipStream_t s) {
     const int total = a.L * a.N;
     const dim3 grid(static_cast<unsigned>(a.N) * a.N / a.L, a.nf);
-    const size_t lds = fft_lds_bytes(a.N, a.L);
+    const size_t lds = fft_lds_bytes(a.N, a.L, sizeof(V2));
     switch (total) {
-        case 2048: launch_zk<T, 8>(inverse, a, grid, lds, s); break;
-        case 1024: launch_zk<T, 4>(inverse, a, grid, lds, s); break;
-        case 512: launch_zk<T, 2>(inverse, a, grid, lds, s); break;
-        default: launch_zk<T, 1>(inverse, a, grid, lds, s); break;
+        case 2048: launch_zk<T, V2, 8>(inverse, a, grid, lds, s); break;
+        case 1024: launch_zk<T, V2, 4>(inverse, a, grid, lds, s); break;
+        case 512: launch_zk<T, V2, 2>(inverse, a, grid, lds, s); break;
+        default: launch_zk<T, V2, 1>(inverse, a, grid, lds, s); break;
     }
     return hipGetLastError();
 }
 
-// Completes the z-pass shape (log2 N, rows per workgroup) and checks it:
-// N a power of two <= 1024, L N <= 2048 elements (K <= 8 per thread).
+// Completes the z-pass shape (log2 N, rows per workgroup) and checks it: N a
+// power of two <= 1024, L N <= 2048 elements (K <= 8 per thread).  z lines
+// are contiguous, so both precisions take 2048-element batches (for float2
+// half the LDS of the axis passes' batches, more workgroups per CU: measured
+// faster than 4096 at 256^3).
 bool z_shape(PropZArgs& a) {
     if (a.N < 2 || a.N > 1024 || (a.N & (a.N - 1)) != 0 || (a.nf != 1 && a.nf != 2)) return false;
     a.logN = 0;
@@ -289,13 +307,13 @@ bool z_shape(PropZArgs& a) {
 hipError_t launch_prop_pack_fftz(const PropZArgs& args, bool fp32, hipStream_t s) {
     PropZArgs a = args;
     if (!z_shape(a)) return hipErrorInvalidValue;
-    return fp32 ? launch_z<float>(false, a, s) : launch_z<double>(false, a, s);
+    return fp32 ? launch_z<float, float2>(false, a, s) : launch_z<double, double2>(false, a, s);
 }
 
 hipError_t launch_prop_ifftz_unpack(const PropZArgs& args, bool fp32, hipStream_t s) {
     PropZArgs a = args;
     if (!z_shape(a)) return hipErrorInvalidValue;
-    return fp32 ? launch_z<float>(true, a, s) : launch_z<double>(true, a, s);
+    return fp32 ? launch_z<float, float2>(true, a, s) : launch_z<double, double2>(true, a, s);
 }
 
 size_t prop_table_entries(int N) {
@@ -313,17 +331,19 @@ std::vector<uint32_t> prop_triples(int N) {
     return out;
 }
 
-hipError_t launch_prop_modes(const PropModeArgs& a, hipStream_t s) {
+hipError_t launch_prop_modes(const PropModeArgs& a, bool fp32, hipStream_t s) {
     if (a.nf != 1 && a.nf != 2) return hipErrorInvalidValue;
     const unsigned tgrid = static_cast<unsigned>((a.ntriples + 255) / 256);
     const size_t M = a.N / 2 + 1;
     const unsigned mgrid = static_cast<unsigned>((M * M * M + 255) / 256);
     if (a.nf == 1) {
         hipLaunchKernelGGL(prop_transfer<1>, dim3(tgrid), dim3(256), 0, s, a);
-        hipLaunchKernelGGL(prop_modes<1>, dim3(mgrid), dim3(256), 0, s, a);
+        if (fp32) hipLaunchKernelGGL((prop_modes<1, float2>), dim3(mgrid), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((prop_modes<1, double2>), dim3(mgrid), dim3(256), 0, s, a);
     } else {
         hipLaunchKernelGGL(prop_transfer<2>, dim3(tgrid), dim3(256), 0, s, a);
-        hipLaunchKernelGGL(prop_modes<2>, dim3(mgrid), dim3(256), 0, s, a);
+        if (fp32) hipLaunchKernelGGL((prop_modes<2, float2>), dim3(mgrid), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((prop_modes<2, double2>), dim3(mgrid), dim3(256), 0, s, a);
     }
     return hipGetLastError();
 }

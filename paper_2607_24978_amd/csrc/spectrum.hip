@@ -18,9 +18,10 @@
 
 namespace cl {
 
-struct SpecFftArgs {
-    double2* data;       // N^3 complex, site (x N + y) N + z
-    const double2* tw;   // exp(-2 pi i k / N), k < N / 2
+template <typename V2>
+struct FftArgs {
+    V2* data;            // N^3 complex, site (x N + y) N + z
+    const V2* tw;        // exp(-2 pi i k / N), k < N / 2
     int N, logN, L, logL, axis;  // axis 0: z, 1: y, 2: x (N, L powers of two)
     int inverse;         // 1: exp(+2 pi i k / N) (conjugate twiddles), no scaling
 };
@@ -28,7 +29,8 @@ struct SpecFftArgs {
 // Global index of element e of line l of batch b: for the y and x axes the
 // batch fixes the outer coordinate and the first z of its L lines
 // (`outer`, `z0`, formed once per workgroup).
-__device__ __forceinline__ size_t line_elem(const SpecFftArgs& a, int b, size_t outer, size_t z0, int l, int e) {
+template <typename V2>
+__device__ __forceinline__ size_t line_elem(const FftArgs<V2>& a, int b, size_t outer, size_t z0, int l, int e) {
     const size_t N = a.N;
     if (a.axis == 0) return (static_cast<size_t>(b) * a.L + l) * N + e;
     const size_t z = z0 + l;
@@ -38,7 +40,8 @@ __device__ __forceinline__ size_t line_elem(const SpecFftArgs& a, int b, size_t 
 
 // Element idx of a batch -> (line l, element e): the z axis takes whole
 // lines in turn, the y and x axes the L lines' element e side by side.
-__device__ __forceinline__ void line_split(const SpecFftArgs& a, int idx, int& l, int& e) {
+template <typename V2>
+__device__ __forceinline__ void line_split(const FftArgs<V2>& a, int idx, int& l, int& e) {
     if (a.axis == 0) {
         l = idx >> a.logN;
         e = idx & (a.N - 1);
@@ -50,9 +53,9 @@ __device__ __forceinline__ void line_split(const SpecFftArgs& a, int idx, int& l
 
 // A batch of K * 256 elements into LDS, bit-reversed along each line: every
 // global load of a thread first, then its LDS stores.
-template <int K>
-__device__ __forceinline__ void load_lines(const SpecFftArgs& a, int b, size_t outer, size_t z0, double2* buf) {
-    double2 v[K];
+template <int K, typename V2>
+__device__ __forceinline__ void load_lines(const FftArgs<V2>& a, int b, size_t outer, size_t z0, V2* buf) {
+    V2 v[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         int l, e;
@@ -68,8 +71,10 @@ __device__ __forceinline__ void load_lines(const SpecFftArgs& a, int b, size_t o
     }
 }
 
-__global__ __launch_bounds__(256) void fft_lines(SpecFftArgs a) {
-    extern __shared__ double2 buf[];  // [L][N] plus one pad slot per 16 (slot())
+template <typename V2>
+__global__ __launch_bounds__(256) void fft_lines(FftArgs<V2> a) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    V2* buf = reinterpret_cast<V2*>(lds_raw);  // [L][N] plus one pad slot per 16 (slot())
     const int N = a.N, L = a.L, b = blockIdx.x;
     const int logN = a.logN, logL = a.logL;
     const int total = L * N;
@@ -235,22 +240,33 @@ hipError_t launch_gw_bin(const double2* U, int N, double width, int nbins, doubl
     return hipGetLastError();
 }
 
-hipError_t launch_spec_fft(double2* data, const double2* tw, int N, int axis, hipStream_t s, bool inverse) {
-    SpecFftArgs a;
+namespace {
+template <typename V2>
+hipError_t launch_fft(V2* data, const V2* tw, int N, int L, int axis, hipStream_t s, bool inverse) {
+    FftArgs<V2> a;
     a.inverse = inverse ? 1 : 0;
     a.data = data;
     a.tw = tw;
     a.N = N;
     a.logN = 0;
     while ((1 << a.logN) < N) ++a.logN;
-    a.L = fft_lines_per_block(N);
+    a.L = L;
     a.logL = 0;
     while ((1 << a.logL) < a.L) ++a.logL;
     a.axis = axis;
     const int batches = N * N / a.L;
-    const size_t lds = fft_lds_bytes(N, a.L);
-    hipLaunchKernelGGL(fft_lines, dim3(batches), dim3(256), lds, s, a);
+    const size_t lds = fft_lds_bytes(N, a.L, sizeof(V2));
+    hipLaunchKernelGGL(fft_lines<V2>, dim3(batches), dim3(256), lds, s, a);
     return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_spec_fft(double2* data, const double2* tw, int N, int axis, hipStream_t s, bool inverse) {
+    return launch_fft(data, tw, N, fft_lines_per_block(N), axis, s, inverse);
+}
+
+hipError_t launch_fft_f32(float2* data, const float2* tw, int N, int axis, hipStream_t s, bool inverse) {
+    return launch_fft(data, tw, N, fft_lines_per_block_f32(N), axis, s, inverse);
 }
 
 hipError_t launch_spec_extract(const void* state, bool fp32, int N, int nf, int arr, double2* out, hipStream_t s) {

@@ -91,16 +91,24 @@ struct cl_surrogate {
     double fluct_tol = 0.25;
     // jump: network increment or linear propagation of the fluctuations
     cl_jump_mode jump_mode = CL_JUMP_NETWORK;
-    int propN = 0;                              // lattice size and spacing of the buffers below
+    int propN = 0;                              // lattice size, spacing and precision of the buffers below
     double propdx = 0.0;
-    double2* pz[2] = {nullptr, nullptr};        // packed fluctuations, forward transforms
-    double2* pw[2] = {nullptr, nullptr};        // propagated modes, inverse transforms
+    bool propfp32 = false;
+    void* pz[2] = {nullptr, nullptr};           // packed fluctuations, forward transforms (double2 or float2)
+    void* pw[2] = {nullptr, nullptr};           // propagated modes, inverse transforms
+    float2* tw32 = nullptr;                     // FP32 twiddle factors (N / 2) for FP32 lattices
     double* kap2 = nullptr;                     // [N] lattice Laplacian eigenvalue per index
     double* ptable = nullptr;                   // transfer matrices per distinct kappa^2
     uint32_t* ptriples = nullptr;               // the sorted index triples of the table
     cl::PropStep* psteps = nullptr;             // sub-step coefficients of one jump
     cl::PropStep* psteps_host = nullptr;        // their pinned host staging copy
     int psteps_cap = 0;
+    // pinned host landing place of a jump's reduction (both copies issued
+    // back to back, one wait)
+    struct JumpObs {
+        cl_observables o;
+        cl::Scal sc;
+    }* jump_obs = nullptr;
 };
 
 namespace {
@@ -597,11 +605,11 @@ cl_status cl_surrogate_destroy(cl_surrogate* s) {
         if (ly.bias) hipFree(ly.bias);
     }
     for (void* p : {(void*)s->theta, (void*)s->grad, (void*)s->m, (void*)s->v, (void*)s->ds_fluct,
-                    (void*)s->ds_incr, (void*)s->pz[0], (void*)s->pz[1], (void*)s->pw[0],
-                    (void*)s->pw[1], (void*)s->kap2, (void*)s->ptable, (void*)s->ptriples,
-                    (void*)s->psteps})
+                    (void*)s->ds_incr, s->pz[0], s->pz[1], s->pw[0], s->pw[1], (void*)s->tw32,
+                    (void*)s->kap2, (void*)s->ptable, (void*)s->ptriples, (void*)s->psteps})
         if (p) hipFree(p);
     if (s->psteps_host) hipHostFree(s->psteps_host);
+    if (s->jump_obs) hipHostFree(s->jump_obs);
     if (s->stream) hipStreamDestroy(s->stream);
     delete s;
     return CL_OK;
@@ -989,16 +997,28 @@ namespace {
 // Buffers of the linear propagation for an N^3 lattice of nf fields: nf
 // packed complex arrays in and out, the Laplacian eigenvalues per index, the
 // sub-step table.
+// One axis pass of the line FFT over array q of the forward (pz) or
+// propagated (pw) set, in the lattice's precision.
+hipError_t prop_fft(cl_surrogate* s, int q, bool forward_set, const double2* tw64, int N, int axis, bool fp32,
+                    bool inverse, hipStream_t st) {
+    void* d = forward_set ? s->pz[q] : s->pw[q];
+    if (fp32) return cl::launch_fft_f32(static_cast<float2*>(d), s->tw32, N, axis, st, inverse);
+    return cl::launch_spec_fft(static_cast<double2*>(d), tw64, N, axis, st, inverse);
+}
+
 cl_status ensure_prop_bufs(cl_surrogate* s, const cl_lattice* h, int nsteps) {
     const int N = h->N;
     // the table's index triples are packed 10 bits per index
     if (N > 1024) return sfail(CL_EUNSUPPORTED, "the linear jump supports N <= 1024");
     const size_t n3 = static_cast<size_t>(N) * N * N;
-    if (s->propN != N || s->propdx != h->dx) {
-        for (double2** p : {&s->pz[0], &s->pz[1], &s->pw[0], &s->pw[1]}) {
+    const bool fp32 = h->prec == CL_FP32;
+    if (s->propN != N || s->propdx != h->dx || s->propfp32 != fp32) {
+        for (void** p : {&s->pz[0], &s->pz[1], &s->pw[0], &s->pw[1]}) {
             if (*p) hipFree(*p);
             *p = nullptr;
         }
+        if (s->tw32) hipFree(s->tw32);
+        s->tw32 = nullptr;
         if (s->kap2) hipFree(s->kap2);
         if (s->ptable) hipFree(s->ptable);
         if (s->ptriples) hipFree(s->ptriples);
@@ -1008,8 +1028,13 @@ cl_status ensure_prop_bufs(cl_surrogate* s, const cl_lattice* h, int nsteps) {
         s->propN = 0;
         s->propdx = 0.0;
         for (int q = 0; q < h->nf; ++q) {
-            s->pz[q] = dalloc<double2>(n3);
-            s->pw[q] = dalloc<double2>(n3);
+            if (fp32) {
+                s->pz[q] = dalloc<float2>(n3);
+                s->pw[q] = dalloc<float2>(n3);
+            } else {
+                s->pz[q] = dalloc<double2>(n3);
+                s->pw[q] = dalloc<double2>(n3);
+            }
             if (!s->pz[q] || !s->pw[q]) return sfail(CL_ENOMEM, "propagator buffers");
         }
         s->kap2 = dalloc<double>(N);
@@ -1025,8 +1050,20 @@ cl_status ensure_prop_bufs(cl_surrogate* s, const cl_lattice* h, int nsteps) {
             k2[n] = 4.0 / (h->dx * h->dx) * sn * sn;
         }
         SHIP(hipMemcpy(s->kap2, k2.data(), N * sizeof(double), hipMemcpyHostToDevice));
+        if (fp32) {
+            // exp(-2 pi i k / N) formed in long double, rounded once to FP32
+            std::vector<float2> tw(std::max(N / 2, 1));
+            for (int k = 0; k < N / 2; ++k) {
+                const long double t = -2.0L * pi * k / N;
+                tw[k] = make_float2(static_cast<float>(std::cos(t)), static_cast<float>(std::sin(t)));
+            }
+            s->tw32 = dalloc<float2>(tw.size());
+            if (!s->tw32) return sfail(CL_ENOMEM, "propagator buffers");
+            SHIP(hipMemcpy(s->tw32, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice));
+        }
         s->propN = N;
         s->propdx = h->dx;
+        s->propfp32 = fp32;
     }
     if (s->psteps_cap < nsteps) {
         if (s->psteps) hipFree(s->psteps);
@@ -1092,6 +1129,13 @@ cl_status cl_surrogate_advance(cl_lattice* h, cl_surrogate* s, cl_integrator fal
     } ev_guard{ev};
     const double al = h->alpha, mp2 = h->mp * h->mp;
     const bool fp32 = h->prec == CL_FP32;
+    // twiddles of the fused z passes, in the lattice's precision
+    const void* const twz = fp32 ? static_cast<const void*>(s->tw32) : static_cast<const void*>(tw);
+    if (!s->jump_obs &&
+        hipHostMalloc(reinterpret_cast<void**>(&s->jump_obs), sizeof(cl_surrogate::JumpObs)) != hipSuccess) {
+        s->jump_obs = nullptr;
+        return sfail(CL_ENOMEM, "pinned host staging of the jump observables");
+    }
     for (int j = 0; j < n_jumps; ++j) {
         // the jump writes the other state buffer; the current one is the
         // snapshot until the jump is kept
@@ -1131,7 +1175,7 @@ cl_status cl_surrogate_advance(cl_lattice* h, cl_surrogate* s, cl_integrator fal
             pk.state = src;
             pk.N = N;
             pk.nf = h->nf;
-            pk.tw = tw;
+            pk.tw = twz;
             for (int jf = 0; jf < h->nf; ++jf) {
                 pk.mean[jf] = o.mean[jf];
                 pk.mean[h->nf + jf] = sc.mean_p[jf];
@@ -1139,7 +1183,7 @@ cl_status cl_surrogate_advance(cl_lattice* h, cl_surrogate* s, cl_integrator fal
             for (int q = 0; q < h->nf; ++q) pk.z[q] = s->pz[q];
             SHIP(cl::launch_prop_pack_fftz(pk, fp32, h->stream));
             for (int q = 0; q < h->nf; ++q)
-                for (int axis = 1; axis < 3; ++axis) SHIP(cl::launch_spec_fft(s->pz[q], tw, N, axis, h->stream));
+                for (int axis = 1; axis < 3; ++axis) SHIP(prop_fft(s, q, true, tw, N, axis, fp32, false, h->stream));
         }
         // predictor: homogeneous modes and background over the jump, in FP64
         double f[2] = {o.mean[0], o.mean[1]}, pm[2] = {sc.mean_p[0], sc.mean_p[1]}, var[2] = {o.var[0], o.var[1]};
@@ -1173,14 +1217,14 @@ cl_status cl_surrogate_advance(cl_lattice* h, cl_surrogate* s, cl_integrator fal
             pmd.table = s->ptable;
             pmd.triples = s->ptriples;
             pmd.ntriples = cl::prop_table_entries(N);
-            SHIP(cl::launch_prop_modes(pmd, h->stream));
+            SHIP(cl::launch_prop_modes(pmd, fp32, h->stream));
             for (int q = 0; q < h->nf; ++q)
-                for (int axis = 2; axis >= 1; --axis) SHIP(cl::launch_spec_fft(s->pw[q], tw, N, axis, h->stream, true));
+                for (int axis = 2; axis >= 1; --axis) SHIP(prop_fft(s, q, false, tw, N, axis, fp32, true, h->stream));
             cl::PropZArgs pu{};
             pu.out = dst;
             pu.N = N;
             pu.nf = h->nf;
-            pu.tw = tw;
+            pu.tw = twz;
             for (int jf = 0; jf < h->nf; ++jf) {
                 pu.mean[jf] = f[jf];
                 pu.mean[h->nf + jf] = pm[jf];
@@ -1219,8 +1263,10 @@ cl_status cl_surrogate_advance(cl_lattice* h, cl_surrogate* s, cl_integrator fal
             h->cur = cur0 ^ 1;
             st = cl::set_background_async(h, a_pred, b, eta1, step1, f);
             if (st) return sfail(st, cl_last_error(h));
-            st = cl::observe_once(h, &after, &sca);
+            st = cl::observe_once(h, &s->jump_obs->o, &s->jump_obs->sc);
             if (st) return sfail(st, cl_last_error(h));
+            after = s->jump_obs->o;
+            sca = s->jump_obs->sc;
             ok = !after.nonfinite;
         } else {
             SHIP(hipStreamSynchronize(h->stream));

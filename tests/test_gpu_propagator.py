@@ -141,3 +141,110 @@ def test_linear_jump_fp32_state_and_gates():
     print(f"linear jumps vs FP64 VV4 after 64 steps: fluctuation-relative deviation {dev:.3g}", flush=True)
     assert dev < 5e-2
     ref.close()
+
+
+def test_one_handle_two_spacings():
+    """One surrogate handle advancing two lattices of the same N but
+    different spacing: the mode table follows each lattice's dx (both equal
+    their integrator for free fields on a static background)."""
+    lib = _lib()
+    sg = lib.Surrogate(n_fields=2, extra_inputs=2, layers=2, jump_steps=16, init_seed=1)
+    sg.set_jump("linear")
+    sg.set_gate(0.0)
+    for dx in (0.4, 0.9):
+        P, s0, lat = _free_static()
+        lat.close()
+        lat = lib.Lattice(32, dx, 2, "fp64")
+        ref = lib.Lattice(32, dx, 2, "fp64")
+        for h in (lat, ref):
+            h.set_background(1.0, "static", 1.0, 1.0)
+            h.set_potential(P.m2, P.lam, P.g2, 0.0)
+            h.set_fields(s0.f, s0.p)
+        recs, rep = sg.advance(lat, "vv4", 0.05, 1, threshold=float("inf"))
+        assert rep["fallbacks"] == 0
+        ref.step("vv4", 0.05, 16, record=False)
+        f, p = lat.get_fields()
+        fr, pr = ref.get_fields()
+        err = max(np.max(np.abs(f - fr)) / np.max(np.abs(fr)), np.max(np.abs(p - pr)) / np.max(np.abs(pr)))
+        print(f"dx {dx}: relative deviation from the integrator {err:.3g}", flush=True)
+        assert err <= 1e-11
+        lat.close()
+        ref.close()
+    sg.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_rejected_linear_jumps_are_the_integrator(precision):
+    """Every jump rejected (threshold 0): the jump's result went to the other
+    state buffer and is dropped, so the lattice ends bitwise where the
+    integrator alone takes it, with the same background."""
+    lib = _lib()
+    w = W.C1.with_(N=32, k_ir=1.0, precision=precision)
+    from oracle import lattice as L
+    from oracle import seed as S
+    P = L.Params(N=32, dx=w.dx, n_fields=2, m2=w.m2, lam=w.lam, g2=w.g2, V0=w.V0)
+    s0 = S.seed_state(P, w.k_ir, w.fbar[:2], w.pbar[:2], w.seed, amp=1.0)
+    hs = []
+    for _ in range(2):
+        h = lib.Lattice(32, w.dx, 2, precision)
+        h.set_potential(w.m2, w.lam, w.g2, w.V0)
+        h.set_fields(s0.f, s0.p)
+        hs.append(h)
+    lat, ref = hs
+    sg = lib.Surrogate(n_fields=2, extra_inputs=2, layers=2, jump_steps=16, init_seed=1)
+    sg.set_jump("linear")
+    recs, rep = sg.advance(lat, "vv4", w.dt, 3, threshold=0.0)
+    assert rep["fallbacks"] == 3
+    for _ in range(3):
+        ref.step("vv4", w.dt, 16, record=False)
+    f, p = lat.get_fields()
+    fr, pr = ref.get_fields()
+    assert np.array_equal(f, fr) and np.array_equal(p, pr)
+    assert lat.get_state() == ref.get_state()
+    for h in (lat, ref, sg):
+        h.close()
+
+
+def test_linear_jump_fp32_against_oracle():
+    """FP32 lattice (the fluctuations then go through the FP32 line FFT) on
+    the interacting two-field model, one accepted jump (threshold = inf,
+    second gate off), against the oracle's FP64 jump from the same
+    FP32-rounded state.  Error budget per element: the rounding of the result
+    to FP32 (half an ulp of the field value, allowed 4 eps32 |f|) plus the
+    FP32 transforms, packing and unpacking of the fluctuations (a few eps32
+    per radix-2 stage, 2 log2(N^3) stages; allowed 64 eps32 max|fluct|)."""
+    from oracle import lattice as L
+    from oracle import propagator as PR
+    from oracle import seed as S
+    lib = _lib()
+    N = 32
+    w = W.C1.with_(N=N, k_ir=1.0, precision="fp32")
+    P = L.Params(N=N, dx=w.dx, n_fields=2, m2=w.m2, lam=w.lam, g2=w.g2, V0=w.V0)
+    s0 = S.seed_state(P, w.k_ir, w.fbar[:2], w.pbar[:2], w.seed, amp=20.0)
+    f32 = s0.f.astype(np.float32).astype(np.float64)
+    p32 = s0.p.astype(np.float32).astype(np.float64)
+    rho, _ = L.rho_pressure(*L.energies(f32, p32, s0.a, P))
+    sr = L.State(f32, p32, s0.a, L.hubble_from_rho(s0.a, rho, P))
+    lat = lib.Lattice(N, w.dx, 2, "fp32")
+    lat.set_potential(w.m2, w.lam, w.g2, w.V0)
+    lat.set_fields(f32, p32)
+    sg = lib.Surrogate(n_fields=2, extra_inputs=2, layers=2, jump_steps=16, init_seed=1)
+    sg.set_jump("linear")
+    sg.set_gate(0.0)
+    recs, rep = sg.advance(lat, "vv4", w.dt, 1, threshold=float("inf"))
+    assert rep["fallbacks"] == 0
+    f, p = lat.get_fields()
+    s, r = PR.linear_jump(sr, w.dt, 16, "vv4", P)
+    st = lat.get_state()
+    eps = float(np.finfo(np.float32).eps)
+    for got, want in ((f, s.f), (p, s.p)):
+        fl = want - want.mean(axis=(1, 2, 3), keepdims=True)
+        tol = 4 * eps * np.max(np.abs(want)) + 64 * eps * np.max(np.abs(fl))
+        err = np.max(np.abs(got - want))
+        print(f"max deviation {err:.3g}, allowed {tol:.3g} (fluctuation scale {np.max(np.abs(fl)):.3g})", flush=True)
+        assert err <= tol
+    print(f"a {st['a']:.10g} vs {s.a:.10g}; r {recs['r'][0]:.6g} vs {r:.6g}", flush=True)
+    assert abs(st["a"] - s.a) <= 1e-6 * s.a
+    assert abs(recs["r"][0] - r) <= 1e-5
+    lat.close()
+    sg.close()
