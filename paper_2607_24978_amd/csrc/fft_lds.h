@@ -19,9 +19,10 @@ __host__ __device__ inline int fft_lines_per_block(int N) { return N <= 32 ? N :
 __host__ __device__ inline int fft_lines_per_block_f32(int N) { return N <= 64 ? N : (N <= 4096 ? 4096 / N : 1); }
 
 // LDS bytes of a batch of L lines of N values of `vbytes` bytes each, with
-// the pad slots of slot().
+// the pad slots of slot(), followed by the N / 2 twiddle factors.
+__host__ __device__ inline size_t fft_lds_values(int N, int L) { return static_cast<size_t>(L) * N * 17 / 16; }
 inline size_t fft_lds_bytes(int N, int L, size_t vbytes = sizeof(double2)) {
-    return static_cast<size_t>(L) * N * 17 / 16 * vbytes;
+    return (fft_lds_values(N, L) + (N / 2 > 0 ? N / 2 : 1)) * vbytes;
 }
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
@@ -79,6 +80,16 @@ __device__ __forceinline__ void fft_pass(V2* buf, const V2* __restrict__ tw, int
 #pragma unroll
         for (int j = 0; j < R; ++j) buf[slot(base + j * m)] = x[j];
     }
+}
+
+// Copies the N / 2 twiddle factors behind the batch in LDS (every thread of
+// the block takes part; they are read after the caller's barrier that
+// follows the batch's stores) and returns their LDS address.
+template <typename V2>
+__device__ __forceinline__ const V2* stage_twiddles(V2* buf, const V2* __restrict__ tw, int N, int L) {
+    V2* t = buf + fft_lds_values(N, L);
+    for (int i = threadIdx.x; i < N / 2; i += blockDim.x) t[i] = tw[i];
+    return t;
 }
 
 // Every stage of the transform of the L bit-reversed lines in LDS, up to

@@ -83,8 +83,9 @@ __global__ __launch_bounds__(256) void prop_pack_fftz(PropZArgs a) {
                 make_v2<V2>(static_cast<double>(re[k]) - m0, static_cast<double>(im[k]) - m1);
         }
     }
+    const V2* tws = stage_twiddles(buf, static_cast<const V2*>(a.tw), N, L);
     __syncthreads();
-    fft_lds_stages(buf, static_cast<const V2*>(a.tw), logN, L, false);
+    fft_lds_stages(buf, tws, logN, L, false);
     V2* out = static_cast<V2*>(a.z[q]) + row0 * N;
     for (int idx = threadIdx.x; idx < total; idx += blockDim.x) out[idx] = buf[slot(idx)];
 }
@@ -110,8 +111,9 @@ __global__ __launch_bounds__(256) void prop_ifftz_unpack(PropZArgs a) {
         const int idx = static_cast<int>(threadIdx.x) + k * 256;
         if (K > 1 || idx < total) buf[slot((idx >> logN) * N + bitrev(idx & (N - 1), logN))] = v[k];
     }
+    const V2* tws = stage_twiddles(buf, static_cast<const V2*>(a.tw), N, L);
     __syncthreads();
-    fft_lds_stages(buf, static_cast<const V2*>(a.tw), logN, L, true);
+    fft_lds_stages(buf, tws, logN, L, true);
     T* st = static_cast<T*>(a.out);
     const double m0 = a.mean[2 * q], m1 = a.mean[2 * q + 1];
     for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {

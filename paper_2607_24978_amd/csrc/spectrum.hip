@@ -94,9 +94,10 @@ __global__ __launch_bounds__(256) void fft_lines(FftArgs<V2> a) {
             const int r = bitrev(e, logN);
             buf[slot(l * N + r)] = a.data[line_elem(a, b, outer, z0, l, e)];
         }
+    const V2* tws = stage_twiddles(buf, a.tw, N, L);
     __syncthreads();
     // the log2 N butterfly stages, up to three per pass over LDS
-    fft_lds_stages(buf, a.tw, logN, L, a.inverse != 0);
+    fft_lds_stages(buf, tws, logN, L, a.inverse != 0);
     for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
         int l, e;
         if (a.axis == 0) {
