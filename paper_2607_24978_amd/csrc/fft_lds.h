@@ -93,13 +93,15 @@ __device__ __forceinline__ const V2* stage_twiddles(V2* buf, const V2* __restric
 }
 
 // Every stage of the transform of the L bit-reversed lines in LDS, up to
-// three per pass, a barrier after each pass (the caller has placed one after
-// its stores).  The result is in natural order.
-template <typename V2>
+// SMAX per pass (3: radix-8 passes; 4: radix-16, fewer LDS sweeps for more
+// registers), a barrier after each pass (the caller has placed one after its
+// stores).  The result is in natural order.
+template <int SMAX = 3, typename V2>
 __device__ __forceinline__ void fft_lds_stages(V2* buf, const V2* __restrict__ tw, int logN, int L, bool inverse) {
     for (int lm = 0; lm < logN;) {
-        const int s = logN - lm >= 3 ? 3 : logN - lm;
-        if (s == 3) fft_pass<3>(buf, tw, logN, L, lm, inverse);
+        const int s = logN - lm >= SMAX ? SMAX : logN - lm;
+        if (SMAX >= 4 && s == 4) fft_pass<(SMAX >= 4 ? 4 : 3)>(buf, tw, logN, L, lm, inverse);
+        else if (s == 3) fft_pass<3>(buf, tw, logN, L, lm, inverse);
         else if (s == 2) fft_pass<2>(buf, tw, logN, L, lm, inverse);
         else fft_pass<1>(buf, tw, logN, L, lm, inverse);
         __syncthreads();

@@ -97,7 +97,8 @@ __global__ __launch_bounds__(256) void fft_lines(FftArgs<V2> a) {
     const V2* tws = stage_twiddles(buf, a.tw, N, L);
     __syncthreads();
     // the log2 N butterfly stages, up to three per pass over LDS
-    fft_lds_stages(buf, tws, logN, L, a.inverse != 0);
+    // FP32 values: radix-16 passes (two LDS sweeps at N = 256 instead of three)
+    fft_lds_stages<sizeof(V2) == 8 ? 4 : 3>(buf, tws, logN, L, a.inverse != 0);
     for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
         int l, e;
         if (a.axis == 0) {
