@@ -248,3 +248,51 @@ def test_linear_jump_fp32_against_oracle():
     assert abs(recs["r"][0] - r) <= 1e-5
     lat.close()
     sg.close()
+
+
+@pytest.mark.parametrize("N,precision", [(64, "fp32"), (128, "fp32"), (256, "fp32"), (256, "fp64")])
+def test_free_fields_at_size_equal_the_integrator(N, precision):
+    """The launch shapes the benchmark times (256^3: 2048-value fused z
+    batches, 16-line FP32 axis batches with radix-16 passes, 129^3 folded
+    index triples) and the sizes between: free fields of two masses on a
+    static background, where one linear jump of 16 VV4 steps equals the
+    integrator up to rounding, against the library's FP64 integrator.
+    Allowed: 1e-11 of the field scale in FP64; in FP32 the rounding of the
+    state (4 eps32 of the scale) plus the FP32 transforms (64 eps32 of the
+    fluctuations), plus the FP32 state's own rounding at the start."""
+    lib = _lib()
+    rng = np.random.default_rng(11)
+    m2 = (0.6, 2.3)
+    dx = 0.4
+    f = np.stack([0.9 + 0.3 * rng.standard_normal((N, N, N)), 0.05 + 0.3 * rng.standard_normal((N, N, N))])
+    p = np.stack([0.02 + 0.3 * rng.standard_normal((N, N, N)), -0.01 + 0.3 * rng.standard_normal((N, N, N))])
+    if precision == "fp32":
+        f = f.astype(np.float32).astype(np.float64)
+        p = p.astype(np.float32).astype(np.float64)
+    hs = []
+    for prec in (precision, "fp64"):
+        h = lib.Lattice(N, dx, 2, prec)
+        h.set_background(1.0, "static", 1.0, 1.0)
+        h.set_potential(m2, (0.0, 0.0), 0.0, 0.0)
+        h.set_fields(f, p)
+        hs.append(h)
+    lat, ref = hs
+    del f, p
+    sg = lib.Surrogate(n_fields=2, extra_inputs=2, layers=2, jump_steps=16, init_seed=1)
+    sg.set_jump("linear")
+    sg.set_gate(0.0)
+    _, rep = sg.advance(lat, "vv4", 0.05, 1, threshold=float("inf"))
+    assert rep["fallbacks"] == 0
+    ref.step("vv4", 0.05, 16, record=False)
+    got = lat.get_fields()
+    want = ref.get_fields()
+    eps = float(np.finfo(np.float32).eps)
+    for g, w in zip(got, want):
+        scale = float(np.max(np.abs(w)))
+        fl = float(np.max(np.abs(w - w.mean(axis=(1, 2, 3), keepdims=True))))
+        tol = 1e-11 * scale if precision == "fp64" else 4 * eps * scale + 64 * eps * fl
+        err = float(np.max(np.abs(g - w)))
+        print(f"N={N} {precision}: max deviation {err:.3g}, allowed {tol:.3g}", flush=True)
+        assert err <= tol
+    for h in (lat, ref, sg):
+        h.close()
