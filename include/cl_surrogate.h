@@ -145,8 +145,10 @@ cl_status cl_surrogate_save(const cl_surrogate* s, const char* path);
 cl_status cl_surrogate_load(cl_surrogate* s, const char* path);
 
 /* Advance the lattice by n_jumps applications of the network, each standing
- * for jump_steps steps of size dt.  One jump: snapshot the state; the network
- * predicts the fluctuation increment; the homogeneous modes and (a, a') are
+ * for jump_steps steps of size dt.  One jump: the new state is formed in the
+ * lattice's second state buffer (the current one is kept as the snapshot and
+ * becomes the other buffer if the jump is kept); the network predicts the
+ * fluctuation increment; the homogeneous modes and (a, a') are
  * advanced over the jump by the FP64 equations of motion of a uniform
  * lattice with the integrator's sub-step pattern (predictor: force and
  * potential averaged over Gaussian fluctuations of the start variances, the
