@@ -158,6 +158,7 @@ def batched_run(steps, warmup, solo_steps=100):
         lat.set_potential(w.m2, w.lam, w.g2, w.V0)
         lat.seed(w.seed, w.fbar[:1], w.pbar[:1], w.cutoff_modes, w.amp)
         lats.append(lat)
+    progress(f"ensemble: {len(lats)} members seeded")
     sites = sum(w.sites for w in ws)
     # solo: each member on its own stream-less handle, back to back
     torch.cuda.synchronize()
@@ -167,9 +168,11 @@ def batched_run(steps, warmup, solo_steps=100):
     for lat, w in zip(lats, ws):
         lat.step("leapfrog", w.dt, solo_steps)
     solo_s = time.perf_counter() - t0
+    progress(f"ensemble: members run one by one ({solo_s:.2f} s)")
     ens = _lib.Ensemble(lats)
     for i, w in enumerate(ws):
         ens.set_dt(i, w.dt)
+    progress("ensemble: created, searching the work layout")
     tune = ens.autotune(reps=3)  # the library's decomposition search (states unchanged)
     progress(f"ensemble layout {tune['best']}")
     chunk = min(steps, 500)
@@ -353,12 +356,15 @@ def surrogate_run(epochs=12, pairs_per_seed=64, train_seeds=range(2000, 2008), e
             lat.step("vv4", w.dt, K, record=False)
             s.record_target(lat)
         lat.close()
+        progress(f"surrogate: training pairs of seed {seed} recorded")
     torch.cuda.synchronize()
     out["pairs"] = s.dataset_size()
     out["datagen_s"] = time.perf_counter() - t0
+    progress(f"surrogate: training ({epochs} epochs)")
     rep = s.train(epochs=epochs, lr=5e-4, lr_final=5e-6, shuffle_seed=0, holdout=pairs_per_seed // 2)
     out["train"] = rep
     out["train_steps_per_s"] = rep["steps"] / rep["seconds"]
+    progress(f"surrogate: trained, held-out loss {rep['holdout_loss']:.4g}")
 
     def evaluate(N, k_ir, njumps):
         w = W.C1.with_(N=N, k_ir=k_ir, seed=eval_seed)
@@ -371,6 +377,7 @@ def surrogate_run(epochs=12, pairs_per_seed=64, train_seeds=range(2000, 2008), e
             return tuned(lat, N, prec)
 
         res = {"N": N, "k_ir": k_ir, "dx": w.dx, "jumps": njumps, "steps": njumps * K}
+        progress(f"surrogate: evaluation at {N}^3, k_IR = {k_ir}")
         # every form makes one untimed jump first (graph capture, buffers), then njumps timed ones
         ref = lattice("fp64")
         rr = np.concatenate([ref.step("vv4", w.dt, K)[-1:] for _ in range(njumps + 1)])[1:]
@@ -402,6 +409,7 @@ def surrogate_run(epochs=12, pairs_per_seed=64, train_seeds=range(2000, 2008), e
         sec = time.perf_counter() - t1
         errs = _scalar_errors(recs, rr, 2)
         flops = surrogate_flops_per_site(extra_inputs) * w.sites * njumps
+        progress("surrogate: surrogate form done")
         forms["surrogate"] = {"effective_site_updates_per_s": w.sites * njumps * K / sec, "seconds": sec,
                               "fallbacks": srep["fallbacks"], "fallback_rate": srep["fallbacks"] / max(1, njumps),
                               "accepted_fraction": 1.0 - srep["fallbacks"] / max(1, njumps),
@@ -423,6 +431,7 @@ def surrogate_run(epochs=12, pairs_per_seed=64, train_seeds=range(2000, 2008), e
         torch.cuda.synchronize()
         sec = time.perf_counter() - t1
         errs = _scalar_errors(recs, rr, 2)
+        progress("surrogate: linear jump form done")
         forms["linear_jump"] = {"effective_site_updates_per_s": w.sites * njumps * K / sec, "seconds": sec,
                                 "accepted_fraction": 1.0 - srep["fallbacks"] / max(1, njumps),
                                 "fluct_gate_rejects": srep["fluct_rejects"], "max_residual": srep["max_residual"],
@@ -443,6 +452,7 @@ def surrogate_run(epochs=12, pairs_per_seed=64, train_seeds=range(2000, 2008), e
         s.set_gate(0.25)
         s.set_jump("network")
         errs = _scalar_errors(recs, rr, 2)
+        progress("surrogate: linear jump hubble gate only form done")
         forms["linear_jump_hubble_gate_only"] = {"effective_site_updates_per_s": w.sites * njumps * K / sec,
                                                  "accepted_fraction": 1.0 - srep["fallbacks"] / max(1, njumps),
                                                  "max_residual": srep["max_residual"],
@@ -460,6 +470,7 @@ def surrogate_run(epochs=12, pairs_per_seed=64, train_seeds=range(2000, 2008), e
         sec = time.perf_counter() - t1
         s.set_gate(0.25)
         errs = _scalar_errors(recs, rr, 2)
+        progress("surrogate: surrogate hubble gate only form done")
         forms["surrogate_hubble_gate_only"] = {"effective_site_updates_per_s": w.sites * njumps * K / sec,
                                                "accepted_fraction": 1.0 - srep["fallbacks"] / max(1, njumps),
                                                "max_residual": srep["max_residual"],

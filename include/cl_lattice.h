@@ -321,9 +321,11 @@ cl_status cl_get_tile(const cl_lattice* h, cl_tile* out);
 cl_status cl_set_tile(cl_lattice* h, const cl_tile* t);
 
 /* Autotuner: times `reps` fused drift-kick passes of every candidate tile on
- * the current state (fields and background are left unchanged), selects the
- * fastest and writes a JSON report (NUL-terminated, truncated to
- * report_cap) if report is not NULL.  If the environment variable
+ * the current state (fields and background are left unchanged), then times
+ * the four fastest again in three interleaved rounds of at least 40 passes
+ * each, selects the finalist with the shortest round and writes a JSON
+ * report ("candidates": the screening, "finalists", "best"; NUL-terminated,
+ * truncated to report_cap) if report is not NULL.  If the environment variable
  * CL_TUNE_CACHE names a file, the result is appended there as one JSON line
  * and later cl_create calls for the same (N, n_fields, precision) start from
  * it. */
