@@ -18,9 +18,13 @@ __host__ __device__ inline int fft_lines_per_block(int N) { return N <= 32 ? N :
 // access of the y and x passes still moves 16 consecutive values (128 bytes).
 __host__ __device__ inline int fft_lines_per_block_f32(int N) { return N <= 64 ? N : (N <= 4096 ? 4096 / N : 1); }
 
+// LDS slots of one line of N values: one pad slot per 16 values and one more
+// per line (see slot()).
+__host__ __device__ inline int fft_line_slots(int N) { return N + (N >> 4) + 1; }
+
 // LDS bytes of a batch of L lines of N values of `vbytes` bytes each, with
 // the pad slots of slot(), followed by the N / 2 twiddle factors.
-__host__ __device__ inline size_t fft_lds_values(int N, int L) { return static_cast<size_t>(L) * N * 17 / 16; }
+__host__ __device__ inline size_t fft_lds_values(int N, int L) { return static_cast<size_t>(L) * fft_line_slots(N); }
 inline size_t fft_lds_bytes(int N, int L, size_t vbytes = sizeof(double2)) {
     return (fft_lds_values(N, L) + (N / 2 > 0 ? N / 2 : 1)) * vbytes;
 }
@@ -32,10 +36,13 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
     return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
 }
 
-// LDS slot of element i (= l N + e) of a batch: one pad slot after every 16
-// elements, so that the bit-reversed stores (positions 16 apart) and the
-// first pass's groups (8 apart) fall in different banks.
-__device__ __forceinline__ int slot(int i) { return i + (i >> 4); }
+// LDS slot of element e of line l of a batch: one pad slot after every 16
+// elements of a line, so that the bit-reversed stores (positions 16 apart)
+// and the radix passes' groups fall in different banks, and one more slot
+// per line, so that the y and x passes -- whose lanes store and read one
+// element of 16 different lines -- do not stride the lines on one bank (the
+// line stride is then odd in slots, 17 N / 16 + 1).
+__device__ __forceinline__ int slot(int l, int e, int N) { return l * fft_line_slots(N) + e + (e >> 4); }
 
 // Bit-reversed position of element e of a line of 2^logN values.
 __device__ __forceinline__ int bitrev(int e, int logN) {
@@ -58,10 +65,9 @@ __device__ __forceinline__ void fft_pass(V2* buf, const V2* __restrict__ tw, int
     for (int t = threadIdx.x; t < groups; t += blockDim.x) {
         const int l = t >> (logN - S), q = t & ((N >> S) - 1);
         const int pos = q & (m - 1), i0 = ((q >> lm) << (lm + S)) + pos;
-        const int base = l * N + i0;
         V2 x[R];
 #pragma unroll
-        for (int j = 0; j < R; ++j) x[j] = buf[slot(base + j * m)];
+        for (int j = 0; j < R; ++j) x[j] = buf[slot(l, i0 + j * m, N)];
 #pragma unroll
         for (int k = 0; k < S; ++k) {
             const int hk = 1 << k, sh = logN - 1 - lm - k;
@@ -78,7 +84,7 @@ __device__ __forceinline__ void fft_pass(V2* buf, const V2* __restrict__ tw, int
             }
         }
 #pragma unroll
-        for (int j = 0; j < R; ++j) buf[slot(base + j * m)] = x[j];
+        for (int j = 0; j < R; ++j) buf[slot(l, i0 + j * m, N)] = x[j];
     }
 }
 

@@ -79,7 +79,7 @@ __global__ __launch_bounds__(256) void prop_pack_fftz(PropZArgs a) {
         const int idx = static_cast<int>(threadIdx.x) + k * 256;
         if (K > 1 || idx < total) {
             const int l = idx >> logN, e = idx & (N - 1);
-            buf[slot(l * N + bitrev(e, logN))] =
+            buf[slot(l, bitrev(e, logN), N)] =
                 make_v2<V2>(static_cast<double>(re[k]) - m0, static_cast<double>(im[k]) - m1);
         }
     }
@@ -87,7 +87,7 @@ __global__ __launch_bounds__(256) void prop_pack_fftz(PropZArgs a) {
     __syncthreads();
     fft_lds_stages(buf, tws, logN, L, false);
     V2* out = static_cast<V2*>(a.z[q]) + row0 * N;
-    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) out[idx] = buf[slot(idx)];
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) out[idx] = buf[slot(idx >> logN, idx & (N - 1), N)];
 }
 
 // Rows of z[q] -> LDS bit-reversed, inverse z transform, then the means
@@ -109,7 +109,7 @@ __global__ __launch_bounds__(256) void prop_ifftz_unpack(PropZArgs a) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int idx = static_cast<int>(threadIdx.x) + k * 256;
-        if (K > 1 || idx < total) buf[slot((idx >> logN) * N + bitrev(idx & (N - 1), logN))] = v[k];
+        if (K > 1 || idx < total) buf[slot(idx >> logN, bitrev(idx & (N - 1), logN), N)] = v[k];
     }
     const V2* tws = stage_twiddles(buf, static_cast<const V2*>(a.tw), N, L);
     __syncthreads();
@@ -117,7 +117,7 @@ __global__ __launch_bounds__(256) void prop_ifftz_unpack(PropZArgs a) {
     T* st = static_cast<T*>(a.out);
     const double m0 = a.mean[2 * q], m1 = a.mean[2 * q + 1];
     for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-        const V2 w = buf[slot(idx)];
+        const V2 w = buf[slot(idx >> logN, idx & (N - 1), N)];
         const size_t i = chan_index(row0, idx, logN, 2 * q, na);
         st[i] = static_cast<T>(m0 + w.x);
         st[i + N] = static_cast<T>(m1 + w.y);

@@ -67,14 +67,14 @@ __device__ __forceinline__ void load_lines(const FftArgs<V2>& a, int b, size_t o
         int l, e;
         line_split(a, static_cast<int>(threadIdx.x) + k * 256, l, e);
         const int r = bitrev(e, a.logN);
-        buf[slot(l * a.N + r)] = v[k];
+        buf[slot(l, r, a.N)] = v[k];
     }
 }
 
 template <typename V2>
 __global__ __launch_bounds__(256) void fft_lines(FftArgs<V2> a) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    V2* buf = reinterpret_cast<V2*>(lds_raw);  // [L][N] plus one pad slot per 16 (slot())
+    V2* buf = reinterpret_cast<V2*>(lds_raw);  // [L][N] plus the pad slots of slot()
     const int N = a.N, L = a.L, b = blockIdx.x;
     const int logN = a.logN, logL = a.logL;
     const int total = L * N;
@@ -92,7 +92,7 @@ __global__ __launch_bounds__(256) void fft_lines(FftArgs<V2> a) {
             int l, e;
             line_split(a, idx, l, e);
             const int r = bitrev(e, logN);
-            buf[slot(l * N + r)] = a.data[line_elem(a, b, outer, z0, l, e)];
+            buf[slot(l, r, N)] = a.data[line_elem(a, b, outer, z0, l, e)];
         }
     const V2* tws = stage_twiddles(buf, a.tw, N, L);
     __syncthreads();
@@ -108,7 +108,7 @@ __global__ __launch_bounds__(256) void fft_lines(FftArgs<V2> a) {
             e = idx >> logL;
             l = idx & (L - 1);
         }
-        a.data[line_elem(a, b, outer, z0, l, e)] = buf[slot(l * N + e)];
+        a.data[line_elem(a, b, outer, z0, l, e)] = buf[slot(l, e, N)];
     }
 }
 
