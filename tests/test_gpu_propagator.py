@@ -205,11 +205,12 @@ def test_rejected_linear_jumps_are_the_integrator(precision):
         h.close()
 
 
-def test_linear_jump_fp32_against_oracle():
+@pytest.mark.parametrize("nf", [1, 2])
+def test_linear_jump_fp32_against_oracle(nf):
     """FP32 lattice (the fluctuations then go through the FP32 line FFT) on
-    the interacting two-field model, one accepted jump (threshold = inf,
-    second gate off), against the oracle's FP64 jump from the same
-    FP32-rounded state.  Error budget per element: the rounding of the result
+    the interacting model (one field: lambda phi^4 at 16^3; two fields: the
+    q = 100 model at 32^3), one accepted jump (threshold = inf, second gate
+    off), against the oracle's FP64 jump from the same FP32-rounded state.  Error budget per element: the rounding of the result
     to FP32 (half an ulp of the field value, allowed 4 eps32 |f|) plus the
     FP32 transforms, packing and unpacking of the fluctuations (a few eps32
     per radix-2 stage, 2 log2(N^3) stages; allowed 64 eps32 max|fluct|)."""
@@ -217,18 +218,20 @@ def test_linear_jump_fp32_against_oracle():
     from oracle import propagator as PR
     from oracle import seed as S
     lib = _lib()
-    N = 32
+    N = 32 if nf == 2 else 16
     w = W.C1.with_(N=N, k_ir=1.0, precision="fp32")
-    P = L.Params(N=N, dx=w.dx, n_fields=2, m2=w.m2, lam=w.lam, g2=w.g2, V0=w.V0)
-    s0 = S.seed_state(P, w.k_ir, w.fbar[:2], w.pbar[:2], w.seed, amp=20.0)
+    m2 = w.m2 if nf == 2 else (0.0, 0.0)
+    g2 = w.g2 if nf == 2 else 0.0
+    P = L.Params(N=N, dx=w.dx, n_fields=nf, m2=m2, lam=w.lam, g2=g2, V0=w.V0)
+    s0 = S.seed_state(P, w.k_ir, w.fbar[:nf], w.pbar[:nf], w.seed, amp=20.0)
     f32 = s0.f.astype(np.float32).astype(np.float64)
     p32 = s0.p.astype(np.float32).astype(np.float64)
     rho, _ = L.rho_pressure(*L.energies(f32, p32, s0.a, P))
     sr = L.State(f32, p32, s0.a, L.hubble_from_rho(s0.a, rho, P))
-    lat = lib.Lattice(N, w.dx, 2, "fp32")
-    lat.set_potential(w.m2, w.lam, w.g2, w.V0)
+    lat = lib.Lattice(N, w.dx, nf, "fp32")
+    lat.set_potential(m2, w.lam, g2, w.V0)
     lat.set_fields(f32, p32)
-    sg = lib.Surrogate(n_fields=2, extra_inputs=2, layers=2, jump_steps=16, init_seed=1)
+    sg = lib.Surrogate(n_fields=nf, extra_inputs=2, layers=2, jump_steps=16, init_seed=1)
     sg.set_jump("linear")
     sg.set_gate(0.0)
     recs, rep = sg.advance(lat, "vv4", w.dt, 1, threshold=float("inf"))
@@ -250,7 +253,7 @@ def test_linear_jump_fp32_against_oracle():
     sg.close()
 
 
-@pytest.mark.parametrize("N,precision", [(64, "fp32"), (128, "fp32"), (256, "fp32"), (256, "fp64")])
+@pytest.mark.parametrize("N,precision", [(64, "fp32"), (128, "fp32"), (256, "fp32"), (256, "fp64"), (512, "fp32")])
 def test_free_fields_at_size_equal_the_integrator(N, precision):
     """The launch shapes the benchmark times (256^3: 2048-value fused z
     batches, 16-line FP32 axis batches with radix-16 passes, 129^3 folded
