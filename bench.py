@@ -540,6 +540,40 @@ def surrogate_run(epochs=12, pairs_per_seed=64, train_seeds=range(2000, 2008), e
         out["eval"].append(evaluate(256, 0.5, min(jumps, 40)))  # half the training dx: out of distribution
     if s is not None:
         s.close()
+    out["summary"] = surrogate_summary(out["eval"])
+    return out
+
+
+def surrogate_summary(evals):
+    """The comparison the metric names, per evaluated 256^3 workload: rate
+    (site-updates/s) and error (worst relative error of the volume averages
+    against FP64 VV4) of FP64 VV4, FP32 VV4, FP32 leapfrog at dt, the linear
+    jump and the network jump (both gates), and the linear jump's rate over
+    FP64 VV4's and over the fastest integrator form whose error is no larger
+    than its own."""
+    out = []
+    for e in evals:
+        if e["N"] != 256:
+            continue
+        f = e["forms"]
+
+        def form(k):
+            v = f[k]
+            r = {"site_updates_per_s": v["effective_site_updates_per_s"], "error": v.get("error_vs_fp64_vv4", 0.0)}
+            if "accepted_fraction" in v:
+                r["accepted_fraction"] = v["accepted_fraction"]
+            return r
+
+        rows = {k: form(k) for k in ("fp64_vv4", "fp32_vv4", "fp32_leapfrog", "fp32_leapfrog_dt4",
+                                     "linear_jump", "surrogate")}
+        lj = rows["linear_jump"]
+        peers = [v["site_updates_per_s"] for k, v in rows.items()
+                 if k not in ("linear_jump", "surrogate") and v["error"] <= lj["error"]]
+        out.append({"workload": f"256^3 two-field FP32, k_IR = {e['k_ir']}, {e['jumps']} jumps of 16 VV4 steps",
+                    "forms": rows,
+                    "linear_jump_over_fp64_vv4": lj["site_updates_per_s"] / rows["fp64_vv4"]["site_updates_per_s"],
+                    "linear_jump_over_fastest_integrator_at_no_larger_error":
+                        lj["site_updates_per_s"] / max(peers) if peers else None})
     return out
 
 
