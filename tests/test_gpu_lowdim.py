@@ -50,6 +50,19 @@ def test_lowdim_fp64_parity(d, N, integrator):
     assert np.max(np.abs(p - s.p)) <= 1e-11 * np.max(np.abs(s.p))
 
 
+@pytest.mark.parametrize("N,steps", [(1024, 3), (2048, 2)])
+def test_lowdim_fp64_parity_long_marches(N, steps):
+    """2-D lattices large enough that a work item marches several rows (4 at
+    1024^2: one unrolled group of three and a remainder; 16 at 2048^2), in
+    FP64 against the oracle: per-step scalars and final fields within
+    1e-11."""
+    recs, orecs, (f, p), s = run_both(2, N, "vv4", steps)
+    assert not np.any(recs["nonfinite"])
+    compare_records(recs, orecs, 2, 1e-11)
+    assert np.max(np.abs(f - s.f)) <= 1e-11 * np.max(np.abs(s.f))
+    assert np.max(np.abs(p - s.p)) <= 1e-11 * np.max(np.abs(s.p))
+
+
 @pytest.mark.parametrize("d,N", [(1, 4096), (2, 64)])
 def test_lowdim_fp32_parity(d, N):
     recs, orecs, _, _ = run_both(d, N, "vv4", 30, precision="fp32", famp=0.05, pamp=0.05)
