@@ -1125,7 +1125,7 @@ __device__ __forceinline__ const Scal* ens_scal_before(const EnsMember& M, int p
 }
 
 template <typename T, int NF, int MAXRY>
-__global__ __launch_bounds__(256) void ensemble_pass(EnsArgs E) {
+__global__ __launch_bounds__(256, (NF == 1 && MAXRY == 1) ? 3 : 1) void ensemble_pass(EnsArgs E) {
     constexpr int NS = kSumsPerField * NF + 1;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double tot[kMaxSums];
