@@ -650,9 +650,10 @@ def lowdim_run(w, steps, warmup, chunk=500):
 
 def spectrum_run(w, reps=5):
     """Cost of one power spectrum of f_0 on the workload's lattice: device
-    FFT in FP64 (extraction, three line-FFT passes, binning) plus the copy of
-    the bins; algorithmic bytes 4 (or 8) + 16 to extract, 32 per FFT pass,
-    16 to bin, per site."""
+    FFT in FP64 (extraction fused with the z pass, the y pass, the x pass
+    fused with the binning) plus the copy of the bins; algorithmic bytes per
+    site: 4 (or 8) read + 16 written by the first pass, 32 by the y pass,
+    16 read by the last."""
     import torch
     stream = torch.cuda.Stream()
     lat = make(w, w.precision, stream, tune=False)
@@ -666,7 +667,7 @@ def spectrum_run(w, reps=5):
     lat.close()
     sec = float(np.median(times))
     e = 4 if w.precision == "fp32" else 8
-    alg = (e + 16 + 3 * 32 + 16) * w.sites
+    alg = (e + 16 + 32 + 16) * w.sites
     return {"field": "f_0", "binning": "canonical (width 1)", "bins": int(len(k)), "ms": 1e3 * sec,
             "hbm_frac": alg / sec / 1e9 / HBM_PEAK_GBS, "alg_bytes": alg}
 

@@ -186,8 +186,13 @@ hipError_t launch_spec_extract(const void* state, bool fp32, int N, int nf, int 
 hipError_t launch_spec_fft(double2* data, const double2* tw, int N, int axis, hipStream_t s, bool inverse = false);
 // The same in FP32 (complex float values and twiddles).
 hipError_t launch_fft_f32(float2* data, const float2* tw, int N, int axis, hipStream_t s, bool inverse);
-hipError_t launch_spec_bin(const double2* F, int N, double width, int nbins, double* sums,
-                           unsigned long long* counts, hipStream_t s);
+// The power spectrum's fused first pass (extraction of array `arr` + the z
+// transform) and last pass (the x transform + binning into sums / counts,
+// which the caller has cleared).
+hipError_t launch_spec_extract_fftz(const void* state, bool fp32, int N, int na, int arr, const double2* tw,
+                                   double2* F, hipStream_t s);
+hipError_t launch_spec_fftx_bin(const double2* F, const double2* tw, int N, double width, int nbins, double* sums,
+                                unsigned long long* counts, hipStream_t s);
 // Gravitational-wave spectrum: projected |U|^2 per centred shell (sums has
 // nbins + 1 slots, the last for the modes beyond the bins).
 hipError_t launch_gw_bin(const double2* U, int N, double width, int nbins, double* sums, unsigned long long* counts,

@@ -1217,11 +1217,15 @@ cl_status cl_power_spectrum(cl_lattice* h, int field, int what, double width, in
     }
     if ((st = ensure_twiddles(h)) || (st = ensure_bins(h, nbins))) return st;
     const int arr = what == 0 ? field : arrays(h) + field;
-    HIPCHECK(h, cl::launch_spec_extract(h->buf[h->cur], h->prec == CL_FP32, N, arrays(h), arr, h->spec, h->stream));
-    for (int axis = 0; axis < 3; ++axis) HIPCHECK(h, cl::launch_spec_fft(h->spec, h->spec_tw, N, axis, h->stream));
+    // extraction fused with the z pass, the y pass, the x pass fused with the
+    // binning: three sweeps of the complex array
     HIPCHECK(h, hipMemsetAsync(h->spec_sums, 0, nbins * sizeof(double), h->stream));
     HIPCHECK(h, hipMemsetAsync(h->spec_counts, 0, nbins * sizeof(unsigned long long), h->stream));
-    HIPCHECK(h, cl::launch_spec_bin(h->spec, N, width, nbins, h->spec_sums, h->spec_counts, h->stream));
+    HIPCHECK(h, cl::launch_spec_extract_fftz(h->buf[h->cur], h->prec == CL_FP32, N, 2 * arrays(h), arr, h->spec_tw,
+                                             h->spec, h->stream));
+    HIPCHECK(h, cl::launch_spec_fft(h->spec, h->spec_tw, N, 1, h->stream));
+    HIPCHECK(h, cl::launch_spec_fftx_bin(h->spec, h->spec_tw, N, width, nbins, h->spec_sums, h->spec_counts,
+                                         h->stream));
     std::vector<double> s(nbins);
     std::vector<unsigned long long> c(nbins);
     HIPCHECK(h, hipMemcpyAsync(s.data(), h->spec_sums, nbins * sizeof(double), hipMemcpyDeviceToHost, h->stream));

@@ -1,14 +1,18 @@
 // Power spectrum of one lattice array (Sect. 4.3, Eqs. discretePSaux,
 // discretePST2): the forward DFT f(n~) = sum_n exp(-2 pi i n~.n / N) f(n) in
 // FP64 as three passes of line transforms (z, then y, then x), and
-// the binning of |f(n~)|^2 into centred spherical shells of |n~|.
+// the binning of |f(n~)|^2 into centred spherical shells of |n~|.  The
+// extraction of the array from the state is fused with the z pass and the
+// binning with the x pass, so the complex array is swept three times.
 //
 // Line transform: a workgroup stages L lines of N complex values in LDS
-// (L N = 2048, 32 KB, for 64 <= N <= 2048), loaded in bit-reversed order, and runs the
-// log2 N butterfly stages of an iterative decimation-in-time FFT, three
-// stages per pass over LDS (radix-8 passes) with a barrier between passes.  For the z axis the L lines are consecutive rows;
-// for the y and x axes they are L consecutive z positions of one y-z (x-z)
-// slab, so every global access moves L consecutive complex values.
+// (L N = 2048, 32 KB, for 64 <= N <= 2048), loaded in bit-reversed order,
+// and runs the log2 N butterfly stages of an iterative decimation-in-time
+// FFT, three stages per pass over LDS (radix-8 passes; radix-16 for FP32
+// values) with a barrier between passes (fft_lds.h).  For the z axis the L
+// lines are consecutive rows; for the y and x axes they are L consecutive z
+// positions of one y-z (x-z) slab, so every global access moves L
+// consecutive complex values.
 #include "fft_lds.h"
 #include "internal.h"
 
@@ -123,30 +127,94 @@ __global__ void spec_extract(const T* __restrict__ state, int N, int nf, int arr
     }
 }
 
-// |F|^2 into centred shells l = floor(|n~| / w + 1/2) < nbins: per-workgroup
-// shared bins, then one global atomic per bin and workgroup.
-__global__ __launch_bounds__(256) void spec_bin(const double2* __restrict__ F, int N, double inv_w, int nbins,
-                                                double* __restrict__ sums, unsigned long long* __restrict__ counts) {
-    extern __shared__ unsigned char raw[];
-    double* s_sum = reinterpret_cast<double*>(raw);
+// Fused first pass of the power spectrum: array `arr` of L consecutive rows
+// of the row-interleaved state, as complex (value, 0), into LDS bit-reversed
+// along z, the z transform, out to F (the extraction's write and the z pass's
+// read of the complex array are saved).  K = L N / 256 values per thread.
+template <typename T, int K>
+__global__ __launch_bounds__(256) void spec_extract_fftz(const T* __restrict__ state, int N, int logN, int L,
+                                                         int na, int arr, const double2* __restrict__ tw,
+                                                         double2* __restrict__ F) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    double2* buf = reinterpret_cast<double2*>(lds_raw);
+    const int total = L * N;
+    const size_t row0 = static_cast<size_t>(blockIdx.x) * L;
+    T v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int idx = static_cast<int>(threadIdx.x) + k * 256;
+        if (K > 1 || idx < total) v[k] = state[((row0 + (idx >> logN)) * na + arr) * N + (idx & (N - 1))];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int idx = static_cast<int>(threadIdx.x) + k * 256;
+        if (K > 1 || idx < total)
+            buf[slot(idx >> logN, bitrev(idx & (N - 1), logN), N)] = make_double2(static_cast<double>(v[k]), 0.0);
+    }
+    const double2* tws = stage_twiddles(buf, tw, N, L);
+    __syncthreads();
+    fft_lds_stages(buf, tws, logN, L, false);
+    double2* out = F + row0 * N;
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) out[idx] = buf[slot(idx >> logN, idx & (N - 1), N)];
+}
+
+// Fused last pass of the power spectrum: the x transform of each batch of L
+// lines (L consecutive z of one y, as in fft_lines), then |F|^2 of every
+// mode into centred shells l = floor(|n~| / w + 1/2) < nbins in LDS; a
+// workgroup takes batches blockIdx.x, + gridDim.x, ... and adds its shells
+// to the global sums and counts once (the x pass's write and the binning
+// pass's read of the complex array are saved).
+template <int K>
+__global__ __launch_bounds__(256) void spec_fftx_bin(const double2* __restrict__ F, int N, int logN, int L, int logL,
+                                                     const double2* __restrict__ tw, double inv_w, int nbins,
+                                                     double* __restrict__ sums,
+                                                     unsigned long long* __restrict__ counts) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    double2* buf = reinterpret_cast<double2*>(lds_raw);
+    const size_t nv = fft_lds_values(N, L) + (N / 2 > 0 ? N / 2 : 1);
+    double* s_sum = reinterpret_cast<double*>(buf + nv);
     unsigned* s_cnt = reinterpret_cast<unsigned*>(s_sum + nbins);
+    const double2* tws = stage_twiddles(buf, tw, N, L);
     for (int i = threadIdx.x; i < nbins; i += blockDim.x) {
         s_sum[i] = 0.0;
         s_cnt[i] = 0u;
     }
-    __syncthreads();
-    const size_t n3 = static_cast<size_t>(N) * N * N;
-    const int hN = N / 2;
-    for (size_t s = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; s < n3;
-         s += static_cast<size_t>(gridDim.x) * blockDim.x) {
-        const int z = static_cast<int>(s % N), y = static_cast<int>((s / N) % N), x = static_cast<int>(s / (static_cast<size_t>(N) * N));
-        const int nx = x <= hN ? x : x - N, ny = y <= hN ? y : y - N, nz = z <= hN ? z : z - N;
-        const double r = sqrt(static_cast<double>(nx * nx + ny * ny + nz * nz));
-        const int lb = static_cast<int>(floor(r * inv_w + 0.5));
-        if (lb < nbins) {
-            const double2 v = F[s];
-            atomicAdd(&s_sum[lb], fma(v.x, v.x, v.y * v.y));
-            atomicAdd(&s_cnt[lb], 1u);
+    const int total = L * N, hN = N / 2;
+    const int logper = logN - logL;  // batches per y: N / L
+    const int batches = N << logper;
+    for (int b = blockIdx.x; b < batches; b += gridDim.x) {
+        const size_t y = static_cast<size_t>(b) >> logper;
+        const int z0 = (b & ((1 << logper) - 1)) << logL;
+        __syncthreads();  // the previous batch no longer reads LDS
+        // element idx: x = idx >> logL, z = z0 + (idx & (L - 1)); L
+        // consecutive z of a row per global access; every load of a thread
+        // before its LDS stores (K = L N / 256 per thread, 1 below 256)
+        double2 v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int idx = static_cast<int>(threadIdx.x) + k * 256;
+            if (K > 1 || idx < total)
+                v[k] = F[(static_cast<size_t>(idx >> logL) * N + y) * N + z0 + (idx & (L - 1))];
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int idx = static_cast<int>(threadIdx.x) + k * 256;
+            if (K > 1 || idx < total) buf[slot(idx & (L - 1), bitrev(idx >> logL, logN), N)] = v[k];
+        }
+        __syncthreads();
+        fft_lds_stages(buf, tws, logN, L, false);
+        const int ny = static_cast<int>(y) <= hN ? static_cast<int>(y) : static_cast<int>(y) - N;
+        for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+            const int e = idx >> logL, l = idx & (L - 1);
+            const int z = z0 + l;
+            const int nx = e <= hN ? e : e - N, nz = z <= hN ? z : z - N;
+            const double r = sqrt(static_cast<double>(nx * nx + ny * ny + nz * nz));
+            const int lb = static_cast<int>(floor(r * inv_w + 0.5));
+            if (lb < nbins) {
+                const double2 v = buf[slot(l, e, N)];
+                atomicAdd(&s_sum[lb], fma(v.x, v.x, v.y * v.y));
+                atomicAdd(&s_cnt[lb], 1u);
+            }
         }
     }
     __syncthreads();
@@ -279,13 +347,54 @@ hipError_t launch_spec_extract(const void* state, bool fp32, int N, int nf, int 
     return hipGetLastError();
 }
 
-hipError_t launch_spec_bin(const double2* F, int N, double width, int nbins, double* sums, unsigned long long* counts,
-                           hipStream_t s) {
-    const size_t n3 = static_cast<size_t>(N) * N * N;
-    const unsigned grid = static_cast<unsigned>(std::min<size_t>((n3 + 255) / 256, 2048));
-    const size_t lds = static_cast<size_t>(nbins) * (sizeof(double) + sizeof(unsigned));
-    hipLaunchKernelGGL(spec_bin, dim3(grid), dim3(256), lds, s, F, N, 1.0 / width, nbins, sums, counts);
+hipError_t launch_spec_extract_fftz(const void* state, bool fp32, int N, int na, int arr, const double2* tw,
+                                   double2* F, hipStream_t s) {
+    int logN = 0;
+    while ((1 << logN) < N) ++logN;
+    const int L = fft_lines_per_block(N), total = L * N;
+    if ((1 << logN) != N || total > 2048) return hipErrorInvalidValue;
+    const dim3 grid(static_cast<unsigned>(N) * N / L);
+    const size_t lds = fft_lds_bytes(N, L);
+#define CL_SPEC_XZ(T, K)                                                                                          \
+    hipLaunchKernelGGL((spec_extract_fftz<T, K>), grid, dim3(256), lds, s, static_cast<const T*>(state), N, logN, L, \
+                       na, arr, tw, F)
+    if (fp32) {
+        if (total == 2048) CL_SPEC_XZ(float, 8);
+        else if (total == 1024) CL_SPEC_XZ(float, 4);
+        else if (total == 512) CL_SPEC_XZ(float, 2);
+        else CL_SPEC_XZ(float, 1);
+    } else {
+        if (total == 2048) CL_SPEC_XZ(double, 8);
+        else if (total == 1024) CL_SPEC_XZ(double, 4);
+        else if (total == 512) CL_SPEC_XZ(double, 2);
+        else CL_SPEC_XZ(double, 1);
+    }
+#undef CL_SPEC_XZ
     return hipGetLastError();
 }
+
+hipError_t launch_spec_fftx_bin(const double2* F, const double2* tw, int N, double width, int nbins, double* sums,
+                                unsigned long long* counts, hipStream_t s) {
+    int logN = 0;
+    while ((1 << logN) < N) ++logN;
+    const int L = fft_lines_per_block(N);
+    int logL = 0;
+    while ((1 << logL) < L) ++logL;
+    if ((1 << logN) != N || (1 << logL) != L) return hipErrorInvalidValue;
+    const int batches = N * N / L;
+    const unsigned grid = static_cast<unsigned>(std::min(batches, 2048));
+    const size_t lds = fft_lds_bytes(N, L) + static_cast<size_t>(nbins) * (sizeof(double) + sizeof(unsigned));
+    const int total = L * N;
+#define CL_SPEC_XB(K) \
+    hipLaunchKernelGGL((spec_fftx_bin<K>), dim3(grid), dim3(256), lds, s, F, N, logN, L, logL, tw, 1.0 / width, nbins, sums, counts)
+    if (total == 2048) CL_SPEC_XB(8);
+    else if (total == 1024) CL_SPEC_XB(4);
+    else if (total == 512) CL_SPEC_XB(2);
+    else if (total <= 256) CL_SPEC_XB(1);
+    else return hipErrorInvalidValue;
+#undef CL_SPEC_XB
+    return hipGetLastError();
+}
+
 
 }  // namespace cl
