@@ -181,7 +181,6 @@ hipError_t launch_pass(const PassArgs& a, const Tile& t, cl_precision prec, hipS
 // One workgroup of t.NT threads: the pending scalar step of the last pass.
 hipError_t launch_finish(const PassArgs& a, const Tile& t, int nf, hipStream_t s);
 // Power spectrum (spectrum.hip).
-hipError_t launch_spec_extract(const void* state, bool fp32, int N, int nf, int arr, double2* out, hipStream_t s);
 // One axis pass of the line FFT (in place); inverse: conjugate twiddles, no 1/N.
 hipError_t launch_spec_fft(double2* data, const double2* tw, int N, int axis, hipStream_t s, bool inverse = false);
 // The same in FP32 (complex float values and twiddles).

@@ -1294,9 +1294,10 @@ cl_status cl_gw_spectrum(cl_lattice* h, double width, int nbins, int64_t* counts
     if ((st = ensure_twiddles(h)) || (st = ensure_bins(h, nbins + 1))) return st;
     for (int c = 0; c < 5; ++c) {
         double2* dst = h->gw_spec + c * n3;
-        HIPCHECK(h, cl::launch_spec_extract(h->buf[h->cur], h->prec == CL_FP32, N, arrays(h), arrays(h) + h->nf + c,
-                                            dst, h->stream));
-        for (int axis = 0; axis < 3; ++axis) HIPCHECK(h, cl::launch_spec_fft(dst, h->spec_tw, N, axis, h->stream));
+        // extraction of the component fused with the z pass, then y and x
+        HIPCHECK(h, cl::launch_spec_extract_fftz(h->buf[h->cur], h->prec == CL_FP32, N, 2 * arrays(h),
+                                                 arrays(h) + h->nf + c, h->spec_tw, dst, h->stream));
+        for (int axis = 1; axis < 3; ++axis) HIPCHECK(h, cl::launch_spec_fft(dst, h->spec_tw, N, axis, h->stream));
     }
     HIPCHECK(h, hipMemsetAsync(h->spec_sums, 0, (nbins + 1) * sizeof(double), h->stream));
     HIPCHECK(h, hipMemsetAsync(h->spec_counts, 0, nbins * sizeof(unsigned long long), h->stream));

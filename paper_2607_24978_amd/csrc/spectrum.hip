@@ -116,17 +116,6 @@ __global__ __launch_bounds__(256) void fft_lines(FftArgs<V2> a) {
     }
 }
 
-// Array `arr` of the row-interleaved state -> complex (value, 0).
-template <typename T>
-__global__ void spec_extract(const T* __restrict__ state, int N, int nf, int arr, double2* __restrict__ out) {
-    const size_t n3 = static_cast<size_t>(N) * N * N;
-    for (size_t s = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; s < n3;
-         s += static_cast<size_t>(gridDim.x) * blockDim.x) {
-        const size_t z = s % N, row = s / N;
-        out[s] = make_double2(static_cast<double>(state[(row * 2 * nf + arr) * N + z]), 0.0);
-    }
-}
-
 // Fused first pass of the power spectrum: array `arr` of L consecutive rows
 // of the row-interleaved state, as complex (value, 0), into LDS bit-reversed
 // along z, the z transform, out to F (the extraction's write and the z pass's
@@ -339,13 +328,6 @@ hipError_t launch_fft_f32(float2* data, const float2* tw, int N, int axis, hipSt
     return launch_fft(data, tw, N, fft_lines_per_block_f32(N), axis, s, inverse);
 }
 
-hipError_t launch_spec_extract(const void* state, bool fp32, int N, int nf, int arr, double2* out, hipStream_t s) {
-    const size_t n3 = static_cast<size_t>(N) * N * N;
-    const unsigned grid = static_cast<unsigned>(std::min<size_t>((n3 + 255) / 256, 8192));
-    if (fp32) hipLaunchKernelGGL(spec_extract<float>, dim3(grid), dim3(256), 0, s, static_cast<const float*>(state), N, nf, arr, out);
-    else hipLaunchKernelGGL(spec_extract<double>, dim3(grid), dim3(256), 0, s, static_cast<const double*>(state), N, nf, arr, out);
-    return hipGetLastError();
-}
 
 hipError_t launch_spec_extract_fftz(const void* state, bool fp32, int N, int na, int arr, const double2* tw,
                                    double2* F, hipStream_t s) {
