@@ -192,17 +192,37 @@ __global__ __launch_bounds__(256) void spec_fftx_bin(const double2* __restrict__
         }
         __syncthreads();
         fft_lds_stages(buf, tws, logN, L, false);
+        // a thread walks the L modes of one x (consecutive z: mostly one
+        // shell) and adds a run of equal shells to LDS once
         const int ny = static_cast<int>(y) <= hN ? static_cast<int>(y) : static_cast<int>(y) - N;
-        for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-            const int e = idx >> logL, l = idx & (L - 1);
-            const int z = z0 + l;
-            const int nx = e <= hN ? e : e - N, nz = z <= hN ? z : z - N;
-            const double r = sqrt(static_cast<double>(nx * nx + ny * ny + nz * nz));
-            const int lb = static_cast<int>(floor(r * inv_w + 0.5));
-            if (lb < nbins) {
-                const double2 v = buf[slot(l, e, N)];
-                atomicAdd(&s_sum[lb], fma(v.x, v.x, v.y * v.y));
-                atomicAdd(&s_cnt[lb], 1u);
+        for (int e = threadIdx.x; e < N; e += blockDim.x) {
+            const int nx = e <= hN ? e : e - N;
+            int cur = -1;
+            double run = 0.0;
+            unsigned cnt = 0u;
+            for (int l = 0; l < L; ++l) {
+                const int z = z0 + l;
+                const int nz = z <= hN ? z : z - N;
+                const double r = sqrt(static_cast<double>(nx * nx + ny * ny + nz * nz));
+                const int lb = static_cast<int>(floor(r * inv_w + 0.5));
+                if (lb != cur) {
+                    if (cnt) {
+                        atomicAdd(&s_sum[cur], run);
+                        atomicAdd(&s_cnt[cur], cnt);
+                    }
+                    cur = lb;
+                    run = 0.0;
+                    cnt = 0u;
+                }
+                if (lb < nbins) {
+                    const double2 v = buf[slot(l, e, N)];
+                    run = fma(v.x, v.x, fma(v.y, v.y, run));
+                    ++cnt;
+                }
+            }
+            if (cnt) {
+                atomicAdd(&s_sum[cur], run);
+                atomicAdd(&s_cnt[cur], cnt);
             }
         }
     }
