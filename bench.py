@@ -837,7 +837,7 @@ def main():
     ap.add_argument("--no-c3", action="store_true", help="skip the 1024^3 leapfrog leg of the default run")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the power-spectrum, gravitational-wave and 2+1 legs of the default run")
-    ap.add_argument("--profile-leg", choices=["gw", "batched", "surrogate", "spectrum"], default=None,
+    ap.add_argument("--profile-leg", choices=["gw", "batched", "surrogate", "spectrum", "lowdim"], default=None,
                     help="only run that leg (for a kernel profile; --steps / --warmup set the length of gw and "
                          "batched) and print it")
     ap.add_argument("--workload", choices=["c1", "c3"], default="c1",
@@ -867,6 +867,9 @@ def main():
     if args.profile_leg == "surrogate":
         print(json.dumps(surrogate_run(epochs=args.sg_epochs, pairs_per_seed=args.sg_pairs, jumps=args.sg_jumps,
                                        extra_inputs=args.sg_extra, ablation=args.sg_ablation)), flush=True)
+        return
+    if args.profile_leg == "lowdim":
+        print(json.dumps(lowdim_run(W.C4, args.steps or 2000, args.warmup or 200)), flush=True)
         return
     if args.profile_leg == "spectrum":
         print(json.dumps(spectrum_run(W.C1, reps=args.steps or 20)), flush=True)

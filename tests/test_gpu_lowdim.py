@@ -38,7 +38,7 @@ def run_both(d, N, integrator, n, precision="fp64", seed=61, expansion="self", f
 
 
 @pytest.mark.parametrize("integrator", ["leapfrog", "vv4"])
-@pytest.mark.parametrize("d,N", [(1, 64), (1, 1000), (2, 16), (2, 36), (2, 128)])
+@pytest.mark.parametrize("d,N", [(1, 64), (1, 1000), (2, 16), (2, 36), (2, 128), (2, 256)])
 def test_lowdim_fp64_parity(d, N, integrator):
     """Two-field preheating potential, self-consistent expansion, 30 steps:
     per-step scalars and final fields within 1e-11 (ragged sizes: 1000 and
