@@ -1262,9 +1262,12 @@ cl_status cl_surrogate_advance(cl_lattice* h, cl_surrogate* s, cl_integrator fal
             // about the predicted means
             h->cur = cur0 ^ 1;
             st = cl::set_background_async(h, a_pred, b, eta1, step1, f);
-            if (st) return sfail(st, cl_last_error(h));
-            st = cl::observe_once(h, &s->jump_obs->o, &s->jump_obs->sc);
-            if (st) return sfail(st, cl_last_error(h));
+            if (!st) st = cl::observe_once(h, &s->jump_obs->o, &s->jump_obs->sc);
+            if (st) {
+                // the untouched state stays the current one
+                h->cur = cur0;
+                return sfail(st, cl_last_error(h));
+            }
             after = s->jump_obs->o;
             sca = s->jump_obs->sc;
             ok = !after.nonfinite;
