@@ -172,6 +172,46 @@ def test_fp32_parity_two_field(integrator):
     compare_records(recs, orecs, 2, 1e-4, energy_scale=True)
 
 
+@pytest.mark.parametrize("integrator", ["leapfrog", "vv4"])
+def test_fp32_reductions_with_order_one_fluctuations(integrator):
+    """FP32 form with fluctuations as large as the fields (values of both
+    signs, neighbours that differ by O(f), so differences of neighbours are not
+    exact): the energies and moments the FP32 pass reduces, against the FP64
+    oracle on the same FP32-rounded values.  Each site term is a few correctly
+    rounded FP32 operations (relative error a few 2^-24) and a thread adds at
+    most 16 of them per plane in FP32 before the FP64 sums, so the sums of
+    these positive terms are within 16 * 2^-24 ~ 1e-6 relative; the test
+    allows 3e-6.  Then one step, compared the same way."""
+    w = W.C1.with_(N=32, k_ir=2.0, precision="fp32")
+    rng = np.random.default_rng(4242)
+    shape = (2, w.N, w.N, w.N)
+    f = rng.uniform(-1.0, 1.0, shape) + np.array([0.3, 0.0])[:, None, None, None]
+    p = rng.uniform(-1.0, 1.0, shape)
+    lat = make_lattice(w, precision="fp32")
+    lat.set_fields(f, p)
+    f32, p32 = lat.get_fields()
+    assert np.array_equal(f32, f.astype(np.float32)) and np.array_equal(p32, p.astype(np.float32))
+    P = params(w)
+    st = lat.get_state()
+    s0 = L.State(f32, p32, st["a"], st["b"], st["eta"])
+
+    def check(o, ref, tol):
+        assert abs(o["EV"] - ref["EV"]) <= tol * ref["EV"], ("EV", o["EV"], ref["EV"])
+        for j in range(2):
+            for k in ("EK", "EG", "var"):
+                assert abs(o[k][j] - ref[k][j]) <= tol * ref[k][j], (k, j, o[k][j], ref[k][j])
+            spread = math.sqrt(ref["var"][j])
+            assert abs(o["mean"][j] - ref["mean"][j]) <= tol * spread, ("mean", j)
+
+    check(lat.read_observables(), L.observe(s0, P), 3e-6)
+    # one full step from the same state: the stepped fields differ from the
+    # oracle's by FP32 rounding of the update, so the bar is the FP32 form's
+    recs = lat.step(integrator, w.dt, 1)
+    s1, orecs = L.run(s0, w.dt, 1, P, integrator)
+    compare_records(recs, orecs, 2, 1e-5, energy_scale=False)
+    lat.close()
+
+
 # ------------------------------------------------------------------ runtime properties
 def test_observables_of_current_state():
     w = W.C0.with_(N=16)
