@@ -195,9 +195,10 @@ cl_status cl_surrogate_set_gate(cl_surrogate* s, double fluct_tol);
  * self-interaction over the jump, which the gates catch as it grows.  Needs
  * no training or normalisation.  The propagation over a jump depends on a
  * mode only through kappa^2, even in each mode index and symmetric in their
- * order, so one FP64 transfer matrix per sorted triple of folded indices is
- * built per jump (C(N/2+3, 3) entries of 128 bytes: 47 MB at N = 256); N <=
- * 1024 (CL_EUNSUPPORTED above).  The jump's result is written to the
+ * order, so one transfer matrix per sorted triple of folded indices is built
+ * per jump, in FP64, and stored and applied in the lattice's precision
+ * (C(N/2+3, 3) entries; a workspace of 128 bytes each: 47 MB at N = 256);
+ * N <= 1024 (CL_EUNSUPPORTED above).  The jump's result is written to the
  * lattice's second state buffer, which becomes the current one if the jump
  * is kept (as after an integrator pass). */
 typedef enum { CL_JUMP_NETWORK = 0, CL_JUMP_LINEAR = 1 } cl_jump_mode;

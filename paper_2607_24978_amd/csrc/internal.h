@@ -224,7 +224,8 @@ struct PropModeArgs {
     const PropStep* steps;
     int nsteps;
     double scale;          // 1 / N^3 (the inverse transform's normalisation)
-    double* table;         // [prop_table_entries(N)][16]: transfer matrices (workspace)
+    void* table;           // [prop_table_entries(N)][(2 nf)^2]: transfer matrices, FP32 for FP32
+                           // lattices, else FP64 (workspace of 16 doubles per entry)
     const uint32_t* triples;  // prop_triples(N) on the device
     size_t ntriples;
 };

@@ -31,6 +31,7 @@
 
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <type_traits>
 #include <vector>
 
 namespace cl {
@@ -137,7 +138,7 @@ __device__ __forceinline__ size_t triple_index(size_t i0, size_t i1, size_t i2) 
 // unit vectors (the same operations as on a mode's values; the columns are
 // independent chains).  Layout T[row][col] with a stride of 16 per entry,
 // rows and columns in the channel order f_0.., pi_0...
-template <int NF>
+template <int NF, typename TT>
 __global__ __launch_bounds__(256) void prop_transfer(PropModeArgs a) {
     constexpr int NC = 2 * NF;
     const size_t t = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -175,13 +176,15 @@ __global__ __launch_bounds__(256) void prop_transfer(PropModeArgs a) {
             }
         }
     }
-    double* T = a.table + t * 16;
+    // stored in the lattice's precision (FP32 lattices: the matrices' rounding
+    // is that of the FP32 transforms they act between), rounded once
+    TT* T = static_cast<TT*>(a.table) + t * (NC * NC);
 #pragma unroll
     for (int col = 0; col < NC; ++col)
 #pragma unroll
         for (int j = 0; j < NF; ++j) {
-            T[j * NC + col] = F[col][j];
-            T[(NF + j) * NC + col] = P[col][j];
+            T[j * NC + col] = static_cast<TT>(F[col][j]);
+            T[(NF + j) * NC + col] = static_cast<TT>(P[col][j]);
         }
 }
 
@@ -206,10 +209,15 @@ __global__ __launch_bounds__(256) void prop_modes(PropModeArgs a) {
     if (s0 > s1) { const int x = s0; s0 = s1; s1 = x; }
     if (s1 > s2) { const int x = s1; s1 = s2; s2 = x; }
     if (s0 > s1) { const int x = s0; s0 = s1; s1 = x; }
-    const double2* T2 = reinterpret_cast<const double2*>(a.table + triple_index(s0, s1, s2) * 16);
-    double2 Tv[NC * NC / 2];
+    // the matrix in the table's precision (FP32 for FP32 lattices), 16-byte loads
+    constexpr bool F32 = std::is_same<V2, float2>::value;
+    using TS = typename std::conditional<F32, float, double>::type;
+    using TV = typename std::conditional<F32, float4, double2>::type;
+    constexpr int TPV = sizeof(TV) / sizeof(TS);  // table values per load
+    const TV* T2 = reinterpret_cast<const TV*>(static_cast<const TS*>(a.table) + triple_index(s0, s1, s2) * (NC * NC));
+    TV Tv[NC * NC / TPV];
 #pragma unroll
-    for (int e = 0; e < NC * NC / 2; ++e) Tv[e] = T2[e];
+    for (int e = 0; e < NC * NC / TPV; ++e) Tv[e] = T2[e];
     // representatives (sx, sy, +) of the pairs; an index equal to its mirror
     // (0 or N/2) has one sign only
     const bool x1 = i0 == 0 || 2 * i0 == N, y1 = i1 == 0 || 2 * i1 == N;
@@ -232,40 +240,52 @@ __global__ __launch_bounds__(256) void prop_modes(PropModeArgs a) {
                 vk[p][q] = static_cast<const V2*>(a.in[q])[k[p]];
                 vm[p][q] = static_cast<const V2*>(a.in[q])[m[p]];
             }
-    double Tm[NC * NC];
+    // the channel arithmetic in the table's precision: FP32 for FP32 lattices
+    // (values and matrices are FP32 already; half the registers), FP64 else
+    TS Tm[NC * NC];
 #pragma unroll
-    for (int e = 0; e < NC * NC / 2; ++e) {
-        Tm[2 * e] = Tv[e].x;
-        Tm[2 * e + 1] = Tv[e].y;
+    for (int e = 0; e < NC * NC / TPV; ++e) {
+        const TS* tv = reinterpret_cast<const TS*>(&Tv[e]);
+#pragma unroll
+        for (int u = 0; u < TPV; ++u) Tm[TPV * e + u] = tv[u];
     }
+    const TS half = TS(0.5), sc = static_cast<TS>(a.scale);
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
         if (!on[p]) continue;
-        double2 ch[NC];
+        TS cx[NC], cy[NC];
 #pragma unroll
         for (int q = 0; q < NF; ++q) {
-            const double ux = vk[p][q].x, uy = vk[p][q].y, rx = vm[p][q].x, ry = vm[p][q].y;
-            ch[2 * q] = make_double2(0.5 * (ux + rx), 0.5 * (uy - ry));
-            ch[2 * q + 1] = make_double2(0.5 * (uy + ry), -0.5 * (ux - rx));
+            const TS ux = vk[p][q].x, uy = vk[p][q].y, rx = vm[p][q].x, ry = vm[p][q].y;
+            cx[2 * q] = half * (ux + rx);
+            cy[2 * q] = half * (uy - ry);
+            cx[2 * q + 1] = half * (uy + ry);
+            cy[2 * q + 1] = -half * (ux - rx);
         }
-        double2 out[NC];
+        TS ox[NC], oy[NC];
 #pragma unroll
         for (int i = 0; i < NC; ++i) {
-            double2 v = make_double2(0.0, 0.0);
+            TS vx = TS(0), vy = TS(0);
 #pragma unroll
             for (int j = 0; j < NC; ++j) {
-                const double tij = Tm[i * NC + j];
-                v.x += tij * ch[j].x;
-                v.y += tij * ch[j].y;
+                const TS tij = Tm[i * NC + j];
+                vx += tij * cx[j];
+                vy += tij * cy[j];
             }
-            out[i] = v;
+            ox[i] = vx;
+            oy[i] = vy;
         }
 #pragma unroll
         for (int q = 0; q < NF; ++q) {
-            const double2 x = out[2 * q], y = out[2 * q + 1];
+            const TS xx = ox[2 * q], xy = oy[2 * q], yx = ox[2 * q + 1], yy = oy[2 * q + 1];
             V2* o = static_cast<V2*>(a.out[q]);
-            o[k[p]] = make_v2<V2>(a.scale * (x.x - y.y), a.scale * (x.y + y.x));
-            o[m[p]] = make_v2<V2>(a.scale * (x.x + y.y), a.scale * (y.x - x.y));
+            V2 vk2, vm2;
+            vk2.x = sc * (xx - yy);
+            vk2.y = sc * (xy + yx);
+            vm2.x = sc * (xx + yy);
+            vm2.y = sc * (yx - xy);
+            o[k[p]] = vk2;
+            o[m[p]] = vm2;
         }
     }
 }
@@ -339,13 +359,21 @@ hipError_t launch_prop_modes(const PropModeArgs& a, bool fp32, hipStream_t s) {
     const size_t M = a.N / 2 + 1;
     const unsigned mgrid = static_cast<unsigned>((M * M * M + 255) / 256);
     if (a.nf == 1) {
-        hipLaunchKernelGGL(prop_transfer<1>, dim3(tgrid), dim3(256), 0, s, a);
-        if (fp32) hipLaunchKernelGGL((prop_modes<1, float2>), dim3(mgrid), dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((prop_modes<1, double2>), dim3(mgrid), dim3(256), 0, s, a);
+        if (fp32) {
+            hipLaunchKernelGGL((prop_transfer<1, float>), dim3(tgrid), dim3(256), 0, s, a);
+            hipLaunchKernelGGL((prop_modes<1, float2>), dim3(mgrid), dim3(256), 0, s, a);
+        } else {
+            hipLaunchKernelGGL((prop_transfer<1, double>), dim3(tgrid), dim3(256), 0, s, a);
+            hipLaunchKernelGGL((prop_modes<1, double2>), dim3(mgrid), dim3(256), 0, s, a);
+        }
     } else {
-        hipLaunchKernelGGL(prop_transfer<2>, dim3(tgrid), dim3(256), 0, s, a);
-        if (fp32) hipLaunchKernelGGL((prop_modes<2, float2>), dim3(mgrid), dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((prop_modes<2, double2>), dim3(mgrid), dim3(256), 0, s, a);
+        if (fp32) {
+            hipLaunchKernelGGL((prop_transfer<2, float>), dim3(tgrid), dim3(256), 0, s, a);
+            hipLaunchKernelGGL((prop_modes<2, float2>), dim3(mgrid), dim3(256), 0, s, a);
+        } else {
+            hipLaunchKernelGGL((prop_transfer<2, double>), dim3(tgrid), dim3(256), 0, s, a);
+            hipLaunchKernelGGL((prop_modes<2, double2>), dim3(mgrid), dim3(256), 0, s, a);
+        }
     }
     return hipGetLastError();
 }
