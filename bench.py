@@ -652,8 +652,10 @@ def spectrum_run(w, reps=5):
     """Cost of one power spectrum of f_0 on the workload's lattice: device
     FFT in FP64 (extraction fused with the z pass, the y pass, the x pass
     fused with the binning) plus the copy of the bins; algorithmic bytes per
-    site: 4 (or 8) read + 16 written by the first pass, 32 by the y pass,
-    16 read by the last."""
+    site: 4 (or 8) read + 16 P / N written by the first pass, 32 P / N by the
+    y pass, 16 P / N read by the last, where P is the number of z of the
+    half transform that the y and x passes hold (z <= N / 2 rounded up to
+    whole batches of L = 2048 / N lines: 136 at N = 256)."""
     import torch
     stream = torch.cuda.Stream()
     lat = make(w, w.precision, stream, tune=False)
@@ -667,7 +669,9 @@ def spectrum_run(w, reps=5):
     lat.close()
     sec = float(np.median(times))
     e = 4 if w.precision == "fp32" else 8
-    alg = (e + 16 + 32 + 16) * w.sites
+    L = w.N if w.N <= 32 else 2048 // w.N
+    P = min(w.N, -(-(w.N // 2 + 1) // L) * L)
+    alg = int((e + 64 * P / w.N) * w.sites)
     return {"field": "f_0", "binning": "canonical (width 1)", "bins": int(len(k)), "ms": 1e3 * sec,
             "hbm_frac": alg / sec / 1e9 / HBM_PEAK_GBS, "alg_bytes": alg}
 

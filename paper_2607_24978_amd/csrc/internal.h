@@ -182,16 +182,26 @@ hipError_t launch_pass(const PassArgs& a, const Tile& t, cl_precision prec, hipS
 hipError_t launch_finish(const PassArgs& a, const Tile& t, int nf, hipStream_t s);
 // Power spectrum (spectrum.hip).
 // One axis pass of the line FFT (in place); inverse: conjugate twiddles, no 1/N.
-hipError_t launch_spec_fft(double2* data, const double2* tw, int N, int axis, hipStream_t s, bool inverse = false);
-// The same in FP32 (complex float values and twiddles).
+// P: stored z per (x, y) (0: N); a y or x pass may run over the first P z of
+// an array of pitch P (a multiple of the lines per batch).
+hipError_t launch_spec_fft(double2* data, const double2* tw, int N, int axis, hipStream_t s, bool inverse = false,
+                           int P = 0);
+// The same in FP32 (complex float values and twiddles), whole arrays.
 hipError_t launch_fft_f32(float2* data, const float2* tw, int N, int axis, hipStream_t s, bool inverse);
+// Pitch of the power spectrum's half array along z: z = 0 .. N / 2 rounded
+// up to whole batches of the y and x passes (at most N).
+int spec_half_pitch(int N);
 // The power spectrum's fused first pass (extraction of array `arr` + the z
-// transform) and last pass (the x transform + binning into sums / counts,
-// which the caller has cleared).
+// transform, the first P values of each line stored with pitch P) and last
+// pass (the x transform + binning into sums / counts, which the caller has
+// cleared, of the half array along z, the mirrored modes counted twice).
+// `zs`, `zc`: nzero sums and counts (the bins) that the first workgroup
+// clears for the last pass (nullptr: none).
 hipError_t launch_spec_extract_fftz(const void* state, bool fp32, int N, int na, int arr, const double2* tw,
-                                   double2* F, hipStream_t s);
-hipError_t launch_spec_fftx_bin(const double2* F, const double2* tw, int N, double width, int nbins, double* sums,
-                                unsigned long long* counts, hipStream_t s);
+                                   double2* F, int P, double* zs, unsigned long long* zc, int nzero,
+                                   hipStream_t s);
+hipError_t launch_spec_fftx_bin(const double2* F, const double2* tw, int N, int P, double width, int nbins,
+                                double* sums, unsigned long long* counts, hipStream_t s);
 // Gravitational-wave spectrum: projected |U|^2 per centred shell (sums has
 // nbins + 1 slots, the last for the modes beyond the bins).
 hipError_t launch_gw_bin(const double2* U, int N, double width, int nbins, double* sums, unsigned long long* counts,
@@ -313,8 +323,9 @@ struct cl_lattice {
     double2* spec = nullptr;            // power spectrum: N^3 complex FP64, on first use
     double2* gw_spec = nullptr;         // gravitational-wave spectrum: 5 N^3 complex FP64, on first use
     double2* spec_tw = nullptr;         // its twiddle factors (N / 2)
-    double* spec_sums = nullptr;        // per-bin sums and counts (spec_cap bins)
-    unsigned long long* spec_counts = nullptr;
+    double* spec_sums = nullptr;        // per-bin sums and counts (spec_cap bins; two allocations:
+    unsigned long long* spec_counts = nullptr;  // the last pass's atomics on both were slower in one)
+    double* spec_host = nullptr;        // pinned host copy: spec_cap sums, then spec_cap counts
     int spec_cap = 0;
     int pass_flags = 1;                 // nontemporal stores
     int cur = 0;

@@ -895,6 +895,7 @@ cl_status cl_destroy(cl_lattice* h) {
     free_buffers(h);
     if (h->aux) hipFree(h->aux);
     if (h->aux2) hipFree(h->aux2);
+    if (h->spec_host) (void)hipHostFree(h->spec_host);
     for (void* q : {(void*)h->spec, (void*)h->gw_spec, (void*)h->spec_tw, (void*)h->spec_sums, (void*)h->spec_counts})
         if (q) hipFree(q);
     if (h->sc) hipFree(h->sc);
@@ -1138,11 +1139,14 @@ cl_status ensure_bins(cl_lattice* h, int slots) {
     if (h->spec_cap >= slots) return CL_OK;
     if (h->spec_sums) (void)hipFree(h->spec_sums);
     if (h->spec_counts) (void)hipFree(h->spec_counts);
+    if (h->spec_host) (void)hipHostFree(h->spec_host);
     h->spec_sums = nullptr;
     h->spec_counts = nullptr;
+    h->spec_host = nullptr;
     h->spec_cap = 0;
     HIPCHECK(h, hipMalloc(&h->spec_sums, slots * sizeof(double)));
     HIPCHECK(h, hipMalloc(&h->spec_counts, slots * sizeof(unsigned long long)));
+    HIPCHECK(h, hipHostMalloc(&h->spec_host, 2 * static_cast<size_t>(slots) * sizeof(double)));
     h->spec_cap = slots;
     return CL_OK;
 }
@@ -1218,20 +1222,21 @@ cl_status cl_power_spectrum(cl_lattice* h, int field, int what, double width, in
     if ((st = ensure_twiddles(h)) || (st = ensure_bins(h, nbins))) return st;
     const int arr = what == 0 ? field : arrays(h) + field;
     // extraction fused with the z pass, the y pass, the x pass fused with the
-    // binning: three sweeps of the complex array
-    HIPCHECK(h, hipMemsetAsync(h->spec_sums, 0, nbins * sizeof(double), h->stream));
-    HIPCHECK(h, hipMemsetAsync(h->spec_counts, 0, nbins * sizeof(unsigned long long), h->stream));
+    // binning: three sweeps of the complex array, the last two over the half
+    // z <= N / 2 (pitch P) that a real array's transform needs
+    // (the first pass clears the bins; they are copied to pinned memory)
+    const int P = cl::spec_half_pitch(N), cap = h->spec_cap;
     HIPCHECK(h, cl::launch_spec_extract_fftz(h->buf[h->cur], h->prec == CL_FP32, N, 2 * arrays(h), arr, h->spec_tw,
-                                             h->spec, h->stream));
-    HIPCHECK(h, cl::launch_spec_fft(h->spec, h->spec_tw, N, 1, h->stream));
-    HIPCHECK(h, cl::launch_spec_fftx_bin(h->spec, h->spec_tw, N, width, nbins, h->spec_sums, h->spec_counts,
+                                             h->spec, P, h->spec_sums, h->spec_counts, nbins, h->stream));
+    HIPCHECK(h, cl::launch_spec_fft(h->spec, h->spec_tw, N, 1, h->stream, false, P));
+    HIPCHECK(h, cl::launch_spec_fftx_bin(h->spec, h->spec_tw, N, P, width, nbins, h->spec_sums, h->spec_counts,
                                          h->stream));
-    std::vector<double> s(nbins);
-    std::vector<unsigned long long> c(nbins);
-    HIPCHECK(h, hipMemcpyAsync(s.data(), h->spec_sums, nbins * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-    HIPCHECK(h, hipMemcpyAsync(c.data(), h->spec_counts, nbins * sizeof(unsigned long long), hipMemcpyDeviceToHost,
-                               h->stream));
+    HIPCHECK(h, hipMemcpyAsync(h->spec_host, h->spec_sums, nbins * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHECK(h, hipMemcpyAsync(h->spec_host + cap, h->spec_counts, nbins * sizeof(unsigned long long),
+                               hipMemcpyDeviceToHost, h->stream));
     HIPCHECK(h, hipStreamSynchronize(h->stream));
+    const double* s = h->spec_host;
+    const unsigned long long* c = reinterpret_cast<const unsigned long long*>(h->spec_host + cap);
     const double k_ir = 2.0 * M_PI / (N * h->dx);
     const double n5 = std::pow(static_cast<double>(N), 5.0);
     for (int l = 0; l < nbins; ++l) {
@@ -1296,7 +1301,8 @@ cl_status cl_gw_spectrum(cl_lattice* h, double width, int nbins, int64_t* counts
         double2* dst = h->gw_spec + c * n3;
         // extraction of the component fused with the z pass, then y and x
         HIPCHECK(h, cl::launch_spec_extract_fftz(h->buf[h->cur], h->prec == CL_FP32, N, 2 * arrays(h),
-                                                 arrays(h) + h->nf + c, h->spec_tw, dst, h->stream));
+                                                 arrays(h) + h->nf + c, h->spec_tw, dst, N, nullptr, nullptr,
+                                                 0, h->stream));
         for (int axis = 1; axis < 3; ++axis) HIPCHECK(h, cl::launch_spec_fft(dst, h->spec_tw, N, axis, h->stream));
     }
     HIPCHECK(h, hipMemsetAsync(h->spec_sums, 0, (nbins + 1) * sizeof(double), h->stream));

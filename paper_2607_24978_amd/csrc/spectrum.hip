@@ -24,9 +24,11 @@ namespace cl {
 
 template <typename V2>
 struct FftArgs {
-    V2* data;            // N^3 complex, site (x N + y) N + z
+    V2* data;            // N^2 P complex, site (x N + y) P + z
     const V2* tw;        // exp(-2 pi i k / N), k < N / 2
     int N, logN, L, logL, axis;  // axis 0: z, 1: y, 2: x (N, L powers of two)
+    int P, nzb;          // stored z per (x, y) (N, or fewer for the y and x passes over a half
+                         // spectrum along z), batches of L z per slab (P / L)
     int inverse;         // 1: exp(+2 pi i k / N) (conjugate twiddles), no scaling
 };
 
@@ -35,11 +37,11 @@ struct FftArgs {
 // (`outer`, `z0`, formed once per workgroup).
 template <typename V2>
 __device__ __forceinline__ size_t line_elem(const FftArgs<V2>& a, int b, size_t outer, size_t z0, int l, int e) {
-    const size_t N = a.N;
-    if (a.axis == 0) return (static_cast<size_t>(b) * a.L + l) * N + e;
+    const size_t N = a.N, P = a.P;
+    if (a.axis == 0) return (static_cast<size_t>(b) * a.L + l) * N + e;  // P = N
     const size_t z = z0 + l;
-    if (a.axis == 1) return (outer * N + e) * N + z;      // x = outer, y = e
-    return (static_cast<size_t>(e) * N + outer) * N + z;  // x = e, y = outer
+    if (a.axis == 1) return (outer * N + e) * P + z;      // x = outer, y = e
+    return (static_cast<size_t>(e) * N + outer) * P + z;  // x = e, y = outer
 }
 
 // Element idx of a batch -> (line l, element e): the z axis takes whole
@@ -82,9 +84,8 @@ __global__ __launch_bounds__(256) void fft_lines(FftArgs<V2> a) {
     const int N = a.N, L = a.L, b = blockIdx.x;
     const int logN = a.logN, logL = a.logL;
     const int total = L * N;
-    const int logper = logN - logL;  // batches per slab: N / L
-    const size_t outer = static_cast<size_t>(b) >> logper;
-    const size_t z0 = static_cast<size_t>(b & ((1 << logper) - 1)) << logL;
+    const size_t outer = static_cast<size_t>(b) / a.nzb;  // a.nzb batches per slab
+    const size_t z0 = (static_cast<size_t>(b) - outer * a.nzb) << logL;
     // load: consecutive threads take consecutive global addresses (powers of
     // two: shifts and masks instead of divisions).  Full batches (L N = 2048
     // or 4096: 8 or 16 elements per thread) issue all of a thread's loads
@@ -119,13 +120,23 @@ __global__ __launch_bounds__(256) void fft_lines(FftArgs<V2> a) {
 // Fused first pass of the power spectrum: array `arr` of L consecutive rows
 // of the row-interleaved state, as complex (value, 0), into LDS bit-reversed
 // along z, the z transform, out to F (the extraction's write and the z pass's
-// read of the complex array are saved).  K = L N / 256 values per thread.
+// read of the complex array are saved).  The first P of the N transformed
+// values of a line are stored (row pitch P): the rest follow from Hermitian
+// symmetry of a real array's transform.  K = L N / 256 values per thread.
+// The first workgroup also clears the `nzero` sums and counts of the bins
+// that the last pass, launched after this one on the same stream, adds to.
 template <typename T, int K>
 __global__ __launch_bounds__(256) void spec_extract_fftz(const T* __restrict__ state, int N, int logN, int L,
                                                          int na, int arr, const double2* __restrict__ tw,
-                                                         double2* __restrict__ F) {
+                                                         double2* __restrict__ F, int P, double* __restrict__ zs,
+                                                         unsigned long long* __restrict__ zc, int nzero) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     double2* buf = reinterpret_cast<double2*>(lds_raw);
+    if (blockIdx.x == 0)
+        for (int i = threadIdx.x; i < nzero; i += blockDim.x) {
+            zs[i] = 0.0;
+            zc[i] = 0ull;
+        }
     const int total = L * N;
     const size_t row0 = static_cast<size_t>(blockIdx.x) * L;
     T v[K];
@@ -143,8 +154,11 @@ __global__ __launch_bounds__(256) void spec_extract_fftz(const T* __restrict__ s
     const double2* tws = stage_twiddles(buf, tw, N, L);
     __syncthreads();
     fft_lds_stages(buf, tws, logN, L, false);
-    double2* out = F + row0 * N;
-    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) out[idx] = buf[slot(idx >> logN, idx & (N - 1), N)];
+    double2* out = F + row0 * P;
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        const int l = idx >> logN, e = idx & (N - 1);
+        if (e < P) out[static_cast<size_t>(l) * P + e] = buf[slot(l, e, N)];
+    }
 }
 
 // Fused last pass of the power spectrum: the x transform of each batch of L
@@ -152,11 +166,15 @@ __global__ __launch_bounds__(256) void spec_extract_fftz(const T* __restrict__ s
 // mode into centred shells l = floor(|n~| / w + 1/2) < nbins in LDS; a
 // workgroup takes batches blockIdx.x, + gridDim.x, ... and adds its shells
 // to the global sums and counts once (the x pass's write and the binning
-// pass's read of the complex array are saved).
+// pass's read of the complex array are saved).  Only z <= N / 2 is held
+// (row pitch P, nzb = P / L batches per y): a real array's transform has
+// |F(-n~)| = |F(n~)|, so a mode with 0 < z < N / 2 also stands for its mirror
+// (z' = N - z, same |n~|) and is counted twice; columns beyond N / 2 are
+// padding of the last batch and are skipped.
 template <int K>
 __global__ __launch_bounds__(256) void spec_fftx_bin(const double2* __restrict__ F, int N, int logN, int L, int logL,
-                                                     const double2* __restrict__ tw, double inv_w, int nbins,
-                                                     double* __restrict__ sums,
+                                                     int P, int nzb, const double2* __restrict__ tw, double inv_w,
+                                                     int nbins, double* __restrict__ sums,
                                                      unsigned long long* __restrict__ counts) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     double2* buf = reinterpret_cast<double2*>(lds_raw);
@@ -169,11 +187,10 @@ __global__ __launch_bounds__(256) void spec_fftx_bin(const double2* __restrict__
         s_cnt[i] = 0u;
     }
     const int total = L * N, hN = N / 2;
-    const int logper = logN - logL;  // batches per y: N / L
-    const int batches = N << logper;
+    const int batches = N * nzb;
     for (int b = blockIdx.x; b < batches; b += gridDim.x) {
-        const size_t y = static_cast<size_t>(b) >> logper;
-        const int z0 = (b & ((1 << logper) - 1)) << logL;
+        const size_t y = static_cast<size_t>(b / nzb);
+        const int z0 = (b - static_cast<int>(y) * nzb) << logL;
         __syncthreads();  // the previous batch no longer reads LDS
         // element idx: x = idx >> logL, z = z0 + (idx & (L - 1)); L
         // consecutive z of a row per global access; every load of a thread
@@ -183,7 +200,7 @@ __global__ __launch_bounds__(256) void spec_fftx_bin(const double2* __restrict__
         for (int k = 0; k < K; ++k) {
             const int idx = static_cast<int>(threadIdx.x) + k * 256;
             if (K > 1 || idx < total)
-                v[k] = F[(static_cast<size_t>(idx >> logL) * N + y) * N + z0 + (idx & (L - 1))];
+                v[k] = F[(static_cast<size_t>(idx >> logL) * N + y) * P + z0 + (idx & (L - 1))];
         }
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -201,8 +218,8 @@ __global__ __launch_bounds__(256) void spec_fftx_bin(const double2* __restrict__
             double run = 0.0;
             unsigned cnt = 0u;
             for (int l = 0; l < L; ++l) {
-                const int z = z0 + l;
-                const int nz = z <= hN ? z : z - N;
+                const int nz = z0 + l;
+                if (nz > hN) break;  // padding columns (z grows with l)
                 const double r = sqrt(static_cast<double>(nx * nx + ny * ny + nz * nz));
                 const int lb = static_cast<int>(floor(r * inv_w + 0.5));
                 if (lb != cur) {
@@ -216,8 +233,10 @@ __global__ __launch_bounds__(256) void spec_fftx_bin(const double2* __restrict__
                 }
                 if (lb < nbins) {
                     const double2 v = buf[slot(l, e, N)];
-                    run = fma(v.x, v.x, fma(v.y, v.y, run));
-                    ++cnt;
+                    const double p = fma(v.x, v.x, v.y * v.y);
+                    const bool twice = nz != 0 && nz != hN;
+                    run += twice ? 2.0 * p : p;
+                    cnt += twice ? 2u : 1u;
                 }
             }
             if (cnt) {
@@ -321,7 +340,10 @@ hipError_t launch_gw_bin(const double2* U, int N, double width, int nbins, doubl
 
 namespace {
 template <typename V2>
-hipError_t launch_fft(V2* data, const V2* tw, int N, int L, int axis, hipStream_t s, bool inverse) {
+hipError_t launch_fft(V2* data, const V2* tw, int N, int L, int axis, hipStream_t s, bool inverse, int P) {
+    // the z axis needs whole lines; a y or x pass may cover fewer z (P a
+    // multiple of L, at most N)
+    if (P <= 0 || P > N || P % L != 0 || (axis == 0 && P != N)) return hipErrorInvalidValue;
     FftArgs<V2> a;
     a.inverse = inverse ? 1 : 0;
     a.data = data;
@@ -333,33 +355,42 @@ hipError_t launch_fft(V2* data, const V2* tw, int N, int L, int axis, hipStream_
     a.logL = 0;
     while ((1 << a.logL) < a.L) ++a.logL;
     a.axis = axis;
-    const int batches = N * N / a.L;
+    a.P = P;
+    a.nzb = P / L;
+    const int batches = axis == 0 ? N * N / L : N * a.nzb;
     const size_t lds = fft_lds_bytes(N, a.L, sizeof(V2));
     hipLaunchKernelGGL(fft_lines<V2>, dim3(batches), dim3(256), lds, s, a);
     return hipGetLastError();
 }
 }  // namespace
 
-hipError_t launch_spec_fft(double2* data, const double2* tw, int N, int axis, hipStream_t s, bool inverse) {
-    return launch_fft(data, tw, N, fft_lines_per_block(N), axis, s, inverse);
+hipError_t launch_spec_fft(double2* data, const double2* tw, int N, int axis, hipStream_t s, bool inverse, int P) {
+    return launch_fft(data, tw, N, fft_lines_per_block(N), axis, s, inverse, P > 0 ? P : N);
 }
 
 hipError_t launch_fft_f32(float2* data, const float2* tw, int N, int axis, hipStream_t s, bool inverse) {
-    return launch_fft(data, tw, N, fft_lines_per_block_f32(N), axis, s, inverse);
+    return launch_fft(data, tw, N, fft_lines_per_block_f32(N), axis, s, inverse, N);
+}
+
+int spec_half_pitch(int N) {
+    const int L = fft_lines_per_block(N), need = N / 2 + 1;
+    return std::min(N, (need + L - 1) / L * L);
 }
 
 
 hipError_t launch_spec_extract_fftz(const void* state, bool fp32, int N, int na, int arr, const double2* tw,
-                                   double2* F, hipStream_t s) {
+                                   double2* F, int P, double* zs, unsigned long long* zc, int nzero,
+                                   hipStream_t s) {
+    if (!zs || !zc) nzero = 0;
     int logN = 0;
     while ((1 << logN) < N) ++logN;
     const int L = fft_lines_per_block(N), total = L * N;
-    if ((1 << logN) != N || total > 2048) return hipErrorInvalidValue;
+    if ((1 << logN) != N || total > 2048 || P <= 0 || P > N) return hipErrorInvalidValue;
     const dim3 grid(static_cast<unsigned>(N) * N / L);
     const size_t lds = fft_lds_bytes(N, L);
 #define CL_SPEC_XZ(T, K)                                                                                          \
     hipLaunchKernelGGL((spec_extract_fftz<T, K>), grid, dim3(256), lds, s, static_cast<const T*>(state), N, logN, L, \
-                       na, arr, tw, F)
+                       na, arr, tw, F, P, zs, zc, nzero)
     if (fp32) {
         if (total == 2048) CL_SPEC_XZ(float, 8);
         else if (total == 1024) CL_SPEC_XZ(float, 4);
@@ -375,20 +406,22 @@ hipError_t launch_spec_extract_fftz(const void* state, bool fp32, int N, int na,
     return hipGetLastError();
 }
 
-hipError_t launch_spec_fftx_bin(const double2* F, const double2* tw, int N, double width, int nbins, double* sums,
-                                unsigned long long* counts, hipStream_t s) {
+hipError_t launch_spec_fftx_bin(const double2* F, const double2* tw, int N, int P, double width, int nbins,
+                                double* sums, unsigned long long* counts, hipStream_t s) {
     int logN = 0;
     while ((1 << logN) < N) ++logN;
     const int L = fft_lines_per_block(N);
     int logL = 0;
     while ((1 << logL) < L) ++logL;
-    if ((1 << logN) != N || (1 << logL) != L) return hipErrorInvalidValue;
-    const int batches = N * N / L;
+    if ((1 << logN) != N || (1 << logL) != L || P % L != 0 || P > N || P < N / 2 + 1) return hipErrorInvalidValue;
+    const int nzb = P / L;
+    const int batches = N * nzb;
     const unsigned grid = static_cast<unsigned>(std::min(batches, 2048));
     const size_t lds = fft_lds_bytes(N, L) + static_cast<size_t>(nbins) * (sizeof(double) + sizeof(unsigned));
     const int total = L * N;
 #define CL_SPEC_XB(K) \
-    hipLaunchKernelGGL((spec_fftx_bin<K>), dim3(grid), dim3(256), lds, s, F, N, logN, L, logL, tw, 1.0 / width, nbins, sums, counts)
+    hipLaunchKernelGGL((spec_fftx_bin<K>), dim3(grid), dim3(256), lds, s, F, N, logN, L, logL, P, nzb, tw, 1.0 / width, \
+                       nbins, sums, counts)
     if (total == 2048) CL_SPEC_XB(8);
     else if (total == 1024) CL_SPEC_XB(4);
     else if (total == 512) CL_SPEC_XB(2);

@@ -47,6 +47,23 @@ def test_spectrum_matches_oracle(N, precision, width):
     lat.close()
 
 
+def test_spectrum_matches_oracle_256_fp32():
+    """The benchmark's shape: 256^3 two-field FP32 lattice, where the y and x
+    passes run over the half z <= N / 2 of the transform (136 of 256 stored z,
+    the last batch partly padding) and count the mirrored modes twice."""
+    N = 256
+    rng = np.random.default_rng(77)
+    f = np.stack([1.0 + 0.1 * rng.standard_normal((N, N, N)), 0.05 * rng.standard_normal((N, N, N))])
+    p = 0.01 * rng.standard_normal((2, N, N, N))
+    lat = _lib().Lattice(N, 0.1, 2, "fp32")
+    lat.set_background(1.0, "static", 1.0, 1.0)
+    lat.set_fields(f, p)
+    del f, p
+    f32, _ = lat.get_fields()
+    check(lat, f32[1], 1, "f", 1.0, 0.1)
+    lat.close()
+
+
 def test_spectrum_plane_wave_256():
     """A single plane wave on 256^3 (the y and x passes with four- and
     sixteen-line batches): all power in one bin, A^2 N^6 / 2."""
