@@ -203,9 +203,10 @@ hipError_t launch_spec_extract_fftz(const void* state, bool fp32, int N, int na,
 hipError_t launch_spec_fftx_bin(const double2* F, const double2* tw, int N, int P, double width, int nbins,
                                 double* sums, unsigned long long* counts, hipStream_t s);
 // Gravitational-wave spectrum: projected |U|^2 per centred shell (sums has
-// nbins + 1 slots, the last for the modes beyond the bins).
-hipError_t launch_gw_bin(const double2* U, int N, double width, int nbins, double* sums, unsigned long long* counts,
-                         hipStream_t s);
+// nbins + 1 slots, the last for the modes beyond the bins), U the half
+// z <= N / 2 of the five transforms (pitch P, components N^3 apart).
+hipError_t launch_gw_bin(const double2* U, int N, int P, double width, int nbins, double* sums,
+                         unsigned long long* counts, hipStream_t s);
 // Linear propagation of the fluctuations over a jump (propagator.hip): the
 // 2 nf channels f_0..f_{nf-1}, pi_0..pi_{nf-1} of a site minus their means,
 // packed pairwise into nf complex arrays (channel 2q real, 2q+1 imaginary),

@@ -1297,17 +1297,20 @@ cl_status cl_gw_spectrum(cl_lattice* h, double width, int nbins, int64_t* counts
         }
     }
     if ((st = ensure_twiddles(h)) || (st = ensure_bins(h, nbins + 1))) return st;
+    // the half z <= N / 2 of each transform (pitch P), as for the scalar
+    // spectrum; the first extraction clears the bins
+    const int P = cl::spec_half_pitch(N);
     for (int c = 0; c < 5; ++c) {
         double2* dst = h->gw_spec + c * n3;
         // extraction of the component fused with the z pass, then y and x
         HIPCHECK(h, cl::launch_spec_extract_fftz(h->buf[h->cur], h->prec == CL_FP32, N, 2 * arrays(h),
-                                                 arrays(h) + h->nf + c, h->spec_tw, dst, N, nullptr, nullptr,
-                                                 0, h->stream));
-        for (int axis = 1; axis < 3; ++axis) HIPCHECK(h, cl::launch_spec_fft(dst, h->spec_tw, N, axis, h->stream));
+                                                 arrays(h) + h->nf + c, h->spec_tw, dst, P,
+                                                 c == 0 ? h->spec_sums : nullptr, h->spec_counts, nbins + 1,
+                                                 h->stream));
+        for (int axis = 1; axis < 3; ++axis)
+            HIPCHECK(h, cl::launch_spec_fft(dst, h->spec_tw, N, axis, h->stream, false, P));
     }
-    HIPCHECK(h, hipMemsetAsync(h->spec_sums, 0, (nbins + 1) * sizeof(double), h->stream));
-    HIPCHECK(h, hipMemsetAsync(h->spec_counts, 0, nbins * sizeof(unsigned long long), h->stream));
-    HIPCHECK(h, cl::launch_gw_bin(h->gw_spec, N, width, nbins, h->spec_sums, h->spec_counts, h->stream));
+    HIPCHECK(h, cl::launch_gw_bin(h->gw_spec, N, P, width, nbins, h->spec_sums, h->spec_counts, h->stream));
     std::vector<double> s(nbins + 1);
     std::vector<unsigned long long> c(nbins);
     HIPCHECK(h, hipMemcpyAsync(s.data(), h->spec_sums, (nbins + 1) * sizeof(double), hipMemcpyDeviceToHost, h->stream));

@@ -261,7 +261,55 @@ __global__ __launch_bounds__(256) void spec_fftx_bin(const double2* __restrict__
 // k^ the unit lattice momentum (sin(pi n_i / N)), then sum_ij |.|^2 into the
 // centred shell of |n~| (slot nbins collects the modes beyond the last bin);
 // the mode n~ = 0 carries no waves.
-__global__ __launch_bounds__(256) void gw_bin(const double2* __restrict__ U, int N, double inv_w, int nbins,
+//
+// U holds the half z <= N / 2 of each transform (row pitch P, components n3
+// apart).  A mode with 0 < z < N / 2 also stands for its mirror (-x, -y,
+// N - z), whose transform is the complex conjugate (a real tensor) and whose
+// |n~| is the same: where neither x nor y is the Nyquist index N / 2 the
+// mirror's lattice momentum is -k and the projector, even in k^, gives the
+// same power, so the mode is counted twice; otherwise the mirror keeps +N/2
+// in that component (the index convention of every mode) and its projection
+// is evaluated on its own.
+__device__ __forceinline__ double gw_mode_power(const int n[3], double pin, const double2 c11, const double2 c12,
+                                                const double2 c13, const double2 c22, const double2 c23) {
+    double k[3], kk = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        k[i] = sin(pin * n[i]);
+        kk += k[i] * k[i];
+    }
+    const double inv = 1.0 / sqrt(kk);
+    for (int i = 0; i < 3; ++i) k[i] *= inv;
+    double P[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) P[i][j] = (i == j ? 1.0 : 0.0) - k[i] * k[j];
+    const double2 c33 = make_double2(-c11.x - c22.x, -c11.y - c22.y);
+    const double2 T[3][3] = {{c11, c12, c13}, {c12, c22, c23}, {c13, c23, c33}};
+    double2 PT[3][3], tr = make_double2(0.0, 0.0);
+    for (int i = 0; i < 3; ++i)
+        for (int m = 0; m < 3; ++m) {
+            double2 a = make_double2(0.0, 0.0);
+            for (int l = 0; l < 3; ++l) {
+                a.x = fma(P[i][l], T[l][m].x, a.x);
+                a.y = fma(P[i][l], T[l][m].y, a.y);
+            }
+            PT[i][m] = a;
+            tr.x = fma(P[i][m], T[i][m].x, tr.x);
+            tr.y = fma(P[i][m], T[i][m].y, tr.y);
+        }
+    double pw = 0.0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double hx = -0.5 * P[i][j] * tr.x, hy = -0.5 * P[i][j] * tr.y;
+            for (int m = 0; m < 3; ++m) {
+                hx = fma(PT[i][m].x, P[m][j], hx);
+                hy = fma(PT[i][m].y, P[m][j], hy);
+            }
+            pw = fma(hx, hx, fma(hy, hy, pw));
+        }
+    return pw;
+}
+
+__global__ __launch_bounds__(256) void gw_bin(const double2* __restrict__ U, int N, int P, double inv_w, int nbins,
                                               double* __restrict__ sums, unsigned long long* __restrict__ counts) {
     extern __shared__ unsigned char raw[];
     double* s_sum = reinterpret_cast<double*>(raw);
@@ -272,55 +320,34 @@ __global__ __launch_bounds__(256) void gw_bin(const double2* __restrict__ U, int
     }
     __syncthreads();
     const size_t n3 = static_cast<size_t>(N) * N * N;
-    const int hN = N / 2;
+    const int hN = N / 2, nz = hN + 1;
+    const size_t modes = static_cast<size_t>(N) * N * nz;
     const double pin = M_PI / N;
-    for (size_t s = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; s < n3;
-         s += static_cast<size_t>(gridDim.x) * blockDim.x) {
-        const int z = static_cast<int>(s % N), y = static_cast<int>((s / N) % N),
-                  x = static_cast<int>(s / (static_cast<size_t>(N) * N));
-        const int n[3] = {x <= hN ? x : x - N, y <= hN ? y : y - N, z <= hN ? z : z - N};
+    for (size_t t = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < modes;
+         t += static_cast<size_t>(gridDim.x) * blockDim.x) {
+        const int z = static_cast<int>(t % nz), y = static_cast<int>((t / nz) % N),
+                  x = static_cast<int>(t / (static_cast<size_t>(N) * nz));
+        const size_t s = (static_cast<size_t>(x) * N + y) * P + z;
+        const int n[3] = {x <= hN ? x : x - N, y <= hN ? y : y - N, z};
+        const bool twice = z != 0 && z != hN;
         const double r = sqrt(static_cast<double>(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]));
         const int lb = min(static_cast<int>(floor(r * inv_w + 0.5)), nbins);
         double pw = 0.0;
         if (n[0] | n[1] | n[2]) {
-            double k[3], kk = 0.0;
-            for (int i = 0; i < 3; ++i) {
-                k[i] = sin(pin * n[i]);
-                kk += k[i] * k[i];
-            }
-            const double inv = 1.0 / sqrt(kk);
-            for (int i = 0; i < 3; ++i) k[i] *= inv;
-            double P[3][3];
-            for (int i = 0; i < 3; ++i)
-                for (int j = 0; j < 3; ++j) P[i][j] = (i == j ? 1.0 : 0.0) - k[i] * k[j];
             const double2 c11 = U[s], c12 = U[n3 + s], c13 = U[2 * n3 + s], c22 = U[3 * n3 + s],
                           c23 = U[4 * n3 + s];
-            const double2 c33 = make_double2(-c11.x - c22.x, -c11.y - c22.y);
-            const double2 T[3][3] = {{c11, c12, c13}, {c12, c22, c23}, {c13, c23, c33}};
-            double2 PT[3][3], tr = make_double2(0.0, 0.0);
-            for (int i = 0; i < 3; ++i)
-                for (int m = 0; m < 3; ++m) {
-                    double2 a = make_double2(0.0, 0.0);
-                    for (int l = 0; l < 3; ++l) {
-                        a.x = fma(P[i][l], T[l][m].x, a.x);
-                        a.y = fma(P[i][l], T[l][m].y, a.y);
-                    }
-                    PT[i][m] = a;
-                    tr.x = fma(P[i][m], T[i][m].x, tr.x);
-                    tr.y = fma(P[i][m], T[i][m].y, tr.y);
+            pw = gw_mode_power(n, pin, c11, c12, c13, c22, c23);
+            if (twice) {
+                if (x == hN || y == hN) {
+                    const int m[3] = {x == hN ? hN : -n[0], y == hN ? hN : -n[1], -z};
+                    pw += gw_mode_power(m, pin, c11, c12, c13, c22, c23);
+                } else {
+                    pw *= 2.0;
                 }
-            for (int i = 0; i < 3; ++i)
-                for (int j = 0; j < 3; ++j) {
-                    double hx = -0.5 * P[i][j] * tr.x, hy = -0.5 * P[i][j] * tr.y;
-                    for (int m = 0; m < 3; ++m) {
-                        hx = fma(PT[i][m].x, P[m][j], hx);
-                        hy = fma(PT[i][m].y, P[m][j], hy);
-                    }
-                    pw = fma(hx, hx, fma(hy, hy, pw));
-                }
+            }
         }
         atomicAdd(&s_sum[lb], pw);
-        if (lb < nbins) atomicAdd(&s_cnt[lb], 1u);
+        if (lb < nbins) atomicAdd(&s_cnt[lb], twice ? 2u : 1u);
     }
     __syncthreads();
     for (int i = threadIdx.x; i <= nbins; i += blockDim.x) {
@@ -329,12 +356,13 @@ __global__ __launch_bounds__(256) void gw_bin(const double2* __restrict__ U, int
     }
 }
 
-hipError_t launch_gw_bin(const double2* U, int N, double width, int nbins, double* sums, unsigned long long* counts,
-                         hipStream_t s) {
-    const size_t n3 = static_cast<size_t>(N) * N * N;
-    const unsigned grid = static_cast<unsigned>(std::min<size_t>((n3 + 255) / 256, 2048));
+hipError_t launch_gw_bin(const double2* U, int N, int P, double width, int nbins, double* sums,
+                         unsigned long long* counts, hipStream_t s) {
+    if (P < N / 2 + 1 || P > N) return hipErrorInvalidValue;
+    const size_t modes = static_cast<size_t>(N) * N * (N / 2 + 1);
+    const unsigned grid = static_cast<unsigned>(std::min<size_t>((modes + 255) / 256, 2048));
     const size_t lds = static_cast<size_t>(nbins + 1) * sizeof(double) + static_cast<size_t>(nbins) * sizeof(unsigned);
-    hipLaunchKernelGGL(gw_bin, dim3(grid), dim3(256), lds, s, U, N, 1.0 / width, nbins, sums, counts);
+    hipLaunchKernelGGL(gw_bin, dim3(grid), dim3(256), lds, s, U, N, P, 1.0 / width, nbins, sums, counts);
     return hipGetLastError();
 }
 
